@@ -1,0 +1,195 @@
+/*
+ * raftgp.h -- C ABI of the MI355X (gfx950) implementation of the RaftGP hot
+ * path (Gao et al., "RaftGP: Random Fast Graph Partitioning", IEEE HPEC 2023).
+ *
+ * Problem statement (Sec. II): an undirected, unweighted graph G = (V, E) with
+ * symmetric adjacency A in {0,1}^{N x N} is partitioned into K disjoint
+ * blocks, K not given.  The method (Sec. III) is
+ *   1. random feature extraction   Y = X^q Theta   (Sec. III-A, Eq. 5),
+ *      X = M = D^-1/2 A D^-1/2 (NCut, Eq. 2) or the modularity matrix
+ *      (Eq. 4; full B = A - d d^T/2e applied in low-rank form, or the paper's
+ *      edge-masked reduced matrix Q~);
+ *   2. random embedding            Z = GCN(Y) with untrained random weights
+ *      (Sec. III-B, Eq. 6, tanh, row L2 normalisation);
+ *   3. model selection             k-means on Z for every candidate K of a
+ *      grid, scored by modularity (Eq. 3) and NCut (Eq. 1); K* = argmax Mod.
+ *
+ * Conventions for every call:
+ *   - Return value: raft_status, RAFT_OK (0) or a negative error code.
+ *     Nothing aborts or throws.  raft_last_error() gives a message.
+ *   - Device pointers are HIP device (or managed) memory on the context's
+ *     device; the caller owns every buffer it passes in.  Dense matrices are
+ *     row-major FP32.
+ *   - `stream` is a hipStream_t (NULL = default stream).  Compute calls are
+ *     asynchronous on that stream unless documented otherwise; argument
+ *     errors are reported synchronously before anything is enqueued.
+ *   - Device-detected errors (non-finite values, invalid CSR) are latched in
+ *     a status word and returned by raft_sync_status().
+ *   - A context is used by one host thread at a time.  Graph handles are
+ *     immutable after creation.
+ */
+#ifndef RAFTGP_H
+#define RAFTGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RAFT_ABI_VERSION 1
+
+typedef int32_t raft_status;
+#define RAFT_OK             0
+#define RAFT_E_INVAL       -1   /* bad argument (null pointer, size, range)   */
+#define RAFT_E_CSR         -2   /* CSR not symmetric/sorted/unique/loop-free   */
+#define RAFT_E_NOEDGES     -3   /* e = 0: modularity (Eq. 3) divides by e      */
+#define RAFT_E_WORKSPACE   -4   /* workspace smaller than raft_workspace_size  */
+#define RAFT_E_NOMEM       -5   /* device allocation failed                    */
+#define RAFT_E_DEVICE      -6   /* HIP runtime error                           */
+#define RAFT_E_NUMERIC     -7   /* non-finite value detected on the device     */
+#define RAFT_E_UNSUPPORTED -8   /* width / K outside the compiled kernels      */
+
+/* Structural operator X of the random projection (Sec. III-A). */
+#define RAFT_X_NCUT        0    /* M = D^-1/2 A D^-1/2 (Eq. 2); D^-1/2 = 0 for isolated nodes */
+#define RAFT_X_MOD_FULL    1    /* B = A - d d^T / 2e (Eq. 4), never formed                 */
+#define RAFT_X_MOD_REDUCED 2    /* Q~: B masked to the edge set (Sec. III-A)                */
+#define RAFT_X_GCN         3    /* D^-1/2 (A + I) D^-1/2 with D = deg + 1 (Eq. 6)           */
+
+/* Feature / embedding widths supported by the kernels. */
+#define RAFT_MAX_LAYERS 8
+#define RAFT_MAX_K      255     /* labels are stored as bytes                */
+
+typedef struct raft_ctx raft_ctx;
+typedef struct raft_graph raft_graph;
+
+typedef struct {
+    int32_t  abi_version;              /* must be RAFT_ABI_VERSION                    */
+    int32_t  op;                       /* RAFT_X_NCUT / MOD_FULL / MOD_REDUCED        */
+    int32_t  proj_dim;                 /* L, one of 16, 32, 64, 128, 256              */
+    int32_t  q;                        /* propagation steps, >= 1 (q = 1 is Eq. 5)    */
+    int32_t  n_layers;                 /* GCN layers, 0..RAFT_MAX_LAYERS               */
+    int32_t  layer_dims[RAFT_MAX_LAYERS]; /* L_1..L_n, each in {16,32,64,128,256}; d = last */
+    int32_t  normalize_input;          /* row-normalise Y before layer 1 (default 0)  */
+    int32_t  k_min, k_max, k_step;     /* candidate grid, 1 <= k_min <= k_max <= min(N, 255) */
+    int32_t  kmeans_max_iter;          /* T_max (assignments per candidate), >= 1     */
+    int32_t  check_every;              /* host convergence poll period (0 = 4)        */
+    uint64_t seed;                     /* Philox key word 0 for Theta, W and the race */
+} raft_config;
+
+/* Output buffers of raft_partition / raft_run (device memory, caller-owned).
+ * Kc = number of candidates in the grid, K_max = the largest candidate. */
+typedef struct {
+    float*   Y;            /* [N x L] projected features (nullable)                  */
+    float*   Z;            /* [N x d] embedding (nullable in raft_run)               */
+    int32_t* labels;       /* [N] labels of K*, relabelled by first occurrence       */
+    int32_t* k_selected;   /* [3]: K*, K_eff (non-empty blocks), index of K* in grid */
+    double*  mod;          /* [Kc] modularity per candidate (nullable)               */
+    double*  ncut;         /* [Kc] NCut per candidate (nullable)                     */
+    uint8_t* labels_all;   /* [N x Kc] labels of every candidate, point-major (nullable) */
+    int32_t* picks;        /* [K_max] k-means++ picks (nullable)                     */
+    int32_t* iters;        /* [Kc] Lloyd assignments performed (nullable)            */
+} raft_outputs;
+
+/* ---- context and errors ------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  *out receives the handle. */
+raft_status raft_ctx_create(int device, raft_ctx** out);
+void        raft_ctx_destroy(raft_ctx* ctx);
+const char* raft_status_string(raft_status s);
+/* Copies the last error message of this context into buf (NUL-terminated);
+ * returns the full message length. */
+size_t      raft_last_error(raft_ctx* ctx, char* buf, size_t n);
+int32_t     raft_abi_version(void);
+/* Synchronises `stream` and returns RAFT_E_NUMERIC if a kernel flagged a
+ * non-finite value since the last call (the flag is then cleared). */
+raft_status raft_sync_status(raft_ctx* ctx, void* stream);
+
+/* ---- graph (Sec. II: undirected unweighted A, CSR) ----------------------- */
+
+/* Copies an int32 CSR (row_ptr[n+1], col_idx[nnz]) into library-owned device
+ * memory, validates it on the device (sorted unique columns, no self loops,
+ * symmetric, in range) and computes degrees, 2e and the scale vectors
+ * D^-1/2 and (D+1)^-1/2.  `inputs_on_device` != 0 means the two arrays are
+ * device pointers.  Synchronous: returns after validation (RAFT_E_CSR on a
+ * malformed graph).  The caller may free its arrays on return. */
+raft_status raft_graph_create(raft_ctx* ctx, const int32_t* row_ptr, const int32_t* col_idx,
+                              int64_t n, int64_t nnz, int inputs_on_device, void* stream,
+                              raft_graph** out);
+void        raft_graph_destroy(raft_graph* g);
+/* Device copies of the degree vector (int32 [N]) and of the CSR (for tests). */
+raft_status raft_graph_degrees(const raft_graph* g, int32_t* deg_out, void* stream);
+
+/* ---- workspace ----------------------------------------------------------- */
+
+/* Bytes of device workspace raft_project / raft_embed / raft_partition /
+ * raft_run need for this graph and config (256-byte aligned base). */
+raft_status raft_workspace_size(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg,
+                                size_t* bytes);
+
+/* ---- stage A1: seeded Gaussian matrices (Sec. III-A Eq. 5, Sec. III-B) ---- */
+
+/* out[rows x cols] = FP32(sigma * N(0,1)) drawn from Philox4x64-10 with key
+ * (seed, stream_id), counter (row, col/4, 0, 0): each counter gives four
+ * Box-Muller normals for columns 4*(col/4)..+3.  Theta uses stream 0x10 and
+ * sigma = L^-1/2; GCN layer k (1-based) uses 0x10 + k and sigma = L_{k-1}^-1/2. */
+raft_status raft_gaussian(raft_ctx* ctx, uint64_t seed, uint64_t stream_id, int64_t rows,
+                          int64_t cols, double sigma, float* out, void* stream);
+
+/* ---- stages A2/A3: one sparse step and the projection -------------------- */
+
+/* Y_out = X Y_in for one operator X (RAFT_X_*), Y_in/Y_out [N x L] row-major,
+ * distinct buffers.  MOD_FULL needs workspace for the column sums d^T Y_in.  */
+raft_status raft_spmm(raft_ctx* ctx, const raft_graph* g, int32_t op, int32_t L,
+                      const float* Y_in, float* Y_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Y = X^q Theta (Sec. III-A, Eq. 5 with q powers), Theta drawn as in
+ * raft_gaussian with cfg->seed.  Y_out [N x L]. */
+raft_status raft_project(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg,
+                         void* ws, size_t ws_bytes, float* Y_out, void* stream);
+
+/* ---- stage A4: random GCN (Sec. III-B, Eq. 6) ----------------------------- */
+
+/* One layer: H_out = rownorm(tanh((A_hat_n H_in) W)), W [L_in x L_out]
+ * row-major (device).  With `linear` != 0 the tanh and the normalisation are
+ * skipped (U = A_hat_n H_in W).  P_out (nullable, [N x L_in]) receives
+ * A_hat_n H_in. */
+raft_status raft_gcn_layer(raft_ctx* ctx, const raft_graph* g, int32_t L_in, int32_t L_out,
+                           const float* H_in, const float* W, int32_t linear, float* H_out,
+                           float* P_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Z = GCN(Y) with W^(k) drawn as in raft_gaussian (seed cfg->seed). */
+raft_status raft_embed(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg,
+                       const float* Y, void* ws, size_t ws_bytes, float* Z_out, void* stream);
+
+/* ---- stages A5-A7: model selection --------------------------------------- */
+
+/* k-means for every candidate K of the grid (nested k-means++ exponential
+ * race, Lloyd to a fixed point or T_max), scores per candidate, selection of
+ * K* by modularity.  Z [N x d], d = last layer width (or L when n_layers = 0).
+ * Polls convergence from the host every cfg->check_every iterations, so the
+ * call synchronises `stream`. */
+raft_status raft_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg,
+                           const float* Z, void* ws, size_t ws_bytes, raft_outputs* out,
+                           void* stream);
+
+/* Stage A7 alone: Mod (Eq. 3) and NCut (Eq. 1) of Kc labelings given as
+ * point-major bytes labels_all[N x Kc]; ks[Kc] (host) are the block counts.
+ * mod/ncut are device arrays [Kc]. */
+raft_status raft_score(raft_ctx* ctx, const raft_graph* g, const uint8_t* labels_all,
+                       int32_t Kc, const int32_t* ks, double* mod, double* ncut,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* A1-A7: projection, embedding and model selection (synchronises `stream`). */
+raft_status raft_run(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg,
+                     void* ws, size_t ws_bytes, raft_outputs* out, void* stream);
+
+/* Per-stage device times (ms) of the last raft_run on this context:
+ * [0] project, [1] embed, [2] seeding, [3] Lloyd, [4] scores+select. */
+raft_status raft_get_stage_times(raft_ctx* ctx, double* ms5);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RAFTGP_H */

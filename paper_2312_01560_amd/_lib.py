@@ -1,0 +1,109 @@
+"""ctypes declarations of libraftgp.so (include/raftgp.h).  Argument
+marshalling only: every stage of the path runs in the HIP library."""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libraftgp.so")
+
+ABI_VERSION = 1
+MAX_LAYERS = 8
+MAX_K = 255
+
+OK, E_INVAL, E_CSR, E_NOEDGES, E_WORKSPACE, E_NOMEM, E_DEVICE, E_NUMERIC, E_UNSUPPORTED = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
+
+X_NCUT, X_MOD_FULL, X_MOD_REDUCED, X_GCN = 0, 1, 2, 3
+
+# every symbol include/raftgp.h declares
+EXPORTS = [
+    "raft_ctx_create", "raft_ctx_destroy", "raft_status_string", "raft_last_error",
+    "raft_abi_version", "raft_sync_status", "raft_graph_create", "raft_graph_destroy",
+    "raft_graph_degrees", "raft_workspace_size", "raft_gaussian", "raft_spmm", "raft_project",
+    "raft_gcn_layer", "raft_embed", "raft_partition", "raft_score", "raft_run",
+    "raft_get_stage_times",
+]
+
+
+class RaftConfig(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("op", ctypes.c_int32),
+        ("proj_dim", ctypes.c_int32),
+        ("q", ctypes.c_int32),
+        ("n_layers", ctypes.c_int32),
+        ("layer_dims", ctypes.c_int32 * MAX_LAYERS),
+        ("normalize_input", ctypes.c_int32),
+        ("k_min", ctypes.c_int32),
+        ("k_max", ctypes.c_int32),
+        ("k_step", ctypes.c_int32),
+        ("kmeans_max_iter", ctypes.c_int32),
+        ("check_every", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+class RaftOutputs(ctypes.Structure):
+    _fields_ = [
+        ("Y", ctypes.c_void_p),
+        ("Z", ctypes.c_void_p),
+        ("labels", ctypes.c_void_p),
+        ("k_selected", ctypes.c_void_p),
+        ("mod", ctypes.c_void_p),
+        ("ncut", ctypes.c_void_p),
+        ("labels_all", ctypes.c_void_p),
+        ("picks", ctypes.c_void_p),
+        ("iters", ctypes.c_void_p),
+    ]
+
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_U64 = ctypes.c_uint64
+_SZ = ctypes.c_size_t
+
+_SIGNATURES = {
+    "raft_ctx_create": (_I32, [ctypes.c_int, ctypes.POINTER(_P)]),
+    "raft_ctx_destroy": (None, [_P]),
+    "raft_status_string": (ctypes.c_char_p, [_I32]),
+    "raft_last_error": (_SZ, [_P, ctypes.c_char_p, _SZ]),
+    "raft_abi_version": (_I32, []),
+    "raft_sync_status": (_I32, [_P, _P]),
+    "raft_graph_create": (_I32, [_P, _P, _P, _I64, _I64, ctypes.c_int, _P, ctypes.POINTER(_P)]),
+    "raft_graph_destroy": (None, [_P]),
+    "raft_graph_degrees": (_I32, [_P, _P, _P]),
+    "raft_workspace_size": (_I32, [_P, _P, ctypes.POINTER(RaftConfig), ctypes.POINTER(_SZ)]),
+    "raft_gaussian": (_I32, [_P, _U64, _U64, _I64, _I64, ctypes.c_double, _P, _P]),
+    "raft_spmm": (_I32, [_P, _P, _I32, _I32, _P, _P, _P, _SZ, _P]),
+    "raft_project": (_I32, [_P, _P, ctypes.POINTER(RaftConfig), _P, _SZ, _P, _P]),
+    "raft_gcn_layer": (_I32, [_P, _P, _I32, _I32, _P, _P, _I32, _P, _P, _P, _SZ, _P]),
+    "raft_embed": (_I32, [_P, _P, ctypes.POINTER(RaftConfig), _P, _P, _SZ, _P, _P]),
+    "raft_partition": (_I32, [_P, _P, ctypes.POINTER(RaftConfig), _P, _P, _SZ,
+                              ctypes.POINTER(RaftOutputs), _P]),
+    "raft_score": (_I32, [_P, _P, _P, _I32, ctypes.POINTER(_I32), _P, _P, _P, _SZ, _P]),
+    "raft_run": (_I32, [_P, _P, ctypes.POINTER(RaftConfig), _P, _SZ,
+                        ctypes.POINTER(RaftOutputs), _P]),
+    "raft_get_stage_times": (_I32, [_P, ctypes.POINTER(ctypes.c_double)]),
+}
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load libraftgp.so; raises if it is missing (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with "
+                           "`python -m paper_2312_01560_amd.build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if lib.raft_abi_version() != ABI_VERSION:
+        raise RuntimeError("libraftgp.so ABI version mismatch")
+    _lib = lib
+    return lib

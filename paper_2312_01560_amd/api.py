@@ -1,0 +1,278 @@
+"""Python binding of the HIP library: device memory and streams come from
+torch; every computation is a call into libraftgp.so."""
+import ctypes
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import RaftConfig, RaftOutputs, X_GCN, X_MOD_FULL, X_MOD_REDUCED, X_NCUT  # noqa: F401
+
+STREAM_THETA = 0x10
+STREAM_W_BASE = 0x10
+
+
+class RaftError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"raftgp error {status}: {message}")
+        self.status = status
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+@dataclass
+class Config:
+    """Method settings (mirror of raft_config)."""
+    op: int = X_MOD_FULL
+    proj_dim: int = 64
+    q: int = 3
+    layer_dims: list = field(default_factory=lambda: [64, 64])
+    normalize_input: bool = False
+    k_min: int = 2
+    k_max: int = 30
+    k_step: int = 1
+    kmeans_max_iter: int = 100
+    check_every: int = 4
+    seed: int = 0
+
+    @property
+    def ks(self):
+        return list(range(self.k_min, self.k_max + 1, self.k_step))
+
+    @property
+    def embed_dim(self):
+        return self.layer_dims[-1] if self.layer_dims else self.proj_dim
+
+    def to_c(self):
+        c = RaftConfig()
+        c.abi_version = _lib.ABI_VERSION
+        c.op = self.op
+        c.proj_dim = self.proj_dim
+        c.q = self.q
+        c.n_layers = len(self.layer_dims)
+        for i, v in enumerate(self.layer_dims):
+            c.layer_dims[i] = v
+        c.normalize_input = int(bool(self.normalize_input))
+        c.k_min, c.k_max, c.k_step = self.k_min, self.k_max, self.k_step
+        c.kmeans_max_iter = self.kmeans_max_iter
+        c.check_every = self.check_every
+        c.seed = self.seed
+        return c
+
+
+class Context:
+    def __init__(self, device=0):
+        self.lib = _lib.load()
+        self.device = device
+        h = ctypes.c_void_p()
+        st = self.lib.raft_ctx_create(device, ctypes.byref(h))
+        if st != 0:
+            raise RaftError(st, "raft_ctx_create failed")
+        self.h = h
+        self.torch_device = torch.device("cuda", device)
+
+    def check(self, st):
+        if st != 0:
+            buf = ctypes.create_string_buffer(1024)
+            self.lib.raft_last_error(self.h, buf, 1024)
+            raise RaftError(st, buf.value.decode(errors="replace"))
+
+    def sync_status(self):
+        self.check(self.lib.raft_sync_status(self.h, _stream()))
+
+    def close(self):
+        if self.h:
+            self.lib.raft_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def empty(self, shape, dtype):
+        return torch.empty(shape, dtype=dtype, device=self.torch_device)
+
+    def workspace(self, nbytes):
+        ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.torch_device)
+        assert ws.data_ptr() % 256 == 0
+        return ws
+
+
+class Graph:
+    """Device CSR owned by the library (raft_graph)."""
+
+    def __init__(self, ctx, row_ptr, col_idx, n=None):
+        self.ctx = ctx
+        if isinstance(row_ptr, torch.Tensor) and row_ptr.is_cuda:
+            rp = row_ptr.to(torch.int32).contiguous()
+            ci = col_idx.to(torch.int32).contiguous()
+            on_dev = 1
+            rp_p, ci_p = _ptr(rp), _ptr(ci)
+            nnz = ci.numel()
+            keep = (rp, ci)
+        else:
+            rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+            ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+            on_dev = 0
+            rp_p = rp.ctypes.data_as(ctypes.c_void_p)
+            ci_p = ci.ctypes.data_as(ctypes.c_void_p)
+            nnz = ci.size
+            keep = (rp, ci)
+        self.n = int(len(rp) - 1) if n is None else int(n)
+        self.nnz = int(nnz)
+        h = ctypes.c_void_p()
+        st = ctx.lib.raft_graph_create(ctx.h, rp_p, ci_p, self.n, self.nnz, on_dev, _stream(),
+                                       ctypes.byref(h))
+        del keep
+        ctx.check(st)
+        self.h = h
+
+    def degrees(self):
+        out = self.ctx.empty((self.n,), torch.int32)
+        self.ctx.check(self.ctx.lib.raft_graph_degrees(self.h, _ptr(out), _stream()))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.raft_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def workspace_size(ctx, g, cfg):
+    c = cfg.to_c()
+    n = ctypes.c_size_t()
+    ctx.check(ctx.lib.raft_workspace_size(ctx.h, g.h, ctypes.byref(c), ctypes.byref(n)))
+    return n.value
+
+
+def gaussian(ctx, seed, stream_id, rows, cols, sigma):
+    out = ctx.empty((rows, cols), torch.float32)
+    ctx.check(ctx.lib.raft_gaussian(ctx.h, seed, stream_id, rows, cols, float(sigma), _ptr(out),
+                                    _stream()))
+    return out
+
+
+def spmm(ctx, g, op, Y, out=None, ws=None):
+    Y = Y.contiguous()
+    L = Y.shape[1]
+    out = ctx.empty((g.n, L), torch.float32) if out is None else out
+    if ws is None:
+        ws = ctx.workspace(64 * 1024 * 1024 if g.n * L * 8 < 2**26 else g.n * L * 8)
+    ctx.check(ctx.lib.raft_spmm(ctx.h, g.h, op, L, _ptr(Y), _ptr(out), _ptr(ws), ws.numel(),
+                                _stream()))
+    return out
+
+
+def _ws_for(ctx, g, cfg, ws):
+    need = workspace_size(ctx, g, cfg)
+    if ws is None or ws.numel() < need:
+        ws = ctx.workspace(need)
+    return ws
+
+
+def project(ctx, g, cfg, ws=None, out=None):
+    ws = _ws_for(ctx, g, cfg, ws)
+    out = ctx.empty((g.n, cfg.proj_dim), torch.float32) if out is None else out
+    c = cfg.to_c()
+    ctx.check(ctx.lib.raft_project(ctx.h, g.h, ctypes.byref(c), _ptr(ws), ws.numel(), _ptr(out),
+                                   _stream()))
+    return out
+
+
+def gcn_layer(ctx, g, H, W, linear=False, want_p=False):
+    H = H.contiguous()
+    W = W.contiguous()
+    lin, lout = W.shape
+    out = ctx.empty((g.n, lout), torch.float32)
+    P = ctx.empty((g.n, lin), torch.float32)
+    ctx.check(ctx.lib.raft_gcn_layer(ctx.h, g.h, lin, lout, _ptr(H), _ptr(W), int(linear),
+                                     _ptr(out), _ptr(P), ctypes.c_void_p(0), 0, _stream()))
+    return (out, P) if want_p else out
+
+
+def embed(ctx, g, cfg, Y, ws=None, out=None):
+    ws = _ws_for(ctx, g, cfg, ws)
+    out = ctx.empty((g.n, cfg.embed_dim), torch.float32) if out is None else out
+    c = cfg.to_c()
+    ctx.check(ctx.lib.raft_embed(ctx.h, g.h, ctypes.byref(c), _ptr(Y.contiguous()), _ptr(ws),
+                                 ws.numel(), _ptr(out), _stream()))
+    return out
+
+
+def _outputs(ctx, g, cfg, want_y=False, want_z=False):
+    kc = len(cfg.ks)
+    o = {
+        "labels": ctx.empty((g.n,), torch.int32),
+        "k_selected": ctx.empty((3,), torch.int32),
+        "mod": ctx.empty((kc,), torch.float64),
+        "ncut": ctx.empty((kc,), torch.float64),
+        "labels_all": ctx.empty((g.n, kc), torch.uint8),
+        "picks": ctx.empty((max(cfg.ks),), torch.int32),
+        "iters": ctx.empty((kc,), torch.int32),
+    }
+    if want_y:
+        o["Y"] = ctx.empty((g.n, cfg.proj_dim), torch.float32)
+    if want_z:
+        o["Z"] = ctx.empty((g.n, cfg.embed_dim), torch.float32)
+    s = RaftOutputs()
+    for name, _ in RaftOutputs._fields_:
+        t = o.get(name)
+        setattr(s, name, t.data_ptr() if t is not None else None)
+    return o, s
+
+
+def partition(ctx, g, cfg, Z, ws=None):
+    ws = _ws_for(ctx, g, cfg, ws)
+    o, s = _outputs(ctx, g, cfg)
+    c = cfg.to_c()
+    ctx.check(ctx.lib.raft_partition(ctx.h, g.h, ctypes.byref(c), _ptr(Z.contiguous()),
+                                     _ptr(ws), ws.numel(), ctypes.byref(s), _stream()))
+    return o
+
+
+def run(ctx, g, cfg, ws=None, want_y=True, want_z=True, outputs=None):
+    """A1-A7 on one graph; returns a dict of device tensors."""
+    ws = _ws_for(ctx, g, cfg, ws)
+    if outputs is None:
+        outputs = _outputs(ctx, g, cfg, want_y, want_z)
+    o, s = outputs
+    c = cfg.to_c()
+    ctx.check(ctx.lib.raft_run(ctx.h, g.h, ctypes.byref(c), _ptr(ws), ws.numel(), ctypes.byref(s),
+                               _stream()))
+    return o
+
+
+def score(ctx, g, labels_all, ks):
+    labels_all = labels_all.to(torch.uint8).contiguous()
+    kc = len(ks)
+    mod = ctx.empty((kc,), torch.float64)
+    nc = ctx.empty((kc,), torch.float64)
+    ks_arr = (ctypes.c_int32 * kc)(*ks)
+    stride = (kc + 3) // 4 * 4
+    sk = sum(ks)
+    # upper bound of the library's layout (score grid <= 1024 work-groups)
+    ws = ctx.workspace(8 * kc + g.n * stride + 2 * 1024 * sk * 4 + 16 * sk + 8 * 256)
+    ctx.check(ctx.lib.raft_score(ctx.h, g.h, _ptr(labels_all), kc, ks_arr, _ptr(mod), _ptr(nc),
+                                 _ptr(ws), ws.numel(), _stream()))
+    return mod, nc
+
+
+def stage_times(ctx):
+    arr = (ctypes.c_double * 5)()
+    ctx.check(ctx.lib.raft_get_stage_times(ctx.h, arr))
+    return list(arr)

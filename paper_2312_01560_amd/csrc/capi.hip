@@ -1,0 +1,823 @@
+// C ABI of the RaftGP hot path: argument checks, workspace planning and the
+// stage sequence (projection -> GCN -> k-means grid -> scores -> selection).
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "../../include/raftgp.h"
+#include "kernels.h"
+
+using namespace raft;
+
+struct raft_ctx {
+    int device = 0;
+    int num_cu = 256;
+    size_t lds_max = 65536;
+    std::string err;
+    int32_t* d_status = nullptr;   // device status word
+    int32_t* h_pinned = nullptr;   // pinned host scratch (8 ints)
+    double stage_ms[5] = {0, 0, 0, 0, 0};
+    hipEvent_t ev[6] = {};
+};
+
+struct raft_graph {
+    raft_ctx* ctx = nullptr;
+    int32_t n = 0;
+    int64_t nnz = 0;
+    int32_t* rp = nullptr;
+    int32_t* ci = nullptr;
+    int32_t* deg = nullptr;
+    float* s = nullptr;
+    float* sh = nullptr;
+    float* dcoef = nullptr;
+    GraphView view() const {
+        GraphView v;
+        v.n = n;
+        v.nnz = nnz;
+        v.rp = rp;
+        v.ci = ci;
+        v.deg = deg;
+        v.s = s;
+        v.sh = sh;
+        v.dcoef = dcoef;
+        return v;
+    }
+};
+
+namespace {
+
+raft_status fail(raft_ctx* ctx, raft_status code, const char* fmt, ...) {
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return code;
+}
+
+#define HIP_TRY(ctx, call)                                                                  \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((ctx), RAFT_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define RAFT_TRY(call)                 \
+    do {                               \
+        raft_status s_ = (call);       \
+        if (s_ != RAFT_OK) return s_;  \
+    } while (0)
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+bool width_ok(int v) { return v == 16 || v == 32 || v == 64 || v == 128 || v == 256; }
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Bump allocator over the caller's workspace (or a size-only dry run).
+struct Arena {
+    char* base = nullptr;
+    size_t off = 0;
+    template <typename T>
+    T* take(size_t count) {
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += align256(count * sizeof(T));
+        return p;
+    }
+};
+
+struct Grid {
+    std::vector<int32_t> ks, koff16, koff, grp, cand_of;
+    int Kc = 0, KP = 0, SK = 0, k_max = 0, groups = 0;
+};
+
+Grid make_grid(int k_min, int k_max, int k_step) {
+    Grid g;
+    for (int k = k_min; k <= k_max; k += k_step) g.ks.push_back(k);
+    g.Kc = (int)g.ks.size();
+    for (int k : g.ks) {
+        g.koff16.push_back(g.KP);
+        g.koff.push_back(g.SK);
+        const int pad = (k + 15) / 16 * 16;
+        for (int r = 0; r < pad; ++r) g.cand_of.push_back((int)g.koff16.size() - 1);
+        g.KP += pad;
+        g.SK += k;
+        g.k_max = std::max(g.k_max, k);
+    }
+    // candidate groups of the assignment kernel: about 256 padded centres each
+    g.grp.push_back(0);
+    int acc = 0;
+    for (int i = 0; i < g.Kc; ++i) {
+        acc += (g.ks[i] + 15) / 16 * 16;
+        if (acc >= 256 && i + 1 < g.Kc) {
+            g.grp.push_back(i + 1);
+            acc = 0;
+        }
+    }
+    g.grp.push_back(g.Kc);
+    g.groups = (int)g.grp.size() - 1;
+    return g;
+}
+
+int embed_dim(const raft_config* c) {
+    return c->n_layers > 0 ? c->layer_dims[c->n_layers - 1] : c->proj_dim;
+}
+
+int max_width(const raft_config* c) {
+    int m = c->proj_dim;
+    for (int k = 0; k < c->n_layers; ++k) m = std::max(m, c->layer_dims[k]);
+    return m;
+}
+
+raft_status check_config(raft_ctx* ctx, const raft_graph* g, const raft_config* c) {
+    if (!c) return fail(ctx, RAFT_E_INVAL, "config is null");
+    if (c->abi_version != RAFT_ABI_VERSION)
+        return fail(ctx, RAFT_E_INVAL, "abi_version %d != %d", c->abi_version, RAFT_ABI_VERSION);
+    if (c->op < RAFT_X_NCUT || c->op > RAFT_X_MOD_REDUCED)
+        return fail(ctx, RAFT_E_INVAL, "op %d not a projection operator", c->op);
+    if (!width_ok(c->proj_dim)) return fail(ctx, RAFT_E_UNSUPPORTED, "proj_dim %d", c->proj_dim);
+    if (c->q < 1) return fail(ctx, RAFT_E_INVAL, "q must be >= 1");
+    if (c->n_layers < 0 || c->n_layers > RAFT_MAX_LAYERS)
+        return fail(ctx, RAFT_E_INVAL, "n_layers %d", c->n_layers);
+    int lin = c->proj_dim;
+    for (int k = 0; k < c->n_layers; ++k) {
+        if (!width_ok(c->layer_dims[k]) || !dense_supported(lin, c->layer_dims[k]))
+            return fail(ctx, RAFT_E_UNSUPPORTED, "layer %d width %d", k + 1, c->layer_dims[k]);
+        lin = c->layer_dims[k];
+    }
+    if (c->k_step < 1 || c->k_min < 1 || c->k_min > c->k_max || c->k_max > RAFT_MAX_K)
+        return fail(ctx, RAFT_E_INVAL, "candidate grid %d..%d step %d", c->k_min, c->k_max,
+                    c->k_step);
+    if (g && c->k_max > g->n) return fail(ctx, RAFT_E_INVAL, "k_max %d exceeds N", c->k_max);
+    if (c->kmeans_max_iter < 1) return fail(ctx, RAFT_E_INVAL, "kmeans_max_iter < 1");
+    return RAFT_OK;
+}
+
+// Workspace layout shared by every staged call.
+struct Plan {
+    int L = 0, d = 0, Lmax = 0, spmm_grid_ = 0, score_grid_ = 0, S = 0, chunks = 0, chunk_len = 0,
+        race_grid = 0;
+    Grid grid;
+    // projection / embedding
+    float *y0, *y1, *pbuf, *yout, *zout, *wbuf;
+    double *cpart, *c64;
+    float* cvec;
+    // k-means
+    KmeansPlan km;
+    int32_t* meta;   // ks, koff16, koff, grp, cand_of packed
+    // scores
+    ScorePlan sc;
+    uint8_t* lab_pm;
+    double *mod_int, *ncut_int;
+    int32_t* ksel_int;
+    int32_t* picks_int;
+    int32_t* iters_int;
+    size_t bytes = 0;
+};
+
+void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char* base, Plan& P) {
+    const int n = g->n;
+    P.L = c->proj_dim;
+    P.d = embed_dim(c);
+    P.Lmax = max_width(c);
+    P.grid = make_grid(c->k_min, c->k_max, c->k_step);
+    P.spmm_grid_ = spmm_grid(n, P.Lmax, ctx->num_cu, nullptr);
+    // every width uses the same grid formula (it does not depend on L)
+    P.score_grid_ = score_grid(n, ctx->num_cu);
+    P.S = (P.grid.Kc + 3) / 4 * 4;
+    P.chunks = std::max(1, std::min(64, (n + 2047) / 2048));
+    P.chunk_len = (n + P.chunks - 1) / P.chunks;
+    P.chunks = std::max(1, (n + P.chunk_len - 1) / P.chunk_len);
+    P.race_grid = kmeans_race_grid(n, ctx->num_cu);
+    Arena a;
+    a.base = base;
+    const size_t nL = (size_t)n * P.Lmax;
+    P.y0 = a.take<float>(nL);
+    P.y1 = a.take<float>(nL);
+    P.pbuf = a.take<float>(nL);
+    P.yout = a.take<float>((size_t)n * P.L);
+    P.zout = a.take<float>((size_t)n * P.d);
+    size_t wmax = 1;
+    int lin = P.L;
+    for (int k = 0; k < c->n_layers; ++k) {
+        wmax = std::max(wmax, (size_t)lin * c->layer_dims[k]);
+        lin = c->layer_dims[k];
+    }
+    P.wbuf = a.take<float>(wmax);
+    P.cpart = a.take<double>((size_t)P.spmm_grid_ * P.Lmax);
+    P.c64 = a.take<double>(P.Lmax);
+    P.cvec = a.take<float>(P.Lmax);
+    // k-means
+    const Grid& G = P.grid;
+    const size_t meta_n = (size_t)3 * G.Kc + G.grp.size() + G.KP;
+    P.meta = a.take<int32_t>(meta_n);
+    KmeansPlan& km = P.km;
+    km.n = n;
+    km.d = P.d;
+    km.Kc = G.Kc;
+    km.k_max = G.k_max;
+    km.KP = G.KP;
+    km.SK = G.SK;
+    km.groups = G.groups;
+    km.chunks = P.chunks;
+    km.chunk_len = P.chunk_len;
+    km.race_grid = P.race_grid;
+    km.ks = P.meta;
+    km.koff16 = P.meta ? P.meta + G.Kc : nullptr;
+    km.koff = P.meta ? P.meta + 2 * G.Kc : nullptr;
+    km.grp = P.meta ? P.meta + 3 * G.Kc : nullptr;
+    km.cand_of = P.meta ? P.meta + 3 * G.Kc + G.grp.size() : nullptr;
+    km.active = a.take<int32_t>(G.Kc);
+    km.changes = a.take<int32_t>(G.Kc);
+    P.iters_int = a.take<int32_t>(G.Kc);
+    km.iters = P.iters_int;
+    km.active_count = a.take<int32_t>(1);
+    km.C = a.take<float>((size_t)G.KP * P.d);
+    km.cnorm = a.take<float>(G.KP);
+    km.psum = a.take<float>((size_t)P.chunks * G.KP * P.d);
+    km.pcnt = a.take<int32_t>((size_t)P.chunks * G.KP);
+    km.w = a.take<float>(n);
+    km.race_val = a.take<double>(P.race_grid);
+    km.race_idx = a.take<int32_t>(P.race_grid);
+    km.race_counter = a.take<uint32_t>(1);
+    P.picks_int = a.take<int32_t>(G.k_max);
+    km.picks = P.picks_int;
+    km.lab_cm = a.take<uint8_t>((size_t)G.Kc * n);
+    km.status = ctx->d_status;
+    // scores
+    ScorePlan& sc = P.sc;
+    sc.n = n;
+    sc.Kc = G.Kc;
+    sc.S = P.S;
+    sc.SK = G.SK;
+    sc.grid = P.score_grid_;
+    sc.nnz = g->nnz;
+    sc.ks = km.ks;
+    sc.koff = km.koff;
+    sc.lpart = a.take<int32_t>((size_t)P.score_grid_ * G.SK);
+    sc.vpart = a.take<int32_t>((size_t)P.score_grid_ * G.SK);
+    sc.l64 = a.take<int64_t>(G.SK);
+    sc.v64 = a.take<int64_t>(G.SK);
+    P.mod_int = a.take<double>(G.Kc);
+    P.ncut_int = a.take<double>(G.Kc);
+    sc.mod = P.mod_int;
+    sc.ncut = P.ncut_int;
+    sc.best = a.take<int32_t>(1);
+    sc.first = a.take<int32_t>(RAFT_MAX_K + 1);
+    sc.remap = a.take<int32_t>(RAFT_MAX_K + 1);
+    sc.status = ctx->d_status;
+    P.ksel_int = a.take<int32_t>(4);
+    P.lab_pm = a.take<uint8_t>((size_t)n * P.S);
+    P.bytes = a.off;
+}
+
+raft_status upload_meta(raft_ctx* ctx, const Plan& P, hipStream_t st) {
+    const Grid& G = P.grid;
+    std::vector<int32_t> meta;
+    meta.insert(meta.end(), G.ks.begin(), G.ks.end());
+    meta.insert(meta.end(), G.koff16.begin(), G.koff16.end());
+    meta.insert(meta.end(), G.koff.begin(), G.koff.end());
+    meta.insert(meta.end(), G.grp.begin(), G.grp.end());
+    meta.insert(meta.end(), G.cand_of.begin(), G.cand_of.end());
+    HIP_TRY(ctx, hipMemcpyAsync(P.meta, meta.data(), meta.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, st));
+    // pageable source: wait so the host vector may go out of scope
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    return RAFT_OK;
+}
+
+raft_status check_ws(raft_ctx* ctx, void* ws, size_t ws_bytes, size_t need) {
+    if (!ws) return fail(ctx, RAFT_E_INVAL, "workspace is null");
+    if (reinterpret_cast<uintptr_t>(ws) % 256)
+        return fail(ctx, RAFT_E_INVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(ctx, RAFT_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, need);
+    return RAFT_OK;
+}
+
+raft_status check_graph(raft_ctx* ctx, const raft_graph* g) {
+    if (!ctx) return RAFT_E_INVAL;
+    if (!g) return fail(ctx, RAFT_E_INVAL, "graph is null");
+    if (g->ctx != ctx) return fail(ctx, RAFT_E_INVAL, "graph belongs to another context");
+    return RAFT_OK;
+}
+
+raft_status launch_check(raft_ctx* ctx) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(ctx, RAFT_E_DEVICE, "kernel launch: %s", hipGetErrorString(e));
+    return RAFT_OK;
+}
+
+// Y = X^q Theta into `out` using the plan's ping-pong buffers.
+raft_status do_project(raft_ctx* ctx, const raft_graph* g, const raft_config* c, Plan& P,
+                       float* out, hipStream_t st) {
+    const int L = P.L;
+    const GraphView gv = g->view();
+    float* src = P.y0;
+    launch_gaussian(c->seed, 0x10, g->n, L, 1.0 / std::sqrt((double)L), src, st);
+    const bool mod_full = c->op == RAFT_X_MOD_FULL;
+    if (mod_full) {
+        launch_colsum_partials(gv, L, src, P.cpart, ctx->num_cu, st);
+        launch_colsum_finish(P.cpart, spmm_grid(g->n, L, ctx->num_cu, nullptr), L, P.c64, P.cvec,
+                             st);
+    }
+    for (int t = 1; t <= c->q; ++t) {
+        float* dst = (t == c->q) ? out : (src == P.y0 ? P.y1 : P.y0);
+        const bool need_cs = mod_full && t < c->q;
+        launch_spmm(gv, c->op, L, src, dst, P.cvec, need_cs ? P.cpart : nullptr, ctx->num_cu, st);
+        if (need_cs)
+            launch_colsum_finish(P.cpart, spmm_grid(g->n, L, ctx->num_cu, nullptr), L, P.c64,
+                                 P.cvec, st);
+        src = dst;
+    }
+    return launch_check(ctx);
+}
+
+raft_status do_embed(raft_ctx* ctx, const raft_graph* g, const raft_config* c, Plan& P,
+                     const float* Y, float* Z, hipStream_t st) {
+    const GraphView gv = g->view();
+    const float* h = Y;
+    int lin = P.L;
+    if (c->n_layers == 0) {
+        if (Z != Y)
+            HIP_TRY(ctx, hipMemcpyAsync(Z, Y, (size_t)g->n * lin * sizeof(float),
+                                        hipMemcpyDeviceToDevice, st));
+        if (c->normalize_input) launch_rownorm(Z, g->n, lin, st);
+        return launch_check(ctx);
+    }
+    if (c->normalize_input) {
+        HIP_TRY(ctx, hipMemcpyAsync(P.y1, Y, (size_t)g->n * lin * sizeof(float),
+                                    hipMemcpyDeviceToDevice, st));
+        launch_rownorm(P.y1, g->n, lin, st);
+        h = P.y1;
+    }
+    for (int k = 1; k <= c->n_layers; ++k) {
+        const int lout = c->layer_dims[k - 1];
+        launch_gaussian(c->seed, 0x10 + (uint64_t)k, lin, lout, 1.0 / std::sqrt((double)lin),
+                        P.wbuf, st);
+        launch_spmm(gv, kOpGcn, lin, h, P.pbuf, nullptr, nullptr, ctx->num_cu, st);
+        float* dst = (k == c->n_layers) ? Z : (h == P.y0 ? P.y1 : P.y0);
+        launch_dense_layer(P.pbuf, P.wbuf, dst, g->n, lin, lout, false, ctx->d_status, st);
+        h = dst;
+        lin = lout;
+    }
+    return launch_check(ctx);
+}
+
+raft_status do_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* c, Plan& P,
+                         const float* Z, raft_outputs* out, hipStream_t st, bool timed) {
+    KmeansPlan km = P.km;
+    if (out && out->picks) km.picks = out->picks;
+    if (out && out->iters) km.iters = out->iters;
+    ScorePlan sc = P.sc;
+    if (out && out->mod) sc.mod = out->mod;
+    if (out && out->ncut) sc.ncut = out->ncut;
+    int32_t* ksel = (out && out->k_selected) ? out->k_selected : P.ksel_int;
+    const int t_max = c->kmeans_max_iter;
+    const int check = c->check_every > 0 ? c->check_every : 4;
+    if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[2], st));
+    launch_kmeans_reset(km, st);
+    for (int t = 0; t < km.k_max; ++t) launch_race_pick(km, Z, t, c->seed, st);
+    launch_init_centres(km, Z, st);
+    RAFT_TRY(launch_check(ctx));
+    if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[3], st));
+    for (int it = 1; it <= t_max; ++it) {
+        launch_assign(km, Z, st);
+        launch_iter_finalize(km, it, t_max, st);
+        if (it == t_max) break;
+        launch_update(km, Z, ctx->lds_max, st);
+        if (it % check == 0) {
+            HIP_TRY(ctx, hipMemcpyAsync(ctx->h_pinned, km.active_count, sizeof(int32_t),
+                                        hipMemcpyDeviceToHost, st));
+            HIP_TRY(ctx, hipStreamSynchronize(st));
+            if (ctx->h_pinned[0] == 0) break;
+        }
+    }
+    RAFT_TRY(launch_check(ctx));
+    if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[4], st));
+    launch_transpose_labels(km.lab_cm, g->n, P.grid.Kc, P.lab_pm, P.S, st);
+    launch_edge_score(g->view(), sc, P.lab_pm, st);
+    launch_score_finish(sc, st);
+    launch_select(sc, P.lab_pm, out ? out->labels : nullptr, ksel, st);
+    if (out && out->labels_all)
+        launch_copy_labels(P.lab_pm, g->n, P.grid.Kc, P.S, out->labels_all, st);
+    if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[5], st));
+    return launch_check(ctx);
+}
+
+raft_status plan_for(raft_ctx* ctx, const raft_graph* g, const raft_config* c, void* ws,
+                     size_t ws_bytes, Plan& P) {
+    RAFT_TRY(check_config(ctx, g, c));
+    plan_layout(ctx, g, c, nullptr, P);
+    const int d = embed_dim(c);
+    if (!kmeans_supported(d)) return fail(ctx, RAFT_E_UNSUPPORTED, "embedding width %d", d);
+    if (kmeans_update_waves(P.grid.k_max, d, ctx->lds_max) < 1)
+        return fail(ctx, RAFT_E_UNSUPPORTED, "k_max %d too large for width %d", P.grid.k_max, d);
+    if (!score_supported(P.grid.SK))
+        return fail(ctx, RAFT_E_UNSUPPORTED, "sum of candidate K %d > 16384", P.grid.SK);
+    RAFT_TRY(check_ws(ctx, ws, ws_bytes, P.bytes));
+    plan_layout(ctx, g, c, reinterpret_cast<char*>(ws), P);
+    return RAFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t raft_abi_version(void) { return RAFT_ABI_VERSION; }
+
+const char* raft_status_string(raft_status s) {
+    switch (s) {
+        case RAFT_OK: return "ok";
+        case RAFT_E_INVAL: return "invalid argument";
+        case RAFT_E_CSR: return "malformed CSR";
+        case RAFT_E_NOEDGES: return "graph has no edges";
+        case RAFT_E_WORKSPACE: return "workspace too small";
+        case RAFT_E_NOMEM: return "out of device memory";
+        case RAFT_E_DEVICE: return "HIP runtime error";
+        case RAFT_E_NUMERIC: return "non-finite value";
+        case RAFT_E_UNSUPPORTED: return "unsupported size";
+        default: return "unknown status";
+    }
+}
+
+raft_status raft_ctx_create(int device, raft_ctx** out) {
+    if (!out) return RAFT_E_INVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return RAFT_E_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return RAFT_E_DEVICE;
+    raft_ctx* c = new raft_ctx();
+    c->device = device;
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+        cu > 0)
+        c->num_cu = cu;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeSharedMemPerBlockOptin, device) ==
+            hipSuccess &&
+        lds > 0)
+        c->lds_max = (size_t)lds;
+    else if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
+                 hipSuccess &&
+             lds > 0)
+        c->lds_max = (size_t)lds;
+    if (hipMalloc(&c->d_status, 256) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_pinned, 64, hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return RAFT_E_NOMEM;
+    }
+    if (hipMemset(c->d_status, 0, 256) != hipSuccess) {
+        delete c;
+        return RAFT_E_DEVICE;
+    }
+    for (auto& e : c->ev) (void)hipEventCreate(&e);
+    *out = c;
+    return RAFT_OK;
+}
+
+void raft_ctx_destroy(raft_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipDeviceSynchronize();
+    for (auto& e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->d_status) (void)hipFree(ctx->d_status);
+    if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
+    delete ctx;
+}
+
+size_t raft_last_error(raft_ctx* ctx, char* buf, size_t n) {
+    if (!ctx) return 0;
+    if (buf && n) {
+        const size_t m = std::min(n - 1, ctx->err.size());
+        memcpy(buf, ctx->err.data(), m);
+        buf[m] = 0;
+    }
+    return ctx->err.size();
+}
+
+raft_status raft_sync_status(raft_ctx* ctx, void* stream) {
+    if (!ctx) return RAFT_E_INVAL;
+    hipStream_t st = as_stream(stream);
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->h_pinned, ctx->d_status, sizeof(int32_t),
+                                hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    const int32_t s = ctx->h_pinned[0];
+    if (s) {
+        HIP_TRY(ctx, hipMemsetAsync(ctx->d_status, 0, sizeof(int32_t), st));
+        HIP_TRY(ctx, hipStreamSynchronize(st));
+        if (s & kStatusNumeric) return fail(ctx, RAFT_E_NUMERIC, "non-finite value (status %#x)", s);
+        if (s & kStatusLabel) return fail(ctx, RAFT_E_INVAL, "label out of range (status %#x)", s);
+        return fail(ctx, RAFT_E_CSR, "device status %#x", s);
+    }
+    return RAFT_OK;
+}
+
+raft_status raft_graph_create(raft_ctx* ctx, const int32_t* row_ptr, const int32_t* col_idx,
+                              int64_t n, int64_t nnz, int inputs_on_device, void* stream,
+                              raft_graph** out) {
+    if (!ctx) return RAFT_E_INVAL;
+    if (!out) return fail(ctx, RAFT_E_INVAL, "out is null");
+    *out = nullptr;
+    if (!row_ptr || (nnz > 0 && !col_idx)) return fail(ctx, RAFT_E_INVAL, "null CSR array");
+    if (n < 1 || n >= INT32_MAX) return fail(ctx, RAFT_E_INVAL, "n = %lld", (long long)n);
+    if (nnz < 0 || nnz >= INT32_MAX) return fail(ctx, RAFT_E_INVAL, "nnz = %lld", (long long)nnz);
+    hipStream_t st = as_stream(stream);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    // row_ptr is checked on the host before any kernel indexes col_idx with it
+    std::vector<int32_t> h_rp((size_t)n + 1);
+    if (inputs_on_device) {
+        HIP_TRY(ctx, hipMemcpyAsync(h_rp.data(), row_ptr, h_rp.size() * sizeof(int32_t),
+                                    hipMemcpyDeviceToHost, st));
+        HIP_TRY(ctx, hipStreamSynchronize(st));
+    } else {
+        memcpy(h_rp.data(), row_ptr, h_rp.size() * sizeof(int32_t));
+    }
+    if (h_rp[0] != 0 || h_rp[n] != nnz)
+        return fail(ctx, RAFT_E_CSR, "row_ptr must start at 0 and end at nnz");
+    for (int64_t i = 0; i < n; ++i)
+        if (h_rp[i + 1] < h_rp[i]) return fail(ctx, RAFT_E_CSR, "row_ptr decreases at %lld", (long long)i);
+    if (nnz % 2) return fail(ctx, RAFT_E_CSR, "odd nnz cannot be a symmetric loop-free CSR");
+    raft_graph* g = new raft_graph();
+    g->ctx = ctx;
+    g->n = (int32_t)n;
+    g->nnz = nnz;
+    bool ok = hipMalloc(&g->rp, sizeof(int32_t) * (n + 1)) == hipSuccess &&
+              hipMalloc(&g->ci, sizeof(int32_t) * std::max<int64_t>(nnz, 1)) == hipSuccess &&
+              hipMalloc(&g->deg, sizeof(int32_t) * n) == hipSuccess &&
+              hipMalloc(&g->s, sizeof(float) * n) == hipSuccess &&
+              hipMalloc(&g->sh, sizeof(float) * n) == hipSuccess &&
+              hipMalloc(&g->dcoef, sizeof(float) * n) == hipSuccess;
+    if (!ok) {
+        raft_graph_destroy(g);
+        return fail(ctx, RAFT_E_NOMEM, "graph allocation failed");
+    }
+    const hipMemcpyKind kind = inputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    hipError_t e = hipMemcpyAsync(g->rp, h_rp.data(), sizeof(int32_t) * (n + 1),
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && nnz > 0)
+        e = hipMemcpyAsync(g->ci, col_idx, sizeof(int32_t) * nnz, kind, st);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->d_status, 0, sizeof(int32_t), st);
+    if (e != hipSuccess) {
+        raft_graph_destroy(g);
+        return fail(ctx, RAFT_E_DEVICE, "graph upload: %s", hipGetErrorString(e));
+    }
+    launch_validate_csr(g->rp, g->ci, g->n, ctx->d_status, ctx->num_cu, st);
+    launch_degrees(g->rp, g->n, nnz, g->deg, g->s, g->sh, g->dcoef, st);
+    e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->h_pinned, ctx->d_status, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        raft_graph_destroy(g);
+        return fail(ctx, RAFT_E_DEVICE, "graph validation: %s", hipGetErrorString(e));
+    }
+    const int32_t status = ctx->h_pinned[0];
+    if (status) {
+        (void)hipMemsetAsync(ctx->d_status, 0, sizeof(int32_t), st);
+        (void)hipStreamSynchronize(st);
+        raft_graph_destroy(g);
+        return fail(ctx, RAFT_E_CSR, "CSR invalid (%s%s%s%s%s)",
+                    (status & kStatusCsrRange) ? "range " : "",
+                    (status & kStatusCsrOrder) ? "order " : "",
+                    (status & kStatusCsrLoop) ? "self-loop " : "",
+                    (status & kStatusCsrSym) ? "asymmetric " : "",
+                    (status & kStatusCsrRowPtr) ? "row_ptr " : "");
+    }
+    *out = g;
+    return RAFT_OK;
+}
+
+void raft_graph_destroy(raft_graph* g) {
+    if (!g) return;
+    (void)hipDeviceSynchronize();
+    if (g->rp) (void)hipFree(g->rp);
+    if (g->ci) (void)hipFree(g->ci);
+    if (g->deg) (void)hipFree(g->deg);
+    if (g->s) (void)hipFree(g->s);
+    if (g->sh) (void)hipFree(g->sh);
+    if (g->dcoef) (void)hipFree(g->dcoef);
+    delete g;
+}
+
+raft_status raft_graph_degrees(const raft_graph* g, int32_t* deg_out, void* stream) {
+    if (!g || !deg_out) return RAFT_E_INVAL;
+    raft_ctx* ctx = g->ctx;
+    HIP_TRY(ctx, hipMemcpyAsync(deg_out, g->deg, sizeof(int32_t) * g->n, hipMemcpyDeviceToDevice,
+                                as_stream(stream)));
+    return RAFT_OK;
+}
+
+raft_status raft_workspace_size(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg,
+                                size_t* bytes) {
+    RAFT_TRY(check_graph(ctx, g));
+    if (!bytes) return fail(ctx, RAFT_E_INVAL, "bytes is null");
+    RAFT_TRY(check_config(ctx, g, cfg));
+    Plan P;
+    plan_layout(ctx, g, cfg, nullptr, P);
+    *bytes = P.bytes;
+    return RAFT_OK;
+}
+
+raft_status raft_gaussian(raft_ctx* ctx, uint64_t seed, uint64_t stream_id, int64_t rows,
+                          int64_t cols, double sigma, float* out, void* stream) {
+    if (!ctx) return RAFT_E_INVAL;
+    if (rows < 0 || cols < 0) return fail(ctx, RAFT_E_INVAL, "negative size");
+    if (rows * cols > 0 && !out) return fail(ctx, RAFT_E_INVAL, "out is null");
+    if (!std::isfinite(sigma)) return fail(ctx, RAFT_E_INVAL, "sigma not finite");
+    launch_gaussian(seed, stream_id, rows, cols, sigma, out, as_stream(stream));
+    return launch_check(ctx);
+}
+
+static size_t spmm_ws_bytes(raft_ctx* ctx, const raft_graph* g, int L) {
+    const int grid = spmm_grid(g->n, L, ctx->num_cu, nullptr);
+    return align256((size_t)grid * L * sizeof(double)) + align256(L * sizeof(double)) +
+           align256(L * sizeof(float));
+}
+
+raft_status raft_spmm(raft_ctx* ctx, const raft_graph* g, int32_t op, int32_t L,
+                      const float* Y_in, float* Y_out, void* ws, size_t ws_bytes, void* stream) {
+    RAFT_TRY(check_graph(ctx, g));
+    if (op < RAFT_X_NCUT || op > RAFT_X_GCN) return fail(ctx, RAFT_E_INVAL, "op %d", op);
+    if (!spmm_supported(L)) return fail(ctx, RAFT_E_UNSUPPORTED, "width %d", L);
+    if (!Y_in || !Y_out || Y_in == Y_out) return fail(ctx, RAFT_E_INVAL, "bad Y buffers");
+    if ((op == RAFT_X_MOD_FULL || op == RAFT_X_MOD_REDUCED) && g->nnz == 0)
+        return fail(ctx, RAFT_E_NOEDGES, "modularity needs e > 0");
+    hipStream_t st = as_stream(stream);
+    const GraphView gv = g->view();
+    if (op == RAFT_X_MOD_FULL) {
+        RAFT_TRY(check_ws(ctx, ws, ws_bytes, spmm_ws_bytes(ctx, g, L)));
+        Arena a;
+        a.base = reinterpret_cast<char*>(ws);
+        const int grid = spmm_grid(g->n, L, ctx->num_cu, nullptr);
+        double* cpart = a.take<double>((size_t)grid * L);
+        double* c64 = a.take<double>(L);
+        float* cvec = a.take<float>(L);
+        launch_colsum_partials(gv, L, Y_in, cpart, ctx->num_cu, st);
+        launch_colsum_finish(cpart, grid, L, c64, cvec, st);
+        launch_spmm(gv, op, L, Y_in, Y_out, cvec, nullptr, ctx->num_cu, st);
+    } else {
+        launch_spmm(gv, op, L, Y_in, Y_out, nullptr, nullptr, ctx->num_cu, st);
+    }
+    return launch_check(ctx);
+}
+
+raft_status raft_project(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg, void* ws,
+                         size_t ws_bytes, float* Y_out, void* stream) {
+    RAFT_TRY(check_graph(ctx, g));
+    if (!Y_out) return fail(ctx, RAFT_E_INVAL, "Y_out is null");
+    if (cfg && cfg->op != RAFT_X_NCUT && g->nnz == 0)
+        return fail(ctx, RAFT_E_NOEDGES, "modularity needs e > 0");
+    Plan P;
+    RAFT_TRY(plan_for(ctx, g, cfg, ws, ws_bytes, P));
+    return do_project(ctx, g, cfg, P, Y_out, as_stream(stream));
+}
+
+raft_status raft_gcn_layer(raft_ctx* ctx, const raft_graph* g, int32_t L_in, int32_t L_out,
+                           const float* H_in, const float* W, int32_t linear, float* H_out,
+                           float* P_out, void* ws, size_t ws_bytes, void* stream) {
+    RAFT_TRY(check_graph(ctx, g));
+    if (!dense_supported(L_in, L_out) || !spmm_supported(L_in))
+        return fail(ctx, RAFT_E_UNSUPPORTED, "widths %d -> %d", L_in, L_out);
+    if (!H_in || !W || !H_out) return fail(ctx, RAFT_E_INVAL, "null buffer");
+    hipStream_t st = as_stream(stream);
+    float* P = P_out;
+    if (!P) {
+        const size_t need = align256((size_t)g->n * L_in * sizeof(float));
+        RAFT_TRY(check_ws(ctx, ws, ws_bytes, need));
+        P = reinterpret_cast<float*>(ws);
+    }
+    launch_spmm(g->view(), kOpGcn, L_in, H_in, P, nullptr, nullptr, ctx->num_cu, st);
+    launch_dense_layer(P, W, H_out, g->n, L_in, L_out, linear != 0, ctx->d_status, st);
+    return launch_check(ctx);
+}
+
+raft_status raft_embed(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg, const float* Y,
+                       void* ws, size_t ws_bytes, float* Z_out, void* stream) {
+    RAFT_TRY(check_graph(ctx, g));
+    if (!Y || !Z_out) return fail(ctx, RAFT_E_INVAL, "null buffer");
+    Plan P;
+    RAFT_TRY(plan_for(ctx, g, cfg, ws, ws_bytes, P));
+    return do_embed(ctx, g, cfg, P, Y, Z_out, as_stream(stream));
+}
+
+raft_status raft_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg,
+                           const float* Z, void* ws, size_t ws_bytes, raft_outputs* out,
+                           void* stream) {
+    RAFT_TRY(check_graph(ctx, g));
+    if (!Z) return fail(ctx, RAFT_E_INVAL, "Z is null");
+    if (g->nnz == 0) return fail(ctx, RAFT_E_NOEDGES, "modularity needs e > 0");
+    Plan P;
+    RAFT_TRY(plan_for(ctx, g, cfg, ws, ws_bytes, P));
+    hipStream_t st = as_stream(stream);
+    RAFT_TRY(upload_meta(ctx, P, st));
+    return do_partition(ctx, g, cfg, P, Z, out, st, false);
+}
+
+raft_status raft_score(raft_ctx* ctx, const raft_graph* g, const uint8_t* labels_all, int32_t Kc,
+                       const int32_t* ks, double* mod, double* ncut, void* ws, size_t ws_bytes,
+                       void* stream) {
+    RAFT_TRY(check_graph(ctx, g));
+    if (!labels_all || !ks || !mod || !ncut || Kc < 1)
+        return fail(ctx, RAFT_E_INVAL, "bad score arguments");
+    if (g->nnz == 0) return fail(ctx, RAFT_E_NOEDGES, "modularity needs e > 0");
+    std::vector<int32_t> koff(Kc);
+    int SK = 0;
+    for (int k = 0; k < Kc; ++k) {
+        if (ks[k] < 1 || ks[k] > RAFT_MAX_K) return fail(ctx, RAFT_E_INVAL, "ks[%d] = %d", k, ks[k]);
+        koff[k] = SK;
+        SK += ks[k];
+    }
+    if (!score_supported(SK)) return fail(ctx, RAFT_E_UNSUPPORTED, "sum of K %d", SK);
+    const int S = (Kc + 3) / 4 * 4;
+    const int grid = score_grid(g->n, ctx->num_cu);
+    Arena a;
+    a.base = nullptr;
+    a.take<int32_t>(2 * (size_t)Kc);
+    a.take<uint8_t>((size_t)g->n * S);
+    a.take<int32_t>((size_t)grid * SK);
+    a.take<int32_t>((size_t)grid * SK);
+    a.take<int64_t>(SK);
+    a.take<int64_t>(SK);
+    RAFT_TRY(check_ws(ctx, ws, ws_bytes, a.off));
+    a.base = reinterpret_cast<char*>(ws);
+    a.off = 0;
+    hipStream_t st = as_stream(stream);
+    int32_t* meta = a.take<int32_t>(2 * (size_t)Kc);
+    uint8_t* pm = a.take<uint8_t>((size_t)g->n * S);
+    ScorePlan sc;
+    sc.n = g->n;
+    sc.Kc = Kc;
+    sc.S = S;
+    sc.SK = SK;
+    sc.grid = grid;
+    sc.nnz = g->nnz;
+    sc.ks = meta;
+    sc.koff = meta + Kc;
+    sc.lpart = a.take<int32_t>((size_t)grid * SK);
+    sc.vpart = a.take<int32_t>((size_t)grid * SK);
+    sc.l64 = a.take<int64_t>(SK);
+    sc.v64 = a.take<int64_t>(SK);
+    sc.mod = mod;
+    sc.ncut = ncut;
+    sc.best = nullptr;
+    sc.first = nullptr;
+    sc.remap = nullptr;
+    sc.status = ctx->d_status;
+    std::vector<int32_t> hm(ks, ks + Kc);
+    hm.insert(hm.end(), koff.begin(), koff.end());
+    HIP_TRY(ctx, hipMemcpyAsync(meta, hm.data(), hm.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    // dense point-major [n x Kc] -> stride-S layout
+    if (S == Kc) {
+        HIP_TRY(ctx, hipMemcpyAsync(pm, labels_all, (size_t)g->n * S, hipMemcpyDeviceToDevice, st));
+    } else {
+        HIP_TRY(ctx, hipMemset2DAsync(pm, S, 0, S, g->n, st));
+        HIP_TRY(ctx, hipMemcpy2DAsync(pm, S, labels_all, Kc, Kc, g->n, hipMemcpyDeviceToDevice, st));
+    }
+    launch_edge_score(g->view(), sc, pm, st);
+    launch_score_finish(sc, st);
+    return launch_check(ctx);
+}
+
+raft_status raft_run(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg, void* ws,
+                     size_t ws_bytes, raft_outputs* out, void* stream) {
+    RAFT_TRY(check_graph(ctx, g));
+    if (g->nnz == 0) return fail(ctx, RAFT_E_NOEDGES, "modularity needs e > 0");
+    Plan P;
+    RAFT_TRY(plan_for(ctx, g, cfg, ws, ws_bytes, P));
+    hipStream_t st = as_stream(stream);
+    RAFT_TRY(upload_meta(ctx, P, st));
+    float* Y = (out && out->Y) ? out->Y : P.yout;
+    float* Z = (out && out->Z) ? out->Z : P.zout;
+    HIP_TRY(ctx, hipEventRecord(ctx->ev[0], st));
+    RAFT_TRY(do_project(ctx, g, cfg, P, Y, st));
+    HIP_TRY(ctx, hipEventRecord(ctx->ev[1], st));
+    RAFT_TRY(do_embed(ctx, g, cfg, P, Y, Z, st));
+    RAFT_TRY(do_partition(ctx, g, cfg, P, Z, out, st, true));
+    HIP_TRY(ctx, hipEventSynchronize(ctx->ev[5]));
+    float ms = 0;
+    for (int s = 0; s < 5; ++s) {
+        if (hipEventElapsedTime(&ms, ctx->ev[s], ctx->ev[s + 1]) == hipSuccess)
+            ctx->stage_ms[s] = ms;
+    }
+    return RAFT_OK;
+}
+
+raft_status raft_get_stage_times(raft_ctx* ctx, double* ms5) {
+    if (!ctx || !ms5) return RAFT_E_INVAL;
+    for (int s = 0; s < 5; ++s) ms5[s] = ctx->stage_ms[s];
+    return RAFT_OK;
+}
+
+}  // extern "C"

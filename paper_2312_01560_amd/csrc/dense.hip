@@ -1,0 +1,151 @@
+// Dense part of a GCN layer (Sec. III-B, Eq. 6): U = P W with P = A_hat_n H,
+// Z = tanh(U), rows L2-normalised (the normalisation the paper applies before
+// the next layer and to the final embedding).
+//
+// MFMA FP32 (v_mfma_f32_16x16x4f32): a wave computes a 16-row tile against
+// all output columns.  The contraction index is permuted so that each lane's
+// A operand is a contiguous run of its P row (lane group g = lane/16 owns
+// k = g*LIN/4 .. g*LIN/4 + LIN/4 - 1), loaded with float4; B is read from W
+// with the same permutation.  The 16x16 result block of a wave keeps rows
+// 4g..4g+3 in lane group g, columns in lane%16, so a row norm is an in-lane
+// sum over column blocks plus a 16-lane xor reduction.
+#include "kernels.h"
+
+namespace raft {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+template <int LIN, int LOUT, bool LINEAR>
+__global__ __launch_bounds__(256) void k_dense(const float* __restrict__ P,
+                                               const float* __restrict__ W,
+                                               float* __restrict__ H, int n,
+                                               int32_t* __restrict__ status) {
+    constexpr int KS = LIN / 4;
+    constexpr int NB = LOUT / 16;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int g = lane >> 4;
+    const int li = lane & 15;
+    const int row0 = (blockIdx.x * 4 + wid) * 16;
+    if (row0 >= n) return;
+    const int ra = min(row0 + li, n - 1);
+    float a[KS];
+    const float* prow = P + (size_t)ra * LIN + g * KS;
+#pragma unroll
+    for (int s = 0; s < KS; s += 4) {
+        const float4 v = *reinterpret_cast<const float4*>(prow + s);
+        a[s] = v.x;
+        a[s + 1] = v.y;
+        a[s + 2] = v.z;
+        a[s + 3] = v.w;
+    }
+    floatx4 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        acc[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const float* wcol = W + (size_t)(g * KS) * LOUT + nb * 16 + li;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const float b = wcol[(size_t)s * LOUT];
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b, acc[nb], 0, 0, 0);
+        }
+    }
+    float inv[4] = {1.f, 1.f, 1.f, 1.f};
+    if (!LINEAR) {
+        float ss[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float z = tanhf(acc[nb][v]);
+                acc[nb][v] = z;
+                ss[v] += z * z;
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) ss[v] += __shfl_xor(ss[v], off, kWave);
+            const float nrm = sqrtf(ss[v]);
+            if (!(nrm <= 3.0e38f)) atomicOr(status, kStatusNumeric);
+            inv[v] = 1.0f / fmaxf(nrm, 1e-12f);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int row = row0 + 4 * g + v;
+        if (row < n) {
+            float* hrow = H + (size_t)row * LOUT + li;
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) hrow[nb * 16] = acc[nb][v] * inv[v];
+        }
+    }
+}
+
+// Row L2 normalisation, one wave per row, lanes over columns.
+__global__ __launch_bounds__(256) void k_rownorm(float* __restrict__ x, int n, int L) {
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (wave >= n) return;
+    float* row = x + (size_t)wave * L;
+    float ss = 0.f;
+    for (int c = lane; c < L; c += kWave) ss += row[c] * row[c];
+    ss = wave_sum(ss);
+    const float inv = 1.0f / fmaxf(sqrtf(ss), 1e-12f);
+    for (int c = lane; c < L; c += kWave) row[c] *= inv;
+}
+
+static bool pow2_width(int v) { return v == 16 || v == 32 || v == 64 || v == 128 || v == 256; }
+
+bool dense_supported(int lin, int lout) {
+    return pow2_width(lin) && pow2_width(lout) && lin * lout <= 128 * 256;
+}
+
+template <int LIN, int LOUT>
+static void dense_launch2(const float* P, const float* W, float* H, int32_t n, bool linear,
+                          int32_t* status, hipStream_t st) {
+    const int grid = (n + 63) / 64;
+    if (linear)
+        hipLaunchKernelGGL((k_dense<LIN, LOUT, true>), dim3(grid), dim3(256), 0, st, P, W, H, n,
+                           status);
+    else
+        hipLaunchKernelGGL((k_dense<LIN, LOUT, false>), dim3(grid), dim3(256), 0, st, P, W, H, n,
+                           status);
+}
+
+template <int LIN>
+static void dense_launch1(const float* P, const float* W, float* H, int32_t n, int lout,
+                          bool linear, int32_t* status, hipStream_t st) {
+    switch (lout) {
+        case 16: dense_launch2<LIN, 16>(P, W, H, n, linear, status, st); break;
+        case 32: dense_launch2<LIN, 32>(P, W, H, n, linear, status, st); break;
+        case 64: dense_launch2<LIN, 64>(P, W, H, n, linear, status, st); break;
+        case 128: dense_launch2<LIN, 128>(P, W, H, n, linear, status, st); break;
+        case 256:
+            if constexpr (LIN <= 128) dense_launch2<LIN, 256>(P, W, H, n, linear, status, st);
+            break;
+        default: break;
+    }
+}
+
+void launch_dense_layer(const float* P, const float* W, float* H, int32_t n, int lin, int lout,
+                        bool linear, int32_t* status, hipStream_t st) {
+    if (n == 0) return;
+    switch (lin) {
+        case 16: dense_launch1<16>(P, W, H, n, lout, linear, status, st); break;
+        case 32: dense_launch1<32>(P, W, H, n, lout, linear, status, st); break;
+        case 64: dense_launch1<64>(P, W, H, n, lout, linear, status, st); break;
+        case 128: dense_launch1<128>(P, W, H, n, lout, linear, status, st); break;
+        case 256: dense_launch1<256>(P, W, H, n, lout, linear, status, st); break;
+        default: break;
+    }
+}
+
+void launch_rownorm(float* x, int32_t n, int L, hipStream_t st) {
+    if (n == 0) return;
+    const int64_t threads = (int64_t)n * kWave;
+    hipLaunchKernelGGL(k_rownorm, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, x, n,
+                       L);
+}
+
+}  // namespace raft

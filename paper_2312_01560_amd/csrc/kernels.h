@@ -1,0 +1,136 @@
+// Kernel launchers of the HIP path (internal interface between the C ABI and
+// the .hip translation units).  All launches are asynchronous on `st`.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace raft {
+
+// ---- graph.hip -----------------------------------------------------------
+void launch_validate_csr(const int32_t* rp, const int32_t* ci, int32_t n, int32_t* status,
+                         int num_cu, hipStream_t st);
+void launch_degrees(const int32_t* rp, int32_t n, int64_t nnz, int32_t* deg, float* s, float* sh,
+                    float* dcoef, hipStream_t st);
+
+// ---- gauss.hip -----------------------------------------------------------
+void launch_gaussian(uint64_t seed, uint64_t stream_id, int64_t rows, int64_t cols, double sigma,
+                     float* out, hipStream_t st);
+
+// ---- spmm.hip ------------------------------------------------------------
+enum SpmmOp { kOpNcut = 0, kOpModFull = 1, kOpModReduced = 2, kOpGcn = 3 };
+
+struct GraphView {
+    int32_t n;
+    int64_t nnz;
+    const int32_t* rp;
+    const int32_t* ci;
+    const int32_t* deg;
+    const float* s;      // D^-1/2 (0 for isolated nodes)
+    const float* sh;     // (D+1)^-1/2
+    const float* dcoef;  // d_i / 2e
+};
+
+// Grid size (work-groups) of one SpMM launch; colsum partial buffers hold
+// spmm_grid(...) * L doubles.
+int spmm_grid(int32_t n, int L, int num_cu, int* rows_per_wave);
+bool spmm_supported(int L);
+// y = X x for operator op.  cvec: FP32 d^T x (MOD_FULL only).  If colsum_part
+// is non-null, also writes per-work-group FP64 partials of d^T y.
+void launch_spmm(const GraphView& g, int op, int L, const float* x, float* y, const float* cvec,
+                 double* colsum_part, int num_cu, hipStream_t st);
+// FP64 partials of d^T x over row blocks (grid = spmm_grid(...)).
+void launch_colsum_partials(const GraphView& g, int L, const float* x, double* part, int num_cu,
+                            hipStream_t st);
+// c = sum of `parts` partial rows (fixed order), cvec = FP32(c).
+void launch_colsum_finish(const double* part, int parts, int L, double* c64, float* cvec,
+                          hipStream_t st);
+
+// ---- dense.hip -----------------------------------------------------------
+bool dense_supported(int lin, int lout);
+// H = rownorm(tanh(P W)) (or U = P W when linear), P [n x lin], W [lin x lout].
+void launch_dense_layer(const float* P, const float* W, float* H, int32_t n, int lin, int lout,
+                        bool linear, int32_t* status, hipStream_t st);
+// Row L2 normalisation in place (x / max(||x||, 1e-12)).
+void launch_rownorm(float* x, int32_t n, int L, hipStream_t st);
+
+// ---- kmeans.hip ----------------------------------------------------------
+struct KmeansPlan {
+    int32_t n, d, Kc, k_max;
+    int32_t KP;          // padded centre rows (sum of ceil16(K))
+    int32_t SK;          // real centre count (sum of K)
+    int32_t groups;      // candidate groups of the assignment kernel
+    int32_t chunks;      // point chunks of the update kernel
+    int32_t chunk_len;
+    int32_t race_grid;
+    // device arrays
+    const int32_t* ks;       // [Kc]
+    const int32_t* koff16;   // [Kc] padded centre offsets
+    const int32_t* koff;     // [Kc] real offsets (score tables)
+    const int32_t* grp;      // [groups + 1] candidate ranges of the groups
+    const int32_t* cand_of;  // [KP] candidate of each padded centre row
+    int32_t* active;         // [Kc]
+    int32_t* changes;        // [Kc]
+    int32_t* iters;          // [Kc]
+    int32_t* active_count;   // [1]
+    float* C;                // [KP x d]
+    float* cnorm;            // [KP]
+    float* psum;             // [chunks x KP x d]
+    int32_t* pcnt;           // [chunks x KP]
+    float* w;                // [n]
+    double* race_val;        // [race_grid]
+    int32_t* race_idx;       // [race_grid]
+    uint32_t* race_counter;  // [1]
+    int32_t* picks;          // [k_max]
+    uint8_t* lab_cm;         // [Kc x n] candidate-major labels
+    int32_t* status;
+};
+
+bool kmeans_supported(int d);
+int kmeans_race_grid(int32_t n, int num_cu);
+void launch_kmeans_reset(const KmeansPlan& p, hipStream_t st);
+void launch_race_pick(const KmeansPlan& p, const float* Z, int t, uint64_t seed, hipStream_t st);
+void launch_init_centres(const KmeansPlan& p, const float* Z, hipStream_t st);
+void launch_assign(const KmeansPlan& p, const float* Z, hipStream_t st);
+void launch_iter_finalize(const KmeansPlan& p, int it, int t_max, hipStream_t st);
+void launch_update(const KmeansPlan& p, const float* Z, size_t lds_max, hipStream_t st);
+// LDS bytes the update kernel needs per work-group for the largest K.
+size_t kmeans_update_lds(int k_max, int d, int waves);
+int kmeans_update_waves(int k_max, int d, size_t lds_max);
+
+// ---- score.hip -----------------------------------------------------------
+struct ScorePlan {
+    int32_t n, Kc, S;     // S = row stride of point-major labels (multiple of 4)
+    int32_t SK;           // sum of K
+    int32_t grid;
+    int64_t nnz;
+    const int32_t* ks;
+    const int32_t* koff;
+    int32_t* lpart;       // [grid x SK]
+    int32_t* vpart;       // [grid x SK]
+    int64_t* l64;         // [SK]
+    int64_t* v64;         // [SK]
+    double* mod;          // [Kc]
+    double* ncut;         // [Kc]
+    int32_t* best;        // [1]
+    int32_t* first;       // [RAFT_MAX_K + 1]
+    int32_t* remap;       // [RAFT_MAX_K + 1]
+    int32_t* status;
+};
+
+int score_grid(int32_t n, int num_cu);
+bool score_supported(int SK);
+void launch_transpose_labels(const uint8_t* cm, int32_t n, int Kc, uint8_t* pm, int S,
+                             hipStream_t st);
+void launch_edge_score(const GraphView& g, const ScorePlan& p, const uint8_t* lab_pm,
+                       hipStream_t st);
+void launch_score_finish(const ScorePlan& p, hipStream_t st);
+// Selection of K* (first maximum of Mod) and canonical relabelling.
+void launch_select(const ScorePlan& p, const uint8_t* lab_pm, int32_t* labels_out,
+                   int32_t* k_selected, hipStream_t st);
+// Copy point-major labels [n x S] into a dense [n x Kc] output.
+void launch_copy_labels(const uint8_t* pm, int32_t n, int Kc, int S, uint8_t* out, hipStream_t st);
+
+}  // namespace raft

@@ -1,0 +1,509 @@
+// k-means over every candidate block count of the grid at once (the paper
+// clusters the embedding with KMeans, Sec. II and Sec. III-C; the grid of
+// candidates is scored afterwards).
+//
+// Seeding: nested k-means++ picks by an exponential race: pick t is
+//   argmin_{i: w_i > 0} E_{t,i} / w_i,  E_{t,i} = -ln u(Philox(i, t | seed, 0x20)),
+// w_i = 1 before the first pick, then the squared distance to the nearest
+// pick (ties to the lowest index; all-zero weights take the lowest unpicked
+// index).  One launch per pick; the last work-group to finish reduces the
+// per-group minima (lexicographic on (ratio, index), so the result does not
+// depend on scheduling).
+//
+// Lloyd, all candidates together: the assignment is a dense contraction of
+// the points against the table of all centres (rows of each candidate padded
+// to a multiple of 16), on MFMA (v_mfma_f32_16x16x4f32), score
+// ||c||^2 - 2 z.c, argmin per candidate segment with ties to the lowest
+// index.  The update accumulates per (point chunk, candidate) in LDS: each
+// wave owns a private copy and each lane a column, so every LDS address is
+// updated by one lane in program order and the sums are deterministic; the
+// chunk partials are combined in fixed order in FP64.
+#include <float.h>
+#include <limits.h>
+
+#include <algorithm>
+
+#include "kernels.h"
+
+namespace raft {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr uint64_t kStreamRace = 0x20;
+constexpr int kRaceThreads = 256;
+
+__device__ __forceinline__ bool lex_less(double v, int i, double bv, int bi) {
+    return v < bv || (v == bv && i < bi);
+}
+
+template <int D>
+__global__ __launch_bounds__(kRaceThreads) void k_race(KmeansPlan p, const float* __restrict__ Z,
+                                                       int t, uint64_t seed) {
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int stride = gridDim.x * blockDim.x;
+    double best = INFINITY;
+    int bidx = INT_MAX;
+    const int prev = t > 0 ? p.picks[t - 1] : -1;
+    const float* zp = prev >= 0 ? Z + (size_t)prev * D : Z;
+    for (int i = tid; i < p.n; i += stride) {
+        float wi = 1.0f;
+        if (t > 0) {
+            const float* zi = Z + (size_t)i * D;
+            float dist = 0.f;
+#pragma unroll 4
+            for (int c = 0; c < D; c += 4) {
+                const float4 a = *reinterpret_cast<const float4*>(zi + c);
+                const float4 b = *reinterpret_cast<const float4*>(zp + c);
+                const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z, dw = a.w - b.w;
+                dist += dx * dx;
+                dist += dy * dy;
+                dist += dz * dz;
+                dist += dw * dw;
+            }
+            wi = (t == 1) ? dist : fminf(p.w[i], dist);
+            p.w[i] = wi;
+        }
+        if (wi > 0.f) {
+            const U64x4 b = philox4x64_10((uint64_t)i, (uint64_t)t, 0, 0, seed, kStreamRace);
+            const double e = -own_ln(uniform52(b.v[0]));
+            const double ratio = e / (double)wi;
+            if (ratio < best) {
+                best = ratio;
+                bidx = i;
+            }
+        }
+    }
+    // work-group reduction
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(best, off, kWave);
+        const int oi = __shfl_xor(bidx, off, kWave);
+        if (lex_less(ov, oi, best, bidx)) {
+            best = ov;
+            bidx = oi;
+        }
+    }
+    __shared__ double sv[kRaceThreads / kWave];
+    __shared__ int si[kRaceThreads / kWave];
+    __shared__ bool last;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    if (lane == 0) {
+        sv[wid] = best;
+        si[wid] = bidx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = sv[0];
+        int bi = si[0];
+        for (int w = 1; w < kRaceThreads / kWave; ++w)
+            if (lex_less(sv[w], si[w], b, bi)) {
+                b = sv[w];
+                bi = si[w];
+            }
+        p.race_val[blockIdx.x] = b;
+        p.race_idx[blockIdx.x] = bi;
+        __threadfence();
+        const unsigned prev_cnt = atomicAdd(p.race_counter, 1u);
+        last = (prev_cnt == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    // last work-group: reduce all group minima
+    best = INFINITY;
+    bidx = INT_MAX;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
+        const double v = __hip_atomic_load(&p.race_val[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int i = __hip_atomic_load(&p.race_idx[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lex_less(v, i, best, bidx)) {
+            best = v;
+            bidx = i;
+        }
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(best, off, kWave);
+        const int oi = __shfl_xor(bidx, off, kWave);
+        if (lex_less(ov, oi, best, bidx)) {
+            best = ov;
+            bidx = oi;
+        }
+    }
+    __syncthreads();
+    if (lane == 0) {
+        sv[wid] = best;
+        si[wid] = bidx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = sv[0];
+        int bi = si[0];
+        for (int w = 1; w < kRaceThreads / kWave; ++w)
+            if (lex_less(sv[w], si[w], b, bi)) {
+                b = sv[w];
+                bi = si[w];
+            }
+        if (bi == INT_MAX) {
+            // every weight is zero: lowest index not picked yet (at most t)
+            for (int c = 0; c <= t; ++c) {
+                bool taken = false;
+                for (int q = 0; q < t; ++q) taken |= (p.picks[q] == c);
+                if (!taken) {
+                    bi = c;
+                    break;
+                }
+            }
+        }
+        p.picks[t] = bi;
+        *p.race_counter = 0u;
+    }
+}
+
+// Copy the first K picks of every candidate into its centre rows; padding
+// rows are zero with norm +inf.  One wave per padded centre row.
+template <int D>
+__global__ __launch_bounds__(256) void k_init_centres(KmeansPlan p, const float* __restrict__ Z) {
+    const int c = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (c >= p.KP) return;
+    const int k = p.cand_of[c];
+    const int r = c - p.koff16[k];
+    float* crow = p.C + (size_t)c * D;
+    if (r >= p.ks[k]) {
+        for (int dd = lane; dd < D; dd += kWave) crow[dd] = 0.f;
+        if (lane == 0) p.cnorm[c] = INFINITY;
+        return;
+    }
+    const float* z = Z + (size_t)p.picks[r] * D;
+    float ss = 0.f;
+    for (int dd = lane; dd < D; dd += kWave) {
+        const float v = z[dd];
+        crow[dd] = v;
+        ss += v * v;
+    }
+    ss = wave_sum(ss);
+    if (lane == 0) p.cnorm[c] = ss;
+}
+
+// Assignment for all active candidates of one candidate group.
+// Grid: x = point tiles (4 waves x 16*PS points), y = candidate group.
+template <int D, int PS>
+__global__ __launch_bounds__(256) void k_assign(KmeansPlan p, const float* __restrict__ Z) {
+    constexpr int KS = D / 4;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int g = lane >> 4;
+    const int li = lane & 15;
+    const int pbase = (blockIdx.x * 4 + wid) * 16 * PS;
+    if (pbase >= p.n) return;
+    float b[PS][KS];
+#pragma unroll
+    for (int ps = 0; ps < PS; ++ps) {
+        const int pt = min(pbase + 16 * ps + li, p.n - 1);
+        const float* zr = Z + (size_t)pt * D + g * KS;
+#pragma unroll
+        for (int s = 0; s < KS; s += 4) {
+            const float4 v = *reinterpret_cast<const float4*>(zr + s);
+            b[ps][s] = v.x;
+            b[ps][s + 1] = v.y;
+            b[ps][s + 2] = v.z;
+            b[ps][s + 3] = v.w;
+        }
+    }
+    const int k0 = p.grp[blockIdx.y], k1 = p.grp[blockIdx.y + 1];
+    for (int k = k0; k < k1; ++k) {
+        if (!p.active[k]) continue;
+        const int K = p.ks[k];
+        const int c0 = p.koff16[k];
+        const int ntiles = (K + 15) >> 4;
+        float bv[PS];
+        int bi[PS];
+#pragma unroll
+        for (int ps = 0; ps < PS; ++ps) {
+            bv[ps] = INFINITY;
+            bi[ps] = 0;
+        }
+        for (int tile = 0; tile < ntiles; ++tile) {
+            const int cb = c0 + tile * 16;
+            float a[KS];
+            const float* cr = p.C + (size_t)(cb + li) * D + g * KS;
+#pragma unroll
+            for (int s = 0; s < KS; s += 4) {
+                const float4 v = *reinterpret_cast<const float4*>(cr + s);
+                a[s] = v.x;
+                a[s + 1] = v.y;
+                a[s + 2] = v.z;
+                a[s + 3] = v.w;
+            }
+            const float4 cn = *reinterpret_cast<const float4*>(p.cnorm + cb + 4 * g);
+            const float cnv[4] = {cn.x, cn.y, cn.z, cn.w};
+#pragma unroll
+            for (int ps = 0; ps < PS; ++ps) {
+                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < KS; ++s)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[ps][s], acc, 0, 0, 0);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float sc = cnv[v] - 2.0f * acc[v];
+                    if (sc < bv[ps]) {
+                        bv[ps] = sc;
+                        bi[ps] = tile * 16 + 4 * g + v;
+                    }
+                }
+            }
+        }
+        int mine = 0;
+#pragma unroll
+        for (int ps = 0; ps < PS; ++ps) {
+#pragma unroll
+            for (int off = 16; off < kWave; off <<= 1) {
+                const float ov = __shfl_xor(bv[ps], off, kWave);
+                const int oi = __shfl_xor(bi[ps], off, kWave);
+                if (ov < bv[ps] || (ov == bv[ps] && oi < bi[ps])) {
+                    bv[ps] = ov;
+                    bi[ps] = oi;
+                }
+            }
+            if (ps == g) mine = bi[ps];
+        }
+        const int pt = pbase + 16 * g + li;
+        bool changed = false;
+        if (g < PS && pt < p.n) {
+            uint8_t* lp = p.lab_cm + (size_t)k * p.n + pt;
+            const uint8_t old = *lp;
+            const uint8_t nw = (uint8_t)mine;
+            changed = old != nw;
+            *lp = nw;
+        }
+        const uint64_t m = __ballot(changed);
+        if (lane == 0 && m) atomicAdd(&p.changes[k], (int)__popcll(m));
+    }
+}
+
+// After an assignment: a candidate whose labels did not change (from the
+// second assignment on) has converged; count the remaining active ones.
+__global__ __launch_bounds__(256) void k_iter_finalize(KmeansPlan p, int it, int t_max) {
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    int mine = 0;
+    for (int k = threadIdx.x; k < p.Kc; k += blockDim.x) {
+        if (!p.active[k]) continue;
+        const int ch = p.changes[k];
+        p.changes[k] = 0;
+        if (it >= 2 && ch == 0) {
+            p.active[k] = 0;
+            p.iters[k] = it;
+        } else if (it >= t_max) {
+            p.active[k] = 0;
+            p.iters[k] = it;
+        } else {
+            ++mine;
+        }
+    }
+    atomicAdd(&cnt, mine);
+    __syncthreads();
+    if (threadIdx.x == 0) *p.active_count = cnt;
+}
+
+// Centre sums of one (point chunk, candidate).  Dynamic LDS:
+// float acc[W][K][D], int cnt[W][K].
+template <int D>
+__global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __restrict__ Z) {
+    const int k = blockIdx.y;
+    if (!p.active[k]) return;
+    extern __shared__ float lds[];
+    const int K = p.ks[k];
+    const int W = blockDim.x / kWave;
+    float* acc = lds;
+    int* cnt = reinterpret_cast<int*>(lds + (size_t)W * K * D);
+    for (int idx = threadIdx.x; idx < W * K * (D + 1); idx += blockDim.x) lds[idx] = 0.f;
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int p0 = blockIdx.x * p.chunk_len;
+    const int p1 = min(p.n, p0 + p.chunk_len);
+    const int len = max(0, p1 - p0);
+    const int per = (len + W - 1) / W;
+    const int q0 = p0 + wid * per;
+    const int q1 = min(p1, q0 + per);
+    const uint8_t* lab = p.lab_cm + (size_t)k * p.n;
+    float* my = acc + (size_t)wid * K * D;
+    int* myc = cnt + wid * K;
+    constexpr int CPL = D >= kWave ? D / kWave : 1;   // columns per lane
+    const bool lane_on = lane < D;
+    int q = q0;
+    for (; q + 4 <= q1; q += 4) {
+        int a[4];
+        float v[4][CPL];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] = lab[q + u];
+#pragma unroll
+            for (int c = 0; c < CPL; ++c)
+                v[u][c] = lane_on ? Z[(size_t)(q + u) * D + lane + c * kWave] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (lane_on) {
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) atomicAdd(&my[a[u] * D + lane + c * kWave], v[u][c]);
+            }
+            if (lane == 0) atomicAdd(&myc[a[u]], 1);
+        }
+    }
+    for (; q < q1; ++q) {
+        const int a = lab[q];
+        if (lane_on) {
+#pragma unroll
+            for (int c = 0; c < CPL; ++c)
+                atomicAdd(&my[a * D + lane + c * kWave], Z[(size_t)q * D + lane + c * kWave]);
+        }
+        if (lane == 0) atomicAdd(&myc[a], 1);
+    }
+    __syncthreads();
+    const size_t rowbase = (size_t)blockIdx.x * p.KP + p.koff16[k];
+    for (int idx = threadIdx.x; idx < K * D; idx += blockDim.x) {
+        float s = 0.f;
+        for (int w = 0; w < W; ++w) s += acc[(size_t)w * K * D + idx];
+        p.psum[rowbase * D + idx] = s;
+    }
+    for (int idx = threadIdx.x; idx < K; idx += blockDim.x) {
+        int s = 0;
+        for (int w = 0; w < W; ++w) s += cnt[w * K + idx];
+        p.pcnt[rowbase + idx] = s;
+    }
+}
+
+// Means from the chunk partials (fixed order, FP64); an empty cluster keeps
+// its centre.  One wave per padded centre row.
+template <int D>
+__global__ __launch_bounds__(256) void k_update_finish(KmeansPlan p) {
+    const int c = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (c >= p.KP) return;
+    const int k = p.cand_of[c];
+    if (!p.active[k]) return;
+    if (c - p.koff16[k] >= p.ks[k]) return;
+    int count = 0;
+    for (int ch = 0; ch < p.chunks; ++ch) count += p.pcnt[(size_t)ch * p.KP + c];
+    if (count == 0) return;
+    float* crow = p.C + (size_t)c * D;
+    float ss = 0.f;
+    for (int dd = lane; dd < D; dd += kWave) {
+        double s = 0.0;
+        for (int ch = 0; ch < p.chunks; ++ch) s += (double)p.psum[((size_t)ch * p.KP + c) * D + dd];
+        const float v = (float)(s / (double)count);
+        crow[dd] = v;
+        ss += v * v;
+    }
+    ss = wave_sum(ss);
+    if (lane == 0) p.cnorm[c] = ss;
+}
+
+__global__ void k_kmeans_reset(KmeansPlan p) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = tid; i < (int64_t)p.Kc * p.n; i += stride) p.lab_cm[i] = 0xFF;
+    for (int64_t k = tid; k < p.Kc; k += stride) {
+        p.active[k] = 1;
+        p.changes[k] = 0;
+        p.iters[k] = 0;
+    }
+    if (tid == 0) {
+        *p.race_counter = 0u;
+        *p.active_count = p.Kc;
+    }
+}
+
+bool kmeans_supported(int d) { return d == 16 || d == 32 || d == 64 || d == 128 || d == 256; }
+
+int kmeans_race_grid(int32_t n, int num_cu) {
+    const int64_t want = ((int64_t)n + kRaceThreads * 4 - 1) / (kRaceThreads * 4);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)num_cu * 4));
+}
+
+size_t kmeans_update_lds(int k_max, int d, int waves) {
+    return (size_t)waves * k_max * (d + 1) * sizeof(float);
+}
+
+int kmeans_update_waves(int k_max, int d, size_t lds_max) {
+    for (int w = 4; w >= 1; --w)
+        if (kmeans_update_lds(k_max, d, w) <= lds_max) return w;
+    return 0;
+}
+
+void launch_kmeans_reset(const KmeansPlan& p, hipStream_t st) {
+    const int64_t total = std::max<int64_t>((int64_t)p.Kc * p.n, p.Kc);
+    const int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_kmeans_reset, dim3(grid), dim3(256), 0, st, p);
+}
+
+#define RAFT_D_SWITCH(D_, CALL) \
+    switch (D_) {                \
+        case 16: CALL(16); break;  \
+        case 32: CALL(32); break;  \
+        case 64: CALL(64); break;  \
+        case 128: CALL(128); break; \
+        case 256: CALL(256); break; \
+        default: break;            \
+    }
+
+void launch_race_pick(const KmeansPlan& p, const float* Z, int t, uint64_t seed, hipStream_t st) {
+#define RACE(DV) \
+    hipLaunchKernelGGL(k_race<DV>, dim3(p.race_grid), dim3(kRaceThreads), 0, st, p, Z, t, seed)
+    RAFT_D_SWITCH(p.d, RACE)
+#undef RACE
+}
+
+void launch_init_centres(const KmeansPlan& p, const float* Z, hipStream_t st) {
+    const int grid = (p.KP * kWave + 255) / 256;
+#define INIT(DV) hipLaunchKernelGGL(k_init_centres<DV>, dim3(grid), dim3(256), 0, st, p, Z)
+    RAFT_D_SWITCH(p.d, INIT)
+#undef INIT
+}
+
+template <int D>
+static constexpr int assign_ps() {
+    return D <= 64 ? 4 : (D == 128 ? 2 : 1);
+}
+
+void launch_assign(const KmeansPlan& p, const float* Z, hipStream_t st) {
+#define ASSIGN(DV)                                                                        \
+    {                                                                                     \
+        constexpr int PS = assign_ps<DV>();                                               \
+        const int pts_per_block = 4 * 16 * PS;                                            \
+        dim3 grid((p.n + pts_per_block - 1) / pts_per_block, p.groups);                   \
+        hipLaunchKernelGGL((k_assign<DV, PS>), grid, dim3(256), 0, st, p, Z);             \
+    }
+    RAFT_D_SWITCH(p.d, ASSIGN)
+#undef ASSIGN
+}
+
+void launch_iter_finalize(const KmeansPlan& p, int it, int t_max, hipStream_t st) {
+    hipLaunchKernelGGL(k_iter_finalize, dim3(1), dim3(256), 0, st, p, it, t_max);
+}
+
+void launch_update(const KmeansPlan& p, const float* Z, size_t lds_max, hipStream_t st) {
+    const int waves = kmeans_update_waves(p.k_max, p.d, lds_max);
+    const size_t lds = kmeans_update_lds(p.k_max, p.d, waves);
+    dim3 grid(p.chunks, p.Kc);
+#define UPD(DV)                                                                              \
+    {                                                                                        \
+        static bool attr_set = false;                                                        \
+        if (!attr_set) {                                                                     \
+            (void)hipFuncSetAttribute((const void*)k_update<DV>,                             \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max); \
+            attr_set = true;                                                                 \
+        }                                                                                    \
+        hipLaunchKernelGGL(k_update<DV>, grid, dim3(waves * kWave), lds, st, p, Z);          \
+    }
+    RAFT_D_SWITCH(p.d, UPD)
+#undef UPD
+    const int fgrid = (p.KP * kWave + 255) / 256;
+#define FIN(DV) hipLaunchKernelGGL(k_update_finish<DV>, dim3(fgrid), dim3(256), 0, st, p)
+    RAFT_D_SWITCH(p.d, FIN)
+#undef FIN
+}
+
+}  // namespace raft

@@ -1,0 +1,305 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars: integer results bit-exact; FP32 features within 1e-5 relative
+Frobenius error per column against FP64; labels NMI >= 0.999 against the
+oracle under the same seed.  Shapes span several tiles and ragged tails."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import gcn as ogcn
+from oracle import graph as ograph
+from oracle import kmeans as okm
+from oracle import pipeline, projection, scores
+from synth import dcsbm, make_workload, two_cliques
+from synth.dcsbm import edges_to_csr
+
+pytestmark = pytest.mark.gpu
+
+COL_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2312_01560_amd import api
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def api_mod():
+    from paper_2312_01560_amd import api
+    return api
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    # 3001 nodes: not a multiple of any tile; heavy-tailed degrees (> 64 per row)
+    return dcsbm(3001, 9, gamma=2.2, d_min=5, d_max=400, rho=2.0, seed=11)
+
+
+def col_err(got, ref):
+    got = np.asarray(got, dtype=np.float64)
+    nrm = np.linalg.norm(ref, axis=0)
+    return np.linalg.norm(got - ref, axis=0) / np.maximum(nrm, 1e-300)
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+# ---------------------------------------------------------------- A0 -----
+
+def test_degrees_bit_exact(ctx, api_mod, ragged):
+    g = api_mod.Graph(ctx, ragged.row_ptr, ragged.col_idx)
+    assert np.array_equal(to_np(g.degrees()), ograph.degrees(ragged.row_ptr))
+
+
+def test_device_inputs_and_isolated_nodes(ctx, api_mod):
+    rp, ci = edges_to_csr(6, [0, 1, 3], [1, 2, 4])          # node 5 isolated
+    g = api_mod.Graph(ctx, torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda())
+    assert to_np(g.degrees()).tolist() == [1, 2, 1, 1, 1, 0]
+    y = torch.randn(6, 16, device="cuda")
+    out = api_mod.spmm(ctx, g, api_mod.X_NCUT, y)
+    ref = projection.ncut_operator(rp, ci, 6) @ to_np(y).astype(np.float64)
+    assert np.all(to_np(out)[5] == 0)
+    np.testing.assert_allclose(to_np(out), ref, rtol=1e-6, atol=1e-7)
+
+
+@pytest.mark.parametrize("bad", ["range", "order", "loop", "asym", "rowptr"])
+def test_csr_rejected(ctx, api_mod, bad):
+    g = two_cliques(4)
+    rp, ci = g.row_ptr.copy(), g.col_idx.copy()
+    if bad == "range":
+        ci[0] = 99
+    elif bad == "order":
+        ci[0], ci[1] = ci[1], ci[0]
+    elif bad == "loop":
+        ci[0] = 0
+    elif bad == "asym":
+        rp, ci = edges_to_csr(3, [0, 1], [1, 2])
+        ci = ci.copy()
+        ci[-1] = 0
+    elif bad == "rowptr":
+        rp[3] = rp[2] - 1
+    with pytest.raises(api_mod.RaftError) as ei:
+        api_mod.Graph(ctx, rp, ci)
+    assert ei.value.status == -2
+
+
+# ---------------------------------------------------------------- A1 -----
+
+@pytest.mark.parametrize("rows,cols,stream,sigma", [(1000, 64, 0x10, 0.125), (3001, 6, 0x11, 1.0),
+                                                    (257, 128, 0x10, 128 ** -0.5),
+                                                    (64, 256, 0x12, 0.0625)])
+def test_gaussian_bit_exact(ctx, api_mod, rows, cols, stream, sigma):
+    got = to_np(api_mod.gaussian(ctx, 7, stream, rows, cols, sigma))
+    ref = projection.gaussian_matrix(7, stream, rows, cols, sigma)
+    assert got.dtype == np.float32
+    assert np.array_equal(got.astype(np.float64), ref)
+
+
+def test_gaussian_bit_exact_large(ctx, api_mod):
+    # 2^20 draws at the full-size projection width
+    got = to_np(api_mod.gaussian(ctx, 0, 0x10, 16384, 64, 0.125))
+    ref = projection.gaussian_matrix(0, 0x10, 16384, 64, 0.125)
+    assert np.array_equal(got.astype(np.float64), ref)
+
+
+# ---------------------------------------------------------------- A2/A3 --
+
+@pytest.mark.parametrize("L", [16, 32, 64, 128, 256])
+@pytest.mark.parametrize("op", [0, 1, 2, 3])
+def test_spmm_one_step(ctx, api_mod, ragged, op, L):
+    g = api_mod.Graph(ctx, ragged.row_ptr, ragged.col_idx)
+    y = torch.randn(ragged.n, L, device="cuda", generator=torch.Generator("cuda").manual_seed(L))
+    got = to_np(api_mod.spmm(ctx, g, op, y))
+    x = to_np(y).astype(np.float64)
+    rp, ci, n = ragged.row_ptr, ragged.col_idx, ragged.n
+    if op == 0:
+        ref = projection.ncut_operator(rp, ci, n) @ x
+    elif op == 1:
+        a = ograph.adjacency(rp, ci, n)
+        d = ograph.degrees(rp).astype(float)
+        ref = projection.apply_modularity(a, d, float(ograph.two_e(rp)), x)
+    elif op == 2:
+        ref = projection.reduced_modularity_operator(rp, ci, n) @ x
+    else:
+        ref = ogcn.gcn_operator(rp, ci, n) @ x
+    assert col_err(got, ref).max() < COL_TOL
+
+
+@pytest.mark.parametrize("op", [0, 1, 2])
+def test_project_q3(ctx, api_mod, small_graph, op):
+    g0, m = small_graph
+    g = api_mod.Graph(ctx, g0.row_ptr, g0.col_idx)
+    cfg = api_mod.Config(op=op, **m)
+    got = to_np(api_mod.project(ctx, g, cfg))
+    ref = projection.project(g0.row_ptr, g0.col_idx, g0.n, op, m["proj_dim"], m["q"], 0)
+    assert col_err(got, ref).max() < COL_TOL
+
+
+# ---------------------------------------------------------------- A4 -----
+
+@pytest.mark.parametrize("lin,lout", [(64, 64), (128, 128), (64, 32), (256, 64), (16, 256)])
+def test_gcn_layer(ctx, api_mod, ragged, lin, lout):
+    g = api_mod.Graph(ctx, ragged.row_ptr, ragged.col_idx)
+    h = torch.randn(ragged.n, lin, device="cuda")
+    w = api_mod.gaussian(ctx, 3, 0x11, lin, lout, lin ** -0.5)
+    got, p = api_mod.gcn_layer(ctx, g, h, w, want_p=True)
+    ah = ogcn.gcn_operator(ragged.row_ptr, ragged.col_idx, ragged.n)
+    pref = ah @ to_np(h).astype(np.float64)
+    assert col_err(to_np(p), pref).max() < COL_TOL
+    z = ogcn.row_normalize(np.tanh(to_np(p).astype(np.float64) @ to_np(w).astype(np.float64)))
+    assert col_err(to_np(got), z).max() < COL_TOL
+    lin_out, _ = api_mod.gcn_layer(ctx, g, h, w, linear=True, want_p=True)
+    u = to_np(p).astype(np.float64) @ to_np(w).astype(np.float64)
+    assert col_err(to_np(lin_out), u).max() < COL_TOL
+
+
+def test_embed(ctx, api_mod, small_graph):
+    g0, m = small_graph
+    g = api_mod.Graph(ctx, g0.row_ptr, g0.col_idx)
+    cfg = api_mod.Config(op=0, **m)
+    y = api_mod.project(ctx, g, cfg)
+    z = to_np(api_mod.embed(ctx, g, cfg, y))
+    ref = ogcn.embed(g0.row_ptr, g0.col_idx, g0.n, to_np(y).astype(np.float64),
+                     m["layer_dims"], 0)
+    assert col_err(z, ref).max() < COL_TOL
+    np.testing.assert_allclose(np.linalg.norm(z, axis=1), 1.0, rtol=1e-5)
+
+
+# ---------------------------------------------------------------- A7 -----
+
+def test_scores_bit_exact(ctx, api_mod, ragged):
+    g = api_mod.Graph(ctx, ragged.row_ptr, ragged.col_idx)
+    rng = np.random.default_rng(0)
+    ks = [1, 2, 3, 7, 9, 16, 31, 64, 255]
+    lab = np.stack([rng.integers(0, k, ragged.n) for k in ks], axis=1)
+    lab[:, 4] = ragged.planted                         # the planted partition
+    mod, nc = api_mod.score(ctx, g, torch.from_numpy(lab.astype(np.uint8)).cuda(), ks)
+    rmod, rnc = scores.score_candidates(ragged.row_ptr, ragged.col_idx, lab, ks)
+    assert np.array_equal(to_np(mod), rmod)
+    assert np.array_equal(to_np(nc), rnc)
+
+
+def test_scores_closed_form(ctx, api_mod):
+    for m, num, den in ((4, 11, 26), (5, 19, 42), (6, 29, 62)):
+        g0 = two_cliques(m)
+        g = api_mod.Graph(ctx, g0.row_ptr, g0.col_idx)
+        mod, nc = api_mod.score(ctx, g, torch.from_numpy(g0.planted[:, None].astype(np.uint8)).cuda(), [2])
+        assert abs(to_np(mod)[0] - num / den) < 1e-15
+        assert abs(to_np(nc)[0] - 1.0 / (m * (m - 1) + 1)) < 1e-15
+
+
+# ---------------------------------------------------------------- A5/A6 --
+
+def test_kmeans_from_oracle_embedding(ctx, api_mod, small_graph):
+    """Same FP32 embedding into both sides: picks, labels per candidate, and
+    scores of the GPU labels recomputed by the oracle (bit-exact)."""
+    g0, m = small_graph
+    z64 = ogcn.embed(g0.row_ptr, g0.col_idx, g0.n,
+                     projection.project(g0.row_ptr, g0.col_idx, g0.n, 0, 64, 3, 0), [64, 64], 0)
+    z32 = z64.astype(np.float32)
+    zin = z32.astype(np.float64)
+    g = api_mod.Graph(ctx, g0.row_ptr, g0.col_idx)
+    cfg = api_mod.Config(op=0, **m)
+    out = api_mod.partition(ctx, g, cfg, torch.from_numpy(z32).cuda())
+    ref = okm.multi_k(zin, cfg.ks, 0, 100)
+    picks = to_np(out["picks"])
+    assert np.array_equal(picks, ref["picks"])
+    lab = to_np(out["labels_all"]).astype(np.int64)
+    for j, k in enumerate(cfg.ks):
+        assert lab[:, j].max() < k
+        assert scores.nmi(lab[:, j], ref["labels"][:, j]) >= 0.999, k
+    rmod, rnc = scores.score_candidates(g0.row_ptr, g0.col_idx, lab, cfg.ks)
+    assert np.array_equal(to_np(out["mod"]), rmod)
+    assert np.array_equal(to_np(out["ncut"]), rnc)
+    best = scores.select(rmod)
+    ks = to_np(out["k_selected"])
+    assert ks[0] == cfg.ks[best] and ks[2] == best
+    can, keff = scores.canonical(lab[:, best])
+    assert np.array_equal(to_np(out["labels"]), can) and ks[1] == keff
+
+
+def test_kmeans_fixed_point(ctx, api_mod, ragged):
+    """At termination every point sits at its nearest centre (FP64 check with
+    a tolerance for FP32 near-ties) for every candidate."""
+    z = np.random.default_rng(1).standard_normal((ragged.n, 32)).astype(np.float32)
+    z /= np.linalg.norm(z, axis=1, keepdims=True)
+    g = api_mod.Graph(ctx, ragged.row_ptr, ragged.col_idx)
+    cfg = api_mod.Config(op=0, proj_dim=32, layer_dims=[32], k_min=2, k_max=40, k_step=3,
+                         kmeans_max_iter=300)
+    out = api_mod.partition(ctx, g, cfg, torch.from_numpy(z).cuda())
+    lab = to_np(out["labels_all"]).astype(np.int64)
+    iters = to_np(out["iters"])
+    z64 = z.astype(np.float64)
+    for j, k in enumerate(cfg.ks):
+        assert iters[j] < 300
+        cen = np.stack([z64[lab[:, j] == r].mean(0) if np.any(lab[:, j] == r) else np.full(32, np.nan)
+                        for r in range(k)])
+        d = okm.sq_distances(z64, np.nan_to_num(cen, nan=1e3))
+        mine = d[np.arange(ragged.n), lab[:, j]]
+        assert np.all(mine <= d.min(axis=1) + 1e-5)
+
+
+# ---------------------------------------------------------------- A1-A7 --
+
+@pytest.mark.parametrize("op", [0, 1, 2])
+def test_run_end_to_end_small(ctx, api_mod, small_graph, op):
+    g0, m = small_graph
+    g = api_mod.Graph(ctx, g0.row_ptr, g0.col_idx)
+    cfg = api_mod.Config(op=op, **m)
+    out = api_mod.run(ctx, g, cfg)
+    torch.cuda.synchronize()
+    ctx.sync_status()
+    ref = pipeline.run(g0.row_ptr, g0.col_idx, g0.n, pipeline.Config(op=op, **m))
+    assert col_err(to_np(out["Y"]), ref["Y"]).max() < COL_TOL
+    assert col_err(to_np(out["Z"]), ref["Z"]).max() < COL_TOL
+    assert scores.nmi(to_np(out["labels"]), ref["labels"]) >= 0.999
+    # the GPU's scores of its own labels are the oracle's scores of those labels
+    lab = to_np(out["labels_all"]).astype(np.int64)
+    rmod, _ = scores.score_candidates(g0.row_ptr, g0.col_idx, lab, cfg.ks)
+    assert np.array_equal(to_np(out["mod"]), rmod)
+
+
+def test_run_two_cliques(ctx, api_mod):
+    g0 = two_cliques(5)
+    g = api_mod.Graph(ctx, g0.row_ptr, g0.col_idx)
+    cfg = api_mod.Config(op=1, proj_dim=64, q=1, layer_dims=[64, 64], k_min=2, k_max=5)
+    out = api_mod.run(ctx, g, cfg)
+    ks = to_np(out["k_selected"])
+    assert ks[0] == 2 and ks[1] == 2
+    assert to_np(out["labels"]).tolist() == [0] * 5 + [1] * 5
+    assert abs(to_np(out["mod"])[0] - 19 / 42) < 1e-15
+
+
+def test_run_deterministic(ctx, api_mod, ragged):
+    g = api_mod.Graph(ctx, ragged.row_ptr, ragged.col_idx)
+    cfg = api_mod.Config(op=1, proj_dim=64, q=3, layer_dims=[64, 64], k_min=2, k_max=20)
+    a = api_mod.run(ctx, g, cfg)
+    a = {k: to_np(v).copy() for k, v in a.items()}
+    b = api_mod.run(ctx, g, cfg)
+    for k, v in b.items():
+        assert np.array_equal(to_np(v), a[k]), k
+
+
+def test_workspace_too_small(ctx, api_mod, small_graph):
+    g0, m = small_graph
+    g = api_mod.Graph(ctx, g0.row_ptr, g0.col_idx)
+    cfg = api_mod.Config(op=0, **m)
+    need = api_mod.workspace_size(ctx, g, cfg)
+    import ctypes
+    ws = ctx.workspace(need)
+    y = ctx.empty((g0.n, 64), torch.float32)
+    c = cfg.to_c()
+    st = ctx.lib.raft_project(ctx.h, g.h, ctypes.byref(c), ws.data_ptr(), need - 4096,
+                              y.data_ptr(), None)
+    assert st == -4
+    st = ctx.lib.raft_project(ctx.h, g.h, ctypes.byref(c), ws.data_ptr(), need, y.data_ptr(), None)
+    assert st == 0
+    bad = api_mod.Config(op=0, **{**m, "k_max": 256})
+    with pytest.raises(api_mod.RaftError):
+        api_mod.workspace_size(ctx, g, bad)
