@@ -1,0 +1,255 @@
+#!/usr/bin/env python3
+"""End-to-end benchmark of the RaftGP hot path on one MI355X.
+
+One step = the whole path on one synthetic graph already resident in HBM:
+graph ingest (CSR validation and degrees from the device-resident CSR), then
+for each projection variant (NCut and full modularity by default) the random
+projection, the random GCN, k-means over every candidate K, the per-edge
+scores and the selection of K*.  `value` is graphs per second (both variants
+per graph).
+
+The dominant kernel class is timed live with HIP events around each of its
+launches inside the timed steps (library profiling hooks); its algorithmic
+work per launch gives the roofline fraction.  The FP64 oracle is timed on a
+bounded sample of the same workload on the host cores (rank 0, N=1 only).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload n50k]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM = 8.0e12            # bytes/s, MI355X HBM3E
+PEAK_MFMA_F32 = 157.3e12     # FLOP/s, dense FP32 matrix
+VARIANTS = {"ncut": 0, "mod_full": 1, "mod_reduced": 2}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="n50k")
+    ap.add_argument("--variants", default="ncut,mod_full")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-stride", type=int, default=16)
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="also run one plain device copy of this size (counter calibration)")
+    return ap.parse_args()
+
+
+def source_hash(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+KERNEL_SOURCES = {
+    "assign": ["paper_2312_01560_amd/csrc/kmeans.hip"],
+    "spmm": ["paper_2312_01560_amd/csrc/spmm.hip"],
+}
+
+
+def measured_traffic(kind, workload):
+    """HBM bytes per launch from committed rocprofv3 counter runs, or None if
+    absent or taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f).get(f"{kind}:{workload}")
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_hash") != source_hash(KERNEL_SOURCES[kind]):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(graph, method, variants, gpu_out, stride):
+    """Oracle (FP64, as it stands) on a bounded sample of one step: full
+    projection and GCN for every variant; k-means for every `stride`-th
+    candidate plus the GPU's K*, scaled to the whole grid by the GPU's
+    per-candidate work sum(K * iterations); scores of the sampled candidates
+    scaled the same way."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import gcn, kmeans, projection, scores
+
+    ks = list(range(method["k_min"], method["k_max"] + 1, method["k_step"]))
+    total_s = 0.0
+    nmis = []
+    nmi_star = []
+    sample_desc = []
+    for name in variants:
+        op = VARIANTS[name]
+        t0 = time.perf_counter()
+        y = projection.project(graph.row_ptr, graph.col_idx, graph.n, op, method["proj_dim"],
+                               method["q"], 0)
+        z = gcn.embed(graph.row_ptr, graph.col_idx, graph.n, y, method["layer_dims"], 0)
+        t_embed = time.perf_counter() - t0
+        out = gpu_out[name]
+        iters = out["iters"]
+        best = int(out["k_selected"][2])
+        sample = sorted(set(range(0, len(ks), stride)) | {best})
+        t0 = time.perf_counter()
+        picks = kmeans.seed_picks(z, max(ks[j] for j in sample), 0)
+        labs = {}
+        for j in sample:
+            a, _, _ = kmeans.lloyd(z, z[picks[:ks[j]]], 100)
+            labs[j] = a
+        t_km = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for j in sample:
+            scores.modularity(graph.row_ptr, graph.col_idx, labs[j], ks[j])
+            scores.ncut(graph.row_ptr, graph.col_idx, labs[j], ks[j])
+        t_sc = time.perf_counter() - t0
+        work_all = float(sum(k * max(int(it), 1) for k, it in zip(ks, iters)))
+        work_smp = float(sum(ks[j] * max(int(iters[j]), 1) for j in sample))
+        scale = work_all / work_smp
+        total_s += t_embed + (t_km + t_sc) * scale
+        for j in sample:
+            v = scores.nmi(out["labels_all"][:, j], labs[j])
+            nmis.append(v)
+            if j == best:
+                nmi_star.append(v)
+        sample_desc.append(f"{name}: full projection+GCN, k-means+scores for K in "
+                           f"{[ks[j] for j in sample]} scaled x{scale:.2f}")
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {
+        "value": 1.0 / total_s, "unit": "graphs/s", "cores": threads, "kind": "oracle",
+        "sample": "; ".join(sample_desc) + f"; estimated {total_s:.1f} s per graph",
+    }, float(min(nmis)), float(min(nmi_star))
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: the hot path is single-GPU; "
+              "multi-GPU sharding is a design note only", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2312_01560_amd import api
+    from synth import make_workload
+
+    graph, method = make_workload(args.workload)
+    variants = [v for v in args.variants.split(",") if v]
+    ctx = api.Context(0)
+    dev = ctx.torch_device
+    rp = torch.from_numpy(graph.row_ptr).to(dev)
+    ci = torch.from_numpy(graph.col_idx).to(dev)
+    cfgs = {v: api.Config(op=VARIANTS[v], **method) for v in variants}
+    g0 = api.Graph(ctx, rp, ci)
+    ws = ctx.workspace(max(api.workspace_size(ctx, g0, c) for c in cfgs.values()))
+    g0.close()
+    outs = {v: api._outputs(ctx, g0, cfgs[v], want_y=True, want_z=True) for v in variants}
+
+    def step():
+        g = api.Graph(ctx, rp, ci)
+        for v in variants:
+            api.run(ctx, g, cfgs[v], ws=ws, outputs=outs[v])
+        g.close()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.sync_status()
+    api.profile_read(ctx)
+    api.profile_enable(ctx, (1 << 0) | (1 << 3))      # SpMM and k-means assignment
+    stage = {v: np.zeros(5) for v in variants}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g = api.Graph(ctx, rp, ci)
+        for v in variants:
+            api.run(ctx, g, cfgs[v], ws=ws, outputs=outs[v])
+            stage[v] += np.array(api.stage_times(ctx))
+        g.close()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = api.profile_read(ctx)
+    api.profile_enable(ctx, 0)
+    ctx.sync_status()
+    elapsed = t1 - t0
+    value = args.steps / elapsed
+
+    host = {v: {k: t.cpu().numpy() for k, t in outs[v][0].items()} for v in variants}
+    n, nnz = graph.n, graph.nnz
+    d = cfgs[variants[0]].embed_dim
+    ks = cfgs[variants[0]].ks
+    # algorithmic work of one step
+    assign_flops = sum(2.0 * n * d * float(np.dot(ks, host[v]["iters"])) for v in variants)
+    spmm_bytes_per_launch = 4.0 * (n + 1) + 4.0 * nnz + 8.0 * n * method["proj_dim"]
+    ms_assign, n_assign = prof["assign"]
+    ms_spmm, n_spmm = prof["spmm"]
+    assign_ach = assign_flops * args.steps / (ms_assign * 1e-3) if ms_assign > 0 else 0.0
+    spmm_ach = spmm_bytes_per_launch * n_spmm / (ms_spmm * 1e-3) if ms_spmm > 0 else 0.0
+    dominant = "assign" if ms_assign >= ms_spmm else "spmm"
+    if dominant == "assign":
+        roof = {"kernel": "k_assign (MFMA FP32, all candidates)", "bound": "mfma",
+                "achieved": assign_ach / 1e12, "peak": PEAK_MFMA_F32 / 1e12, "unit": "TFLOP/s",
+                "frac": assign_ach / PEAK_MFMA_F32,
+                "per_launch": {"flops": assign_flops * args.steps / max(n_assign, 1),
+                               "avg_ms": ms_assign / max(n_assign, 1)}}
+    else:
+        roof = {"kernel": "k_spmm", "bound": "hbm", "achieved": spmm_ach / 1e9,
+                "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": spmm_ach / PEAK_HBM,
+                "per_launch": {"bytes": spmm_bytes_per_launch, "avg_ms": ms_spmm / max(n_spmm, 1)}}
+    roof["traffic"] = measured_traffic(dominant, args.workload)
+
+    from oracle import scores as oscores   # NMI bookkeeping only
+    nmi_planted = {v: oscores.nmi(host[v]["labels"], graph.planted) for v in variants}
+
+    rec = {
+        "metric": "end-to-end graphs/s (N=50k DC-SBM, NCut + modularity variants), "
+                  "SpMM GB/s (% HBM peak), NMI vs oracle",
+        "value": value, "unit": "graphs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "nnz": nnz, "edges": nnz // 2,
+                   "proj_dim": method["proj_dim"], "q": method["q"],
+                   "layer_dims": method["layer_dims"],
+                   "k_grid": [method["k_min"], method["k_max"], method["k_step"]],
+                   "variants": variants},
+        "roofline": roof,
+        "spmm": {"achieved_gbs": spmm_ach / 1e9, "frac_hbm": spmm_ach / PEAK_HBM,
+                 "avg_us": 1e3 * ms_spmm / max(n_spmm, 1), "launches": n_spmm,
+                 "bytes_per_launch": spmm_bytes_per_launch,
+                 "edges_features_per_s": nnz * method["proj_dim"] * n_spmm / (ms_spmm * 1e-3)
+                 if ms_spmm > 0 else 0.0},
+        "stages_ms_per_step": {v: dict(zip(["project", "embed", "seed", "lloyd", "score"],
+                                           (stage[v] / args.steps).round(3).tolist()))
+                               for v in variants},
+        "k_star": {v: int(host[v]["k_selected"][0]) for v in variants},
+        "nmi_vs_planted": nmi_planted,
+    }
+    if args.copy_calib_mib:
+        a = torch.empty(args.copy_calib_mib << 18, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        rec["copy_calib_bytes"] = a.numel() * 4
+    if not args.no_cpu_baseline:
+        base, nmi_min, nmi_star = cpu_baseline(graph, method, variants, host,
+                                               args.cpu_sample_stride)
+        rec["cpu_baseline"] = base
+        rec["nmi_vs_oracle"] = {"selected_k": nmi_star, "min_over_sample": nmi_min}
+    print(json.dumps(rec))
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

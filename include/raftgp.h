@@ -185,6 +185,25 @@ raft_status raft_score(raft_ctx* ctx, const raft_graph* g, const uint8_t* labels
 raft_status raft_run(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg,
                      void* ws, size_t ws_bytes, raft_outputs* out, void* stream);
 
+/* ---- measurement ---------------------------------------------------------- */
+
+/* Kernel classes timed by raft_profile_enable (bit k of the mask = class k). */
+#define RAFT_PROF_SPMM    0   /* sparse products of the projection and GCN aggregation */
+#define RAFT_PROF_DENSE   1   /* GCN dense layer (MFMA)                               */
+#define RAFT_PROF_RACE    2   /* k-means++ race pick                                  */
+#define RAFT_PROF_ASSIGN  3   /* k-means assignment over all candidates (MFMA)        */
+#define RAFT_PROF_UPDATE  4   /* k-means centre update                                */
+#define RAFT_PROF_SCORE   5   /* per-edge candidate scores                            */
+#define RAFT_PROF_CLASSES 6
+
+/* Brackets every later launch of the enabled kernel classes with HIP events
+ * on the launch stream (mask 0 disables).  Synchronises the device. */
+raft_status raft_profile_enable(raft_ctx* ctx, uint32_t mask);
+/* Accumulated device milliseconds and launch counts per class since the last
+ * read (ms[RAFT_PROF_CLASSES], launches[RAFT_PROF_CLASSES]); resets them.
+ * Synchronises the device. */
+raft_status raft_profile_read(raft_ctx* ctx, double* ms, int64_t* launches);
+
 /* Per-stage device times (ms) of the last raft_run on this context:
  * [0] project, [1] embed, [2] seeding, [3] Lloyd, [4] scores+select. */
 raft_status raft_get_stage_times(raft_ctx* ctx, double* ms5);

@@ -21,8 +21,11 @@ EXPORTS = [
     "raft_abi_version", "raft_sync_status", "raft_graph_create", "raft_graph_destroy",
     "raft_graph_degrees", "raft_workspace_size", "raft_gaussian", "raft_spmm", "raft_project",
     "raft_gcn_layer", "raft_embed", "raft_partition", "raft_score", "raft_run",
-    "raft_get_stage_times",
+    "raft_get_stage_times", "raft_profile_enable", "raft_profile_read",
 ]
+
+PROF_SPMM, PROF_DENSE, PROF_RACE, PROF_ASSIGN, PROF_UPDATE, PROF_SCORE = range(6)
+PROF_CLASSES = 6
 
 
 class RaftConfig(ctypes.Structure):
@@ -85,6 +88,8 @@ _SIGNATURES = {
     "raft_run": (_I32, [_P, _P, ctypes.POINTER(RaftConfig), _P, _SZ,
                         ctypes.POINTER(RaftOutputs), _P]),
     "raft_get_stage_times": (_I32, [_P, ctypes.POINTER(ctypes.c_double)]),
+    "raft_profile_enable": (_I32, [_P, ctypes.c_uint32]),
+    "raft_profile_read": (_I32, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
 }
 
 _lib = None

@@ -263,7 +263,7 @@ def score(ctx, g, labels_all, ks):
     mod = ctx.empty((kc,), torch.float64)
     nc = ctx.empty((kc,), torch.float64)
     ks_arr = (ctypes.c_int32 * kc)(*ks)
-    stride = (kc + 3) // 4 * 4
+    stride = (kc + 7) // 8 * 8
     sk = sum(ks)
     # upper bound of the library's layout (score grid <= 1024 work-groups)
     ws = ctx.workspace(8 * kc + g.n * stride + 2 * 1024 * sk * 4 + 16 * sk + 8 * 256)
@@ -276,3 +276,16 @@ def stage_times(ctx):
     arr = (ctypes.c_double * 5)()
     ctx.check(ctx.lib.raft_get_stage_times(ctx.h, arr))
     return list(arr)
+
+
+def profile_enable(ctx, mask):
+    ctx.check(ctx.lib.raft_profile_enable(ctx.h, mask))
+
+
+def profile_read(ctx):
+    """{class: (ms, launches)} accumulated since the last read."""
+    ms = (ctypes.c_double * _lib.PROF_CLASSES)()
+    n = (ctypes.c_int64 * _lib.PROF_CLASSES)()
+    ctx.check(ctx.lib.raft_profile_read(ctx.h, ms, n))
+    names = ["spmm", "dense", "race", "assign", "update", "score"]
+    return {names[k]: (ms[k], n[k]) for k in range(_lib.PROF_CLASSES)}

@@ -21,9 +21,16 @@ struct raft_ctx {
     size_t lds_max = 65536;
     std::string err;
     int32_t* d_status = nullptr;   // device status word
-    int32_t* h_pinned = nullptr;   // pinned host scratch (8 ints)
+    int32_t* h_pinned = nullptr;   // pinned host scratch (4096 ints)
     double stage_ms[5] = {0, 0, 0, 0, 0};
     hipEvent_t ev[6] = {};
+    // per-kernel-class event timing (raft_profile_enable)
+    uint32_t prof_mask = 0;
+    std::vector<hipEvent_t> prof_pool;
+    size_t prof_used = 0;
+    std::vector<std::pair<int, size_t>> prof_recs;
+    double prof_ms[RAFT_PROF_CLASSES] = {};
+    int64_t prof_n[RAFT_PROF_CLASSES] = {};
 };
 
 struct raft_graph {
@@ -51,6 +58,46 @@ struct raft_graph {
 };
 
 namespace {
+
+// Brackets one launch with a pair of pooled events when its class is enabled.
+struct ProfScope {
+    raft_ctx* c;
+    int kind;
+    hipStream_t st;
+    size_t idx = (size_t)-1;
+    ProfScope(raft_ctx* c_, int kind_, hipStream_t st_) : c(c_), kind(kind_), st(st_) {
+        if (!(c->prof_mask & (1u << kind))) return;
+        if (c->prof_used + 2 > c->prof_pool.size()) {
+            for (int i = 0; i < 256; ++i) {
+                hipEvent_t e;
+                if (hipEventCreate(&e) != hipSuccess) return;
+                c->prof_pool.push_back(e);
+            }
+        }
+        idx = c->prof_used;
+        c->prof_used += 2;
+        (void)hipEventRecord(c->prof_pool[idx], st);
+    }
+    ~ProfScope() {
+        if (idx == (size_t)-1) return;
+        (void)hipEventRecord(c->prof_pool[idx + 1], st);
+        c->prof_recs.push_back({kind, idx});
+    }
+};
+
+// Folds finished event pairs into the per-class totals (after a sync).
+void prof_collect(raft_ctx* c) {
+    for (auto& r : c->prof_recs) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->prof_pool[r.second], c->prof_pool[r.second + 1]) ==
+            hipSuccess) {
+            c->prof_ms[r.first] += ms;
+            c->prof_n[r.first] += 1;
+        }
+    }
+    c->prof_recs.clear();
+    c->prof_used = 0;
+}
 
 raft_status fail(raft_ctx* ctx, raft_status code, const char* fmt, ...) {
     if (ctx) {
@@ -96,8 +143,8 @@ struct Arena {
 };
 
 struct Grid {
-    std::vector<int32_t> ks, koff16, koff, grp, cand_of;
-    int Kc = 0, KP = 0, SK = 0, k_max = 0, groups = 0;
+    std::vector<int32_t> ks, koff16, koff, cand_of;
+    int Kc = 0, KP = 0, SK = 0, k_max = 0;
 };
 
 Grid make_grid(int k_min, int k_max, int k_step) {
@@ -113,19 +160,56 @@ Grid make_grid(int k_min, int k_max, int k_step) {
         g.SK += k;
         g.k_max = std::max(g.k_max, k);
     }
-    // candidate groups of the assignment kernel: about 256 padded centres each
-    g.grp.push_back(0);
+    return g;
+}
+
+// Work lists over the candidates still active: alist holds their ids;
+// agrp splits alist into groups of about 256 padded centres (assignment),
+// ugrp into groups whose clusters fit the update kernel's LDS budget.
+struct Lists {
+    std::vector<int32_t> alist, agrp, ugrp;
+};
+
+Lists make_lists(const Grid& G, const int32_t* active, int ucap) {
+    Lists l;
+    for (int k = 0; k < G.Kc; ++k)
+        if (!active || active[k]) l.alist.push_back(k);
+    l.agrp.push_back(0);
     int acc = 0;
-    for (int i = 0; i < g.Kc; ++i) {
-        acc += (g.ks[i] + 15) / 16 * 16;
-        if (acc >= 256 && i + 1 < g.Kc) {
-            g.grp.push_back(i + 1);
+    for (size_t t = 0; t < l.alist.size(); ++t) {
+        acc += (G.ks[l.alist[t]] + 15) / 16 * 16;
+        if (acc >= 256 && t + 1 < l.alist.size()) {
+            l.agrp.push_back((int32_t)t + 1);
             acc = 0;
         }
     }
-    g.grp.push_back(g.Kc);
-    g.groups = (int)g.grp.size() - 1;
-    return g;
+    l.agrp.push_back((int32_t)l.alist.size());
+    l.ugrp.push_back(0);
+    acc = 0;
+    int cnt = 0;
+    for (size_t t = 0; t < l.alist.size(); ++t) {
+        const int rows = kmeans_update_rows(G.ks[l.alist[t]]);
+        if (cnt > 0 && (acc + rows > ucap || cnt >= kmeans_update_max_candidates())) {
+            l.ugrp.push_back((int32_t)t);
+            acc = 0;
+            cnt = 0;
+        }
+        acc += rows;
+        ++cnt;
+    }
+    l.ugrp.push_back((int32_t)l.alist.size());
+    return l;
+}
+
+// LDS budget of one update work-group (two work-groups per CU).
+constexpr size_t kUpdateLdsBudget = 72 * 1024;
+
+int update_cap(const Grid& G, int d) {
+    const size_t fixed = kmeans_update_lds(0, d);
+    const size_t per = kmeans_update_lds(1, d) - fixed;
+    int most = 0;
+    for (int k : G.ks) most = std::max(most, kmeans_update_rows(k));
+    return std::max<int>(most, (int)((kUpdateLdsBudget - fixed) / per));
 }
 
 int embed_dim(const raft_config* c) {
@@ -164,16 +248,18 @@ raft_status check_config(raft_ctx* ctx, const raft_graph* g, const raft_config* 
 
 // Workspace layout shared by every staged call.
 struct Plan {
-    int L = 0, d = 0, Lmax = 0, spmm_grid_ = 0, score_grid_ = 0, S = 0, chunks = 0, chunk_len = 0,
-        race_grid = 0;
+    int L = 0, d = 0, Lmax = 0, spmm_grid_ = 0, score_grid_ = 0, S = 0, race_grid = 0;
     Grid grid;
+    Lists lists;
+    int ucap = 0;
     // projection / embedding
     float *y0, *y1, *pbuf, *yout, *zout, *wbuf;
     double *cpart, *c64;
     float* cvec;
     // k-means
     KmeansPlan km;
-    int32_t* meta;   // ks, koff16, koff, grp, cand_of packed
+    int32_t* meta;   // ks, koff16, koff, cand_of, alist, agrp, ugrp packed
+    int32_t* dyn;    // alist, agrp, ugrp (rewritten at convergence polls)
     // scores
     ScorePlan sc;
     uint8_t* lab_pm;
@@ -193,10 +279,9 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
     P.spmm_grid_ = spmm_grid(n, P.Lmax, ctx->num_cu, nullptr);
     // every width uses the same grid formula (it does not depend on L)
     P.score_grid_ = score_grid(n, ctx->num_cu);
-    P.S = (P.grid.Kc + 3) / 4 * 4;
-    P.chunks = std::max(1, std::min(64, (n + 2047) / 2048));
-    P.chunk_len = (n + P.chunks - 1) / P.chunks;
-    P.chunks = std::max(1, (n + P.chunk_len - 1) / P.chunk_len);
+    P.S = (P.grid.Kc + 7) / 8 * 8;
+    P.ucap = update_cap(P.grid, P.d);
+    P.lists = make_lists(P.grid, nullptr, P.ucap);
     P.race_grid = kmeans_race_grid(n, ctx->num_cu);
     Arena a;
     a.base = base;
@@ -213,13 +298,14 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
         lin = c->layer_dims[k];
     }
     P.wbuf = a.take<float>(wmax);
-    P.cpart = a.take<double>((size_t)P.spmm_grid_ * P.Lmax);
+    P.cpart = a.take<double>(((size_t)spmm_grid(n, P.L, ctx->num_cu, nullptr) + kColsumStageRows) * P.L);
     P.c64 = a.take<double>(P.Lmax);
     P.cvec = a.take<float>(P.Lmax);
     // k-means
     const Grid& G = P.grid;
-    const size_t meta_n = (size_t)3 * G.Kc + G.grp.size() + G.KP;
+    const size_t meta_n = (size_t)3 * G.Kc + G.KP + (size_t)3 * G.Kc + 2;
     P.meta = a.take<int32_t>(meta_n);
+    P.dyn = P.meta ? P.meta + 3 * G.Kc + G.KP : nullptr;
     KmeansPlan& km = P.km;
     km.n = n;
     km.d = P.d;
@@ -227,15 +313,25 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
     km.k_max = G.k_max;
     km.KP = G.KP;
     km.SK = G.SK;
-    km.groups = G.groups;
-    km.chunks = P.chunks;
-    km.chunk_len = P.chunk_len;
+    km.agroups = (int)P.lists.agrp.size() - 1;
+    km.ugroups = (int)P.lists.ugrp.size() - 1;
+    km.usk_max = P.ucap;
+    {
+        const int nsl = P.d > 64 ? P.d / 64 : 1;
+        const int want = (2 * ctx->num_cu + km.ugroups * nsl - 1) / (km.ugroups * nsl);
+        const int max_ranges = std::max(1, (n + 63) / 64);
+        const int ranges = std::max(1, std::min(want, max_ranges));
+        km.range_len = ((n + ranges - 1) / ranges + 63) / 64 * 64;
+        km.ranges = (n + km.range_len - 1) / km.range_len;
+    }
     km.race_grid = P.race_grid;
     km.ks = P.meta;
     km.koff16 = P.meta ? P.meta + G.Kc : nullptr;
     km.koff = P.meta ? P.meta + 2 * G.Kc : nullptr;
-    km.grp = P.meta ? P.meta + 3 * G.Kc : nullptr;
-    km.cand_of = P.meta ? P.meta + 3 * G.Kc + G.grp.size() : nullptr;
+    km.cand_of = P.meta ? P.meta + 3 * G.Kc : nullptr;
+    km.alist = P.dyn;
+    km.agrp = P.dyn ? P.dyn + G.Kc : nullptr;
+    km.ugrp = P.dyn ? P.dyn + 2 * G.Kc + 1 : nullptr;
     km.active = a.take<int32_t>(G.Kc);
     km.changes = a.take<int32_t>(G.Kc);
     P.iters_int = a.take<int32_t>(G.Kc);
@@ -243,8 +339,9 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
     km.active_count = a.take<int32_t>(1);
     km.C = a.take<float>((size_t)G.KP * P.d);
     km.cnorm = a.take<float>(G.KP);
-    km.psum = a.take<float>((size_t)P.chunks * G.KP * P.d);
-    km.pcnt = a.take<int32_t>((size_t)P.chunks * G.KP);
+    km.psum = a.take<float>((size_t)km.ranges * G.KP * P.d);
+    km.pcnt = a.take<int32_t>((size_t)km.ranges * G.KP);
+    km.zmax_bits = a.take<uint32_t>(1);
     km.w = a.take<float>(n);
     km.race_val = a.take<double>(P.race_grid);
     km.race_idx = a.take<int32_t>(P.race_grid);
@@ -280,14 +377,24 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
     P.bytes = a.off;
 }
 
+// Packs the dynamic lists at fixed offsets: alist [Kc], agrp [Kc+1], ugrp [Kc+1].
+void pack_lists(const Lists& l, int Kc, int32_t* out) {
+    std::fill(out, out + 3 * Kc + 2, 0);
+    std::copy(l.alist.begin(), l.alist.end(), out);
+    std::copy(l.agrp.begin(), l.agrp.end(), out + Kc);
+    std::copy(l.ugrp.begin(), l.ugrp.end(), out + 2 * Kc + 1);
+}
+
 raft_status upload_meta(raft_ctx* ctx, const Plan& P, hipStream_t st) {
     const Grid& G = P.grid;
     std::vector<int32_t> meta;
     meta.insert(meta.end(), G.ks.begin(), G.ks.end());
     meta.insert(meta.end(), G.koff16.begin(), G.koff16.end());
     meta.insert(meta.end(), G.koff.begin(), G.koff.end());
-    meta.insert(meta.end(), G.grp.begin(), G.grp.end());
     meta.insert(meta.end(), G.cand_of.begin(), G.cand_of.end());
+    const size_t at = meta.size();
+    meta.resize(at + 3 * (size_t)G.Kc + 2);
+    pack_lists(P.lists, G.Kc, meta.data() + at);
     HIP_TRY(ctx, hipMemcpyAsync(P.meta, meta.data(), meta.size() * sizeof(int32_t),
                                 hipMemcpyHostToDevice, st));
     // pageable source: wait so the host vector may go out of scope
@@ -333,7 +440,11 @@ raft_status do_project(raft_ctx* ctx, const raft_graph* g, const raft_config* c,
     for (int t = 1; t <= c->q; ++t) {
         float* dst = (t == c->q) ? out : (src == P.y0 ? P.y1 : P.y0);
         const bool need_cs = mod_full && t < c->q;
-        launch_spmm(gv, c->op, L, src, dst, P.cvec, need_cs ? P.cpart : nullptr, ctx->num_cu, st);
+        {
+            ProfScope ps(ctx, RAFT_PROF_SPMM, st);
+            launch_spmm(gv, c->op, L, src, dst, P.cvec, need_cs ? P.cpart : nullptr, ctx->num_cu,
+                        st);
+        }
         if (need_cs)
             launch_colsum_finish(P.cpart, spmm_grid(g->n, L, ctx->num_cu, nullptr), L, P.c64,
                                  P.cvec, st);
@@ -364,9 +475,15 @@ raft_status do_embed(raft_ctx* ctx, const raft_graph* g, const raft_config* c, P
         const int lout = c->layer_dims[k - 1];
         launch_gaussian(c->seed, 0x10 + (uint64_t)k, lin, lout, 1.0 / std::sqrt((double)lin),
                         P.wbuf, st);
-        launch_spmm(gv, kOpGcn, lin, h, P.pbuf, nullptr, nullptr, ctx->num_cu, st);
+        {
+            ProfScope ps(ctx, RAFT_PROF_SPMM, st);
+            launch_spmm(gv, kOpGcn, lin, h, P.pbuf, nullptr, nullptr, ctx->num_cu, st);
+        }
         float* dst = (k == c->n_layers) ? Z : (h == P.y0 ? P.y1 : P.y0);
-        launch_dense_layer(P.pbuf, P.wbuf, dst, g->n, lin, lout, false, ctx->d_status, st);
+        {
+            ProfScope ps(ctx, RAFT_PROF_DENSE, st);
+            launch_dense_layer(P.pbuf, P.wbuf, dst, g->n, lin, lout, false, ctx->d_status, st);
+        }
         h = dst;
         lin = lout;
     }
@@ -386,26 +503,51 @@ raft_status do_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* 
     const int check = c->check_every > 0 ? c->check_every : 4;
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[2], st));
     launch_kmeans_reset(km, st);
-    for (int t = 0; t < km.k_max; ++t) launch_race_pick(km, Z, t, c->seed, st);
+    launch_zmax(km, Z, ctx->num_cu, st);
+    for (int t = 0; t < km.k_max; ++t) {
+        ProfScope ps(ctx, RAFT_PROF_RACE, st);
+        launch_race_pick(km, Z, t, c->seed, st);
+    }
     launch_init_centres(km, Z, st);
     RAFT_TRY(launch_check(ctx));
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[3], st));
+    const int Kc = P.grid.Kc;
+    int32_t* h_active = ctx->h_pinned + 16;
+    int32_t* h_lists = ctx->h_pinned + 16 + RAFT_MAX_K + 1;
     for (int it = 1; it <= t_max; ++it) {
-        launch_assign(km, Z, st);
+        {
+            ProfScope ps(ctx, RAFT_PROF_ASSIGN, st);
+            launch_assign(km, Z, st);
+        }
         launch_iter_finalize(km, it, t_max, st);
         if (it == t_max) break;
-        launch_update(km, Z, ctx->lds_max, st);
+        {
+            ProfScope ps(ctx, RAFT_PROF_UPDATE, st);
+            launch_update(km, Z, ctx->lds_max, st);
+        }
         if (it % check == 0) {
-            HIP_TRY(ctx, hipMemcpyAsync(ctx->h_pinned, km.active_count, sizeof(int32_t),
+            HIP_TRY(ctx, hipMemcpyAsync(h_active, km.active, Kc * sizeof(int32_t),
                                         hipMemcpyDeviceToHost, st));
             HIP_TRY(ctx, hipStreamSynchronize(st));
-            if (ctx->h_pinned[0] == 0) break;
+            int live = 0;
+            for (int k = 0; k < Kc; ++k) live += h_active[k] != 0;
+            if (live == 0) break;
+            // compact the work lists to the candidates still iterating
+            const Lists l = make_lists(P.grid, h_active, P.ucap);
+            pack_lists(l, Kc, h_lists);
+            HIP_TRY(ctx, hipMemcpyAsync(P.dyn, h_lists, (3 * (size_t)Kc + 2) * sizeof(int32_t),
+                                        hipMemcpyHostToDevice, st));
+            km.agroups = (int)l.agrp.size() - 1;
+            km.ugroups = (int)l.ugrp.size() - 1;
         }
     }
     RAFT_TRY(launch_check(ctx));
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[4], st));
     launch_transpose_labels(km.lab_cm, g->n, P.grid.Kc, P.lab_pm, P.S, st);
-    launch_edge_score(g->view(), sc, P.lab_pm, st);
+    {
+        ProfScope ps(ctx, RAFT_PROF_SCORE, st);
+        launch_edge_score(g->view(), sc, P.lab_pm, st);
+    }
     launch_score_finish(sc, st);
     launch_select(sc, P.lab_pm, out ? out->labels : nullptr, ksel, st);
     if (out && out->labels_all)
@@ -420,7 +562,7 @@ raft_status plan_for(raft_ctx* ctx, const raft_graph* g, const raft_config* c, v
     plan_layout(ctx, g, c, nullptr, P);
     const int d = embed_dim(c);
     if (!kmeans_supported(d)) return fail(ctx, RAFT_E_UNSUPPORTED, "embedding width %d", d);
-    if (kmeans_update_waves(P.grid.k_max, d, ctx->lds_max) < 1)
+    if (kmeans_update_lds(P.ucap, d) > ctx->lds_max)
         return fail(ctx, RAFT_E_UNSUPPORTED, "k_max %d too large for width %d", P.grid.k_max, d);
     if (!score_supported(P.grid.SK))
         return fail(ctx, RAFT_E_UNSUPPORTED, "sum of candidate K %d > 16384", P.grid.SK);
@@ -473,7 +615,7 @@ raft_status raft_ctx_create(int device, raft_ctx** out) {
              lds > 0)
         c->lds_max = (size_t)lds;
     if (hipMalloc(&c->d_status, 256) != hipSuccess ||
-        hipHostMalloc((void**)&c->h_pinned, 64, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void**)&c->h_pinned, 16384, hipHostMallocDefault) != hipSuccess) {
         delete c;
         return RAFT_E_NOMEM;
     }
@@ -491,6 +633,7 @@ void raft_ctx_destroy(raft_ctx* ctx) {
     (void)hipDeviceSynchronize();
     for (auto& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto& e : ctx->prof_pool) (void)hipEventDestroy(e);
     if (ctx->d_status) (void)hipFree(ctx->d_status);
     if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
     delete ctx;
@@ -641,7 +784,7 @@ raft_status raft_gaussian(raft_ctx* ctx, uint64_t seed, uint64_t stream_id, int6
 
 static size_t spmm_ws_bytes(raft_ctx* ctx, const raft_graph* g, int L) {
     const int grid = spmm_grid(g->n, L, ctx->num_cu, nullptr);
-    return align256((size_t)grid * L * sizeof(double)) + align256(L * sizeof(double)) +
+    return align256(((size_t)grid + kColsumStageRows) * L * sizeof(double)) + align256(L * sizeof(double)) +
            align256(L * sizeof(float));
 }
 
@@ -660,7 +803,7 @@ raft_status raft_spmm(raft_ctx* ctx, const raft_graph* g, int32_t op, int32_t L,
         Arena a;
         a.base = reinterpret_cast<char*>(ws);
         const int grid = spmm_grid(g->n, L, ctx->num_cu, nullptr);
-        double* cpart = a.take<double>((size_t)grid * L);
+        double* cpart = a.take<double>(((size_t)grid + kColsumStageRows) * L);
         double* c64 = a.take<double>(L);
         float* cvec = a.take<float>(L);
         launch_colsum_partials(gv, L, Y_in, cpart, ctx->num_cu, st);
@@ -739,7 +882,7 @@ raft_status raft_score(raft_ctx* ctx, const raft_graph* g, const uint8_t* labels
         SK += ks[k];
     }
     if (!score_supported(SK)) return fail(ctx, RAFT_E_UNSUPPORTED, "sum of K %d", SK);
-    const int S = (Kc + 3) / 4 * 4;
+    const int S = (Kc + 7) / 8 * 8;
     const int grid = score_grid(g->n, ctx->num_cu);
     Arena a;
     a.base = nullptr;
@@ -806,10 +949,32 @@ raft_status raft_run(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg,
     RAFT_TRY(do_embed(ctx, g, cfg, P, Y, Z, st));
     RAFT_TRY(do_partition(ctx, g, cfg, P, Z, out, st, true));
     HIP_TRY(ctx, hipEventSynchronize(ctx->ev[5]));
+    prof_collect(ctx);
     float ms = 0;
     for (int s = 0; s < 5; ++s) {
         if (hipEventElapsedTime(&ms, ctx->ev[s], ctx->ev[s + 1]) == hipSuccess)
             ctx->stage_ms[s] = ms;
+    }
+    return RAFT_OK;
+}
+
+raft_status raft_profile_enable(raft_ctx* ctx, uint32_t mask) {
+    if (!ctx) return RAFT_E_INVAL;
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    prof_collect(ctx);
+    ctx->prof_mask = mask & ((1u << RAFT_PROF_CLASSES) - 1);
+    return RAFT_OK;
+}
+
+raft_status raft_profile_read(raft_ctx* ctx, double* ms, int64_t* launches) {
+    if (!ctx || !ms || !launches) return RAFT_E_INVAL;
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    prof_collect(ctx);
+    for (int k = 0; k < RAFT_PROF_CLASSES; ++k) {
+        ms[k] = ctx->prof_ms[k];
+        launches[k] = ctx->prof_n[k];
+        ctx->prof_ms[k] = 0;
+        ctx->prof_n[k] = 0;
     }
     return RAFT_OK;
 }

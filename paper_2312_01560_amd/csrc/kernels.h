@@ -44,7 +44,9 @@ void launch_spmm(const GraphView& g, int op, int L, const float* x, float* y, co
 // FP64 partials of d^T x over row blocks (grid = spmm_grid(...)).
 void launch_colsum_partials(const GraphView& g, int L, const float* x, double* part, int num_cu,
                             hipStream_t st);
-// c = sum of `parts` partial rows (fixed order), cvec = FP32(c).
+// c = sum of `parts` partial rows (fixed order), cvec = FP32(c).  The partial
+// buffer must hold kColsumStageRows more rows after the partials (stage).
+constexpr int kColsumStageRows = 64;
 void launch_colsum_finish(const double* part, int parts, int L, double* c64, float* cvec,
                           hipStream_t st);
 
@@ -61,24 +63,29 @@ struct KmeansPlan {
     int32_t n, d, Kc, k_max;
     int32_t KP;          // padded centre rows (sum of ceil16(K))
     int32_t SK;          // real centre count (sum of K)
-    int32_t groups;      // candidate groups of the assignment kernel
-    int32_t chunks;      // point chunks of the update kernel
-    int32_t chunk_len;
+    int32_t agroups;     // candidate groups of the assignment kernel (over alist)
+    int32_t ugroups;     // candidate groups of the update kernel (over alist)
+    int32_t usk_max;     // bound on the accumulator rows of an update group (LDS sizing)
+    int32_t ranges;      // point ranges of the update kernel
+    int32_t range_len;
     int32_t race_grid;
     // device arrays
     const int32_t* ks;       // [Kc]
     const int32_t* koff16;   // [Kc] padded centre offsets
     const int32_t* koff;     // [Kc] real offsets (score tables)
-    const int32_t* grp;      // [groups + 1] candidate ranges of the groups
     const int32_t* cand_of;  // [KP] candidate of each padded centre row
+    const int32_t* alist;    // [Kc] candidates still active at the last poll
+    const int32_t* agrp;     // [agroups + 1] offsets into alist
+    const int32_t* ugrp;     // [ugroups + 1] offsets into alist
     int32_t* active;         // [Kc]
     int32_t* changes;        // [Kc]
     int32_t* iters;          // [Kc]
     int32_t* active_count;   // [1]
     float* C;                // [KP x d]
     float* cnorm;            // [KP]
-    float* psum;             // [chunks x KP x d]
-    int32_t* pcnt;           // [chunks x KP]
+    float* psum;             // [ranges x KP x d] per-range centre sums
+    int32_t* pcnt;           // [ranges x KP]
+    uint32_t* zmax_bits;     // [1] largest |z| (float bits), sets the fixed-point scale
     float* w;                // [n]
     double* race_val;        // [race_grid]
     int32_t* race_idx;       // [race_grid]
@@ -90,19 +97,23 @@ struct KmeansPlan {
 
 bool kmeans_supported(int d);
 int kmeans_race_grid(int32_t n, int num_cu);
+// LDS bytes of one update work-group whose candidates total sum_rows
+// accumulator rows (kmeans_update_rows(K) per candidate).
+size_t kmeans_update_lds(int sum_rows, int d);
+int kmeans_update_rows(int K);
+// Candidates one update work-group can hold.
+int kmeans_update_max_candidates();
 void launch_kmeans_reset(const KmeansPlan& p, hipStream_t st);
+void launch_zmax(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t st);
 void launch_race_pick(const KmeansPlan& p, const float* Z, int t, uint64_t seed, hipStream_t st);
 void launch_init_centres(const KmeansPlan& p, const float* Z, hipStream_t st);
 void launch_assign(const KmeansPlan& p, const float* Z, hipStream_t st);
 void launch_iter_finalize(const KmeansPlan& p, int it, int t_max, hipStream_t st);
 void launch_update(const KmeansPlan& p, const float* Z, size_t lds_max, hipStream_t st);
-// LDS bytes the update kernel needs per work-group for the largest K.
-size_t kmeans_update_lds(int k_max, int d, int waves);
-int kmeans_update_waves(int k_max, int d, size_t lds_max);
 
 // ---- score.hip -----------------------------------------------------------
 struct ScorePlan {
-    int32_t n, Kc, S;     // S = row stride of point-major labels (multiple of 4)
+    int32_t n, Kc, S;     // S = row stride of point-major labels (multiple of 8)
     int32_t SK;           // sum of K
     int32_t grid;
     int64_t nnz;

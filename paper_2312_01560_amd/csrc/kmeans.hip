@@ -210,8 +210,9 @@ __global__ __launch_bounds__(256) void k_assign(KmeansPlan p, const float* __res
             b[ps][s + 3] = v.w;
         }
     }
-    const int k0 = p.grp[blockIdx.y], k1 = p.grp[blockIdx.y + 1];
-    for (int k = k0; k < k1; ++k) {
+    const int t0 = p.agrp[blockIdx.y], t1 = p.agrp[blockIdx.y + 1];
+    for (int t = t0; t < t1; ++t) {
+        const int k = p.alist[t];
         if (!p.active[k]) continue;
         const int K = p.ks[k];
         const int c0 = p.koff16[k];
@@ -307,77 +308,124 @@ __global__ __launch_bounds__(256) void k_iter_finalize(KmeansPlan p, int it, int
     if (threadIdx.x == 0) *p.active_count = cnt;
 }
 
-// Centre sums of one (point chunk, candidate).  Dynamic LDS:
-// float acc[W][K][D], int cnt[W][K].
-template <int D>
-__global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __restrict__ Z) {
-    const int k = blockIdx.y;
-    if (!p.active[k]) return;
-    extern __shared__ float lds[];
-    const int K = p.ks[k];
-    const int W = blockDim.x / kWave;
-    float* acc = lds;
-    int* cnt = reinterpret_cast<int*>(lds + (size_t)W * K * D);
-    for (int idx = threadIdx.x; idx < W * K * (D + 1); idx += blockDim.x) lds[idx] = 0.f;
+// Largest |z| (bit pattern of a non-negative float orders as an integer):
+// block maximum, then one atomic per block.
+__global__ __launch_bounds__(256) void k_zmax(KmeansPlan p, const float* __restrict__ Z) {
+    const int64_t total = (int64_t)p.n * p.d;
+    float m = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, fabsf(Z[i]));
+    if (!(m <= 3.0e38f)) m = 3.0e38f;   // non-finite input: keep the exponent sane
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, kWave));
+    __shared__ float wm[4];
+    if ((threadIdx.x & (kWave - 1)) == 0) wm[threadIdx.x / kWave] = m;
     __syncthreads();
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    const int p0 = blockIdx.x * p.chunk_len;
-    const int p1 = min(p.n, p0 + p.chunk_len);
-    const int len = max(0, p1 - p0);
-    const int per = (len + W - 1) / W;
-    const int q0 = p0 + wid * per;
-    const int q1 = min(p1, q0 + per);
-    const uint8_t* lab = p.lab_cm + (size_t)k * p.n;
-    float* my = acc + (size_t)wid * K * D;
-    int* myc = cnt + wid * K;
-    constexpr int CPL = D >= kWave ? D / kWave : 1;   // columns per lane
-    const bool lane_on = lane < D;
-    int q = q0;
-    for (; q + 4 <= q1; q += 4) {
-        int a[4];
-        float v[4][CPL];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            a[u] = lab[q + u];
-#pragma unroll
-            for (int c = 0; c < CPL; ++c)
-                v[u][c] = lane_on ? Z[(size_t)(q + u) * D + lane + c * kWave] : 0.f;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (lane_on) {
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) atomicAdd(&my[a[u] * D + lane + c * kWave], v[u][c]);
-            }
-            if (lane == 0) atomicAdd(&myc[a[u]], 1);
-        }
-    }
-    for (; q < q1; ++q) {
-        const int a = lab[q];
-        if (lane_on) {
-#pragma unroll
-            for (int c = 0; c < CPL; ++c)
-                atomicAdd(&my[a * D + lane + c * kWave], Z[(size_t)q * D + lane + c * kWave]);
-        }
-        if (lane == 0) atomicAdd(&myc[a], 1);
-    }
-    __syncthreads();
-    const size_t rowbase = (size_t)blockIdx.x * p.KP + p.koff16[k];
-    for (int idx = threadIdx.x; idx < K * D; idx += blockDim.x) {
-        float s = 0.f;
-        for (int w = 0; w < W; ++w) s += acc[(size_t)w * K * D + idx];
-        p.psum[rowbase * D + idx] = s;
-    }
-    for (int idx = threadIdx.x; idx < K; idx += blockDim.x) {
-        int s = 0;
-        for (int w = 0; w < W; ++w) s += cnt[w * K + idx];
-        p.pcnt[rowbase + idx] = s;
+    if (threadIdx.x == 0) {
+        const float b = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
+        atomicMax(p.zmax_bits, __float_as_uint(b));
     }
 }
 
-// Means from the chunk partials (fixed order, FP64); an empty cluster keeps
-// its centre.  One wave per padded centre row.
-template <int D>
+// Fixed-point exponent e: |z| * 2^e < 2^30 for every |z| <= zmax.
+__device__ __forceinline__ int fixed_exp(const KmeansPlan& p) {
+    const float zmax = __uint_as_float(*p.zmax_bits);
+    if (!(zmax > 0.f)) return 0;
+    int ez;
+    frexpf(zmax, &ez);
+    return 30 - ez;
+}
+
+// Centre sums for one (point range, update group, 64-column slice).  Points
+// are quantised to int32 (z * 2^e) and summed in int64 LDS accumulators that
+// all waves of the work-group share: integer addition is associative, so the
+// sums do not depend on the order of the atomic adds (deterministic), and
+// integer LDS atomics are fast on this hardware where float ones are not.
+// A wave holds 64 points of its slice in registers (lane = column) and adds
+// each into the cluster row of every active candidate of the group; padding
+// points go to a dummy row so the inner loop has no branches.  Each range's
+// exact sums are written as FP32 partials, combined in FP64 in a fixed
+// order by k_update_finish.
+constexpr int kUpdWaves = 4;
+constexpr int kUpdMaxCand = 32;
+
+__global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __restrict__ Z) {
+    extern __shared__ unsigned long long acc64[];
+    const int nsl = p.d > 64 ? p.d / 64 : 1;
+    const int g = blockIdx.y / nsl, sl = blockIdx.y % nsl;
+    const int t0 = p.ugrp[g], t1 = p.ugrp[g + 1];
+    int rows = 0;
+    bool any = false;
+    for (int t = t0; t < t1; ++t) {
+        const int k = p.alist[t];
+        rows += p.ks[k];
+        any |= p.active[k] != 0;
+    }
+    if (!any) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int total_rows = rows + 1;                          // + one dummy row
+    int* cnt = reinterpret_cast<int*>(acc64 + (size_t)total_rows * kWave);
+    for (int idx = threadIdx.x; idx < total_rows * kWave; idx += blockDim.x) acc64[idx] = 0ull;
+    for (int idx = threadIdx.x; idx < total_rows; idx += blockDim.x) cnt[idx] = 0;
+    __syncthreads();
+    const float sc = ldexpf(1.0f, fixed_exp(p));
+    const int dummy = rows;
+    const int col = sl * 64 + lane;
+    const bool on = col < p.d;
+    const int r0 = blockIdx.x * p.range_len;
+    const int r1 = min(p.n, r0 + p.range_len);
+    unsigned long long* acol = acc64 + lane;
+    for (int cs = r0 + wid * kWave; cs < r1; cs += kUpdWaves * kWave) {
+        const int np = min(kWave, r1 - cs);
+        int zf[kWave];
+#pragma unroll
+        for (int q = 0; q < kWave; ++q) {
+            const int pt = cs + min(q, np - 1);
+            const float v = (on && q < np) ? Z[(size_t)pt * p.d + col] : 0.f;
+            zf[q] = __float2int_rn(v * sc);
+        }
+        int base = 0;
+        for (int t = t0; t < t1; ++t) {
+            const int k = p.alist[t];
+            const int K = p.ks[k];
+            if (p.active[k]) {
+                const int row = lane < np ? base + (int)p.lab_cm[(size_t)k * p.n + cs + lane] : dummy;
+                if (sl == 0) atomicAdd(&cnt[row], 1);
+#pragma unroll
+                for (int q = 0; q < kWave; ++q) {
+                    const int a = __builtin_amdgcn_readlane(row, q);
+                    atomicAdd(acol + (size_t)a * kWave, (unsigned long long)(long long)zf[q]);
+                }
+            }
+            base += K;
+        }
+    }
+    __syncthreads();
+    const float inv = ldexpf(1.0f, -fixed_exp(p));
+    int base = 0;
+    for (int t = t0; t < t1; ++t) {
+        const int k = p.alist[t];
+        const int K = p.ks[k];
+        if (p.active[k]) {
+            float* dst = p.psum + ((size_t)blockIdx.x * p.KP + p.koff16[k]) * p.d + sl * 64;
+            const int sw = min(64, p.d);
+            for (int idx = threadIdx.x; idx < K * sw; idx += blockDim.x) {
+                const int r = idx / sw, c = idx - (idx / sw) * sw;
+                const long long v = (long long)acc64[(size_t)(base + r) * kWave + c];
+                dst[(size_t)r * p.d + c] = (float)((double)v * (double)inv);
+            }
+            if (sl == 0)
+                for (int idx = threadIdx.x; idx < K; idx += blockDim.x)
+                    p.pcnt[(size_t)blockIdx.x * p.KP + p.koff16[k] + idx] = cnt[base + idx];
+        }
+        base += K;
+    }
+}
+
+// Means from the range partials (FP64, ranges in order); an empty cluster
+// keeps its centre.  One wave per padded centre row.
 __global__ __launch_bounds__(256) void k_update_finish(KmeansPlan p) {
     const int c = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int lane = threadIdx.x & (kWave - 1);
@@ -386,13 +434,24 @@ __global__ __launch_bounds__(256) void k_update_finish(KmeansPlan p) {
     if (!p.active[k]) return;
     if (c - p.koff16[k] >= p.ks[k]) return;
     int count = 0;
-    for (int ch = 0; ch < p.chunks; ++ch) count += p.pcnt[(size_t)ch * p.KP + c];
+    for (int ch = 0; ch < p.ranges; ++ch) count += p.pcnt[(size_t)ch * p.KP + c];
     if (count == 0) return;
-    float* crow = p.C + (size_t)c * D;
+    float* crow = p.C + (size_t)c * p.d;
     float ss = 0.f;
-    for (int dd = lane; dd < D; dd += kWave) {
+    const size_t stride = (size_t)p.KP * p.d;
+    for (int dd = lane; dd < p.d; dd += kWave) {
+        const float* src = p.psum + (size_t)c * p.d + dd;
         double s = 0.0;
-        for (int ch = 0; ch < p.chunks; ++ch) s += (double)p.psum[((size_t)ch * p.KP + c) * D + dd];
+        int ch = 0;
+        for (; ch + 4 <= p.ranges; ch += 4) {
+            const double a0 = src[ch * stride], a1 = src[(ch + 1) * stride];
+            const double a2 = src[(ch + 2) * stride], a3 = src[(ch + 3) * stride];
+            s += a0;
+            s += a1;
+            s += a2;
+            s += a3;
+        }
+        for (; ch < p.ranges; ++ch) s += (double)src[ch * stride];
         const float v = (float)(s / (double)count);
         crow[dd] = v;
         ss += v * v;
@@ -413,24 +472,30 @@ __global__ void k_kmeans_reset(KmeansPlan p) {
     if (tid == 0) {
         *p.race_counter = 0u;
         *p.active_count = p.Kc;
+        *p.zmax_bits = 0u;
     }
 }
 
 bool kmeans_supported(int d) { return d == 16 || d == 32 || d == 64 || d == 128 || d == 256; }
 
 int kmeans_race_grid(int32_t n, int num_cu) {
-    const int64_t want = ((int64_t)n + kRaceThreads * 4 - 1) / (kRaceThreads * 4);
-    return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)num_cu * 4));
+    const int64_t want = ((int64_t)n + kRaceThreads - 1) / kRaceThreads;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)num_cu * 8));
 }
 
-size_t kmeans_update_lds(int k_max, int d, int waves) {
-    return (size_t)waves * k_max * (d + 1) * sizeof(float);
+size_t kmeans_update_lds(int sum_rows, int d) {
+    (void)d;
+    return (size_t)(sum_rows + 1) * (kWave * sizeof(unsigned long long) + sizeof(int));
 }
 
-int kmeans_update_waves(int k_max, int d, size_t lds_max) {
-    for (int w = 4; w >= 1; --w)
-        if (kmeans_update_lds(k_max, d, w) <= lds_max) return w;
-    return 0;
+int kmeans_update_rows(int K) { return K; }
+
+int kmeans_update_max_candidates() { return kUpdMaxCand; }
+
+void launch_zmax(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t st) {
+    const int64_t total = (int64_t)p.n * p.d;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, num_cu * 2));
+    hipLaunchKernelGGL(k_zmax, dim3(grid), dim3(256), 0, st, p, Z);
 }
 
 void launch_kmeans_reset(const KmeansPlan& p, hipStream_t st) {
@@ -473,7 +538,7 @@ void launch_assign(const KmeansPlan& p, const float* Z, hipStream_t st) {
     {                                                                                     \
         constexpr int PS = assign_ps<DV>();                                               \
         const int pts_per_block = 4 * 16 * PS;                                            \
-        dim3 grid((p.n + pts_per_block - 1) / pts_per_block, p.groups);                   \
+        dim3 grid((p.n + pts_per_block - 1) / pts_per_block, p.agroups);                   \
         hipLaunchKernelGGL((k_assign<DV, PS>), grid, dim3(256), 0, st, p, Z);             \
     }
     RAFT_D_SWITCH(p.d, ASSIGN)
@@ -485,25 +550,18 @@ void launch_iter_finalize(const KmeansPlan& p, int it, int t_max, hipStream_t st
 }
 
 void launch_update(const KmeansPlan& p, const float* Z, size_t lds_max, hipStream_t st) {
-    const int waves = kmeans_update_waves(p.k_max, p.d, lds_max);
-    const size_t lds = kmeans_update_lds(p.k_max, p.d, waves);
-    dim3 grid(p.chunks, p.Kc);
-#define UPD(DV)                                                                              \
-    {                                                                                        \
-        static bool attr_set = false;                                                        \
-        if (!attr_set) {                                                                     \
-            (void)hipFuncSetAttribute((const void*)k_update<DV>,                             \
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max); \
-            attr_set = true;                                                                 \
-        }                                                                                    \
-        hipLaunchKernelGGL(k_update<DV>, grid, dim3(waves * kWave), lds, st, p, Z);          \
+    const size_t lds = kmeans_update_lds(p.usk_max, p.d);
+    const int nsl = p.d > 64 ? p.d / 64 : 1;
+    dim3 grid(p.ranges, p.ugroups * nsl);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void*)k_update, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds_max);
+        attr_set = true;
     }
-    RAFT_D_SWITCH(p.d, UPD)
-#undef UPD
+    hipLaunchKernelGGL(k_update, grid, dim3(kUpdWaves * kWave), lds, st, p, Z);
     const int fgrid = (p.KP * kWave + 255) / 256;
-#define FIN(DV) hipLaunchKernelGGL(k_update_finish<DV>, dim3(fgrid), dim3(256), 0, st, p)
-    RAFT_D_SWITCH(p.d, FIN)
-#undef FIN
+    hipLaunchKernelGGL(k_update_finish, dim3(fgrid), dim3(256), 0, st, p);
 }
 
 }  // namespace raft

@@ -8,11 +8,13 @@
 // ascending order without contraction.  K* is the first maximum of Mod over
 // the grid; its labels are renumbered by first occurrence in node order.
 //
-// Edge kernel: labels are point-major bytes, row stride S (multiple of 4), so
-// one uint32 load gives four candidates' labels of a node; LPR lanes cover a
-// node's label row and 64/LPR edges are compared per wave step with a
-// per-byte equality mask.  Counts are reduced over the edge slots by xor
-// shuffles and accumulated per work-group in LDS, then written as partials.
+// Edge kernel: labels are point-major bytes, row stride S (multiple of 8),
+// so one 8-byte load gives eight candidates' labels of a node.  LPR lanes
+// cover a node's label row and a wave scores 64/LPR rows side by side: per
+// batch of 16 edges the lanes of a row group load the same column indices
+// (broadcast loads) and gather the neighbours' label words back to back,
+// comparing bytes with an exact per-byte zero mask.  Counts are accumulated per work-group in LDS and
+// written as partials; all counts are integers, so their sums are exact.
 #include <limits.h>
 
 #include <algorithm>
@@ -48,71 +50,84 @@ __device__ __forceinline__ uint32_t zero_bytes_mask(uint32_t x) {
 
 template <int LPR>
 __global__ __launch_bounds__(256) void k_edge_score(GraphView g, ScorePlan p,
-                                                    const uint8_t* __restrict__ lab) {
-    constexpr int SLOTS = kWave / LPR;
+                                                    const uint8_t* __restrict__ lab, int rpw) {
+    constexpr int G = kWave / LPR;                  // rows side by side per wave
     extern __shared__ int sm[];
     int* sl = sm;
     int* sv = sm + p.SK;
     for (int idx = threadIdx.x; idx < 2 * p.SK; idx += blockDim.x) sm[idx] = 0;
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
     const int slot = lane / LPR;
     const int m = lane % LPR;
-    const bool on = 4 * m < p.S;
-    const int waves = gridDim.x * (blockDim.x / kWave);
-    const int wave = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    for (int i = wave; i < g.n; i += waves) {
-        const uint32_t li = on ? *reinterpret_cast<const uint32_t*>(lab + (size_t)i * p.S + 4 * m) : 0u;
-        int c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-        const int beg = g.rp[i], end = g.rp[i + 1];
-        int e = beg + slot;
-        for (; e + 3 * SLOTS < end; e += 4 * SLOTS) {
-            int j[4];
-            uint32_t lj[4];
+    const bool on = 8 * m < p.S;
+    const int row0 = (blockIdx.x * (blockDim.x / kWave) + wid) * rpw * G;
+    const int nrw = rpw * G;
+    const bool pre = nrw < kWave;
+    const int rpv = pre ? g.rp[min(row0 + lane, g.n)] : 0;
+    for (int r = 0; r < rpw; ++r) {
+        const int i = row0 + r * G + slot;
+        const bool valid = i < g.n;
+        if (__ballot(valid) == 0) break;
+        int beg, end;
+        if (pre) {
+            beg = __shfl(rpv, r * G + slot, kWave);
+            end = __shfl(rpv, r * G + slot + 1, kWave);
+        } else {
+            beg = valid ? g.rp[i] : 0;
+            end = valid ? g.rp[i + 1] : 0;
+        }
+        if (!valid) end = beg;
+        int maxdeg = end - beg;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) j[u] = g.ci[e + u * SLOTS];
+        for (int off = LPR; off < kWave; off <<= 1)
+            maxdeg = max(maxdeg, __shfl_xor(maxdeg, off, kWave));
+        uint2 li = make_uint2(0u, 0u);
+        if (valid && on) li = *reinterpret_cast<const uint2*>(lab + (size_t)i * p.S + 8 * m);
+        int c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int base = 0; base < maxdeg; base += 16) {
+            int jv[16];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                lj[u] = on ? *reinterpret_cast<const uint32_t*>(lab + (size_t)j[u] * p.S + 4 * m) : 1u;
+            for (int q = 0; q < 16; ++q) {
+                const int e = beg + base + q;
+                jv[q] = e < end ? g.ci[e] : -1;
+            }
+            uint2 lj[16];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint32_t z = zero_bytes_mask(li ^ lj[u]);
-                c0 += (z >> 7) & 1u;
-                c1 += (z >> 15) & 1u;
-                c2 += (z >> 23) & 1u;
-                c3 += (z >> 31) & 1u;
+            for (int q = 0; q < 16; ++q) {
+                // a non-edge compares against a word with no byte equal to li
+                lj[q] = make_uint2(~li.x, ~li.y);
+                if (jv[q] >= 0 && on)
+                    lj[q] = *reinterpret_cast<const uint2*>(lab + (size_t)jv[q] * p.S + 8 * m);
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const uint32_t z0 = zero_bytes_mask(li.x ^ lj[q].x);
+                const uint32_t z1 = zero_bytes_mask(li.y ^ lj[q].y);
+                c[0] += (z0 >> 7) & 1u;
+                c[1] += (z0 >> 15) & 1u;
+                c[2] += (z0 >> 23) & 1u;
+                c[3] += (z0 >> 31) & 1u;
+                c[4] += (z1 >> 7) & 1u;
+                c[5] += (z1 >> 15) & 1u;
+                c[6] += (z1 >> 23) & 1u;
+                c[7] += (z1 >> 31) & 1u;
             }
         }
-        for (; e < end; e += SLOTS) {
-            const int j = g.ci[e];
-            const uint32_t lj = on ? *reinterpret_cast<const uint32_t*>(lab + (size_t)j * p.S + 4 * m) : 1u;
-            const uint32_t z = zero_bytes_mask(li ^ lj);
-            c0 += (z >> 7) & 1u;
-            c1 += (z >> 15) & 1u;
-            c2 += (z >> 23) & 1u;
-            c3 += (z >> 31) & 1u;
-        }
-#pragma unroll
-        for (int off = LPR; off < kWave; off <<= 1) {
-            c0 += __shfl_xor(c0, off, kWave);
-            c1 += __shfl_xor(c1, off, kWave);
-            c2 += __shfl_xor(c2, off, kWave);
-            c3 += __shfl_xor(c3, off, kWave);
-        }
-        if (slot == 0 && on) {
+        if (valid && on) {
             const int d = end - beg;
-            const int cc[4] = {c0, c1, c2, c3};
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int k = 4 * m + b;
+            for (int b = 0; b < 8; ++b) {
+                const int k = 8 * m + b;
                 if (k < p.Kc) {
-                    const int r = (li >> (8 * b)) & 0xFF;
-                    if (r >= p.ks[k]) {
+                    const int rr = ((b < 4 ? li.x : li.y) >> (8 * (b & 3))) & 0xFF;
+                    if (rr >= p.ks[k]) {
                         atomicOr(p.status, kStatusLabel);
                         continue;
                     }
-                    const int slotk = p.koff[k] + r;
-                    if (cc[b]) atomicAdd(&sl[slotk], cc[b]);
+                    const int slotk = p.koff[k] + rr;
+                    if (c[b]) atomicAdd(&sl[slotk], c[b]);
                     if (d) atomicAdd(&sv[slotk], d);
                 }
             }
@@ -125,39 +140,65 @@ __global__ __launch_bounds__(256) void k_edge_score(GraphView g, ScorePlan p,
     }
 }
 
+// Sum of the work-group partials: 16 entries x 16 slices per block, slices
+// combined through LDS.  Integer sums, exact.
 __global__ __launch_bounds__(256) void k_reduce_counts(ScorePlan p) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= p.SK) return;
-    int64_t l = 0, v = 0;
-    for (int b = 0; b < p.grid; ++b) {
-        l += p.lpart[(size_t)b * p.SK + idx];
-        v += p.vpart[(size_t)b * p.SK + idx];
+    __shared__ long long sl[16][17], sv[16][17];
+    const int e = threadIdx.x & 15, sl_id = threadIdx.x >> 4;
+    const int idx = blockIdx.x * 16 + e;
+    long long l = 0, v = 0;
+    if (idx < p.SK) {
+        const int per = (p.grid + 15) / 16;
+        const int b0 = sl_id * per, b1 = min(p.grid, b0 + per);
+        for (int b = b0; b < b1; ++b) {
+            l += p.lpart[(size_t)b * p.SK + idx];
+            v += p.vpart[(size_t)b * p.SK + idx];
+        }
     }
-    p.l64[idx] = l / 2;
-    p.v64[idx] = v;
+    sl[e][sl_id] = l;
+    sv[e][sl_id] = v;
+    __syncthreads();
+    if (sl_id == 0 && idx < p.SK) {
+        long long tl = 0, tv = 0;
+        for (int q = 0; q < 16; ++q) {
+            tl += sl[e][q];
+            tv += sv[e][q];
+        }
+        p.l64[idx] = tl / 2;
+        p.v64[idx] = tv;
+    }
 }
 
-__global__ __launch_bounds__(256) void k_score_finalize(ScorePlan p) {
-#pragma clang fp contract(off)
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per candidate: the counts are staged in LDS, the FP64 sums run
+// over r in ascending order on one lane.
+__global__ __launch_bounds__(64) void k_score_finalize(ScorePlan p) {
+    __shared__ long long ls[RAFT_MAX_K_DEV + 1], vs[RAFT_MAX_K_DEV + 1];
+    const int k = blockIdx.x;
     if (k >= p.Kc) return;
     const int K = p.ks[k];
-    const int64_t* l = p.l64 + p.koff[k];
-    const int64_t* v = p.v64 + p.koff[k];
-    const double e = (double)(p.nnz / 2);
-    const double m2 = (double)p.nnz;
-    double mod = 0.0;
-    for (int r = 0; r < K; ++r) {
-        const double t = (double)v[r] / m2;
-        const double term = (double)l[r] / e - t * t;
-        mod = mod + term;
+    for (int r = threadIdx.x; r < K; r += blockDim.x) {
+        ls[r] = p.l64[p.koff[k] + r];
+        vs[r] = p.v64[p.koff[k] + r];
     }
-    double nc = 0.0;
-    for (int r = 0; r < K; ++r) {
-        if (v[r] > 0) nc = nc + (double)(v[r] - 2 * l[r]) / (double)v[r];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    {
+#pragma clang fp contract(off)
+        const double e = (double)(p.nnz / 2);
+        const double m2 = (double)p.nnz;
+        double mod = 0.0;
+        for (int r = 0; r < K; ++r) {
+            const double t = (double)vs[r] / m2;
+            const double term = (double)ls[r] / e - t * t;
+            mod = mod + term;
+        }
+        double nc = 0.0;
+        for (int r = 0; r < K; ++r) {
+            if (vs[r] > 0) nc = nc + (double)(vs[r] - 2 * ls[r]) / (double)vs[r];
+        }
+        p.mod[k] = mod;
+        p.ncut[k] = 0.5 * nc;
     }
-    p.mod[k] = mod;
-    p.ncut[k] = 0.5 * nc;
 }
 
 // K* = first maximum of Mod; init first-occurrence table.
@@ -174,10 +215,15 @@ __global__ void k_select_best(ScorePlan p, int32_t* k_selected) {
 }
 
 __global__ __launch_bounds__(256) void k_first_occ(ScorePlan p, const uint8_t* __restrict__ lab) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= p.n) return;
-    const int r = lab[(size_t)i * p.S + *p.best];
-    atomicMin(&p.first[r], i);
+    __shared__ int first[RAFT_MAX_K_DEV + 1];
+    for (int r = threadIdx.x; r <= RAFT_MAX_K_DEV; r += blockDim.x) first[r] = INT_MAX;
+    __syncthreads();
+    const int best = *p.best;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < p.n; i += gridDim.x * blockDim.x)
+        atomicMin(&first[lab[(size_t)i * p.S + best]], i);
+    __syncthreads();
+    for (int r = threadIdx.x; r <= RAFT_MAX_K_DEV; r += blockDim.x)
+        if (first[r] != INT_MAX) atomicMin(&p.first[r], first[r]);
 }
 
 __global__ void k_rank(ScorePlan p, int32_t* k_selected) {
@@ -207,6 +253,19 @@ __global__ __launch_bounds__(256) void k_apply(ScorePlan p, const uint8_t* __res
     out[i] = p.remap[lab[(size_t)i * p.S + *p.best]];
 }
 
+static int score_lpr(int S) {
+    const int words = S / 8;
+    int lpr = 1;
+    while (lpr < words) lpr <<= 1;
+    return lpr;
+}
+
+static int score_rpw(int32_t n, int S, int grid) {
+    const int G = kWave / score_lpr(S);
+    const int64_t rows_per_block = ((int64_t)n + grid - 1) / grid;
+    return (int)std::max<int64_t>(1, (rows_per_block + 4 * G - 1) / (4 * G));
+}
+
 int score_grid(int32_t n, int num_cu) {
     const int64_t want = ((int64_t)n + 63) / 64;
     return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)num_cu * 2));
@@ -233,9 +292,8 @@ void launch_copy_labels(const uint8_t* pm, int32_t n, int Kc, int S, uint8_t* ou
 void launch_edge_score(const GraphView& g, const ScorePlan& p, const uint8_t* lab,
                        hipStream_t st) {
     const size_t lds = (size_t)2 * p.SK * sizeof(int);
-    const int words = p.S / 4;
-    int lpr = 1;
-    while (lpr < words) lpr <<= 1;
+    const int lpr = score_lpr(p.S);
+    const int rpw = score_rpw(g.n, p.S, p.grid);
 #define EDGE(LV)                                                                              \
     {                                                                                         \
         static bool attr = false;                                                             \
@@ -244,7 +302,7 @@ void launch_edge_score(const GraphView& g, const ScorePlan& p, const uint8_t* la
                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024); \
             attr = true;                                                                      \
         }                                                                                     \
-        hipLaunchKernelGGL(k_edge_score<LV>, dim3(p.grid), dim3(256), lds, st, g, p, lab);    \
+        hipLaunchKernelGGL(k_edge_score<LV>, dim3(p.grid), dim3(256), lds, st, g, p, lab, rpw); \
     }
     switch (lpr) {
         case 1: EDGE(1) break;
@@ -252,15 +310,14 @@ void launch_edge_score(const GraphView& g, const ScorePlan& p, const uint8_t* la
         case 4: EDGE(4) break;
         case 8: EDGE(8) break;
         case 16: EDGE(16) break;
-        case 32: EDGE(32) break;
-        default: EDGE(64) break;
+        default: EDGE(32) break;
     }
 #undef EDGE
 }
 
 void launch_score_finish(const ScorePlan& p, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_counts, dim3((p.SK + 255) / 256), dim3(256), 0, st, p);
-    hipLaunchKernelGGL(k_score_finalize, dim3((p.Kc + 255) / 256), dim3(256), 0, st, p);
+    hipLaunchKernelGGL(k_reduce_counts, dim3((p.SK + 15) / 16), dim3(256), 0, st, p);
+    hipLaunchKernelGGL(k_score_finalize, dim3(p.Kc), dim3(64), 0, st, p);
 }
 
 void launch_select(const ScorePlan& p, const uint8_t* lab, int32_t* labels_out,
@@ -268,7 +325,7 @@ void launch_select(const ScorePlan& p, const uint8_t* lab, int32_t* labels_out,
     hipLaunchKernelGGL(k_select_best, dim3(1), dim3(256), 0, st, p, k_selected);
     if (p.n == 0) return;
     const int grid = (p.n + 255) / 256;
-    hipLaunchKernelGGL(k_first_occ, dim3(grid), dim3(256), 0, st, p, lab);
+    hipLaunchKernelGGL(k_first_occ, dim3(std::min(grid, 256)), dim3(256), 0, st, p, lab);
     hipLaunchKernelGGL(k_rank, dim3(1), dim3(256), 0, st, p, k_selected);
     if (labels_out)
         hipLaunchKernelGGL(k_apply, dim3(grid), dim3(256), 0, st, p, lab, labels_out);

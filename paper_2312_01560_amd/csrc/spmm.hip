@@ -6,132 +6,149 @@
 //   GCN         y_i = sh_i (sum_{j in N(i)} sh_j x_j + sh_i x_i)       (A_hat_n)
 // with s = D^-1/2 and sh = (D+1)^-1/2.
 //
-// Row-split CSR: one wave per row.  The wave reads up to 64 column indices
-// coalesced (one per lane), then gathers feature rows: each lane loads a
-// float4, L/4 lanes cover one row of x, so 256/L edges are gathered per wave
-// instruction and several such steps are kept in flight.  Partial sums of
-// the edge slots are folded with xor shuffles.  Rows are assigned in
-// contiguous runs per wave; the optional epilogue accumulates FP64 partials
-// of d^T y per work-group (the rank-1 term of the next MOD_FULL step), in a
-// fixed order so the column sums are deterministic.
+// Row-split CSR with one row per lane group: L/4 lanes hold one feature row
+// (a float4 each), so a wave works on 256/L rows side by side.  The row
+// pointers of a wave's rows come in one load; per batch of 16 edges the lanes
+// of a row group load the same column indices (broadcast loads), then all 16
+// neighbour rows are gathered back to back, the edge weight (a per-node
+// scale) loaded next to each feature row.  Rows are assigned in contiguous runs per wave; the optional
+// epilogue accumulates FP64 partials of d^T y per work-group (the rank-1 term
+// of the next MOD_FULL step) in a fixed order, so the column sums are
+// deterministic.
 #include "kernels.h"
 
 namespace raft {
 
 constexpr int kSpmmWaves = 4;
 
+template <int L, int OP>
+__device__ __forceinline__ float edge_weight(const GraphView& g, int j) {
+    if (OP == kOpNcut) return g.s[j];
+    if (OP == kOpGcn) return g.sh[j];
+    if (OP == kOpModReduced) return (float)g.deg[j];
+    return 1.f;
+}
+
 template <int L, int OP, bool CS>
 __global__ __launch_bounds__(256) void k_spmm(GraphView g, const float* __restrict__ x,
                                               float* __restrict__ y,
                                               const float* __restrict__ cvec,
                                               double* __restrict__ cpart, int rpw) {
-    constexpr int LANES = L / 4;
-    constexpr int SLOTS = kWave / LANES;
-    constexpr int UNR = SLOTS >= 16 ? 1 : 16 / SLOTS;
+    constexpr int LANES = L / 4;                  // lanes per feature row
+    constexpr int G = kWave / LANES;              // rows side by side per wave
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
     const int slot = lane / LANES;
     const int sub = lane % LANES;
-    const int row0 = (blockIdx.x * kSpmmWaves + wid) * rpw;
+    const int row0 = (blockIdx.x * kSpmmWaves + wid) * rpw * G;
     double cs0 = 0, cs1 = 0, cs2 = 0, cs3 = 0;
 
+    // row pointers of all the wave's rows in one load (lane t holds rp[row0 + t])
+    const int nrw = rpw * G;
+    const bool pre = nrw < kWave;
+    const int rpv = pre ? g.rp[min(row0 + lane, g.n)] : 0;
     for (int r = 0; r < rpw; ++r) {
-        const int i = row0 + r;
-        if (i >= g.n) break;
-        const int beg = g.rp[i], end = g.rp[i + 1];
+        const int i = row0 + r * G + slot;
+        const bool valid = i < g.n;
+        if (__ballot(valid) == 0) break;
+        int beg, end;
+        if (pre) {
+            beg = __shfl(rpv, r * G + slot, kWave);
+            end = __shfl(rpv, r * G + slot + 1, kWave);
+        } else {
+            beg = valid ? g.rp[i] : 0;
+            end = valid ? g.rp[i + 1] : 0;
+        }
+        if (!valid) end = beg;
+        int maxdeg = end - beg;
+#pragma unroll
+        for (int off = LANES; off < kWave; off <<= 1)
+            maxdeg = max(maxdeg, __shfl_xor(maxdeg, off, kWave));
         float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
         float4 acc2 = make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int base = beg; base < end; base += kWave) {
-            const int e = base + lane;
-            int j = i;
-            float w = 0.f;
-            if (e < end) {
-                j = g.ci[e];
-                if (OP == kOpNcut) w = g.s[j];
-                else if (OP == kOpGcn) w = g.sh[j];
-                else if (OP == kOpModReduced) w = (float)g.deg[j];
-                else w = 1.f;
+        // batches of 16 edges per row: the lanes of a row group load the same
+        // column index (a broadcast load), then all feature rows are gathered
+        for (int base = 0; base < maxdeg; base += 16) {
+            int jv[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int e = beg + base + q;
+                jv[q] = e < end ? g.ci[e] : -1;
             }
-            const int cnt = min(kWave, end - base);
-            for (int t = 0; t < cnt; t += SLOTS * UNR) {
-                float4 v[UNR];
-                float ww[UNR];
+            float4 xv[16];
+            float wv[16];
 #pragma unroll
-                for (int u = 0; u < UNR; ++u) {
-                    const int src = t + u * SLOTS + slot;
-                    const int jj = __shfl(j, src & (kWave - 1), kWave);
-                    ww[u] = __shfl(w, src & (kWave - 1), kWave);
-                    v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (src < cnt)
-                        v[u] = *reinterpret_cast<const float4*>(x + (size_t)jj * L + sub * 4);
+            for (int q = 0; q < 16; ++q) {
+                xv[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+                wv[q] = 0.f;
+                if (jv[q] >= 0) {
+                    xv[q] = *reinterpret_cast<const float4*>(x + (size_t)jv[q] * L + sub * 4);
+                    wv[q] = edge_weight<L, OP>(g, jv[q]);
                 }
+            }
 #pragma unroll
-                for (int u = 0; u < UNR; ++u) {
-                    if (OP == kOpModFull) {
-                        acc.x += v[u].x;
-                        acc.y += v[u].y;
-                        acc.z += v[u].z;
-                        acc.w += v[u].w;
-                    } else if (OP == kOpModReduced) {
-                        acc.x += v[u].x;
-                        acc.y += v[u].y;
-                        acc.z += v[u].z;
-                        acc.w += v[u].w;
-                        acc2.x += ww[u] * v[u].x;
-                        acc2.y += ww[u] * v[u].y;
-                        acc2.z += ww[u] * v[u].z;
-                        acc2.w += ww[u] * v[u].w;
-                    } else {
-                        acc.x += ww[u] * v[u].x;
-                        acc.y += ww[u] * v[u].y;
-                        acc.z += ww[u] * v[u].z;
-                        acc.w += ww[u] * v[u].w;
-                    }
+            for (int q = 0; q < 16; ++q) {
+                if (OP == kOpModFull) {
+                    acc.x += xv[q].x;
+                    acc.y += xv[q].y;
+                    acc.z += xv[q].z;
+                    acc.w += xv[q].w;
+                } else if (OP == kOpModReduced) {
+                    acc.x += xv[q].x;
+                    acc.y += xv[q].y;
+                    acc.z += xv[q].z;
+                    acc.w += xv[q].w;
+                    acc2.x += wv[q] * xv[q].x;
+                    acc2.y += wv[q] * xv[q].y;
+                    acc2.z += wv[q] * xv[q].z;
+                    acc2.w += wv[q] * xv[q].w;
+                } else {
+                    acc.x += wv[q] * xv[q].x;
+                    acc.y += wv[q] * xv[q].y;
+                    acc.z += wv[q] * xv[q].z;
+                    acc.w += wv[q] * xv[q].w;
                 }
             }
         }
-#pragma unroll
-        for (int off = LANES; off < kWave; off <<= 1) {
-            acc.x += __shfl_xor(acc.x, off, kWave);
-            acc.y += __shfl_xor(acc.y, off, kWave);
-            acc.z += __shfl_xor(acc.z, off, kWave);
-            acc.w += __shfl_xor(acc.w, off, kWave);
-            if (OP == kOpModReduced) {
-                acc2.x += __shfl_xor(acc2.x, off, kWave);
-                acc2.y += __shfl_xor(acc2.y, off, kWave);
-                acc2.z += __shfl_xor(acc2.z, off, kWave);
-                acc2.w += __shfl_xor(acc2.w, off, kWave);
+        if (valid) {
+            float4 o;
+            if (OP == kOpNcut) {
+                const float si = g.s[i];
+                o = make_float4(si * acc.x, si * acc.y, si * acc.z, si * acc.w);
+            } else if (OP == kOpGcn) {
+                const float si = g.sh[i];
+                const float4 xi = *reinterpret_cast<const float4*>(x + (size_t)i * L + sub * 4);
+                o = make_float4(si * (acc.x + si * xi.x), si * (acc.y + si * xi.y),
+                                si * (acc.z + si * xi.z), si * (acc.w + si * xi.w));
+            } else if (OP == kOpModFull) {
+                const float ci = g.dcoef[i];
+                const float4 c = *reinterpret_cast<const float4*>(cvec + sub * 4);
+                o = make_float4(acc.x - ci * c.x, acc.y - ci * c.y, acc.z - ci * c.z,
+                                acc.w - ci * c.w);
+            } else {
+                const float ci = g.dcoef[i];
+                o = make_float4(acc.x - ci * acc2.x, acc.y - ci * acc2.y, acc.z - ci * acc2.z,
+                                acc.w - ci * acc2.w);
             }
-        }
-        float4 o;
-        if (OP == kOpNcut) {
-            const float si = g.s[i];
-            o = make_float4(si * acc.x, si * acc.y, si * acc.z, si * acc.w);
-        } else if (OP == kOpGcn) {
-            const float si = g.sh[i];
-            const float4 xi = *reinterpret_cast<const float4*>(x + (size_t)i * L + sub * 4);
-            o = make_float4(si * (acc.x + si * xi.x), si * (acc.y + si * xi.y),
-                            si * (acc.z + si * xi.z), si * (acc.w + si * xi.w));
-        } else if (OP == kOpModFull) {
-            const float ci = g.dcoef[i];
-            const float4 c = *reinterpret_cast<const float4*>(cvec + sub * 4);
-            o = make_float4(acc.x - ci * c.x, acc.y - ci * c.y, acc.z - ci * c.z,
-                            acc.w - ci * c.w);
-        } else {
-            const float ci = g.dcoef[i];
-            o = make_float4(acc.x - ci * acc2.x, acc.y - ci * acc2.y, acc.z - ci * acc2.z,
-                            acc.w - ci * acc2.w);
-        }
-        if (slot == 0) *reinterpret_cast<float4*>(y + (size_t)i * L + sub * 4) = o;
-        if (CS) {
-            const double di = (double)g.deg[i];
-            cs0 += di * (double)o.x;
-            cs1 += di * (double)o.y;
-            cs2 += di * (double)o.z;
-            cs3 += di * (double)o.w;
+            *reinterpret_cast<float4*>(y + (size_t)i * L + sub * 4) = o;
+            if (CS) {
+                const double di = (double)g.deg[i];
+                cs0 += di * (double)o.x;
+                cs1 += di * (double)o.y;
+                cs2 += di * (double)o.z;
+                cs3 += di * (double)o.w;
+            }
         }
     }
     if (CS) {
+        // fold the row slots of the wave (fixed butterfly order), then the waves
+#pragma unroll
+        for (int off = LANES; off < kWave; off <<= 1) {
+            cs0 += __shfl_xor(cs0, off, kWave);
+            cs1 += __shfl_xor(cs1, off, kWave);
+            cs2 += __shfl_xor(cs2, off, kWave);
+            cs3 += __shfl_xor(cs3, off, kWave);
+        }
         __shared__ double red[kSpmmWaves][L];
         if (slot == 0) {
             red[wid][sub * 4 + 0] = cs0;
@@ -148,20 +165,22 @@ __global__ __launch_bounds__(256) void k_spmm(GraphView g, const float* __restri
     }
 }
 
-// FP64 partials of d^T x, same row mapping as k_spmm.
+// FP64 partials of d^T x over the same row blocks as k_spmm<L>.
 template <int L>
 __global__ __launch_bounds__(256) void k_colsum_part(GraphView g, const float* __restrict__ x,
                                                      double* __restrict__ cpart, int rpw) {
     constexpr int LANES = L / 4;
+    constexpr int G = kWave / LANES;
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
-    const int row0 = (blockIdx.x * kSpmmWaves + wid) * rpw;
+    const int slot = lane / LANES;
+    const int sub = lane % LANES;
+    const int row0 = (blockIdx.x * kSpmmWaves + wid) * rpw * G;
     double cs0 = 0, cs1 = 0, cs2 = 0, cs3 = 0;
-    if (lane < LANES) {
-        for (int r = 0; r < rpw; ++r) {
-            const int i = row0 + r;
-            if (i >= g.n) break;
-            const float4 o = *reinterpret_cast<const float4*>(x + (size_t)i * L + lane * 4);
+    for (int r = 0; r < rpw; ++r) {
+        const int i = row0 + r * G + slot;
+        if (i < g.n) {
+            const float4 o = *reinterpret_cast<const float4*>(x + (size_t)i * L + sub * 4);
             const double di = (double)g.deg[i];
             cs0 += di * (double)o.x;
             cs1 += di * (double)o.y;
@@ -169,12 +188,19 @@ __global__ __launch_bounds__(256) void k_colsum_part(GraphView g, const float* _
             cs3 += di * (double)o.w;
         }
     }
+#pragma unroll
+    for (int off = LANES; off < kWave; off <<= 1) {
+        cs0 += __shfl_xor(cs0, off, kWave);
+        cs1 += __shfl_xor(cs1, off, kWave);
+        cs2 += __shfl_xor(cs2, off, kWave);
+        cs3 += __shfl_xor(cs3, off, kWave);
+    }
     __shared__ double red[kSpmmWaves][L];
-    if (lane < LANES) {
-        red[wid][lane * 4 + 0] = cs0;
-        red[wid][lane * 4 + 1] = cs1;
-        red[wid][lane * 4 + 2] = cs2;
-        red[wid][lane * 4 + 3] = cs3;
+    if (slot == 0) {
+        red[wid][sub * 4 + 0] = cs0;
+        red[wid][sub * 4 + 1] = cs1;
+        red[wid][sub * 4 + 2] = cs2;
+        red[wid][sub * 4 + 3] = cs3;
     }
     __syncthreads();
     for (int c = threadIdx.x; c < L; c += blockDim.x) {
@@ -184,26 +210,32 @@ __global__ __launch_bounds__(256) void k_colsum_part(GraphView g, const float* _
     }
 }
 
-// c = sum over parts (fixed split into `per` contiguous slices per column,
-// slices combined in order), cvec = FP32(c).
-__global__ __launch_bounds__(1024) void k_colsum_finish(const double* __restrict__ part, int parts,
-                                                        int L, double* __restrict__ c64,
-                                                        float* __restrict__ cvec) {
-    const int per = blockDim.x / L;
-    const int col = threadIdx.x % L;
-    const int sl = threadIdx.x / L;
-    __shared__ double red[1024];
-    double s = 0;
-    if (sl < per) {
-        const int len = (parts + per - 1) / per;
-        const int b0 = sl * len, b1 = min(parts, b0 + len);
-        for (int b = b0; b < b1; ++b) s += part[(size_t)b * L + col];
+// c = sum over the partial rows in two fixed-order levels: block b sums the
+// contiguous slice b of the partials into stage[b]; one block then sums the
+// stage rows in order.  cvec = FP32(c).
+constexpr int kColsumSlices = 64;
+
+__global__ __launch_bounds__(256) void k_colsum_slices(const double* __restrict__ part, int parts,
+                                                       int L, double* __restrict__ stage) {
+    const int per = (parts + kColsumSlices - 1) / kColsumSlices;
+    const int b0 = blockIdx.x * per, b1 = min(parts, b0 + per);
+    for (int col = threadIdx.x; col < L; col += blockDim.x) {
+        double s = 0;
+        int b = b0;
+        for (; b + 4 <= b1; b += 4)
+            s += part[(size_t)b * L + col] + part[(size_t)(b + 1) * L + col] +
+                 part[(size_t)(b + 2) * L + col] + part[(size_t)(b + 3) * L + col];
+        for (; b < b1; ++b) s += part[(size_t)b * L + col];
+        stage[(size_t)blockIdx.x * L + col] = s;
     }
-    red[threadIdx.x] = s;
-    __syncthreads();
-    if (sl == 0) {
+}
+
+__global__ __launch_bounds__(256) void k_colsum_finish(const double* __restrict__ stage, int L,
+                                                       double* __restrict__ c64,
+                                                       float* __restrict__ cvec) {
+    for (int col = threadIdx.x; col < L; col += blockDim.x) {
         double t = 0;
-        for (int k = 0; k < per; ++k) t += red[k * L + col];
+        for (int k = 0; k < kColsumSlices; ++k) t += stage[(size_t)k * L + col];
         c64[col] = t;
         cvec[col] = (float)t;
     }
@@ -212,12 +244,13 @@ __global__ __launch_bounds__(1024) void k_colsum_finish(const double* __restrict
 bool spmm_supported(int L) { return L == 16 || L == 32 || L == 64 || L == 128 || L == 256; }
 
 int spmm_grid(int32_t n, int L, int num_cu, int* rows_per_wave) {
-    (void)L;
-    const int target_waves = num_cu * 32;
-    int rpw = (int)((n + (int64_t)target_waves - 1) / target_waves);
+    const int G = kWave / (L / 4);
+    const int64_t target_waves = (int64_t)num_cu * 32;
+    const int64_t per_wave = ((int64_t)n + target_waves - 1) / target_waves;
+    int rpw = (int)((per_wave + G - 1) / G);
     rpw = rpw < 1 ? 1 : (rpw > 64 ? 64 : rpw);
     if (rows_per_wave) *rows_per_wave = rpw;
-    const int64_t rows_per_block = (int64_t)rpw * kSpmmWaves;
+    const int64_t rows_per_block = (int64_t)rpw * G * kSpmmWaves;
     return (int)((n + rows_per_block - 1) / rows_per_block);
 }
 
@@ -273,8 +306,10 @@ void launch_colsum_partials(const GraphView& g, int L, const float* x, double* p
 
 void launch_colsum_finish(const double* part, int parts, int L, double* c64, float* cvec,
                           hipStream_t st) {
-    const int threads = (1024 / L) * L;
-    hipLaunchKernelGGL(k_colsum_finish, dim3(1), dim3(threads), 0, st, part, parts, L, c64, cvec);
+    // the caller reserves kColsumSlices more rows after the partials for the stage
+    double* stage = const_cast<double*>(part) + (size_t)parts * L;
+    hipLaunchKernelGGL(k_colsum_slices, dim3(kColsumSlices), dim3(256), 0, st, part, parts, L, stage);
+    hipLaunchKernelGGL(k_colsum_finish, dim3(1), dim3(256), 0, st, stage, L, c64, cvec);
 }
 
 }  // namespace raft
