@@ -167,10 +167,19 @@ Grid make_grid(int k_min, int k_max, int k_step) {
 // agrp splits alist into groups of about 256 padded centres (assignment),
 // ugrp into groups whose clusters fit the update kernel's LDS budget.
 struct Lists {
-    std::vector<int32_t> alist, agrp, ugrp;
+    std::vector<int32_t> alist, agrp, ugrp, uwi0, ulen, cranges;
+    int uwork = 0;
 };
 
-Lists make_lists(const Grid& G, const int32_t* active, int ucap) {
+// Length of the dynamic work lists (see pack_lists).
+constexpr int kDynLen(int Kc) { return 6 * Kc + 3; }
+
+// Point ranges per update group are capped so the partial buffers stay bounded.
+int update_ranges_max(int n, int num_cu) {
+    return std::max(1, std::min(num_cu, (n + 63) / 64));
+}
+
+Lists make_lists(const Grid& G, const int32_t* active, int ucap, int n, int num_cu) {
     Lists l;
     for (int k = 0; k < G.Kc; ++k)
         if (!active || active[k]) l.alist.push_back(k);
@@ -198,6 +207,24 @@ Lists make_lists(const Grid& G, const int32_t* active, int ucap) {
         ++cnt;
     }
     l.ugrp.push_back((int32_t)l.alist.size());
+    // work items: about 2 per CU in total, split over the groups in
+    // proportion to their candidate counts (the update's work per point)
+    const int ug = (int)l.ugrp.size() - 1;
+    const int total_c = std::max<int>(1, (int)l.alist.size());
+    const int max_r = update_ranges_max(n, num_cu);
+    l.cranges.assign(G.Kc, 1);
+    l.uwi0.push_back(0);
+    for (int gi = 0; gi < ug; ++gi) {
+        const int c = l.ugrp[gi + 1] - l.ugrp[gi];
+        int r = (int)((2LL * num_cu * c) / total_c);
+        r = std::max(1, std::min(r, max_r));
+        const int len = ((n + r - 1) / r + 63) / 64 * 64;
+        r = (n + len - 1) / len;
+        l.ulen.push_back(len);
+        l.uwi0.push_back(l.uwi0.back() + r);
+        for (int t = l.ugrp[gi]; t < l.ugrp[gi + 1]; ++t) l.cranges[l.alist[t]] = r;
+    }
+    l.uwork = l.uwi0.back();
     return l;
 }
 
@@ -252,6 +279,7 @@ struct Plan {
     Grid grid;
     Lists lists;
     int ucap = 0;
+    int ranges_max = 0;
     // projection / embedding
     float *y0, *y1, *pbuf, *yout, *zout, *wbuf;
     double *cpart, *c64;
@@ -281,7 +309,7 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
     P.score_grid_ = score_grid(n, ctx->num_cu);
     P.S = (P.grid.Kc + 7) / 8 * 8;
     P.ucap = update_cap(P.grid, P.d);
-    P.lists = make_lists(P.grid, nullptr, P.ucap);
+    P.lists = make_lists(P.grid, nullptr, P.ucap, n, ctx->num_cu);
     P.race_grid = kmeans_race_grid(n, ctx->num_cu);
     Arena a;
     a.base = base;
@@ -303,7 +331,7 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
     P.cvec = a.take<float>(P.Lmax);
     // k-means
     const Grid& G = P.grid;
-    const size_t meta_n = (size_t)3 * G.Kc + G.KP + (size_t)3 * G.Kc + 2;
+    const size_t meta_n = (size_t)3 * G.Kc + G.KP + (size_t)kDynLen(G.Kc);
     P.meta = a.take<int32_t>(meta_n);
     P.dyn = P.meta ? P.meta + 3 * G.Kc + G.KP : nullptr;
     KmeansPlan& km = P.km;
@@ -316,14 +344,8 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
     km.agroups = (int)P.lists.agrp.size() - 1;
     km.ugroups = (int)P.lists.ugrp.size() - 1;
     km.usk_max = P.ucap;
-    {
-        const int nsl = P.d > 64 ? P.d / 64 : 1;
-        const int want = (2 * ctx->num_cu + km.ugroups * nsl - 1) / (km.ugroups * nsl);
-        const int max_ranges = std::max(1, (n + 63) / 64);
-        const int ranges = std::max(1, std::min(want, max_ranges));
-        km.range_len = ((n + ranges - 1) / ranges + 63) / 64 * 64;
-        km.ranges = (n + km.range_len - 1) / km.range_len;
-    }
+    P.ranges_max = update_ranges_max(n, ctx->num_cu);
+    km.uwork = P.lists.uwork;
     km.race_grid = P.race_grid;
     km.ks = P.meta;
     km.koff16 = P.meta ? P.meta + G.Kc : nullptr;
@@ -332,6 +354,9 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
     km.alist = P.dyn;
     km.agrp = P.dyn ? P.dyn + G.Kc : nullptr;
     km.ugrp = P.dyn ? P.dyn + 2 * G.Kc + 1 : nullptr;
+    km.uwi0 = P.dyn ? P.dyn + 3 * G.Kc + 2 : nullptr;
+    km.ulen = P.dyn ? P.dyn + 4 * G.Kc + 3 : nullptr;
+    km.cranges = P.dyn ? P.dyn + 5 * G.Kc + 3 : nullptr;
     km.active = a.take<int32_t>(G.Kc);
     km.changes = a.take<int32_t>(G.Kc);
     P.iters_int = a.take<int32_t>(G.Kc);
@@ -339,8 +364,8 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
     km.active_count = a.take<int32_t>(1);
     km.C = a.take<float>((size_t)G.KP * P.d);
     km.cnorm = a.take<float>(G.KP);
-    km.psum = a.take<float>((size_t)km.ranges * G.KP * P.d);
-    km.pcnt = a.take<int32_t>((size_t)km.ranges * G.KP);
+    km.psum = a.take<float>((size_t)P.ranges_max * G.KP * P.d);
+    km.pcnt = a.take<int32_t>((size_t)P.ranges_max * G.KP);
     km.zmax_bits = a.take<uint32_t>(1);
     km.w = a.take<float>(n);
     km.race_val = a.take<double>(P.race_grid);
@@ -377,12 +402,16 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
     P.bytes = a.off;
 }
 
-// Packs the dynamic lists at fixed offsets: alist [Kc], agrp [Kc+1], ugrp [Kc+1].
+// Packs the dynamic lists at fixed offsets: alist [Kc], agrp [Kc+1],
+// ugrp [Kc+1], uwi0 [Kc+1], ulen [Kc], cranges [Kc].
 void pack_lists(const Lists& l, int Kc, int32_t* out) {
-    std::fill(out, out + 3 * Kc + 2, 0);
+    std::fill(out, out + kDynLen(Kc), 0);
     std::copy(l.alist.begin(), l.alist.end(), out);
     std::copy(l.agrp.begin(), l.agrp.end(), out + Kc);
     std::copy(l.ugrp.begin(), l.ugrp.end(), out + 2 * Kc + 1);
+    std::copy(l.uwi0.begin(), l.uwi0.end(), out + 3 * Kc + 2);
+    std::copy(l.ulen.begin(), l.ulen.end(), out + 4 * Kc + 3);
+    std::copy(l.cranges.begin(), l.cranges.end(), out + 5 * Kc + 3);
 }
 
 raft_status upload_meta(raft_ctx* ctx, const Plan& P, hipStream_t st) {
@@ -393,7 +422,7 @@ raft_status upload_meta(raft_ctx* ctx, const Plan& P, hipStream_t st) {
     meta.insert(meta.end(), G.koff.begin(), G.koff.end());
     meta.insert(meta.end(), G.cand_of.begin(), G.cand_of.end());
     const size_t at = meta.size();
-    meta.resize(at + 3 * (size_t)G.Kc + 2);
+    meta.resize(at + (size_t)kDynLen(G.Kc));
     pack_lists(P.lists, G.Kc, meta.data() + at);
     HIP_TRY(ctx, hipMemcpyAsync(P.meta, meta.data(), meta.size() * sizeof(int32_t),
                                 hipMemcpyHostToDevice, st));
@@ -533,12 +562,13 @@ raft_status do_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* 
             for (int k = 0; k < Kc; ++k) live += h_active[k] != 0;
             if (live == 0) break;
             // compact the work lists to the candidates still iterating
-            const Lists l = make_lists(P.grid, h_active, P.ucap);
+            const Lists l = make_lists(P.grid, h_active, P.ucap, g->n, ctx->num_cu);
             pack_lists(l, Kc, h_lists);
-            HIP_TRY(ctx, hipMemcpyAsync(P.dyn, h_lists, (3 * (size_t)Kc + 2) * sizeof(int32_t),
+            HIP_TRY(ctx, hipMemcpyAsync(P.dyn, h_lists, (size_t)kDynLen(Kc) * sizeof(int32_t),
                                         hipMemcpyHostToDevice, st));
             km.agroups = (int)l.agrp.size() - 1;
             km.ugroups = (int)l.ugrp.size() - 1;
+            km.uwork = l.uwork;
         }
     }
     RAFT_TRY(launch_check(ctx));

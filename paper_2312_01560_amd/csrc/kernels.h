@@ -66,8 +66,7 @@ struct KmeansPlan {
     int32_t agroups;     // candidate groups of the assignment kernel (over alist)
     int32_t ugroups;     // candidate groups of the update kernel (over alist)
     int32_t usk_max;     // bound on the accumulator rows of an update group (LDS sizing)
-    int32_t ranges;      // point ranges of the update kernel
-    int32_t range_len;
+    int32_t uwork;       // update work items (group, point range)
     int32_t race_grid;
     // device arrays
     const int32_t* ks;       // [Kc]
@@ -77,14 +76,17 @@ struct KmeansPlan {
     const int32_t* alist;    // [Kc] candidates still active at the last poll
     const int32_t* agrp;     // [agroups + 1] offsets into alist
     const int32_t* ugrp;     // [ugroups + 1] offsets into alist
+    const int32_t* uwi0;     // [ugroups + 1] first work item of each update group
+    const int32_t* ulen;     // [ugroups] point range length of each update group
+    const int32_t* cranges;  // [Kc] point ranges of each candidate's update group
     int32_t* active;         // [Kc]
     int32_t* changes;        // [Kc]
     int32_t* iters;          // [Kc]
     int32_t* active_count;   // [1]
     float* C;                // [KP x d]
     float* cnorm;            // [KP]
-    float* psum;             // [ranges x KP x d] per-range centre sums
-    int32_t* pcnt;           // [ranges x KP]
+    float* psum;             // [max ranges x KP x d] per-range centre sums
+    int32_t* pcnt;           // [max ranges x KP]
     uint32_t* zmax_bits;     // [1] largest |z| (float bits), sets the fixed-point scale
     float* w;                // [n]
     double* race_val;        // [race_grid]

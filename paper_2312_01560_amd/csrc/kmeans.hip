@@ -187,6 +187,24 @@ __global__ __launch_bounds__(256) void k_init_centres(KmeansPlan p, const float*
 
 // Assignment for all active candidates of one candidate group.
 // Grid: x = point tiles (4 waves x 16*PS points), y = candidate group.
+// The group's centre tiles are walked as one flat sequence (candidate by
+// candidate, 16 centres per tile); the operands of the next tile are loaded
+// while the MFMAs of the current one run.
+template <int KS>
+__device__ __forceinline__ void load_ctile(const KmeansPlan& p, int cb, int li, int g, float* a,
+                                           float4& cn) {
+    const float* cr = p.C + (size_t)(cb + li) * (KS * 4) + g * KS;
+#pragma unroll
+    for (int s = 0; s < KS; s += 4) {
+        const float4 v = *reinterpret_cast<const float4*>(cr + s);
+        a[s] = v.x;
+        a[s + 1] = v.y;
+        a[s + 2] = v.z;
+        a[s + 3] = v.w;
+    }
+    cn = *reinterpret_cast<const float4*>(p.cnorm + cb + 4 * g);
+}
+
 template <int D, int PS>
 __global__ __launch_bounds__(256) void k_assign(KmeansPlan p, const float* __restrict__ Z) {
     constexpr int KS = D / 4;
@@ -211,74 +229,90 @@ __global__ __launch_bounds__(256) void k_assign(KmeansPlan p, const float* __res
         }
     }
     const int t0 = p.agrp[blockIdx.y], t1 = p.agrp[blockIdx.y + 1];
-    for (int t = t0; t < t1; ++t) {
-        const int k = p.alist[t];
-        if (!p.active[k]) continue;
-        const int K = p.ks[k];
-        const int c0 = p.koff16[k];
-        const int ntiles = (K + 15) >> 4;
-        float bv[PS];
-        int bi[PS];
+    // first active candidate of the group
+    int t = t0;
+    while (t < t1 && !p.active[p.alist[t]]) ++t;
+    if (t >= t1) return;
+    int k = p.alist[t];
+    int ntiles = (p.ks[k] + 15) >> 4;
+    int tile = 0;
+    float an[KS];
+    float4 cnn;
+    load_ctile<KS>(p, p.koff16[k], li, g, an, cnn);
+    float bv[PS];
+    int bi[PS];
+#pragma unroll
+    for (int ps = 0; ps < PS; ++ps) {
+        bv[ps] = INFINITY;
+        bi[ps] = 0;
+    }
+    while (true) {
+        float a[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) a[s] = an[s];
+        const float cnv[4] = {cnn.x, cnn.y, cnn.z, cnn.w};
+        // coordinates of the next tile, and its prefetch
+        int nk = k, ntile = tile + 1, nt = t, nntiles = ntiles;
+        if (ntile >= ntiles) {
+            ntile = 0;
+            nt = t + 1;
+            while (nt < t1 && !p.active[p.alist[nt]]) ++nt;
+            if (nt < t1) {
+                nk = p.alist[nt];
+                nntiles = (p.ks[nk] + 15) >> 4;
+            }
+        }
+        if (nt < t1) load_ctile<KS>(p, p.koff16[nk] + ntile * 16, li, g, an, cnn);
 #pragma unroll
         for (int ps = 0; ps < PS; ++ps) {
-            bv[ps] = INFINITY;
-            bi[ps] = 0;
-        }
-        for (int tile = 0; tile < ntiles; ++tile) {
-            const int cb = c0 + tile * 16;
-            float a[KS];
-            const float* cr = p.C + (size_t)(cb + li) * D + g * KS;
+            floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int s = 0; s < KS; s += 4) {
-                const float4 v = *reinterpret_cast<const float4*>(cr + s);
-                a[s] = v.x;
-                a[s + 1] = v.y;
-                a[s + 2] = v.z;
-                a[s + 3] = v.w;
+            for (int s = 0; s < KS; ++s)
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[ps][s], acc, 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float sc = cnv[v] - 2.0f * acc[v];
+                if (sc < bv[ps]) {
+                    bv[ps] = sc;
+                    bi[ps] = tile * 16 + 4 * g + v;
+                }
             }
-            const float4 cn = *reinterpret_cast<const float4*>(p.cnorm + cb + 4 * g);
-            const float cnv[4] = {cn.x, cn.y, cn.z, cn.w};
+        }
+        if (tile == ntiles - 1) {
+            // candidate finished: fold the lane groups, write labels, count changes
+            int mine = 0;
 #pragma unroll
             for (int ps = 0; ps < PS; ++ps) {
-                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int s = 0; s < KS; ++s)
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[ps][s], acc, 0, 0, 0);
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const float sc = cnv[v] - 2.0f * acc[v];
-                    if (sc < bv[ps]) {
-                        bv[ps] = sc;
-                        bi[ps] = tile * 16 + 4 * g + v;
+                for (int off = 16; off < kWave; off <<= 1) {
+                    const float ov = __shfl_xor(bv[ps], off, kWave);
+                    const int oi = __shfl_xor(bi[ps], off, kWave);
+                    if (ov < bv[ps] || (ov == bv[ps] && oi < bi[ps])) {
+                        bv[ps] = ov;
+                        bi[ps] = oi;
                     }
                 }
+                if (ps == g) mine = bi[ps];
+                bv[ps] = INFINITY;
+                bi[ps] = 0;
             }
-        }
-        int mine = 0;
-#pragma unroll
-        for (int ps = 0; ps < PS; ++ps) {
-#pragma unroll
-            for (int off = 16; off < kWave; off <<= 1) {
-                const float ov = __shfl_xor(bv[ps], off, kWave);
-                const int oi = __shfl_xor(bi[ps], off, kWave);
-                if (ov < bv[ps] || (ov == bv[ps] && oi < bi[ps])) {
-                    bv[ps] = ov;
-                    bi[ps] = oi;
-                }
+            const int pt = pbase + 16 * g + li;
+            bool changed = false;
+            if (g < PS && pt < p.n) {
+                uint8_t* lp = p.lab_cm + (size_t)k * p.n + pt;
+                const uint8_t old = *lp;
+                const uint8_t nw = (uint8_t)mine;
+                changed = old != nw;
+                *lp = nw;
             }
-            if (ps == g) mine = bi[ps];
+            const uint64_t m = __ballot(changed);
+            if (lane == 0 && m) atomicAdd(&p.changes[k], (int)__popcll(m));
         }
-        const int pt = pbase + 16 * g + li;
-        bool changed = false;
-        if (g < PS && pt < p.n) {
-            uint8_t* lp = p.lab_cm + (size_t)k * p.n + pt;
-            const uint8_t old = *lp;
-            const uint8_t nw = (uint8_t)mine;
-            changed = old != nw;
-            *lp = nw;
-        }
-        const uint64_t m = __ballot(changed);
-        if (lane == 0 && m) atomicAdd(&p.changes[k], (int)__popcll(m));
+        if (nt >= t1) break;
+        k = nk;
+        tile = ntile;
+        t = nt;
+        ntiles = nntiles;
     }
 }
 
@@ -337,23 +371,31 @@ __device__ __forceinline__ int fixed_exp(const KmeansPlan& p) {
     return 30 - ez;
 }
 
-// Centre sums for one (point range, update group, 64-column slice).  Points
-// are quantised to int32 (z * 2^e) and summed in int64 LDS accumulators that
-// all waves of the work-group share: integer addition is associative, so the
-// sums do not depend on the order of the atomic adds (deterministic), and
-// integer LDS atomics are fast on this hardware where float ones are not.
-// A wave holds 64 points of its slice in registers (lane = column) and adds
-// each into the cluster row of every active candidate of the group; padding
-// points go to a dummy row so the inner loop has no branches.  Each range's
-// exact sums are written as FP32 partials, combined in FP64 in a fixed
-// order by k_update_finish.
+// Centre sums for one work item (update group, point range) and one slice of
+// up to 64 columns.  Points are quantised to int32 (z * 2^e) and summed in
+// int64 LDS accumulators shared by all waves of the work-group: integer
+// addition is associative, so the sums do not depend on the order of the
+// atomic adds (deterministic), and integer LDS atomics are fast on this
+// hardware where float ones are not.  A wave holds a chunk of 64 points of
+// its slice in registers (lane = column) and adds each point, one contiguous
+// accumulator row per instruction (no bank conflicts), into the cluster row
+// of every active candidate of the group; padding points go to a dummy row,
+// so the inner loop has no branches.  A group's points are split into as
+// many ranges as it has candidates times a constant, so work items carry
+// equal work.  Each range's exact sums are written as FP32 partials,
+// combined in FP64 in a fixed order by k_update_finish.
 constexpr int kUpdWaves = 4;
-constexpr int kUpdMaxCand = 32;
+constexpr int kUpdMaxCand = 16;
+constexpr int kUpdSlice = 64;
 
 __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __restrict__ Z) {
     extern __shared__ unsigned long long acc64[];
-    const int nsl = p.d > 64 ? p.d / 64 : 1;
-    const int g = blockIdx.y / nsl, sl = blockIdx.y % nsl;
+    // work item -> (group, range slot)
+    const int wi = blockIdx.x;
+    int g = 0;
+    while (g + 1 < p.ugroups && p.uwi0[g + 1] <= wi) ++g;
+    const int slot = wi - p.uwi0[g];
+    const int sl = blockIdx.y;
     const int t0 = p.ugrp[g], t1 = p.ugrp[g + 1];
     int rows = 0;
     bool any = false;
@@ -366,19 +408,42 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int total_rows = rows + 1;                          // + one dummy row
-    int* cnt = reinterpret_cast<int*>(acc64 + (size_t)total_rows * kWave);
-    for (int idx = threadIdx.x; idx < total_rows * kWave; idx += blockDim.x) acc64[idx] = 0ull;
+    int* cnt = reinterpret_cast<int*>(acc64 + (size_t)total_rows * kUpdSlice);
+    for (int idx = threadIdx.x; idx < total_rows * kUpdSlice; idx += blockDim.x) acc64[idx] = 0ull;
     for (int idx = threadIdx.x; idx < total_rows; idx += blockDim.x) cnt[idx] = 0;
     __syncthreads();
     const float sc = ldexpf(1.0f, fixed_exp(p));
     const int dummy = rows;
-    const int col = sl * 64 + lane;
+    const int col = sl * kUpdSlice + lane;
     const bool on = col < p.d;
-    const int r0 = blockIdx.x * p.range_len;
-    const int r1 = min(p.n, r0 + p.range_len);
+    const int len = p.ulen[g];
+    const int r0 = slot * len;
+    const int r1 = min(p.n, r0 + len);
     unsigned long long* acol = acc64 + lane;
+    // the group's candidates (uniform): label column, accumulator base row
+    const int nc = t1 - t0;
+    const uint8_t* labp[kUpdMaxCand];
+    int rbase[kUpdMaxCand];
+    bool act[kUpdMaxCand];
+    {
+        int base = 0;
+#pragma unroll
+        for (int m = 0; m < kUpdMaxCand; ++m) {
+            act[m] = false;
+            labp[m] = p.lab_cm;
+            rbase[m] = 0;
+            if (m < nc) {
+                const int k = p.alist[t0 + m];
+                act[m] = p.active[k] != 0;
+                labp[m] = p.lab_cm + (size_t)k * p.n;
+                rbase[m] = base;
+                base += p.ks[k];
+            }
+        }
+    }
     for (int cs = r0 + wid * kWave; cs < r1; cs += kUpdWaves * kWave) {
         const int np = min(kWave, r1 - cs);
+        // every load of the chunk is issued before any atomic
         int zf[kWave];
 #pragma unroll
         for (int q = 0; q < kWave; ++q) {
@@ -386,78 +451,89 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
             const float v = (on && q < np) ? Z[(size_t)pt * p.d + col] : 0.f;
             zf[q] = __float2int_rn(v * sc);
         }
-        int base = 0;
-        for (int t = t0; t < t1; ++t) {
-            const int k = p.alist[t];
-            const int K = p.ks[k];
-            if (p.active[k]) {
-                const int row = lane < np ? base + (int)p.lab_cm[(size_t)k * p.n + cs + lane] : dummy;
-                if (sl == 0) atomicAdd(&cnt[row], 1);
+        int row[kUpdMaxCand];
+#pragma unroll
+        for (int m = 0; m < kUpdMaxCand; ++m)
+            if (act[m]) row[m] = lane < np ? rbase[m] + (int)labp[m][cs + lane] : dummy;
+#pragma unroll
+        for (int m = 0; m < kUpdMaxCand; ++m) {
+            if (act[m]) {
+                if (sl == 0) atomicAdd(&cnt[row[m]], 1);
 #pragma unroll
                 for (int q = 0; q < kWave; ++q) {
-                    const int a = __builtin_amdgcn_readlane(row, q);
-                    atomicAdd(acol + (size_t)a * kWave, (unsigned long long)(long long)zf[q]);
+                    const int a = __builtin_amdgcn_readlane(row[m], q);
+                    atomicAdd(acol + (size_t)a * kUpdSlice, (unsigned long long)(long long)zf[q]);
                 }
             }
-            base += K;
         }
     }
     __syncthreads();
     const float inv = ldexpf(1.0f, -fixed_exp(p));
+    const int sw = min(kUpdSlice, p.d);
     int base = 0;
     for (int t = t0; t < t1; ++t) {
         const int k = p.alist[t];
         const int K = p.ks[k];
         if (p.active[k]) {
-            float* dst = p.psum + ((size_t)blockIdx.x * p.KP + p.koff16[k]) * p.d + sl * 64;
-            const int sw = min(64, p.d);
+            float* dst = p.psum + ((size_t)slot * p.KP + p.koff16[k]) * p.d + sl * kUpdSlice;
             for (int idx = threadIdx.x; idx < K * sw; idx += blockDim.x) {
-                const int r = idx / sw, c = idx - (idx / sw) * sw;
-                const long long v = (long long)acc64[(size_t)(base + r) * kWave + c];
-                dst[(size_t)r * p.d + c] = (float)((double)v * (double)inv);
+                const int r = idx / sw, cc = idx - (idx / sw) * sw;
+                const long long v = (long long)acc64[(size_t)(base + r) * kUpdSlice + cc];
+                dst[(size_t)r * p.d + cc] = (float)((double)v * (double)inv);
             }
             if (sl == 0)
                 for (int idx = threadIdx.x; idx < K; idx += blockDim.x)
-                    p.pcnt[(size_t)blockIdx.x * p.KP + p.koff16[k] + idx] = cnt[base + idx];
+                    p.pcnt[(size_t)slot * p.KP + p.koff16[k] + idx] = cnt[base + idx];
         }
         base += K;
     }
 }
 
-// Means from the range partials (FP64, ranges in order); an empty cluster
-// keeps its centre.  One wave per padded centre row.
+// Means from the range partials; an empty cluster keeps its centre.  One
+// work-group per padded centre row: 4 slices of the ranges x 64 columns,
+// each slice summed in FP64 in order, the slices combined in order.
 __global__ __launch_bounds__(256) void k_update_finish(KmeansPlan p) {
-    const int c = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int lane = threadIdx.x & (kWave - 1);
-    if (c >= p.KP) return;
+    const int c = blockIdx.x;
     const int k = p.cand_of[c];
     if (!p.active[k]) return;
     if (c - p.koff16[k] >= p.ks[k]) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int q = threadIdx.x / kWave;
+    const int nr = p.cranges[k];
+    const int per = (nr + 3) / 4;
+    const int ch0 = q * per, ch1 = min(nr, ch0 + per);
+    __shared__ double part[4][kWave];
+    __shared__ int pc[4];
     int count = 0;
-    for (int ch = 0; ch < p.ranges; ++ch) count += p.pcnt[(size_t)ch * p.KP + c];
-    if (count == 0) return;
+    for (int ch = ch0 + lane; ch < ch1; ch += kWave) count += p.pcnt[(size_t)ch * p.KP + c];
+    count = wave_sum(count);
+    if (lane == 0) pc[q] = count;
+    const size_t stride = (size_t)p.KP * p.d;
     float* crow = p.C + (size_t)c * p.d;
     float ss = 0.f;
-    const size_t stride = (size_t)p.KP * p.d;
-    for (int dd = lane; dd < p.d; dd += kWave) {
-        const float* src = p.psum + (size_t)c * p.d + dd;
+    for (int d0 = 0; d0 < p.d; d0 += kWave) {
+        const int dd = d0 + lane;
         double s = 0.0;
-        int ch = 0;
-        for (; ch + 4 <= p.ranges; ch += 4) {
-            const double a0 = src[ch * stride], a1 = src[(ch + 1) * stride];
-            const double a2 = src[(ch + 2) * stride], a3 = src[(ch + 3) * stride];
-            s += a0;
-            s += a1;
-            s += a2;
-            s += a3;
+        if (dd < p.d) {
+            const float* src = p.psum + (size_t)c * p.d + dd;
+            for (int ch = ch0; ch < ch1; ++ch) s += (double)src[ch * stride];
         }
-        for (; ch < p.ranges; ++ch) s += (double)src[ch * stride];
-        const float v = (float)(s / (double)count);
-        crow[dd] = v;
-        ss += v * v;
+        __syncthreads();
+        part[q][lane] = s;
+        __syncthreads();
+        const int total = pc[0] + pc[1] + pc[2] + pc[3];
+        if (total == 0) return;   // uniform across the work-group
+        if (q == 0 && dd < p.d) {
+            const double t = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+            const float v = (float)(t / (double)total);
+            crow[dd] = v;
+            ss += v * v;
+        }
     }
-    ss = wave_sum(ss);
-    if (lane == 0) p.cnorm[c] = ss;
+    if (q == 0) {
+        ss = wave_sum(ss);
+        if (lane == 0) p.cnorm[c] = ss;
+    }
 }
 
 __global__ void k_kmeans_reset(KmeansPlan p) {
@@ -485,7 +561,7 @@ int kmeans_race_grid(int32_t n, int num_cu) {
 
 size_t kmeans_update_lds(int sum_rows, int d) {
     (void)d;
-    return (size_t)(sum_rows + 1) * (kWave * sizeof(unsigned long long) + sizeof(int));
+    return (size_t)(sum_rows + 1) * (kUpdSlice * sizeof(unsigned long long) + sizeof(int));
 }
 
 int kmeans_update_rows(int K) { return K; }
@@ -551,8 +627,8 @@ void launch_iter_finalize(const KmeansPlan& p, int it, int t_max, hipStream_t st
 
 void launch_update(const KmeansPlan& p, const float* Z, size_t lds_max, hipStream_t st) {
     const size_t lds = kmeans_update_lds(p.usk_max, p.d);
-    const int nsl = p.d > 64 ? p.d / 64 : 1;
-    dim3 grid(p.ranges, p.ugroups * nsl);
+    const int nsl = (p.d + kUpdSlice - 1) / kUpdSlice;
+    dim3 grid(p.uwork, nsl);
     static bool attr_set = false;
     if (!attr_set) {
         (void)hipFuncSetAttribute((const void*)k_update, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -560,8 +636,7 @@ void launch_update(const KmeansPlan& p, const float* Z, size_t lds_max, hipStrea
         attr_set = true;
     }
     hipLaunchKernelGGL(k_update, grid, dim3(kUpdWaves * kWave), lds, st, p, Z);
-    const int fgrid = (p.KP * kWave + 255) / 256;
-    hipLaunchKernelGGL(k_update_finish, dim3(fgrid), dim3(256), 0, st, p);
+    hipLaunchKernelGGL(k_update_finish, dim3(p.KP), dim3(256), 0, st, p);
 }
 
 }  // namespace raft
