@@ -185,6 +185,48 @@ raft_status raft_score(raft_ctx* ctx, const raft_graph* g, const uint8_t* labels
 raft_status raft_run(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg,
                      void* ws, size_t ws_bytes, raft_outputs* out, void* stream);
 
+/* ---- training the GCN weights (optional; the method itself keeps them random) ----
+ * Relaxed modularity: with hard memberships H, tr(H^T B H)/2e is the
+ * modularity of Eq. 3 (matrix form Eq. 4); replacing H by row-softmax
+ * assignments S gives the loss -tr(S^T B S)/2e.  The model is the GCN of
+ * Eq. 6 with trainable W^(k): hidden layers tanh + row normalisation, the
+ * last layer linear (its output U are the logits of S).
+ * Widths dims[0..n_layers] each in {16, 32, 64, 128}, dims[k]*dims[k+1] <=
+ * 8192.  W[k] are device pointers to [dims[k] x dims[k+1]] row-major.
+ * Buffers are device memory owned by the caller; pointer arrays are host
+ * arrays of device pointers. */
+
+/* Workspace bytes for raft_gcn_forward/backward and raft_modloss_* with
+ * logits width K. */
+raft_status raft_train_workspace_size(raft_ctx* ctx, const raft_graph* g, int32_t n_layers,
+                                      const int32_t* dims, int32_t K, size_t* bytes);
+/* U_out [N x dims[n_layers]] = logits; H_saved[k] (k = 0..n_layers-2)
+ * receive the output of hidden layer k+1, i.e. the input of layer k+2, kept
+ * for the backward pass (pre-activations are recomputed there). */
+raft_status raft_gcn_forward(raft_ctx* ctx, const raft_graph* g, int32_t n_layers,
+                             const int32_t* dims, const float* H0, const float* const* W,
+                             float* const* H_saved, float* U_out, void* ws, size_t ws_bytes,
+                             void* stream);
+/* Adjoint of raft_gcn_forward: G_W[k] = dL/dW^(k) from G_U = dL/dU; G_H0
+ * (nullable) = dL/dH0.  Recomputes A_hat_n H and the pre-activations. */
+raft_status raft_gcn_backward(raft_ctx* ctx, const raft_graph* g, int32_t n_layers,
+                              const int32_t* dims, const float* H0, const float* const* W,
+                              const float* const* H_saved, const float* G_U, float* const* G_W,
+                              float* G_H0, void* ws, size_t ws_bytes, void* stream);
+/* S_out = softmax_rows(U) [N x K]; *loss (device double) = -tr(S^T B S)/2e. */
+raft_status raft_modloss_forward(raft_ctx* ctx, const raft_graph* g, const float* U, int32_t K,
+                                 float* S_out, double* loss, void* ws, size_t ws_bytes,
+                                 void* stream);
+/* G_U = scale * dloss/dU for S = softmax(U) (B S recomputed from S);
+ * scale: device float (nullable = 1). */
+raft_status raft_modloss_backward(raft_ctx* ctx, const raft_graph* g, const float* S, int32_t K,
+                                  const float* scale, float* G_U, void* ws, size_t ws_bytes,
+                                  void* stream);
+/* One Adam step (Kingma & Ba) on n parameters; step counts from 1. */
+raft_status raft_adam_step(raft_ctx* ctx, float* w, float* m, float* v, const float* grad,
+                           int64_t n, float lr, float beta1, float beta2, float eps, int32_t step,
+                           void* stream);
+
 /* ---- measurement ---------------------------------------------------------- */
 
 /* Kernel classes timed by raft_profile_enable (bit k of the mask = class k). */

@@ -22,6 +22,8 @@ EXPORTS = [
     "raft_graph_degrees", "raft_workspace_size", "raft_gaussian", "raft_spmm", "raft_project",
     "raft_gcn_layer", "raft_embed", "raft_partition", "raft_score", "raft_run",
     "raft_get_stage_times", "raft_profile_enable", "raft_profile_read",
+    "raft_train_workspace_size", "raft_gcn_forward", "raft_gcn_backward", "raft_modloss_forward",
+    "raft_modloss_backward", "raft_adam_step",
 ]
 
 PROF_SPMM, PROF_DENSE, PROF_RACE, PROF_ASSIGN, PROF_UPDATE, PROF_SCORE = range(6)
@@ -90,6 +92,16 @@ _SIGNATURES = {
     "raft_get_stage_times": (_I32, [_P, ctypes.POINTER(ctypes.c_double)]),
     "raft_profile_enable": (_I32, [_P, ctypes.c_uint32]),
     "raft_profile_read": (_I32, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
+    "raft_train_workspace_size": (_I32, [_P, _P, _I32, ctypes.POINTER(_I32), _I32,
+                                         ctypes.POINTER(_SZ)]),
+    "raft_gcn_forward": (_I32, [_P, _P, _I32, ctypes.POINTER(_I32), _P, ctypes.POINTER(_P),
+                                ctypes.POINTER(_P), _P, _P, _SZ, _P]),
+    "raft_gcn_backward": (_I32, [_P, _P, _I32, ctypes.POINTER(_I32), _P, ctypes.POINTER(_P),
+                                 ctypes.POINTER(_P), _P, ctypes.POINTER(_P), _P, _P, _SZ, _P]),
+    "raft_modloss_forward": (_I32, [_P, _P, _P, _I32, _P, _P, _P, _SZ, _P]),
+    "raft_modloss_backward": (_I32, [_P, _P, _P, _I32, _P, _P, _P, _SZ, _P]),
+    "raft_adam_step": (_I32, [_P, _P, _P, _P, _P, _I64, ctypes.c_float, ctypes.c_float,
+                              ctypes.c_float, ctypes.c_float, _I32, _P]),
 }
 
 _lib = None

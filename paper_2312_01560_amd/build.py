@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libraftgp.so")
-SOURCES = ["capi.hip", "graph.hip", "gauss.hip", "spmm.hip", "dense.hip", "kmeans.hip",
+SOURCES = ["capi.hip", "graph.hip", "gauss.hip", "spmm.hip", "dense.hip", "kmeans.hip", "train.hip",
            "score.hip"]
 ARCH = "gfx950"
 

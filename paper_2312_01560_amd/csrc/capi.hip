@@ -988,6 +988,183 @@ raft_status raft_run(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg,
     return RAFT_OK;
 }
 
+// ---- training -------------------------------------------------------------
+
+namespace {
+
+bool train_width_ok(int v) { return v == 16 || v == 32 || v == 64 || v == 128; }
+
+struct TrainWs {
+    float *P, *U, *Ga, *Gb, *WT, *wpart, *S2;
+    double* dpart;
+    size_t bytes = 0;
+};
+
+raft_status train_check(raft_ctx* ctx, const raft_graph* g, int32_t n_layers, const int32_t* dims) {
+    RAFT_TRY(check_graph(ctx, g));
+    if (n_layers < 1 || n_layers > RAFT_MAX_LAYERS || !dims)
+        return fail(ctx, RAFT_E_INVAL, "n_layers %d", n_layers);
+    for (int k = 0; k <= n_layers; ++k)
+        if (!train_width_ok(dims[k])) return fail(ctx, RAFT_E_UNSUPPORTED, "width %d", dims[k]);
+    for (int k = 0; k < n_layers; ++k)
+        if (!wgrad_supported(dims[k], dims[k + 1]) || !dense_supported(dims[k], dims[k + 1]) ||
+            !dense_supported(dims[k + 1], dims[k]))
+            return fail(ctx, RAFT_E_UNSUPPORTED, "layer %d: %d x %d", k + 1, dims[k], dims[k + 1]);
+    return RAFT_OK;
+}
+
+void train_layout(raft_ctx* ctx, const raft_graph* g, int n_layers, const int32_t* dims, int K,
+                  char* base, TrainWs& t) {
+    int lmax = K;
+    for (int k = 0; k <= n_layers; ++k) lmax = std::max(lmax, (int)dims[k]);
+    Arena a;
+    a.base = base;
+    const size_t nl = (size_t)g->n * lmax;
+    t.P = a.take<float>(nl);
+    t.U = a.take<float>(nl);
+    t.Ga = a.take<float>(nl);
+    t.Gb = a.take<float>(nl);
+    t.S2 = a.take<float>(nl);
+    t.WT = a.take<float>((size_t)lmax * lmax);
+    t.wpart = a.take<float>((size_t)wgrad_parts(g->n) * lmax * lmax);
+    // column-sum partials (+ stage) for the rank-1 term of B S, and loss partials
+    const size_t cs = ((size_t)spmm_grid(g->n, K, ctx->num_cu, nullptr) + kColsumStageRows) * K + 2 * (size_t)K;
+    t.dpart = a.take<double>(std::max<size_t>(cs, (size_t)rowdot_parts((int64_t)g->n * K)) + 64);
+    t.bytes = a.off;
+}
+
+// B S into out (column sums through the workspace's FP64 partials).
+void apply_b(raft_ctx* ctx, const raft_graph* g, const float* S, int K, float* out, double* dpart,
+             hipStream_t st) {
+    const GraphView gv = g->view();
+    const int grid = spmm_grid(g->n, K, ctx->num_cu, nullptr);
+    double* c64 = dpart + ((size_t)grid + kColsumStageRows) * K;
+    float* cvec = reinterpret_cast<float*>(c64 + K);
+    launch_colsum_partials(gv, K, S, dpart, ctx->num_cu, st);
+    launch_colsum_finish(dpart, grid, K, c64, cvec, st);
+    launch_spmm(gv, kOpModFull, K, S, out, cvec, nullptr, ctx->num_cu, st);
+}
+
+}  // namespace
+
+raft_status raft_train_workspace_size(raft_ctx* ctx, const raft_graph* g, int32_t n_layers,
+                                      const int32_t* dims, int32_t K, size_t* bytes) {
+    RAFT_TRY(train_check(ctx, g, n_layers, dims));
+    if (!bytes || !train_width_ok(K)) return fail(ctx, RAFT_E_INVAL, "bad K or bytes");
+    TrainWs t;
+    train_layout(ctx, g, n_layers, dims, K, nullptr, t);
+    *bytes = t.bytes;
+    return RAFT_OK;
+}
+
+raft_status raft_gcn_forward(raft_ctx* ctx, const raft_graph* g, int32_t n_layers,
+                             const int32_t* dims, const float* H0, const float* const* W,
+                             float* const* H_saved, float* U_out, void* ws, size_t ws_bytes,
+                             void* stream) {
+    RAFT_TRY(train_check(ctx, g, n_layers, dims));
+    if (!H0 || !W || !U_out || (n_layers > 1 && !H_saved))
+        return fail(ctx, RAFT_E_INVAL, "null buffer");
+    TrainWs t;
+    train_layout(ctx, g, n_layers, dims, dims[n_layers], nullptr, t);
+    RAFT_TRY(check_ws(ctx, ws, ws_bytes, t.bytes));
+    train_layout(ctx, g, n_layers, dims, dims[n_layers], reinterpret_cast<char*>(ws), t);
+    hipStream_t st = as_stream(stream);
+    const GraphView gv = g->view();
+    const float* h = H0;
+    for (int k = 0; k < n_layers; ++k) {
+        launch_spmm(gv, kOpGcn, dims[k], h, t.P, nullptr, nullptr, ctx->num_cu, st);
+        const bool last = k == n_layers - 1;
+        float* out = last ? U_out : H_saved[k];
+        if (!out || !W[k]) return fail(ctx, RAFT_E_INVAL, "null layer buffer");
+        launch_dense_layer(t.P, W[k], out, g->n, dims[k], dims[k + 1], last, ctx->d_status, st);
+        h = out;
+    }
+    return launch_check(ctx);
+}
+
+raft_status raft_gcn_backward(raft_ctx* ctx, const raft_graph* g, int32_t n_layers,
+                              const int32_t* dims, const float* H0, const float* const* W,
+                              const float* const* H_saved, const float* G_U, float* const* G_W,
+                              float* G_H0, void* ws, size_t ws_bytes, void* stream) {
+    RAFT_TRY(train_check(ctx, g, n_layers, dims));
+    if (!H0 || !W || !G_U || !G_W || (n_layers > 1 && !H_saved))
+        return fail(ctx, RAFT_E_INVAL, "null buffer");
+    TrainWs t;
+    train_layout(ctx, g, n_layers, dims, dims[n_layers], nullptr, t);
+    RAFT_TRY(check_ws(ctx, ws, ws_bytes, t.bytes));
+    train_layout(ctx, g, n_layers, dims, dims[n_layers], reinterpret_cast<char*>(ws), t);
+    hipStream_t st = as_stream(stream);
+    const GraphView gv = g->view();
+    const float* gcur = G_U;        // gradient w.r.t. this layer's output
+    float* gnext = t.Ga;
+    for (int k = n_layers - 1; k >= 0; --k) {
+        const int li = dims[k], lo = dims[k + 1];
+        const float* hin = k == 0 ? H0 : H_saved[k - 1];
+        launch_spmm(gv, kOpGcn, li, hin, t.P, nullptr, nullptr, ctx->num_cu, st);   // recompute P
+        const float* gu = gcur;
+        if (k != n_layers - 1) {
+            // recompute the pre-activation, then back through normalisation and tanh
+            launch_dense_layer(t.P, W[k], t.U, g->n, li, lo, true, ctx->d_status, st);
+            launch_tanh_norm_backward(t.U, const_cast<float*>(gcur), g->n, lo, st);
+        }
+        launch_wgrad(t.P, gu, g->n, li, lo, t.wpart, G_W[k], st);
+        if (k > 0 || G_H0) {
+            launch_transpose(W[k], li, lo, t.WT, st);
+            launch_dense_layer(gu, t.WT, t.Gb, g->n, lo, li, true, ctx->d_status, st);   // G_P
+            float* dst = (k == 0) ? G_H0 : gnext;
+            launch_spmm(gv, kOpGcn, li, t.Gb, dst, nullptr, nullptr, ctx->num_cu, st);   // A_hat_n G_P
+            gcur = dst;
+            gnext = (gnext == t.Ga) ? t.S2 : t.Ga;
+        }
+    }
+    return launch_check(ctx);
+}
+
+raft_status raft_modloss_forward(raft_ctx* ctx, const raft_graph* g, const float* U, int32_t K,
+                                 float* S_out, double* loss, void* ws, size_t ws_bytes,
+                                 void* stream) {
+    RAFT_TRY(check_graph(ctx, g));
+    if (!U || !S_out || !loss || !train_width_ok(K)) return fail(ctx, RAFT_E_INVAL, "bad arguments");
+    if (g->nnz == 0) return fail(ctx, RAFT_E_NOEDGES, "modularity needs e > 0");
+    const int32_t dims[2] = {K, K};
+    TrainWs t;
+    train_layout(ctx, g, 1, dims, K, nullptr, t);
+    RAFT_TRY(check_ws(ctx, ws, ws_bytes, t.bytes));
+    train_layout(ctx, g, 1, dims, K, reinterpret_cast<char*>(ws), t);
+    hipStream_t st = as_stream(stream);
+    launch_softmax_rows(U, S_out, g->n, K, st);
+    apply_b(ctx, g, S_out, K, t.U, t.dpart, st);
+    launch_modloss_value(S_out, t.U, (int64_t)g->n * K, (double)g->nnz, t.dpart, loss, st);
+    return launch_check(ctx);
+}
+
+raft_status raft_modloss_backward(raft_ctx* ctx, const raft_graph* g, const float* S, int32_t K,
+                                  const float* scale, float* G_U, void* ws, size_t ws_bytes,
+                                  void* stream) {
+    RAFT_TRY(check_graph(ctx, g));
+    if (!S || !G_U || !train_width_ok(K)) return fail(ctx, RAFT_E_INVAL, "bad arguments");
+    if (g->nnz == 0) return fail(ctx, RAFT_E_NOEDGES, "modularity needs e > 0");
+    const int32_t dims[2] = {K, K};
+    TrainWs t;
+    train_layout(ctx, g, 1, dims, K, nullptr, t);
+    RAFT_TRY(check_ws(ctx, ws, ws_bytes, t.bytes));
+    train_layout(ctx, g, 1, dims, K, reinterpret_cast<char*>(ws), t);
+    hipStream_t st = as_stream(stream);
+    apply_b(ctx, g, S, K, t.U, t.dpart, st);
+    launch_modloss_grad(S, t.U, g->n, K, 2.0 / (double)g->nnz, scale, G_U, st);
+    return launch_check(ctx);
+}
+
+raft_status raft_adam_step(raft_ctx* ctx, float* w, float* m, float* v, const float* grad,
+                           int64_t n, float lr, float beta1, float beta2, float eps, int32_t step,
+                           void* stream) {
+    if (!ctx) return RAFT_E_INVAL;
+    if (n < 0 || (n > 0 && (!w || !m || !v || !grad)) || step < 1)
+        return fail(ctx, RAFT_E_INVAL, "bad Adam arguments");
+    launch_adam(w, m, v, grad, n, lr, beta1, beta2, eps, step, as_stream(stream));
+    return launch_check(ctx);
+}
+
 raft_status raft_profile_enable(raft_ctx* ctx, uint32_t mask) {
     if (!ctx) return RAFT_E_INVAL;
     HIP_TRY(ctx, hipDeviceSynchronize());

@@ -146,4 +146,22 @@ void launch_select(const ScorePlan& p, const uint8_t* lab_pm, int32_t* labels_ou
 // Copy point-major labels [n x S] into a dense [n x Kc] output.
 void launch_copy_labels(const uint8_t* pm, int32_t n, int Kc, int S, uint8_t* out, hipStream_t st);
 
+// ---- train.hip -----------------------------------------------------------
+void launch_softmax_rows(const float* U, float* S, int n, int K, hipStream_t st);
+int rowdot_parts(int64_t total);
+// loss = -sum(S o BS) / m2 in FP64 (part: rowdot_parts(total) doubles)
+void launch_modloss_value(const float* S, const float* BS, int64_t total, double m2, double* part,
+                          double* loss, hipStream_t st);
+void launch_modloss_grad(const float* S, const float* BS, int n, int K, double inv_e,
+                         const float* scale, float* GU, hipStream_t st);
+void launch_tanh_norm_backward(const float* U, float* G, int n, int L, hipStream_t st);
+void launch_transpose(const float* W, int rows, int cols, float* WT, hipStream_t st);
+int wgrad_parts(int n);
+bool wgrad_supported(int li, int lo);
+// GW = P^T GU (part: wgrad_parts(n) * li * lo floats)
+void launch_wgrad(const float* P, const float* GU, int n, int li, int lo, float* part, float* GW,
+                  hipStream_t st);
+void launch_adam(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1,
+                 float b2, float eps, int step, hipStream_t st);
+
 }  // namespace raft

@@ -1,0 +1,133 @@
+"""Parity of the training path (relaxed modularity loss, hand-written GCN
+adjoint, Adam) with the FP64 oracle, whose gradients are pinned by finite
+differences in tests/test_oracle_modloss.py.  Tolerances: forward values
+1e-5 relative (FP32 vs FP64), gradients 1e-4 relative Frobenius (FP32
+accumulation over all rows)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import gcn as ogcn
+from oracle import modloss, projection, scores
+from synth import dcsbm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2312_01560_amd import api
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def graph():
+    return dcsbm(1500, 8, gamma=2.4, d_min=6, d_max=120, rho=2.5, seed=21)
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def to_np(t):
+    return t.detach().cpu().double().numpy()
+
+
+def _setup(ctx, g0, dims, seed=4):
+    from paper_2312_01560_amd import api
+    from paper_2312_01560_amd.train import Trainer
+    g = api.Graph(ctx, g0.row_ptr, g0.col_idx)
+    y = api.project(ctx, g, api.Config(op=0, proj_dim=dims[0], q=2, layer_dims=[dims[0]]))
+    ws = [api.gaussian(ctx, seed, 0x10 + k + 1, dims[k], dims[k + 1], dims[k] ** -0.5)
+          for k in range(len(dims) - 1)]
+    return g, y, ws, Trainer(ctx, g, dims)
+
+
+@pytest.mark.parametrize("dims", [[64, 64, 64, 64], [32, 64, 16], [128, 64]])
+def test_forward_backward_vs_oracle(ctx, graph, dims):
+    g, y, ws, tr = _setup(ctx, graph, dims)
+    U, saved = tr.forward(y, ws)
+    y64 = to_np(y)
+    w64 = [to_np(w) for w in ws]
+    u_ref, inputs = modloss.forward(graph.row_ptr, graph.col_idx, graph.n, y64, w64)
+    assert rel(to_np(U), u_ref) < 1e-5
+    for k, h in enumerate(saved):
+        assert rel(to_np(h), inputs[k + 1]) < 1e-5
+    S, loss = tr.modloss_forward(U)
+    s_ref = modloss.softmax_rows(to_np(U))
+    assert rel(to_np(S), s_ref) < 1e-5
+    l_ref = modloss.loss_of_s(graph.row_ptr, graph.col_idx, graph.n, to_np(S))
+    assert abs(float(loss.item()) - l_ref) <= 1e-5 * abs(l_ref) + 1e-9
+    GU = tr.modloss_backward(S)
+    gu_ref = modloss.softmax_backward(to_np(S), modloss.grad_s(graph.row_ptr, graph.col_idx,
+                                                                graph.n, to_np(S)))
+    assert rel(to_np(GU), gu_ref) < 1e-4
+    GW, GH0 = tr.backward(y, ws, saved, GU, want_h0=True)
+    gw_ref, gy_ref = modloss.backward(graph.row_ptr, graph.col_idx, graph.n, w64,
+                                      [y64] + [to_np(h) for h in saved], to_np(GU))
+    for k in range(len(ws)):
+        assert rel(to_np(GW[k]), gw_ref[k]) < 1e-4, k
+    assert rel(to_np(GH0), gy_ref) < 1e-4
+
+
+def test_autograd_end_to_end_matches_oracle(ctx, graph):
+    from paper_2312_01560_amd.train import RaftGCN, RaftModLoss
+    dims = [64, 64, 64, 64]
+    g, y, ws, tr = _setup(ctx, graph, dims, seed=9)
+    params = [w.clone().requires_grad_(True) for w in ws]
+    U = RaftGCN.apply(tr, y, *params)
+    loss = RaftModLoss.apply(tr, U)
+    (2.0 * loss).backward()
+    l_ref, g_ref, _, _ = modloss.loss_and_grads(graph.row_ptr, graph.col_idx, graph.n, to_np(y),
+                                                [to_np(w) for w in ws])
+    assert abs(loss.item() - l_ref) <= 1e-5 * abs(l_ref)
+    for k, p in enumerate(params):
+        assert rel(to_np(p.grad), 2.0 * g_ref[k]) < 1e-4
+
+
+def test_adam_matches_oracle(ctx, graph):
+    from paper_2312_01560_amd.train import Trainer
+    from paper_2312_01560_amd import api
+    g = api.Graph(ctx, graph.row_ptr, graph.col_idx)
+    tr = Trainer(ctx, g, [16, 16])
+    rng = np.random.default_rng(0)
+    w = rng.standard_normal(1000)
+    m = np.zeros(1000)
+    v = np.zeros(1000)
+    wt = torch.tensor(w, dtype=torch.float32, device="cuda")
+    mt = torch.zeros_like(wt)
+    vt = torch.zeros_like(wt)
+    for step in range(1, 6):
+        grad = rng.standard_normal(1000)
+        tr.adam(wt, mt, vt, torch.tensor(grad, dtype=torch.float32, device="cuda"), step)
+        w, m, v = modloss.adam_step(w, m, v, grad.astype(np.float32).astype(np.float64), step)
+    assert rel(to_np(wt), w) < 1e-6
+
+
+def test_training_lowers_loss_and_partitions(ctx, graph):
+    """20 Adam steps lower the loss; the hard partition of the trained model
+    scores its modularity exactly as the oracle does (Eq. 3)."""
+    from paper_2312_01560_amd import api
+    dims = [64, 64, 64]
+    g, y, ws, tr = _setup(ctx, graph, dims, seed=5)
+    params = [w.clone() for w in ws]
+    ms = [torch.zeros_like(w) for w in ws]
+    vs = [torch.zeros_like(w) for w in ws]
+    losses = []
+    for step in range(1, 21):
+        U, saved = tr.forward(y, params)
+        S, loss = tr.modloss_forward(U)
+        losses.append(loss.item())
+        GW, _ = tr.backward(y, params, saved, tr.modloss_backward(S))
+        for k in range(len(params)):
+            tr.adam(params[k], ms[k], vs[k], GW[k], step)
+    assert losses[-1] < losses[0]
+    lab = torch.argmax(S, dim=1).to(torch.uint8)[:, None].contiguous()
+    k = int(lab.max().item()) + 1
+    mod, _ = api.score(ctx, g, lab, [max(k, 1)])
+    ref = scores.modularity(graph.row_ptr, graph.col_idx, lab[:, 0].cpu().numpy().astype(np.int64), max(k, 1))
+    assert to_np(mod)[0] == ref
