@@ -1,7 +1,7 @@
 """End-to-end oracle of the hot path: projection -> GCN -> k-means grid ->
 scores -> selection (Sec. III: random feature extraction, random embedding
-derivation, model selection; the flat candidate grid replaces Alg. 1 here,
-Alg. 1 itself is in ``hierarchical``)."""
+derivation, model selection).  Model selection scans a flat grid of
+candidate K; the hierarchical search of Alg. 1 is not part of this path."""
 from dataclasses import dataclass, field
 
 import numpy as np
