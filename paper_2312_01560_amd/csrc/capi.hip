@@ -15,6 +15,11 @@
 
 using namespace raft;
 
+// Pinned host scratch of a context: status words, and the active flags and
+// work lists of the k-means convergence polls (16 + 9 Kc + 4 ints for Kc
+// candidates in total).  Allocated once per context.
+constexpr size_t kPinnedInts = 64 * 1024;
+
 struct raft_ctx {
     int device = 0;
     int num_cu = 256;
@@ -692,17 +697,6 @@ raft_status do_embed(raft_ctx* ctx, const raft_graph* g, const raft_config* c, P
     return launch_check(ctx);
 }
 
-raft_status ensure_pinned(raft_ctx* ctx, size_t ints) {
-    if (ints <= ctx->pinned_ints) return RAFT_OK;
-    HIP_TRY(ctx, hipDeviceSynchronize());
-    if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
-    ctx->h_pinned = nullptr;
-    ctx->pinned_ints = 0;
-    HIP_TRY(ctx, hipHostMalloc((void**)&ctx->h_pinned, ints * sizeof(int32_t), hipHostMallocDefault));
-    ctx->pinned_ints = ints;
-    return RAFT_OK;
-}
-
 raft_status do_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* c, Plan& P,
                          const float* Z, raft_outputs* out, hipStream_t st, bool timed) {
     KmeansPlan km = P.km;
@@ -715,7 +709,15 @@ raft_status do_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* 
     const int t_max = c->kmeans_max_iter;
     const int check = c->check_every > 0 ? c->check_every : 4;
     const int Kt = P.tgrid.Kc;
-    RAFT_TRY(ensure_pinned(ctx, 16 + (size_t)Kt + (size_t)kDynLen(Kt)));
+    // host copies of the active flags and the work lists: the context's
+    // pinned scratch when they fit (it is never freed before the context),
+    // else pageable memory with a wait after each upload
+    const size_t host_ints = (size_t)Kt + (size_t)kDynLen(Kt);
+    std::vector<int32_t> pageable;
+    const bool pinned = 16 + host_ints <= ctx->pinned_ints;
+    if (!pinned) pageable.resize(host_ints);
+    int32_t* h_active = pinned ? ctx->h_pinned + 16 : pageable.data();
+    int32_t* h_lists = h_active + Kt;
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[2], st));
     launch_kmeans_reset(km, st);
     launch_zmax(km, Z, ctx->num_cu, st);
@@ -731,8 +733,6 @@ raft_status do_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* 
     launch_init_centres(km, Z, st);
     RAFT_TRY(launch_check(ctx));
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[3], st));
-    int32_t* h_active = ctx->h_pinned + 16;
-    int32_t* h_lists = ctx->h_pinned + 16 + Kt;
     for (int it = 1; it <= t_max; ++it) {
         {
             ProfScope ps(ctx, RAFT_PROF_ASSIGN, st);
@@ -757,6 +757,7 @@ raft_status do_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* 
             pack_lists(l, Kt, h_lists);
             HIP_TRY(ctx, hipMemcpyAsync(P.dyn, h_lists, (size_t)kDynLen(Kt) * sizeof(int32_t),
                                         hipMemcpyHostToDevice, st));
+            if (!pinned) HIP_TRY(ctx, hipStreamSynchronize(st));
             km.agroups = (int)l.agrp.size() - 1;
             km.ugroups = (int)l.ugrp.size() - 1;
             km.awork = l.awork;
@@ -864,7 +865,8 @@ raft_status raft_ctx_create(int device, raft_ctx** out) {
              lds > 0)
         c->lds_max = (size_t)lds;
     if (hipMalloc(&c->d_status, 256) != hipSuccess ||
-        hipHostMalloc((void**)&c->h_pinned, 4096 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void**)&c->h_pinned, kPinnedInts * sizeof(int32_t), hipHostMallocDefault) !=
+            hipSuccess) {
         delete c;
         return RAFT_E_NOMEM;
     }
@@ -872,7 +874,7 @@ raft_status raft_ctx_create(int device, raft_ctx** out) {
         delete c;
         return RAFT_E_DEVICE;
     }
-    c->pinned_ints = 4096;
+    c->pinned_ints = kPinnedInts;
     for (auto& e : c->ev) (void)hipEventCreate(&e);
     *out = c;
     return RAFT_OK;

@@ -34,6 +34,14 @@ def make_workload(name, seed=0):
     return dcsbm(seed=seed, **w["graph"]), dict(w["method"])
 
 
+BATCH_METHOD = dict(proj_dim=64, q=3, layer_dims=[64, 64], k_min=2, k_max=64, k_step=1)
+
+
+def make_batch(count=64, seed=0):
+    """The batched workload: graphs of ``batch_specs`` and its method settings."""
+    return [dcsbm(**s) for s in batch_specs(count, seed)], dict(BATCH_METHOD)
+
+
 def batch_specs(count=64, seed=0, n_lo=1000, n_hi=50000):
     """Per-graph DC-SBM recipes of the batched workload."""
     rng = np.random.default_rng(np.random.SeedSequence([0xB4, int(seed)]))
