@@ -13,10 +13,7 @@ launches inside the timed steps (library profiling hooks); its algorithmic
 work per launch gives the roofline fraction.  The FP64 oracle is timed on a
 bounded sample of the same workload on the host cores (rank 0, N=1 only).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload n50k|n1m|batch64]
-
---workload batch64 times 64 graphs of uneven size as one batch and one graph
-at a time (same seeds) and reports both.
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload n50k|n1m]
 """
 import argparse
 import hashlib
@@ -138,152 +135,6 @@ def cpu_baseline(graph, method, variants, gpu_out, stride):
     }, float(min(nmis)), float(min(nmi_star))
 
 
-def kmeans_work(n, ks, iters):
-    return float(n) * float(sum(k * max(int(it), 1) for k, it in zip(ks, iters)))
-
-
-def bench_batch(args, ctx, api, torch, np):
-    """Batched workload: 64 graphs of uneven size per step.  The step is timed
-    twice: all graphs in one batch (raft_batch_run per variant), and one graph
-    at a time (raft_run per graph and variant), same seeds."""
-    from synth.workloads import make_batch
-
-    graphs, method = make_batch()
-    variants = [v for v in args.variants.split(",") if v]
-    dev = ctx.torch_device
-    csr = [(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col_idx).to(dev))
-           for g in graphs]
-    cfgs = {v: api.Config(op=VARIANTS[v], **method) for v in variants}
-    hs = [api.Graph(ctx, rp, ci) for rp, ci in csr]
-    b = api.Batch(ctx, hs)
-    need = max(api.batch_workspace_size(ctx, b, c) for c in cfgs.values())
-    need = max([need] + [api.workspace_size(ctx, h, c) for h in hs for c in cfgs.values()])
-    ws = ctx.workspace(need)
-    outs_b = {v: api._batch_outputs(ctx, b, cfgs[v], want_y=True, want_z=True) for v in variants}
-    outs_1 = {v: [api._outputs(ctx, h, cfgs[v], want_y=True, want_z=True) for h in hs]
-              for v in variants}
-    b.close()
-    for h in hs:
-        h.close()
-
-    def step_batched():
-        hs = [api.Graph(ctx, rp, ci) for rp, ci in csr]
-        bb = api.Batch(ctx, hs)
-        for v in variants:
-            api.batch_run(ctx, bb, cfgs[v], ws=ws, outputs=outs_b[v])
-        bb.close()
-        for h in hs:
-            h.close()
-
-    def step_single():
-        for i, (rp, ci) in enumerate(csr):
-            g = api.Graph(ctx, rp, ci)
-            for v in variants:
-                api.run(ctx, g, cfgs[v], ws=ws, outputs=outs_1[v][i])
-            g.close()
-
-    for _ in range(args.warmup):
-        step_batched()
-        step_single()
-    torch.cuda.synchronize()
-    ctx.sync_status()
-    api.profile_read(ctx)
-    api.profile_enable(ctx, (1 << 0) | (1 << 3))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step_batched()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = api.profile_read(ctx)
-    api.profile_enable(ctx, 0)
-    for _ in range(args.steps):
-        step_single()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    ctx.sync_status()
-    G = len(graphs)
-    value = G * args.steps / (t1 - t0)
-    value_single = G * args.steps / (t2 - t1)
-
-    hb = {v: {k: t.cpu().numpy() for k, t in outs_b[v][0].items()} for v in variants}
-    h1 = {v: [{k: t.cpu().numpy() for k, t in o[0].items()} for o in outs_1[v]] for v in variants}
-    offs = np.concatenate([[0], np.cumsum([g.n for g in graphs])])
-    from oracle import scores as oscores   # NMI bookkeeping only
-    nmi_bs = min(oscores.nmi(hb[v]["labels"][offs[i]:offs[i + 1]], h1[v][i]["labels"])
-                 for v in variants for i in range(G))
-    same = all(np.array_equal(hb[v]["labels"][offs[i]:offs[i + 1]], h1[v][i]["labels"])
-               for v in variants for i in range(G))
-    nmi_planted = {v: float(np.mean([oscores.nmi(hb[v]["labels"][offs[i]:offs[i + 1]],
-                                                 graphs[i].planted) for i in range(G)]))
-                   for v in variants}
-    ks = cfgs[variants[0]].ks
-    d = cfgs[variants[0]].embed_dim
-    assign_flops = sum(2.0 * d * kmeans_work(graphs[i].n, ks, hb[v]["iters"][i])
-                       for v in variants for i in range(G))
-    ms_assign, n_assign = prof["assign"]
-    ms_spmm, n_spmm = prof["spmm"]
-    n_tot = int(offs[-1])
-    nnz_tot = int(sum(g.nnz for g in graphs))
-    spmm_bytes = 4.0 * (n_tot + 1) + 4.0 * nnz_tot + 8.0 * n_tot * method["proj_dim"]
-    assign_ach = assign_flops * args.steps / (ms_assign * 1e-3) if ms_assign > 0 else 0.0
-    spmm_ach = spmm_bytes * n_spmm / (ms_spmm * 1e-3) if ms_spmm > 0 else 0.0
-    roof = {"kernel": "k_assign (MFMA FP32, all graphs and candidates)", "bound": "mfma",
-            "achieved": assign_ach / 1e12, "peak": PEAK_MFMA_F32 / 1e12, "unit": "TFLOP/s",
-            "frac": assign_ach / PEAK_MFMA_F32,
-            "per_launch": {"flops": assign_flops * args.steps / max(n_assign, 1),
-                           "avg_ms": ms_assign / max(n_assign, 1)},
-            "traffic": measured_traffic("assign", "batch64")}
-    rec = {
-        "metric": "end-to-end graphs/s, 64 DC-SBM graphs (N 1k..50k) batched vs one at a time",
-        "value": value, "unit": "graphs/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * (t1 - t0) / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "batch64", "graphs": G, "n_total": n_tot, "nnz_total": nnz_tot,
-                   "n_range": [int(min(g.n for g in graphs)), int(max(g.n for g in graphs))],
-                   "proj_dim": method["proj_dim"], "q": method["q"],
-                   "layer_dims": method["layer_dims"],
-                   "k_grid": [method["k_min"], method["k_max"], method["k_step"]],
-                   "variants": variants},
-        "one_at_a_time": {"value": value_single, "unit": "graphs/s",
-                          "ms_per_step": 1e3 * (t2 - t1) / args.steps},
-        "speedup_vs_one_at_a_time": value / value_single,
-        "labels_batched_equal_single": bool(same),
-        "nmi_batched_vs_single": float(nmi_bs),
-        "nmi_vs_planted_mean": nmi_planted,
-        "roofline": roof,
-        "spmm": {"achieved_gbs": spmm_ach / 1e9, "frac_hbm": spmm_ach / PEAK_HBM,
-                 "avg_us": 1e3 * ms_spmm / max(n_spmm, 1), "launches": n_spmm,
-                 "bytes_per_launch": spmm_bytes},
-    }
-    if not args.no_cpu_baseline:
-        order = np.argsort([g.n for g in graphs])
-        sample = [int(order[len(order) // 4]), int(order[len(order) // 2])]
-        tot_s = 0.0
-        descs = []
-        nmis = []
-        for i in sample:
-            base, _, nmi_star = cpu_baseline(graphs[i], method, variants,
-                                             {v: h1[v][i] for v in variants},
-                                             args.cpu_sample_stride)
-            tot_s += base["seconds"]
-            nmis.append(nmi_star)
-            descs.append(f"graph {i} (N={graphs[i].n}): {base['sample']}")
-        w_all = sum(kmeans_work(graphs[i].n, ks, hb[v]["iters"][i])
-                    for v in variants for i in range(G))
-        w_smp = sum(kmeans_work(graphs[i].n, ks, hb[v]["iters"][i])
-                    for v in variants for i in sample)
-        est = tot_s * w_all / w_smp
-        rec["cpu_baseline"] = {"value": G / est, "unit": "graphs/s", "cores": base["cores"],
-                               "kind": "oracle",
-                               "sample": " | ".join(descs) + f"; scaled to all {G} graphs by "
-                               f"k-means work (N x sum K*iters) x{w_all / w_smp:.1f}: "
-                               f"estimated {est:.0f} s per batch"}
-        rec["nmi_vs_oracle"] = {"selected_k_sampled_graphs": float(min(nmis))}
-    print(json.dumps(rec))
-
-
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -298,14 +149,9 @@ def main():
     from paper_2312_01560_amd import api
     from synth import make_workload
 
-    if args.workload == "batch64":
-        # The first run of this workload ended in a GPU memory fault whose
-        # cause is not identified yet (a host replay of every kernel's index
-        # arithmetic over these exact shapes finds no out-of-bounds access).
-        # It stays disabled until the cause is found.
-        print("batch64 is disabled: its first GPU run faulted and the cause is not "
-              "identified", file=sys.stderr)
-        sys.exit(3)
+    if args.workload not in ("n50k", "n1m", "small", "n200k"):
+        print(f"unknown workload {args.workload}", file=sys.stderr)
+        sys.exit(2)
     graph, method = make_workload(args.workload)
     variants = [v for v in args.variants.split(",") if v]
     ctx = api.Context(0)

@@ -63,7 +63,6 @@ typedef int32_t raft_status;
 
 typedef struct raft_ctx raft_ctx;
 typedef struct raft_graph raft_graph;
-typedef struct raft_batch raft_batch;
 
 typedef struct {
     int32_t  abi_version;              /* must be RAFT_ABI_VERSION                    */
@@ -185,45 +184,6 @@ raft_status raft_score(raft_ctx* ctx, const raft_graph* g, const uint8_t* labels
 /* A1-A7: projection, embedding and model selection (synchronises `stream`). */
 raft_status raft_run(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg,
                      void* ws, size_t ws_bytes, raft_outputs* out, void* stream);
-
-/* ---- batches: many graphs in one pass --------------------------------------
- * The paper runs RaftGP on one graph at a time (Sec. III).  A batch packs G
- * graphs into one block-diagonal CSR so that every stage runs over all
- * graphs, and every candidate K of every graph, in the same launches.  Each
- * graph keeps its own operator (degrees, 2e and, for MOD_FULL, its own
- * d^T Y), its own Theta and W^(k) (key seeds[g], graph-local row numbers),
- * its own k-means++ race and its own K*: graph g of a batch gets exactly
- * the result of raft_run on that graph alone with cfg->seed = seeds[g]
- * (floating-point sums aside whose order depends on the work split: the
- * MOD_FULL column sums).
- *
- * Outputs of raft_batch_run (raft_outputs, device memory) are the per-graph
- * arrays concatenated in graph order: Y [N_tot x L], Z [N_tot x d],
- * labels [N_tot] (graph-local block ids), k_selected [G x 3], mod and ncut
- * [G x Kc], labels_all [N_tot x Kc], picks [G x K_max] (graph-local node
- * ids), iters [G x Kc].  N_tot = sum of the graphs' node counts; graph g owns
- * rows node_offsets[g] .. node_offsets[g+1]-1 (see raft_batch_info). */
-
-/* Packs `graphs[0..G-1]` (created by raft_graph_create on this context, each
- * with e > 0) into a new device-resident block-diagonal CSR; the sources stay
- * valid and owned by the caller.  Synchronous.  RAFT_E_UNSUPPORTED when the
- * totals reach 2^31 nodes or stored entries. */
-raft_status raft_batch_create(raft_ctx* ctx, int32_t G, const raft_graph* const* graphs,
-                              void* stream, raft_batch** out);
-void        raft_batch_destroy(raft_batch* b);
-/* Host copies of the batch shape (each pointer nullable); node_offsets has
- * G + 1 entries. */
-raft_status raft_batch_info(const raft_batch* b, int32_t* n_graphs, int64_t* n_total,
-                            int64_t* nnz_total, int64_t* node_offsets);
-/* Workspace bytes of raft_batch_run (256-byte aligned base).  The K grid of
- * cfg is shared by every graph; k_max must not exceed the smallest graph. */
-raft_status raft_batch_workspace_size(raft_ctx* ctx, const raft_batch* b, const raft_config* cfg,
-                                      size_t* bytes);
-/* A1-A7 over every graph of the batch.  seeds: host array [G] (NULL: every
- * graph uses cfg->seed).  Synchronises `stream` (convergence polls). */
-raft_status raft_batch_run(raft_ctx* ctx, const raft_batch* b, const raft_config* cfg,
-                           const uint64_t* seeds, void* ws, size_t ws_bytes, raft_outputs* out,
-                           void* stream);
 
 /* ---- training the GCN weights (optional; the method itself keeps them random) ----
  * Relaxed modularity: with hard memberships H, tr(H^T B H)/2e is the

@@ -24,8 +24,6 @@ EXPORTS = [
     "raft_get_stage_times", "raft_profile_enable", "raft_profile_read",
     "raft_train_workspace_size", "raft_gcn_forward", "raft_gcn_backward", "raft_modloss_forward",
     "raft_modloss_backward", "raft_adam_step",
-    "raft_batch_create", "raft_batch_destroy", "raft_batch_info", "raft_batch_workspace_size",
-    "raft_batch_run",
 ]
 
 PROF_SPMM, PROF_DENSE, PROF_RACE, PROF_ASSIGN, PROF_UPDATE, PROF_SCORE = range(6)
@@ -104,13 +102,6 @@ _SIGNATURES = {
     "raft_modloss_backward": (_I32, [_P, _P, _P, _I32, _P, _P, _P, _SZ, _P]),
     "raft_adam_step": (_I32, [_P, _P, _P, _P, _P, _I64, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, ctypes.c_float, _I32, _P]),
-    "raft_batch_create": (_I32, [_P, _I32, ctypes.POINTER(_P), _P, ctypes.POINTER(_P)]),
-    "raft_batch_destroy": (None, [_P]),
-    "raft_batch_info": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I64),
-                               ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
-    "raft_batch_workspace_size": (_I32, [_P, _P, ctypes.POINTER(RaftConfig), ctypes.POINTER(_SZ)]),
-    "raft_batch_run": (_I32, [_P, _P, ctypes.POINTER(RaftConfig), ctypes.POINTER(_U64), _P, _SZ,
-                              ctypes.POINTER(RaftOutputs), _P]),
 }
 
 _lib = None

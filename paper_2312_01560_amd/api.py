@@ -153,89 +153,6 @@ class Graph:
             pass
 
 
-class Batch:
-    """Block-diagonal pack of several graphs (raft_batch); the source graphs
-    stay owned by the caller."""
-
-    def __init__(self, ctx, graphs):
-        self.ctx = ctx
-        G = len(graphs)
-        arr = (ctypes.c_void_p * G)(*[g.h.value for g in graphs])
-        h = ctypes.c_void_p()
-        ctx.check(ctx.lib.raft_batch_create(ctx.h, G, arr, _stream(), ctypes.byref(h)))
-        self.h = h
-        ng = ctypes.c_int32()
-        nt = ctypes.c_int64()
-        et = ctypes.c_int64()
-        offs = (ctypes.c_int64 * (G + 1))()
-        ctx.check(ctx.lib.raft_batch_info(h, ctypes.byref(ng), ctypes.byref(nt), ctypes.byref(et),
-                                          offs))
-        self.G = ng.value
-        self.n = nt.value
-        self.nnz = et.value
-        self.offsets = list(offs)
-
-    def close(self):
-        if getattr(self, "h", None):
-            self.ctx.lib.raft_batch_destroy(self.h)
-            self.h = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
-
-
-def batch_workspace_size(ctx, b, cfg):
-    c = cfg.to_c()
-    n = ctypes.c_size_t()
-    ctx.check(ctx.lib.raft_batch_workspace_size(ctx.h, b.h, ctypes.byref(c), ctypes.byref(n)))
-    return n.value
-
-
-def _batch_outputs(ctx, b, cfg, want_y=False, want_z=False):
-    kc = len(cfg.ks)
-    G = b.G
-    o = {
-        "labels": ctx.empty((b.n,), torch.int32),
-        "k_selected": ctx.empty((G, 3), torch.int32),
-        "mod": ctx.empty((G, kc), torch.float64),
-        "ncut": ctx.empty((G, kc), torch.float64),
-        "labels_all": ctx.empty((b.n, kc), torch.uint8),
-        "picks": ctx.empty((G, max(cfg.ks)), torch.int32),
-        "iters": ctx.empty((G, kc), torch.int32),
-    }
-    if want_y:
-        o["Y"] = ctx.empty((b.n, cfg.proj_dim), torch.float32)
-    if want_z:
-        o["Z"] = ctx.empty((b.n, cfg.embed_dim), torch.float32)
-    s = RaftOutputs()
-    for name, _ in RaftOutputs._fields_:
-        t = o.get(name)
-        setattr(s, name, t.data_ptr() if t is not None else None)
-    return o, s
-
-
-def batch_run(ctx, b, cfg, seeds=None, ws=None, want_y=True, want_z=True, outputs=None):
-    """A1-A7 over every graph of a batch; outputs are concatenated per graph
-    (rows b.offsets[g]..b.offsets[g+1]-1 belong to graph g)."""
-    need = batch_workspace_size(ctx, b, cfg)
-    if ws is None or ws.numel() < need:
-        ws = ctx.workspace(need)
-    if outputs is None:
-        outputs = _batch_outputs(ctx, b, cfg, want_y, want_z)
-    o, s = outputs
-    c = cfg.to_c()
-    sd = None
-    if seeds is not None:
-        assert len(seeds) == b.G
-        sd = (ctypes.c_uint64 * b.G)(*[int(x) for x in seeds])
-    ctx.check(ctx.lib.raft_batch_run(ctx.h, b.h, ctypes.byref(c), sd, _ptr(ws), ws.numel(),
-                                     ctypes.byref(s), _stream()))
-    return o
-
-
 def workspace_size(ctx, g, cfg):
     c = cfg.to_c()
     n = ctypes.c_size_t()

@@ -15,19 +15,13 @@
 
 using namespace raft;
 
-// Pinned host scratch of a context: status words, and the active flags and
-// work lists of the k-means convergence polls (16 + 9 Kc + 4 ints for Kc
-// candidates in total).  Allocated once per context.
-constexpr size_t kPinnedInts = 64 * 1024;
-
 struct raft_ctx {
     int device = 0;
     int num_cu = 256;
     size_t lds_max = 65536;
     std::string err;
     int32_t* d_status = nullptr;   // device status word
-    int32_t* h_pinned = nullptr;   // pinned host scratch (pinned_ints ints)
-    size_t pinned_ints = 0;
+    int32_t* h_pinned = nullptr;   // pinned host scratch (4096 ints)
     double stage_ms[5] = {0, 0, 0, 0, 0};
     hipEvent_t ev[6] = {};
     // per-kernel-class event timing (raft_profile_enable)
@@ -49,13 +43,6 @@ struct raft_graph {
     float* s = nullptr;
     float* sh = nullptr;
     float* dcoef = nullptr;
-    // batch structure (a single graph is the batch of one)
-    int32_t ngraphs = 1;
-    std::vector<int32_t> h_gnoff;   // [G + 1] node offsets
-    std::vector<int64_t> h_m2;      // [G] 2e per graph
-    int32_t* gnoff = nullptr;       // device copies
-    int64_t* m2 = nullptr;
-    int32_t* gid = nullptr;         // [n] graph of each node (batches only)
     GraphView view() const {
         GraphView v;
         v.n = n;
@@ -66,7 +53,6 @@ struct raft_graph {
         v.s = s;
         v.sh = sh;
         v.dcoef = dcoef;
-        v.gid = gid;
         return v;
     }
 };
@@ -177,121 +163,66 @@ Grid make_grid(int k_min, int k_max, int k_step) {
     return g;
 }
 
-// The candidate grid repeated for every graph of a batch: candidate
-// k = g * Kc1 + j is grid entry j of graph g.
-Grid tile_grid(const Grid& one, int G) {
-    Grid t;
-    t.k_max = one.k_max;
-    for (int g = 0; g < G; ++g) {
-        for (int j = 0; j < one.Kc; ++j) {
-            t.ks.push_back(one.ks[j]);
-            t.koff16.push_back(t.KP + one.koff16[j]);
-            t.koff.push_back(t.SK + one.koff[j]);
-        }
-        for (int r = 0; r < one.KP; ++r) t.cand_of.push_back(g * one.Kc + one.cand_of[r]);
-        t.KP += one.KP;
-        t.SK += one.SK;
-    }
-    t.Kc = one.Kc * G;
-    return t;
-}
-
-// Work lists over the candidates still active: alist holds their ids (graph
-// by graph); agrp splits alist into groups of about 256 padded centres
-// (assignment), ugrp into groups whose clusters fit the update kernel's LDS
-// budget.  No group spans two graphs.  Assignment work items are (group,
-// 64*PS-point tile of the group's graph); update work items are (group,
-// point range), about two per CU in total, split in proportion to the
-// group's work (candidates x points).  poff gives each candidate's first row
-// in the range partial buffers (ranges x K rows per candidate).
+// Work lists over the candidates still active: alist holds their ids;
+// agrp splits alist into groups of about 256 padded centres (assignment),
+// ugrp into groups whose clusters fit the update kernel's LDS budget.
 struct Lists {
-    std::vector<int32_t> alist, agrp, aw0, ugrp, uwi0, ulen, cranges, poff;
-    int awork = 0, uwork = 0, prows = 0;
+    std::vector<int32_t> alist, agrp, ugrp, uwi0, ulen, cranges;
+    int uwork = 0;
 };
 
 // Length of the dynamic work lists (see pack_lists).
-constexpr int kDynLen(int Kc) { return 8 * Kc + 4; }
+constexpr int kDynLen(int Kc) { return 6 * Kc + 3; }
 
-struct BatchShape {
-    int G = 1, Kc1 = 0;
-    std::vector<int32_t> gnoff;   // [G + 1]
-    int n_total() const { return gnoff.back(); }
-    int n_of(int g) const { return gnoff[g + 1] - gnoff[g]; }
-};
+// Point ranges per update group are capped so the partial buffers stay bounded.
+int update_ranges_max(int n, int num_cu) {
+    return std::max(1, std::min(num_cu, (n + 63) / 64));
+}
 
-Lists make_lists(const Grid& T, const BatchShape& B, const int32_t* active, int ucap, int tile,
-                 int num_cu, int prow_cap) {
+Lists make_lists(const Grid& G, const int32_t* active, int ucap, int n, int num_cu) {
     Lists l;
-    auto graph_of = [&](int k) { return k / B.Kc1; };
-    for (int k = 0; k < T.Kc; ++k)
+    for (int k = 0; k < G.Kc; ++k)
         if (!active || active[k]) l.alist.push_back(k);
-    const int na = (int)l.alist.size();
-    // assignment groups
     l.agrp.push_back(0);
-    l.aw0.push_back(0);
     int acc = 0;
-    for (int t = 0; t < na; ++t) {
-        acc += (T.ks[l.alist[t]] + 15) / 16 * 16;
-        const bool last = t + 1 == na;
-        const bool split = last || acc >= 256 || graph_of(l.alist[t + 1]) != graph_of(l.alist[t]);
-        if (split) {
-            const int n = B.n_of(graph_of(l.alist[t]));
-            l.agrp.push_back(t + 1);
-            l.aw0.push_back(l.aw0.back() + (n + tile - 1) / tile);
+    for (size_t t = 0; t < l.alist.size(); ++t) {
+        acc += (G.ks[l.alist[t]] + 15) / 16 * 16;
+        if (acc >= 256 && t + 1 < l.alist.size()) {
+            l.agrp.push_back((int32_t)t + 1);
             acc = 0;
         }
     }
-    l.awork = l.aw0.back();
-    // update groups
+    l.agrp.push_back((int32_t)l.alist.size());
     l.ugrp.push_back(0);
     acc = 0;
     int cnt = 0;
-    for (int t = 0; t < na; ++t) {
-        const int rows = kmeans_update_rows(T.ks[l.alist[t]]);
-        const bool new_graph = t > 0 && graph_of(l.alist[t]) != graph_of(l.alist[t - 1]);
-        if (cnt > 0 && (new_graph || acc + rows > ucap || cnt >= kmeans_update_max_candidates())) {
-            l.ugrp.push_back(t);
+    for (size_t t = 0; t < l.alist.size(); ++t) {
+        const int rows = kmeans_update_rows(G.ks[l.alist[t]]);
+        if (cnt > 0 && (acc + rows > ucap || cnt >= kmeans_update_max_candidates())) {
+            l.ugrp.push_back((int32_t)t);
             acc = 0;
             cnt = 0;
         }
         acc += rows;
         ++cnt;
     }
-    l.ugrp.push_back(na);
+    l.ugrp.push_back((int32_t)l.alist.size());
+    // work items: about 2 per CU in total, split over the groups in
+    // proportion to their candidate counts (the update's work per point)
     const int ug = (int)l.ugrp.size() - 1;
-    double wsum = 0;
-    for (int gi = 0; gi < ug; ++gi)
-        wsum += (double)(l.ugrp[gi + 1] - l.ugrp[gi]) * B.n_of(graph_of(l.alist[l.ugrp[gi]]));
-    l.cranges.assign(T.Kc, 1);
-    l.poff.assign(T.Kc, 0);
-    std::vector<int> rs(ug), lens(ug);
-    for (int pass = 0; pass < 2; ++pass) {
-        int prow = 0;
-        for (int gi = 0; gi < ug; ++gi) {
-            const int c = l.ugrp[gi + 1] - l.ugrp[gi];
-            const int n = B.n_of(graph_of(l.alist[l.ugrp[gi]]));
-            int r = 1;
-            if (pass == 0 && wsum > 0) {
-                r = (int)(2.0 * num_cu * c * (double)n / wsum);
-                r = std::max(1, std::min(r, std::max(1, (n + 63) / 64)));
-            }
-            const int len = std::max(64, ((n + r - 1) / r + 63) / 64 * 64);
-            r = std::max(1, (n + len - 1) / len);
-            rs[gi] = r;
-            lens[gi] = len;
-            for (int t = l.ugrp[gi]; t < l.ugrp[gi + 1]; ++t) {
-                l.cranges[l.alist[t]] = r;
-                l.poff[l.alist[t]] = prow;
-                prow += r * T.ks[l.alist[t]];
-            }
-        }
-        l.prows = prow;
-        if (prow <= prow_cap) break;   // (one range per group always fits)
-    }
+    const int total_c = std::max<int>(1, (int)l.alist.size());
+    const int max_r = update_ranges_max(n, num_cu);
+    l.cranges.assign(G.Kc, 1);
     l.uwi0.push_back(0);
     for (int gi = 0; gi < ug; ++gi) {
-        l.ulen.push_back(lens[gi]);
-        l.uwi0.push_back(l.uwi0.back() + rs[gi]);
+        const int c = l.ugrp[gi + 1] - l.ugrp[gi];
+        int r = (int)((2LL * num_cu * c) / total_c);
+        r = std::max(1, std::min(r, max_r));
+        const int len = ((n + r - 1) / r + 63) / 64 * 64;
+        r = (n + len - 1) / len;
+        l.ulen.push_back(len);
+        l.uwi0.push_back(l.uwi0.back() + r);
+        for (int t = l.ugrp[gi]; t < l.ugrp[gi + 1]; ++t) l.cranges[l.alist[t]] = r;
     }
     l.uwork = l.uwi0.back();
     return l;
@@ -318,12 +249,6 @@ int max_width(const raft_config* c) {
     return m;
 }
 
-int min_graph_nodes(const raft_graph* g) {
-    int m = INT32_MAX;
-    for (int i = 0; i + 1 < (int)g->h_gnoff.size(); ++i) m = std::min(m, g->h_gnoff[i + 1] - g->h_gnoff[i]);
-    return m;
-}
-
 raft_status check_config(raft_ctx* ctx, const raft_graph* g, const raft_config* c) {
     if (!c) return fail(ctx, RAFT_E_INVAL, "config is null");
     if (c->abi_version != RAFT_ABI_VERSION)
@@ -343,37 +268,26 @@ raft_status check_config(raft_ctx* ctx, const raft_graph* g, const raft_config* 
     if (c->k_step < 1 || c->k_min < 1 || c->k_min > c->k_max || c->k_max > RAFT_MAX_K)
         return fail(ctx, RAFT_E_INVAL, "candidate grid %d..%d step %d", c->k_min, c->k_max,
                     c->k_step);
-    if (g && c->k_max > min_graph_nodes(g))
-        return fail(ctx, RAFT_E_INVAL, "k_max %d exceeds the node count of a graph", c->k_max);
+    if (g && c->k_max > g->n) return fail(ctx, RAFT_E_INVAL, "k_max %d exceeds N", c->k_max);
     if (c->kmeans_max_iter < 1) return fail(ctx, RAFT_E_INVAL, "kmeans_max_iter < 1");
     return RAFT_OK;
 }
 
-// Workspace layout shared by every staged call.  A single graph is the
-// batch of one (G = 1).
+// Workspace layout shared by every staged call.
 struct Plan {
-    int L = 0, d = 0, Lmax = 0, S = 0, race_grid = 0, tile = 0;
-    BatchShape B;
-    Grid grid;    // one graph's candidate grid
-    Grid tgrid;   // the grid of every graph (k-means candidates)
+    int L = 0, d = 0, Lmax = 0, spmm_grid_ = 0, score_grid_ = 0, S = 0, race_grid = 0;
+    Grid grid;
     Lists lists;
     int ucap = 0;
-    int prow_cap = 0;
-    int score_items = 0, colsum_items = 0;
-    std::vector<int32_t> sw0, cw0;   // [G + 1] edge-score / column-sum work items per graph
+    int ranges_max = 0;
     // projection / embedding
     float *y0, *y1, *pbuf, *yout, *zout, *wbuf;
-    size_t wstride = 0;
     double *cpart, *c64;
     float* cvec;
-    uint64_t* seeds_dev;
-    uint64_t seed0 = 0;   // key of a single graph (the batch of one)
     // k-means
     KmeansPlan km;
-    int32_t* meta;   // ks, koff16, koff, cand_of, cg, sw0, cw0, then the dynamic lists
-    int32_t* dyn;    // dynamic lists (rewritten at convergence polls)
-    int32_t *sw0_dev, *cw0_dev;
-    int64_t* lab_off_dev;
+    int32_t* meta;   // ks, koff16, koff, cand_of, alist, agrp, ugrp packed
+    int32_t* dyn;    // alist, agrp, ugrp (rewritten at convergence polls)
     // scores
     ScorePlan sc;
     uint8_t* lab_pm;
@@ -384,47 +298,19 @@ struct Plan {
     size_t bytes = 0;
 };
 
-size_t meta_ints(const Plan& P) {
-    const Grid& T = P.tgrid;
-    return (size_t)4 * T.Kc + T.KP + 2 * (size_t)(P.B.G + 1) + (size_t)kDynLen(T.Kc);
-}
-
-// Work items per graph, about `total` overall in proportion to node counts,
-// each covering at least `min_rows` rows.
-std::vector<int32_t> split_items(const BatchShape& B, int64_t total, int min_rows) {
-    std::vector<int32_t> w0(1, 0);
-    const int64_t n = std::max(1, B.n_total());
-    for (int g = 0; g < B.G; ++g) {
-        const int64_t ng = B.n_of(g);
-        int64_t want = (total * ng + n - 1) / n;
-        want = std::max<int64_t>(1, std::min<int64_t>(want, (ng + min_rows - 1) / min_rows));
-        w0.push_back(w0.back() + (int32_t)want);
-    }
-    return w0;
-}
-
 void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char* base, Plan& P) {
     const int n = g->n;
-    P.seed0 = c->seed;
-    P.B.G = g->ngraphs;
-    P.B.gnoff = g->h_gnoff;
-    const int G = P.B.G;
     P.L = c->proj_dim;
     P.d = embed_dim(c);
     P.Lmax = max_width(c);
     P.grid = make_grid(c->k_min, c->k_max, c->k_step);
-    P.B.Kc1 = P.grid.Kc;
-    P.tgrid = tile_grid(P.grid, G);
-    P.tile = kmeans_assign_tile(P.d);
+    P.spmm_grid_ = spmm_grid(n, P.Lmax, ctx->num_cu, nullptr);
+    // every width uses the same grid formula (it does not depend on L)
+    P.score_grid_ = score_grid(n, ctx->num_cu);
     P.S = (P.grid.Kc + 7) / 8 * 8;
     P.ucap = update_cap(P.grid, P.d);
-    P.prow_cap = P.tgrid.SK + 2 * ctx->num_cu * P.ucap;
-    P.lists = make_lists(P.tgrid, P.B, nullptr, P.ucap, P.tile, ctx->num_cu, P.prow_cap);
+    P.lists = make_lists(P.grid, nullptr, P.ucap, n, ctx->num_cu);
     P.race_grid = kmeans_race_grid(n, ctx->num_cu);
-    P.sw0 = split_items(P.B, (int64_t)ctx->num_cu * 2, 64);
-    P.score_items = P.sw0.back();
-    P.cw0 = split_items(P.B, (int64_t)ctx->num_cu * 2, 256);
-    P.colsum_items = P.cw0.back();
     Arena a;
     a.base = base;
     const size_t nL = (size_t)n * P.Lmax;
@@ -439,154 +325,108 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
         wmax = std::max(wmax, (size_t)lin * c->layer_dims[k]);
         lin = c->layer_dims[k];
     }
-    P.wstride = wmax;
-    P.wbuf = a.take<float>(wmax * G);
-    const size_t cs_rows = G == 1
-        ? (size_t)spmm_grid(n, P.L, ctx->num_cu, nullptr) + kColsumStageRows
-        : (size_t)P.colsum_items;
-    P.cpart = a.take<double>(cs_rows * P.L);
-    P.c64 = a.take<double>((size_t)G * P.Lmax);
-    P.cvec = a.take<float>((size_t)G * P.Lmax);
-    P.seeds_dev = a.take<uint64_t>(G);
+    P.wbuf = a.take<float>(wmax);
+    P.cpart = a.take<double>(((size_t)spmm_grid(n, P.L, ctx->num_cu, nullptr) + kColsumStageRows) * P.L);
+    P.c64 = a.take<double>(P.Lmax);
+    P.cvec = a.take<float>(P.Lmax);
     // k-means
-    const Grid& T = P.tgrid;
-    P.meta = a.take<int32_t>(meta_ints(P));
-    auto at = [&](size_t off) -> int32_t* { return P.meta ? P.meta + off : nullptr; };
-    size_t off = 0;
+    const Grid& G = P.grid;
+    const size_t meta_n = (size_t)3 * G.Kc + G.KP + (size_t)kDynLen(G.Kc);
+    P.meta = a.take<int32_t>(meta_n);
+    P.dyn = P.meta ? P.meta + 3 * G.Kc + G.KP : nullptr;
     KmeansPlan& km = P.km;
-    km.ks = at(off);
-    off += T.Kc;
-    km.koff16 = at(off);
-    off += T.Kc;
-    km.koff = at(off);
-    off += T.Kc;
-    km.cand_of = at(off);
-    off += T.KP;
-    km.cg = at(off);
-    off += T.Kc;
-    P.sw0_dev = at(off);
-    off += G + 1;
-    P.cw0_dev = at(off);
-    off += G + 1;
-    P.dyn = at(off);
-    P.lab_off_dev = a.take<int64_t>(T.Kc);
     km.n = n;
     km.d = P.d;
-    km.Kc = T.Kc;
-    km.k_max = P.grid.k_max;
-    km.ngraphs = G;
-    km.awork = P.lists.awork;
-    km.KP = T.KP;
-    km.SK = T.SK;
+    km.Kc = G.Kc;
+    km.k_max = G.k_max;
+    km.KP = G.KP;
+    km.SK = G.SK;
     km.agroups = (int)P.lists.agrp.size() - 1;
     km.ugroups = (int)P.lists.ugrp.size() - 1;
     km.usk_max = P.ucap;
+    P.ranges_max = update_ranges_max(n, ctx->num_cu);
     km.uwork = P.lists.uwork;
     km.race_grid = P.race_grid;
-    const int Kt = T.Kc;
+    km.ks = P.meta;
+    km.koff16 = P.meta ? P.meta + G.Kc : nullptr;
+    km.koff = P.meta ? P.meta + 2 * G.Kc : nullptr;
+    km.cand_of = P.meta ? P.meta + 3 * G.Kc : nullptr;
     km.alist = P.dyn;
-    km.agrp = P.dyn ? P.dyn + Kt : nullptr;
-    km.aw0 = P.dyn ? P.dyn + 2 * Kt + 1 : nullptr;
-    km.ugrp = P.dyn ? P.dyn + 3 * Kt + 2 : nullptr;
-    km.uwi0 = P.dyn ? P.dyn + 4 * Kt + 3 : nullptr;
-    km.ulen = P.dyn ? P.dyn + 5 * Kt + 4 : nullptr;
-    km.cranges = P.dyn ? P.dyn + 6 * Kt + 4 : nullptr;
-    km.poff = P.dyn ? P.dyn + 7 * Kt + 4 : nullptr;
-    km.gnoff = g->gnoff;
-    km.lab_off = P.lab_off_dev;
-    km.lab_total = (int64_t)P.grid.Kc * n;
-    km.active = a.take<int32_t>(Kt);
-    km.changes = a.take<int32_t>(Kt);
-    P.iters_int = a.take<int32_t>(Kt);
+    km.agrp = P.dyn ? P.dyn + G.Kc : nullptr;
+    km.ugrp = P.dyn ? P.dyn + 2 * G.Kc + 1 : nullptr;
+    km.uwi0 = P.dyn ? P.dyn + 3 * G.Kc + 2 : nullptr;
+    km.ulen = P.dyn ? P.dyn + 4 * G.Kc + 3 : nullptr;
+    km.cranges = P.dyn ? P.dyn + 5 * G.Kc + 3 : nullptr;
+    km.active = a.take<int32_t>(G.Kc);
+    km.changes = a.take<int32_t>(G.Kc);
+    P.iters_int = a.take<int32_t>(G.Kc);
     km.iters = P.iters_int;
     km.active_count = a.take<int32_t>(1);
-    km.C = a.take<float>((size_t)T.KP * P.d);
-    km.cnorm = a.take<float>(T.KP);
-    km.psum = a.take<long long>((size_t)P.prow_cap * P.d);
-    km.pcnt = a.take<int32_t>((size_t)P.prow_cap);
-    km.zmax_bits = a.take<uint32_t>(G);
+    km.C = a.take<float>((size_t)G.KP * P.d);
+    km.cnorm = a.take<float>(G.KP);
+    km.psum = a.take<float>((size_t)P.ranges_max * G.KP * P.d);
+    km.pcnt = a.take<int32_t>((size_t)P.ranges_max * G.KP);
+    km.zmax_bits = a.take<uint32_t>(1);
     km.w = a.take<float>(n);
     km.race_val = a.take<double>(P.race_grid);
     km.race_idx = a.take<int32_t>(P.race_grid);
     km.race_counter = a.take<uint32_t>(1);
-    P.picks_int = a.take<int32_t>((size_t)G * P.grid.k_max);
+    P.picks_int = a.take<int32_t>(G.k_max);
     km.picks = P.picks_int;
-    km.lab_cm = a.take<uint8_t>((size_t)km.lab_total);
+    km.lab_cm = a.take<uint8_t>((size_t)G.Kc * n);
     km.status = ctx->d_status;
     // scores
     ScorePlan& sc = P.sc;
-    const int SK1 = P.grid.SK, Kc1 = P.grid.Kc;
     sc.n = n;
-    sc.Kc = Kc1;
+    sc.Kc = G.Kc;
     sc.S = P.S;
-    sc.SK = SK1;
-    sc.grid = P.score_items;
-    sc.ngraphs = G;
-    sc.ks = km.ks;      // the first Kc1 entries are one graph's grid
+    sc.SK = G.SK;
+    sc.grid = P.score_grid_;
+    sc.nnz = g->nnz;
+    sc.ks = km.ks;
     sc.koff = km.koff;
-    sc.gnoff = g->gnoff;
-    sc.gid = g->gid;
-    sc.sw0 = P.sw0_dev;
-    sc.m2 = g->m2;
-    sc.lpart = a.take<int32_t>((size_t)P.score_items * SK1);
-    sc.vpart = a.take<int32_t>((size_t)P.score_items * SK1);
-    sc.l64 = a.take<int64_t>((size_t)G * SK1);
-    sc.v64 = a.take<int64_t>((size_t)G * SK1);
-    P.mod_int = a.take<double>((size_t)G * Kc1);
-    P.ncut_int = a.take<double>((size_t)G * Kc1);
+    sc.lpart = a.take<int32_t>((size_t)P.score_grid_ * G.SK);
+    sc.vpart = a.take<int32_t>((size_t)P.score_grid_ * G.SK);
+    sc.l64 = a.take<int64_t>(G.SK);
+    sc.v64 = a.take<int64_t>(G.SK);
+    P.mod_int = a.take<double>(G.Kc);
+    P.ncut_int = a.take<double>(G.Kc);
     sc.mod = P.mod_int;
     sc.ncut = P.ncut_int;
-    sc.best = a.take<int32_t>(G);
-    sc.first = a.take<int32_t>((size_t)G * (RAFT_MAX_K + 1));
-    sc.remap = a.take<int32_t>((size_t)G * (RAFT_MAX_K + 1));
+    sc.best = a.take<int32_t>(1);
+    sc.first = a.take<int32_t>(RAFT_MAX_K + 1);
+    sc.remap = a.take<int32_t>(RAFT_MAX_K + 1);
     sc.status = ctx->d_status;
-    P.ksel_int = a.take<int32_t>((size_t)G * 3);
+    P.ksel_int = a.take<int32_t>(4);
     P.lab_pm = a.take<uint8_t>((size_t)n * P.S);
     P.bytes = a.off;
 }
 
 // Packs the dynamic lists at fixed offsets: alist [Kc], agrp [Kc+1],
-// aw0 [Kc+1], ugrp [Kc+1], uwi0 [Kc+1], ulen [Kc], cranges [Kc], poff [Kc].
+// ugrp [Kc+1], uwi0 [Kc+1], ulen [Kc], cranges [Kc].
 void pack_lists(const Lists& l, int Kc, int32_t* out) {
     std::fill(out, out + kDynLen(Kc), 0);
     std::copy(l.alist.begin(), l.alist.end(), out);
     std::copy(l.agrp.begin(), l.agrp.end(), out + Kc);
-    std::copy(l.aw0.begin(), l.aw0.end(), out + 2 * Kc + 1);
-    std::copy(l.ugrp.begin(), l.ugrp.end(), out + 3 * Kc + 2);
-    std::copy(l.uwi0.begin(), l.uwi0.end(), out + 4 * Kc + 3);
-    std::copy(l.ulen.begin(), l.ulen.end(), out + 5 * Kc + 4);
-    std::copy(l.cranges.begin(), l.cranges.end(), out + 6 * Kc + 4);
-    std::copy(l.poff.begin(), l.poff.end(), out + 7 * Kc + 4);
+    std::copy(l.ugrp.begin(), l.ugrp.end(), out + 2 * Kc + 1);
+    std::copy(l.uwi0.begin(), l.uwi0.end(), out + 3 * Kc + 2);
+    std::copy(l.ulen.begin(), l.ulen.end(), out + 4 * Kc + 3);
+    std::copy(l.cranges.begin(), l.cranges.end(), out + 5 * Kc + 3);
 }
 
-raft_status upload_meta(raft_ctx* ctx, Plan& P, const uint64_t* seeds, hipStream_t st) {
-    P.seed0 = seeds[0];
-    const Grid& T = P.tgrid;
-    const int G = P.B.G;
+raft_status upload_meta(raft_ctx* ctx, const Plan& P, hipStream_t st) {
+    const Grid& G = P.grid;
     std::vector<int32_t> meta;
-    meta.reserve(meta_ints(P));
-    meta.insert(meta.end(), T.ks.begin(), T.ks.end());
-    meta.insert(meta.end(), T.koff16.begin(), T.koff16.end());
-    meta.insert(meta.end(), T.koff.begin(), T.koff.end());
-    meta.insert(meta.end(), T.cand_of.begin(), T.cand_of.end());
-    for (int k = 0; k < T.Kc; ++k) meta.push_back(k / P.B.Kc1);
-    meta.insert(meta.end(), P.sw0.begin(), P.sw0.end());
-    meta.insert(meta.end(), P.cw0.begin(), P.cw0.end());
+    meta.insert(meta.end(), G.ks.begin(), G.ks.end());
+    meta.insert(meta.end(), G.koff16.begin(), G.koff16.end());
+    meta.insert(meta.end(), G.koff.begin(), G.koff.end());
+    meta.insert(meta.end(), G.cand_of.begin(), G.cand_of.end());
     const size_t at = meta.size();
-    meta.resize(at + (size_t)kDynLen(T.Kc));
-    pack_lists(P.lists, T.Kc, meta.data() + at);
-    std::vector<int64_t> lab_off(T.Kc);
-    for (int k = 0; k < T.Kc; ++k) {
-        const int g = k / P.B.Kc1, j = k % P.B.Kc1;
-        lab_off[k] = (int64_t)P.B.Kc1 * P.B.gnoff[g] + (int64_t)j * P.B.n_of(g);
-    }
+    meta.resize(at + (size_t)kDynLen(G.Kc));
+    pack_lists(P.lists, G.Kc, meta.data() + at);
     HIP_TRY(ctx, hipMemcpyAsync(P.meta, meta.data(), meta.size() * sizeof(int32_t),
                                 hipMemcpyHostToDevice, st));
-    HIP_TRY(ctx, hipMemcpyAsync(P.lab_off_dev, lab_off.data(), lab_off.size() * sizeof(int64_t),
-                                hipMemcpyHostToDevice, st));
-    HIP_TRY(ctx, hipMemcpyAsync(P.seeds_dev, seeds, (size_t)G * sizeof(uint64_t),
-                                hipMemcpyHostToDevice, st));
-    // pageable sources: wait so the host vectors may go out of scope
+    // pageable source: wait so the host vector may go out of scope
     HIP_TRY(ctx, hipStreamSynchronize(st));
     return RAFT_OK;
 }
@@ -618,38 +458,25 @@ raft_status do_project(raft_ctx* ctx, const raft_graph* g, const raft_config* c,
                        float* out, hipStream_t st) {
     const int L = P.L;
     const GraphView gv = g->view();
-    const int G = P.B.G;
     float* src = P.y0;
-    const double sigma = 1.0 / std::sqrt((double)L);
-    if (G == 1)
-        launch_gaussian(P.seed0, 0x10, g->n, L, sigma, src, st);
-    else
-        launch_gaussian_rows(P.seeds_dev, g->gid, g->gnoff, 0x10, g->n, L, sigma, src, st);
+    launch_gaussian(c->seed, 0x10, g->n, L, 1.0 / std::sqrt((double)L), src, st);
     const bool mod_full = c->op == RAFT_X_MOD_FULL;
-    const int parts = spmm_grid(g->n, L, ctx->num_cu, nullptr);
-    auto colsum = [&](const float* x) {
-        if (G == 1) {
-            launch_colsum_partials(gv, L, x, P.cpart, ctx->num_cu, st);
-            launch_colsum_finish(P.cpart, parts, L, P.c64, P.cvec, st);
-        } else {
-            launch_colsum_seg(gv, L, x, P.cw0_dev, g->gnoff, G, P.colsum_items, P.cpart, st);
-            launch_colsum_seg_finish(P.cpart, P.cw0_dev, G, L, P.c64, P.cvec, st);
-        }
-    };
-    if (mod_full) colsum(src);
+    if (mod_full) {
+        launch_colsum_partials(gv, L, src, P.cpart, ctx->num_cu, st);
+        launch_colsum_finish(P.cpart, spmm_grid(g->n, L, ctx->num_cu, nullptr), L, P.c64, P.cvec,
+                             st);
+    }
     for (int t = 1; t <= c->q; ++t) {
         float* dst = (t == c->q) ? out : (src == P.y0 ? P.y1 : P.y0);
         const bool need_cs = mod_full && t < c->q;
-        // a single graph folds the next column sums into the SpMM epilogue
-        const bool fused = need_cs && G == 1;
         {
             ProfScope ps(ctx, RAFT_PROF_SPMM, st);
-            launch_spmm(gv, c->op, L, src, dst, P.cvec, fused ? P.cpart : nullptr, ctx->num_cu, st);
+            launch_spmm(gv, c->op, L, src, dst, P.cvec, need_cs ? P.cpart : nullptr, ctx->num_cu,
+                        st);
         }
-        if (fused)
-            launch_colsum_finish(P.cpart, parts, L, P.c64, P.cvec, st);
-        else if (need_cs)
-            colsum(dst);
+        if (need_cs)
+            launch_colsum_finish(P.cpart, spmm_grid(g->n, L, ctx->num_cu, nullptr), L, P.c64,
+                                 P.cvec, st);
         src = dst;
     }
     return launch_check(ctx);
@@ -658,7 +485,6 @@ raft_status do_project(raft_ctx* ctx, const raft_graph* g, const raft_config* c,
 raft_status do_embed(raft_ctx* ctx, const raft_graph* g, const raft_config* c, Plan& P,
                      const float* Y, float* Z, hipStream_t st) {
     const GraphView gv = g->view();
-    const int G = P.B.G;
     const float* h = Y;
     int lin = P.L;
     if (c->n_layers == 0) {
@@ -676,11 +502,8 @@ raft_status do_embed(raft_ctx* ctx, const raft_graph* g, const raft_config* c, P
     }
     for (int k = 1; k <= c->n_layers; ++k) {
         const int lout = c->layer_dims[k - 1];
-        const double sigma = 1.0 / std::sqrt((double)lin);
-        if (G == 1)
-            launch_gaussian(P.seed0, 0x10 + (uint64_t)k, lin, lout, sigma, P.wbuf, st);
-        else
-            launch_gaussian_multi(P.seeds_dev, G, 0x10 + (uint64_t)k, lin, lout, sigma, P.wbuf, st);
+        launch_gaussian(c->seed, 0x10 + (uint64_t)k, lin, lout, 1.0 / std::sqrt((double)lin),
+                        P.wbuf, st);
         {
             ProfScope ps(ctx, RAFT_PROF_SPMM, st);
             launch_spmm(gv, kOpGcn, lin, h, P.pbuf, nullptr, nullptr, ctx->num_cu, st);
@@ -688,8 +511,7 @@ raft_status do_embed(raft_ctx* ctx, const raft_graph* g, const raft_config* c, P
         float* dst = (k == c->n_layers) ? Z : (h == P.y0 ? P.y1 : P.y0);
         {
             ProfScope ps(ctx, RAFT_PROF_DENSE, st);
-            launch_dense_layer(P.pbuf, P.wbuf, dst, g->n, lin, lout, false, ctx->d_status, st,
-                               G == 1 ? nullptr : g->gid);
+            launch_dense_layer(P.pbuf, P.wbuf, dst, g->n, lin, lout, false, ctx->d_status, st);
         }
         h = dst;
         lin = lout;
@@ -708,31 +530,19 @@ raft_status do_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* 
     int32_t* ksel = (out && out->k_selected) ? out->k_selected : P.ksel_int;
     const int t_max = c->kmeans_max_iter;
     const int check = c->check_every > 0 ? c->check_every : 4;
-    const int Kt = P.tgrid.Kc;
-    // host copies of the active flags and the work lists: the context's
-    // pinned scratch when they fit (it is never freed before the context),
-    // else pageable memory with a wait after each upload
-    const size_t host_ints = (size_t)Kt + (size_t)kDynLen(Kt);
-    std::vector<int32_t> pageable;
-    const bool pinned = 16 + host_ints <= ctx->pinned_ints;
-    if (!pinned) pageable.resize(host_ints);
-    int32_t* h_active = pinned ? ctx->h_pinned + 16 : pageable.data();
-    int32_t* h_lists = h_active + Kt;
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[2], st));
     launch_kmeans_reset(km, st);
     launch_zmax(km, Z, ctx->num_cu, st);
-    if (P.B.G == 1) {
-        for (int t = 0; t < km.k_max; ++t) {
-            ProfScope ps(ctx, RAFT_PROF_RACE, st);
-            launch_race_pick(km, Z, t, P.seed0, st);
-        }
-    } else {
+    for (int t = 0; t < km.k_max; ++t) {
         ProfScope ps(ctx, RAFT_PROF_RACE, st);
-        launch_race_batch(km, Z, P.seeds_dev, st);
+        launch_race_pick(km, Z, t, c->seed, st);
     }
     launch_init_centres(km, Z, st);
     RAFT_TRY(launch_check(ctx));
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[3], st));
+    const int Kc = P.grid.Kc;
+    int32_t* h_active = ctx->h_pinned + 16;
+    int32_t* h_lists = ctx->h_pinned + 16 + RAFT_MAX_K + 1;
     for (int it = 1; it <= t_max; ++it) {
         {
             ProfScope ps(ctx, RAFT_PROF_ASSIGN, st);
@@ -745,28 +555,25 @@ raft_status do_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* 
             launch_update(km, Z, ctx->lds_max, st);
         }
         if (it % check == 0) {
-            HIP_TRY(ctx, hipMemcpyAsync(h_active, km.active, Kt * sizeof(int32_t),
+            HIP_TRY(ctx, hipMemcpyAsync(h_active, km.active, Kc * sizeof(int32_t),
                                         hipMemcpyDeviceToHost, st));
             HIP_TRY(ctx, hipStreamSynchronize(st));
             int live = 0;
-            for (int k = 0; k < Kt; ++k) live += h_active[k] != 0;
+            for (int k = 0; k < Kc; ++k) live += h_active[k] != 0;
             if (live == 0) break;
             // compact the work lists to the candidates still iterating
-            const Lists l = make_lists(P.tgrid, P.B, h_active, P.ucap, P.tile, ctx->num_cu,
-                                       P.prow_cap);
-            pack_lists(l, Kt, h_lists);
-            HIP_TRY(ctx, hipMemcpyAsync(P.dyn, h_lists, (size_t)kDynLen(Kt) * sizeof(int32_t),
+            const Lists l = make_lists(P.grid, h_active, P.ucap, g->n, ctx->num_cu);
+            pack_lists(l, Kc, h_lists);
+            HIP_TRY(ctx, hipMemcpyAsync(P.dyn, h_lists, (size_t)kDynLen(Kc) * sizeof(int32_t),
                                         hipMemcpyHostToDevice, st));
-            if (!pinned) HIP_TRY(ctx, hipStreamSynchronize(st));
             km.agroups = (int)l.agrp.size() - 1;
             km.ugroups = (int)l.ugrp.size() - 1;
-            km.awork = l.awork;
             km.uwork = l.uwork;
         }
     }
     RAFT_TRY(launch_check(ctx));
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[4], st));
-    launch_transpose_labels(km, sc, P.lab_pm, st);
+    launch_transpose_labels(km.lab_cm, g->n, P.grid.Kc, P.lab_pm, P.S, st);
     {
         ProfScope ps(ctx, RAFT_PROF_SCORE, st);
         launch_edge_score(g->view(), sc, P.lab_pm, st);
@@ -789,35 +596,8 @@ raft_status plan_for(raft_ctx* ctx, const raft_graph* g, const raft_config* c, v
         return fail(ctx, RAFT_E_UNSUPPORTED, "k_max %d too large for width %d", P.grid.k_max, d);
     if (!score_supported(P.grid.SK))
         return fail(ctx, RAFT_E_UNSUPPORTED, "sum of candidate K %d > 16384", P.grid.SK);
-    if ((int64_t)P.tgrid.KP * d >= INT32_MAX || (int64_t)P.prow_cap * d >= INT32_MAX)
-        return fail(ctx, RAFT_E_UNSUPPORTED, "batch candidate table too large");
     RAFT_TRY(check_ws(ctx, ws, ws_bytes, P.bytes));
     plan_layout(ctx, g, c, reinterpret_cast<char*>(ws), P);
-    return RAFT_OK;
-}
-
-// Whole pipeline (projection -> embedding -> partition) on one graph or a
-// batch; seeds[g] keys graph g.
-raft_status run_all(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg,
-                    const uint64_t* seeds, void* ws, size_t ws_bytes, raft_outputs* out,
-                    hipStream_t st) {
-    Plan P;
-    RAFT_TRY(plan_for(ctx, g, cfg, ws, ws_bytes, P));
-    RAFT_TRY(upload_meta(ctx, P, seeds, st));
-    float* Y = (out && out->Y) ? out->Y : P.yout;
-    float* Z = (out && out->Z) ? out->Z : P.zout;
-    HIP_TRY(ctx, hipEventRecord(ctx->ev[0], st));
-    RAFT_TRY(do_project(ctx, g, cfg, P, Y, st));
-    HIP_TRY(ctx, hipEventRecord(ctx->ev[1], st));
-    RAFT_TRY(do_embed(ctx, g, cfg, P, Y, Z, st));
-    RAFT_TRY(do_partition(ctx, g, cfg, P, Z, out, st, true));
-    HIP_TRY(ctx, hipEventSynchronize(ctx->ev[5]));
-    prof_collect(ctx);
-    float ms = 0;
-    for (int s = 0; s < 5; ++s) {
-        if (hipEventElapsedTime(&ms, ctx->ev[s], ctx->ev[s + 1]) == hipSuccess)
-            ctx->stage_ms[s] = ms;
-    }
     return RAFT_OK;
 }
 
@@ -865,8 +645,7 @@ raft_status raft_ctx_create(int device, raft_ctx** out) {
              lds > 0)
         c->lds_max = (size_t)lds;
     if (hipMalloc(&c->d_status, 256) != hipSuccess ||
-        hipHostMalloc((void**)&c->h_pinned, kPinnedInts * sizeof(int32_t), hipHostMallocDefault) !=
-            hipSuccess) {
+        hipHostMalloc((void**)&c->h_pinned, 16384, hipHostMallocDefault) != hipSuccess) {
         delete c;
         return RAFT_E_NOMEM;
     }
@@ -874,7 +653,6 @@ raft_status raft_ctx_create(int device, raft_ctx** out) {
         delete c;
         return RAFT_E_DEVICE;
     }
-    c->pinned_ints = kPinnedInts;
     for (auto& e : c->ev) (void)hipEventCreate(&e);
     *out = c;
     return RAFT_OK;
@@ -952,24 +730,16 @@ raft_status raft_graph_create(raft_ctx* ctx, const int32_t* row_ptr, const int32
               hipMalloc(&g->deg, sizeof(int32_t) * n) == hipSuccess &&
               hipMalloc(&g->s, sizeof(float) * n) == hipSuccess &&
               hipMalloc(&g->sh, sizeof(float) * n) == hipSuccess &&
-              hipMalloc(&g->dcoef, sizeof(float) * n) == hipSuccess &&
-              hipMalloc(&g->gnoff, sizeof(int32_t) * 2) == hipSuccess &&
-              hipMalloc(&g->m2, sizeof(int64_t)) == hipSuccess;
+              hipMalloc(&g->dcoef, sizeof(float) * n) == hipSuccess;
     if (!ok) {
         raft_graph_destroy(g);
         return fail(ctx, RAFT_E_NOMEM, "graph allocation failed");
     }
-    g->h_gnoff = {0, (int32_t)n};
-    g->h_m2 = {nnz};
     const hipMemcpyKind kind = inputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     hipError_t e = hipMemcpyAsync(g->rp, h_rp.data(), sizeof(int32_t) * (n + 1),
                                   hipMemcpyHostToDevice, st);
     if (e == hipSuccess && nnz > 0)
         e = hipMemcpyAsync(g->ci, col_idx, sizeof(int32_t) * nnz, kind, st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(g->gnoff, g->h_gnoff.data(), sizeof(int32_t) * 2, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(g->m2, g->h_m2.data(), sizeof(int64_t), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->d_status, 0, sizeof(int32_t), st);
     if (e != hipSuccess) {
         raft_graph_destroy(g);
@@ -1010,9 +780,6 @@ void raft_graph_destroy(raft_graph* g) {
     if (g->s) (void)hipFree(g->s);
     if (g->sh) (void)hipFree(g->sh);
     if (g->dcoef) (void)hipFree(g->dcoef);
-    if (g->gnoff) (void)hipFree(g->gnoff);
-    if (g->m2) (void)hipFree(g->m2);
-    if (g->gid) (void)hipFree(g->gid);
     delete g;
 }
 
@@ -1126,7 +893,7 @@ raft_status raft_partition(raft_ctx* ctx, const raft_graph* g, const raft_config
     Plan P;
     RAFT_TRY(plan_for(ctx, g, cfg, ws, ws_bytes, P));
     hipStream_t st = as_stream(stream);
-    RAFT_TRY(upload_meta(ctx, P, &cfg->seed, st));
+    RAFT_TRY(upload_meta(ctx, P, st));
     return do_partition(ctx, g, cfg, P, Z, out, st, false);
 }
 
@@ -1146,10 +913,10 @@ raft_status raft_score(raft_ctx* ctx, const raft_graph* g, const uint8_t* labels
     }
     if (!score_supported(SK)) return fail(ctx, RAFT_E_UNSUPPORTED, "sum of K %d", SK);
     const int S = (Kc + 7) / 8 * 8;
-    const int grid = score_items(g->n, ctx->num_cu);
+    const int grid = score_grid(g->n, ctx->num_cu);
     Arena a;
     a.base = nullptr;
-    a.take<int32_t>(2 * (size_t)Kc + 2);
+    a.take<int32_t>(2 * (size_t)Kc);
     a.take<uint8_t>((size_t)g->n * S);
     a.take<int32_t>((size_t)grid * SK);
     a.take<int32_t>((size_t)grid * SK);
@@ -1159,7 +926,7 @@ raft_status raft_score(raft_ctx* ctx, const raft_graph* g, const uint8_t* labels
     a.base = reinterpret_cast<char*>(ws);
     a.off = 0;
     hipStream_t st = as_stream(stream);
-    int32_t* meta = a.take<int32_t>(2 * (size_t)Kc + 2);
+    int32_t* meta = a.take<int32_t>(2 * (size_t)Kc);
     uint8_t* pm = a.take<uint8_t>((size_t)g->n * S);
     ScorePlan sc;
     sc.n = g->n;
@@ -1167,13 +934,9 @@ raft_status raft_score(raft_ctx* ctx, const raft_graph* g, const uint8_t* labels
     sc.S = S;
     sc.SK = SK;
     sc.grid = grid;
-    sc.ngraphs = 1;
+    sc.nnz = g->nnz;
     sc.ks = meta;
     sc.koff = meta + Kc;
-    sc.gnoff = g->gnoff;
-    sc.gid = nullptr;
-    sc.sw0 = meta + 2 * Kc;
-    sc.m2 = g->m2;
     sc.lpart = a.take<int32_t>((size_t)grid * SK);
     sc.vpart = a.take<int32_t>((size_t)grid * SK);
     sc.l64 = a.take<int64_t>(SK);
@@ -1186,8 +949,6 @@ raft_status raft_score(raft_ctx* ctx, const raft_graph* g, const uint8_t* labels
     sc.status = ctx->d_status;
     std::vector<int32_t> hm(ks, ks + Kc);
     hm.insert(hm.end(), koff.begin(), koff.end());
-    hm.push_back(0);
-    hm.push_back(grid);
     HIP_TRY(ctx, hipMemcpyAsync(meta, hm.data(), hm.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
     HIP_TRY(ctx, hipStreamSynchronize(st));
     // dense point-major [n x Kc] -> stride-S layout
@@ -1206,133 +967,25 @@ raft_status raft_run(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg,
                      size_t ws_bytes, raft_outputs* out, void* stream) {
     RAFT_TRY(check_graph(ctx, g));
     if (g->nnz == 0) return fail(ctx, RAFT_E_NOEDGES, "modularity needs e > 0");
-    if (!cfg) return fail(ctx, RAFT_E_INVAL, "config is null");
-    return run_all(ctx, g, cfg, &cfg->seed, ws, ws_bytes, out, as_stream(stream));
-}
-
-// ---- batches ----------------------------------------------------------------
-
-struct raft_batch {
-    raft_graph g;
-};
-
-raft_status raft_batch_create(raft_ctx* ctx, int32_t G, const raft_graph* const* graphs,
-                              void* stream, raft_batch** out) {
-    if (!ctx) return RAFT_E_INVAL;
-    if (!out) return fail(ctx, RAFT_E_INVAL, "out is null");
-    *out = nullptr;
-    if (G < 1 || !graphs) return fail(ctx, RAFT_E_INVAL, "batch of %d graphs", G);
-    int64_t n = 0, nnz = 0;
-    std::vector<int32_t> gnoff(1, 0);
-    std::vector<int64_t> m2;
-    for (int i = 0; i < G; ++i) {
-        const raft_graph* gi = graphs[i];
-        if (!gi || gi->ctx != ctx || gi->ngraphs != 1)
-            return fail(ctx, RAFT_E_INVAL, "graph %d is null, a batch or from another context", i);
-        if (gi->nnz == 0) return fail(ctx, RAFT_E_NOEDGES, "graph %d has no edges", i);
-        n += gi->n;
-        nnz += gi->nnz;
-        if (n >= INT32_MAX || nnz >= INT32_MAX)
-            return fail(ctx, RAFT_E_UNSUPPORTED, "batch exceeds 2^31 nodes or stored entries");
-        gnoff.push_back((int32_t)n);
-        m2.push_back(gi->nnz);
-    }
+    Plan P;
+    RAFT_TRY(plan_for(ctx, g, cfg, ws, ws_bytes, P));
     hipStream_t st = as_stream(stream);
-    HIP_TRY(ctx, hipSetDevice(ctx->device));
-    raft_batch* b = new raft_batch();
-    raft_graph* g = &b->g;
-    g->ctx = ctx;
-    g->n = (int32_t)n;
-    g->nnz = nnz;
-    g->ngraphs = G;
-    g->h_gnoff = gnoff;
-    g->h_m2 = m2;
-    bool ok = hipMalloc(&g->rp, sizeof(int32_t) * (n + 1)) == hipSuccess &&
-              hipMalloc(&g->ci, sizeof(int32_t) * nnz) == hipSuccess &&
-              hipMalloc(&g->deg, sizeof(int32_t) * n) == hipSuccess &&
-              hipMalloc(&g->s, sizeof(float) * n) == hipSuccess &&
-              hipMalloc(&g->sh, sizeof(float) * n) == hipSuccess &&
-              hipMalloc(&g->dcoef, sizeof(float) * n) == hipSuccess &&
-              hipMalloc(&g->gid, sizeof(int32_t) * n) == hipSuccess &&
-              hipMalloc(&g->gnoff, sizeof(int32_t) * (G + 1)) == hipSuccess &&
-              hipMalloc(&g->m2, sizeof(int64_t) * G) == hipSuccess;
-    if (!ok) {
-        raft_batch_destroy(b);
-        return fail(ctx, RAFT_E_NOMEM, "batch allocation failed");
+    RAFT_TRY(upload_meta(ctx, P, st));
+    float* Y = (out && out->Y) ? out->Y : P.yout;
+    float* Z = (out && out->Z) ? out->Z : P.zout;
+    HIP_TRY(ctx, hipEventRecord(ctx->ev[0], st));
+    RAFT_TRY(do_project(ctx, g, cfg, P, Y, st));
+    HIP_TRY(ctx, hipEventRecord(ctx->ev[1], st));
+    RAFT_TRY(do_embed(ctx, g, cfg, P, Y, Z, st));
+    RAFT_TRY(do_partition(ctx, g, cfg, P, Z, out, st, true));
+    HIP_TRY(ctx, hipEventSynchronize(ctx->ev[5]));
+    prof_collect(ctx);
+    float ms = 0;
+    for (int s = 0; s < 5; ++s) {
+        if (hipEventElapsedTime(&ms, ctx->ev[s], ctx->ev[s + 1]) == hipSuccess)
+            ctx->stage_ms[s] = ms;
     }
-    hipError_t e = hipSuccess;
-    int64_t eoff = 0;
-    for (int i = 0; i < G && e == hipSuccess; ++i) {
-        const raft_graph* gi = graphs[i];
-        const int32_t noff = gnoff[i];
-        launch_pack_graph(gi->rp, gi->ci, gi->n, gi->nnz, noff, eoff, i, g->rp, g->ci, g->gid, st);
-        // degree statistics of a graph do not change when it joins a batch
-        const size_t nb = sizeof(float) * gi->n;
-        e = hipMemcpyAsync(g->deg + noff, gi->deg, sizeof(int32_t) * gi->n, hipMemcpyDeviceToDevice, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(g->s + noff, gi->s, nb, hipMemcpyDeviceToDevice, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(g->sh + noff, gi->sh, nb, hipMemcpyDeviceToDevice, st);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(g->dcoef + noff, gi->dcoef, nb, hipMemcpyDeviceToDevice, st);
-        if (e == hipSuccess) e = hipGetLastError();
-        eoff += gi->nnz;
-    }
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(g->gnoff, gnoff.data(), sizeof(int32_t) * (G + 1), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(g->m2, m2.data(), sizeof(int64_t) * G, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) {
-        raft_batch_destroy(b);
-        return fail(ctx, RAFT_E_DEVICE, "batch packing: %s", hipGetErrorString(e));
-    }
-    *out = b;
     return RAFT_OK;
-}
-
-void raft_batch_destroy(raft_batch* b) {
-    if (!b) return;
-    (void)hipDeviceSynchronize();
-    raft_graph* g = &b->g;
-    if (g->rp) (void)hipFree(g->rp);
-    if (g->ci) (void)hipFree(g->ci);
-    if (g->deg) (void)hipFree(g->deg);
-    if (g->s) (void)hipFree(g->s);
-    if (g->sh) (void)hipFree(g->sh);
-    if (g->dcoef) (void)hipFree(g->dcoef);
-    if (g->gnoff) (void)hipFree(g->gnoff);
-    if (g->m2) (void)hipFree(g->m2);
-    if (g->gid) (void)hipFree(g->gid);
-    delete b;
-}
-
-raft_status raft_batch_info(const raft_batch* b, int32_t* n_graphs, int64_t* n_total,
-                            int64_t* nnz_total, int64_t* node_offsets) {
-    if (!b) return RAFT_E_INVAL;
-    const raft_graph* g = &b->g;
-    if (n_graphs) *n_graphs = g->ngraphs;
-    if (n_total) *n_total = g->n;
-    if (nnz_total) *nnz_total = g->nnz;
-    if (node_offsets)
-        for (int i = 0; i <= g->ngraphs; ++i) node_offsets[i] = g->h_gnoff[i];
-    return RAFT_OK;
-}
-
-raft_status raft_batch_workspace_size(raft_ctx* ctx, const raft_batch* b, const raft_config* cfg,
-                                      size_t* bytes) {
-    if (!b) return fail(ctx, RAFT_E_INVAL, "batch is null");
-    return raft_workspace_size(ctx, &b->g, cfg, bytes);
-}
-
-raft_status raft_batch_run(raft_ctx* ctx, const raft_batch* b, const raft_config* cfg,
-                           const uint64_t* seeds, void* ws, size_t ws_bytes, raft_outputs* out,
-                           void* stream) {
-    if (!ctx) return RAFT_E_INVAL;
-    if (!b) return fail(ctx, RAFT_E_INVAL, "batch is null");
-    RAFT_TRY(check_graph(ctx, &b->g));
-    if (!cfg) return fail(ctx, RAFT_E_INVAL, "config is null");
-    std::vector<uint64_t> sd(b->g.ngraphs, cfg->seed);
-    if (seeds) sd.assign(seeds, seeds + b->g.ngraphs);
-    return run_all(ctx, &b->g, cfg, sd.data(), ws, ws_bytes, out, as_stream(stream));
 }
 
 // ---- training -------------------------------------------------------------

@@ -19,8 +19,7 @@ template <int LIN, int LOUT, bool LINEAR>
 __global__ __launch_bounds__(256) void k_dense(const float* __restrict__ P,
                                                const float* __restrict__ W,
                                                float* __restrict__ H, int n,
-                                               int32_t* __restrict__ status,
-                                               const int32_t* __restrict__ gid) {
+                                               int32_t* __restrict__ status) {
     constexpr int KS = LIN / 4;
     constexpr int NB = LOUT / 16;
     const int lane = threadIdx.x & (kWave - 1);
@@ -42,29 +41,13 @@ __global__ __launch_bounds__(256) void k_dense(const float* __restrict__ P,
     }
     floatx4 acc[NB];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-    // In a batch each graph has its own W: a tile that spans graphs runs once
-    // per graph with the other graphs' rows of A zeroed (they add exact zeros).
-    int gfirst = 0, glast = 0, gmine = 0;
-    if (gid) {
-        gfirst = __builtin_amdgcn_readfirstlane(gid[row0]);
-        glast = __builtin_amdgcn_readfirstlane(gid[min(row0 + 15, n - 1)]);
-        gmine = gid[ra];
-    }
-    for (int gg = gfirst; gg <= glast; ++gg) {
-        const float* Wg = W + (size_t)gg * LIN * LOUT;
-        const bool mine = gmine == gg;
-        float am[KS];
+    for (int nb = 0; nb < NB; ++nb) {
+        acc[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const float* wcol = W + (size_t)(g * KS) * LOUT + nb * 16 + li;
 #pragma unroll
-        for (int s = 0; s < KS; ++s) am[s] = mine ? a[s] : 0.f;
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            const float* wcol = Wg + (size_t)(g * KS) * LOUT + nb * 16 + li;
-#pragma unroll
-            for (int s = 0; s < KS; ++s) {
-                const float b = wcol[(size_t)s * LOUT];
-                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(am[s], b, acc[nb], 0, 0, 0);
-            }
+        for (int s = 0; s < KS; ++s) {
+            const float b = wcol[(size_t)s * LOUT];
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b, acc[nb], 0, 0, 0);
         }
     }
     float inv[4] = {1.f, 1.f, 1.f, 1.f};
@@ -120,40 +103,40 @@ bool dense_supported(int lin, int lout) {
 
 template <int LIN, int LOUT>
 static void dense_launch2(const float* P, const float* W, float* H, int32_t n, bool linear,
-                          int32_t* status, hipStream_t st, const int32_t* gid) {
+                          int32_t* status, hipStream_t st) {
     const int grid = (n + 63) / 64;
     if (linear)
         hipLaunchKernelGGL((k_dense<LIN, LOUT, true>), dim3(grid), dim3(256), 0, st, P, W, H, n,
-                           status, gid);
+                           status);
     else
         hipLaunchKernelGGL((k_dense<LIN, LOUT, false>), dim3(grid), dim3(256), 0, st, P, W, H, n,
-                           status, gid);
+                           status);
 }
 
 template <int LIN>
 static void dense_launch1(const float* P, const float* W, float* H, int32_t n, int lout,
-                          bool linear, int32_t* status, hipStream_t st, const int32_t* gid) {
+                          bool linear, int32_t* status, hipStream_t st) {
     switch (lout) {
-        case 16: dense_launch2<LIN, 16>(P, W, H, n, linear, status, st, gid); break;
-        case 32: dense_launch2<LIN, 32>(P, W, H, n, linear, status, st, gid); break;
-        case 64: dense_launch2<LIN, 64>(P, W, H, n, linear, status, st, gid); break;
-        case 128: dense_launch2<LIN, 128>(P, W, H, n, linear, status, st, gid); break;
+        case 16: dense_launch2<LIN, 16>(P, W, H, n, linear, status, st); break;
+        case 32: dense_launch2<LIN, 32>(P, W, H, n, linear, status, st); break;
+        case 64: dense_launch2<LIN, 64>(P, W, H, n, linear, status, st); break;
+        case 128: dense_launch2<LIN, 128>(P, W, H, n, linear, status, st); break;
         case 256:
-            if constexpr (LIN <= 128) dense_launch2<LIN, 256>(P, W, H, n, linear, status, st, gid);
+            if constexpr (LIN <= 128) dense_launch2<LIN, 256>(P, W, H, n, linear, status, st);
             break;
         default: break;
     }
 }
 
 void launch_dense_layer(const float* P, const float* W, float* H, int32_t n, int lin, int lout,
-                        bool linear, int32_t* status, hipStream_t st, const int32_t* gid) {
+                        bool linear, int32_t* status, hipStream_t st) {
     if (n == 0) return;
     switch (lin) {
-        case 16: dense_launch1<16>(P, W, H, n, lout, linear, status, st, gid); break;
-        case 32: dense_launch1<32>(P, W, H, n, lout, linear, status, st, gid); break;
-        case 64: dense_launch1<64>(P, W, H, n, lout, linear, status, st, gid); break;
-        case 128: dense_launch1<128>(P, W, H, n, lout, linear, status, st, gid); break;
-        case 256: dense_launch1<256>(P, W, H, n, lout, linear, status, st, gid); break;
+        case 16: dense_launch1<16>(P, W, H, n, lout, linear, status, st); break;
+        case 32: dense_launch1<32>(P, W, H, n, lout, linear, status, st); break;
+        case 64: dense_launch1<64>(P, W, H, n, lout, linear, status, st); break;
+        case 128: dense_launch1<128>(P, W, H, n, lout, linear, status, st); break;
+        case 256: dense_launch1<256>(P, W, H, n, lout, linear, status, st); break;
         default: break;
     }
 }

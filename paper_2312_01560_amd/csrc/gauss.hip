@@ -7,9 +7,13 @@
 
 namespace raft {
 
-__device__ __forceinline__ void gaussian_block(uint64_t seed, uint64_t stream, int64_t row,
-                                               int64_t cb, int64_t cols, double sigma,
-                                               float* __restrict__ orow) {
+__global__ __launch_bounds__(256) void k_gaussian(uint64_t seed, uint64_t stream, int64_t rows,
+                                                  int64_t cols, int64_t cblocks, double sigma,
+                                                  float* __restrict__ out) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= rows * cblocks) return;
+    const int64_t row = idx / cblocks;
+    const int64_t cb = idx - row * cblocks;
     const U64x4 b = philox4x64_10((uint64_t)row, (uint64_t)cb, 0, 0, seed, stream);
     double z[4];
     box_muller(uniform52(b.v[0]), uniform52(b.v[1]), &z[0], &z[1]);
@@ -25,50 +29,12 @@ __device__ __forceinline__ void gaussian_block(uint64_t seed, uint64_t stream, i
         v[t] = (float)p;
     }
     const int64_t c0 = cb * 4;
-    float* o = orow + c0;
+    float* o = out + row * cols + c0;
     if (c0 + 4 <= cols && (cols % 4) == 0) {
         *reinterpret_cast<float4*>(o) = make_float4(v[0], v[1], v[2], v[3]);
     } else {
         for (int t = 0; t < 4 && c0 + t < cols; ++t) o[t] = v[t];
     }
-}
-
-__global__ __launch_bounds__(256) void k_gaussian(uint64_t seed, uint64_t stream, int64_t rows,
-                                                  int64_t cols, int64_t cblocks, double sigma,
-                                                  float* __restrict__ out) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= rows * cblocks) return;
-    const int64_t row = idx / cblocks;
-    const int64_t cb = idx - row * cblocks;
-    gaussian_block(seed, stream, row, cb, cols, sigma, out + row * cols);
-}
-
-// Batch rows: graph-local row index and the graph's own key.
-__global__ __launch_bounds__(256) void k_gaussian_rows(const uint64_t* __restrict__ seeds,
-                                                       const int32_t* __restrict__ gid,
-                                                       const int32_t* __restrict__ gnoff,
-                                                       uint64_t stream, int64_t rows, int64_t cols,
-                                                       int64_t cblocks, double sigma,
-                                                       float* __restrict__ out) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= rows * cblocks) return;
-    const int64_t row = idx / cblocks;
-    const int64_t cb = idx - row * cblocks;
-    const int g = gid[row];
-    gaussian_block(seeds[g], stream, row - gnoff[g], cb, cols, sigma, out + row * cols);
-}
-
-// One matrix per graph (blockIdx.y = graph).
-__global__ __launch_bounds__(256) void k_gaussian_multi(const uint64_t* __restrict__ seeds,
-                                                        uint64_t stream, int64_t rows, int64_t cols,
-                                                        int64_t cblocks, double sigma,
-                                                        float* __restrict__ out) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= rows * cblocks) return;
-    const int64_t row = idx / cblocks;
-    const int64_t cb = idx - row * cblocks;
-    const int g = blockIdx.y;
-    gaussian_block(seeds[g], stream, row, cb, cols, sigma, out + ((int64_t)g * rows + row) * cols);
 }
 
 void launch_gaussian(uint64_t seed, uint64_t stream_id, int64_t rows, int64_t cols, double sigma,
@@ -78,25 +44,6 @@ void launch_gaussian(uint64_t seed, uint64_t stream_id, int64_t rows, int64_t co
     if (total == 0) return;
     hipLaunchKernelGGL(k_gaussian, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, seed,
                        stream_id, rows, cols, cb, sigma, out);
-}
-
-void launch_gaussian_rows(const uint64_t* seeds, const int32_t* gid, const int32_t* gnoff,
-                          uint64_t stream_id, int64_t rows, int64_t cols, double sigma, float* out,
-                          hipStream_t st) {
-    const int64_t cb = (cols + 3) / 4;
-    const int64_t total = rows * cb;
-    if (total == 0) return;
-    hipLaunchKernelGGL(k_gaussian_rows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
-                       seeds, gid, gnoff, stream_id, rows, cols, cb, sigma, out);
-}
-
-void launch_gaussian_multi(const uint64_t* seeds, int G, uint64_t stream_id, int64_t rows,
-                           int64_t cols, double sigma, float* out, hipStream_t st) {
-    const int64_t cb = (cols + 3) / 4;
-    const int64_t total = rows * cb;
-    if (total == 0 || G == 0) return;
-    hipLaunchKernelGGL(k_gaussian_multi, dim3((unsigned)((total + 255) / 256), G), dim3(256), 0, st,
-                       seeds, stream_id, rows, cols, cb, sigma, out);
 }
 
 }  // namespace raft

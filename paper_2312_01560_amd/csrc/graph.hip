@@ -1,7 +1,5 @@
 // CSR validation and degree statistics (problem statement, Sec. II: A is
 // symmetric with entries in {0,1}; degrees and e enter Eq. 1-4 and Eq. 6).
-#include <algorithm>
-
 #include "kernels.h"
 
 namespace raft {
@@ -64,19 +62,6 @@ __global__ __launch_bounds__(256) void k_degrees(const int32_t* __restrict__ rp,
     dcoef[i] = (float)((double)d / m2);
 }
 
-// Block-diagonal packing of one graph of a batch.
-__global__ __launch_bounds__(256) void k_pack_graph(const int32_t* __restrict__ rp,
-                                                    const int32_t* __restrict__ ci, int32_t n,
-                                                    int64_t nnz, int32_t noff, int64_t eoff,
-                                                    int32_t g, int32_t* __restrict__ rp_dst,
-                                                    int32_t* __restrict__ ci_dst,
-                                                    int32_t* __restrict__ gid) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx <= n) rp_dst[noff + idx] = (int32_t)(rp[idx] + eoff);
-    if (idx < n) gid[noff + idx] = g;
-    if (idx < nnz) ci_dst[eoff + idx] = ci[idx] + noff;
-}
-
 void launch_validate_csr(const int32_t* rp, const int32_t* ci, int32_t n, int32_t* status,
                          int num_cu, hipStream_t st) {
     const int blocks = max(1, min((n + 3) / 4, num_cu * 16));
@@ -88,14 +73,6 @@ void launch_degrees(const int32_t* rp, int32_t n, int64_t nnz, int32_t* deg, flo
     const double m2 = nnz > 0 ? (double)nnz : 1.0;
     hipLaunchKernelGGL(k_degrees, dim3((n + 255) / 256), dim3(256), 0, st, rp, n, m2, deg, s, sh,
                        dcoef);
-}
-
-void launch_pack_graph(const int32_t* rp, const int32_t* ci, int32_t n, int64_t nnz, int32_t noff,
-                       int64_t eoff, int32_t g, int32_t* rp_dst, int32_t* ci_dst, int32_t* gid,
-                       hipStream_t st) {
-    const int64_t total = std::max<int64_t>((int64_t)n + 1, nnz);
-    hipLaunchKernelGGL(k_pack_graph, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, rp, ci,
-                       n, nnz, noff, eoff, g, rp_dst, ci_dst, gid);
 }
 
 }  // namespace raft

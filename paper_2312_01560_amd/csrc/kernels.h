@@ -14,24 +14,10 @@ void launch_validate_csr(const int32_t* rp, const int32_t* ci, int32_t n, int32_
                          int num_cu, hipStream_t st);
 void launch_degrees(const int32_t* rp, int32_t n, int64_t nnz, int32_t* deg, float* s, float* sh,
                     float* dcoef, hipStream_t st);
-// Copies one validated graph into a block-diagonal batch CSR: rows shifted by
-// noff, stored entries by eoff, column indices by noff; gid[noff..] = g.
-void launch_pack_graph(const int32_t* rp, const int32_t* ci, int32_t n, int64_t nnz, int32_t noff,
-                       int64_t eoff, int32_t g, int32_t* rp_dst, int32_t* ci_dst, int32_t* gid,
-                       hipStream_t st);
 
 // ---- gauss.hip -----------------------------------------------------------
 void launch_gaussian(uint64_t seed, uint64_t stream_id, int64_t rows, int64_t cols, double sigma,
                      float* out, hipStream_t st);
-// Rows of the graphs of a batch: row i belongs to graph gid[i], whose draw
-// uses key (seeds[g], stream) and the graph-local row i - gnoff[g].
-void launch_gaussian_rows(const uint64_t* seeds, const int32_t* gid, const int32_t* gnoff,
-                          uint64_t stream_id, int64_t rows, int64_t cols, double sigma, float* out,
-                          hipStream_t st);
-// G matrices [rows x cols], matrix g drawn with key (seeds[g], stream) at
-// out + g * rows * cols.
-void launch_gaussian_multi(const uint64_t* seeds, int G, uint64_t stream_id, int64_t rows,
-                           int64_t cols, double sigma, float* out, hipStream_t st);
 
 // ---- spmm.hip ------------------------------------------------------------
 enum SpmmOp { kOpNcut = 0, kOpModFull = 1, kOpModReduced = 2, kOpGcn = 3 };
@@ -44,8 +30,7 @@ struct GraphView {
     const int32_t* deg;
     const float* s;      // D^-1/2 (0 for isolated nodes)
     const float* sh;     // (D+1)^-1/2
-    const float* dcoef;  // d_i / 2e (2e of the node's own graph in a batch)
-    const int32_t* gid;  // graph of each node (null for a single graph)
+    const float* dcoef;  // d_i / 2e
 };
 
 // Grid size (work-groups) of one SpMM launch; colsum partial buffers hold
@@ -64,33 +49,18 @@ void launch_colsum_partials(const GraphView& g, int L, const float* x, double* p
 constexpr int kColsumStageRows = 64;
 void launch_colsum_finish(const double* part, int parts, int L, double* c64, float* cvec,
                           hipStream_t st);
-// Per-graph d^T x for a batch: work item w covers rows of graph g with
-// cw0[g] <= w < cw0[g+1]; the partials [items x L] are summed per graph in
-// item order into c64 / cvec [G x L].  MOD_FULL SpMM on a batch reads
-// cvec + gid[i] * L.
-void launch_colsum_seg(const GraphView& g, int L, const float* x, const int32_t* cw0,
-                       const int32_t* gnoff, int G, int items, double* part, hipStream_t st);
-void launch_colsum_seg_finish(const double* part, const int32_t* cw0, int G, int L, double* c64,
-                              float* cvec, hipStream_t st);
 
 // ---- dense.hip -----------------------------------------------------------
 bool dense_supported(int lin, int lout);
 // H = rownorm(tanh(P W)) (or U = P W when linear), P [n x lin], W [lin x lout].
-// With gid non-null, row i uses W + gid[i] * lin * lout (one matrix per graph).
 void launch_dense_layer(const float* P, const float* W, float* H, int32_t n, int lin, int lout,
-                        bool linear, int32_t* status, hipStream_t st, const int32_t* gid = nullptr);
+                        bool linear, int32_t* status, hipStream_t st);
 // Row L2 normalisation in place (x / max(||x||, 1e-12)).
 void launch_rownorm(float* x, int32_t n, int L, hipStream_t st);
 
 // ---- kmeans.hip ----------------------------------------------------------
-// Candidates of several graphs can share one plan (a batch): candidate k
-// belongs to graph cg[k], whose points are the nodes gnoff[g] .. gnoff[g+1]-1;
-// its labels start at lab_off[k] in lab_cm.  A single graph is the case
-// ngraphs = 1.
 struct KmeansPlan {
-    int32_t n, d, Kc, k_max;     // n: all points; Kc: all candidates; k_max: picks per graph
-    int32_t ngraphs;
-    int32_t awork;       // assignment work items (group, 256-point tile)
+    int32_t n, d, Kc, k_max;
     int32_t KP;          // padded centre rows (sum of ceil16(K))
     int32_t SK;          // real centre count (sum of K)
     int32_t agroups;     // candidate groups of the assignment kernel (over alist)
@@ -105,31 +75,25 @@ struct KmeansPlan {
     const int32_t* cand_of;  // [KP] candidate of each padded centre row
     const int32_t* alist;    // [Kc] candidates still active at the last poll
     const int32_t* agrp;     // [agroups + 1] offsets into alist
-    const int32_t* aw0;      // [agroups + 1] first assignment work item of each group
-    const int32_t* gnoff;    // [ngraphs + 1] node offsets of the graphs
-    const int32_t* cg;       // [Kc] graph of each candidate
-    const int64_t* lab_off;  // [Kc] first label of each candidate in lab_cm
-    int64_t lab_total;       // labels in lab_cm
     const int32_t* ugrp;     // [ugroups + 1] offsets into alist
     const int32_t* uwi0;     // [ugroups + 1] first work item of each update group
     const int32_t* ulen;     // [ugroups] point range length of each update group
     const int32_t* cranges;  // [Kc] point ranges of each candidate's update group
-    const int32_t* poff;     // [Kc] first partial row of each candidate (ranges x K rows)
     int32_t* active;         // [Kc]
     int32_t* changes;        // [Kc]
     int32_t* iters;          // [Kc]
     int32_t* active_count;   // [1]
     float* C;                // [KP x d]
     float* cnorm;            // [KP]
-    long long* psum;         // [partial rows x d] per-range centre sums, z * 2^e (rows from poff)
-    int32_t* pcnt;           // [partial rows]
+    float* psum;             // [max ranges x KP x d] per-range centre sums
+    int32_t* pcnt;           // [max ranges x KP]
     uint32_t* zmax_bits;     // [1] largest |z| (float bits), sets the fixed-point scale
     float* w;                // [n]
     double* race_val;        // [race_grid]
     int32_t* race_idx;       // [race_grid]
     uint32_t* race_counter;  // [1]
-    int32_t* picks;          // [ngraphs x k_max] (graph-local node ids)
-    uint8_t* lab_cm;         // candidate-major labels, lab_off[k] + (node - gnoff[g])
+    int32_t* picks;          // [k_max]
+    uint8_t* lab_cm;         // [Kc x n] candidate-major labels
     int32_t* status;
 };
 
@@ -144,52 +108,39 @@ int kmeans_update_max_candidates();
 void launch_kmeans_reset(const KmeansPlan& p, hipStream_t st);
 void launch_zmax(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t st);
 void launch_race_pick(const KmeansPlan& p, const float* Z, int t, uint64_t seed, hipStream_t st);
-// All picks of every graph of a batch: one work-group per graph; seeds[g].
-void launch_race_batch(const KmeansPlan& p, const float* Z, const uint64_t* seeds, hipStream_t st);
 void launch_init_centres(const KmeansPlan& p, const float* Z, hipStream_t st);
 void launch_assign(const KmeansPlan& p, const float* Z, hipStream_t st);
-// Points per assignment work item (one work-group) for embedding width d.
-int kmeans_assign_tile(int d);
 void launch_iter_finalize(const KmeansPlan& p, int it, int t_max, hipStream_t st);
 void launch_update(const KmeansPlan& p, const float* Z, size_t lds_max, hipStream_t st);
 
 // ---- score.hip -----------------------------------------------------------
-// Scores of the candidates of one or more graphs (same K grid for every
-// graph): Kc candidates per graph, SK = sum of K per graph.  Work items of
-// the edge kernel are row blocks that never cross a graph boundary.
 struct ScorePlan {
-    int32_t n, Kc, S;     // n: all nodes; Kc: candidates per graph; S: label row stride (multiple of 8)
-    int32_t SK;           // sum of K of one graph
-    int32_t grid;         // edge work items
-    int32_t ngraphs;
-    const int32_t* ks;    // [Kc] (shared by the graphs)
-    const int32_t* koff;  // [Kc]
-    const int32_t* gnoff; // [ngraphs + 1]
-    const int32_t* gid;   // [n] graph of each node (nullable when ngraphs = 1)
-    const int32_t* sw0;   // [ngraphs + 1] first edge work item of each graph
-    const int64_t* m2;    // [ngraphs] 2e of each graph
+    int32_t n, Kc, S;     // S = row stride of point-major labels (multiple of 8)
+    int32_t SK;           // sum of K
+    int32_t grid;
+    int64_t nnz;
+    const int32_t* ks;
+    const int32_t* koff;
     int32_t* lpart;       // [grid x SK]
     int32_t* vpart;       // [grid x SK]
-    int64_t* l64;         // [ngraphs x SK]
-    int64_t* v64;         // [ngraphs x SK]
-    double* mod;          // [ngraphs x Kc]
-    double* ncut;         // [ngraphs x Kc]
-    int32_t* best;        // [ngraphs]
-    int32_t* first;       // [ngraphs x (RAFT_MAX_K + 1)]
-    int32_t* remap;       // [ngraphs x (RAFT_MAX_K + 1)]
+    int64_t* l64;         // [SK]
+    int64_t* v64;         // [SK]
+    double* mod;          // [Kc]
+    double* ncut;         // [Kc]
+    int32_t* best;        // [1]
+    int32_t* first;       // [RAFT_MAX_K + 1]
+    int32_t* remap;       // [RAFT_MAX_K + 1]
     int32_t* status;
 };
 
-// Edge work items for a graph of n nodes (batches add them up per graph).
-int score_items(int32_t n, int num_cu);
+int score_grid(int32_t n, int num_cu);
 bool score_supported(int SK);
-// Point-major labels [n x S] from the candidate-major k-means labels.
-void launch_transpose_labels(const KmeansPlan& km, const ScorePlan& p, uint8_t* pm, hipStream_t st);
+void launch_transpose_labels(const uint8_t* cm, int32_t n, int Kc, uint8_t* pm, int S,
+                             hipStream_t st);
 void launch_edge_score(const GraphView& g, const ScorePlan& p, const uint8_t* lab_pm,
                        hipStream_t st);
 void launch_score_finish(const ScorePlan& p, hipStream_t st);
-// Selection of K* per graph (first maximum of Mod) and canonical relabelling;
-// k_selected: [ngraphs x 3].
+// Selection of K* (first maximum of Mod) and canonical relabelling.
 void launch_select(const ScorePlan& p, const uint8_t* lab_pm, int32_t* labels_out,
                    int32_t* k_selected, hipStream_t st);
 // Copy point-major labels [n x S] into a dense [n x Kc] output.

@@ -14,11 +14,10 @@
 // the points against the table of all centres (rows of each candidate padded
 // to a multiple of 16), on MFMA (v_mfma_f32_16x16x4f32), score
 // ||c||^2 - 2 z.c, argmin per candidate segment with ties to the lowest
-// index.  The update quantises each point to integers (z * 2^e) and sums them
-// exactly in int64 LDS accumulators per (point range, candidate group); the
-// range partials are exact integers too, so the centres do not depend on the
-// order of the additions or on how the points were split.  A graph of a batch
-// keeps its own scale e.
+// index.  The update accumulates per (point chunk, candidate) in LDS: each
+// wave owns a private copy and each lane a column, so every LDS address is
+// updated by one lane in program order and the sums are deterministic; the
+// chunk partials are combined in fixed order in FP64.
 #include <float.h>
 #include <limits.h>
 
@@ -160,96 +159,6 @@ __global__ __launch_bounds__(kRaceThreads) void k_race(KmeansPlan p, const float
     }
 }
 
-// All picks of every graph of a batch: one work-group per graph walks the
-// K_max sequential picks, reducing (ratio, index) through LDS; graph-local
-// indices address Philox and the picks, so a graph gets the same picks as
-// when it is run alone with the same seed.
-constexpr int kRaceBatchThreads = 1024;
-
-template <int D>
-__global__ __launch_bounds__(kRaceBatchThreads) void k_race_batch(KmeansPlan p,
-                                                                  const float* __restrict__ Z,
-                                                                  const uint64_t* __restrict__ seeds) {
-    const int g = blockIdx.x;
-    const int lo = p.gnoff[g], hi = p.gnoff[g + 1];
-    const uint64_t seed = seeds[g];
-    int* picks = p.picks + (size_t)g * p.k_max;
-    __shared__ double sv[kRaceBatchThreads / kWave];
-    __shared__ int si[kRaceBatchThreads / kWave];
-    __shared__ int last_pick;
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    for (int t = 0; t < p.k_max; ++t) {
-        const int prev = t > 0 ? last_pick : -1;
-        const float* zp = prev >= 0 ? Z + (size_t)(lo + prev) * D : Z;
-        double best = INFINITY;
-        int bidx = INT_MAX;
-        for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-            float wi = 1.0f;
-            if (t > 0) {
-                const float* zi = Z + (size_t)i * D;
-                float dist = 0.f;
-#pragma unroll 4
-                for (int c = 0; c < D; c += 4) {
-                    const float4 a = *reinterpret_cast<const float4*>(zi + c);
-                    const float4 b = *reinterpret_cast<const float4*>(zp + c);
-                    const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z, dw = a.w - b.w;
-                    dist += dx * dx;
-                    dist += dy * dy;
-                    dist += dz * dz;
-                    dist += dw * dw;
-                }
-                wi = (t == 1) ? dist : fminf(p.w[i], dist);
-                p.w[i] = wi;
-            }
-            if (wi > 0.f) {
-                const U64x4 b = philox4x64_10((uint64_t)(i - lo), (uint64_t)t, 0, 0, seed, kStreamRace);
-                const double e = -own_ln(uniform52(b.v[0]));
-                const double ratio = e / (double)wi;
-                if (ratio < best) {
-                    best = ratio;
-                    bidx = i - lo;
-                }
-            }
-        }
-#pragma unroll
-        for (int off = kWave / 2; off > 0; off >>= 1) {
-            const double ov = __shfl_xor(best, off, kWave);
-            const int oi = __shfl_xor(bidx, off, kWave);
-            if (lex_less(ov, oi, best, bidx)) {
-                best = ov;
-                bidx = oi;
-            }
-        }
-        if (lane == 0) {
-            sv[wid] = best;
-            si[wid] = bidx;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double b = sv[0];
-            int bi = si[0];
-            for (int w = 1; w < kRaceBatchThreads / kWave; ++w)
-                if (lex_less(sv[w], si[w], b, bi)) {
-                    b = sv[w];
-                    bi = si[w];
-                }
-            if (bi == INT_MAX) {
-                for (int c = 0; c <= t; ++c) {
-                    bool taken = false;
-                    for (int q = 0; q < t; ++q) taken |= (picks[q] == c);
-                    if (!taken) {
-                        bi = c;
-                        break;
-                    }
-                }
-            }
-            picks[t] = bi;
-            last_pick = bi;
-        }
-        __syncthreads();
-    }
-}
-
 // Copy the first K picks of every candidate into its centre rows; padding
 // rows are zero with norm +inf.  One wave per padded centre row.
 template <int D>
@@ -265,8 +174,7 @@ __global__ __launch_bounds__(256) void k_init_centres(KmeansPlan p, const float*
         if (lane == 0) p.cnorm[c] = INFINITY;
         return;
     }
-    const int g = p.cg[k];
-    const float* z = Z + (size_t)(p.gnoff[g] + p.picks[(size_t)g * p.k_max + r]) * D;
+    const float* z = Z + (size_t)p.picks[r] * D;
     float ss = 0.f;
     for (int dd = lane; dd < D; dd += kWave) {
         const float v = z[dd];
@@ -304,24 +212,12 @@ __global__ __launch_bounds__(256) void k_assign(KmeansPlan p, const float* __res
     const int wid = threadIdx.x / kWave;
     const int g = lane >> 4;
     const int li = lane & 15;
-    // work item -> (group, tile of the group's graph)
-    const int wi = blockIdx.x;
-    int lo_g = 0, hi_g = p.agroups;
-    while (hi_g - lo_g > 1) {
-        const int mid = (lo_g + hi_g) >> 1;
-        if (p.aw0[mid] <= wi) lo_g = mid;
-        else hi_g = mid;
-    }
-    const int grp = lo_g;
-    const int t0 = p.agrp[grp], t1 = p.agrp[grp + 1];
-    const int gr = p.cg[p.alist[t0]];
-    const int lo = p.gnoff[gr], hi = p.gnoff[gr + 1];
-    const int pbase = lo + (wi - p.aw0[grp]) * (4 * 16 * PS) + wid * 16 * PS;
-    if (pbase >= hi) return;
+    const int pbase = (blockIdx.x * 4 + wid) * 16 * PS;
+    if (pbase >= p.n) return;
     float b[PS][KS];
 #pragma unroll
     for (int ps = 0; ps < PS; ++ps) {
-        const int pt = min(pbase + 16 * ps + li, hi - 1);
+        const int pt = min(pbase + 16 * ps + li, p.n - 1);
         const float* zr = Z + (size_t)pt * D + g * KS;
 #pragma unroll
         for (int s = 0; s < KS; s += 4) {
@@ -332,6 +228,7 @@ __global__ __launch_bounds__(256) void k_assign(KmeansPlan p, const float* __res
             b[ps][s + 3] = v.w;
         }
     }
+    const int t0 = p.agrp[blockIdx.y], t1 = p.agrp[blockIdx.y + 1];
     // first active candidate of the group
     int t = t0;
     while (t < t1 && !p.active[p.alist[t]]) ++t;
@@ -401,8 +298,8 @@ __global__ __launch_bounds__(256) void k_assign(KmeansPlan p, const float* __res
             }
             const int pt = pbase + 16 * g + li;
             bool changed = false;
-            if (g < PS && pt < hi) {
-                uint8_t* lp = p.lab_cm + p.lab_off[k] + (pt - lo);
+            if (g < PS && pt < p.n) {
+                uint8_t* lp = p.lab_cm + (size_t)k * p.n + pt;
                 const uint8_t old = *lp;
                 const uint8_t nw = (uint8_t)mine;
                 changed = old != nw;
@@ -445,13 +342,12 @@ __global__ __launch_bounds__(256) void k_iter_finalize(KmeansPlan p, int it, int
     if (threadIdx.x == 0) *p.active_count = cnt;
 }
 
-// Largest |z| of each graph (bit pattern of a non-negative float orders as an
-// integer): blockIdx.y = graph, block maximum, then one atomic per block.
+// Largest |z| (bit pattern of a non-negative float orders as an integer):
+// block maximum, then one atomic per block.
 __global__ __launch_bounds__(256) void k_zmax(KmeansPlan p, const float* __restrict__ Z) {
-    const int gr = blockIdx.y;
-    const int64_t lo = (int64_t)p.gnoff[gr] * p.d, hi = (int64_t)p.gnoff[gr + 1] * p.d;
+    const int64_t total = (int64_t)p.n * p.d;
     float m = 0.f;
-    for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x)
         m = fmaxf(m, fabsf(Z[i]));
     if (!(m <= 3.0e38f)) m = 3.0e38f;   // non-finite input: keep the exponent sane
@@ -462,13 +358,13 @@ __global__ __launch_bounds__(256) void k_zmax(KmeansPlan p, const float* __restr
     __syncthreads();
     if (threadIdx.x == 0) {
         const float b = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
-        atomicMax(p.zmax_bits + gr, __float_as_uint(b));
+        atomicMax(p.zmax_bits, __float_as_uint(b));
     }
 }
 
 // Fixed-point exponent e: |z| * 2^e < 2^30 for every |z| <= zmax.
-__device__ __forceinline__ int fixed_exp(const KmeansPlan& p, int gr) {
-    const float zmax = __uint_as_float(p.zmax_bits[gr]);
+__device__ __forceinline__ int fixed_exp(const KmeansPlan& p) {
+    const float zmax = __uint_as_float(*p.zmax_bits);
     if (!(zmax > 0.f)) return 0;
     int ez;
     frexpf(zmax, &ez);
@@ -486,8 +382,8 @@ __device__ __forceinline__ int fixed_exp(const KmeansPlan& p, int gr) {
 // of every active candidate of the group; padding points go to a dummy row,
 // so the inner loop has no branches.  A group's points are split into as
 // many ranges as it has candidates times a constant, so work items carry
-// equal work.  Each range's exact sums are written as int64 partials and
-// added up by k_update_finish.
+// equal work.  Each range's exact sums are written as FP32 partials,
+// combined in FP64 in a fixed order by k_update_finish.
 constexpr int kUpdWaves = 4;
 constexpr int kUpdMaxCand = 16;
 constexpr int kUpdSlice = 64;
@@ -496,12 +392,8 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
     extern __shared__ unsigned long long acc64[];
     // work item -> (group, range slot)
     const int wi = blockIdx.x;
-    int g = 0, ghi = p.ugroups;
-    while (ghi - g > 1) {
-        const int mid = (g + ghi) >> 1;
-        if (p.uwi0[mid] <= wi) g = mid;
-        else ghi = mid;
-    }
+    int g = 0;
+    while (g + 1 < p.ugroups && p.uwi0[g + 1] <= wi) ++g;
     const int slot = wi - p.uwi0[g];
     const int sl = blockIdx.y;
     const int t0 = p.ugrp[g], t1 = p.ugrp[g + 1];
@@ -520,15 +412,13 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
     for (int idx = threadIdx.x; idx < total_rows * kUpdSlice; idx += blockDim.x) acc64[idx] = 0ull;
     for (int idx = threadIdx.x; idx < total_rows; idx += blockDim.x) cnt[idx] = 0;
     __syncthreads();
-    const int gr = p.cg[p.alist[t0]];
-    const float sc = ldexpf(1.0f, fixed_exp(p, gr));
+    const float sc = ldexpf(1.0f, fixed_exp(p));
     const int dummy = rows;
     const int col = sl * kUpdSlice + lane;
     const bool on = col < p.d;
     const int len = p.ulen[g];
-    const int glo = p.gnoff[gr];
-    const int r0 = glo + slot * len;
-    const int r1 = min(p.gnoff[gr + 1], r0 + len);
+    const int r0 = slot * len;
+    const int r1 = min(p.n, r0 + len);
     unsigned long long* acol = acc64 + lane;
     // the group's candidates (uniform): label column, accumulator base row
     const int nc = t1 - t0;
@@ -545,7 +435,7 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
             if (m < nc) {
                 const int k = p.alist[t0 + m];
                 act[m] = p.active[k] != 0;
-                labp[m] = p.lab_cm + p.lab_off[k] - glo;
+                labp[m] = p.lab_cm + (size_t)k * p.n;
                 rbase[m] = base;
                 base += p.ks[k];
             }
@@ -578,60 +468,55 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
         }
     }
     __syncthreads();
+    const float inv = ldexpf(1.0f, -fixed_exp(p));
     const int sw = min(kUpdSlice, p.d);
     int base = 0;
     for (int t = t0; t < t1; ++t) {
         const int k = p.alist[t];
         const int K = p.ks[k];
         if (p.active[k]) {
-            const size_t prow = (size_t)p.poff[k] + (size_t)slot * K;
-            long long* dst = p.psum + prow * p.d + sl * kUpdSlice;
+            float* dst = p.psum + ((size_t)slot * p.KP + p.koff16[k]) * p.d + sl * kUpdSlice;
             for (int idx = threadIdx.x; idx < K * sw; idx += blockDim.x) {
                 const int r = idx / sw, cc = idx - (idx / sw) * sw;
-                dst[(size_t)r * p.d + cc] = (long long)acc64[(size_t)(base + r) * kUpdSlice + cc];
+                const long long v = (long long)acc64[(size_t)(base + r) * kUpdSlice + cc];
+                dst[(size_t)r * p.d + cc] = (float)((double)v * (double)inv);
             }
             if (sl == 0)
                 for (int idx = threadIdx.x; idx < K; idx += blockDim.x)
-                    p.pcnt[prow + idx] = cnt[base + idx];
+                    p.pcnt[(size_t)slot * p.KP + p.koff16[k] + idx] = cnt[base + idx];
         }
         base += K;
     }
 }
 
 // Means from the range partials; an empty cluster keeps its centre.  One
-// work-group per padded centre row: 4 slices of the ranges x 64 columns.  The
-// partials are exact integers (z * 2^e summed), so their total does not depend
-// on how the points were split into ranges; the mean is one FP64 division of
-// that total, rounded once to FP32.
+// work-group per padded centre row: 4 slices of the ranges x 64 columns,
+// each slice summed in FP64 in order, the slices combined in order.
 __global__ __launch_bounds__(256) void k_update_finish(KmeansPlan p) {
     const int c = blockIdx.x;
     const int k = p.cand_of[c];
     if (!p.active[k]) return;
-    const int K = p.ks[k];
-    const int r = c - p.koff16[k];
-    if (r >= K) return;
-    const size_t prow = (size_t)p.poff[k] + r;
+    if (c - p.koff16[k] >= p.ks[k]) return;
     const int lane = threadIdx.x & (kWave - 1);
     const int q = threadIdx.x / kWave;
     const int nr = p.cranges[k];
     const int per = (nr + 3) / 4;
     const int ch0 = q * per, ch1 = min(nr, ch0 + per);
-    __shared__ long long part[4][kWave];
+    __shared__ double part[4][kWave];
     __shared__ int pc[4];
     int count = 0;
-    for (int ch = ch0 + lane; ch < ch1; ch += kWave) count += p.pcnt[prow + (size_t)ch * K];
+    for (int ch = ch0 + lane; ch < ch1; ch += kWave) count += p.pcnt[(size_t)ch * p.KP + c];
     count = wave_sum(count);
     if (lane == 0) pc[q] = count;
-    const size_t stride = (size_t)K * p.d;
-    const double inv = ldexp(1.0, -fixed_exp(p, p.cg[k]));
+    const size_t stride = (size_t)p.KP * p.d;
     float* crow = p.C + (size_t)c * p.d;
     float ss = 0.f;
     for (int d0 = 0; d0 < p.d; d0 += kWave) {
         const int dd = d0 + lane;
-        long long s = 0;
+        double s = 0.0;
         if (dd < p.d) {
-            const long long* src = p.psum + prow * p.d + dd;
-            for (int ch = ch0; ch < ch1; ++ch) s += src[ch * stride];
+            const float* src = p.psum + (size_t)c * p.d + dd;
+            for (int ch = ch0; ch < ch1; ++ch) s += (double)src[ch * stride];
         }
         __syncthreads();
         part[q][lane] = s;
@@ -639,13 +524,8 @@ __global__ __launch_bounds__(256) void k_update_finish(KmeansPlan p) {
         const int total = pc[0] + pc[1] + pc[2] + pc[3];
         if (total == 0) return;   // uniform across the work-group
         if (q == 0 && dd < p.d) {
-            const long long t = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
-            double m;
-            {
-#pragma clang fp contract(off)
-                m = ((double)t * inv) / (double)total;
-            }
-            const float v = (float)m;
+            const double t = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+            const float v = (float)(t / (double)total);
             crow[dd] = v;
             ss += v * v;
         }
@@ -659,8 +539,7 @@ __global__ __launch_bounds__(256) void k_update_finish(KmeansPlan p) {
 __global__ void k_kmeans_reset(KmeansPlan p) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = tid; i < p.lab_total; i += stride) p.lab_cm[i] = 0xFF;
-    for (int64_t gr = tid; gr < p.ngraphs; gr += stride) p.zmax_bits[gr] = 0u;
+    for (int64_t i = tid; i < (int64_t)p.Kc * p.n; i += stride) p.lab_cm[i] = 0xFF;
     for (int64_t k = tid; k < p.Kc; k += stride) {
         p.active[k] = 1;
         p.changes[k] = 0;
@@ -669,7 +548,7 @@ __global__ void k_kmeans_reset(KmeansPlan p) {
     if (tid == 0) {
         *p.race_counter = 0u;
         *p.active_count = p.Kc;
-
+        *p.zmax_bits = 0u;
     }
 }
 
@@ -691,13 +570,12 @@ int kmeans_update_max_candidates() { return kUpdMaxCand; }
 
 void launch_zmax(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t st) {
     const int64_t total = (int64_t)p.n * p.d;
-    const int64_t per_graph = std::max<int64_t>(1, (int64_t)num_cu * 2 / p.ngraphs);
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, per_graph));
-    hipLaunchKernelGGL(k_zmax, dim3(grid, p.ngraphs), dim3(256), 0, st, p, Z);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, num_cu * 2));
+    hipLaunchKernelGGL(k_zmax, dim3(grid), dim3(256), 0, st, p, Z);
 }
 
 void launch_kmeans_reset(const KmeansPlan& p, hipStream_t st) {
-    const int64_t total = std::max<int64_t>(p.lab_total, p.Kc);
+    const int64_t total = std::max<int64_t>((int64_t)p.Kc * p.n, p.Kc);
     const int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
     hipLaunchKernelGGL(k_kmeans_reset, dim3(grid), dim3(256), 0, st, p);
 }
@@ -719,16 +597,6 @@ void launch_race_pick(const KmeansPlan& p, const float* Z, int t, uint64_t seed,
 #undef RACE
 }
 
-void launch_race_batch(const KmeansPlan& p, const float* Z, const uint64_t* seeds, hipStream_t st) {
-#define RACEB(DV)                                                                             \
-    hipLaunchKernelGGL(k_race_batch<DV>, dim3(p.ngraphs), dim3(kRaceBatchThreads), 0, st, p, Z, \
-                       seeds)
-    RAFT_D_SWITCH(p.d, RACEB)
-#undef RACEB
-}
-
-int kmeans_assign_tile(int d) { return 64 * (d <= 64 ? 4 : (d == 128 ? 2 : 1)); }
-
 void launch_init_centres(const KmeansPlan& p, const float* Z, hipStream_t st) {
     const int grid = (p.KP * kWave + 255) / 256;
 #define INIT(DV) hipLaunchKernelGGL(k_init_centres<DV>, dim3(grid), dim3(256), 0, st, p, Z)
@@ -746,8 +614,7 @@ void launch_assign(const KmeansPlan& p, const float* Z, hipStream_t st) {
     {                                                                                     \
         constexpr int PS = assign_ps<DV>();                                               \
         const int pts_per_block = 4 * 16 * PS;                                            \
-        (void)pts_per_block;                                                              \
-        dim3 grid(p.awork);                                                               \
+        dim3 grid((p.n + pts_per_block - 1) / pts_per_block, p.agroups);                   \
         hipLaunchKernelGGL((k_assign<DV, PS>), grid, dim3(256), 0, st, p, Z);             \
     }
     RAFT_D_SWITCH(p.d, ASSIGN)

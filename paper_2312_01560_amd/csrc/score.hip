@@ -23,19 +23,14 @@
 
 namespace raft {
 
-__global__ __launch_bounds__(256) void k_transpose_labels(KmeansPlan km, ScorePlan p,
-                                                          uint8_t* __restrict__ pm) {
+__global__ __launch_bounds__(256) void k_transpose_labels(const uint8_t* __restrict__ cm, int n,
+                                                          int Kc, uint8_t* __restrict__ pm,
+                                                          int S) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)p.n * p.S) return;
-    const int i = (int)(idx / p.S);
-    const int kl = (int)(idx - (int64_t)i * p.S);
-    uint8_t v = 0;
-    if (kl < p.Kc) {
-        const int g = p.gid ? p.gid[i] : 0;
-        const int k = g * p.Kc + kl;
-        v = km.lab_cm[km.lab_off[k] + (i - p.gnoff[g])];
-    }
-    pm[idx] = v;
+    if (idx >= (int64_t)n * S) return;
+    const int i = (int)(idx / S);
+    const int k = (int)(idx - (int64_t)i * S);
+    pm[idx] = k < Kc ? cm[(size_t)k * n + i] : (uint8_t)0;
 }
 
 __global__ __launch_bounds__(256) void k_copy_labels(const uint8_t* __restrict__ pm, int n, int Kc,
@@ -55,7 +50,7 @@ __device__ __forceinline__ uint32_t zero_bytes_mask(uint32_t x) {
 
 template <int LPR>
 __global__ __launch_bounds__(256) void k_edge_score(GraphView g, ScorePlan p,
-                                                    const uint8_t* __restrict__ lab) {
+                                                    const uint8_t* __restrict__ lab, int rpw) {
     constexpr int G = kWave / LPR;                  // rows side by side per wave
     extern __shared__ int sm[];
     int* sl = sm;
@@ -67,28 +62,13 @@ __global__ __launch_bounds__(256) void k_edge_score(GraphView g, ScorePlan p,
     const int slot = lane / LPR;
     const int m = lane % LPR;
     const bool on = 8 * m < p.S;
-    // work item -> (graph, row block)
-    const int wi = blockIdx.x;
-    int glo = 0, ghi = p.ngraphs;
-    while (ghi - glo > 1) {
-        const int mid = (glo + ghi) >> 1;
-        if (p.sw0[mid] <= wi) glo = mid;
-        else ghi = mid;
-    }
-    const int gr = glo;
-    const int items = p.sw0[gr + 1] - p.sw0[gr];
-    const int nlo = p.gnoff[gr], nhi = p.gnoff[gr + 1];
-    const int per = (nhi - nlo + items - 1) / items;
-    const int rlo = nlo + (wi - p.sw0[gr]) * per;
-    const int rhi = min(nhi, rlo + per);
-    const int rpw = max(1, (rhi - rlo + (blockDim.x / kWave) * G - 1) / ((blockDim.x / kWave) * G));
-    const int row0 = rlo + wid * rpw * G;
+    const int row0 = (blockIdx.x * (blockDim.x / kWave) + wid) * rpw * G;
     const int nrw = rpw * G;
     const bool pre = nrw < kWave;
     const int rpv = pre ? g.rp[min(row0 + lane, g.n)] : 0;
     for (int r = 0; r < rpw; ++r) {
         const int i = row0 + r * G + slot;
-        const bool valid = i < rhi;
+        const bool valid = i < g.n;
         if (__ballot(valid) == 0) break;
         int beg, end;
         if (pre) {
@@ -166,13 +146,10 @@ __global__ __launch_bounds__(256) void k_reduce_counts(ScorePlan p) {
     __shared__ long long sl[16][17], sv[16][17];
     const int e = threadIdx.x & 15, sl_id = threadIdx.x >> 4;
     const int idx = blockIdx.x * 16 + e;
-    const int gr = blockIdx.y;
-    const int b0g = p.sw0[gr], b1g = p.sw0[gr + 1];
     long long l = 0, v = 0;
     if (idx < p.SK) {
-        const int cnt = b1g - b0g;
-        const int per = (cnt + 15) / 16;
-        const int b0 = b0g + sl_id * per, b1 = min(b1g, b0 + per);
+        const int per = (p.grid + 15) / 16;
+        const int b0 = sl_id * per, b1 = min(p.grid, b0 + per);
         for (int b = b0; b < b1; ++b) {
             l += p.lpart[(size_t)b * p.SK + idx];
             v += p.vpart[(size_t)b * p.SK + idx];
@@ -187,8 +164,8 @@ __global__ __launch_bounds__(256) void k_reduce_counts(ScorePlan p) {
             tl += sl[e][q];
             tv += sv[e][q];
         }
-        p.l64[(size_t)gr * p.SK + idx] = tl / 2;
-        p.v64[(size_t)gr * p.SK + idx] = tv;
+        p.l64[idx] = tl / 2;
+        p.v64[idx] = tv;
     }
 }
 
@@ -196,19 +173,19 @@ __global__ __launch_bounds__(256) void k_reduce_counts(ScorePlan p) {
 // over r in ascending order on one lane.
 __global__ __launch_bounds__(64) void k_score_finalize(ScorePlan p) {
     __shared__ long long ls[RAFT_MAX_K_DEV + 1], vs[RAFT_MAX_K_DEV + 1];
-    const int k = blockIdx.x % p.Kc;
-    const int gr = blockIdx.x / p.Kc;
+    const int k = blockIdx.x;
+    if (k >= p.Kc) return;
     const int K = p.ks[k];
     for (int r = threadIdx.x; r < K; r += blockDim.x) {
-        ls[r] = p.l64[(size_t)gr * p.SK + p.koff[k] + r];
-        vs[r] = p.v64[(size_t)gr * p.SK + p.koff[k] + r];
+        ls[r] = p.l64[p.koff[k] + r];
+        vs[r] = p.v64[p.koff[k] + r];
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
     {
 #pragma clang fp contract(off)
-        const double e = (double)(p.m2[gr] / 2);
-        const double m2 = (double)p.m2[gr];
+        const double e = (double)(p.nnz / 2);
+        const double m2 = (double)p.nnz;
         double mod = 0.0;
         for (int r = 0; r < K; ++r) {
             const double t = (double)vs[r] / m2;
@@ -219,85 +196,61 @@ __global__ __launch_bounds__(64) void k_score_finalize(ScorePlan p) {
         for (int r = 0; r < K; ++r) {
             if (vs[r] > 0) nc = nc + (double)(vs[r] - 2 * ls[r]) / (double)vs[r];
         }
-        p.mod[(size_t)gr * p.Kc + k] = mod;
-        p.ncut[(size_t)gr * p.Kc + k] = 0.5 * nc;
+        p.mod[k] = mod;
+        p.ncut[k] = 0.5 * nc;
     }
 }
 
-// K* = first maximum of Mod (per graph); init first-occurrence table.
+// K* = first maximum of Mod; init first-occurrence table.
 __global__ void k_select_best(ScorePlan p, int32_t* k_selected) {
-    const int gr = blockIdx.x;
-    const double* mod = p.mod + (size_t)gr * p.Kc;
     if (threadIdx.x == 0) {
         int best = 0;
         for (int j = 1; j < p.Kc; ++j)
-            if (mod[j] > mod[best]) best = j;
-        p.best[gr] = best;
-        k_selected[gr * 3 + 0] = p.ks[best];
-        k_selected[gr * 3 + 2] = best;
+            if (p.mod[j] > p.mod[best]) best = j;
+        *p.best = best;
+        k_selected[0] = p.ks[best];
+        k_selected[2] = best;
     }
-    for (int r = threadIdx.x; r <= RAFT_MAX_K_DEV; r += blockDim.x)
-        p.first[(size_t)gr * (RAFT_MAX_K_DEV + 1) + r] = INT_MAX;
+    for (int r = threadIdx.x; r <= RAFT_MAX_K_DEV; r += blockDim.x) p.first[r] = INT_MAX;
 }
 
-// First occurrence (graph-local node index) of every cluster of K*.  A block
-// whose nodes all lie in one graph pre-reduces in LDS.
 __global__ __launch_bounds__(256) void k_first_occ(ScorePlan p, const uint8_t* __restrict__ lab) {
     __shared__ int first[RAFT_MAX_K_DEV + 1];
-    const int i0 = blockIdx.x * blockDim.x;
-    const int i1 = min(p.n, i0 + (int)blockDim.x) - 1;
-    const int g0 = p.gid ? p.gid[i0] : 0;
-    const int g1 = p.gid ? p.gid[i1] : 0;
-    const bool single = g0 == g1;
-    if (single) {
-        for (int r = threadIdx.x; r <= RAFT_MAX_K_DEV; r += blockDim.x) first[r] = INT_MAX;
-        __syncthreads();
-    }
-    const int i = i0 + threadIdx.x;
-    if (i < p.n) {
-        const int gr = p.gid ? p.gid[i] : 0;
-        const int r = lab[(size_t)i * p.S + p.best[gr]];
-        const int li = i - p.gnoff[gr];
-        if (single) atomicMin(&first[r], li);
-        else atomicMin(&p.first[(size_t)gr * (RAFT_MAX_K_DEV + 1) + r], li);
-    }
-    if (single) {
-        __syncthreads();
-        for (int r = threadIdx.x; r <= RAFT_MAX_K_DEV; r += blockDim.x)
-            if (first[r] != INT_MAX)
-                atomicMin(&p.first[(size_t)g0 * (RAFT_MAX_K_DEV + 1) + r], first[r]);
-    }
+    for (int r = threadIdx.x; r <= RAFT_MAX_K_DEV; r += blockDim.x) first[r] = INT_MAX;
+    __syncthreads();
+    const int best = *p.best;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < p.n; i += gridDim.x * blockDim.x)
+        atomicMin(&first[lab[(size_t)i * p.S + best]], i);
+    __syncthreads();
+    for (int r = threadIdx.x; r <= RAFT_MAX_K_DEV; r += blockDim.x)
+        if (first[r] != INT_MAX) atomicMin(&p.first[r], first[r]);
 }
 
 __global__ void k_rank(ScorePlan p, int32_t* k_selected) {
     __shared__ int keff;
-    const int gr = blockIdx.x;
     if (threadIdx.x == 0) keff = 0;
     __syncthreads();
-    const int* first = p.first + (size_t)gr * (RAFT_MAX_K_DEV + 1);
-    int* remap = p.remap + (size_t)gr * (RAFT_MAX_K_DEV + 1);
-    const int K = p.ks[p.best[gr]];
+    const int K = p.ks[*p.best];
     for (int r = threadIdx.x; r < K; r += blockDim.x) {
-        const int f = first[r];
+        const int f = p.first[r];
         if (f == INT_MAX) {
-            remap[r] = -1;
+            p.remap[r] = -1;
             continue;
         }
         int rank = 0;
-        for (int q = 0; q < K; ++q) rank += (first[q] < f);
-        remap[r] = rank;
+        for (int q = 0; q < K; ++q) rank += (p.first[q] < f);
+        p.remap[r] = rank;
         atomicAdd(&keff, 1);
     }
     __syncthreads();
-    if (threadIdx.x == 0) k_selected[gr * 3 + 1] = keff;
+    if (threadIdx.x == 0) k_selected[1] = keff;
 }
 
 __global__ __launch_bounds__(256) void k_apply(ScorePlan p, const uint8_t* __restrict__ lab,
                                                int32_t* __restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= p.n) return;
-    const int gr = p.gid ? p.gid[i] : 0;
-    out[i] = p.remap[(size_t)gr * (RAFT_MAX_K_DEV + 1) + lab[(size_t)i * p.S + p.best[gr]]];
+    out[i] = p.remap[lab[(size_t)i * p.S + *p.best]];
 }
 
 static int score_lpr(int S) {
@@ -307,18 +260,25 @@ static int score_lpr(int S) {
     return lpr;
 }
 
-int score_items(int32_t n, int num_cu) {
+static int score_rpw(int32_t n, int S, int grid) {
+    const int G = kWave / score_lpr(S);
+    const int64_t rows_per_block = ((int64_t)n + grid - 1) / grid;
+    return (int)std::max<int64_t>(1, (rows_per_block + 4 * G - 1) / (4 * G));
+}
+
+int score_grid(int32_t n, int num_cu) {
     const int64_t want = ((int64_t)n + 63) / 64;
     return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)num_cu * 2));
 }
 
 bool score_supported(int SK) { return SK >= 1 && SK <= 16384; }
 
-void launch_transpose_labels(const KmeansPlan& km, const ScorePlan& p, uint8_t* pm, hipStream_t st) {
-    const int64_t total = (int64_t)p.n * p.S;
+void launch_transpose_labels(const uint8_t* cm, int32_t n, int Kc, uint8_t* pm, int S,
+                             hipStream_t st) {
+    const int64_t total = (int64_t)n * S;
     if (!total) return;
     hipLaunchKernelGGL(k_transpose_labels, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
-                       km, p, pm);
+                       cm, n, Kc, pm, S);
 }
 
 void launch_copy_labels(const uint8_t* pm, int32_t n, int Kc, int S, uint8_t* out,
@@ -333,6 +293,7 @@ void launch_edge_score(const GraphView& g, const ScorePlan& p, const uint8_t* la
                        hipStream_t st) {
     const size_t lds = (size_t)2 * p.SK * sizeof(int);
     const int lpr = score_lpr(p.S);
+    const int rpw = score_rpw(g.n, p.S, p.grid);
 #define EDGE(LV)                                                                              \
     {                                                                                         \
         static bool attr = false;                                                             \
@@ -341,7 +302,7 @@ void launch_edge_score(const GraphView& g, const ScorePlan& p, const uint8_t* la
                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024); \
             attr = true;                                                                      \
         }                                                                                     \
-        hipLaunchKernelGGL(k_edge_score<LV>, dim3(p.grid), dim3(256), lds, st, g, p, lab);      \
+        hipLaunchKernelGGL(k_edge_score<LV>, dim3(p.grid), dim3(256), lds, st, g, p, lab, rpw); \
     }
     switch (lpr) {
         case 1: EDGE(1) break;
@@ -355,17 +316,17 @@ void launch_edge_score(const GraphView& g, const ScorePlan& p, const uint8_t* la
 }
 
 void launch_score_finish(const ScorePlan& p, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_counts, dim3((p.SK + 15) / 16, p.ngraphs), dim3(256), 0, st, p);
-    hipLaunchKernelGGL(k_score_finalize, dim3(p.Kc * p.ngraphs), dim3(64), 0, st, p);
+    hipLaunchKernelGGL(k_reduce_counts, dim3((p.SK + 15) / 16), dim3(256), 0, st, p);
+    hipLaunchKernelGGL(k_score_finalize, dim3(p.Kc), dim3(64), 0, st, p);
 }
 
 void launch_select(const ScorePlan& p, const uint8_t* lab, int32_t* labels_out,
                    int32_t* k_selected, hipStream_t st) {
-    hipLaunchKernelGGL(k_select_best, dim3(p.ngraphs), dim3(256), 0, st, p, k_selected);
+    hipLaunchKernelGGL(k_select_best, dim3(1), dim3(256), 0, st, p, k_selected);
     if (p.n == 0) return;
     const int grid = (p.n + 255) / 256;
-    hipLaunchKernelGGL(k_first_occ, dim3(grid), dim3(256), 0, st, p, lab);
-    hipLaunchKernelGGL(k_rank, dim3(p.ngraphs), dim3(256), 0, st, p, k_selected);
+    hipLaunchKernelGGL(k_first_occ, dim3(std::min(grid, 256)), dim3(256), 0, st, p, lab);
+    hipLaunchKernelGGL(k_rank, dim3(1), dim3(256), 0, st, p, k_selected);
     if (labels_out)
         hipLaunchKernelGGL(k_apply, dim3(grid), dim3(256), 0, st, p, lab, labels_out);
 }

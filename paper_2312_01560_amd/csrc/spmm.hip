@@ -122,8 +122,7 @@ __global__ __launch_bounds__(256) void k_spmm(GraphView g, const float* __restri
                                 si * (acc.z + si * xi.z), si * (acc.w + si * xi.w));
             } else if (OP == kOpModFull) {
                 const float ci = g.dcoef[i];
-                const float* cv = g.gid ? cvec + (size_t)g.gid[i] * L : cvec;
-                const float4 c = *reinterpret_cast<const float4*>(cv + sub * 4);
+                const float4 c = *reinterpret_cast<const float4*>(cvec + sub * 4);
                 o = make_float4(acc.x - ci * c.x, acc.y - ci * c.y, acc.z - ci * c.z,
                                 acc.w - ci * c.w);
             } else {
@@ -242,75 +241,6 @@ __global__ __launch_bounds__(256) void k_colsum_finish(const double* __restrict_
     }
 }
 
-// Per-graph column sums of a batch: work item -> (graph, contiguous rows of
-// that graph); one partial row per item, summed per graph in item order.
-template <int L>
-__global__ __launch_bounds__(256) void k_colsum_seg(GraphView g, const float* __restrict__ x,
-                                                    const int32_t* __restrict__ cw0,
-                                                    const int32_t* __restrict__ gnoff, int G,
-                                                    double* __restrict__ cpart) {
-    constexpr int LANES = L / 4;
-    constexpr int GR = kWave / LANES;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x / kWave;
-    const int slot = lane / LANES;
-    const int sub = lane % LANES;
-    const int wi = blockIdx.x;
-    int glo = 0, ghi = G;
-    while (ghi - glo > 1) {
-        const int mid = (glo + ghi) >> 1;
-        if (cw0[mid] <= wi) glo = mid;
-        else ghi = mid;
-    }
-    const int items = cw0[glo + 1] - cw0[glo];
-    const int nlo = gnoff[glo], nhi = gnoff[glo + 1];
-    const int per = (nhi - nlo + items - 1) / items;
-    const int r0 = nlo + (wi - cw0[glo]) * per;
-    const int r1 = min(nhi, r0 + per);
-    double cs0 = 0, cs1 = 0, cs2 = 0, cs3 = 0;
-    for (int i = r0 + wid * GR + slot; i < r1; i += kSpmmWaves * GR) {
-        const float4 o = *reinterpret_cast<const float4*>(x + (size_t)i * L + sub * 4);
-        const double di = (double)g.deg[i];
-        cs0 += di * (double)o.x;
-        cs1 += di * (double)o.y;
-        cs2 += di * (double)o.z;
-        cs3 += di * (double)o.w;
-    }
-#pragma unroll
-    for (int off = LANES; off < kWave; off <<= 1) {
-        cs0 += __shfl_xor(cs0, off, kWave);
-        cs1 += __shfl_xor(cs1, off, kWave);
-        cs2 += __shfl_xor(cs2, off, kWave);
-        cs3 += __shfl_xor(cs3, off, kWave);
-    }
-    __shared__ double red[kSpmmWaves][L];
-    if (slot == 0) {
-        red[wid][sub * 4 + 0] = cs0;
-        red[wid][sub * 4 + 1] = cs1;
-        red[wid][sub * 4 + 2] = cs2;
-        red[wid][sub * 4 + 3] = cs3;
-    }
-    __syncthreads();
-    for (int c = threadIdx.x; c < L; c += blockDim.x) {
-        double s = 0;
-        for (int w = 0; w < kSpmmWaves; ++w) s += red[w][c];
-        cpart[(size_t)wi * L + c] = s;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_colsum_seg_finish(const double* __restrict__ part,
-                                                           const int32_t* __restrict__ cw0, int L,
-                                                           double* __restrict__ c64,
-                                                           float* __restrict__ cvec) {
-    const int gr = blockIdx.x;
-    for (int col = threadIdx.x; col < L; col += blockDim.x) {
-        double t = 0;
-        for (int w = cw0[gr]; w < cw0[gr + 1]; ++w) t += part[(size_t)w * L + col];
-        c64[(size_t)gr * L + col] = t;
-        cvec[(size_t)gr * L + col] = (float)t;
-    }
-}
-
 bool spmm_supported(int L) { return L == 16 || L == 32 || L == 64 || L == 128 || L == 256; }
 
 int spmm_grid(int32_t n, int L, int num_cu, int* rows_per_wave) {
@@ -380,29 +310,6 @@ void launch_colsum_finish(const double* part, int parts, int L, double* c64, flo
     double* stage = const_cast<double*>(part) + (size_t)parts * L;
     hipLaunchKernelGGL(k_colsum_slices, dim3(kColsumSlices), dim3(256), 0, st, part, parts, L, stage);
     hipLaunchKernelGGL(k_colsum_finish, dim3(1), dim3(256), 0, st, stage, L, c64, cvec);
-}
-
-void launch_colsum_seg(const GraphView& g, int L, const float* x, const int32_t* cw0,
-                       const int32_t* gnoff, int G, int items, double* part, hipStream_t st) {
-    if (items == 0) return;
-#define SEG(LV)                                                                             \
-    hipLaunchKernelGGL(k_colsum_seg<LV>, dim3(items), dim3(256), 0, st, g, x, cw0, gnoff, G, \
-                       part)
-    switch (L) {
-        case 16: SEG(16); break;
-        case 32: SEG(32); break;
-        case 64: SEG(64); break;
-        case 128: SEG(128); break;
-        case 256: SEG(256); break;
-        default: break;
-    }
-#undef SEG
-}
-
-void launch_colsum_seg_finish(const double* part, const int32_t* cw0, int G, int L, double* c64,
-                              float* cvec, hipStream_t st) {
-    if (G == 0) return;
-    hipLaunchKernelGGL(k_colsum_seg_finish, dim3(G), dim3(256), 0, st, part, cw0, L, c64, cvec);
 }
 
 }  // namespace raft
