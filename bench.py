@@ -240,7 +240,8 @@ def main():
                  "avg_us": 1e3 * ms_spmm / max(n_spmm, 1), "launches": n_spmm,
                  "bytes_per_launch": spmm_bytes_per_launch,
                  "edges_features_per_s": nnz * method["proj_dim"] * n_spmm / (ms_spmm * 1e-3)
-                 if ms_spmm > 0 else 0.0},
+                 if ms_spmm > 0 else 0.0,
+                 "traffic": measured_traffic("spmm", args.workload)},
         "stages_ms_per_step": {v: dict(zip(["project", "embed", "seed", "lloyd", "score"],
                                            (stage[v] / args.steps).round(3).tolist()))
                                for v in variants},
