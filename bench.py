@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--variants", default="ncut,mod_full")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-stride", type=int, default=16)
+    ap.add_argument("--train", action="store_true",
+                    help="time the trainable-GCN mode on the n200k workload instead")
+    ap.add_argument("--train-steps", type=int, default=200)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
     return ap.parse_args()
@@ -135,6 +138,82 @@ def cpu_baseline(graph, method, variants, gpu_out, stride):
     }, float(min(nmis)), float(min(nmi_star))
 
 
+def bench_train(args, api, torch, np):
+    """Trainable-weight GCN on the n200k workload: 3 layers of width 64, the
+    last one linear into 64 softmax assignments, loss -tr(S^T B S)/2e, Adam.
+    One step = forward + loss + adjoint + Adam on every W (activations are
+    recomputed in the adjoint).  The untrained start is the method's own random
+    GCN; both are compared with the method's partition by modularity and NMI."""
+    from paper_2312_01560_amd.train import Trainer
+    from synth import make_workload
+    from oracle import scores as oscores   # NMI bookkeeping only
+
+    graph, method = make_workload("n200k")
+    ctx = api.Context(0)
+    dev = ctx.torch_device
+    g = api.Graph(ctx, torch.from_numpy(graph.row_ptr).to(dev), torch.from_numpy(graph.col_idx).to(dev))
+    dims = [64, 64, 64, 64]
+    cfg = api.Config(op=1, proj_dim=64, q=3, layer_dims=dims[1:], k_min=2, k_max=64)
+    log(f"n200k: n={graph.n} nnz={graph.nnz}; method run (untrained random GCN)")
+    base = api.run(ctx, g, cfg)
+    torch.cuda.synchronize()
+    y = base["Y"]
+    ws = [api.gaussian(ctx, cfg.seed, api.STREAM_W_BASE + k + 1, dims[k], dims[k + 1],
+                       1.0 / np.sqrt(dims[k])) for k in range(3)]
+    tr = Trainer(ctx, g, dims)
+    params = [w.clone() for w in ws]
+    ms = [torch.zeros_like(w) for w in ws]
+    vs = [torch.zeros_like(w) for w in ws]
+
+    def hard(S):
+        lab = torch.argmax(S, dim=1).to(torch.uint8)[:, None].contiguous()
+        mod, _ = api.score(ctx, g, lab, [64])
+        return lab[:, 0].cpu().numpy().astype(np.int64), float(mod.cpu()[0])
+
+    U, _ = tr.forward(y, params)
+    S0, loss0 = tr.modloss_forward(U)
+    lab0, mod0 = hard(S0)
+    losses = [float(loss0.cpu()[0])]
+    log(f"training {args.train_steps} Adam steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for step in range(1, args.train_steps + 1):
+        U, saved = tr.forward(y, params)
+        S, loss = tr.modloss_forward(U)
+        GW, _ = tr.backward(y, params, saved, tr.modloss_backward(S))
+        for k in range(3):
+            tr.adam(params[k], ms[k], vs[k], GW[k], step)
+        if step % 50 == 0:
+            losses.append(float(loss.cpu()[0]))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.sync_status()
+    U, _ = tr.forward(y, params)
+    S1, loss1 = tr.modloss_forward(U)
+    lab1, mod1 = hard(S1)
+    method_lab = base["labels"].cpu().numpy()
+    method_mod = float(base["mod"].cpu().numpy()[int(base["k_selected"].cpu()[2])])
+    ms_step = 1e3 * (t1 - t0) / args.train_steps
+    rec = {
+        "metric": "trainable GCN steps/s (forward + relaxed-modularity loss + adjoint + Adam), n200k",
+        "value": 1e3 / ms_step, "unit": "steps/s", "n_gpus": 1, "steps": args.train_steps,
+        "warmup": 0, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "n200k", "n": graph.n, "nnz": graph.nnz, "dims": dims,
+                   "softmax_k": 64, "optimizer": "adam lr 1e-2"},
+        "loss": {"step0": losses[0], "every50": losses[1:], "final": float(loss1.cpu()[0])},
+        "modularity": {"untrained_softmax_argmax": mod0, "trained_softmax_argmax": mod1,
+                       "method_partition": method_mod},
+        "nmi": {"trained_vs_untrained": float(oscores.nmi(lab1, lab0)),
+                "trained_vs_method": float(oscores.nmi(lab1, method_lab)),
+                "trained_vs_planted": float(oscores.nmi(lab1, graph.planted)),
+                "method_vs_planted": float(oscores.nmi(method_lab, graph.planted))},
+        "spmm_per_step": 9,
+    }
+    print(json.dumps(rec))
+    ctx.close()
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -149,6 +228,9 @@ def main():
     from paper_2312_01560_amd import api
     from synth import make_workload
 
+    if args.train:
+        bench_train(args, api, torch, np)
+        return
     if args.workload not in ("n50k", "n1m", "small", "n200k"):
         print(f"unknown workload {args.workload}", file=sys.stderr)
         sys.exit(2)

@@ -303,3 +303,92 @@ def test_workspace_too_small(ctx, api_mod, small_graph):
     bad = api_mod.Config(op=0, **{**m, "k_max": 256})
     with pytest.raises(api_mod.RaftError):
         api_mod.workspace_size(ctx, g, bad)
+
+
+# ------------------------------------------------- wide candidate grids ---
+
+@pytest.mark.parametrize("k_max", [64, 80])
+def test_partition_wide_grid(ctx, api_mod, ragged, k_max):
+    """Grids of 63 and 79 candidates: the edge-score kernel then reads 8 and
+    16 label words per row (its widest instances), and the k-means groups
+    hold single large candidates.  Picks bit-exact, fixed points, scores of
+    the GPU labels equal the oracle's."""
+    z = np.random.default_rng(5).standard_normal((ragged.n, 64)).astype(np.float32)
+    z /= np.linalg.norm(z, axis=1, keepdims=True)
+    g = api_mod.Graph(ctx, ragged.row_ptr, ragged.col_idx)
+    cfg = api_mod.Config(op=0, k_min=2, k_max=k_max, kmeans_max_iter=200)
+    out = api_mod.partition(ctx, g, cfg, torch.from_numpy(z).cuda())
+    torch.cuda.synchronize()
+    ctx.sync_status()
+    z64 = z.astype(np.float64)
+    assert np.array_equal(to_np(out["picks"]), okm.seed_picks(z64, k_max, 0))
+    lab = to_np(out["labels_all"]).astype(np.int64)
+    iters = to_np(out["iters"])
+    for j, k in enumerate(cfg.ks):
+        assert lab[:, j].max() < k
+        if iters[j] < 200:
+            live = [r for r in range(k) if np.any(lab[:, j] == r)]
+            cen = np.stack([z64[lab[:, j] == r].mean(0) for r in live])
+            d = okm.sq_distances(z64, cen)
+            pos = {r: t for t, r in enumerate(live)}
+            mine = d[np.arange(ragged.n), [pos[r] for r in lab[:, j]]]
+            assert np.all(mine <= d.min(axis=1) + 1e-5)
+    rmod, rnc = scores.score_candidates(ragged.row_ptr, ragged.col_idx, lab, cfg.ks)
+    assert np.array_equal(to_np(out["mod"]), rmod)
+    assert np.array_equal(to_np(out["ncut"]), rnc)
+    best = scores.select(rmod)
+    can, keff = scores.canonical(lab[:, best])
+    ks = to_np(out["k_selected"])
+    assert ks[0] == cfg.ks[best] and ks[1] == keff
+    assert np.array_equal(to_np(out["labels"]), can)
+
+
+# ------------------------------------------- full size, bench launch shape ---
+
+@pytest.fixture(scope="module")
+def n50k():
+    return make_workload("n50k")
+
+
+@pytest.mark.parametrize("op", [0, 1])
+def test_n50k_full_size(ctx, api_mod, n50k, op):
+    """The benchmark's workload and launch configuration (N = 50,000, L = d =
+    64, q = 3, K 2..80): Y and Z against the FP64 oracle column by column,
+    k-means++ picks bit-exact on the GPU's embedding, every converged
+    candidate a Lloyd fixed point, Mod/NCut of the GPU labels equal to the
+    oracle's, K* and canonical labels consistent."""
+    g0, m = n50k
+    rp = torch.from_numpy(g0.row_ptr).cuda()
+    ci = torch.from_numpy(g0.col_idx).cuda()
+    g = api_mod.Graph(ctx, rp, ci)                      # device-resident input, as timed
+    cfg = api_mod.Config(op=op, **m)
+    out = api_mod.run(ctx, g, cfg)
+    torch.cuda.synchronize()
+    ctx.sync_status()
+    y = projection.project(g0.row_ptr, g0.col_idx, g0.n, op, m["proj_dim"], m["q"], 0)
+    zr = ogcn.embed(g0.row_ptr, g0.col_idx, g0.n, y, m["layer_dims"], 0)
+    assert col_err(to_np(out["Y"]), y).max() < COL_TOL
+    assert col_err(to_np(out["Z"]), zr).max() < COL_TOL
+    z32 = to_np(out["Z"])
+    z64 = z32.astype(np.float64)
+    assert np.array_equal(to_np(out["picks"]), okm.seed_picks(z64, max(cfg.ks), 0))
+    lab = to_np(out["labels_all"]).astype(np.int64)
+    iters = to_np(out["iters"])
+    for j in range(0, len(cfg.ks), 6):                   # a sample of candidates
+        k = cfg.ks[j]
+        if iters[j] >= cfg.kmeans_max_iter:
+            continue
+        live = [r for r in range(k) if np.any(lab[:, j] == r)]
+        cen = np.stack([z64[lab[:, j] == r].mean(0) for r in live])
+        d = okm.sq_distances(z64, cen)
+        pos = {r: t for t, r in enumerate(live)}
+        mine = d[np.arange(g0.n), [pos[r] for r in lab[:, j]]]
+        assert np.all(mine <= d.min(axis=1) + 1e-5), k
+    rmod, rnc = scores.score_candidates(g0.row_ptr, g0.col_idx, lab, cfg.ks)
+    assert np.array_equal(to_np(out["mod"]), rmod)
+    assert np.array_equal(to_np(out["ncut"]), rnc)
+    best = scores.select(rmod)
+    can, keff = scores.canonical(lab[:, best])
+    ks = to_np(out["k_selected"])
+    assert ks[0] == cfg.ks[best] and ks[1] == keff
+    assert np.array_equal(to_np(out["labels"]), can)
