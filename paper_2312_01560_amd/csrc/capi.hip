@@ -185,9 +185,14 @@ Lists make_lists(const Grid& G, const int32_t* active, int ucap, int n, int num_
         if (!active || active[k]) l.alist.push_back(k);
     l.agrp.push_back(0);
     int acc = 0;
+    // groups of about 256 padded centres; the assignment kernel keeps a
+    // group's candidates one per lane, so a group never exceeds 64 of them
+    int in_group = 0;
     for (size_t t = 0; t < l.alist.size(); ++t) {
         acc += (G.ks[l.alist[t]] + 15) / 16 * 16;
-        if (acc >= 256 && t + 1 < l.alist.size()) {
+        ++in_group;
+        if ((acc >= 256 || in_group == 64) && t + 1 < l.alist.size()) {
+            in_group = 0;
             l.agrp.push_back((int32_t)t + 1);
             acc = 0;
         }
@@ -546,7 +551,7 @@ raft_status do_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* 
     for (int it = 1; it <= t_max; ++it) {
         {
             ProfScope ps(ctx, RAFT_PROF_ASSIGN, st);
-            launch_assign(km, Z, st);
+            launch_assign(km, Z, ctx->num_cu, st);
         }
         launch_iter_finalize(km, it, t_max, st);
         if (it == t_max) break;

@@ -109,7 +109,7 @@ void launch_kmeans_reset(const KmeansPlan& p, hipStream_t st);
 void launch_zmax(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t st);
 void launch_race_pick(const KmeansPlan& p, const float* Z, int t, uint64_t seed, hipStream_t st);
 void launch_init_centres(const KmeansPlan& p, const float* Z, hipStream_t st);
-void launch_assign(const KmeansPlan& p, const float* Z, hipStream_t st);
+void launch_assign(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t st);
 void launch_iter_finalize(const KmeansPlan& p, int it, int t_max, hipStream_t st);
 void launch_update(const KmeansPlan& p, const float* Z, size_t lds_max, hipStream_t st);
 
