@@ -28,6 +28,9 @@ if ROOT not in sys.path:
 
 PEAK_HBM = 8.0e12            # bytes/s, MI355X HBM3E
 PEAK_MFMA_F32 = 157.3e12     # FLOP/s, dense FP32 matrix
+PEAK_MFMA_F16 = 2.5e15       # FLOP/s, dense FP16 matrix
+# the split-fp16 assignment issues three fp16 products per FP32 product
+PEAK_SPLIT_F16 = PEAK_MFMA_F16 / 3.0
 VARIANTS = {"ncut": 0, "mod_full": 1, "mod_reduced": 2}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
@@ -62,7 +65,7 @@ def source_hash(files):
 
 
 KERNEL_SOURCES = {
-    "assign": ["paper_2312_01560_amd/csrc/kmeans.hip"],
+    "assign": ["paper_2312_01560_amd/csrc/kmeans.hip"],  # k_assign / k_assign_h
     "spmm": ["paper_2312_01560_amd/csrc/spmm.hip"],
 }
 
@@ -291,9 +294,13 @@ def main():
     spmm_ach = spmm_bytes_per_launch * n_spmm / (ms_spmm * 1e-3) if ms_spmm > 0 else 0.0
     dominant = "assign" if ms_assign >= ms_spmm else "spmm"
     if dominant == "assign":
-        roof = {"kernel": "k_assign (MFMA FP32, all candidates)", "bound": "mfma",
-                "achieved": assign_ach / 1e12, "peak": PEAK_MFMA_F32 / 1e12, "unit": "TFLOP/s",
-                "frac": assign_ach / PEAK_MFMA_F32,
+        split = d % 32 == 0
+        peak = PEAK_SPLIT_F16 if split else PEAK_MFMA_F32
+        kname = ("k_assign_h (split-fp16 MFMA: 3 fp16 products per FP32 product, FP32 accumulate;"
+                 " FP32-equivalent FLOP against fp16 peak / 3)") if split else "k_assign (MFMA FP32)"
+        roof = {"kernel": kname, "bound": "mfma",
+                "achieved": assign_ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                "frac": assign_ach / peak,
                 "per_launch": {"flops": assign_flops * args.steps / max(n_assign, 1),
                                "avg_ms": ms_assign / max(n_assign, 1)}}
     else:

@@ -369,6 +369,11 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
     km.active_count = a.take<int32_t>(1);
     km.C = a.take<float>((size_t)G.KP * P.d);
     km.cnorm = a.take<float>(G.KP);
+    km.split = kmeans_split_supported(P.d) ? 1 : 0;
+    km.zh = a.take<uint16_t>(km.split ? (size_t)n * P.d : 1);
+    km.zl = a.take<uint16_t>(km.split ? (size_t)n * P.d : 1);
+    km.ch = a.take<uint16_t>(km.split ? (size_t)G.KP * P.d : 1);
+    km.cl = a.take<uint16_t>(km.split ? (size_t)G.KP * P.d : 1);
     km.psum = a.take<float>((size_t)P.ranges_max * G.KP * P.d);
     km.pcnt = a.take<int32_t>((size_t)P.ranges_max * G.KP);
     km.zmax_bits = a.take<uint32_t>(1);
@@ -538,6 +543,7 @@ raft_status do_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* 
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[2], st));
     launch_kmeans_reset(km, st);
     launch_zmax(km, Z, ctx->num_cu, st);
+    if (km.split) launch_split_points(km, Z, st);
     for (int t = 0; t < km.k_max; ++t) {
         ProfScope ps(ctx, RAFT_PROF_RACE, st);
         launch_race_pick(km, Z, t, c->seed, st);

@@ -85,6 +85,13 @@ struct KmeansPlan {
     int32_t* active_count;   // [1]
     float* C;                // [KP x d]
     float* cnorm;            // [KP]
+    // Split-fp16 operands of the assignment (split != 0): x 2^s = hi + lo,
+    // s = 10 - (exponent of the largest |z|), both halves fp16 bit patterns.
+    int32_t split;
+    uint16_t* zh;            // [n x d]
+    uint16_t* zl;            // [n x d]
+    uint16_t* ch;            // [KP x d]
+    uint16_t* cl;            // [KP x d]
     float* psum;             // [max ranges x KP x d] per-range centre sums
     int32_t* pcnt;           // [max ranges x KP]
     uint32_t* zmax_bits;     // [1] largest |z| (float bits), sets the fixed-point scale
@@ -110,6 +117,10 @@ void launch_zmax(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t st
 void launch_race_pick(const KmeansPlan& p, const float* Z, int t, uint64_t seed, hipStream_t st);
 void launch_init_centres(const KmeansPlan& p, const float* Z, hipStream_t st);
 void launch_assign(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t st);
+// Split-fp16 assignment is available for d multiple of 32.
+bool kmeans_split_supported(int d);
+// zh/zl from Z (after launch_zmax).
+void launch_split_points(const KmeansPlan& p, const float* Z, hipStream_t st);
 void launch_iter_finalize(const KmeansPlan& p, int it, int t_max, hipStream_t st);
 void launch_update(const KmeansPlan& p, const float* Z, size_t lds_max, hipStream_t st);
 

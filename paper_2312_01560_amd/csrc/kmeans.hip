@@ -32,6 +32,25 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr uint64_t kStreamRace = 0x20;
 constexpr int kRaceThreads = 256;
 
+// Split-fp16 scale exponent s: |z| 2^s < 2^10 for every |z| <= zmax.
+__device__ __forceinline__ int split_exp(const KmeansPlan& p) {
+    const float zmax = __uint_as_float(*p.zmax_bits);
+    if (!(zmax > 0.f)) return 0;
+    int ez;
+    frexpf(zmax, &ez);
+    return 10 - ez;
+}
+
+// x 2^s = hi + lo with hi = fp16(x 2^s), lo = fp16(x 2^s - hi); the
+// difference is exact in FP32, so hi + lo carries 22 bits of x.
+__device__ __forceinline__ void split_half(float x, float sc, uint16_t* hi, uint16_t* lo) {
+    const float xs = x * sc;
+    const _Float16 h = (_Float16)xs;
+    const _Float16 l = (_Float16)(xs - (float)h);
+    *hi = __builtin_bit_cast(uint16_t, h);
+    *lo = __builtin_bit_cast(uint16_t, l);
+}
+
 __device__ __forceinline__ bool lex_less(double v, int i, double bv, int bi) {
     return v < bv || (v == bv && i < bi);
 }
@@ -170,15 +189,23 @@ __global__ __launch_bounds__(256) void k_init_centres(KmeansPlan p, const float*
     const int r = c - p.koff16[k];
     float* crow = p.C + (size_t)c * D;
     if (r >= p.ks[k]) {
-        for (int dd = lane; dd < D; dd += kWave) crow[dd] = 0.f;
+        for (int dd = lane; dd < D; dd += kWave) {
+            crow[dd] = 0.f;
+            if (p.split) {
+                p.ch[(size_t)c * D + dd] = 0;
+                p.cl[(size_t)c * D + dd] = 0;
+            }
+        }
         if (lane == 0) p.cnorm[c] = INFINITY;
         return;
     }
     const float* z = Z + (size_t)p.picks[r] * D;
+    const float sc = ldexpf(1.0f, split_exp(p));
     float ss = 0.f;
     for (int dd = lane; dd < D; dd += kWave) {
         const float v = z[dd];
         crow[dd] = v;
+        if (p.split) split_half(v, sc, p.ch + (size_t)c * D + dd, p.cl + (size_t)c * D + dd);
         ss += v * v;
     }
     ss = wave_sum(ss);
@@ -331,6 +358,154 @@ __global__ __launch_bounds__(256) void k_assign(KmeansPlan p, const float* __res
     }
 }
 
+// Split-fp16 assignment (d a multiple of 32): the same walk and argmin as
+// k_assign, with each 16 x 16 x d score block from v_mfma_f32_16x16x32_f16
+// over the split halves: z.c 2^2s = zh.ch + zl.ch + zh.cl (the lo.lo term is
+// below 2^-22 relative); products of fp16 values are exact in FP32, which
+// accumulates.  Lane l holds A[l%16][8(l/16)+i] (centres) and
+// B[8(l/16)+i][l%16] (points) per 32-wide k chunk; D as in the FP32 MFMA.
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+
+template <int NC>
+__device__ __forceinline__ void load_ctile_h(const KmeansPlan& p, int cb, int li, int g, half8* ah,
+                                             half8* al, float4& cn) {
+    const size_t row = (size_t)(cb + li) * (NC * 32) + 8 * g;
+    const _Float16* hr = reinterpret_cast<const _Float16*>(p.ch) + row;
+    const _Float16* lr = reinterpret_cast<const _Float16*>(p.cl) + row;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        ah[c] = *reinterpret_cast<const half8*>(hr + 32 * c);
+        al[c] = *reinterpret_cast<const half8*>(lr + 32 * c);
+    }
+    cn = *reinterpret_cast<const float4*>(p.cnorm + cb + 4 * g);
+}
+
+template <int D, int PS>
+__global__ __launch_bounds__(256) void k_assign_h(KmeansPlan p) {
+    constexpr int NC = D / 32;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int g = lane >> 4;
+    const int li = lane & 15;
+    const int pbase = (blockIdx.x * 4 + wid) * 16 * PS;
+    if (pbase >= p.n) return;
+    half8 bh[PS][NC], bl[PS][NC];
+#pragma unroll
+    for (int ps = 0; ps < PS; ++ps) {
+        const int pt = min(pbase + 16 * ps + li, p.n - 1);
+        const size_t row = (size_t)pt * D + 8 * g;
+        const _Float16* hr = reinterpret_cast<const _Float16*>(p.zh) + row;
+        const _Float16* lr = reinterpret_cast<const _Float16*>(p.zl) + row;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            bh[ps][c] = *reinterpret_cast<const half8*>(hr + 32 * c);
+            bl[ps][c] = *reinterpret_cast<const half8*>(lr + 32 * c);
+        }
+    }
+    const int t0 = p.agrp[blockIdx.y], t1 = p.agrp[blockIdx.y + 1];
+    const int nc = min(t1 - t0, kWave);
+    int my_k = 0, my_tiles = 0, my_off = 0;
+    bool my_act = false;
+    if (lane < nc) {
+        my_k = p.alist[t0 + lane];
+        my_act = p.active[my_k] != 0;
+        my_tiles = (p.ks[my_k] + 15) >> 4;
+        my_off = p.koff16[my_k];
+    }
+    const uint64_t amask = __ballot(my_act);
+    if (amask == 0) return;
+    const float dsc = ldexpf(1.0f, -2 * split_exp(p));
+    int t = __builtin_ctzll(amask);
+    int k = __builtin_amdgcn_readlane(my_k, t);
+    int ntiles = __builtin_amdgcn_readlane(my_tiles, t);
+    int koff = __builtin_amdgcn_readlane(my_off, t);
+    int tile = 0;
+    half8 nah[NC], nal[NC];
+    float4 cnn;
+    load_ctile_h<NC>(p, koff, li, g, nah, nal, cnn);
+    float bv[PS];
+    int bi[PS];
+#pragma unroll
+    for (int ps = 0; ps < PS; ++ps) {
+        bv[ps] = INFINITY;
+        bi[ps] = 0;
+    }
+    while (true) {
+        half8 ah[NC], al[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            ah[c] = nah[c];
+            al[c] = nal[c];
+        }
+        const float cnv[4] = {cnn.x, cnn.y, cnn.z, cnn.w};
+        int nk = k, ntile = tile + 1, nt = t, nntiles = ntiles, nkoff = koff;
+        if (ntile >= ntiles) {
+            ntile = 0;
+            const uint64_t rest = amask & ~((2ull << t) - 1ull);
+            nt = rest ? __builtin_ctzll(rest) : nc;
+            if (nt < nc) {
+                nk = __builtin_amdgcn_readlane(my_k, nt);
+                nntiles = __builtin_amdgcn_readlane(my_tiles, nt);
+                nkoff = __builtin_amdgcn_readlane(my_off, nt);
+            }
+        }
+        if (nt < nc) load_ctile_h<NC>(p, nkoff + ntile * 16, li, g, nah, nal, cnn);
+#pragma unroll
+        for (int ps = 0; ps < PS; ++ps) {
+            floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[c], bh[ps][c], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[c], bl[ps][c], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[c], bh[ps][c], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float sc = cnv[v] - 2.0f * (acc[v] * dsc);
+                if (sc < bv[ps]) {
+                    bv[ps] = sc;
+                    bi[ps] = tile * 16 + 4 * g + v;
+                }
+            }
+        }
+        if (tile == ntiles - 1) {
+            int mine = 0;
+#pragma unroll
+            for (int ps = 0; ps < PS; ++ps) {
+#pragma unroll
+                for (int off = 16; off < kWave; off <<= 1) {
+                    const float ov = __shfl_xor(bv[ps], off, kWave);
+                    const int oi = __shfl_xor(bi[ps], off, kWave);
+                    if (ov < bv[ps] || (ov == bv[ps] && oi < bi[ps])) {
+                        bv[ps] = ov;
+                        bi[ps] = oi;
+                    }
+                }
+                if (ps == g) mine = bi[ps];
+                bv[ps] = INFINITY;
+                bi[ps] = 0;
+            }
+            const int pt = pbase + 16 * g + li;
+            bool changed = false;
+            if (g < PS && pt < p.n) {
+                uint8_t* lp = p.lab_cm + (size_t)k * p.n + pt;
+                const uint8_t old = *lp;
+                const uint8_t nw = (uint8_t)mine;
+                changed = old != nw;
+                *lp = nw;
+            }
+            const uint64_t m = __ballot(changed);
+            if (lane == 0 && m) atomicAdd(&p.changes[k], (int)__popcll(m));
+        }
+        if (nt >= nc) break;
+        k = nk;
+        tile = ntile;
+        t = nt;
+        ntiles = nntiles;
+        koff = nkoff;
+    }
+}
+
 // After an assignment: a candidate whose labels did not change (from the
 // second assignment on) has converged; count the remaining active ones.
 __global__ __launch_bounds__(256) void k_iter_finalize(KmeansPlan p, int it, int t_max) {
@@ -384,6 +559,14 @@ __device__ __forceinline__ int fixed_exp(const KmeansPlan& p) {
     int ez;
     frexpf(zmax, &ez);
     return 30 - ez;
+}
+
+__global__ __launch_bounds__(256) void k_split_points(KmeansPlan p, const float* __restrict__ Z) {
+    const int64_t total = (int64_t)p.n * p.d;
+    const float sc = ldexpf(1.0f, split_exp(p));
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x)
+        split_half(Z[i], sc, p.zh + i, p.zl + i);
 }
 
 // Centre sums for one work item (update group, point range) and one slice of
@@ -542,6 +725,9 @@ __global__ __launch_bounds__(256) void k_update_finish(KmeansPlan p) {
             const double t = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
             const float v = (float)(t / (double)total);
             crow[dd] = v;
+            if (p.split)
+                split_half(v, ldexpf(1.0f, split_exp(p)), p.ch + (size_t)c * p.d + dd,
+                           p.cl + (size_t)c * p.d + dd);
             ss += v * v;
         }
     }
@@ -635,10 +821,25 @@ void launch_assign(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t 
         constexpr int PS = assign_ps<DV>();                                               \
         const int pts_per_block = 4 * 16 * PS;                                            \
         dim3 grid((p.n + pts_per_block - 1) / pts_per_block, p.agroups);                   \
+        if constexpr (DV % 32 == 0) {                                                     \
+            if (p.split) {                                                                \
+                hipLaunchKernelGGL((k_assign_h<DV, PS>), grid, dim3(256), 0, st, p);      \
+                break;                                                                    \
+            }                                                                             \
+        }                                                                                 \
         hipLaunchKernelGGL((k_assign<DV, PS>), grid, dim3(256), 0, st, p, Z);             \
     }
     RAFT_D_SWITCH(p.d, ASSIGN)
 #undef ASSIGN
+}
+
+bool kmeans_split_supported(int d) { return d % 32 == 0 && d >= 32 && d <= 256; }
+
+void launch_split_points(const KmeansPlan& p, const float* Z, hipStream_t st) {
+    const int64_t total = (int64_t)p.n * p.d;
+    if (total == 0) return;
+    const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_split_points, dim3(grid), dim3(256), 0, st, p, Z);
 }
 
 void launch_iter_finalize(const KmeansPlan& p, int it, int t_max, hipStream_t st) {
