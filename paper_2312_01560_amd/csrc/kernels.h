@@ -80,7 +80,7 @@ struct KmeansPlan {
     const int32_t* ulen;     // [ugroups] point range length of each update group
     const int32_t* cranges;  // [Kc] point ranges of each candidate's update group
     int32_t* active;         // [Kc]
-    int32_t* changes;        // [Kc]
+    int32_t* changes;        // [Kc] non-zero when a label of the candidate changed
     int32_t* iters;          // [Kc]
     int32_t* active_count;   // [1]
     float* C;                // [KP x d]

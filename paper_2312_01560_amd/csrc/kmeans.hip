@@ -347,7 +347,7 @@ __global__ __launch_bounds__(256) void k_assign(KmeansPlan p, const float* __res
                 *lp = nw;
             }
             const uint64_t m = __ballot(changed);
-            if (lane == 0 && m) atomicAdd(&p.changes[k], (int)__popcll(m));
+            if (lane == 0 && m) p.changes[k] = 1;   // only zero / non-zero is read
         }
         if (nt >= nc) break;
         k = nk;
@@ -366,29 +366,25 @@ __global__ __launch_bounds__(256) void k_assign(KmeansPlan p, const float* __res
 // B[8(l/16)+i][l%16] (points) per 32-wide k chunk; D as in the FP32 MFMA.
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 
-template <int NC>
-__device__ __forceinline__ void load_ctile_h(const KmeansPlan& p, int cb, int li, int g, half8* ah,
-                                             half8* al, float4& cn) {
-    const size_t row = (size_t)(cb + li) * (NC * 32) + 8 * g;
-    const _Float16* hr = reinterpret_cast<const _Float16*>(p.ch) + row;
-    const _Float16* lr = reinterpret_cast<const _Float16*>(p.cl) + row;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        ah[c] = *reinterpret_cast<const half8*>(hr + 32 * c);
-        al[c] = *reinterpret_cast<const half8*>(lr + 32 * c);
-    }
-    cn = *reinterpret_cast<const float4*>(p.cnorm + cb + 4 * g);
-}
-
+// Centre tiles pass through LDS: the four waves of a work-group walk the same
+// candidate group, so the 256 threads load each 16-centre tile (hi and lo
+// halves, norms) once, one tile ahead of the MFMAs, into a double buffer;
+// one barrier per tile.  Rows are padded by 8 halves against bank conflicts.
 template <int D, int PS>
 __global__ __launch_bounds__(256) void k_assign_h(KmeansPlan p) {
     constexpr int NC = D / 32;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x / kWave;
+    constexpr int RS = D + 8;                 // LDS row stride (halves)
+    constexpr int CPR = D / 8;                // 16-byte chunks per row and half
+    constexpr int CHUNKS = 16 * CPR * 2;      // chunks per tile (hi and lo)
+    __shared__ _Float16 hs[2][16][RS], ls[2][16][RS];
+    __shared__ float cs[2][16];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wid = tid / kWave;
     const int g = lane >> 4;
     const int li = lane & 15;
+    // every wave takes part in the barriers; rows beyond n are clamped
     const int pbase = (blockIdx.x * 4 + wid) * 16 * PS;
-    if (pbase >= p.n) return;
     half8 bh[PS][NC], bl[PS][NC];
 #pragma unroll
     for (int ps = 0; ps < PS; ++ps) {
@@ -402,6 +398,7 @@ __global__ __launch_bounds__(256) void k_assign_h(KmeansPlan p) {
             bl[ps][c] = *reinterpret_cast<const half8*>(lr + 32 * c);
         }
     }
+    // the group's candidates, one per lane (the same in every wave)
     const int t0 = p.agrp[blockIdx.y], t1 = p.agrp[blockIdx.y + 1];
     const int nc = min(t1 - t0, kWave);
     int my_k = 0, my_tiles = 0, my_off = 0;
@@ -413,16 +410,53 @@ __global__ __launch_bounds__(256) void k_assign_h(KmeansPlan p) {
         my_off = p.koff16[my_k];
     }
     const uint64_t amask = __ballot(my_act);
-    if (amask == 0) return;
+    if (amask == 0) return;                   // uniform across the work-group
     const float dsc = ldexpf(1.0f, -2 * split_exp(p));
+    const _Float16* chp = reinterpret_cast<const _Float16*>(p.ch);
+    const _Float16* clp = reinterpret_cast<const _Float16*>(p.cl);
+    // tile loader: global -> registers (issued early), registers -> LDS
+    uint4 stage[(CHUNKS + 255) / 256];
+    float cstage = 0.f;
+    auto issue = [&](int koff_, int tile_) {
+        const int base = koff_ + tile_ * 16;
+#pragma unroll
+        for (int q = 0; q < (CHUNKS + 255) / 256; ++q) {
+            const int c = tid + 256 * q;
+            if (c < CHUNKS) {
+                const int which = c / (16 * CPR), rem = c - which * (16 * CPR);
+                const int r = rem / CPR, c8 = rem - r * CPR;
+                const _Float16* src = (which ? clp : chp) + (size_t)(base + r) * D + 8 * c8;
+                stage[q] = *reinterpret_cast<const uint4*>(src);
+            }
+        }
+        if (tid < 16) cstage = p.cnorm[base + tid];
+    };
+    auto commit = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < (CHUNKS + 255) / 256; ++q) {
+            const int c = tid + 256 * q;
+            if (c < CHUNKS) {
+                const int which = c / (16 * CPR), rem = c - which * (16 * CPR);
+                const int r = rem / CPR, c8 = rem - r * CPR;
+                _Float16* dst = (which ? &ls[buf][r][0] : &hs[buf][r][0]) + 8 * c8;
+                *reinterpret_cast<uint4*>(dst) = stage[q];
+            }
+        }
+        if (tid < 16) cs[buf][tid] = cstage;
+    };
+    // the walk: position t in the group, tile within the candidate
     int t = __builtin_ctzll(amask);
     int k = __builtin_amdgcn_readlane(my_k, t);
     int ntiles = __builtin_amdgcn_readlane(my_tiles, t);
     int koff = __builtin_amdgcn_readlane(my_off, t);
     int tile = 0;
-    half8 nah[NC], nal[NC];
-    float4 cnn;
-    load_ctile_h<NC>(p, koff, li, g, nah, nal, cnn);
+    issue(koff, 0);
+    commit(0);
+    __syncthreads();
+    const int ptl = pbase + 16 * g + li;
+    const bool wl = g < PS && ptl < p.n;
+    uint8_t old_lab = wl ? p.lab_cm[(size_t)k * p.n + ptl] : 0;
+    uint8_t next_old = 0;
     float bv[PS];
     int bi[PS];
 #pragma unroll
@@ -430,14 +464,9 @@ __global__ __launch_bounds__(256) void k_assign_h(KmeansPlan p) {
         bv[ps] = INFINITY;
         bi[ps] = 0;
     }
+    int buf = 0;
     while (true) {
-        half8 ah[NC], al[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            ah[c] = nah[c];
-            al[c] = nal[c];
-        }
-        const float cnv[4] = {cnn.x, cnn.y, cnn.z, cnn.w};
+        // next tile of the walk, and the issue of its loads
         int nk = k, ntile = tile + 1, nt = t, nntiles = ntiles, nkoff = koff;
         if (ntile >= ntiles) {
             ntile = 0;
@@ -447,9 +476,20 @@ __global__ __launch_bounds__(256) void k_assign_h(KmeansPlan p) {
                 nk = __builtin_amdgcn_readlane(my_k, nt);
                 nntiles = __builtin_amdgcn_readlane(my_tiles, nt);
                 nkoff = __builtin_amdgcn_readlane(my_off, nt);
+                next_old = wl ? p.lab_cm[(size_t)nk * p.n + ptl] : 0;
             }
         }
-        if (nt < nc) load_ctile_h<NC>(p, nkoff + ntile * 16, li, g, nah, nal, cnn);
+        const bool more = nt < nc;
+        if (more) issue(nkoff, ntile);
+        // this tile's operands from LDS
+        half8 ah[NC], al[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            ah[c] = *reinterpret_cast<const half8*>(&hs[buf][li][8 * g + 32 * c]);
+            al[c] = *reinterpret_cast<const half8*>(&ls[buf][li][8 * g + 32 * c]);
+        }
+        const float4 cnn = *reinterpret_cast<const float4*>(&cs[buf][4 * g]);
+        const float cnv[4] = {cnn.x, cnn.y, cnn.z, cnn.w};
 #pragma unroll
         for (int ps = 0; ps < PS; ++ps) {
             floatx4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -485,19 +525,20 @@ __global__ __launch_bounds__(256) void k_assign_h(KmeansPlan p) {
                 bv[ps] = INFINITY;
                 bi[ps] = 0;
             }
-            const int pt = pbase + 16 * g + li;
             bool changed = false;
-            if (g < PS && pt < p.n) {
-                uint8_t* lp = p.lab_cm + (size_t)k * p.n + pt;
-                const uint8_t old = *lp;
+            if (wl) {
                 const uint8_t nw = (uint8_t)mine;
-                changed = old != nw;
-                *lp = nw;
+                changed = old_lab != nw;
+                p.lab_cm[(size_t)k * p.n + ptl] = nw;
             }
             const uint64_t m = __ballot(changed);
-            if (lane == 0 && m) atomicAdd(&p.changes[k], (int)__popcll(m));
+            if (lane == 0 && m) p.changes[k] = 1;   // only zero / non-zero is read
         }
-        if (nt >= nc) break;
+        if (!more) break;                     // uniform across the work-group
+        commit(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+        if (nt != t) old_lab = next_old;
         k = nk;
         tile = ntile;
         t = nt;
@@ -508,6 +549,8 @@ __global__ __launch_bounds__(256) void k_assign_h(KmeansPlan p) {
 
 // After an assignment: a candidate whose labels did not change (from the
 // second assignment on) has converged; count the remaining active ones.
+// changes[k] is a flag (plain stores of 1): a counter updated by every wave
+// serialises tens of thousands of atomics on a few cache lines.
 __global__ __launch_bounds__(256) void k_iter_finalize(KmeansPlan p, int it, int t_max) {
     __shared__ int cnt;
     if (threadIdx.x == 0) cnt = 0;
