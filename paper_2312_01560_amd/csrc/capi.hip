@@ -374,8 +374,11 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
     km.zl = a.take<uint16_t>(km.split ? (size_t)n * P.d : 1);
     km.ch = a.take<uint16_t>(km.split ? (size_t)G.KP * P.d : 1);
     km.cl = a.take<uint16_t>(km.split ? (size_t)G.KP * P.d : 1);
-    km.psum = a.take<float>((size_t)P.ranges_max * G.KP * P.d);
+    km.S64 = a.take<long long>((size_t)G.KP * P.d);
+    km.N32 = a.take<int32_t>(G.KP);
+    km.pdelta = a.take<long long>((size_t)P.ranges_max * G.KP * P.d);
     km.pcnt = a.take<int32_t>((size_t)P.ranges_max * G.KP);
+    km.pdirty = a.take<uint8_t>((size_t)P.ranges_max * G.KP);
     km.zmax_bits = a.take<uint32_t>(1);
     km.w = a.take<float>(n);
     km.race_val = a.take<double>(P.race_grid);
@@ -384,6 +387,7 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
     P.picks_int = a.take<int32_t>(G.k_max);
     km.picks = P.picks_int;
     km.lab_cm = a.take<uint8_t>((size_t)G.Kc * n);
+    km.lab_old = a.take<uint8_t>((size_t)G.Kc * n);
     km.status = ctx->d_status;
     // scores
     ScorePlan& sc = P.sc;

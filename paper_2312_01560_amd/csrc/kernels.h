@@ -92,8 +92,11 @@ struct KmeansPlan {
     uint16_t* zl;            // [n x d]
     uint16_t* ch;            // [KP x d]
     uint16_t* cl;            // [KP x d]
-    float* psum;             // [max ranges x KP x d] per-range centre sums
-    int32_t* pcnt;           // [max ranges x KP]
+    long long* S64;          // [KP x d] centre sums, fixed point (z * 2^e as int32, summed)
+    int32_t* N32;            // [KP] cluster sizes
+    long long* pdelta;       // [max ranges x KP x d] per-range changes of S64 (flagged rows)
+    int32_t* pcnt;           // [max ranges x KP] per-range changes of N32
+    uint8_t* pdirty;         // [max ranges x KP] a point moved into or out of the row
     uint32_t* zmax_bits;     // [1] largest |z| (float bits), sets the fixed-point scale
     float* w;                // [n]
     double* race_val;        // [race_grid]
@@ -101,6 +104,7 @@ struct KmeansPlan {
     uint32_t* race_counter;  // [1]
     int32_t* picks;          // [k_max]
     uint8_t* lab_cm;         // [Kc x n] candidate-major labels
+    uint8_t* lab_old;        // [Kc x n] labels before the last assignment (0xFF: none)
     int32_t* status;
 };
 

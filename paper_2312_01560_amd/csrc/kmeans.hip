@@ -345,6 +345,7 @@ __global__ __launch_bounds__(256) void k_assign(KmeansPlan p, const float* __res
                 const uint8_t nw = (uint8_t)mine;
                 changed = old != nw;
                 *lp = nw;
+                p.lab_old[(size_t)k * p.n + pt] = old;
             }
             const uint64_t m = __ballot(changed);
             if (lane == 0 && m) p.changes[k] = 1;   // only zero / non-zero is read
@@ -530,6 +531,7 @@ __global__ __launch_bounds__(256) void k_assign_h(KmeansPlan p) {
                 const uint8_t nw = (uint8_t)mine;
                 changed = old_lab != nw;
                 p.lab_cm[(size_t)k * p.n + ptl] = nw;
+                p.lab_old[(size_t)k * p.n + ptl] = old_lab;
             }
             const uint64_t m = __ballot(changed);
             if (lane == 0 && m) p.changes[k] = 1;   // only zero / non-zero is read
@@ -612,22 +614,41 @@ __global__ __launch_bounds__(256) void k_split_points(KmeansPlan p, const float*
         split_half(Z[i], sc, p.zh + i, p.zl + i);
 }
 
-// Centre sums for one work item (update group, point range) and one slice of
-// up to 64 columns.  Points are quantised to int32 (z * 2^e) and summed in
-// int64 LDS accumulators shared by all waves of the work-group: integer
-// addition is associative, so the sums do not depend on the order of the
-// atomic adds (deterministic), and integer LDS atomics are fast on this
-// hardware where float ones are not.  A wave holds a chunk of 64 points of
-// its slice in registers (lane = column) and adds each point, one contiguous
-// accumulator row per instruction (no bank conflicts), into the cluster row
-// of every active candidate of the group; padding points go to a dummy row,
-// so the inner loop has no branches.  A group's points are split into as
-// many ranges as it has candidates times a constant, so work items carry
-// equal work.  Each range's exact sums are written as FP32 partials,
-// combined in FP64 in a fixed order by k_update_finish.
+// Centre update, incremental and exact.  The sums of every centre are kept
+// between iterations as integers: each point is quantised to int32
+// (z * 2^e, e fixed for the whole partition) and a centre's sum is an int64
+// total of such values.  An assignment records each point's previous label
+// next to the new one; the update then adds the points whose label changed
+// to their new cluster and subtracts them from their old one (the first
+// assignment has no old cluster).  Integer addition is associative, so the
+// totals equal those of summing every cluster from scratch, in any order,
+// while the work shrinks with the number of moved points.
+//
+// One work item = (update group, point range) and one slice of up to 64
+// columns.  Per chunk of 64 points a wave first reads both label columns of
+// every candidate of the group (lane = point) into LDS and counts the moves,
+// then loads z of the points that moved for any candidate (lane = column,
+// one register per point), and walks the candidates again applying the +/-
+// into int64 LDS accumulators shared by the work-group, one contiguous
+// accumulator row per instruction.  A candidate where most points moved and
+// none had a cluster before (the first assignment) takes a branch-free sweep
+// over the chunk (unmoved points go to a dummy row); otherwise each point is
+// a uniform bit test, skipped when it did not move.  At the end the
+// work-group writes, per accumulator row, a flag saying whether any point
+// moved in or out and, if so, the row's partial sums and count change;
+// k_update_finish folds the flagged partials of each row into the totals.
 constexpr int kUpdWaves = 4;
 constexpr int kUpdMaxCand = 16;
 constexpr int kUpdSlice = 64;
+// label staging: [wave][candidate][point] bytes, new and previous labels
+constexpr size_t kUpdStageBytes = (size_t)2 * kUpdWaves * kUpdMaxCand * kWave;
+
+// int32 -> int64 at the point of use: the empty asm keeps the compiler from
+// hoisting 64 widened copies out of the candidate loop (128 more registers).
+__device__ __forceinline__ unsigned long long widen_at_use(int x) {
+    asm volatile("" : "+v"(x));
+    return (unsigned long long)(long long)x;
+}
 
 __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __restrict__ Z) {
     extern __shared__ unsigned long long acc64[];
@@ -650,10 +671,17 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int total_rows = rows + 1;                          // + one dummy row
     int* cnt = reinterpret_cast<int*>(acc64 + (size_t)total_rows * kUpdSlice);
+    int* touch = cnt + total_rows;
+    uint8_t* stage_n = reinterpret_cast<uint8_t*>(touch + total_rows) +
+                       (size_t)wid * 2 * kUpdMaxCand * kWave;
+    uint8_t* stage_o = stage_n + kUpdMaxCand * kWave;
     for (int idx = threadIdx.x; idx < total_rows * kUpdSlice; idx += blockDim.x) acc64[idx] = 0ull;
-    for (int idx = threadIdx.x; idx < total_rows; idx += blockDim.x) cnt[idx] = 0;
+    for (int idx = threadIdx.x; idx < total_rows; idx += blockDim.x) {
+        cnt[idx] = 0;
+        touch[idx] = 0;
+    }
     __syncthreads();
-    const float sc = ldexpf(1.0f, fixed_exp(p));
+    const int fe = fixed_exp(p);
     const int dummy = rows;
     const int col = sl * kUpdSlice + lane;
     const bool on = col < p.d;
@@ -661,78 +689,115 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
     const int r0 = slot * len;
     const int r1 = min(p.n, r0 + len);
     unsigned long long* acol = acc64 + lane;
-    // the group's candidates (uniform): label column, accumulator base row
     const int nc = t1 - t0;
-    const uint8_t* labp[kUpdMaxCand];
-    int rbase[kUpdMaxCand];
-    bool act[kUpdMaxCand];
-    {
-        int base = 0;
-#pragma unroll
-        for (int m = 0; m < kUpdMaxCand; ++m) {
-            act[m] = false;
-            labp[m] = p.lab_cm;
-            rbase[m] = 0;
-            if (m < nc) {
-                const int k = p.alist[t0 + m];
-                act[m] = p.active[k] != 0;
-                labp[m] = p.lab_cm + (size_t)k * p.n;
-                rbase[m] = base;
-                base += p.ks[k];
-            }
-        }
-    }
     for (int cs = r0 + wid * kWave; cs < r1; cs += kUpdWaves * kWave) {
         const int np = min(kWave, r1 - cs);
-        // every load of the chunk is issued before any atomic
+        const bool lv = lane < np;
+        // pass 1: labels to LDS, counts, and the points moved for any candidate
+        uint64_t U = 0;
+        {
+            int base = 0;
+            for (int m = 0; m < nc; ++m) {
+                const int k = p.alist[t0 + m];
+                const int K = p.ks[k];
+                int nl = 0, ol = 0;
+                if (p.active[k] != 0 && lv) {
+                    nl = p.lab_cm[(size_t)k * p.n + cs + lane];
+                    ol = p.lab_old[(size_t)k * p.n + cs + lane];
+                }
+                stage_n[m * kWave + lane] = (uint8_t)nl;
+                stage_o[m * kWave + lane] = (uint8_t)ol;
+                const bool moved = nl != ol;
+                U |= __ballot(moved);
+                if (moved) {
+                    atomicAdd(&touch[base + nl], 1);
+                    if (sl == 0) atomicAdd(&cnt[base + nl], 1);
+                    if (ol != 0xFF) {
+                        atomicAdd(&touch[base + ol], 1);
+                        if (sl == 0) atomicSub(&cnt[base + ol], 1);
+                    }
+                }
+                base += K;
+            }
+        }
+        if (U == 0) continue;
+        // z of the moved points (lane = column)
         int zf[kWave];
 #pragma unroll
         for (int q = 0; q < kWave; ++q) {
-            const int pt = cs + min(q, np - 1);
-            const float v = (on && q < np) ? Z[(size_t)pt * p.d + col] : 0.f;
-            zf[q] = __float2int_rn(v * sc);
+            float v = 0.f;
+            if (((U >> q) & 1ull) && on) v = Z[(size_t)(cs + q) * p.d + col];
+            zf[q] = __float2int_rn(ldexpf(v, fe));
         }
-        int row[kUpdMaxCand];
-#pragma unroll
-        for (int m = 0; m < kUpdMaxCand; ++m)
-            if (act[m]) row[m] = lane < np ? rbase[m] + (int)labp[m][cs + lane] : dummy;
-#pragma unroll
-        for (int m = 0; m < kUpdMaxCand; ++m) {
-            if (act[m]) {
-                if (sl == 0) atomicAdd(&cnt[row[m]], 1);
+        // pass 2: the adds and subtractions, candidate by candidate
+        int base = 0;
+        for (int m = 0; m < nc; ++m) {
+            const int K = p.ks[p.alist[t0 + m]];
+            const int nl = stage_n[m * kWave + lane];
+            const int ol = stage_o[m * kWave + lane];
+            const bool moved = nl != ol;
+            const bool had = moved && ol != 0xFF;
+            const uint64_t mv = __ballot(moved);
+            const uint64_t mo = __ballot(had);
+            const int nrow = moved ? base + nl : dummy;
+            const int orow = had ? base + ol : dummy;
+            base += K;
+            if (mv == 0) continue;
+            if (mo == 0 && __popcll(mv) >= kWave / 2) {
 #pragma unroll
                 for (int q = 0; q < kWave; ++q) {
-                    const int a = __builtin_amdgcn_readlane(row[m], q);
-                    atomicAdd(acol + (size_t)a * kUpdSlice, (unsigned long long)(long long)zf[q]);
+                    const int a = __builtin_amdgcn_readlane(nrow, q);
+                    atomicAdd(acol + (size_t)a * kUpdSlice, widen_at_use(zf[q]));
+                }
+                continue;
+            }
+#pragma unroll
+            for (int q = 0; q < kWave; ++q) {
+                if ((mv >> q) & 1ull) {
+                    const int a = __builtin_amdgcn_readlane(nrow, q);
+                    atomicAdd(acol + (size_t)a * kUpdSlice, widen_at_use(zf[q]));
+                }
+            }
+            if (mo == 0) continue;
+#pragma unroll
+            for (int q = 0; q < kWave; ++q) {
+                if ((mo >> q) & 1ull) {
+                    const int o = __builtin_amdgcn_readlane(orow, q);
+                    atomicSub(acol + (size_t)o * kUpdSlice, widen_at_use(zf[q]));
                 }
             }
         }
     }
     __syncthreads();
-    const float inv = ldexpf(1.0f, -fixed_exp(p));
-    const int sw = min(kUpdSlice, p.d);
+    const int sw = min(kUpdSlice, p.d - sl * kUpdSlice);
     int base = 0;
     for (int t = t0; t < t1; ++t) {
         const int k = p.alist[t];
         const int K = p.ks[k];
         if (p.active[k]) {
-            float* dst = p.psum + ((size_t)slot * p.KP + p.koff16[k]) * p.d + sl * kUpdSlice;
-            for (int idx = threadIdx.x; idx < K * sw; idx += blockDim.x) {
-                const int r = idx / sw, cc = idx - (idx / sw) * sw;
-                const long long v = (long long)acc64[(size_t)(base + r) * kUpdSlice + cc];
-                dst[(size_t)r * p.d + cc] = (float)((double)v * (double)inv);
+            const size_t row0 = (size_t)slot * p.KP + p.koff16[k];
+            long long* dst = p.pdelta + row0 * p.d + sl * kUpdSlice;
+            for (int r = wid; r < K; r += kUpdWaves) {
+                if (touch[base + r] == 0) continue;          // uniform per wave
+                if (lane < sw)
+                    dst[(size_t)r * p.d + lane] =
+                        (long long)acc64[(size_t)(base + r) * kUpdSlice + lane];
             }
             if (sl == 0)
-                for (int idx = threadIdx.x; idx < K; idx += blockDim.x)
-                    p.pcnt[(size_t)slot * p.KP + p.koff16[k] + idx] = cnt[base + idx];
+                for (int idx = threadIdx.x; idx < K; idx += blockDim.x) {
+                    p.pdirty[row0 + idx] = touch[base + idx] != 0 ? 1 : 0;
+                    p.pcnt[row0 + idx] = cnt[base + idx];
+                }
         }
         base += K;
     }
 }
 
-// Means from the range partials; an empty cluster keeps its centre.  One
-// work-group per padded centre row: 4 slices of the ranges x 64 columns,
-// each slice summed in FP64 in order, the slices combined in order.
+// Folds the flagged partials of one centre row into its integer totals and
+// recomputes the centre as total * 2^-e / count (FP64, then FP32); a row no
+// point moved into or out of keeps its centre, and so does an empty cluster.
+// One work-group per padded centre row: 4 slices of the ranges x 64 columns;
+// the integer sums do not depend on the order.
 __global__ __launch_bounds__(256) void k_update_finish(KmeansPlan p) {
     const int c = blockIdx.x;
     const int k = p.cand_of[c];
@@ -743,40 +808,59 @@ __global__ __launch_bounds__(256) void k_update_finish(KmeansPlan p) {
     const int nr = p.cranges[k];
     const int per = (nr + 3) / 4;
     const int ch0 = q * per, ch1 = min(nr, ch0 + per);
-    __shared__ double part[4][kWave];
-    __shared__ int pc[4];
-    int count = 0;
-    for (int ch = ch0 + lane; ch < ch1; ch += kWave) count += p.pcnt[(size_t)ch * p.KP + c];
+    __shared__ long long part[4][kWave];
+    __shared__ int pc[4], pd[4];
+    int count = 0, dirty = 0;
+    for (int ch = ch0 + lane; ch < ch1; ch += kWave) {
+        const size_t r = (size_t)ch * p.KP + c;
+        if (p.pdirty[r]) {
+            count += p.pcnt[r];
+            dirty = 1;
+        }
+    }
     count = wave_sum(count);
-    if (lane == 0) pc[q] = count;
+    dirty = wave_sum(dirty);
+    if (lane == 0) {
+        pc[q] = count;
+        pd[q] = dirty;
+    }
+    __syncthreads();
+    if (pd[0] + pd[1] + pd[2] + pd[3] == 0) return;   // uniform: nothing moved
+    const int total = p.N32[c] + ((pc[0] + pc[1]) + pc[2]) + pc[3];
+    const double inv = ldexp(1.0, -fixed_exp(p));
     const size_t stride = (size_t)p.KP * p.d;
     float* crow = p.C + (size_t)c * p.d;
     float ss = 0.f;
     for (int d0 = 0; d0 < p.d; d0 += kWave) {
         const int dd = d0 + lane;
-        double s = 0.0;
+        long long s = 0;
         if (dd < p.d) {
-            const float* src = p.psum + (size_t)c * p.d + dd;
-            for (int ch = ch0; ch < ch1; ++ch) s += (double)src[ch * stride];
+            const long long* src = p.pdelta + (size_t)c * p.d + dd;
+            for (int ch = ch0; ch < ch1; ++ch)
+                if (p.pdirty[(size_t)ch * p.KP + c]) s += src[ch * stride];
         }
         __syncthreads();
         part[q][lane] = s;
         __syncthreads();
-        const int total = pc[0] + pc[1] + pc[2] + pc[3];
-        if (total == 0) return;   // uniform across the work-group
         if (q == 0 && dd < p.d) {
-            const double t = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
-            const float v = (float)(t / (double)total);
-            crow[dd] = v;
-            if (p.split)
-                split_half(v, ldexpf(1.0f, split_exp(p)), p.ch + (size_t)c * p.d + dd,
-                           p.cl + (size_t)c * p.d + dd);
-            ss += v * v;
+            const long long t =
+                p.S64[(size_t)c * p.d + dd] + part[0][lane] + part[1][lane] + part[2][lane] +
+                part[3][lane];
+            p.S64[(size_t)c * p.d + dd] = t;
+            if (total > 0) {
+                const float v = (float)((double)t * inv / (double)total);
+                crow[dd] = v;
+                if (p.split)
+                    split_half(v, ldexpf(1.0f, split_exp(p)), p.ch + (size_t)c * p.d + dd,
+                               p.cl + (size_t)c * p.d + dd);
+                ss += v * v;
+            }
         }
     }
     if (q == 0) {
+        if (lane == 0) p.N32[c] = total;
         ss = wave_sum(ss);
-        if (lane == 0) p.cnorm[c] = ss;
+        if (lane == 0 && total > 0) p.cnorm[c] = ss;
     }
 }
 
@@ -784,6 +868,8 @@ __global__ void k_kmeans_reset(KmeansPlan p) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = tid; i < (int64_t)p.Kc * p.n; i += stride) p.lab_cm[i] = 0xFF;
+    for (int64_t i = tid; i < (int64_t)p.KP * p.d; i += stride) p.S64[i] = 0;
+    for (int64_t i = tid; i < p.KP; i += stride) p.N32[i] = 0;
     for (int64_t k = tid; k < p.Kc; k += stride) {
         p.active[k] = 1;
         p.changes[k] = 0;
@@ -805,7 +891,8 @@ int kmeans_race_grid(int32_t n, int num_cu) {
 
 size_t kmeans_update_lds(int sum_rows, int d) {
     (void)d;
-    return (size_t)(sum_rows + 1) * (kUpdSlice * sizeof(unsigned long long) + sizeof(int));
+    return (size_t)(sum_rows + 1) * (kUpdSlice * sizeof(unsigned long long) + 2 * sizeof(int)) +
+           kUpdStageBytes;
 }
 
 int kmeans_update_rows(int K) { return K; }
