@@ -174,9 +174,11 @@ struct Lists {
 // Length of the dynamic work lists (see pack_lists).
 constexpr int kDynLen(int Kc) { return 6 * Kc + 3; }
 
-// Point ranges per update group are capped so the partial buffers stay bounded.
+// Point ranges per update group are capped so the partial buffers stay
+// bounded, and at 256 so each of the finishing kernel's 4 waves folds at most
+// 64 ranges (one per lane).
 int update_ranges_max(int n, int num_cu) {
-    return std::max(1, std::min(num_cu, (n + 63) / 64));
+    return std::max(1, std::min(std::min(num_cu, 256), (n + 63) / 64));
 }
 
 Lists make_lists(const Grid& G, const int32_t* active, int ucap, int n, int num_cu) {

@@ -232,6 +232,43 @@ __device__ __forceinline__ void load_ctile(const KmeansPlan& p, int cb, int li, 
     cn = *reinterpret_cast<const float4*>(p.cnorm + cb + 4 * g);
 }
 
+// End of a candidate in the assignment kernels.  Lane (li, g) holds, for
+// each point 16 ps + li of its wave, the best score and row over the centre
+// rows 4g..4g+3 of every tile; the four lane groups are folded through a
+// wave-private LDS area (fold: PS x 64 floats then PS x 64 ints): each lane
+// writes its PS partials, then lane (li, g) reads the four partials of point
+// 16 g + li and keeps the lowest score, the lowest row among equal scores.
+// Returns that row (0 for lanes with g >= PS) and resets the partials.
+template <int PS>
+__device__ __forceinline__ int fold_lane_groups(float (&bv)[PS], int (&bi)[PS], float* fold,
+                                                int lane) {
+    const int li = lane & 15, g = lane >> 4;
+    int* foldi = reinterpret_cast<int*>(fold + PS * kWave);
+#pragma unroll
+    for (int ps = 0; ps < PS; ++ps) {
+        fold[lane * PS + ps] = bv[ps];
+        foldi[lane * PS + ps] = bi[ps];
+        bv[ps] = INFINITY;
+        bi[ps] = 0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    int best = 0;
+    if (g < PS) {
+        float v = fold[li * PS + g];
+        best = foldi[li * PS + g];
+#pragma unroll
+        for (int h = 1; h < 4; ++h) {
+            const float ov = fold[(h * 16 + li) * PS + g];
+            const int oi = foldi[(h * 16 + li) * PS + g];
+            const bool take = (ov < v) | ((ov == v) & (oi < best));
+            v = take ? ov : v;
+            best = take ? oi : best;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    return best;
+}
+
 template <int D, int PS>
 __global__ __launch_bounds__(256) void k_assign(KmeansPlan p, const float* __restrict__ Z) {
     constexpr int KS = D / 4;
@@ -239,6 +276,8 @@ __global__ __launch_bounds__(256) void k_assign(KmeansPlan p, const float* __res
     const int wid = threadIdx.x / kWave;
     const int g = lane >> 4;
     const int li = lane & 15;
+    __shared__ float fold_all[4][2 * PS * kWave];
+    float* fold = fold_all[wid];
     const int pbase = (blockIdx.x * 4 + wid) * 16 * PS;
     if (pbase >= p.n) return;
     float b[PS][KS];
@@ -321,22 +360,7 @@ __global__ __launch_bounds__(256) void k_assign(KmeansPlan p, const float* __res
         }
         if (tile == ntiles - 1) {
             // candidate finished: fold the lane groups, write labels, count changes
-            int mine = 0;
-#pragma unroll
-            for (int ps = 0; ps < PS; ++ps) {
-#pragma unroll
-                for (int off = 16; off < kWave; off <<= 1) {
-                    const float ov = __shfl_xor(bv[ps], off, kWave);
-                    const int oi = __shfl_xor(bi[ps], off, kWave);
-                    if (ov < bv[ps] || (ov == bv[ps] && oi < bi[ps])) {
-                        bv[ps] = ov;
-                        bi[ps] = oi;
-                    }
-                }
-                if (ps == g) mine = bi[ps];
-                bv[ps] = INFINITY;
-                bi[ps] = 0;
-            }
+            const int mine = fold_lane_groups<PS>(bv, bi, fold, lane);
             const int pt = pbase + 16 * g + li;
             bool changed = false;
             if (g < PS && pt < p.n) {
@@ -379,6 +403,7 @@ __global__ __launch_bounds__(256) void k_assign_h(KmeansPlan p) {
     constexpr int CHUNKS = 16 * CPR * 2;      // chunks per tile (hi and lo)
     __shared__ _Float16 hs[2][16][RS], ls[2][16][RS];
     __shared__ float cs[2][16];
+    __shared__ float fold_all[4][2 * PS * kWave];
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wid = tid / kWave;
@@ -412,7 +437,9 @@ __global__ __launch_bounds__(256) void k_assign_h(KmeansPlan p) {
     }
     const uint64_t amask = __ballot(my_act);
     if (amask == 0) return;                   // uniform across the work-group
-    const float dsc = ldexpf(1.0f, -2 * split_exp(p));
+    // scores in units of 2^(1-2s): cnorm 2^(2s-1) - acc orders the centres
+    // exactly as cnorm - 2 z.c does (scaling by a power of two is exact)
+    const int nexp = 2 * split_exp(p) - 1;
     const _Float16* chp = reinterpret_cast<const _Float16*>(p.ch);
     const _Float16* clp = reinterpret_cast<const _Float16*>(p.cl);
     // tile loader: global -> registers (issued early), registers -> LDS
@@ -443,7 +470,7 @@ __global__ __launch_bounds__(256) void k_assign_h(KmeansPlan p) {
                 *reinterpret_cast<uint4*>(dst) = stage[q];
             }
         }
-        if (tid < 16) cs[buf][tid] = cstage;
+        if (tid < 16) cs[buf][tid] = ldexpf(cstage, nexp);
     };
     // the walk: position t in the group, tile within the candidate
     int t = __builtin_ctzll(amask);
@@ -491,18 +518,28 @@ __global__ __launch_bounds__(256) void k_assign_h(KmeansPlan p) {
         }
         const float4 cnn = *reinterpret_cast<const float4*>(&cs[buf][4 * g]);
         const float cnv[4] = {cnn.x, cnn.y, cnn.z, cnn.w};
+        // the PS accumulators are independent: interleaving them keeps the
+        // matrix unit busy instead of waiting on one dependent chain
+        floatx4 acc[PS];
+#pragma unroll
+        for (int ps = 0; ps < PS; ++ps) acc[ps] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+#pragma unroll
+            for (int ps = 0; ps < PS; ++ps)
+                acc[ps] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[c], bh[ps][c], acc[ps], 0, 0, 0);
+#pragma unroll
+            for (int ps = 0; ps < PS; ++ps)
+                acc[ps] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[c], bl[ps][c], acc[ps], 0, 0, 0);
+#pragma unroll
+            for (int ps = 0; ps < PS; ++ps)
+                acc[ps] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[c], bh[ps][c], acc[ps], 0, 0, 0);
+        }
 #pragma unroll
         for (int ps = 0; ps < PS; ++ps) {
-            floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[c], bh[ps][c], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[c], bl[ps][c], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[c], bh[ps][c], acc, 0, 0, 0);
-            }
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const float sc = cnv[v] - 2.0f * (acc[v] * dsc);
+                const float sc = cnv[v] - acc[ps][v];
                 if (sc < bv[ps]) {
                     bv[ps] = sc;
                     bi[ps] = tile * 16 + 4 * g + v;
@@ -510,22 +547,7 @@ __global__ __launch_bounds__(256) void k_assign_h(KmeansPlan p) {
             }
         }
         if (tile == ntiles - 1) {
-            int mine = 0;
-#pragma unroll
-            for (int ps = 0; ps < PS; ++ps) {
-#pragma unroll
-                for (int off = 16; off < kWave; off <<= 1) {
-                    const float ov = __shfl_xor(bv[ps], off, kWave);
-                    const int oi = __shfl_xor(bi[ps], off, kWave);
-                    if (ov < bv[ps] || (ov == bv[ps] && oi < bi[ps])) {
-                        bv[ps] = ov;
-                        bi[ps] = oi;
-                    }
-                }
-                if (ps == g) mine = bi[ps];
-                bv[ps] = INFINITY;
-                bi[ps] = 0;
-            }
+            const int mine = fold_lane_groups<PS>(bv, bi, fold_all[wid], lane);
             bool changed = false;
             if (wl) {
                 const uint8_t nw = (uint8_t)mine;
@@ -690,21 +712,37 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
     const int r1 = min(p.n, r0 + len);
     unsigned long long* acol = acc64 + lane;
     const int nc = t1 - t0;
+    // the group's candidates, one per lane, read back with readlane
+    int my_k = 0, my_K = 0, my_act = 0;
+    if (lane < nc) {
+        my_k = p.alist[t0 + lane];
+        my_K = p.ks[my_k];
+        my_act = p.active[my_k] != 0;
+    }
     for (int cs = r0 + wid * kWave; cs < r1; cs += kUpdWaves * kWave) {
         const int np = min(kWave, r1 - cs);
         const bool lv = lane < np;
-        // pass 1: labels to LDS, counts, and the points moved for any candidate
+        // pass 1: labels to LDS, counts, and the points moved for any candidate;
+        // every label load of the chunk is issued before the first is used
         uint64_t U = 0;
         {
-            int base = 0;
-            for (int m = 0; m < nc; ++m) {
-                const int k = p.alist[t0 + m];
-                const int K = p.ks[k];
-                int nl = 0, ol = 0;
-                if (p.active[k] != 0 && lv) {
-                    nl = p.lab_cm[(size_t)k * p.n + cs + lane];
-                    ol = p.lab_old[(size_t)k * p.n + cs + lane];
+            int nlv[kUpdMaxCand], olv[kUpdMaxCand];
+#pragma unroll
+            for (int m = 0; m < kUpdMaxCand; ++m) {
+                nlv[m] = 0;
+                olv[m] = 0;
+                const int k = __builtin_amdgcn_readlane(my_k, m);
+                if (m < nc && __builtin_amdgcn_readlane(my_act, m) != 0 && lv) {
+                    nlv[m] = p.lab_cm[(size_t)k * p.n + cs + lane];
+                    olv[m] = p.lab_old[(size_t)k * p.n + cs + lane];
                 }
+            }
+            int base = 0;
+#pragma unroll
+            for (int m = 0; m < kUpdMaxCand; ++m) {
+                if (m >= nc) break;
+                const int K = __builtin_amdgcn_readlane(my_K, m);
+                const int nl = nlv[m], ol = olv[m];
                 stage_n[m * kWave + lane] = (uint8_t)nl;
                 stage_o[m * kWave + lane] = (uint8_t)ol;
                 const bool moved = nl != ol;
@@ -721,18 +759,21 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
             }
         }
         if (U == 0) continue;
-        // z of the moved points (lane = column)
-        int zf[kWave];
+        // z of the moved points (lane = column): every load is issued before
+        // the first conversion, so the loads overlap
+        float zr[kWave];
 #pragma unroll
         for (int q = 0; q < kWave; ++q) {
-            float v = 0.f;
-            if (((U >> q) & 1ull) && on) v = Z[(size_t)(cs + q) * p.d + col];
-            zf[q] = __float2int_rn(ldexpf(v, fe));
+            zr[q] = 0.f;
+            if (((U >> q) & 1ull) && on) zr[q] = Z[(size_t)(cs + q) * p.d + col];
         }
+        int zf[kWave];
+#pragma unroll
+        for (int q = 0; q < kWave; ++q) zf[q] = __float2int_rn(ldexpf(zr[q], fe));
         // pass 2: the adds and subtractions, candidate by candidate
         int base = 0;
         for (int m = 0; m < nc; ++m) {
-            const int K = p.ks[p.alist[t0 + m]];
+            const int K = __builtin_amdgcn_readlane(my_K, m);
             const int nl = stage_n[m * kWave + lane];
             const int ol = stage_o[m * kWave + lane];
             const bool moved = nl != ol;
@@ -810,19 +851,15 @@ __global__ __launch_bounds__(256) void k_update_finish(KmeansPlan p) {
     const int ch0 = q * per, ch1 = min(nr, ch0 + per);
     __shared__ long long part[4][kWave];
     __shared__ int pc[4], pd[4];
-    int count = 0, dirty = 0;
-    for (int ch = ch0 + lane; ch < ch1; ch += kWave) {
-        const size_t r = (size_t)ch * p.KP + c;
-        if (p.pdirty[r]) {
-            count += p.pcnt[r];
-            dirty = 1;
-        }
-    }
+    // a wave's ranges (at most 64, one per lane): which of them saw a move
+    const int chl = ch0 + lane;
+    const bool dl = chl < ch1 && p.pdirty[(size_t)chl * p.KP + c] != 0;
+    const uint64_t dmask = __ballot(dl);
+    int count = dl ? p.pcnt[(size_t)chl * p.KP + c] : 0;
     count = wave_sum(count);
-    dirty = wave_sum(dirty);
     if (lane == 0) {
         pc[q] = count;
-        pd[q] = dirty;
+        pd[q] = dmask != 0;
     }
     __syncthreads();
     if (pd[0] + pd[1] + pd[2] + pd[3] == 0) return;   // uniform: nothing moved
@@ -836,8 +873,20 @@ __global__ __launch_bounds__(256) void k_update_finish(KmeansPlan p) {
         long long s = 0;
         if (dd < p.d) {
             const long long* src = p.pdelta + (size_t)c * p.d + dd;
-            for (int ch = ch0; ch < ch1; ++ch)
-                if (p.pdirty[(size_t)ch * p.KP + c]) s += src[ch * stride];
+            // the flagged ranges, four independent loads at a time
+            uint64_t rem = dmask;
+            while (rem) {
+                long long v[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    v[j] = 0;
+                    if (rem) {
+                        v[j] = src[(size_t)(ch0 + __builtin_ctzll(rem)) * stride];
+                        rem &= rem - 1;
+                    }
+                }
+                s += (v[0] + v[1]) + (v[2] + v[3]);
+            }
         }
         __syncthreads();
         part[q][lane] = s;
