@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define RAFT_ABI_VERSION 1
+#define RAFT_ABI_VERSION 2
 
 typedef int32_t raft_status;
 #define RAFT_OK             0
@@ -90,6 +90,10 @@ typedef struct {
     uint8_t* labels_all;   /* [N x Kc] labels of every candidate, point-major (nullable) */
     int32_t* picks;        /* [K_max] k-means++ picks (nullable)                     */
     int32_t* iters;        /* [Kc] Lloyd assignments performed (nullable)            */
+    float*   centres;      /* [sum of K x d] final centres, candidate after candidate in
+                            * grid order, K rows each (nullable).  A candidate that
+                            * converged has each non-empty centre equal to the mean of
+                            * its points; an empty cluster keeps its last centre.     */
 } raft_outputs;
 
 /* ---- context and errors ------------------------------------------------- */

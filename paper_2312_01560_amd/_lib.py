@@ -6,7 +6,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libraftgp.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 MAX_LAYERS = 8
 MAX_K = 255
 
@@ -59,6 +59,7 @@ class RaftOutputs(ctypes.Structure):
         ("labels_all", ctypes.c_void_p),
         ("picks", ctypes.c_void_p),
         ("iters", ctypes.c_void_p),
+        ("centres", ctypes.c_void_p),
     ]
 
 

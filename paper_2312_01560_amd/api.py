@@ -214,7 +214,7 @@ def embed(ctx, g, cfg, Y, ws=None, out=None):
     return out
 
 
-def _outputs(ctx, g, cfg, want_y=False, want_z=False):
+def _outputs(ctx, g, cfg, want_y=False, want_z=False, want_centres=False):
     kc = len(cfg.ks)
     o = {
         "labels": ctx.empty((g.n,), torch.int32),
@@ -229,6 +229,8 @@ def _outputs(ctx, g, cfg, want_y=False, want_z=False):
         o["Y"] = ctx.empty((g.n, cfg.proj_dim), torch.float32)
     if want_z:
         o["Z"] = ctx.empty((g.n, cfg.embed_dim), torch.float32)
+    if want_centres:
+        o["centres"] = ctx.empty((sum(cfg.ks), cfg.embed_dim), torch.float32)
     s = RaftOutputs()
     for name, _ in RaftOutputs._fields_:
         t = o.get(name)
@@ -236,20 +238,20 @@ def _outputs(ctx, g, cfg, want_y=False, want_z=False):
     return o, s
 
 
-def partition(ctx, g, cfg, Z, ws=None):
+def partition(ctx, g, cfg, Z, ws=None, want_centres=False):
     ws = _ws_for(ctx, g, cfg, ws)
-    o, s = _outputs(ctx, g, cfg)
+    o, s = _outputs(ctx, g, cfg, want_centres=want_centres)
     c = cfg.to_c()
     ctx.check(ctx.lib.raft_partition(ctx.h, g.h, ctypes.byref(c), _ptr(Z.contiguous()),
                                      _ptr(ws), ws.numel(), ctypes.byref(s), _stream()))
     return o
 
 
-def run(ctx, g, cfg, ws=None, want_y=True, want_z=True, outputs=None):
+def run(ctx, g, cfg, ws=None, want_y=True, want_z=True, outputs=None, want_centres=False):
     """A1-A7 on one graph; returns a dict of device tensors."""
     ws = _ws_for(ctx, g, cfg, ws)
     if outputs is None:
-        outputs = _outputs(ctx, g, cfg, want_y, want_z)
+        outputs = _outputs(ctx, g, cfg, want_y, want_z, want_centres)
     o, s = outputs
     c = cfg.to_c()
     ctx.check(ctx.lib.raft_run(ctx.h, g.h, ctypes.byref(c), _ptr(ws), ws.numel(), ctypes.byref(s),

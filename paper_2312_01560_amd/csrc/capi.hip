@@ -590,6 +590,7 @@ raft_status do_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* 
     }
     RAFT_TRY(launch_check(ctx));
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[4], st));
+    if (out && out->centres) launch_copy_centres(km, out->centres, st);
     launch_transpose_labels(km.lab_cm, g->n, P.grid.Kc, P.lab_pm, P.S, st);
     {
         ProfScope ps(ctx, RAFT_PROF_SCORE, st);

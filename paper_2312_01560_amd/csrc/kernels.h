@@ -127,6 +127,8 @@ bool kmeans_split_supported(int d);
 void launch_split_points(const KmeansPlan& p, const float* Z, hipStream_t st);
 void launch_iter_finalize(const KmeansPlan& p, int it, int t_max, hipStream_t st);
 void launch_update(const KmeansPlan& p, const float* Z, size_t lds_max, hipStream_t st);
+// Real centre rows of every candidate, compacted: out [SK x d] (grid order).
+void launch_copy_centres(const KmeansPlan& p, float* out, hipStream_t st);
 
 // ---- score.hip -----------------------------------------------------------
 struct ScorePlan {

@@ -738,9 +738,7 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
                 }
             }
             int base = 0;
-#pragma unroll
-            for (int m = 0; m < kUpdMaxCand; ++m) {
-                if (m >= nc) break;
+            for (int m = 0; m < nc; ++m) {
                 const int K = __builtin_amdgcn_readlane(my_K, m);
                 const int nl = nlv[m], ol = olv[m];
                 stage_n[m * kWave + lane] = (uint8_t)nl;
@@ -1019,6 +1017,24 @@ void launch_split_points(const KmeansPlan& p, const float* Z, hipStream_t st) {
     if (total == 0) return;
     const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
     hipLaunchKernelGGL(k_split_points, dim3(grid), dim3(256), 0, st, p, Z);
+}
+
+__global__ __launch_bounds__(256) void k_copy_centres(KmeansPlan p, float* __restrict__ out) {
+    const int64_t total = (int64_t)p.KP * p.d;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i / p.d), col = (int)(i - (int64_t)c * p.d);
+        const int k = p.cand_of[c];
+        const int r = c - p.koff16[k];
+        if (r < p.ks[k]) out[(size_t)(p.koff[k] + r) * p.d + col] = p.C[i];
+    }
+}
+
+void launch_copy_centres(const KmeansPlan& p, float* out, hipStream_t st) {
+    const int64_t total = (int64_t)p.KP * p.d;
+    if (total == 0) return;
+    const int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_copy_centres, dim3(grid), dim3(256), 0, st, p, out);
 }
 
 void launch_iter_finalize(const KmeansPlan& p, int it, int t_max, hipStream_t st) {

@@ -35,7 +35,7 @@ def test_config_struct_layout():
     # 19 int32 fields (76 bytes), padding to 8, then the uint64 seed
     assert _lib.RaftConfig.seed.offset == 80
     assert ctypes.sizeof(_lib.RaftConfig) == 88
-    assert ctypes.sizeof(_lib.RaftOutputs) == 9 * 8
+    assert ctypes.sizeof(_lib.RaftOutputs) == 10 * 8
 
 
 def test_no_device_is_an_error_not_a_crash():

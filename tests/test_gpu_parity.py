@@ -245,6 +245,49 @@ def test_kmeans_fixed_point(ctx, api_mod, ragged):
         assert np.all(mine <= d.min(axis=1) + 1e-5)
 
 
+def check_centres(centres, z64, lab, ks, iters, t_max, cands):
+    """Each non-empty centre of a converged candidate is the mean of its
+    points.  The library keeps exact integer sums of z 2^e (e = 30 - the
+    exponent of the largest |z|) across iterations and adds or subtracts only
+    the points that moved, so its centre may differ from the FP64 mean by the
+    quantisation (at most 2^-30 of the largest |z|) plus one FP32 rounding."""
+    zmax = np.abs(z64).max()
+    off = np.concatenate([[0], np.cumsum(ks)])
+    checked = 0
+    for j in cands:
+        if iters[j] >= t_max:
+            continue
+        c = centres[off[j]:off[j + 1]].astype(np.float64)
+        for r in range(ks[j]):
+            members = lab[:, j] == r
+            if not np.any(members):
+                continue
+            mean = z64[members].mean(0)
+            tol = 1.01 * (2.0 ** -24 * np.abs(mean) + 2.0 ** -29 * zmax)
+            assert np.all(np.abs(c[r] - mean) <= tol), (ks[j], r, np.abs(c[r] - mean).max())
+            checked += 1
+    assert checked > 0
+
+
+@pytest.mark.parametrize("d", [16, 64])
+def test_kmeans_centres_are_means(ctx, api_mod, ragged, d):
+    """The incremental update (only moved points added and subtracted) ends
+    with the same centres as a sum from scratch over the final labels, for
+    the FP32 (d = 16) and split-fp16 (d = 64) assignment paths."""
+    z = np.random.default_rng(3).standard_normal((ragged.n, d)).astype(np.float32)
+    z /= np.linalg.norm(z, axis=1, keepdims=True)
+    g = api_mod.Graph(ctx, ragged.row_ptr, ragged.col_idx)
+    cfg = api_mod.Config(op=0, proj_dim=d, layer_dims=[d], k_min=2, k_max=80, k_step=3,
+                         kmeans_max_iter=300)
+    out = api_mod.partition(ctx, g, cfg, torch.from_numpy(z).cuda(), want_centres=True)
+    torch.cuda.synchronize()
+    ctx.sync_status()
+    lab = to_np(out["labels_all"]).astype(np.int64)
+    iters = to_np(out["iters"])
+    check_centres(to_np(out["centres"]), z.astype(np.float64), lab, cfg.ks, iters, 300,
+                  range(len(cfg.ks)))
+
+
 # ---------------------------------------------------------------- A1-A7 --
 
 @pytest.mark.parametrize("op", [0, 1, 2])
@@ -362,7 +405,7 @@ def test_n50k_full_size(ctx, api_mod, n50k, op):
     ci = torch.from_numpy(g0.col_idx).cuda()
     g = api_mod.Graph(ctx, rp, ci)                      # device-resident input, as timed
     cfg = api_mod.Config(op=op, **m)
-    out = api_mod.run(ctx, g, cfg)
+    out = api_mod.run(ctx, g, cfg, want_centres=True)
     torch.cuda.synchronize()
     ctx.sync_status()
     y = projection.project(g0.row_ptr, g0.col_idx, g0.n, op, m["proj_dim"], m["q"], 0)
@@ -384,6 +427,8 @@ def test_n50k_full_size(ctx, api_mod, n50k, op):
         pos = {r: t for t, r in enumerate(live)}
         mine = d[np.arange(g0.n), [pos[r] for r in lab[:, j]]]
         assert np.all(mine <= d.min(axis=1) + 1e-5), k
+    check_centres(to_np(out["centres"]), z64, lab, cfg.ks, iters, cfg.kmeans_max_iter,
+                  range(0, len(cfg.ks), 6))
     rmod, rnc = scores.score_candidates(g0.row_ptr, g0.col_idx, lab, cfg.ks)
     assert np.array_equal(to_np(out["mod"]), rmod)
     assert np.array_equal(to_np(out["ncut"]), rnc)
