@@ -565,11 +565,13 @@ raft_status do_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* 
             ProfScope ps(ctx, RAFT_PROF_ASSIGN, st);
             launch_assign(km, Z, ctx->num_cu, st);
         }
-        launch_iter_finalize(km, it, t_max, st);
-        if (it == t_max) break;
+        if (it == t_max) {
+            launch_iter_finalize(km, it, t_max, st);
+            break;
+        }
         {
             ProfScope ps(ctx, RAFT_PROF_UPDATE, st);
-            launch_update(km, Z, ctx->lds_max, st);
+            launch_update(km, Z, ctx->lds_max, it, t_max, st);
         }
         if (it % check == 0) {
             HIP_TRY(ctx, hipMemcpyAsync(h_active, km.active, Kc * sizeof(int32_t),

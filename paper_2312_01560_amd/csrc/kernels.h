@@ -126,7 +126,10 @@ bool kmeans_split_supported(int d);
 // zh/zl from Z (after launch_zmax).
 void launch_split_points(const KmeansPlan& p, const float* Z, hipStream_t st);
 void launch_iter_finalize(const KmeansPlan& p, int it, int t_max, hipStream_t st);
-void launch_update(const KmeansPlan& p, const float* Z, size_t lds_max, hipStream_t st);
+// Update of iteration `it` followed by the end-of-iteration bookkeeping
+// (what launch_iter_finalize does, fused into the finishing kernel).
+void launch_update(const KmeansPlan& p, const float* Z, size_t lds_max, int it, int t_max,
+                   hipStream_t st);
 // Real centre rows of every candidate, compacted: out [SK x d] (grid order).
 void launch_copy_centres(const KmeansPlan& p, float* out, hipStream_t st);
 

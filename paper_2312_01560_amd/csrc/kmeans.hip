@@ -575,7 +575,8 @@ __global__ __launch_bounds__(256) void k_assign_h(KmeansPlan p) {
 // second assignment on) has converged; count the remaining active ones.
 // changes[k] is a flag (plain stores of 1): a counter updated by every wave
 // serialises tens of thousands of atomics on a few cache lines.
-__global__ __launch_bounds__(256) void k_iter_finalize(KmeansPlan p, int it, int t_max) {
+// One work-group: the whole candidate table.
+__device__ __forceinline__ void finalize_candidates(const KmeansPlan& p, int it, int t_max) {
     __shared__ int cnt;
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
@@ -597,6 +598,10 @@ __global__ __launch_bounds__(256) void k_iter_finalize(KmeansPlan p, int it, int
     atomicAdd(&cnt, mine);
     __syncthreads();
     if (threadIdx.x == 0) *p.active_count = cnt;
+}
+
+__global__ __launch_bounds__(256) void k_iter_finalize(KmeansPlan p, int it, int t_max) {
+    finalize_candidates(p, it, t_max);
 }
 
 // Largest |z| (bit pattern of a non-negative float orders as an integer):
@@ -837,7 +842,16 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
 // point moved into or out of keeps its centre, and so does an empty cluster.
 // One work-group per padded centre row: 4 slices of the ranges x 64 columns;
 // the integer sums do not depend on the order.
-__global__ __launch_bounds__(256) void k_update_finish(KmeansPlan p) {
+//
+// The extra work-group KP runs the end-of-iteration bookkeeping
+// (finalize_candidates) in the same launch: a candidate it retires has no
+// moved point, so no other work-group of this launch or of the update
+// depends on its flags.
+__global__ __launch_bounds__(256) void k_update_finish(KmeansPlan p, int it, int t_max) {
+    if ((int)blockIdx.x == p.KP) {
+        finalize_candidates(p, it, t_max);
+        return;
+    }
     const int c = blockIdx.x;
     const int k = p.cand_of[c];
     if (!p.active[k]) return;
@@ -1041,7 +1055,8 @@ void launch_iter_finalize(const KmeansPlan& p, int it, int t_max, hipStream_t st
     hipLaunchKernelGGL(k_iter_finalize, dim3(1), dim3(256), 0, st, p, it, t_max);
 }
 
-void launch_update(const KmeansPlan& p, const float* Z, size_t lds_max, hipStream_t st) {
+void launch_update(const KmeansPlan& p, const float* Z, size_t lds_max, int it, int t_max,
+                   hipStream_t st) {
     const size_t lds = kmeans_update_lds(p.usk_max, p.d);
     const int nsl = (p.d + kUpdSlice - 1) / kUpdSlice;
     dim3 grid(p.uwork, nsl);
@@ -1052,7 +1067,7 @@ void launch_update(const KmeansPlan& p, const float* Z, size_t lds_max, hipStrea
         attr_set = true;
     }
     hipLaunchKernelGGL(k_update, grid, dim3(kUpdWaves * kWave), lds, st, p, Z);
-    hipLaunchKernelGGL(k_update_finish, dim3(p.KP), dim3(256), 0, st, p);
+    hipLaunchKernelGGL(k_update_finish, dim3(p.KP + 1), dim3(256), 0, st, p, it, t_max);
 }
 
 }  // namespace raft
