@@ -24,6 +24,7 @@ struct raft_ctx {
     int32_t* h_pinned = nullptr;   // pinned host scratch (4096 ints)
     double stage_ms[5] = {0, 0, 0, 0, 0};
     hipEvent_t ev[6] = {};
+    hipEvent_t poll_ev[2] = {};    // convergence polls of the Lloyd loop (no timing)
     // per-kernel-class event timing (raft_profile_enable)
     uint32_t prof_mask = 0;
     std::vector<hipEvent_t> prof_pool;
@@ -558,8 +559,20 @@ raft_status do_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* 
     RAFT_TRY(launch_check(ctx));
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[3], st));
     const int Kc = P.grid.Kc;
-    int32_t* h_active = ctx->h_pinned + 16;
-    int32_t* h_lists = ctx->h_pinned + 16 + RAFT_MAX_K + 1;
+    // Convergence polls without stalling the GPU: at every `check`-th
+    // iteration the active flags are copied to pinned host memory behind an
+    // event, and the host acts on the copy of the previous poll (the GPU is
+    // past it and still has the iterations since queued).  The work lists
+    // built from it are one poll stale: they may still hold candidates that
+    // retired since, which every kernel skips, so results do not change.
+    // Two pinned slots each for the flags and the packed lists: a slot is
+    // rewritten only after the event of the poll that last used it.
+    int32_t* h_active[2] = {ctx->h_pinned + 16, ctx->h_pinned + 16 + (RAFT_MAX_K + 1)};
+    int32_t* h_lists[2] = {ctx->h_pinned + 16 + 2 * (RAFT_MAX_K + 1),
+                           ctx->h_pinned + 16 + 2 * (RAFT_MAX_K + 1) + kDynLen(RAFT_MAX_K)};
+    static_assert(16 + 2 * (RAFT_MAX_K + 1) + 2 * kDynLen(RAFT_MAX_K) <= 4096,
+                  "poll slots exceed the pinned scratch");
+    int poll = 0;
     for (int it = 1; it <= t_max; ++it) {
         {
             ProfScope ps(ctx, RAFT_PROF_ASSIGN, st);
@@ -574,20 +587,26 @@ raft_status do_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* 
             launch_update(km, Z, ctx->lds_max, it, t_max, st);
         }
         if (it % check == 0) {
-            HIP_TRY(ctx, hipMemcpyAsync(h_active, km.active, Kc * sizeof(int32_t),
+            if (poll > 0) {
+                HIP_TRY(ctx, hipEventSynchronize(ctx->poll_ev[(poll - 1) & 1]));
+                const int32_t* ha = h_active[(poll - 1) & 1];
+                int live = 0;
+                for (int k = 0; k < Kc; ++k) live += ha[k] != 0;
+                if (live == 0) break;
+                // compact the work lists to the candidates still iterating
+                const Lists l = make_lists(P.grid, ha, P.ucap, g->n, ctx->num_cu);
+                int32_t* hl = h_lists[poll & 1];
+                pack_lists(l, Kc, hl);
+                HIP_TRY(ctx, hipMemcpyAsync(P.dyn, hl, (size_t)kDynLen(Kc) * sizeof(int32_t),
+                                            hipMemcpyHostToDevice, st));
+                km.agroups = (int)l.agrp.size() - 1;
+                km.ugroups = (int)l.ugrp.size() - 1;
+                km.uwork = l.uwork;
+            }
+            HIP_TRY(ctx, hipMemcpyAsync(h_active[poll & 1], km.active, Kc * sizeof(int32_t),
                                         hipMemcpyDeviceToHost, st));
-            HIP_TRY(ctx, hipStreamSynchronize(st));
-            int live = 0;
-            for (int k = 0; k < Kc; ++k) live += h_active[k] != 0;
-            if (live == 0) break;
-            // compact the work lists to the candidates still iterating
-            const Lists l = make_lists(P.grid, h_active, P.ucap, g->n, ctx->num_cu);
-            pack_lists(l, Kc, h_lists);
-            HIP_TRY(ctx, hipMemcpyAsync(P.dyn, h_lists, (size_t)kDynLen(Kc) * sizeof(int32_t),
-                                        hipMemcpyHostToDevice, st));
-            km.agroups = (int)l.agrp.size() - 1;
-            km.ugroups = (int)l.ugrp.size() - 1;
-            km.uwork = l.uwork;
+            HIP_TRY(ctx, hipEventRecord(ctx->poll_ev[poll & 1], st));
+            ++poll;
         }
     }
     RAFT_TRY(launch_check(ctx));
@@ -674,6 +693,7 @@ raft_status raft_ctx_create(int device, raft_ctx** out) {
         return RAFT_E_DEVICE;
     }
     for (auto& e : c->ev) (void)hipEventCreate(&e);
+    for (auto& e : c->poll_ev) (void)hipEventCreateWithFlags(&e, hipEventDisableTiming);
     *out = c;
     return RAFT_OK;
 }
@@ -682,6 +702,8 @@ void raft_ctx_destroy(raft_ctx* ctx) {
     if (!ctx) return;
     (void)hipDeviceSynchronize();
     for (auto& e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto& e : ctx->poll_ev)
         if (e) (void)hipEventDestroy(e);
     for (auto& e : ctx->prof_pool) (void)hipEventDestroy(e);
     if (ctx->d_status) (void)hipFree(ctx->d_status);
