@@ -660,7 +660,8 @@ __global__ __launch_bounds__(256) void k_split_points(KmeansPlan p, const float*
 // accumulator row per instruction.  A candidate where most points moved and
 // none had a cluster before (the first assignment) takes a branch-free sweep
 // over the chunk (unmoved points go to a dummy row); otherwise each point is
-// a uniform bit test, skipped when it did not move.  At the end the
+// a uniform bit test, skipped when it did not move, with the add and the
+// subtraction under one test when every moved point had a cluster.  At the end the
 // work-group writes, per accumulator row, a flag saying whether any point
 // moved in or out and, if so, the row's partial sums and count change;
 // k_update_finish folds the flagged partials of each row into the totals.
@@ -792,6 +793,21 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
                 for (int q = 0; q < kWave; ++q) {
                     const int a = __builtin_amdgcn_readlane(nrow, q);
                     atomicAdd(acol + (size_t)a * kUpdSlice, widen_at_use(zf[q]));
+                }
+                continue;
+            }
+            if (mo == mv) {
+                // every moved point had a cluster (all iterations after the
+                // first): one bit test per point for both the add and the
+                // subtraction
+#pragma unroll
+                for (int q = 0; q < kWave; ++q) {
+                    if ((mv >> q) & 1ull) {
+                        const int a = __builtin_amdgcn_readlane(nrow, q);
+                        const int o = __builtin_amdgcn_readlane(orow, q);
+                        atomicAdd(acol + (size_t)a * kUpdSlice, widen_at_use(zf[q]));
+                        atomicSub(acol + (size_t)o * kUpdSlice, widen_at_use(zf[q]));
+                    }
                 }
                 continue;
             }
