@@ -671,6 +671,14 @@ constexpr int kUpdSlice = 64;
 // label staging: [wave][candidate][point] bytes, new and previous labels
 constexpr size_t kUpdStageBytes = (size_t)2 * kUpdWaves * kUpdMaxCand * kWave;
 
+// Bit q of a uniform 64-bit mask (q a compile-time constant after
+// unrolling), tested on its 32-bit half so the AND alone sets the branch
+// condition.
+__device__ __forceinline__ bool bit_set(uint64_t m, int q) {
+    const uint32_t w = q < 32 ? (uint32_t)m : (uint32_t)(m >> 32);
+    return (w & (1u << (q & 31))) != 0u;
+}
+
 // int32 -> int64 at the point of use: the empty asm keeps the compiler from
 // hoisting 64 widened copies out of the candidate loop (128 more registers).
 __device__ __forceinline__ unsigned long long widen_at_use(int x) {
@@ -712,7 +720,7 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
     const int fe = fixed_exp(p);
     const int dummy = rows;
     const int col = sl * kUpdSlice + lane;
-    const bool on = col < p.d;
+    const int colc = min(col, p.d - 1);
     const int len = p.ulen[g];
     const int r0 = slot * len;
     const int r1 = min(p.n, r0 + len);
@@ -764,12 +772,13 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
         }
         if (U == 0) continue;
         // z of the moved points (lane = column): every load is issued before
-        // the first conversion, so the loads overlap
+        // the first conversion, so the loads overlap.  Lanes past d read
+        // column d-1; they only feed accumulator columns never written out.
         float zr[kWave];
 #pragma unroll
         for (int q = 0; q < kWave; ++q) {
             zr[q] = 0.f;
-            if (((U >> q) & 1ull) && on) zr[q] = Z[(size_t)(cs + q) * p.d + col];
+            if (bit_set(U, q)) zr[q] = Z[(size_t)(cs + q) * p.d + colc];
         }
         int zf[kWave];
 #pragma unroll
@@ -802,18 +811,18 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
                 // subtraction
 #pragma unroll
                 for (int q = 0; q < kWave; ++q) {
-                    if ((mv >> q) & 1ull) {
+                    if (bit_set(mv, q)) {
                         const int a = __builtin_amdgcn_readlane(nrow, q);
                         const int o = __builtin_amdgcn_readlane(orow, q);
                         atomicAdd(acol + (size_t)a * kUpdSlice, widen_at_use(zf[q]));
-                        atomicSub(acol + (size_t)o * kUpdSlice, widen_at_use(zf[q]));
+                        atomicAdd(acol + (size_t)o * kUpdSlice, widen_at_use(-zf[q]));
                     }
                 }
                 continue;
             }
 #pragma unroll
             for (int q = 0; q < kWave; ++q) {
-                if ((mv >> q) & 1ull) {
+                if (bit_set(mv, q)) {
                     const int a = __builtin_amdgcn_readlane(nrow, q);
                     atomicAdd(acol + (size_t)a * kUpdSlice, widen_at_use(zf[q]));
                 }
@@ -821,9 +830,9 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
             if (mo == 0) continue;
 #pragma unroll
             for (int q = 0; q < kWave; ++q) {
-                if ((mo >> q) & 1ull) {
+                if (bit_set(mo, q)) {
                     const int o = __builtin_amdgcn_readlane(orow, q);
-                    atomicSub(acol + (size_t)o * kUpdSlice, widen_at_use(zf[q]));
+                    atomicAdd(acol + (size_t)o * kUpdSlice, widen_at_use(-zf[q]));
                 }
             }
         }
