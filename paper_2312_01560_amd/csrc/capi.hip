@@ -384,9 +384,8 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
     km.pdirty = a.take<uint8_t>((size_t)P.ranges_max * G.KP);
     km.zmax_bits = a.take<uint32_t>(1);
     km.w = a.take<float>(n);
-    km.race_val = a.take<double>(P.race_grid);
-    km.race_idx = a.take<int32_t>(P.race_grid);
-    km.race_counter = a.take<uint32_t>(1);
+    km.race_val = a.take<double>((size_t)2 * P.race_grid);
+    km.race_idx = a.take<int32_t>((size_t)2 * P.race_grid);
     P.picks_int = a.take<int32_t>(G.k_max);
     km.picks = P.picks_int;
     km.lab_cm = a.take<uint8_t>((size_t)G.Kc * n);

@@ -99,9 +99,8 @@ struct KmeansPlan {
     uint8_t* pdirty;         // [max ranges x KP] a point moved into or out of the row
     uint32_t* zmax_bits;     // [1] largest |z| (float bits), sets the fixed-point scale
     float* w;                // [n]
-    double* race_val;        // [race_grid]
-    int32_t* race_idx;       // [race_grid]
-    uint32_t* race_counter;  // [1]
+    double* race_val;        // [2 x race_grid] per-group minima, by launch parity
+    int32_t* race_idx;       // [2 x race_grid]
     int32_t* picks;          // [k_max]
     uint8_t* lab_cm;         // [Kc x n] candidate-major labels
     uint8_t* lab_old;        // [Kc x n] labels before the last assignment (0xFF: none)
@@ -118,6 +117,8 @@ int kmeans_update_rows(int K);
 int kmeans_update_max_candidates();
 void launch_kmeans_reset(const KmeansPlan& p, hipStream_t st);
 void launch_zmax(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t st);
+// Pick t of the race (launch t resolves pick t-1; the launch of the last
+// pick also resolves it).
 void launch_race_pick(const KmeansPlan& p, const float* Z, int t, uint64_t seed, hipStream_t st);
 void launch_init_centres(const KmeansPlan& p, const float* Z, hipStream_t st);
 void launch_assign(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t st);

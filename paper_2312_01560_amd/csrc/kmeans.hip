@@ -6,18 +6,17 @@
 //   argmin_{i: w_i > 0} E_{t,i} / w_i,  E_{t,i} = -ln u(Philox(i, t | seed, 0x20)),
 // w_i = 1 before the first pick, then the squared distance to the nearest
 // pick (ties to the lowest index; all-zero weights take the lowest unpicked
-// index).  One launch per pick; the last work-group to finish reduces the
+// index).  One launch per pick; each launch reduces the previous launch's
 // per-group minima (lexicographic on (ratio, index), so the result does not
 // depend on scheduling).
 //
 // Lloyd, all candidates together: the assignment is a dense contraction of
 // the points against the table of all centres (rows of each candidate padded
-// to a multiple of 16), on MFMA (v_mfma_f32_16x16x4f32), score
-// ||c||^2 - 2 z.c, argmin per candidate segment with ties to the lowest
-// index.  The update accumulates per (point chunk, candidate) in LDS: each
-// wave owns a private copy and each lane a column, so every LDS address is
-// updated by one lane in program order and the sums are deterministic; the
-// chunk partials are combined in fixed order in FP64.
+// to a multiple of 16) on MFMA, score ||c||^2 - 2 z.c, argmin per candidate
+// with ties to the lowest index: split-fp16 operands (k_assign_h) for d a
+// multiple of 32, FP32 (k_assign) otherwise.  The update keeps exact integer
+// centre sums across iterations and adds or subtracts only the points whose
+// label changed (k_update, k_update_finish).
 #include <float.h>
 #include <limits.h>
 
@@ -55,14 +54,78 @@ __device__ __forceinline__ bool lex_less(double v, int i, double bv, int bi) {
     return v < bv || (v == bv && i < bi);
 }
 
+// Pick t from the per-group minima that launch t wrote (buffer t mod 2).
+// Every work-group of the next launch reduces all of them itself, in the
+// same fixed order (the minimum of a total order, so the same pick in every
+// work-group): no launch needs a grid-wide "last work-group" step.
+// Work-group 0 records the pick.  If every weight was zero, the lowest index
+// not picked yet.
+__device__ int race_resolve(const KmeansPlan& p, int t) {
+    __shared__ double sv[kRaceThreads / kWave];
+    __shared__ int si[kRaceThreads / kWave];
+    __shared__ int pick;
+    const double* rv = p.race_val + (size_t)(t & 1) * p.race_grid;
+    const int* ri = p.race_idx + (size_t)(t & 1) * p.race_grid;
+    double best = INFINITY;
+    int bidx = INT_MAX;
+    for (int b = threadIdx.x; b < p.race_grid; b += blockDim.x) {
+        const double v = rv[b];
+        const int i = ri[b];
+        if (lex_less(v, i, best, bidx)) {
+            best = v;
+            bidx = i;
+        }
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(best, off, kWave);
+        const int oi = __shfl_xor(bidx, off, kWave);
+        if (lex_less(ov, oi, best, bidx)) {
+            best = ov;
+            bidx = oi;
+        }
+    }
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    if (lane == 0) {
+        sv[wid] = best;
+        si[wid] = bidx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = sv[0];
+        int bi = si[0];
+        for (int w = 1; w < kRaceThreads / kWave; ++w)
+            if (lex_less(sv[w], si[w], b, bi)) {
+                b = sv[w];
+                bi = si[w];
+            }
+        if (bi == INT_MAX) {
+            for (int c = 0; c <= t; ++c) {
+                bool taken = false;
+                for (int q = 0; q < t; ++q) taken |= (p.picks[q] == c);
+                if (!taken) {
+                    bi = c;
+                    break;
+                }
+            }
+        }
+        pick = bi;
+        if (blockIdx.x == 0) p.picks[t] = bi;
+    }
+    __syncthreads();
+    return pick;
+}
+
+// Launch t: resolves pick t-1, updates the weights with the distances to it
+// and writes this work-group's minimum of E / w for pick t.
 template <int D>
 __global__ __launch_bounds__(kRaceThreads) void k_race(KmeansPlan p, const float* __restrict__ Z,
                                                        int t, uint64_t seed) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int stride = gridDim.x * blockDim.x;
+    const int prev = t > 0 ? race_resolve(p, t - 1) : -1;
     double best = INFINITY;
     int bidx = INT_MAX;
-    const int prev = t > 0 ? p.picks[t - 1] : -1;
     const float* zp = prev >= 0 ? Z + (size_t)prev * D : Z;
     for (int i = tid; i < p.n; i += stride) {
         float wi = 1.0f;
@@ -92,7 +155,7 @@ __global__ __launch_bounds__(kRaceThreads) void k_race(KmeansPlan p, const float
             }
         }
     }
-    // work-group reduction
+    // work-group minimum, written for the next launch
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) {
         const double ov = __shfl_xor(best, off, kWave);
@@ -104,7 +167,6 @@ __global__ __launch_bounds__(kRaceThreads) void k_race(KmeansPlan p, const float
     }
     __shared__ double sv[kRaceThreads / kWave];
     __shared__ int si[kRaceThreads / kWave];
-    __shared__ bool last;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     if (lane == 0) {
         sv[wid] = best;
@@ -119,63 +181,14 @@ __global__ __launch_bounds__(kRaceThreads) void k_race(KmeansPlan p, const float
                 b = sv[w];
                 bi = si[w];
             }
-        p.race_val[blockIdx.x] = b;
-        p.race_idx[blockIdx.x] = bi;
-        __threadfence();
-        const unsigned prev_cnt = atomicAdd(p.race_counter, 1u);
-        last = (prev_cnt == gridDim.x - 1);
+        p.race_val[(size_t)(t & 1) * p.race_grid + blockIdx.x] = b;
+        p.race_idx[(size_t)(t & 1) * p.race_grid + blockIdx.x] = bi;
     }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    // last work-group: reduce all group minima
-    best = INFINITY;
-    bidx = INT_MAX;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
-        const double v = __hip_atomic_load(&p.race_val[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int i = __hip_atomic_load(&p.race_idx[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (lex_less(v, i, best, bidx)) {
-            best = v;
-            bidx = i;
-        }
-    }
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(best, off, kWave);
-        const int oi = __shfl_xor(bidx, off, kWave);
-        if (lex_less(ov, oi, best, bidx)) {
-            best = ov;
-            bidx = oi;
-        }
-    }
-    __syncthreads();
-    if (lane == 0) {
-        sv[wid] = best;
-        si[wid] = bidx;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double b = sv[0];
-        int bi = si[0];
-        for (int w = 1; w < kRaceThreads / kWave; ++w)
-            if (lex_less(sv[w], si[w], b, bi)) {
-                b = sv[w];
-                bi = si[w];
-            }
-        if (bi == INT_MAX) {
-            // every weight is zero: lowest index not picked yet (at most t)
-            for (int c = 0; c <= t; ++c) {
-                bool taken = false;
-                for (int q = 0; q < t; ++q) taken |= (p.picks[q] == c);
-                if (!taken) {
-                    bi = c;
-                    break;
-                }
-            }
-        }
-        p.picks[t] = bi;
-        *p.race_counter = 0u;
-    }
+}
+
+// The last pick (one work-group).
+__global__ __launch_bounds__(kRaceThreads) void k_race_final(KmeansPlan p) {
+    (void)race_resolve(p, p.k_max - 1);
 }
 
 // Copy the first K picks of every candidate into its centre rows; padding
@@ -962,7 +975,6 @@ __global__ void k_kmeans_reset(KmeansPlan p) {
         p.iters[k] = 0;
     }
     if (tid == 0) {
-        *p.race_counter = 0u;
         *p.active_count = p.Kc;
         *p.zmax_bits = 0u;
     }
@@ -970,9 +982,11 @@ __global__ void k_kmeans_reset(KmeansPlan p) {
 
 bool kmeans_supported(int d) { return d == 16 || d == 32 || d == 64 || d == 128 || d == 256; }
 
+// Every work-group of the next launch reads all per-group minima, so the
+// grid stays at two work-groups per CU or fewer.
 int kmeans_race_grid(int32_t n, int num_cu) {
     const int64_t want = ((int64_t)n + kRaceThreads - 1) / kRaceThreads;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)num_cu * 8));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)num_cu * 2));
 }
 
 size_t kmeans_update_lds(int sum_rows, int d) {
@@ -1012,6 +1026,7 @@ void launch_race_pick(const KmeansPlan& p, const float* Z, int t, uint64_t seed,
     hipLaunchKernelGGL(k_race<DV>, dim3(p.race_grid), dim3(kRaceThreads), 0, st, p, Z, t, seed)
     RAFT_D_SWITCH(p.d, RACE)
 #undef RACE
+    if (t == p.k_max - 1) hipLaunchKernelGGL(k_race_final, dim3(1), dim3(kRaceThreads), 0, st, p);
 }
 
 void launch_init_centres(const KmeansPlan& p, const float* Z, hipStream_t st) {
