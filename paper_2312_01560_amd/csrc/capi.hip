@@ -44,6 +44,7 @@ struct raft_graph {
     float* s = nullptr;
     float* sh = nullptr;
     float* dcoef = nullptr;
+    int32_t* order = nullptr;   // rows by degree class, heaviest first (stable)
     GraphView view() const {
         GraphView v;
         v.n = n;
@@ -54,6 +55,7 @@ struct raft_graph {
         v.s = s;
         v.sh = sh;
         v.dcoef = dcoef;
+        v.order = order;
         return v;
     }
 };
@@ -771,7 +773,8 @@ raft_status raft_graph_create(raft_ctx* ctx, const int32_t* row_ptr, const int32
               hipMalloc(&g->deg, sizeof(int32_t) * n) == hipSuccess &&
               hipMalloc(&g->s, sizeof(float) * n) == hipSuccess &&
               hipMalloc(&g->sh, sizeof(float) * n) == hipSuccess &&
-              hipMalloc(&g->dcoef, sizeof(float) * n) == hipSuccess;
+              hipMalloc(&g->dcoef, sizeof(float) * n) == hipSuccess &&
+              hipMalloc(&g->order, sizeof(int32_t) * n) == hipSuccess;
     if (!ok) {
         raft_graph_destroy(g);
         return fail(ctx, RAFT_E_NOMEM, "graph allocation failed");
@@ -781,6 +784,25 @@ raft_status raft_graph_create(raft_ctx* ctx, const int32_t* row_ptr, const int32
                                   hipMemcpyHostToDevice, st);
     if (e == hipSuccess && nnz > 0)
         e = hipMemcpyAsync(g->ci, col_idx, sizeof(int32_t) * nnz, kind, st);
+    // Row order of the row-split kernels (SpMM, edge scores): a stable
+    // partition by the number of 16-edge batches a row needs (at most 16
+    // classes), heaviest first, so the rows a wave takes side by side have
+    // similar lengths and the longest start first.  Only the schedule
+    // changes: every row is summed in its own edge order.
+    std::vector<int32_t> order((size_t)n);
+    {
+        constexpr int kClasses = 17;
+        auto cls = [&](int64_t i) {
+            const int64_t b = (h_rp[i + 1] - h_rp[i] + 15) / 16;
+            return (int)(kClasses - 1 - std::min<int64_t>(b, kClasses - 1));
+        };
+        int64_t start[kClasses + 1] = {};
+        for (int64_t i = 0; i < n; ++i) ++start[cls(i) + 1];
+        for (int c = 0; c < kClasses; ++c) start[c + 1] += start[c];
+        for (int64_t i = 0; i < n; ++i) order[start[cls(i)]++] = (int32_t)i;
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->order, order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->d_status, 0, sizeof(int32_t), st);
     if (e != hipSuccess) {
         raft_graph_destroy(g);
@@ -821,6 +843,7 @@ void raft_graph_destroy(raft_graph* g) {
     if (g->s) (void)hipFree(g->s);
     if (g->sh) (void)hipFree(g->sh);
     if (g->dcoef) (void)hipFree(g->dcoef);
+    if (g->order) (void)hipFree(g->order);
     delete g;
 }
 

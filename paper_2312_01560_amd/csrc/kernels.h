@@ -31,6 +31,7 @@ struct GraphView {
     const float* s;      // D^-1/2 (0 for isolated nodes)
     const float* sh;     // (D+1)^-1/2
     const float* dcoef;  // d_i / 2e
+    const int32_t* order;  // [n] rows by degree class, heaviest first (row-split schedules)
 };
 
 // Grid size (work-groups) of one SpMM launch; colsum partial buffers hold

@@ -7,11 +7,13 @@
 // with s = D^-1/2 and sh = (D+1)^-1/2.
 //
 // Row-split CSR with one row per lane group: L/4 lanes hold one feature row
-// (a float4 each), so a wave works on 256/L rows side by side.  The row
-// pointers of a wave's rows come in one load; per batch of 16 edges the lanes
+// (a float4 each), so a wave works on 256/L rows side by side, taken in the
+// graph's degree-class order (rows of similar length together, the longest
+// first); per batch of 16 edges the lanes
 // of a row group load the same column indices (broadcast loads), then all 16
 // neighbour rows are gathered back to back, the edge weight (a per-node
-// scale) loaded next to each feature row.  Rows are assigned in contiguous runs per wave; the optional
+// scale) loaded next to each feature row.  For L >= 64 work-groups take
+// 32-column slices, placed per XCD (see SpmmGeom).  The optional
 // epilogue accumulates FP64 partials of d^T y per work-group (the rank-1 term
 // of the next MOD_FULL step) in a fixed order, so the column sums are
 // deterministic.
@@ -29,37 +31,46 @@ __device__ __forceinline__ float edge_weight(const GraphView& g, int j) {
     return 1.f;
 }
 
+// Column slices: for L >= 64 a work-group handles one slice of W = 32
+// columns (one 128-byte line of a feature row) of a block of rows, and the
+// work-groups are dealt to the XCDs (work-group b to XCD b mod 8) so that
+// each XCD only ever touches its own slices: its L2 then holds N x 128 bytes
+// (or 2 slices' worth at L = 64) of X instead of all of it, and the random
+// neighbour gathers hit L2 more often.  For L <= 32 there is one slice.
+template <int L>
+struct SpmmGeom {
+    static constexpr int W = L >= 64 ? 32 : L;   // columns per slice
+    static constexpr int NS = L / W;             // slices
+    static constexpr int XS = 8 / NS;            // XCDs per slice
+    static constexpr int LANES = W / 4;          // lanes per feature row slice
+    static constexpr int G = kWave / LANES;      // rows side by side per wave
+};
+
 template <int L, int OP, bool CS>
 __global__ __launch_bounds__(256) void k_spmm(GraphView g, const float* __restrict__ x,
                                               float* __restrict__ y,
                                               const float* __restrict__ cvec,
-                                              double* __restrict__ cpart, int rpw) {
-    constexpr int LANES = L / 4;                  // lanes per feature row
-    constexpr int G = kWave / LANES;              // rows side by side per wave
+                                              double* __restrict__ cpart, int R, int nrb) {
+    using GE = SpmmGeom<L>;
+    constexpr int W = GE::W, LANES = GE::LANES, G = GE::G, XS = GE::XS;
+    const int b = blockIdx.x;
+    const int xcd = b % 8;
+    const int sl = xcd / XS;                        // column slice
+    const int rb = (b / 8) * XS + xcd % XS;         // row block
+    if (rb >= nrb) return;                          // uniform: padding of the grid
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
     const int slot = lane / LANES;
     const int sub = lane % LANES;
-    const int row0 = (blockIdx.x * kSpmmWaves + wid) * rpw * G;
+    const int cofs = sl * W + sub * 4;              // this lane's 4 columns
+    const int rbeg = rb * R, rend = min(g.n, rbeg + R);
     double cs0 = 0, cs1 = 0, cs2 = 0, cs3 = 0;
-
-    // row pointers of all the wave's rows in one load (lane t holds rp[row0 + t])
-    const int nrw = rpw * G;
-    const bool pre = nrw < kWave;
-    const int rpv = pre ? g.rp[min(row0 + lane, g.n)] : 0;
-    for (int r = 0; r < rpw; ++r) {
-        const int i = row0 + r * G + slot;
-        const bool valid = i < g.n;
-        if (__ballot(valid) == 0) break;
-        int beg, end;
-        if (pre) {
-            beg = __shfl(rpv, r * G + slot, kWave);
-            end = __shfl(rpv, r * G + slot + 1, kWave);
-        } else {
-            beg = valid ? g.rp[i] : 0;
-            end = valid ? g.rp[i + 1] : 0;
-        }
-        if (!valid) end = beg;
+    for (int r0 = rbeg + wid * G; r0 < rend; r0 += kSpmmWaves * G) {
+        // position r0 + slot of the degree-class order
+        const bool valid = r0 + slot < rend;
+        const int i = valid ? g.order[r0 + slot] : 0;
+        const int beg = g.rp[i];
+        const int end = valid ? g.rp[i + 1] : beg;
         int maxdeg = end - beg;
 #pragma unroll
         for (int off = LANES; off < kWave; off <<= 1)
@@ -67,13 +78,21 @@ __global__ __launch_bounds__(256) void k_spmm(GraphView g, const float* __restri
         float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
         float4 acc2 = make_float4(0.f, 0.f, 0.f, 0.f);
         // batches of 16 edges per row: the lanes of a row group load the same
-        // column index (a broadcast load), then all feature rows are gathered
+        // column index (a broadcast load), then all feature rows are gathered.
+        // The next batch's indices are requested before this batch's gathers,
+        // so each batch waits on memory once.
+        int jv[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int e = beg + q;
+            jv[q] = e < end ? g.ci[e] : -1;
+        }
         for (int base = 0; base < maxdeg; base += 16) {
-            int jv[16];
+            int jn[16];
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
-                const int e = beg + base + q;
-                jv[q] = e < end ? g.ci[e] : -1;
+                const int e = beg + base + 16 + q;
+                jn[q] = e < end ? g.ci[e] : -1;
             }
             float4 xv[16];
             float wv[16];
@@ -82,7 +101,7 @@ __global__ __launch_bounds__(256) void k_spmm(GraphView g, const float* __restri
                 xv[q] = make_float4(0.f, 0.f, 0.f, 0.f);
                 wv[q] = 0.f;
                 if (jv[q] >= 0) {
-                    xv[q] = *reinterpret_cast<const float4*>(x + (size_t)jv[q] * L + sub * 4);
+                    xv[q] = *reinterpret_cast<const float4*>(x + (size_t)jv[q] * L + cofs);
                     wv[q] = edge_weight<L, OP>(g, jv[q]);
                 }
             }
@@ -109,6 +128,8 @@ __global__ __launch_bounds__(256) void k_spmm(GraphView g, const float* __restri
                     acc.w += wv[q] * xv[q].w;
                 }
             }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) jv[q] = jn[q];
         }
         if (valid) {
             float4 o;
@@ -117,12 +138,12 @@ __global__ __launch_bounds__(256) void k_spmm(GraphView g, const float* __restri
                 o = make_float4(si * acc.x, si * acc.y, si * acc.z, si * acc.w);
             } else if (OP == kOpGcn) {
                 const float si = g.sh[i];
-                const float4 xi = *reinterpret_cast<const float4*>(x + (size_t)i * L + sub * 4);
+                const float4 xi = *reinterpret_cast<const float4*>(x + (size_t)i * L + cofs);
                 o = make_float4(si * (acc.x + si * xi.x), si * (acc.y + si * xi.y),
                                 si * (acc.z + si * xi.z), si * (acc.w + si * xi.w));
             } else if (OP == kOpModFull) {
                 const float ci = g.dcoef[i];
-                const float4 c = *reinterpret_cast<const float4*>(cvec + sub * 4);
+                const float4 c = *reinterpret_cast<const float4*>(cvec + cofs);
                 o = make_float4(acc.x - ci * c.x, acc.y - ci * c.y, acc.z - ci * c.z,
                                 acc.w - ci * c.w);
             } else {
@@ -130,7 +151,7 @@ __global__ __launch_bounds__(256) void k_spmm(GraphView g, const float* __restri
                 o = make_float4(acc.x - ci * acc2.x, acc.y - ci * acc2.y, acc.z - ci * acc2.z,
                                 acc.w - ci * acc2.w);
             }
-            *reinterpret_cast<float4*>(y + (size_t)i * L + sub * 4) = o;
+            *reinterpret_cast<float4*>(y + (size_t)i * L + cofs) = o;
             if (CS) {
                 const double di = (double)g.deg[i];
                 cs0 += di * (double)o.x;
@@ -141,7 +162,8 @@ __global__ __launch_bounds__(256) void k_spmm(GraphView g, const float* __restri
         }
     }
     if (CS) {
-        // fold the row slots of the wave (fixed butterfly order), then the waves
+        // fold the row slots of the wave (fixed butterfly order), then the
+        // waves; the row block's partial row gets this slice's W columns
 #pragma unroll
         for (int off = LANES; off < kWave; off <<= 1) {
             cs0 += __shfl_xor(cs0, off, kWave);
@@ -149,7 +171,7 @@ __global__ __launch_bounds__(256) void k_spmm(GraphView g, const float* __restri
             cs2 += __shfl_xor(cs2, off, kWave);
             cs3 += __shfl_xor(cs3, off, kWave);
         }
-        __shared__ double red[kSpmmWaves][L];
+        __shared__ double red[kSpmmWaves][W];
         if (slot == 0) {
             red[wid][sub * 4 + 0] = cs0;
             red[wid][sub * 4 + 1] = cs1;
@@ -157,10 +179,10 @@ __global__ __launch_bounds__(256) void k_spmm(GraphView g, const float* __restri
             red[wid][sub * 4 + 3] = cs3;
         }
         __syncthreads();
-        for (int c = threadIdx.x; c < L; c += blockDim.x) {
+        for (int c = threadIdx.x; c < W; c += blockDim.x) {
             double s = 0;
             for (int w = 0; w < kSpmmWaves; ++w) s += red[w][c];
-            cpart[(size_t)blockIdx.x * L + c] = s;
+            cpart[(size_t)rb * L + sl * W + c] = s;
         }
     }
 }
@@ -256,15 +278,20 @@ int spmm_grid(int32_t n, int L, int num_cu, int* rows_per_wave) {
 
 template <int L>
 static void spmm_dispatch_op(const GraphView& g, int op, const float* x, float* y,
-                             const float* cvec, double* cpart, int grid, int rpw, hipStream_t st) {
+                             const float* cvec, double* cpart, int nrb, int rpw, hipStream_t st) {
+    using GE = SpmmGeom<L>;
+    // rows per row block, as in spmm_grid (which k_colsum_part also uses)
+    const int R = rpw * (kWave / (L / 4)) * kSpmmWaves;
+    // every group of 8 consecutive work-groups covers XS row blocks x NS slices
+    const int grid = (nrb + GE::XS - 1) / GE::XS * 8;
 #define RAFT_SPMM_CASE(OPV)                                                                  \
     if (op == OPV) {                                                                         \
         if (cpart)                                                                           \
             hipLaunchKernelGGL((k_spmm<L, OPV, true>), dim3(grid), dim3(256), 0, st, g, x, y, \
-                               cvec, cpart, rpw);                                            \
+                               cvec, cpart, R, nrb);                                         \
         else                                                                                 \
             hipLaunchKernelGGL((k_spmm<L, OPV, false>), dim3(grid), dim3(256), 0, st, g, x,   \
-                               y, cvec, cpart, rpw);                                         \
+                               y, cvec, cpart, R, nrb);                                      \
         return;                                                                              \
     }
     RAFT_SPMM_CASE(kOpNcut)
