@@ -62,23 +62,18 @@ __global__ __launch_bounds__(256) void k_edge_score(GraphView g, ScorePlan p,
     const int slot = lane / LPR;
     const int m = lane % LPR;
     const bool on = 8 * m < p.S;
-    const int row0 = (blockIdx.x * (blockDim.x / kWave) + wid) * rpw * G;
-    const int nrw = rpw * G;
-    const bool pre = nrw < kWave;
-    const int rpv = pre ? g.rp[min(row0 + lane, g.n)] : 0;
-    for (int r = 0; r < rpw; ++r) {
-        const int i = row0 + r * G + slot;
-        const bool valid = i < g.n;
-        if (__ballot(valid) == 0) break;
-        int beg, end;
-        if (pre) {
-            beg = __shfl(rpv, r * G + slot, kWave);
-            end = __shfl(rpv, r * G + slot + 1, kWave);
-        } else {
-            beg = valid ? g.rp[i] : 0;
-            end = valid ? g.rp[i + 1] : 0;
-        }
-        if (!valid) end = beg;
+    // passes of G positions of the graph's degree-class order (rows of
+    // similar length side by side, the longest first), dealt to the waves
+    // round robin so every wave gets its share of long and short rows
+    (void)rpw;
+    const int nwaves = gridDim.x * (blockDim.x / kWave);
+    const int npass = (g.n + G - 1) / G;
+    for (int pp = blockIdx.x * (blockDim.x / kWave) + wid; pp < npass; pp += nwaves) {
+        const int pos = pp * G + slot;
+        const bool valid = pos < g.n;
+        const int i = valid ? g.order[pos] : 0;
+        const int beg = g.rp[i];
+        const int end = valid ? g.rp[i + 1] : beg;
         int maxdeg = end - beg;
 #pragma unroll
         for (int off = LPR; off < kWave; off <<= 1)
