@@ -263,7 +263,7 @@ static int score_rpw(int32_t n, int S, int grid) {
 
 int score_grid(int32_t n, int num_cu) {
     const int64_t want = ((int64_t)n + 63) / 64;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)num_cu * 2));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)num_cu * 4));
 }
 
 bool score_supported(int SK) { return SK >= 1 && SK <= 16384; }
