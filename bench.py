@@ -67,6 +67,7 @@ def source_hash(files):
 KERNEL_SOURCES = {
     "assign": ["paper_2312_01560_amd/csrc/kmeans.hip"],  # k_assign / k_assign_h
     "spmm": ["paper_2312_01560_amd/csrc/spmm.hip"],
+    "score": ["paper_2312_01560_amd/csrc/score.hip"],
 }
 
 
@@ -262,7 +263,7 @@ def main():
     ctx.sync_status()
     log("warm-up done; timed steps")
     api.profile_read(ctx)
-    api.profile_enable(ctx, (1 << 0) | (1 << 3))      # SpMM and k-means assignment
+    api.profile_enable(ctx, (1 << 0) | (1 << 3) | (1 << 5))   # SpMM, assignment, edge scores
     stage = {v: np.zeros(5) for v in variants}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -290,6 +291,11 @@ def main():
     spmm_bytes_per_launch = 4.0 * (n + 1) + 4.0 * nnz + 8.0 * n * method["proj_dim"]
     ms_assign, n_assign = prof["assign"]
     ms_spmm, n_spmm = prof["spmm"]
+    ms_score, n_score = prof["score"]
+    # edge scores: row pointers, column indices, one label row per node, the
+    # row order (the neighbour label gathers are the same rows again)
+    score_bytes_per_launch = 4.0 * (n + 1) + 4.0 * nnz + float(n) * len(ks) + 4.0 * n
+    score_ach = score_bytes_per_launch * n_score / (ms_score * 1e-3) if ms_score > 0 else 0.0
     assign_ach = assign_flops * args.steps / (ms_assign * 1e-3) if ms_assign > 0 else 0.0
     spmm_ach = spmm_bytes_per_launch * n_spmm / (ms_spmm * 1e-3) if ms_spmm > 0 else 0.0
     dominant = "assign" if ms_assign >= ms_spmm else "spmm"
@@ -331,6 +337,12 @@ def main():
                  "edges_features_per_s": nnz * method["proj_dim"] * n_spmm / (ms_spmm * 1e-3)
                  if ms_spmm > 0 else 0.0,
                  "traffic": measured_traffic("spmm", args.workload)},
+        "edge_score": {"achieved_gbs": score_ach / 1e9, "frac_hbm": score_ach / PEAK_HBM,
+                       "avg_us": 1e3 * ms_score / max(n_score, 1), "launches": n_score,
+                       "bytes_per_launch": score_bytes_per_launch,
+                       "edge_candidates_per_s": nnz * len(ks) * n_score / (ms_score * 1e-3)
+                       if ms_score > 0 else 0.0,
+                       "traffic": measured_traffic("score", args.workload)},
         "stages_ms_per_step": {v: dict(zip(["project", "embed", "seed", "lloyd", "score"],
                                            (stage[v] / args.steps).round(3).tolist()))
                                for v in variants},

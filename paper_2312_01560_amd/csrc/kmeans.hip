@@ -683,6 +683,8 @@ constexpr int kUpdMaxCand = 16;
 constexpr int kUpdSlice = 64;
 // label staging: [wave][candidate][point] bytes, new and previous labels
 constexpr size_t kUpdStageBytes = (size_t)2 * kUpdWaves * kUpdMaxCand * kWave;
+constexpr int kUpdSparse = 16;   // moved points per chunk below which the set bits are walked
+typedef int i32x32 __attribute__((ext_vector_type(32)));
 
 // Bit q of a uniform 64-bit mask (q a compile-time constant after
 // unrolling), tested on its 32-bit half so the AND alone sets the branch
@@ -787,15 +789,26 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
         // z of the moved points (lane = column): every load is issued before
         // the first conversion, so the loads overlap.  Lanes past d read
         // column d-1; they only feed accumulator columns never written out.
+        // Only moved points are loaded; the empty asm after the loads keeps
+        // the compiler from pulling each conversion into its load's branch
+        // (which would wait on every load in turn).
         float zr[kWave];
 #pragma unroll
         for (int q = 0; q < kWave; ++q) {
             zr[q] = 0.f;
             if (bit_set(U, q)) zr[q] = Z[(size_t)(cs + q) * p.d + colc];
         }
-        int zf[kWave];
 #pragma unroll
-        for (int q = 0; q < kWave; ++q) zf[q] = __float2int_rn(ldexpf(zr[q], fe));
+        for (int q = 0; q < kWave; ++q) asm volatile("" : "+v"(zr[q]));
+        // quantised z in two 32-wide vectors: constant indices in the unrolled
+        // sweeps, a relative register move in the sparse walk
+        i32x32 zf0, zf1;
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            zf0[q] = __float2int_rn(ldexpf(zr[q], fe));
+            zf1[q] = __float2int_rn(ldexpf(zr[q + 32], fe));
+        }
+#define ZF(q) ((q) < 32 ? zf0[(q)] : zf1[(q) - 32])
         // pass 2: the adds and subtractions, candidate by candidate
         int base = 0;
         for (int m = 0; m < nc; ++m) {
@@ -814,7 +827,19 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
 #pragma unroll
                 for (int q = 0; q < kWave; ++q) {
                     const int a = __builtin_amdgcn_readlane(nrow, q);
-                    atomicAdd(acol + (size_t)a * kUpdSlice, widen_at_use(zf[q]));
+                    atomicAdd(acol + (size_t)a * kUpdSlice, widen_at_use(ZF(q)));
+                }
+                continue;
+            }
+            if (mo == mv && __popcll(mv) <= kUpdSparse) {
+                // few moved points, each with a cluster: walk the set bits
+                for (uint64_t r = mv; r != 0; r &= r - 1) {
+                    const int q = __builtin_ctzll(r);
+                    const int a = __builtin_amdgcn_readlane(nrow, q);
+                    const int o = __builtin_amdgcn_readlane(orow, q);
+                    const int z = q < 32 ? zf0[q] : zf1[q - 32];
+                    atomicAdd(acol + (size_t)a * kUpdSlice, widen_at_use(z));
+                    atomicAdd(acol + (size_t)o * kUpdSlice, widen_at_use(-z));
                 }
                 continue;
             }
@@ -827,8 +852,8 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
                     if (bit_set(mv, q)) {
                         const int a = __builtin_amdgcn_readlane(nrow, q);
                         const int o = __builtin_amdgcn_readlane(orow, q);
-                        atomicAdd(acol + (size_t)a * kUpdSlice, widen_at_use(zf[q]));
-                        atomicAdd(acol + (size_t)o * kUpdSlice, widen_at_use(-zf[q]));
+                        atomicAdd(acol + (size_t)a * kUpdSlice, widen_at_use(ZF(q)));
+                        atomicAdd(acol + (size_t)o * kUpdSlice, widen_at_use(-ZF(q)));
                     }
                 }
                 continue;
@@ -837,7 +862,7 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
             for (int q = 0; q < kWave; ++q) {
                 if (bit_set(mv, q)) {
                     const int a = __builtin_amdgcn_readlane(nrow, q);
-                    atomicAdd(acol + (size_t)a * kUpdSlice, widen_at_use(zf[q]));
+                    atomicAdd(acol + (size_t)a * kUpdSlice, widen_at_use(ZF(q)));
                 }
             }
             if (mo == 0) continue;
@@ -845,11 +870,12 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
             for (int q = 0; q < kWave; ++q) {
                 if (bit_set(mo, q)) {
                     const int o = __builtin_amdgcn_readlane(orow, q);
-                    atomicAdd(acol + (size_t)o * kUpdSlice, widen_at_use(-zf[q]));
+                    atomicAdd(acol + (size_t)o * kUpdSlice, widen_at_use(-ZF(q)));
                 }
             }
         }
     }
+#undef ZF
     __syncthreads();
     const int sw = min(kUpdSlice, p.d - sl * kUpdSlice);
     int base = 0;
