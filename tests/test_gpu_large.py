@@ -1,0 +1,170 @@
+"""Parity at the large single-graph size (N = 1,000,000, ~32M stored entries,
+L = d = 128, q = 4, K = 50..150 step 5), in the launch configuration of the
+benchmark's n1m workload.  The FP64 oracle cannot run the whole path at this
+size within a test, so each check takes what the oracle can compute row by
+row or a property that holds at any size:
+
+* one step of each sparse operator and one GCN layer, on sampled rows (random
+  rows plus the longest ones), against the oracle's operator rows;
+* end to end: the first k-means++ picks bit-exact, sampled points of every
+  converged candidate at their nearest centre, centres equal to the mean of
+  their points (sampled candidates), Mod/NCut of sampled candidates equal to
+  the oracle's scores of the GPU labels bit for bit, K* and the canonical
+  labels consistent with them."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import torch
+
+from oracle import gcn as ogcn
+from oracle import graph as ograph
+from oracle import kmeans as okm
+from oracle import projection, scores
+from synth import make_workload
+
+pytestmark = pytest.mark.gpu
+
+COL_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2312_01560_amd import api
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def api_mod():
+    from paper_2312_01560_amd import api
+    return api
+
+
+@pytest.fixture(scope="module")
+def n1m():
+    return make_workload("n1m")
+
+
+@pytest.fixture(scope="module")
+def dev_graph(ctx, api_mod, n1m):
+    g0, _ = n1m
+    rp = torch.from_numpy(g0.row_ptr).cuda()
+    ci = torch.from_numpy(g0.col_idx).cuda()
+    return api_mod.Graph(ctx, rp, ci)                  # device-resident input, as timed
+
+
+@pytest.fixture(scope="module")
+def rows(n1m):
+    g0, _ = n1m
+    deg = np.diff(g0.row_ptr)
+    rng = np.random.default_rng(7)
+    sample = rng.choice(g0.n, 3000, replace=False)
+    heavy = np.argsort(-deg, kind="stable")[:64]
+    return np.unique(np.concatenate([sample, heavy, [0, g0.n - 1]]))
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def col_err(got, ref):
+    got = np.asarray(got, dtype=np.float64)
+    nrm = np.linalg.norm(ref, axis=0)
+    return np.linalg.norm(got - ref, axis=0) / np.maximum(nrm, 1e-300)
+
+
+@pytest.mark.parametrize("op", [0, 1, 3])
+def test_n1m_spmm_rows(ctx, api_mod, n1m, dev_graph, rows, op):
+    g0, m = n1m
+    L = m["proj_dim"]
+    x = torch.randn(g0.n, L, device="cuda", generator=torch.Generator("cuda").manual_seed(op))
+    got = to_np(api_mod.spmm(ctx, dev_graph, op, x))[rows]
+    torch.cuda.synchronize()
+    ctx.sync_status()
+    x64 = to_np(x).astype(np.float64)
+    rp, ci, n = g0.row_ptr, g0.col_idx, g0.n
+    if op == 0:
+        ref = projection.ncut_operator(rp, ci, n)[rows] @ x64
+    elif op == 1:
+        # B x = A x - d (d^T x) / 2e on the sampled rows (d^T x over all rows)
+        a = ograph.adjacency(rp, ci, n)
+        d = ograph.degrees(rp).astype(np.float64)
+        ref = a[rows] @ x64 - np.outer(d[rows], d @ x64) / float(ograph.two_e(rp))
+    else:
+        ref = ogcn.gcn_operator(rp, ci, n)[rows] @ x64
+    assert col_err(got, ref).max() < COL_TOL
+
+
+def test_n1m_gcn_layer_rows(ctx, api_mod, n1m, dev_graph, rows):
+    g0, m = n1m
+    L = m["proj_dim"]
+    h = torch.randn(g0.n, L, device="cuda", generator=torch.Generator("cuda").manual_seed(11))
+    w64 = ogcn.weight(0, 1, L, m["layer_dims"][0])
+    w = torch.from_numpy(w64.astype(np.float32)).cuda()
+    out, p = api_mod.gcn_layer(ctx, dev_graph, h, w, want_p=True)
+    torch.cuda.synchronize()
+    ctx.sync_status()
+    p_ref = ogcn.gcn_operator(g0.row_ptr, g0.col_idx, g0.n)[rows] @ to_np(h).astype(np.float64)
+    assert col_err(to_np(p)[rows], p_ref).max() < COL_TOL
+    # the dense step from the GPU's own P rows (FP32 inputs, FP64 reference)
+    p_got = to_np(p)[rows].astype(np.float64)
+    out_ref = ogcn.row_normalize(np.tanh(p_got @ w64.astype(np.float32).astype(np.float64)))
+    assert col_err(to_np(out)[rows], out_ref).max() < COL_TOL
+
+
+def cluster_means(z64, lab, k):
+    """Mean of the points of each cluster (rows of empty clusters are nan)."""
+    ind = sp.csr_matrix((np.ones(lab.size), (lab, np.arange(lab.size))), shape=(k, lab.size))
+    cnt = np.asarray(ind.sum(axis=1)).ravel()
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return (ind @ z64) / cnt[:, None], cnt
+
+
+def test_n1m_end_to_end(ctx, api_mod, n1m, dev_graph, rows):
+    g0, m = n1m
+    cfg = api_mod.Config(op=1, **m)
+    out = api_mod.run(ctx, dev_graph, cfg, want_centres=True)
+    torch.cuda.synchronize()
+    ctx.sync_status()
+    z32 = to_np(out["Z"])
+    z64 = z32.astype(np.float64)
+    ks = cfg.ks
+    # k-means++ race: the first picks (each depends only on the earlier ones)
+    assert np.array_equal(to_np(out["picks"])[:10], okm.seed_picks(z64, 10, 0))
+    lab = to_np(out["labels_all"]).astype(np.int64)
+    iters = to_np(out["iters"])
+    cen = to_np(out["centres"]).astype(np.float64)
+    off = np.concatenate([[0], np.cumsum(ks)])
+    zmax = np.abs(z64).max()
+    converged = [j for j in range(len(ks)) if iters[j] < cfg.kmeans_max_iter]
+    assert converged
+    for j in converged:
+        k = ks[j]
+        assert lab[:, j].max() < k
+        c = cen[off[j]:off[j + 1]]
+        # sampled points sit at their nearest centre (FP32 near-ties allowed)
+        d = okm.sq_distances(z64[rows], c)
+        mine = d[np.arange(rows.size), lab[rows, j]]
+        assert np.all(mine <= d.min(axis=1) + 1e-5), k
+    for j in converged[::5]:
+        k = ks[j]
+        means, cnt = cluster_means(z64, lab[:, j], k)
+        c = cen[off[j]:off[j + 1]]
+        live = cnt > 0
+        tol = 1.01 * (2.0 ** -24 * np.abs(means[live]) + 2.0 ** -29 * zmax)
+        assert np.all(np.abs(c[live] - means[live]) <= tol), k
+    # scores of sampled candidates, bit for bit
+    sample = sorted(set([0, len(ks) // 2, len(ks) - 1]))
+    rmod, rnc = scores.score_candidates(g0.row_ptr, g0.col_idx, lab[:, sample],
+                                        [ks[j] for j in sample])
+    assert np.array_equal(to_np(out["mod"])[sample], rmod)
+    assert np.array_equal(to_np(out["ncut"])[sample], rnc)
+    # K* is the first maximum of the GPU's Mod, labels canonical
+    gmod = to_np(out["mod"])
+    best = scores.select(gmod)
+    ksel = to_np(out["k_selected"])
+    assert ksel[0] == ks[best] and ksel[2] == best
+    can, keff = scores.canonical(lab[:, best])
+    assert np.array_equal(to_np(out["labels"]), can) and ksel[1] == keff
