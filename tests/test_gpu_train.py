@@ -131,3 +131,33 @@ def test_training_lowers_loss_and_partitions(ctx, graph):
     mod, _ = api.score(ctx, g, lab, [max(k, 1)])
     ref = scores.modularity(graph.row_ptr, graph.col_idx, lab[:, 0].cpu().numpy().astype(np.int64), max(k, 1))
     assert to_np(mod)[0] == ref
+
+
+def test_forward_backward_full_size_n200k(ctx):
+    """The training workload's size (N = 200,000, GCN 3 x 64): loss, softmax
+    memberships, dL/dU, every weight gradient and dL/dY against the FP64
+    oracle."""
+    from synth import make_workload
+    g0, _ = make_workload("n200k")
+    dims = [64, 64, 64, 64]
+    g, y, ws, tr = _setup(ctx, g0, dims, seed=6)
+    U, saved = tr.forward(y, ws)
+    S, loss = tr.modloss_forward(U)
+    GU = tr.modloss_backward(S)
+    GW, GH0 = tr.backward(y, ws, saved, GU, want_h0=True)
+    torch.cuda.synchronize()
+    y64 = to_np(y)
+    w64 = [to_np(w) for w in ws]
+    u_ref, _ = modloss.forward(g0.row_ptr, g0.col_idx, g0.n, y64, w64)
+    assert rel(to_np(U), u_ref) < 1e-5
+    s64 = to_np(S)
+    assert rel(s64, modloss.softmax_rows(to_np(U))) < 1e-5
+    l_ref = modloss.loss_of_s(g0.row_ptr, g0.col_idx, g0.n, s64)
+    assert abs(float(loss.item()) - l_ref) <= 1e-5 * abs(l_ref) + 1e-9
+    gu_ref = modloss.softmax_backward(s64, modloss.grad_s(g0.row_ptr, g0.col_idx, g0.n, s64))
+    assert rel(to_np(GU), gu_ref) < 1e-4
+    gw_ref, gy_ref = modloss.backward(g0.row_ptr, g0.col_idx, g0.n, w64,
+                                      [y64] + [to_np(h) for h in saved], to_np(GU))
+    for k in range(len(ws)):
+        assert rel(to_np(GW[k]), gw_ref[k]) < 1e-4, k
+    assert rel(to_np(GH0), gy_ref) < 1e-4
