@@ -409,7 +409,7 @@ typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 // halves, norms) once, one tile ahead of the MFMAs, into a double buffer;
 // one barrier per tile.  Rows are padded by 8 halves against bank conflicts.
 template <int D, int PS>
-__global__ __launch_bounds__(256) void k_assign_h(KmeansPlan p) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3))) void k_assign_h(KmeansPlan p) {
     constexpr int NC = D / 32;
     constexpr int RS = D + 8;                 // LDS row stride (halves)
     constexpr int CPR = D / 8;                // 16-byte chunks per row and half
@@ -455,44 +455,47 @@ __global__ __launch_bounds__(256) void k_assign_h(KmeansPlan p) {
     const int nexp = 2 * split_exp(p) - 1;
     const _Float16* chp = reinterpret_cast<const _Float16*>(p.ch);
     const _Float16* clp = reinterpret_cast<const _Float16*>(p.cl);
-    // tile loader: global -> registers (issued early), registers -> LDS
-    uint4 stage[(CHUNKS + 255) / 256];
+    // tile loader: global -> registers (issued early), registers -> LDS.
+    // Written as macros so the staging registers are only ever indexed by
+    // unrolled constants (a lambda capturing them put them on the stack).
+    constexpr int SQ = (CHUNKS + 255) / 256;
+    uint4 stage[SQ];
     float cstage = 0.f;
-    auto issue = [&](int koff_, int tile_) {
-        const int base = koff_ + tile_ * 16;
-#pragma unroll
-        for (int q = 0; q < (CHUNKS + 255) / 256; ++q) {
-            const int c = tid + 256 * q;
-            if (c < CHUNKS) {
-                const int which = c / (16 * CPR), rem = c - which * (16 * CPR);
-                const int r = rem / CPR, c8 = rem - r * CPR;
-                const _Float16* src = (which ? clp : chp) + (size_t)(base + r) * D + 8 * c8;
-                stage[q] = *reinterpret_cast<const uint4*>(src);
-            }
-        }
-        if (tid < 16) cstage = p.cnorm[base + tid];
-    };
-    auto commit = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < (CHUNKS + 255) / 256; ++q) {
-            const int c = tid + 256 * q;
-            if (c < CHUNKS) {
-                const int which = c / (16 * CPR), rem = c - which * (16 * CPR);
-                const int r = rem / CPR, c8 = rem - r * CPR;
-                _Float16* dst = (which ? &ls[buf][r][0] : &hs[buf][r][0]) + 8 * c8;
-                *reinterpret_cast<uint4*>(dst) = stage[q];
-            }
-        }
-        if (tid < 16) cs[buf][tid] = ldexpf(cstage, nexp);
-    };
+#define ASSIGN_ISSUE(KOFF, TILE)                                                            \
+    {                                                                                      \
+        const int base_ = (KOFF) + (TILE) * 16;                                            \
+        _Pragma("unroll") for (int q = 0; q < SQ; ++q) {                                   \
+            const int c = tid + 256 * q;                                                   \
+            if (c < CHUNKS) {                                                              \
+                const int which = c / (16 * CPR), rem = c - which * (16 * CPR);            \
+                const int r = rem / CPR, c8 = rem - r * CPR;                               \
+                const _Float16* src = (which ? clp : chp) + (size_t)(base_ + r) * D + 8 * c8; \
+                stage[q] = *reinterpret_cast<const uint4*>(src);                           \
+            }                                                                              \
+        }                                                                                  \
+        if (tid < 16) cstage = p.cnorm[base_ + tid];                                       \
+    }
+#define ASSIGN_COMMIT(BUF)                                                                 \
+    {                                                                                      \
+        _Pragma("unroll") for (int q = 0; q < SQ; ++q) {                                   \
+            const int c = tid + 256 * q;                                                   \
+            if (c < CHUNKS) {                                                              \
+                const int which = c / (16 * CPR), rem = c - which * (16 * CPR);            \
+                const int r = rem / CPR, c8 = rem - r * CPR;                               \
+                _Float16* dst = (which ? &ls[(BUF)][r][0] : &hs[(BUF)][r][0]) + 8 * c8;    \
+                *reinterpret_cast<uint4*>(dst) = stage[q];                                 \
+            }                                                                              \
+        }                                                                                  \
+        if (tid < 16) cs[(BUF)][tid] = ldexpf(cstage, nexp);                               \
+    }
     // the walk: position t in the group, tile within the candidate
     int t = __builtin_ctzll(amask);
     int k = __builtin_amdgcn_readlane(my_k, t);
     int ntiles = __builtin_amdgcn_readlane(my_tiles, t);
     int koff = __builtin_amdgcn_readlane(my_off, t);
     int tile = 0;
-    issue(koff, 0);
-    commit(0);
+    ASSIGN_ISSUE(koff, 0)
+    ASSIGN_COMMIT(0)
     __syncthreads();
     const int ptl = pbase + 16 * g + li;
     const bool wl = g < PS && ptl < p.n;
@@ -521,32 +524,29 @@ __global__ __launch_bounds__(256) void k_assign_h(KmeansPlan p) {
             }
         }
         const bool more = nt < nc;
-        if (more) issue(nkoff, ntile);
+        if (more) ASSIGN_ISSUE(nkoff, ntile)
         // this tile's operands from LDS
-        half8 ah[NC], al[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            ah[c] = *reinterpret_cast<const half8*>(&hs[buf][li][8 * g + 32 * c]);
-            al[c] = *reinterpret_cast<const half8*>(&ls[buf][li][8 * g + 32 * c]);
-        }
         const float4 cnn = *reinterpret_cast<const float4*>(&cs[buf][4 * g]);
         const float cnv[4] = {cnn.x, cnn.y, cnn.z, cnn.w};
         // the PS accumulators are independent: interleaving them keeps the
-        // matrix unit busy instead of waiting on one dependent chain
+        // matrix unit busy instead of waiting on one dependent chain; each
+        // 32-wide chunk's A operands are read from LDS just before its MFMAs
         floatx4 acc[PS];
 #pragma unroll
         for (int ps = 0; ps < PS; ++ps) acc[ps] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
+            const half8 ah = *reinterpret_cast<const half8*>(&hs[buf][li][8 * g + 32 * c]);
+            const half8 al = *reinterpret_cast<const half8*>(&ls[buf][li][8 * g + 32 * c]);
 #pragma unroll
             for (int ps = 0; ps < PS; ++ps)
-                acc[ps] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[c], bh[ps][c], acc[ps], 0, 0, 0);
+                acc[ps] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[ps][c], acc[ps], 0, 0, 0);
 #pragma unroll
             for (int ps = 0; ps < PS; ++ps)
-                acc[ps] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[c], bl[ps][c], acc[ps], 0, 0, 0);
+                acc[ps] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl[ps][c], acc[ps], 0, 0, 0);
 #pragma unroll
             for (int ps = 0; ps < PS; ++ps)
-                acc[ps] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[c], bh[ps][c], acc[ps], 0, 0, 0);
+                acc[ps] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[ps][c], acc[ps], 0, 0, 0);
         }
 #pragma unroll
         for (int ps = 0; ps < PS; ++ps) {
@@ -572,7 +572,7 @@ __global__ __launch_bounds__(256) void k_assign_h(KmeansPlan p) {
             if (lane == 0 && m) p.changes[k] = 1;   // only zero / non-zero is read
         }
         if (!more) break;                     // uniform across the work-group
-        commit(buf ^ 1);
+        ASSIGN_COMMIT(buf ^ 1)
         __syncthreads();
         buf ^= 1;
         if (nt != t) old_lab = next_old;
@@ -583,6 +583,9 @@ __global__ __launch_bounds__(256) void k_assign_h(KmeansPlan p) {
         koff = nkoff;
     }
 }
+
+#undef ASSIGN_ISSUE
+#undef ASSIGN_COMMIT
 
 // After an assignment: a candidate whose labels did not change (from the
 // second assignment on) has converged; count the remaining active ones.
