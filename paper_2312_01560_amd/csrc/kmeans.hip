@@ -1067,13 +1067,14 @@ void launch_init_centres(const KmeansPlan& p, const float* Z, hipStream_t st) {
 
 template <int D>
 static constexpr int assign_ps() {
-    return D <= 64 ? 4 : (D == 128 ? 2 : 1);
+    return D <= 64 ? 4 : (D == 128 ? 3 : 1);
 }
 
-// The point tile of a work-group is 64 PS points (256 at d <= 64).  Smaller
-// tiles split a launch into more work-groups but re-read the centre tiles
-// more often; measured on gfx950 at N = 50k, 64-point tiles ran the
-// assignment 1.7x slower than 256-point tiles, so the tile is fixed.
+// The point tile of a work-group is 64 PS points (256 at d <= 64, 192 at
+// d = 128).  Smaller tiles split a launch into more work-groups but re-read
+// the centre tiles more often; measured on gfx950 at N = 50k, 64-point tiles
+// ran the assignment 1.7x slower than 256-point tiles, and at N = 1M
+// (d = 128) 48 points per wave ran 12 % faster than 32.
 void launch_assign(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t st) {
     (void)num_cu;
 #define ASSIGN(DV)                                                                        \
