@@ -375,6 +375,9 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
     km.C = a.take<float>((size_t)G.KP * P.d);
     km.cnorm = a.take<float>(G.KP);
     km.split = kmeans_split_supported(P.d) ? 1 : 0;
+    // points (split halves or FP32) beyond 64 MB: assignment blocks of one
+    // point tile run together (see the assignment kernels' block order)
+    km.group_major = (size_t)n * P.d * 4 > ((size_t)64 << 20) ? 1 : 0;
     km.zh = a.take<uint16_t>(km.split ? (size_t)n * P.d : 1);
     km.zl = a.take<uint16_t>(km.split ? (size_t)n * P.d : 1);
     km.ch = a.take<uint16_t>(km.split ? (size_t)G.KP * P.d : 1);

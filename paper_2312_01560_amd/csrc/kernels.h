@@ -89,6 +89,7 @@ struct KmeansPlan {
     // Split-fp16 operands of the assignment (split != 0): x 2^s = hi + lo,
     // s = 10 - (exponent of the largest |z|), both halves fp16 bit patterns.
     int32_t split;
+    int32_t group_major;     // assignment block order: candidate group fastest (large N)
     uint16_t* zh;            // [n x d]
     uint16_t* zl;            // [n x d]
     uint16_t* ch;            // [KP x d]
