@@ -123,15 +123,33 @@ __global__ __launch_bounds__(kRaceThreads) void k_race(KmeansPlan p, const float
                                                        int t, uint64_t seed) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int stride = gridDim.x * blockDim.x;
+    // Odd picks sweep from the last point: the end of Z, read last by the
+    // previous pick, is still in the memory-side cache (the result does not
+    // depend on the order: ties go to the lowest index).
+    auto point = [&](int idx) { return (t & 1) ? p.n - 1 - idx : idx; };
+    // The draws E = -ln u and the old weights of the first kRacePre points
+    // of each thread do not depend on the previous pick: they are computed
+    // and loaded before it is resolved, overlapping that reduction.
+    constexpr int kRacePre = 8;
+    double epre[kRacePre];
+    float wpre[kRacePre];
+#pragma unroll
+    for (int k = 0; k < kRacePre; ++k) {
+        const int idx = tid + k * stride;
+        epre[k] = 0.0;
+        wpre[k] = 1.0f;
+        if (idx < p.n) {
+            const int i = point(idx);
+            const U64x4 b = philox4x64_10((uint64_t)i, (uint64_t)t, 0, 0, seed, kStreamRace);
+            epre[k] = -own_ln(uniform52(b.v[0]));
+            if (t > 1) wpre[k] = p.w[i];
+        }
+    }
     const int prev = t > 0 ? race_resolve(p, t - 1) : -1;
     double best = INFINITY;
     int bidx = INT_MAX;
     const float* zp = prev >= 0 ? Z + (size_t)prev * D : Z;
-    for (int idx = tid; idx < p.n; idx += stride) {
-        // odd picks sweep from the last point: the end of Z, read last by
-        // the previous pick, is still in the memory-side cache (the result
-        // does not depend on the order: ties go to the lowest index)
-        const int i = (t & 1) ? p.n - 1 - idx : idx;
+    auto visit = [&](int i, double e, float wold) {
         float wi = 1.0f;
         if (t > 0) {
             const float* zi = Z + (size_t)i * D;
@@ -146,18 +164,26 @@ __global__ __launch_bounds__(kRaceThreads) void k_race(KmeansPlan p, const float
                 dist += dz * dz;
                 dist += dw * dw;
             }
-            wi = (t == 1) ? dist : fminf(p.w[i], dist);
+            wi = (t == 1) ? dist : fminf(wold, dist);
             p.w[i] = wi;
         }
         if (wi > 0.f) {
-            const U64x4 b = philox4x64_10((uint64_t)i, (uint64_t)t, 0, 0, seed, kStreamRace);
-            const double e = -own_ln(uniform52(b.v[0]));
             const double ratio = e / (double)wi;
             if (ratio < best) {
                 best = ratio;
                 bidx = i;
             }
         }
+    };
+#pragma unroll
+    for (int k = 0; k < kRacePre; ++k) {
+        const int idx = tid + k * stride;
+        if (idx < p.n) visit(point(idx), epre[k], wpre[k]);
+    }
+    for (int idx = tid + kRacePre * stride; idx < p.n; idx += stride) {
+        const int i = point(idx);
+        const U64x4 b = philox4x64_10((uint64_t)i, (uint64_t)t, 0, 0, seed, kStreamRace);
+        visit(i, -own_ln(uniform52(b.v[0])), t > 1 ? p.w[i] : 1.0f);
     }
     // work-group minimum, written for the next launch
 #pragma unroll
