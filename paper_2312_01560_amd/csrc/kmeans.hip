@@ -21,6 +21,7 @@
 #include <limits.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "kernels.h"
 
@@ -1179,12 +1180,11 @@ void launch_update(const KmeansPlan& p, const float* Z, size_t lds_max, int it, 
     const size_t lds = kmeans_update_lds(p.usk_max, p.d);
     const int nsl = (p.d + kUpdSlice - 1) / kUpdSlice;
     dim3 grid(p.uwork, nsl);
-    static bool attr_set = false;
-    if (!attr_set) {
+    static std::once_flag attr_once;   // contexts may launch from several host threads
+    std::call_once(attr_once, [&] {
         (void)hipFuncSetAttribute((const void*)k_update, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds_max);
-        attr_set = true;
-    }
+    });
     hipLaunchKernelGGL(k_update, grid, dim3(kUpdWaves * kWave), lds, st, p, Z);
     hipLaunchKernelGGL(k_update_finish, dim3(p.KP + 1), dim3(256), 0, st, p, it, t_max);
 }

@@ -18,6 +18,7 @@
 #include <limits.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "kernels.h"
 
@@ -291,12 +292,11 @@ void launch_edge_score(const GraphView& g, const ScorePlan& p, const uint8_t* la
     const int rpw = score_rpw(g.n, p.S, p.grid);
 #define EDGE(LV)                                                                              \
     {                                                                                         \
-        static bool attr = false;                                                             \
-        if (!attr) {                                                                          \
+        static std::once_flag attr_once;                                                      \
+        std::call_once(attr_once, [] {                                                        \
             (void)hipFuncSetAttribute((const void*)k_edge_score<LV>,                          \
                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024); \
-            attr = true;                                                                      \
-        }                                                                                     \
+        });                                                                                   \
         hipLaunchKernelGGL(k_edge_score<LV>, dim3(p.grid), dim3(256), lds, st, g, p, lab, rpw); \
     }
     switch (lpr) {

@@ -7,6 +7,7 @@
 //                 G_U = G_Z o (1 - Z^2)
 //   G_W = P^T G_U (MFMA, split over rows, partials combined in fixed order)
 #include <algorithm>
+#include <mutex>
 
 #include "kernels.h"
 
@@ -231,12 +232,11 @@ static void wgrad2(const float* P, const float* GU, int n, float* part, float* G
     const int parts = wgrad_parts(n);
     const int rpb = (n + parts - 1) / parts;
     const size_t lds = (size_t)4 * LI * LO * sizeof(float);
-    static bool attr = false;
-    if (!attr) {
+    static std::once_flag attr_once;   // contexts may launch from several host threads
+    std::call_once(attr_once, [&] {
         (void)hipFuncSetAttribute((const void*)k_wgrad<LI, LO>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
-        attr = true;
-    }
+    });
     hipLaunchKernelGGL((k_wgrad<LI, LO>), dim3(parts), dim3(256), lds, st, P, GU, n, rpb, part);
     hipLaunchKernelGGL(k_wgrad_finish, dim3((LI * LO + 255) / 256), dim3(256), 0, st, part, parts,
                        LI * LO, GW);
