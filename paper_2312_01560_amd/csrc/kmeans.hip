@@ -453,6 +453,16 @@ __global__ __launch_bounds__(256) void k_assign(KmeansPlan p, const float* __res
 // B[8(l/16)+i][l%16] (points) per 32-wide k chunk; D as in the FP32 MFMA.
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 
+// -v for eight fp16 values, by their sign bits (exact for every value)
+__device__ __forceinline__ half8 neg_half8(half8 v) {
+    uint4 u = __builtin_bit_cast(uint4, v);
+    u.x ^= 0x80008000u;
+    u.y ^= 0x80008000u;
+    u.z ^= 0x80008000u;
+    u.w ^= 0x80008000u;
+    return __builtin_bit_cast(half8, u);
+}
+
 // Centre tiles pass through LDS: the four waves of a work-group walk the same
 // candidate group, so the 256 threads load each 16-centre tile (hi and lo
 // halves, norms) once, one tile ahead of the MFMAs, into a double buffer;
@@ -482,8 +492,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3))) voi
         const _Float16* lr = reinterpret_cast<const _Float16*>(p.zl) + row;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            bh[ps][c] = *reinterpret_cast<const half8*>(hr + 32 * c);
-            bl[ps][c] = *reinterpret_cast<const half8*>(lr + 32 * c);
+            bh[ps][c] = neg_half8(*reinterpret_cast<const half8*>(hr + 32 * c));
+            bl[ps][c] = neg_half8(*reinterpret_cast<const half8*>(lr + 32 * c));
         }
     }
     // the group's candidates, one per lane (the same in every wave)
@@ -500,8 +510,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3))) voi
     }
     const uint64_t amask = __ballot(my_act);
     if (amask == 0) return;                   // uniform across the work-group
-    // scores in units of 2^(1-2s): cnorm 2^(2s-1) - acc orders the centres
-    // exactly as cnorm - 2 z.c does (scaling by a power of two is exact)
+    // scores in units of 2^(1-2s): cnorm 2^(2s-1) - z.c 2^2s orders the
+    // centres exactly as cnorm - 2 z.c does (scaling by a power of two is
+    // exact).  The point halves are held negated (exact: a sign flip), so
+    // each tile's MFMA chain starts from the staged norms and ends on the
+    // score itself, with no subtraction per element.
     const int nexp = 2 * split_exp(p) - 1;
     const _Float16* chp = reinterpret_cast<const _Float16*>(p.ch);
     const _Float16* clp = reinterpret_cast<const _Float16*>(p.cl);
@@ -577,13 +590,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3))) voi
         if (more) ASSIGN_ISSUE(nkoff, ntile)
         // this tile's operands from LDS
         const float4 cnn = *reinterpret_cast<const float4*>(&cs[buf][4 * g]);
-        const float cnv[4] = {cnn.x, cnn.y, cnn.z, cnn.w};
         // the PS accumulators are independent: interleaving them keeps the
         // matrix unit busy instead of waiting on one dependent chain; each
         // 32-wide chunk's A operands are read from LDS just before its MFMAs
         floatx4 acc[PS];
 #pragma unroll
-        for (int ps = 0; ps < PS; ++ps) acc[ps] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int ps = 0; ps < PS; ++ps) acc[ps] = floatx4{cnn.x, cnn.y, cnn.z, cnn.w};
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const half8 ah = *reinterpret_cast<const half8*>(&hs[buf][li][8 * g + 32 * c]);
@@ -602,7 +614,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3))) voi
         for (int ps = 0; ps < PS; ++ps) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const float sc = cnv[v] - acc[ps][v];
+                const float sc = acc[ps][v];
                 if (sc < bv[ps]) {
                     bv[ps] = sc;
                     bi[ps] = tile * 16 + 4 * g + v;
