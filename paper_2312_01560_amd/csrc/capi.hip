@@ -395,6 +395,8 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
     km.picks = P.picks_int;
     km.lab_cm = a.take<uint8_t>((size_t)G.Kc * n);
     km.lab_old = a.take<uint8_t>((size_t)G.Kc * n);
+    km.nchunks = (int)(((int64_t)n + 63) / 64);
+    km.moved_it = a.take<int32_t>((size_t)km.nchunks * G.Kc);
     km.status = ctx->d_status;
     // scores
     ScorePlan& sc = P.sc;
@@ -578,6 +580,7 @@ raft_status do_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* 
                   "poll slots exceed the pinned scratch");
     int poll = 0;
     for (int it = 1; it <= t_max; ++it) {
+        km.it = it;
         {
             ProfScope ps(ctx, RAFT_PROF_ASSIGN, st);
             launch_assign(km, Z, ctx->num_cu, st);

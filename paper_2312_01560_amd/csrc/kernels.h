@@ -106,6 +106,12 @@ struct KmeansPlan {
     int32_t* picks;          // [k_max]
     uint8_t* lab_cm;         // [Kc x n] candidate-major labels
     uint8_t* lab_old;        // [Kc x n] labels before the last assignment (0xFF: none)
+    // Last iteration in which a label of the 64-point chunk changed, per
+    // candidate: written by the assignment, read by the update of the same
+    // iteration to skip chunks no point of a candidate left or entered.
+    int32_t* moved_it;       // [nchunks x Kc]
+    int32_t nchunks;         // ceil(n / 64)
+    int32_t it;              // Lloyd iteration of the launch (1-based)
     int32_t* status;
 };
 

@@ -432,6 +432,7 @@ __global__ __launch_bounds__(256) void k_assign(KmeansPlan p, const float* __res
                 changed = old != nw;
                 *lp = nw;
                 p.lab_old[(size_t)k * p.n + pt] = old;
+                if (changed) p.moved_it[(size_t)(pt >> 6) * p.Kc + k] = p.it;
             }
             const uint64_t m = __ballot(changed);
             if (lane == 0 && m) p.changes[k] = 1;   // only zero / non-zero is read
@@ -629,6 +630,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3))) voi
                 changed = old_lab != nw;
                 p.lab_cm[(size_t)k * p.n + ptl] = nw;
                 p.lab_old[(size_t)k * p.n + ptl] = old_lab;
+                if (changed) p.moved_it[(size_t)(ptl >> 6) * p.Kc + k] = p.it;
             }
             const uint64_t m = __ballot(changed);
             if (lane == 0 && m) p.changes[k] = 1;   // only zero / non-zero is read
@@ -730,8 +732,12 @@ __global__ __launch_bounds__(256) void k_split_points(KmeansPlan p, const float*
 // while the work shrinks with the number of moved points.
 //
 // One work item = (update group, point range) and one slice of up to 64
-// columns.  Per chunk of 64 points a wave first reads both label columns of
-// every candidate of the group (lane = point) into LDS and counts the moves,
+// columns.  The assignment marks, per candidate and 64-point chunk, the
+// iteration in which a label of the chunk last changed; a wave reads those
+// marks for four of its chunks at once and passes over every (chunk,
+// candidate) without a move, and over chunks without any (most of them once
+// the candidates settle).  Per remaining chunk a wave first reads both label
+// columns of every marked candidate (lane = point) into LDS and counts the moves,
 // then loads z of the points that moved for any candidate (lane = column,
 // one register per point), and walks the candidates again applying the +/-
 // into int64 LDS accumulators shared by the work-group, one contiguous
@@ -806,136 +812,159 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
     const int r1 = min(p.n, r0 + len);
     unsigned long long* acol = acc64 + lane;
     const int nc = t1 - t0;
-    // the group's candidates, one per lane, read back with readlane
+    // the group's candidates: lane l holds candidate l % 16 (read back with
+    // readlane from lanes 0..15, and by lane in the moved-flag loads), its
+    // centre count and its first accumulator row
+    const int mc = lane & (kUpdMaxCand - 1);
     int my_k = 0, my_K = 0, my_act = 0;
-    if (lane < nc) {
-        my_k = p.alist[t0 + lane];
+    if (mc < nc) {
+        my_k = p.alist[t0 + mc];
         my_K = p.ks[my_k];
         my_act = p.active[my_k] != 0;
     }
-    for (int cs = r0 + wid * kWave; cs < r1; cs += kUpdWaves * kWave) {
-        const int np = min(kWave, r1 - cs);
-        const bool lv = lane < np;
-        // pass 1: labels to LDS, counts, and the points moved for any candidate;
-        // every label load of the chunk is issued before the first is used
-        uint64_t U = 0;
+    int my_base = 0;
+    for (int m = 0, b = 0; m < nc; ++m) {
+        if (mc == m) my_base = b;
+        b += __builtin_amdgcn_readlane(my_K, m);
+    }
+    // Chunks of this wave in batches of four: lane (j, m) reads whether
+    // candidate m moved a point of chunk j in this iteration; the update skips
+    // every (chunk, candidate) without a move, and whole chunks without one.
+    constexpr int kStride = kUpdWaves * kWave;
+    for (int cb = r0 + wid * kWave; cb < r1; cb += 4 * kStride) {
+        uint64_t F;
         {
-            int nlv[kUpdMaxCand], olv[kUpdMaxCand];
+            const int csj = cb + (lane >> 4) * kStride;
+            bool f = false;
+            if (mc < nc && my_act != 0 && csj < r1)
+                f = p.moved_it[(size_t)(csj >> 6) * p.Kc + my_k] == p.it;
+            F = __ballot(f);
+        }
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t cm = (uint32_t)(F >> (16 * j)) & 0xFFFFu;
+            if (cm == 0) continue;                // also every chunk past r1
+            const int cs = cb + j * kStride;
+            const int np = min(kWave, r1 - cs);
+            const bool lv = lane < np;
+            // pass 1: labels to LDS, counts, and the points moved for any candidate;
+            // every label load of the chunk is issued before the first is used
+            uint64_t U = 0;
+            {
+                int nlv[kUpdMaxCand], olv[kUpdMaxCand];
 #pragma unroll
-            for (int m = 0; m < kUpdMaxCand; ++m) {
-                nlv[m] = 0;
-                olv[m] = 0;
-                const int k = __builtin_amdgcn_readlane(my_k, m);
-                if (m < nc && __builtin_amdgcn_readlane(my_act, m) != 0 && lv) {
-                    nlv[m] = p.lab_cm[(size_t)k * p.n + cs + lane];
-                    olv[m] = p.lab_old[(size_t)k * p.n + cs + lane];
-                }
-            }
-            int base = 0;
-            for (int m = 0; m < nc; ++m) {
-                const int K = __builtin_amdgcn_readlane(my_K, m);
-                const int nl = nlv[m], ol = olv[m];
-                stage_n[m * kWave + lane] = (uint8_t)nl;
-                stage_o[m * kWave + lane] = (uint8_t)ol;
-                const bool moved = nl != ol;
-                U |= __ballot(moved);
-                if (moved) {
-                    atomicAdd(&touch[base + nl], 1);
-                    if (sl == 0) atomicAdd(&cnt[base + nl], 1);
-                    if (ol != 0xFF) {
-                        atomicAdd(&touch[base + ol], 1);
-                        if (sl == 0) atomicSub(&cnt[base + ol], 1);
+                for (int m = 0; m < kUpdMaxCand; ++m) {
+                    nlv[m] = 0;
+                    olv[m] = 0;
+                    const int k = __builtin_amdgcn_readlane(my_k, m);
+                    if (((cm >> m) & 1u) != 0u && lv) {
+                        nlv[m] = p.lab_cm[(size_t)k * p.n + cs + lane];
+                        olv[m] = p.lab_old[(size_t)k * p.n + cs + lane];
                     }
                 }
-                base += K;
+                for (int m = 0; m < nc; ++m) {
+                    if (((cm >> m) & 1u) == 0u) continue;
+                    const int base = __builtin_amdgcn_readlane(my_base, m);
+                    const int nl = nlv[m], ol = olv[m];
+                    stage_n[m * kWave + lane] = (uint8_t)nl;
+                    stage_o[m * kWave + lane] = (uint8_t)ol;
+                    const bool moved = nl != ol;
+                    U |= __ballot(moved);
+                    if (moved) {
+                        atomicAdd(&touch[base + nl], 1);
+                        if (sl == 0) atomicAdd(&cnt[base + nl], 1);
+                        if (ol != 0xFF) {
+                            atomicAdd(&touch[base + ol], 1);
+                            if (sl == 0) atomicSub(&cnt[base + ol], 1);
+                        }
+                    }
+                }
             }
-        }
-        if (U == 0) continue;
-        // z of the moved points (lane = column): every load is issued before
-        // the first conversion, so the loads overlap.  Lanes past d read
-        // column d-1; they only feed accumulator columns never written out.
-        // Only moved points are loaded; the empty asm after the loads keeps
-        // the compiler from pulling each conversion into its load's branch
-        // (which would wait on every load in turn).
-        float zr[kWave];
+            if (U == 0) continue;
+            // z of the moved points (lane = column): every load is issued before
+            // the first conversion, so the loads overlap.  Lanes past d read
+            // column d-1; they only feed accumulator columns never written out.
+            // Only moved points are loaded; the empty asm after the loads keeps
+            // the compiler from pulling each conversion into its load's branch
+            // (which would wait on every load in turn).
+            float zr[kWave];
 #pragma unroll
-        for (int q = 0; q < kWave; ++q) {
-            zr[q] = 0.f;
-            if (bit_set(U, q)) zr[q] = Z[(size_t)(cs + q) * p.d + colc];
-        }
+            for (int q = 0; q < kWave; ++q) {
+                zr[q] = 0.f;
+                if (bit_set(U, q)) zr[q] = Z[(size_t)(cs + q) * p.d + colc];
+            }
 #pragma unroll
-        for (int q = 0; q < kWave; ++q) asm volatile("" : "+v"(zr[q]));
-        // quantised z in two 32-wide vectors: constant indices in the unrolled
-        // sweeps, a relative register move in the sparse walk
-        i32x32 zf0, zf1;
+            for (int q = 0; q < kWave; ++q) asm volatile("" : "+v"(zr[q]));
+            // quantised z in two 32-wide vectors: constant indices in the unrolled
+            // sweeps, a relative register move in the sparse walk
+            i32x32 zf0, zf1;
 #pragma unroll
-        for (int q = 0; q < 32; ++q) {
-            zf0[q] = __float2int_rn(ldexpf(zr[q], fe));
-            zf1[q] = __float2int_rn(ldexpf(zr[q + 32], fe));
-        }
+            for (int q = 0; q < 32; ++q) {
+                zf0[q] = __float2int_rn(ldexpf(zr[q], fe));
+                zf1[q] = __float2int_rn(ldexpf(zr[q + 32], fe));
+            }
 #define ZF(q) ((q) < 32 ? zf0[(q)] : zf1[(q) - 32])
-        // pass 2: the adds and subtractions, candidate by candidate
-        int base = 0;
-        for (int m = 0; m < nc; ++m) {
-            const int K = __builtin_amdgcn_readlane(my_K, m);
-            const int nl = stage_n[m * kWave + lane];
-            const int ol = stage_o[m * kWave + lane];
-            const bool moved = nl != ol;
-            const bool had = moved && ol != 0xFF;
-            const uint64_t mv = __ballot(moved);
-            const uint64_t mo = __ballot(had);
-            const int nrow = moved ? base + nl : dummy;
-            const int orow = had ? base + ol : dummy;
-            base += K;
-            if (mv == 0) continue;
-            if (mo == 0 && __popcll(mv) >= kWave / 2) {
+            // pass 2: the adds and subtractions, candidate by candidate
+            for (uint32_t rc = cm; rc != 0u; rc &= rc - 1u) {
+                const int m = __builtin_ctz(rc);
+                const int base = __builtin_amdgcn_readlane(my_base, m);
+                const int nl = stage_n[m * kWave + lane];
+                const int ol = stage_o[m * kWave + lane];
+                const bool moved = nl != ol;
+                const bool had = moved && ol != 0xFF;
+                const uint64_t mv = __ballot(moved);
+                const uint64_t mo = __ballot(had);
+                const int nrow = moved ? base + nl : dummy;
+                const int orow = had ? base + ol : dummy;
+                if (mv == 0) continue;
+                if (mo == 0 && __popcll(mv) >= kWave / 2) {
 #pragma unroll
-                for (int q = 0; q < kWave; ++q) {
-                    const int a = __builtin_amdgcn_readlane(nrow, q);
-                    atomicAdd(acol + (size_t)a * kUpdSlice, widen_at_use(ZF(q)));
+                    for (int q = 0; q < kWave; ++q) {
+                        const int a = __builtin_amdgcn_readlane(nrow, q);
+                        atomicAdd(acol + (size_t)a * kUpdSlice, widen_at_use(ZF(q)));
+                    }
+                    continue;
                 }
-                continue;
-            }
-            if (mo == mv && __popcll(mv) <= kUpdSparse) {
-                // few moved points, each with a cluster: walk the set bits
-                for (uint64_t r = mv; r != 0; r &= r - 1) {
-                    const int q = __builtin_ctzll(r);
-                    const int a = __builtin_amdgcn_readlane(nrow, q);
-                    const int o = __builtin_amdgcn_readlane(orow, q);
-                    const int z = q < 32 ? zf0[q] : zf1[q - 32];
-                    atomicAdd(acol + (size_t)a * kUpdSlice, widen_at_use(z));
-                    atomicAdd(acol + (size_t)o * kUpdSlice, widen_at_use(-z));
+                if (mo == mv && __popcll(mv) <= kUpdSparse) {
+                    // few moved points, each with a cluster: walk the set bits
+                    for (uint64_t r = mv; r != 0; r &= r - 1) {
+                        const int q = __builtin_ctzll(r);
+                        const int a = __builtin_amdgcn_readlane(nrow, q);
+                        const int o = __builtin_amdgcn_readlane(orow, q);
+                        const int z = q < 32 ? zf0[q] : zf1[q - 32];
+                        atomicAdd(acol + (size_t)a * kUpdSlice, widen_at_use(z));
+                        atomicAdd(acol + (size_t)o * kUpdSlice, widen_at_use(-z));
+                    }
+                    continue;
                 }
-                continue;
-            }
-            if (mo == mv) {
-                // every moved point had a cluster (all iterations after the
-                // first): one bit test per point for both the add and the
-                // subtraction
+                if (mo == mv) {
+                    // every moved point had a cluster (all iterations after the
+                    // first): one bit test per point for both the add and the
+                    // subtraction
+#pragma unroll
+                    for (int q = 0; q < kWave; ++q) {
+                        if (bit_set(mv, q)) {
+                            const int a = __builtin_amdgcn_readlane(nrow, q);
+                            const int o = __builtin_amdgcn_readlane(orow, q);
+                            atomicAdd(acol + (size_t)a * kUpdSlice, widen_at_use(ZF(q)));
+                            atomicAdd(acol + (size_t)o * kUpdSlice, widen_at_use(-ZF(q)));
+                        }
+                    }
+                    continue;
+                }
 #pragma unroll
                 for (int q = 0; q < kWave; ++q) {
                     if (bit_set(mv, q)) {
                         const int a = __builtin_amdgcn_readlane(nrow, q);
-                        const int o = __builtin_amdgcn_readlane(orow, q);
                         atomicAdd(acol + (size_t)a * kUpdSlice, widen_at_use(ZF(q)));
-                        atomicAdd(acol + (size_t)o * kUpdSlice, widen_at_use(-ZF(q)));
                     }
                 }
-                continue;
-            }
+                if (mo == 0) continue;
 #pragma unroll
-            for (int q = 0; q < kWave; ++q) {
-                if (bit_set(mv, q)) {
-                    const int a = __builtin_amdgcn_readlane(nrow, q);
-                    atomicAdd(acol + (size_t)a * kUpdSlice, widen_at_use(ZF(q)));
-                }
-            }
-            if (mo == 0) continue;
-#pragma unroll
-            for (int q = 0; q < kWave; ++q) {
-                if (bit_set(mo, q)) {
-                    const int o = __builtin_amdgcn_readlane(orow, q);
-                    atomicAdd(acol + (size_t)o * kUpdSlice, widen_at_use(-ZF(q)));
+                for (int q = 0; q < kWave; ++q) {
+                    if (bit_set(mo, q)) {
+                        const int o = __builtin_amdgcn_readlane(orow, q);
+                        atomicAdd(acol + (size_t)o * kUpdSlice, widen_at_use(-ZF(q)));
+                    }
                 }
             }
         }
@@ -1060,6 +1089,7 @@ __global__ void k_kmeans_reset(KmeansPlan p) {
     for (int64_t i = tid; i < (int64_t)p.Kc * p.n; i += stride) p.lab_cm[i] = 0xFF;
     for (int64_t i = tid; i < (int64_t)p.KP * p.d; i += stride) p.S64[i] = 0;
     for (int64_t i = tid; i < p.KP; i += stride) p.N32[i] = 0;
+    for (int64_t i = tid; i < (int64_t)p.nchunks * p.Kc; i += stride) p.moved_it[i] = 0;
     for (int64_t k = tid; k < p.Kc; k += stride) {
         p.active[k] = 1;
         p.changes[k] = 0;
