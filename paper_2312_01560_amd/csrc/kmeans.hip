@@ -16,8 +16,7 @@
 // with ties to the lowest index: split-fp16 operands (k_assign_h) for d a
 // multiple of 32, FP32 (k_assign) otherwise.  The update keeps exact integer
 // centre sums across iterations and adds or subtracts only the points whose
-// label changed (k_update, k_update_finish), reading labels only in the
-// 64-point chunks the assignment marked as changed.
+// label changed (k_update, k_update_finish).
 #include <float.h>
 #include <limits.h>
 
