@@ -278,19 +278,24 @@ __device__ __forceinline__ void load_ctile(const KmeansPlan& p, int cb, int li, 
 
 // Block order of the assignment kernels (one-dimensional grid).  When the
 // points are too large for the memory-side cache (group_major, set by the
-// host), the candidate group varies fastest, so the work-groups of all groups
-// of one point tile run close together and the tile's points come from HBM
-// once, then from that cache (at N = 1M the points are 512 MB and were
-// streamed once per group: 1.89 -> 2.0 graphs/s).  Otherwise the point tile
-// varies fastest, which keeps a group's centre tiles hot (9 % faster at
-// N = 50k, where all points stay cached).
+// host), all candidate groups of one point tile run back to back on one
+// XCD, so the tile's points come from memory once and then from that XCD's
+// L2: work-groups are dealt to the eight XCDs round robin (block b runs on
+// XCD b mod 8), so block b = 8 s + x takes point tile 8 (s / agroups) + x
+// and candidate group s mod agroups; the host pads the tile count to a
+// multiple of 8 and padding blocks exit.  Otherwise the point tile varies
+// fastest, which keeps a group's centre tiles hot (9 % faster at N = 50k,
+// where all points stay cached).
 __device__ __forceinline__ int assign_group(const KmeansPlan& p) {
+    if (p.group_major) return (int)((blockIdx.x >> 3) % (unsigned)p.agroups);
     const int tiles = (int)(gridDim.x / (unsigned)p.agroups);
-    return p.group_major ? (int)(blockIdx.x % (unsigned)p.agroups) : (int)blockIdx.x / tiles;
+    return (int)blockIdx.x / tiles;
 }
 __device__ __forceinline__ int assign_tile(const KmeansPlan& p) {
+    if (p.group_major)
+        return (int)(((blockIdx.x >> 3) / (unsigned)p.agroups) * 8u + (blockIdx.x & 7u));
     const int tiles = (int)(gridDim.x / (unsigned)p.agroups);
-    return p.group_major ? (int)(blockIdx.x / (unsigned)p.agroups) : (int)blockIdx.x % tiles;
+    return (int)blockIdx.x % tiles;
 }
 
 // End of a candidate in the assignment kernels.  Lane (li, g) holds, for
@@ -482,7 +487,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3))) voi
     const int wid = tid / kWave;
     const int g = lane >> 4;
     const int li = lane & 15;
-    // every wave takes part in the barriers; rows beyond n are clamped
+    // every wave takes part in the barriers; rows beyond n are clamped, and
+    // a work-group wholly past n (tile padding) leaves before any barrier
+    if (p.group_major && assign_tile(p) * 4 * 16 * PS >= p.n) return;
     const int pbase = (assign_tile(p) * 4 + wid) * 16 * PS;
     half8 bh[PS][NC], bl[PS][NC];
 #pragma unroll
@@ -1173,7 +1180,9 @@ void launch_assign(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t 
     {                                                                                     \
         constexpr int PS = assign_ps<DV>();                                               \
         const int pts_per_block = 4 * 16 * PS;                                            \
-        dim3 grid((unsigned)(((p.n + pts_per_block - 1) / pts_per_block) * p.agroups));    \
+        int tiles_ = (p.n + pts_per_block - 1) / pts_per_block;                           \
+        if (p.group_major) tiles_ = (tiles_ + 7) / 8 * 8;                                 \
+        dim3 grid((unsigned)(tiles_ * p.agroups));                                        \
         if constexpr (DV % 32 == 0) {                                                     \
             if (p.split) {                                                                \
                 hipLaunchKernelGGL((k_assign_h<DV, PS>), grid, dim3(256), 0, st, p);      \
