@@ -288,6 +288,46 @@ def test_kmeans_centres_are_means(ctx, api_mod, ragged, d):
                   range(len(cfg.ks)))
 
 
+def test_kmeans_large_point_set(ctx, api_mod):
+    """Points larger than 64 MB (N = 140,001, d = 128: 72 MB) take the
+    assignment's other block order (all candidate groups of a point tile on
+    one XCD, tile count padded to a multiple of 8): the first picks equal the
+    oracle's, every point of every converged candidate sits at its nearest
+    centre, and the centres are the means of their points."""
+    n, d = 140001, 128
+    rp = (2 * np.arange(n + 1)).astype(np.int32)                      # a ring
+    nb = np.stack([(np.arange(n) - 1) % n, (np.arange(n) + 1) % n], axis=1)
+    ci = np.sort(nb, axis=1).reshape(-1).astype(np.int32)
+    # clustered points (40 directions plus noise), so that Lloyd converges
+    # within the iteration cap; isotropic points in 128 dimensions keep
+    # trading boundary points for hundreds of iterations
+    rng = np.random.default_rng(5)
+    dirs = rng.standard_normal((40, d))
+    z = dirs[rng.integers(0, 40, n)] + 0.5 * rng.standard_normal((n, d))
+    z = (z / np.linalg.norm(z, axis=1, keepdims=True)).astype(np.float32)
+    z64 = z.astype(np.float64)
+    g = api_mod.Graph(ctx, rp, ci)
+    cfg = api_mod.Config(op=0, proj_dim=d, layer_dims=[d], k_min=2, k_max=20, k_step=3,
+                         kmeans_max_iter=300)
+    out = api_mod.partition(ctx, g, cfg, torch.from_numpy(z).cuda(), want_centres=True)
+    torch.cuda.synchronize()
+    ctx.sync_status()
+    assert np.array_equal(to_np(out["picks"])[:8], okm.seed_picks(z64, 8, 0))
+    lab = to_np(out["labels_all"]).astype(np.int64)
+    iters = to_np(out["iters"])
+    cen = to_np(out["centres"]).astype(np.float64)
+    off = np.concatenate([[0], np.cumsum(cfg.ks)])
+    converged = [j for j in range(len(cfg.ks)) if iters[j] < 300]
+    assert converged
+    for j in converged:
+        k = cfg.ks[j]
+        assert lab[:, j].max() < k
+        dist = okm.sq_distances(z64, cen[off[j]:off[j + 1]])
+        mine = dist[np.arange(n), lab[:, j]]
+        assert np.all(mine <= dist.min(axis=1) + 1e-5), k
+    check_centres(to_np(out["centres"]), z64, lab, cfg.ks, iters, 300, converged)
+
+
 # ---------------------------------------------------------------- A1-A7 --
 
 @pytest.mark.parametrize("op", [0, 1, 2])
