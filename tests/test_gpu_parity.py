@@ -369,6 +369,29 @@ def test_run_deterministic(ctx, api_mod, ragged):
         assert np.array_equal(to_np(v), a[k]), k
 
 
+def test_poll_period_does_not_change_results(ctx, api_mod, ragged):
+    """The host acts on one-poll-stale copies of the active flags, so the work
+    lists may still hold retired candidates, which every kernel skips: the
+    outputs are the same, bit for bit, whatever the poll period."""
+    z = np.random.default_rng(9).standard_normal((ragged.n, 64)).astype(np.float32)
+    z /= np.linalg.norm(z, axis=1, keepdims=True)
+    zt = torch.from_numpy(z).cuda()
+    g = api_mod.Graph(ctx, ragged.row_ptr, ragged.col_idx)
+    ref = None
+    for every in (4, 1, 7):
+        cfg = api_mod.Config(op=0, proj_dim=64, layer_dims=[64], k_min=2, k_max=60, k_step=2,
+                             kmeans_max_iter=200, check_every=every)
+        out = api_mod.partition(ctx, g, cfg, zt, want_centres=True)
+        torch.cuda.synchronize()
+        ctx.sync_status()
+        got = {k: to_np(v).copy() for k, v in out.items()}
+        if ref is None:
+            ref = got
+            continue
+        for k, v in got.items():
+            assert np.array_equal(v, ref[k]), (every, k)
+
+
 def test_workspace_too_small(ctx, api_mod, small_graph):
     g0, m = small_graph
     g = api_mod.Graph(ctx, g0.row_ptr, g0.col_idx)
