@@ -269,11 +269,13 @@ def check_centres(centres, z64, lab, ks, iters, t_max, cands):
     assert checked > 0
 
 
-@pytest.mark.parametrize("d", [16, 64])
+@pytest.mark.parametrize("d", [16, 64, 128])
 def test_kmeans_centres_are_means(ctx, api_mod, ragged, d):
     """The incremental update (only moved points added and subtracted) ends
     with the same centres as a sum from scratch over the final labels, for
-    the FP32 (d = 16) and split-fp16 (d = 64) assignment paths."""
+    the FP32 (d = 16) and split-fp16 (d = 64, 128) assignment paths; at
+    d = 128 a wave's 48 points straddle the 64-point chunks whose move marks
+    gate the update, and the update takes two column slices."""
     z = np.random.default_rng(3).standard_normal((ragged.n, d)).astype(np.float32)
     z /= np.linalg.norm(z, axis=1, keepdims=True)
     g = api_mod.Graph(ctx, ragged.row_ptr, ragged.col_idx)
