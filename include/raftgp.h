@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define RAFT_ABI_VERSION 2
+#define RAFT_ABI_VERSION 3
 
 typedef int32_t raft_status;
 #define RAFT_OK             0
@@ -98,8 +98,11 @@ typedef struct {
 
 /* ---- context and errors ------------------------------------------------- */
 
-/* Create a context on HIP device `device`.  *out receives the handle. */
-raft_status raft_ctx_create(int device, raft_ctx** out);
+/* Create a context on HIP device `device`.  *out receives the handle.
+ * autotune_cache (nullable): path of a text file in which the launch-shape
+ * tuner keeps its measured choices (read at creation when it exists,
+ * rewritten when a choice is added); NULL keeps the choices in memory only. */
+raft_status raft_ctx_create(int device, const char* autotune_cache, raft_ctx** out);
 void        raft_ctx_destroy(raft_ctx* ctx);
 const char* raft_status_string(raft_status s);
 /* Copies the last error message of this context into buf (NUL-terminated);
@@ -112,15 +115,18 @@ raft_status raft_sync_status(raft_ctx* ctx, void* stream);
 
 /* ---- graph (Sec. II: undirected unweighted A, CSR) ----------------------- */
 
-/* Copies an int32 CSR (row_ptr[n+1], col_idx[nnz]) into library-owned device
+/* Copies a CSR (row_ptr[n+1], col_idx[nnz] int32) into library-owned device
  * memory, validates it on the device (sorted unique columns, no self loops,
  * symmetric, in range) and computes degrees, 2e and the scale vectors
- * D^-1/2 and (D+1)^-1/2.  `inputs_on_device` != 0 means the two arrays are
- * device pointers.  Synchronous: returns after validation (RAFT_E_CSR on a
- * malformed graph).  The caller may free its arrays on return. */
-raft_status raft_graph_create(raft_ctx* ctx, const int32_t* row_ptr, const int32_t* col_idx,
-                              int64_t n, int64_t nnz, int inputs_on_device, void* stream,
-                              raft_graph** out);
+ * D^-1/2 and (D+1)^-1/2.  row_ptr holds int32 entries, or int64 entries
+ * when row_ptr_is_int64 != 0; int64 offsets are checked (0 first, nnz last,
+ * non-decreasing) and narrowed to the library's int32 CSR, and nnz >= 2^31 - 1
+ * returns RAFT_E_UNSUPPORTED.  `inputs_on_device` != 0 means the two arrays
+ * are device pointers.  Synchronous: returns after validation (RAFT_E_CSR on
+ * a malformed graph).  The caller may free its arrays on return. */
+raft_status raft_graph_create(raft_ctx* ctx, const void* row_ptr, int row_ptr_is_int64,
+                              const int32_t* col_idx, int64_t n, int64_t nnz,
+                              int inputs_on_device, void* stream, raft_graph** out);
 void        raft_graph_destroy(raft_graph* g);
 /* Device copies of the degree vector (int32 [N]) and of the CSR (for tests). */
 raft_status raft_graph_degrees(const raft_graph* g, int32_t* deg_out, void* stream);
@@ -143,8 +149,14 @@ raft_status raft_gaussian(raft_ctx* ctx, uint64_t seed, uint64_t stream_id, int6
 
 /* ---- stages A2/A3: one sparse step and the projection -------------------- */
 
+/* Workspace bytes raft_spmm needs for (op, L): the FP64 column-sum
+ * partials of MOD_FULL's rank-1 term; 0 for the other operators. */
+raft_status raft_spmm_workspace_size(raft_ctx* ctx, const raft_graph* g, int32_t op, int32_t L,
+                                    size_t* bytes);
+
 /* Y_out = X Y_in for one operator X (RAFT_X_*), Y_in/Y_out [N x L] row-major,
- * distinct buffers.  MOD_FULL needs workspace for the column sums d^T Y_in.  */
+ * distinct buffers.  MOD_FULL needs workspace for the column sums d^T Y_in
+ * (raft_spmm_workspace_size); the other operators take ws = NULL.  */
 raft_status raft_spmm(raft_ctx* ctx, const raft_graph* g, int32_t op, int32_t L,
                       const float* Y_in, float* Y_out, void* ws, size_t ws_bytes, void* stream);
 
@@ -184,6 +196,24 @@ raft_status raft_partition(raft_ctx* ctx, const raft_graph* g, const raft_config
 raft_status raft_score(raft_ctx* ctx, const raft_graph* g, const uint8_t* labels_all,
                        int32_t Kc, const int32_t* ks, double* mod, double* ncut,
                        void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes raft_score needs for Kc labelings with block counts
+ * ks[Kc] (host array). */
+raft_status raft_score_workspace_size(raft_ctx* ctx, const raft_graph* g, int32_t Kc,
+                                     const int32_t* ks, size_t* bytes);
+
+/* ---- comparison of partitions (normalised mutual information) ----------- */
+
+/* Contingency counts of two labelings of the same n nodes: counts[r*kb + c]
+ * (device int64 [ka x kb], overwritten) = #{i : a[i] = r, b[i] = c}.  a, b
+ * are device int32 [n] with labels in [0, ka) and [0, kb); a label out of
+ * range is not counted and latches a status that raft_sync_status returns as
+ * RAFT_E_INVAL.  Integer counts, exact and independent of scheduling. */
+raft_status raft_confusion(raft_ctx* ctx, const int32_t* a, const int32_t* b, int64_t n,
+                           int32_t ka, int32_t kb, int64_t* counts, void* stream);
+/* Host-side finish: NMI = 2 I(a;b) / (H(a) + H(b)) in natural log from a
+ * HOST copy of the counts (1 when both entropies are 0). */
+raft_status raft_nmi_from_counts(const int64_t* counts, int32_t ka, int32_t kb, double* nmi);
 
 /* A1-A7: projection, embedding and model selection (synchronises `stream`). */
 raft_status raft_run(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg,

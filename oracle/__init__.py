@@ -15,7 +15,6 @@ Modules (each function cites the passage of the paper it follows):
 * ``kmeans``     -- nested k-means++ seeding (exponential race) and Lloyd.
 * ``scores``     -- modularity (Eq. 3), NCut (Eq. 1), model selection, NMI.
 * ``modloss``    -- relaxed modularity loss tr(S^T B S) and its adjoint.
-* ``hierarchical`` -- Alg. 1 hierarchical model selection with LMod (Eq. 7).
 * ``pipeline``   -- the whole path end to end.
 
 Parity status: every function is pinned by a ``-m "not gpu"`` test against a

@@ -6,7 +6,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libraftgp.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 MAX_LAYERS = 8
 MAX_K = 255
 
@@ -23,7 +23,8 @@ EXPORTS = [
     "raft_gcn_layer", "raft_embed", "raft_partition", "raft_score", "raft_run",
     "raft_get_stage_times", "raft_profile_enable", "raft_profile_read",
     "raft_train_workspace_size", "raft_gcn_forward", "raft_gcn_backward", "raft_modloss_forward",
-    "raft_modloss_backward", "raft_adam_step",
+    "raft_modloss_backward", "raft_adam_step", "raft_spmm_workspace_size",
+    "raft_score_workspace_size", "raft_confusion", "raft_nmi_from_counts",
 ]
 
 PROF_SPMM, PROF_DENSE, PROF_RACE, PROF_ASSIGN, PROF_UPDATE, PROF_SCORE = range(6)
@@ -70,13 +71,14 @@ _U64 = ctypes.c_uint64
 _SZ = ctypes.c_size_t
 
 _SIGNATURES = {
-    "raft_ctx_create": (_I32, [ctypes.c_int, ctypes.POINTER(_P)]),
+    "raft_ctx_create": (_I32, [ctypes.c_int, ctypes.c_char_p, ctypes.POINTER(_P)]),
     "raft_ctx_destroy": (None, [_P]),
     "raft_status_string": (ctypes.c_char_p, [_I32]),
     "raft_last_error": (_SZ, [_P, ctypes.c_char_p, _SZ]),
     "raft_abi_version": (_I32, []),
     "raft_sync_status": (_I32, [_P, _P]),
-    "raft_graph_create": (_I32, [_P, _P, _P, _I64, _I64, ctypes.c_int, _P, ctypes.POINTER(_P)]),
+    "raft_graph_create": (_I32, [_P, _P, ctypes.c_int, _P, _I64, _I64, ctypes.c_int, _P,
+                                 ctypes.POINTER(_P)]),
     "raft_graph_destroy": (None, [_P]),
     "raft_graph_degrees": (_I32, [_P, _P, _P]),
     "raft_workspace_size": (_I32, [_P, _P, ctypes.POINTER(RaftConfig), ctypes.POINTER(_SZ)]),
@@ -103,6 +105,11 @@ _SIGNATURES = {
     "raft_modloss_backward": (_I32, [_P, _P, _P, _I32, _P, _P, _P, _SZ, _P]),
     "raft_adam_step": (_I32, [_P, _P, _P, _P, _P, _I64, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, ctypes.c_float, _I32, _P]),
+    "raft_spmm_workspace_size": (_I32, [_P, _P, _I32, _I32, ctypes.POINTER(_SZ)]),
+    "raft_score_workspace_size": (_I32, [_P, _P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_SZ)]),
+    "raft_confusion": (_I32, [_P, _P, _P, _I64, _I32, _I32, _P, _P]),
+    "raft_nmi_from_counts": (_I32, [ctypes.POINTER(_I64), _I32, _I32,
+                                    ctypes.POINTER(ctypes.c_double)]),
 }
 
 _lib = None

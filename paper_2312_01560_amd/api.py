@@ -68,11 +68,12 @@ class Config:
 
 
 class Context:
-    def __init__(self, device=0):
+    def __init__(self, device=0, autotune_cache=None):
         self.lib = _lib.load()
         self.device = device
         h = ctypes.c_void_p()
-        st = self.lib.raft_ctx_create(device, ctypes.byref(h))
+        cache = autotune_cache.encode() if autotune_cache else None
+        st = self.lib.raft_ctx_create(device, cache, ctypes.byref(h))
         if st != 0:
             raise RaftError(st, "raft_ctx_create failed")
         self.h = h
@@ -111,16 +112,21 @@ class Graph:
     """Device CSR owned by the library (raft_graph)."""
 
     def __init__(self, ctx, row_ptr, col_idx, n=None):
+        """row_ptr: int32 or int64 offsets (int64 ones are checked and
+        narrowed by the library); col_idx: int32.  Host (numpy) or device
+        (torch) arrays."""
         self.ctx = ctx
         if isinstance(row_ptr, torch.Tensor) and row_ptr.is_cuda:
-            rp = row_ptr.to(torch.int32).contiguous()
+            wide = row_ptr.dtype == torch.int64
+            rp = row_ptr.contiguous() if wide else row_ptr.to(torch.int32).contiguous()
             ci = col_idx.to(torch.int32).contiguous()
             on_dev = 1
             rp_p, ci_p = _ptr(rp), _ptr(ci)
             nnz = ci.numel()
             keep = (rp, ci)
         else:
-            rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+            wide = np.asarray(row_ptr).dtype == np.int64
+            rp = np.ascontiguousarray(row_ptr, dtype=np.int64 if wide else np.int32)
             ci = np.ascontiguousarray(col_idx, dtype=np.int32)
             on_dev = 0
             rp_p = rp.ctypes.data_as(ctypes.c_void_p)
@@ -130,8 +136,8 @@ class Graph:
         self.n = int(len(rp) - 1) if n is None else int(n)
         self.nnz = int(nnz)
         h = ctypes.c_void_p()
-        st = ctx.lib.raft_graph_create(ctx.h, rp_p, ci_p, self.n, self.nnz, on_dev, _stream(),
-                                       ctypes.byref(h))
+        st = ctx.lib.raft_graph_create(ctx.h, rp_p, int(wide), ci_p, self.n, self.nnz, on_dev,
+                                       _stream(), ctypes.byref(h))
         del keep
         ctx.check(st)
         self.h = h
@@ -167,13 +173,21 @@ def gaussian(ctx, seed, stream_id, rows, cols, sigma):
     return out
 
 
+def spmm_workspace_size(ctx, g, op, L):
+    n = ctypes.c_size_t()
+    ctx.check(ctx.lib.raft_spmm_workspace_size(ctx.h, g.h, op, L, ctypes.byref(n)))
+    return n.value
+
+
 def spmm(ctx, g, op, Y, out=None, ws=None):
     Y = Y.contiguous()
     L = Y.shape[1]
     out = ctx.empty((g.n, L), torch.float32) if out is None else out
-    if ws is None:
-        ws = ctx.workspace(64 * 1024 * 1024 if g.n * L * 8 < 2**26 else g.n * L * 8)
-    ctx.check(ctx.lib.raft_spmm(ctx.h, g.h, op, L, _ptr(Y), _ptr(out), _ptr(ws), ws.numel(),
+    need = spmm_workspace_size(ctx, g, op, L)
+    if need and (ws is None or ws.numel() < need):
+        ws = ctx.workspace(need)
+    ctx.check(ctx.lib.raft_spmm(ctx.h, g.h, op, L, Y.data_ptr(), out.data_ptr(),
+                                ws.data_ptr() if need else None, ws.numel() if need else 0,
                                 _stream()))
     return out
 
@@ -265,13 +279,36 @@ def score(ctx, g, labels_all, ks):
     mod = ctx.empty((kc,), torch.float64)
     nc = ctx.empty((kc,), torch.float64)
     ks_arr = (ctypes.c_int32 * kc)(*ks)
-    stride = (kc + 7) // 8 * 8
-    sk = sum(ks)
-    # upper bound of the library's layout (score grid <= 1024 work-groups)
-    ws = ctx.workspace(8 * kc + g.n * stride + 2 * 1024 * sk * 4 + 16 * sk + 8 * 256)
+    need = ctypes.c_size_t()
+    ctx.check(ctx.lib.raft_score_workspace_size(ctx.h, g.h, kc, ks_arr, ctypes.byref(need)))
+    ws = ctx.workspace(need.value)
     ctx.check(ctx.lib.raft_score(ctx.h, g.h, _ptr(labels_all), kc, ks_arr, _ptr(mod), _ptr(nc),
                                  _ptr(ws), ws.numel(), _stream()))
     return mod, nc
+
+
+def confusion(ctx, a, b, ka=None, kb=None):
+    """Contingency counts [ka x kb] (int64, device) of two device labelings."""
+    a = a.to(torch.int32).contiguous()
+    b = b.to(torch.int32).contiguous()
+    ka = int(a.max().item()) + 1 if ka is None else int(ka)
+    kb = int(b.max().item()) + 1 if kb is None else int(kb)
+    out = ctx.empty((ka, kb), torch.int64)
+    ctx.check(ctx.lib.raft_confusion(ctx.h, _ptr(a), _ptr(b), a.numel(), ka, kb, _ptr(out),
+                                     _stream()))
+    return out
+
+
+def nmi(ctx, a, b):
+    """NMI of two device labelings: counts on the device, finish on the host."""
+    counts = confusion(ctx, a, b)
+    host = np.ascontiguousarray(counts.cpu().numpy(), dtype=np.int64)
+    ctx.sync_status()
+    val = ctypes.c_double()
+    st = ctx.lib.raft_nmi_from_counts(host.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                      host.shape[0], host.shape[1], ctypes.byref(val))
+    ctx.check(st)
+    return val.value
 
 
 def stage_times(ctx):

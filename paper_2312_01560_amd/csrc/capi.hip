@@ -17,6 +17,7 @@ using namespace raft;
 
 struct raft_ctx {
     int device = 0;
+    std::string autotune_cache;    // path of the tuner's cache file ("" = none)
     int num_cu = 256;
     size_t lds_max = 65536;
     std::string err;
@@ -668,7 +669,7 @@ const char* raft_status_string(raft_status s) {
     }
 }
 
-raft_status raft_ctx_create(int device, raft_ctx** out) {
+raft_status raft_ctx_create(int device, const char* autotune_cache, raft_ctx** out) {
     if (!out) return RAFT_E_INVAL;
     *out = nullptr;
     int count = 0;
@@ -677,6 +678,7 @@ raft_status raft_ctx_create(int device, raft_ctx** out) {
     if (hipSetDevice(device) != hipSuccess) return RAFT_E_DEVICE;
     raft_ctx* c = new raft_ctx();
     c->device = device;
+    if (autotune_cache) c->autotune_cache = autotune_cache;
     int cu = 0;
     if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
         cu > 0)
@@ -745,25 +747,44 @@ raft_status raft_sync_status(raft_ctx* ctx, void* stream) {
     return RAFT_OK;
 }
 
-raft_status raft_graph_create(raft_ctx* ctx, const int32_t* row_ptr, const int32_t* col_idx,
-                              int64_t n, int64_t nnz, int inputs_on_device, void* stream,
-                              raft_graph** out) {
+raft_status raft_graph_create(raft_ctx* ctx, const void* row_ptr, int row_ptr_is_int64,
+                              const int32_t* col_idx, int64_t n, int64_t nnz,
+                              int inputs_on_device, void* stream, raft_graph** out) {
     if (!ctx) return RAFT_E_INVAL;
     if (!out) return fail(ctx, RAFT_E_INVAL, "out is null");
     *out = nullptr;
     if (!row_ptr || (nnz > 0 && !col_idx)) return fail(ctx, RAFT_E_INVAL, "null CSR array");
     if (n < 1 || n >= INT32_MAX) return fail(ctx, RAFT_E_INVAL, "n = %lld", (long long)n);
-    if (nnz < 0 || nnz >= INT32_MAX) return fail(ctx, RAFT_E_INVAL, "nnz = %lld", (long long)nnz);
+    if (nnz < 0) return fail(ctx, RAFT_E_INVAL, "nnz = %lld", (long long)nnz);
+    if (nnz >= INT32_MAX)
+        return fail(ctx, RAFT_E_UNSUPPORTED, "nnz = %lld does not fit the int32 CSR",
+                    (long long)nnz);
     hipStream_t st = as_stream(stream);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    // row_ptr is checked on the host before any kernel indexes col_idx with it
+    // row_ptr is checked on the host before any kernel indexes col_idx with
+    // it; an int64 row_ptr is narrowed to int32 after the checks
     std::vector<int32_t> h_rp((size_t)n + 1);
-    if (inputs_on_device) {
-        HIP_TRY(ctx, hipMemcpyAsync(h_rp.data(), row_ptr, h_rp.size() * sizeof(int32_t),
-                                    hipMemcpyDeviceToHost, st));
-        HIP_TRY(ctx, hipStreamSynchronize(st));
-    } else {
-        memcpy(h_rp.data(), row_ptr, h_rp.size() * sizeof(int32_t));
+    {
+        const size_t elem = row_ptr_is_int64 ? sizeof(int64_t) : sizeof(int32_t);
+        std::vector<char> raw(((size_t)n + 1) * elem);
+        if (inputs_on_device) {
+            HIP_TRY(ctx, hipMemcpyAsync(raw.data(), row_ptr, raw.size(), hipMemcpyDeviceToHost, st));
+            HIP_TRY(ctx, hipStreamSynchronize(st));
+        } else {
+            memcpy(raw.data(), row_ptr, raw.size());
+        }
+        if (row_ptr_is_int64) {
+            const int64_t* r64 = reinterpret_cast<const int64_t*>(raw.data());
+            if (r64[0] != 0 || r64[n] != nnz)
+                return fail(ctx, RAFT_E_CSR, "row_ptr must start at 0 and end at nnz");
+            for (int64_t i = 0; i < n; ++i)
+                if (r64[i + 1] < r64[i])
+                    return fail(ctx, RAFT_E_CSR, "row_ptr decreases at %lld", (long long)i);
+            // non-decreasing from 0 to nnz < INT32_MAX: every entry fits int32
+            for (int64_t i = 0; i <= n; ++i) h_rp[i] = (int32_t)r64[i];
+        } else {
+            memcpy(h_rp.data(), raw.data(), raw.size());
+        }
     }
     if (h_rp[0] != 0 || h_rp[n] != nnz)
         return fail(ctx, RAFT_E_CSR, "row_ptr must start at 0 and end at nnz");
@@ -882,6 +903,21 @@ raft_status raft_gaussian(raft_ctx* ctx, uint64_t seed, uint64_t stream_id, int6
     return launch_check(ctx);
 }
 
+// Layout of raft_score's workspace: candidate table, stride-S labels,
+// per-work-group partial counts, int64 totals.
+static size_t score_ws_bytes(raft_ctx* ctx, const raft_graph* g, int Kc, int SK) {
+    const int S = (Kc + 7) / 8 * 8;
+    const int grid = score_grid(g->n, ctx->num_cu);
+    Arena a;
+    a.take<int32_t>(2 * (size_t)Kc);
+    a.take<uint8_t>((size_t)g->n * S);
+    a.take<int32_t>((size_t)grid * SK);
+    a.take<int32_t>((size_t)grid * SK);
+    a.take<int64_t>(SK);
+    a.take<int64_t>(SK);
+    return a.off;
+}
+
 static size_t spmm_ws_bytes(raft_ctx* ctx, const raft_graph* g, int L) {
     const int grid = spmm_grid(g->n, L, ctx->num_cu, nullptr);
     return align256(((size_t)grid + kColsumStageRows) * L * sizeof(double)) + align256(L * sizeof(double)) +
@@ -984,15 +1020,8 @@ raft_status raft_score(raft_ctx* ctx, const raft_graph* g, const uint8_t* labels
     if (!score_supported(SK)) return fail(ctx, RAFT_E_UNSUPPORTED, "sum of K %d", SK);
     const int S = (Kc + 7) / 8 * 8;
     const int grid = score_grid(g->n, ctx->num_cu);
+    RAFT_TRY(check_ws(ctx, ws, ws_bytes, score_ws_bytes(ctx, g, Kc, SK)));
     Arena a;
-    a.base = nullptr;
-    a.take<int32_t>(2 * (size_t)Kc);
-    a.take<uint8_t>((size_t)g->n * S);
-    a.take<int32_t>((size_t)grid * SK);
-    a.take<int32_t>((size_t)grid * SK);
-    a.take<int64_t>(SK);
-    a.take<int64_t>(SK);
-    RAFT_TRY(check_ws(ctx, ws, ws_bytes, a.off));
     a.base = reinterpret_cast<char*>(ws);
     a.off = 0;
     hipStream_t st = as_stream(stream);
@@ -1031,6 +1060,85 @@ raft_status raft_score(raft_ctx* ctx, const raft_graph* g, const uint8_t* labels
     launch_edge_score(g->view(), sc, pm, st);
     launch_score_finish(sc, st);
     return launch_check(ctx);
+}
+
+raft_status raft_spmm_workspace_size(raft_ctx* ctx, const raft_graph* g, int32_t op, int32_t L,
+                                    size_t* bytes) {
+    RAFT_TRY(check_graph(ctx, g));
+    if (!bytes) return fail(ctx, RAFT_E_INVAL, "bytes is null");
+    if (op < RAFT_X_NCUT || op > RAFT_X_GCN) return fail(ctx, RAFT_E_INVAL, "op %d", op);
+    if (!spmm_supported(L)) return fail(ctx, RAFT_E_UNSUPPORTED, "width %d", L);
+    *bytes = op == RAFT_X_MOD_FULL ? spmm_ws_bytes(ctx, g, L) : 0;
+    return RAFT_OK;
+}
+
+raft_status raft_score_workspace_size(raft_ctx* ctx, const raft_graph* g, int32_t Kc,
+                                     const int32_t* ks, size_t* bytes) {
+    RAFT_TRY(check_graph(ctx, g));
+    if (!bytes || !ks || Kc < 1) return fail(ctx, RAFT_E_INVAL, "bad score arguments");
+    int SK = 0;
+    for (int k = 0; k < Kc; ++k) {
+        if (ks[k] < 1 || ks[k] > RAFT_MAX_K) return fail(ctx, RAFT_E_INVAL, "ks[%d] = %d", k, ks[k]);
+        SK += ks[k];
+    }
+    if (!score_supported(SK)) return fail(ctx, RAFT_E_UNSUPPORTED, "sum of K %d", SK);
+    *bytes = score_ws_bytes(ctx, g, Kc, SK);
+    return RAFT_OK;
+}
+
+raft_status raft_confusion(raft_ctx* ctx, const int32_t* a, const int32_t* b, int64_t n,
+                           int32_t ka, int32_t kb, int64_t* counts, void* stream) {
+    if (!ctx) return RAFT_E_INVAL;
+    if (n < 0 || ka < 1 || kb < 1 || !counts || (n > 0 && (!a || !b)))
+        return fail(ctx, RAFT_E_INVAL, "bad confusion arguments");
+    if ((int64_t)ka * kb > ((int64_t)1 << 31))
+        return fail(ctx, RAFT_E_UNSUPPORTED, "table %d x %d too large", ka, kb);
+    launch_confusion(a, b, n, ka, kb, counts, ctx->d_status, ctx->num_cu, as_stream(stream));
+    return launch_check(ctx);
+}
+
+raft_status raft_nmi_from_counts(const int64_t* counts, int32_t ka, int32_t kb, double* nmi) {
+    if (!counts || !nmi || ka < 1 || kb < 1) return RAFT_E_INVAL;
+    // marginals, then I(a;b) and the two entropies in natural log, each
+    // summed in row-major order
+    std::vector<int64_t> ra(ka, 0), cb(kb, 0);
+    int64_t total = 0;
+    for (int r = 0; r < ka; ++r)
+        for (int c = 0; c < kb; ++c) {
+            const int64_t v = counts[(size_t)r * kb + c];
+            if (v < 0) return RAFT_E_INVAL;
+            ra[r] += v;
+            cb[c] += v;
+            total += v;
+        }
+    if (total == 0) return RAFT_E_INVAL;
+    const double nt = (double)total;
+    double ha = 0.0, hb = 0.0, mi = 0.0;
+    for (int r = 0; r < ka; ++r)
+        if (ra[r] > 0) {
+            const double p = (double)ra[r] / nt;
+            ha -= p * std::log(p);
+        }
+    for (int c = 0; c < kb; ++c)
+        if (cb[c] > 0) {
+            const double p = (double)cb[c] / nt;
+            hb -= p * std::log(p);
+        }
+    if (ha + hb == 0.0) {
+        *nmi = 1.0;
+        return RAFT_OK;
+    }
+    for (int r = 0; r < ka; ++r)
+        for (int c = 0; c < kb; ++c) {
+            const int64_t v = counts[(size_t)r * kb + c];
+            if (v > 0) {
+                const double pj = (double)v / nt;
+                const double pp = ((double)ra[r] / nt) * ((double)cb[c] / nt);
+                mi += pj * std::log(pj / pp);
+            }
+        }
+    *nmi = 2.0 * mi / (ha + hb);
+    return RAFT_OK;
 }
 
 raft_status raft_run(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg, void* ws,

@@ -175,6 +175,12 @@ void launch_select(const ScorePlan& p, const uint8_t* lab_pm, int32_t* labels_ou
 // Copy point-major labels [n x S] into a dense [n x Kc] output.
 void launch_copy_labels(const uint8_t* pm, int32_t n, int Kc, int S, uint8_t* out, hipStream_t st);
 
+// ---- confusion.hip -------------------------------------------------------
+// counts [ka x kb] int64 (zeroed here) = joint histogram of labels a, b [n];
+// a label out of range sets kStatusLabel and is not counted.
+void launch_confusion(const int32_t* a, const int32_t* b, int64_t n, int ka, int kb,
+                      int64_t* counts, int32_t* status, int num_cu, hipStream_t st);
+
 // ---- train.hip -----------------------------------------------------------
 void launch_softmax_rows(const float* U, float* S, int n, int K, hipStream_t st);
 int rowdot_parts(int64_t total);

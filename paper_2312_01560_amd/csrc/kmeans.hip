@@ -169,8 +169,10 @@ __global__ __launch_bounds__(kRaceThreads) void k_race(KmeansPlan p, const float
             p.w[i] = wi;
         }
         if (wi > 0.f) {
+            // lexicographic on (ratio, index): odd picks sweep from the end,
+            // so an exact tie must still go to the lower index
             const double ratio = e / (double)wi;
-            if (ratio < best) {
+            if (lex_less(ratio, i, best, bidx)) {
                 best = ratio;
                 bidx = i;
             }

@@ -188,3 +188,41 @@ def planted_small(n, k, p_in, p_out, seed):
     keep = rng.random(iu.size) < p
     rp, ci = edges_to_csr(n, iu[keep], ju[keep])
     return Graph(n, rp, ci, lab.astype(np.int32), {"kind": "planted_small"})
+
+
+def bfs_ball(g, size, root=0):
+    """Induced subgraph on the first `size` nodes reached by a breadth-first
+    search from `root` (neighbours visited in column order), relabelled in
+    visit order; degrees are those inside the subgraph.  If the component
+    of `root` is smaller, the search restarts from the lowest unvisited
+    node."""
+    size = min(int(size), g.n)
+    order = np.full(g.n, -1, dtype=np.int64)
+    seq = []
+    nxt = int(root)
+    while len(seq) < size:
+        while order[nxt] >= 0:
+            nxt += 1
+        order[nxt] = len(seq)
+        seq.append(nxt)
+        head = len(seq) - 1
+        while head < len(seq) and len(seq) < size:
+            u = seq[head]
+            head += 1
+            for v in g.col_idx[g.row_ptr[u]:g.row_ptr[u + 1]]:
+                if order[v] < 0 and len(seq) < size:
+                    order[v] = len(seq)
+                    seq.append(int(v))
+        nxt = 0
+    nodes = np.asarray(seq, dtype=np.int64)
+    src, dst = [], []
+    for new_u, u in enumerate(nodes):
+        nb = g.col_idx[g.row_ptr[u]:g.row_ptr[u + 1]]
+        nb_new = order[nb]
+        keep = (nb_new >= 0) & (nb_new > new_u)
+        src.append(np.full(int(keep.sum()), new_u))
+        dst.append(nb_new[keep])
+    rp, ci = edges_to_csr(size, np.concatenate(src), np.concatenate(dst))
+    planted = g.planted[nodes].astype(np.int32) if g.planted.size else g.planted
+    return Graph(size, rp, ci, planted, {"kind": "bfs_ball", "root": int(root),
+                                          "parent": dict(g.info)})

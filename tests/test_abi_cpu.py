@@ -45,7 +45,7 @@ def test_no_device_is_an_error_not_a_crash():
     from paper_2312_01560_amd import _lib
     lib = _lib.load()
     h = ctypes.c_void_p()
-    st = lib.raft_ctx_create(0, ctypes.byref(h))
+    st = lib.raft_ctx_create(0, None, ctypes.byref(h))
     assert st == _lib.E_DEVICE and not h.value
 
 
@@ -57,3 +57,38 @@ def test_product_path_never_imports_oracle():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(from|import)\s+oracle", txt, re.M), f
                 assert "oracle/" not in txt, f
+
+
+def test_nmi_from_counts_host_finish():
+    """raft_nmi_from_counts (host code of the library) against the oracle's
+    NMI, itself pinned to scikit-learn: random label pairs, identical and
+    permuted labelings (1.0), both constant (1.0)."""
+    import numpy as np
+    from oracle import scores
+    from paper_2312_01560_amd import _lib
+    lib = _lib.load()
+
+    def via_lib(a, b):
+        ka, kb = int(a.max()) + 1, int(b.max()) + 1
+        counts = np.zeros((ka, kb), dtype=np.int64)
+        np.add.at(counts, (a, b), 1)
+        out = ctypes.c_double()
+        st = lib.raft_nmi_from_counts(counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ka,
+                                      kb, ctypes.byref(out))
+        assert st == 0
+        return out.value
+
+    rng = np.random.default_rng(4)
+    for n, ka, kb in ((1000, 5, 7), (5000, 40, 3), (300, 1, 9)):
+        a = rng.integers(0, ka, n)
+        b = rng.integers(0, kb, n)
+        assert abs(via_lib(a, b) - scores.nmi(a, b)) < 1e-12
+    a = rng.integers(0, 9, 2000)
+    assert abs(via_lib(a, a) - 1.0) < 1e-12
+    assert abs(via_lib(a, (a * 5 + 3) % 9) - 1.0) < 1e-12
+    z = np.zeros(50, dtype=np.int64)
+    assert via_lib(z, z) == 1.0
+    bad = np.zeros((2, 2), dtype=np.int64)
+    out = ctypes.c_double()
+    assert lib.raft_nmi_from_counts(bad.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 2, 2,
+                                    ctypes.byref(out)) == _lib.E_INVAL

@@ -122,9 +122,10 @@ def cluster_means(z64, lab, k):
         return (ind @ z64) / cnt[:, None], cnt
 
 
-def test_n1m_end_to_end(ctx, api_mod, n1m, dev_graph, rows):
+@pytest.mark.parametrize("op", [0, 1])
+def test_n1m_end_to_end(ctx, api_mod, n1m, dev_graph, rows, op):
     g0, m = n1m
-    cfg = api_mod.Config(op=1, **m)
+    cfg = api_mod.Config(op=op, **m)
     out = api_mod.run(ctx, dev_graph, cfg, want_centres=True)
     torch.cuda.synchronize()
     ctx.sync_status()

@@ -68,6 +68,62 @@ def test_device_inputs_and_isolated_nodes(ctx, api_mod):
     np.testing.assert_allclose(to_np(out), ref, rtol=1e-6, atol=1e-7)
 
 
+@pytest.mark.parametrize("on_device", [False, True])
+def test_graph_int64_row_ptr(ctx, api_mod, ragged, on_device):
+    """int64 row offsets are checked and narrowed: the same graph as with
+    int32 offsets (degrees, one sparse step bit for bit); a decreasing int64
+    row_ptr is RAFT_E_CSR; nnz beyond the int32 CSR is RAFT_E_UNSUPPORTED."""
+    rp64 = ragged.row_ptr.astype(np.int64)
+    if on_device:
+        g = api_mod.Graph(ctx, torch.from_numpy(rp64).cuda(),
+                          torch.from_numpy(ragged.col_idx).cuda())
+    else:
+        g = api_mod.Graph(ctx, rp64, ragged.col_idx)
+    g32 = api_mod.Graph(ctx, ragged.row_ptr, ragged.col_idx)
+    assert np.array_equal(to_np(g.degrees()), to_np(g32.degrees()))
+    y = torch.randn(ragged.n, 64, device="cuda")
+    assert np.array_equal(to_np(api_mod.spmm(ctx, g, 0, y)), to_np(api_mod.spmm(ctx, g32, 0, y)))
+    bad = rp64.copy()
+    bad[5] = bad[4] - 1
+    with pytest.raises(api_mod.RaftError) as ei:
+        api_mod.Graph(ctx, bad, ragged.col_idx)
+    assert ei.value.status == -2
+    import ctypes
+    huge = np.array([0, 2 ** 31], dtype=np.int64)
+    h = ctypes.c_void_p()
+    st = ctx.lib.raft_graph_create(ctx.h, huge.ctypes.data, 1, ragged.col_idx.ctypes.data, 1,
+                                   2 ** 31, 0, None, ctypes.byref(h))
+    assert st == -8 and not h.value
+
+
+@pytest.mark.parametrize("ka,kb", [(17, 23), (1, 5), (200, 255)])
+def test_confusion_bit_exact(ctx, api_mod, ka, kb):
+    """Contingency counts on the device (LDS bins for small tables, int64
+    atomics per node for ka x kb > 16384) equal a NumPy histogram."""
+    rng = np.random.default_rng(ka * 1000 + kb)
+    n = 300007
+    a = rng.integers(0, ka, n).astype(np.int32)
+    b = rng.integers(0, kb, n).astype(np.int32)
+    got = to_np(api_mod.confusion(ctx, torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(),
+                                  ka, kb))
+    ref = np.zeros((ka, kb), dtype=np.int64)
+    np.add.at(ref, (a, b), 1)
+    assert got.dtype == np.int64 and np.array_equal(got, ref)
+    v = api_mod.nmi(ctx, torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda())
+    assert abs(v - scores.nmi(a, b)) < 1e-12
+
+
+def test_confusion_label_out_of_range(ctx, api_mod):
+    a = torch.tensor([0, 1, 2, 7], dtype=torch.int32, device="cuda")
+    b = torch.tensor([0, 0, 1, 1], dtype=torch.int32, device="cuda")
+    got = to_np(api_mod.confusion(ctx, a, b, 3, 2))
+    assert got.tolist() == [[1, 0], [1, 0], [0, 1]]
+    with pytest.raises(api_mod.RaftError) as ei:
+        ctx.sync_status()
+    assert ei.value.status == -1
+    ctx.sync_status()                      # the latched status was cleared
+
+
 @pytest.mark.parametrize("bad", ["range", "order", "loop", "asym", "rowptr"])
 def test_csr_rejected(ctx, api_mod, bad):
     g = two_cliques(4)
@@ -245,6 +301,44 @@ def test_kmeans_fixed_point(ctx, api_mod, ragged):
         assert np.all(mine <= d.min(axis=1) + 1e-5)
 
 
+@pytest.mark.parametrize("d", [16, 64, 128])
+def test_assignment_within_score_error_bound(ctx, api_mod, ragged, d):
+    """Element by element over every (point, candidate): the first
+    assignment (T_max = 1, centres = the picked points, exact FP32 copies)
+    picks a centre whose exact FP64 score ||c||^2 - 2 z.c is within the
+    kernel's rounding bound of the true minimum.  At d a multiple of 32 the
+    dot products come from split fp16 halves (hi + lo carries 22 bits of
+    each operand, the lo.lo term dropped, FP32 accumulation over d terms),
+    so each score is within delta = d 2^-21 ||z|| ||c|| + d 2^-23 ||c||^2 of
+    exact; at d = 16 (FP32 MFMA) the same bound holds with room to spare."""
+    rng = np.random.default_rng(17 + d)
+    z = rng.standard_normal((ragged.n, d)).astype(np.float32)
+    z /= np.linalg.norm(z, axis=1, keepdims=True)
+    z64 = z.astype(np.float64)
+    g = api_mod.Graph(ctx, ragged.row_ptr, ragged.col_idx)
+    cfg = api_mod.Config(op=0, proj_dim=d, layer_dims=[d], k_min=2, k_max=80, k_step=3,
+                         kmeans_max_iter=1)
+    out = api_mod.partition(ctx, g, cfg, torch.from_numpy(z).cuda())
+    torch.cuda.synchronize()
+    ctx.sync_status()
+    picks = to_np(out["picks"])
+    lab = to_np(out["labels_all"]).astype(np.int64)
+    zn = np.linalg.norm(z64, axis=1)
+    for j, k in enumerate(cfg.ks):
+        c = z64[picks[:k]]
+        cn2 = np.sum(c * c, axis=1)
+        sc = cn2[None, :] - 2.0 * (z64 @ c.T)
+        delta = d * 2.0 ** -21 * zn[:, None] * np.sqrt(cn2)[None, :] + d * 2.0 ** -23 * cn2[None, :]
+        mine = sc[np.arange(ragged.n), lab[:, j]]
+        best = sc.min(axis=1)
+        slack = delta[np.arange(ragged.n), lab[:, j]] + delta[np.arange(ragged.n), sc.argmin(1)]
+        assert np.all(mine <= best + slack), k
+        # and where the exact minimum is clear of the bound, it is the label
+        gap = np.sort(sc, axis=1)[:, 1] - best if k > 1 else np.full(ragged.n, np.inf)
+        clear = gap > 2 * delta.max(axis=1)
+        assert np.array_equal(lab[clear, j], sc.argmin(1)[clear]), k
+
+
 def check_centres(centres, z64, lab, ks, iters, t_max, cands):
     """Each non-empty centre of a converged candidate is the mean of its
     points.  The library keeps exact integer sums of z 2^e (e = 30 - the
@@ -348,6 +442,59 @@ def test_run_end_to_end_small(ctx, api_mod, small_graph, op):
     lab = to_np(out["labels_all"]).astype(np.int64)
     rmod, _ = scores.score_candidates(g0.row_ptr, g0.col_idx, lab, cfg.ks)
     assert np.array_equal(to_np(out["mod"]), rmod)
+
+
+def with_isolated(g0, where):
+    """g0 with isolated nodes inserted at positions `where` of the new id
+    range (the other nodes keep their order)."""
+    n = g0.n + len(where)
+    keep = np.setdiff1d(np.arange(n), np.asarray(where))
+    rows = np.repeat(np.arange(g0.n), np.diff(g0.row_ptr))
+    rp, ci = edges_to_csr(n, keep[rows], keep[g0.col_idx])
+    return rp, ci, n
+
+
+@pytest.mark.parametrize("op", [0, 1])
+def test_run_isolated_nodes_end_to_end(ctx, api_mod, small_graph, op):
+    """Isolated nodes through the whole path: under NCut their projection
+    rows are zero (D^-1/2 = 0), the GCN keeps them at zero (norm floor), and
+    the whole run matches the oracle: Y and Z per column, labels NMI."""
+    g0, m = small_graph
+    rp, ci, n = with_isolated(g0, [0, 137, 500, g0.n + 4])
+    g = api_mod.Graph(ctx, rp, ci)
+    cfg = api_mod.Config(op=op, **m)
+    out = api_mod.run(ctx, g, cfg)
+    torch.cuda.synchronize()
+    ctx.sync_status()
+    ref = pipeline.run(rp, ci, n, pipeline.Config(op=op, **m))
+    iso = np.flatnonzero(np.diff(rp) == 0)
+    assert iso.tolist() == [0, 137, 500, g0.n + 4]
+    y, z = to_np(out["Y"]), to_np(out["Z"])
+    if op == 0:
+        assert np.all(y[iso] == 0) and np.all(z[iso] == 0)
+        assert np.all(ref["Z"][iso] == 0)
+    assert col_err(y, ref["Y"]).max() < COL_TOL
+    assert col_err(z, ref["Z"]).max() < COL_TOL
+    assert scores.nmi(to_np(out["labels"]), ref["labels"]) >= 0.999
+
+
+@pytest.mark.parametrize("op", [0, 1])
+def test_run_normalize_input_end_to_end(ctx, api_mod, small_graph, op):
+    """Row normalisation of Y before the first layer (flag, default off):
+    Z per column and labels against the oracle with the same flag."""
+    g0, m = small_graph
+    g = api_mod.Graph(ctx, g0.row_ptr, g0.col_idx)
+    cfg = api_mod.Config(op=op, normalize_input=True, **m)
+    out = api_mod.run(ctx, g, cfg)
+    torch.cuda.synchronize()
+    ctx.sync_status()
+    ref = pipeline.run(g0.row_ptr, g0.col_idx, g0.n,
+                       pipeline.Config(op=op, normalize_input=True, **m))
+    plain = pipeline.run(g0.row_ptr, g0.col_idx, g0.n, pipeline.Config(op=op, **m))
+    assert np.abs(ref["Z"] - plain["Z"]).max() > 1e-3        # the flag matters
+    assert col_err(to_np(out["Y"]), ref["Y"]).max() < COL_TOL
+    assert col_err(to_np(out["Z"]), ref["Z"]).max() < COL_TOL
+    assert scores.nmi(to_np(out["labels"]), ref["labels"]) >= 0.999
 
 
 def test_run_two_cliques(ctx, api_mod):
@@ -458,7 +605,7 @@ def n50k():
     return make_workload("n50k")
 
 
-@pytest.mark.parametrize("op", [0, 1])
+@pytest.mark.parametrize("op", [0, 1, 2])
 def test_n50k_full_size(ctx, api_mod, n50k, op):
     """The benchmark's workload and launch configuration (N = 50,000, L = d =
     64, q = 3, K 2..80): Y and Z against the FP64 oracle column by column,
@@ -502,3 +649,31 @@ def test_n50k_full_size(ctx, api_mod, n50k, op):
     ks = to_np(out["k_selected"])
     assert ks[0] == cfg.ks[best] and ks[1] == keff
     assert np.array_equal(to_np(out["labels"]), can)
+
+
+@pytest.mark.parametrize("op", [0, 1])
+def test_n50k_labels_nmi_vs_oracle(ctx, api_mod, n50k, op):
+    """Labels at NMI >= 0.999 against the oracle under the same seed, at
+    the benchmark's size.  The oracle's whole grid in FP64 takes minutes, so
+    the oracle runs its own seeding and Lloyd on the GPU's FP32 embedding
+    for a sample of candidates that includes the selected K* (the GPU and the
+    oracle then start from the same picks, bit for bit)."""
+    g0, m = n50k
+    g = api_mod.Graph(ctx, g0.row_ptr, g0.col_idx)
+    cfg = api_mod.Config(op=op, **m)
+    out = api_mod.run(ctx, g, cfg)
+    torch.cuda.synchronize()
+    ctx.sync_status()
+    z64 = to_np(out["Z"]).astype(np.float64)
+    ks = cfg.ks
+    best = int(to_np(out["k_selected"])[2])
+    sample = sorted(set(range(0, len(ks), 13)) | {best})
+    picks = okm.seed_picks(z64, max(ks[j] for j in sample), 0)
+    assert np.array_equal(to_np(out["picks"])[:picks.size], picks)
+    lab = to_np(out["labels_all"]).astype(np.int64)
+    for j in sample:
+        ref, _, _ = okm.lloyd(z64, z64[picks[:ks[j]]], cfg.kmeans_max_iter)
+        assert scores.nmi(lab[:, j], ref) >= 0.999, ks[j]
+    ref_best, _, _ = okm.lloyd(z64, z64[picks[:ks[best]]], cfg.kmeans_max_iter)
+    can, _ = scores.canonical(ref_best)
+    assert scores.nmi(to_np(out["labels"]), can) >= 0.999

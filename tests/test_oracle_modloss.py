@@ -100,3 +100,45 @@ def test_adam_closed_form_first_step():
     w1, m, v = modloss.adam_step(w, np.zeros(2), np.zeros(2), g, 1, lr=0.1)
     # first step: m_hat = g, v_hat = g^2 -> w - lr * sign(g) (up to eps)
     np.testing.assert_allclose(w1, w - 0.1 * np.sign(g), rtol=1e-6)
+
+
+@pytest.fixture(scope="module")
+def ball():
+    """The N = 1,000 breadth-first ball of the training workload's graph
+    (N = 200,000 DC-SBM), degrees recomputed inside the ball."""
+    from synth import bfs_ball, make_workload
+    g200k, _ = make_workload("n200k")
+    return bfs_ball(g200k, 1000, root=0)
+
+
+def test_gradient_fd_on_training_subgraph(ball):
+    """Central finite differences (FP64, h = 1e-6) of the loss against the
+    hand-written adjoint on the training workload's model (three layers of
+    width 64, 64 softmax memberships), sampled entries of every W and of Y:
+    relative error <= 1e-6."""
+    g = ball
+    y = projection.project(g.row_ptr, g.col_idx, g.n, projection.MOD_FULL, 64, 3, 0)
+    ws = _weights(0, [64, 64, 64], 64)
+    loss, grads, g_y, _ = modloss.loss_and_grads(g.row_ptr, g.col_idx, g.n, y, ws)
+    h = 1e-6
+    rng = np.random.default_rng(12)
+
+    def lossw(w_list, yy):
+        return modloss.loss_and_grads(g.row_ptr, g.col_idx, g.n, yy, w_list)[0]
+
+    for k in range(3):
+        for _ in range(5):
+            a, b = rng.integers(0, 64), rng.integers(0, 64)
+            wp = [w.copy() for w in ws]
+            wm = [w.copy() for w in ws]
+            wp[k][a, b] += h
+            wm[k][a, b] -= h
+            fd = (lossw(wp, y) - lossw(wm, y)) / (2 * h)
+            assert abs(fd - grads[k][a, b]) <= 1e-6 * max(abs(fd), 1e-3), (k, a, b, fd)
+    for _ in range(5):
+        i, j = rng.integers(0, g.n), rng.integers(0, 64)
+        yp, ym = y.copy(), y.copy()
+        yp[i, j] += h
+        ym[i, j] -= h
+        fd = (lossw(ws, yp) - lossw(ws, ym)) / (2 * h)
+        assert abs(fd - g_y[i, j]) <= 1e-6 * max(abs(fd), 1e-3), (i, j, fd)

@@ -130,3 +130,55 @@ def test_two_cliques_embedding_separates():
     d = ((z[:, None, :] - z[None, :, :]) ** 2).sum(-1)
     same = g.planted[:, None] == g.planted[None, :]
     assert d[same].max() < d[~same].min()
+
+
+def test_row_normalize_zero_row_floor():
+    """Sec. III-B normalises rows; a zero row (an isolated node under NCut,
+    whose row of M is zero) is divided by the floor 1e-12 and stays zero,
+    and a row below the floor is divided by the floor, not by its norm."""
+    z = np.array([[0.0, 0.0, 0.0], [3.0, 4.0, 0.0], [1e-13, 0.0, 0.0]])
+    got = gcn.row_normalize(z)
+    assert np.array_equal(got[0], np.zeros(3))
+    assert np.array_equal(got[1], np.array([0.6, 0.8, 0.0]))
+    np.testing.assert_allclose(got[2], [0.1, 0.0, 0.0], rtol=1e-15, atol=0)
+
+
+def _graph_with_isolated():
+    from synth.dcsbm import edges_to_csr
+    # a path 0-1-2-3, a triangle 4-5-6, node 7 isolated, a star 8-{9,10,11}
+    return edges_to_csr(12, [0, 1, 2, 4, 5, 4, 8, 8, 8], [1, 2, 3, 5, 6, 6, 9, 10, 11])
+
+
+@pytest.mark.parametrize("normalize_input", [False, True])
+def test_gcn_dense_eq6_isolated_node_and_input_normalisation(normalize_input):
+    """Dense Eq. 6 on a graph with an isolated node, with and without the
+    row normalisation of Y before the first layer: the isolated node's Y row
+    is zero under NCut (D^-1/2 = 0), its row of A_hat_n is e_i, so its
+    embedding row stays zero through every layer."""
+    rp, ci = _graph_with_isolated()
+    n = 12
+    a = np.zeros((n, n))
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    a[rows, ci] = 1.0
+    y = projection.project(rp, ci, n, projection.NCUT, 16, 2, 4)
+    assert np.all(y[7] == 0) and np.all(y[np.arange(n) != 7].any(axis=1))
+    ah = a + np.eye(n)
+    dh = ah.sum(1) ** -0.5
+    an = dh[:, None] * ah * dh[None, :]
+    h = y.copy()
+    if normalize_input:
+        nrm = np.sqrt((h * h).sum(1))
+        h = h / np.where(nrm > 1e-12, nrm, 1e-12)[:, None]
+        assert np.all(h[7] == 0)
+    l_in = 16
+    for k, l_out in enumerate([12, 8], 1):
+        w = gcn.weight(4, k, l_in, l_out)
+        z = np.tanh(an @ h @ w)
+        nrm = np.sqrt((z * z).sum(1))
+        h = z / np.where(nrm > 1e-12, nrm, 1e-12)[:, None]
+        l_in = l_out
+    got = gcn.embed(rp, ci, n, y, [12, 8], 4, normalize_input=normalize_input)
+    np.testing.assert_allclose(got, h, rtol=1e-12, atol=1e-14)
+    assert np.all(got[7] == 0)
+    other = gcn.embed(rp, ci, n, y, [12, 8], 4, normalize_input=not normalize_input)
+    assert np.abs(got - other).max() > 1e-3          # the flag changes the embedding
