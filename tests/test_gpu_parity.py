@@ -460,7 +460,7 @@ def test_run_isolated_nodes_end_to_end(ctx, api_mod, small_graph, op):
     rows are zero (D^-1/2 = 0), the GCN keeps them at zero (norm floor), and
     the whole run matches the oracle: Y and Z per column, labels NMI."""
     g0, m = small_graph
-    rp, ci, n = with_isolated(g0, [0, 137, 500, g0.n + 4])
+    rp, ci, n = with_isolated(g0, [0, 137, 500, g0.n + 3])
     g = api_mod.Graph(ctx, rp, ci)
     cfg = api_mod.Config(op=op, **m)
     out = api_mod.run(ctx, g, cfg)
@@ -468,7 +468,7 @@ def test_run_isolated_nodes_end_to_end(ctx, api_mod, small_graph, op):
     ctx.sync_status()
     ref = pipeline.run(rp, ci, n, pipeline.Config(op=op, **m))
     iso = np.flatnonzero(np.diff(rp) == 0)
-    assert iso.tolist() == [0, 137, 500, g0.n + 4]
+    assert iso.tolist() == [0, 137, 500, g0.n + 3]
     y, z = to_np(out["Y"]), to_np(out["Z"])
     if op == 0:
         assert np.all(y[iso] == 0) and np.all(z[iso] == 0)
