@@ -14,6 +14,7 @@ Modules (each function cites the passage of the paper it follows):
 * ``gcn``        -- random GCN propagation (Sec. III-B, Eq. 6).
 * ``kmeans``     -- nested k-means++ seeding (exponential race) and Lloyd.
 * ``scores``     -- modularity (Eq. 3), NCut (Eq. 1), model selection, NMI.
+* ``hierarchical`` -- local modularity (Eq. 7) and hierarchical model selection (Alg. 1).
 * ``modloss``    -- relaxed modularity loss tr(S^T B S) and its adjoint.
 * ``pipeline``   -- the whole path end to end.
 
