@@ -160,6 +160,19 @@ raft_status raft_spmm_workspace_size(raft_ctx* ctx, const raft_graph* g, int32_t
 raft_status raft_spmm(raft_ctx* ctx, const raft_graph* g, int32_t op, int32_t L,
                       const float* Y_in, float* Y_out, void* ws, size_t ws_bytes, void* stream);
 
+/* raft_spmm for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results, bit for bit, with MOD_FULL's column-sum partials
+ * kept in a fixed scratch array of 16 MiB that the library holds on each GPU
+ * it runs on until the process ends.  Nothing is allocated or freed.  The
+ * caller passes inputs and outputs as for raft_spmm.  MOD_FULL needs
+ * raft_spmm_workspace_size(...) <= 16 MiB (about 2 million rows at L = 256,
+ * 8 million at L = 64), else RAFT_E_WORKSPACE with a message.  Every call on
+ * one GPU shares that GPU's scratch: calls that overlap in time on one GPU
+ * (two streams, two host threads) race and must be serialised by the caller. */
+raft_status raft_spmm_noalloc(raft_ctx* ctx, const raft_graph* g, int32_t op, int32_t L,
+                              const float* Y_in, float* Y_out, void* stream);
+
 /* Y = X^q Theta (Sec. III-A, Eq. 5 with q powers), Theta drawn as in
  * raft_gaussian with cfg->seed.  Y_out [N x L]. */
 raft_status raft_project(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg,

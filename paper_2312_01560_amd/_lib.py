@@ -25,6 +25,7 @@ EXPORTS = [
     "raft_train_workspace_size", "raft_gcn_forward", "raft_gcn_backward", "raft_modloss_forward",
     "raft_modloss_backward", "raft_adam_step", "raft_spmm_workspace_size",
     "raft_score_workspace_size", "raft_confusion", "raft_nmi_from_counts",
+    "raft_spmm_noalloc",
 ]
 
 PROF_SPMM, PROF_DENSE, PROF_RACE, PROF_ASSIGN, PROF_UPDATE, PROF_SCORE = range(6)
@@ -84,6 +85,7 @@ _SIGNATURES = {
     "raft_workspace_size": (_I32, [_P, _P, ctypes.POINTER(RaftConfig), ctypes.POINTER(_SZ)]),
     "raft_gaussian": (_I32, [_P, _U64, _U64, _I64, _I64, ctypes.c_double, _P, _P]),
     "raft_spmm": (_I32, [_P, _P, _I32, _I32, _P, _P, _P, _SZ, _P]),
+    "raft_spmm_noalloc": (_I32, [_P, _P, _I32, _I32, _P, _P, _P]),
     "raft_project": (_I32, [_P, _P, ctypes.POINTER(RaftConfig), _P, _SZ, _P, _P]),
     "raft_gcn_layer": (_I32, [_P, _P, _I32, _I32, _P, _P, _I32, _P, _P, _P, _SZ, _P]),
     "raft_embed": (_I32, [_P, _P, ctypes.POINTER(RaftConfig), _P, _P, _SZ, _P, _P]),

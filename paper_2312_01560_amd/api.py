@@ -192,6 +192,14 @@ def spmm(ctx, g, op, Y, out=None, ws=None):
     return out
 
 
+def spmm_noalloc(ctx, g, op, Y, out):
+    """raft_spmm_noalloc: the caller passes the output; the library allocates
+    nothing (MOD_FULL's partials live in its fixed per-GPU scratch)."""
+    ctx.check(ctx.lib.raft_spmm_noalloc(ctx.h, g.h, op, Y.shape[1], Y.data_ptr(),
+                                        out.data_ptr(), _stream()))
+    return out
+
+
 def _ws_for(ctx, g, cfg, ws):
     need = workspace_size(ctx, g, cfg)
     if ws is None or ws.numel() < need:

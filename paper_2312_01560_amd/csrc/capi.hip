@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,6 +18,7 @@ using namespace raft;
 
 struct raft_ctx {
     int device = 0;
+    void* scratch = nullptr;       // this device's copy of the fixed scratch array
     std::string autotune_cache;    // path of the tuner's cache file ("" = none)
     int num_cu = 256;
     size_t lds_max = 65536;
@@ -60,6 +62,17 @@ struct raft_graph {
         return v;
     }
 };
+
+// Fixed scratch for the allocation-free entry point (raft_spmm_noalloc):
+// one copy of this array per GPU, held until the process ends.  Host code
+// never passes the array's name to a kernel: the device address of each
+// GPU's copy is looked up once per device (hipGetSymbolAddress, with that
+// device current) when the first context on it is created.
+constexpr size_t kNoAllocScratchBytes = (size_t)16 << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) char scratch[kNoAllocScratchBytes];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
 
 namespace {
 
@@ -676,8 +689,21 @@ raft_status raft_ctx_create(int device, const char* autotune_cache, raft_ctx** o
     if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
         return RAFT_E_DEVICE;
     if (hipSetDevice(device) != hipSuccess) return RAFT_E_DEVICE;
+    if (device >= kMaxDevices) return RAFT_E_UNSUPPORTED;
+    void* scratch_ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[device]) {
+            void* p = nullptr;
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+                return RAFT_E_DEVICE;
+            g_scratch_ptr[device] = p;
+        }
+        scratch_ptr = g_scratch_ptr[device];
+    }
     raft_ctx* c = new raft_ctx();
     c->device = device;
+    c->scratch = scratch_ptr;
     if (autotune_cache) c->autotune_cache = autotune_cache;
     int cu = 0;
     if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
@@ -924,18 +950,23 @@ static size_t spmm_ws_bytes(raft_ctx* ctx, const raft_graph* g, int L) {
            align256(L * sizeof(float));
 }
 
-raft_status raft_spmm(raft_ctx* ctx, const raft_graph* g, int32_t op, int32_t L,
-                      const float* Y_in, float* Y_out, void* ws, size_t ws_bytes, void* stream) {
+static raft_status spmm_checks(raft_ctx* ctx, const raft_graph* g, int32_t op, int32_t L,
+                               const float* Y_in, const float* Y_out) {
     RAFT_TRY(check_graph(ctx, g));
     if (op < RAFT_X_NCUT || op > RAFT_X_GCN) return fail(ctx, RAFT_E_INVAL, "op %d", op);
     if (!spmm_supported(L)) return fail(ctx, RAFT_E_UNSUPPORTED, "width %d", L);
     if (!Y_in || !Y_out || Y_in == Y_out) return fail(ctx, RAFT_E_INVAL, "bad Y buffers");
     if ((op == RAFT_X_MOD_FULL || op == RAFT_X_MOD_REDUCED) && g->nnz == 0)
         return fail(ctx, RAFT_E_NOEDGES, "modularity needs e > 0");
-    hipStream_t st = as_stream(stream);
+    return RAFT_OK;
+}
+
+// One sparse step; `ws` holds MOD_FULL's column-sum partials (already checked
+// to be large enough), unused for the other operators.
+static raft_status spmm_body(raft_ctx* ctx, const raft_graph* g, int32_t op, int32_t L,
+                             const float* Y_in, float* Y_out, void* ws, hipStream_t st) {
     const GraphView gv = g->view();
     if (op == RAFT_X_MOD_FULL) {
-        RAFT_TRY(check_ws(ctx, ws, ws_bytes, spmm_ws_bytes(ctx, g, L)));
         Arena a;
         a.base = reinterpret_cast<char*>(ws);
         const int grid = spmm_grid(g->n, L, ctx->num_cu, nullptr);
@@ -949,6 +980,30 @@ raft_status raft_spmm(raft_ctx* ctx, const raft_graph* g, int32_t op, int32_t L,
         launch_spmm(gv, op, L, Y_in, Y_out, nullptr, nullptr, ctx->num_cu, st);
     }
     return launch_check(ctx);
+}
+
+raft_status raft_spmm(raft_ctx* ctx, const raft_graph* g, int32_t op, int32_t L,
+                      const float* Y_in, float* Y_out, void* ws, size_t ws_bytes, void* stream) {
+    RAFT_TRY(spmm_checks(ctx, g, op, L, Y_in, Y_out));
+    if (op == RAFT_X_MOD_FULL) RAFT_TRY(check_ws(ctx, ws, ws_bytes, spmm_ws_bytes(ctx, g, L)));
+    return spmm_body(ctx, g, op, L, Y_in, Y_out, ws, as_stream(stream));
+}
+
+raft_status raft_spmm_noalloc(raft_ctx* ctx, const raft_graph* g, int32_t op, int32_t L,
+                              const float* Y_in, float* Y_out, void* stream) {
+    RAFT_TRY(spmm_checks(ctx, g, op, L, Y_in, Y_out));
+    if (op == RAFT_X_MOD_FULL) {
+        const size_t need = spmm_ws_bytes(ctx, g, L);
+        if (need > kNoAllocScratchBytes)
+            return fail(ctx, RAFT_E_WORKSPACE,
+                        "N = %d at width %d needs %zu bytes of scratch; the fixed scratch holds "
+                        "%zu (use raft_spmm with a workspace)",
+                        g->n, L, need, kNoAllocScratchBytes);
+        if (!ctx->scratch) return fail(ctx, RAFT_E_DEVICE, "scratch address not resolved");
+    }
+    // every partial and stage row is written before it is read, so stale
+    // contents from an earlier call need no clearing
+    return spmm_body(ctx, g, op, L, Y_in, Y_out, ctx->scratch, as_stream(stream));
 }
 
 raft_status raft_project(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg, void* ws,
