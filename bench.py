@@ -45,6 +45,10 @@ def parse():
     ap.add_argument("--train", action="store_true",
                     help="time the trainable-GCN mode on the n200k workload instead")
     ap.add_argument("--train-steps", type=int, default=200)
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched-vs-sequential leg")
+    ap.add_argument("--batch-graphs", type=int, default=64)
+    ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
     return ap.parse_args()
@@ -240,6 +244,71 @@ def bench_train(args, api, torch, np):
     ctx.close()
 
 
+def bench_batch(args, api, torch, np, ctx):
+    """The batched workload: 64 DC-SBM graphs (N log-uniform on [1e3, 5e4])
+    through the whole path (modularity variant, K 2..64) as one batch -- one
+    block-diagonal CSR, one launch per stage over all graphs and candidates,
+    the fixed prefix replayed from a HIP graph -- against the same graphs run
+    one at a time through the single-graph calls.  Both legs start from
+    ingested graphs, preallocated outputs and workspaces; per-graph labels of
+    the two legs are compared (NMI) and against the planted blocks."""
+    from synth.workloads import make_batch
+    graphs, method = make_batch(args.batch_graphs)
+    dev = ctx.torch_device
+    cfg = api.Config(op=1, **method)
+    gs = [api.Graph(ctx, torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col_idx).to(dev))
+          for g in graphs]
+    b = api.Batch(ctx, gs, cfg)
+    bouts = b.outputs()
+    log(f"batch: {len(graphs)} graphs, N={sum(g.n for g in graphs)}, "
+        f"nnz={sum(g.nnz for g in graphs)}; warm-up")
+    for _ in range(max(1, args.warmup // 2)):
+        b.run(outputs=bouts)
+    torch.cuda.synchronize()
+    reps = max(1, args.batch_reps)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.run(outputs=bouts)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    stages = b.stage_times()
+    ws = ctx.workspace(max(api.workspace_size(ctx, g, cfg) for g in gs))
+    souts = [api._outputs(ctx, g, cfg) for g in gs]
+    for g, o in zip(gs, souts):                      # warm-up of the sequential leg
+        api.run(ctx, g, cfg, ws=ws, outputs=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for g, o in zip(gs, souts):
+            api.run(ctx, g, cfg, ws=ws, outputs=o)
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - t0) / reps
+    ctx.sync_status()
+    same = sum(int(torch.equal(bo["labels"], so[0]["labels"]) and
+                   torch.equal(bo["labels_all"], so[0]["labels_all"]))
+               for bo, so in zip(bouts, souts))
+    nmi_bs = [api.nmi(ctx, bo["labels"], so[0]["labels"]) for bo, so in zip(bouts, souts)]
+    nmi_pl = [api.nmi(ctx, bo["labels"], torch.from_numpy(g.planted.astype(np.int32)).to(dev))
+              for bo, g in zip(bouts, graphs)]
+    b.close()
+    for g in gs:
+        g.close()
+    return {
+        "workload": f"batch{len(graphs)}: {len(graphs)} DC-SBM graphs, N log-uniform on "
+                    "[1e3, 5e4], modularity variant, K 2..64",
+        "graphs": len(graphs), "n_total": int(sum(g.n for g in graphs)),
+        "nnz_total": int(sum(g.nnz for g in graphs)),
+        "batched_graphs_per_s": len(graphs) / t_batch,
+        "sequential_graphs_per_s": len(graphs) / t_seq,
+        "speedup": t_seq / t_batch,
+        "ms_per_batch": 1e3 * t_batch, "ms_sequential": 1e3 * t_seq, "reps": reps,
+        "batch_stage_ms": dict(zip(["prefix", "lloyd", "score"], [round(v, 3) for v in stages])),
+        "graphs_bit_identical_to_sequential": same,
+        "nmi_batched_vs_sequential_min": float(min(nmi_bs)),
+        "nmi_vs_planted_mean": float(np.mean(nmi_pl)),
+    }
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -382,6 +451,9 @@ def main():
         "k_star": {v: int(host[v]["k_selected"][0]) for v in variants},
         "nmi_vs_planted": nmi_planted,
     }
+    if not args.no_batch and args.workload == "n50k":
+        log("batched workload (batched vs one graph at a time)")
+        rec["batch"] = bench_batch(args, api, torch, np, ctx)
     if args.copy_calib_mib:
         a = torch.empty(args.copy_calib_mib << 18, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)

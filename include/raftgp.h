@@ -232,6 +232,50 @@ raft_status raft_nmi_from_counts(const int64_t* counts, int32_t ka, int32_t kb, 
 raft_status raft_run(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg,
                      void* ws, size_t ws_bytes, raft_outputs* out, void* stream);
 
+/* ---- batches of graphs ---------------------------------------------------
+ * Many graphs of uneven size through the whole path (A1-A7, as raft_run) at
+ * once.  raft_batch_create packs the graphs into one block-diagonal CSR on
+ * the device (graph g's rows after those of graphs 0..g-1, its column ids and
+ * stored entries shifted to match; a library-owned copy, so the graph handles
+ * may be destroyed afterwards).  Every stage then runs as one launch over all
+ * graphs and all candidate K of the grid, each graph's work-groups doing what
+ * its own launch would; the fixed launch sequence before the Lloyd loop
+ * (projection, GCN, k-means++ race) is recorded once into a HIP graph per
+ * workspace and replayed.  All graphs share `cfg` (operator, widths, q,
+ * candidate grid, T_max); graph g draws Theta, W and the race with seeds[g]
+ * (cfg->seed when seeds is NULL).  Graph g's outputs are those of raft_run on
+ * graph g with cfg->seed = seeds[g], bit for bit.  Errors: RAFT_E_NOEDGES for
+ * a graph without edges, RAFT_E_INVAL when k_max exceeds a graph's N,
+ * RAFT_E_UNSUPPORTED when the packed CSR exceeds int32 indices. */
+typedef struct raft_batch raft_batch;
+raft_status raft_batch_create(raft_ctx* ctx, int32_t G, const raft_graph* const* graphs,
+                              const uint64_t* seeds, const raft_config* cfg, raft_batch** out);
+void        raft_batch_destroy(raft_batch* b);
+/* Workspace bytes of raft_batch_run (caller-owned device memory, 256-byte
+ * aligned).  The HIP graph recorded for a workspace stays valid while the
+ * same workspace pointer is passed. */
+raft_status raft_batch_workspace_size(raft_ctx* ctx, const raft_batch* b, size_t* bytes);
+/* per_graph[G]: the outputs of each graph as for raft_run (any field
+ * nullable).  Polls convergence from the host and synchronises `stream`. */
+raft_status raft_batch_run(raft_ctx* ctx, raft_batch* b, void* ws, size_t ws_bytes,
+                           raft_outputs* per_graph, void* stream);
+/* enable = 0 launches the prefix directly instead of replaying the HIP graph
+ * (same results; default 1). */
+raft_status raft_batch_set_capture(raft_batch* b, int32_t enable);
+/* Host-only check of the batch planner (no device needed): lays out a batch
+ * of G graphs with n[g] rows and nnz[g] stored entries for `cfg` on a device
+ * with num_cu compute units, at stand-in addresses, and verifies that every
+ * array each graph's kernels index lies inside that graph's part of the
+ * workspace, the control block or the packed features, and that every launch
+ * table gives each graph its work-groups.  RAFT_OK or an error with the
+ * reason in msg.  raft_batch_run runs the same check on its real layout. */
+raft_status raft_batch_plan_check(int32_t G, const int32_t* n, const int64_t* nnz,
+                                  const raft_config* cfg, int32_t num_cu, char* msg,
+                                  size_t msg_len);
+/* GPU time of the last raft_batch_run: [0] projection + GCN + seeding,
+ * [1] Lloyd, [2] scores and outputs (ms). */
+raft_status raft_batch_stage_times(const raft_batch* b, double* ms3);
+
 /* ---- training the GCN weights (optional; the method itself keeps them random) ----
  * Relaxed modularity: with hard memberships H, tr(H^T B H)/2e is the
  * modularity of Eq. 3 (matrix form Eq. 4); replacing H by row-softmax

@@ -25,7 +25,8 @@ EXPORTS = [
     "raft_train_workspace_size", "raft_gcn_forward", "raft_gcn_backward", "raft_modloss_forward",
     "raft_modloss_backward", "raft_adam_step", "raft_spmm_workspace_size",
     "raft_score_workspace_size", "raft_confusion", "raft_nmi_from_counts",
-    "raft_spmm_noalloc",
+    "raft_spmm_noalloc", "raft_batch_create", "raft_batch_destroy", "raft_batch_workspace_size",
+    "raft_batch_run", "raft_batch_set_capture", "raft_batch_plan_check", "raft_batch_stage_times",
 ]
 
 PROF_SPMM, PROF_DENSE, PROF_RACE, PROF_ASSIGN, PROF_UPDATE, PROF_SCORE = range(6)
@@ -112,6 +113,15 @@ _SIGNATURES = {
     "raft_confusion": (_I32, [_P, _P, _P, _I64, _I32, _I32, _P, _P]),
     "raft_nmi_from_counts": (_I32, [ctypes.POINTER(_I64), _I32, _I32,
                                     ctypes.POINTER(ctypes.c_double)]),
+    "raft_batch_create": (_I32, [_P, _I32, ctypes.POINTER(_P), ctypes.POINTER(_U64),
+                                 ctypes.POINTER(RaftConfig), ctypes.POINTER(_P)]),
+    "raft_batch_destroy": (None, [_P]),
+    "raft_batch_workspace_size": (_I32, [_P, _P, ctypes.POINTER(_SZ)]),
+    "raft_batch_run": (_I32, [_P, _P, _P, _SZ, ctypes.POINTER(RaftOutputs), _P]),
+    "raft_batch_set_capture": (_I32, [_P, _I32]),
+    "raft_batch_plan_check": (_I32, [_I32, ctypes.POINTER(_I32), ctypes.POINTER(_I64),
+                                     ctypes.POINTER(RaftConfig), _I32, ctypes.c_char_p, _SZ]),
+    "raft_batch_stage_times": (_I32, [_P, ctypes.POINTER(ctypes.c_double)]),
 }
 
 _lib = None

@@ -281,6 +281,70 @@ def run(ctx, g, cfg, ws=None, want_y=True, want_z=True, outputs=None, want_centr
     return o
 
 
+class Batch:
+    """Many graphs through the whole path at once (raft_batch): one
+    block-diagonal CSR on the device, one launch per stage over all graphs
+    and candidates.  Graph g uses seeds[g] (cfg.seed when None)."""
+
+    def __init__(self, ctx, graphs, cfg, seeds=None):
+        self.ctx = ctx
+        self.cfg = cfg
+        self.graphs = list(graphs)
+        G = len(self.graphs)
+        hs = (ctypes.c_void_p * G)(*[g.h.value for g in self.graphs])
+        sd = None
+        if seeds is not None:
+            sd = (ctypes.c_uint64 * G)(*[int(v) for v in seeds])
+        self.seeds = list(seeds) if seeds is not None else [cfg.seed] * G
+        c = cfg.to_c()
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.raft_batch_create(ctx.h, G, hs, sd, ctypes.byref(c), ctypes.byref(h)))
+        self.h = h
+        need = ctypes.c_size_t()
+        ctx.check(ctx.lib.raft_batch_workspace_size(ctx.h, self.h, ctypes.byref(need)))
+        self.ws_bytes = need.value
+        self.ws = None
+
+    def set_capture(self, enable):
+        self.ctx.check(self.ctx.lib.raft_batch_set_capture(self.h, int(bool(enable))))
+
+    def outputs(self, want_y=False, want_z=False):
+        return [_outputs(self.ctx, g, self.cfg, want_y, want_z) for g in self.graphs]
+
+    def run(self, outputs=None, want_y=False, want_z=False):
+        """Returns one dict of device tensors per graph (as api.run)."""
+        if self.ws is None:
+            self.ws = self.ctx.workspace(self.ws_bytes)
+        if outputs is None:
+            outputs = self.outputs(want_y, want_z)
+        arr = (RaftOutputs * len(outputs))(*[s for _, s in outputs])
+        self.ctx.check(self.ctx.lib.raft_batch_run(self.ctx.h, self.h, _ptr(self.ws),
+                                                   self.ws.numel(), arr, _stream()))
+        return [o for o, _ in outputs]
+
+    def stage_times(self):
+        arr = (ctypes.c_double * 3)()
+        self.ctx.check(self.ctx.lib.raft_batch_stage_times(self.h, arr))
+        return list(arr)
+
+    def close(self):
+        if self.h:
+            self.ctx.lib.raft_batch_destroy(self.h)
+            self.h = None
+
+
+def batch_plan_check(ns, nnzs, cfg, num_cu=256):
+    """Host-only check of the batch planner (no GPU): (status, message)."""
+    lib = _lib.load()
+    G = len(ns)
+    n_arr = (ctypes.c_int32 * G)(*[int(v) for v in ns])
+    e_arr = (ctypes.c_int64 * G)(*[int(v) for v in nnzs])
+    c = cfg.to_c()
+    msg = ctypes.create_string_buffer(512)
+    st = lib.raft_batch_plan_check(G, n_arr, e_arr, ctypes.byref(c), num_cu, msg, 512)
+    return st, msg.value.decode(errors="replace")
+
+
 def score(ctx, g, labels_all, ks):
     labels_all = labels_all.to(torch.uint8).contiguous()
     kc = len(ks)

@@ -322,7 +322,10 @@ struct Plan {
     size_t bytes = 0;
 };
 
-void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char* base, Plan& P) {
+// `features` = false leaves out the N x L feature buffers (a batch keeps them
+// packed for all its graphs).
+void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char* base, Plan& P,
+                 bool features = true) {
     const int n = g->n;
     P.L = c->proj_dim;
     P.d = embed_dim(c);
@@ -337,12 +340,13 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
     P.race_grid = kmeans_race_grid(n, ctx->num_cu);
     Arena a;
     a.base = base;
-    const size_t nL = (size_t)n * P.Lmax;
+    const size_t nL = features ? (size_t)n * P.Lmax : 0;
     P.y0 = a.take<float>(nL);
     P.y1 = a.take<float>(nL);
     P.pbuf = a.take<float>(nL);
-    P.yout = a.take<float>((size_t)n * P.L);
-    P.zout = a.take<float>((size_t)n * P.d);
+    P.yout = a.take<float>(features ? (size_t)n * P.L : 0);
+    P.zout = a.take<float>(features ? (size_t)n * P.d : 0);
+    if (!features) P.y0 = P.y1 = P.pbuf = P.yout = P.zout = nullptr;
     size_t wmax = 1;
     int lin = P.L;
     for (int k = 0; k < c->n_layers; ++k) {
@@ -412,6 +416,8 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
     km.nchunks = (int)(((int64_t)n + 63) / 64);
     km.moved_it = a.take<int32_t>((size_t)km.nchunks * G.Kc);
     km.status = ctx->d_status;
+    km.seed = c->seed;
+    km.zoff = 0;
     // scores
     ScorePlan& sc = P.sc;
     sc.n = n;
@@ -573,7 +579,7 @@ raft_status do_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* 
     if (km.split) launch_split_points(km, Z, st);
     for (int t = 0; t < km.k_max; ++t) {
         ProfScope ps(ctx, RAFT_PROF_RACE, st);
-        launch_race_pick(km, Z, t, c->seed, st);
+        launch_race_pick(km, Z, t, st);
     }
     launch_init_centres(km, Z, st);
     RAFT_TRY(launch_check(ctx));
@@ -1422,6 +1428,904 @@ raft_status raft_profile_read(raft_ctx* ctx, double* ms, int64_t* launches) {
 raft_status raft_get_stage_times(raft_ctx* ctx, double* ms5) {
     if (!ctx || !ms5) return RAFT_E_INVAL;
     for (int s = 0; s < 5; ++s) ms5[s] = ctx->stage_ms[s];
+    return RAFT_OK;
+}
+
+}  // extern "C"
+
+// ---- batches of graphs (block-diagonal CSR, one launch per stage) --------
+
+struct raft_batch {
+    raft_ctx* ctx = nullptr;
+    int G = 0;
+    raft_config cfg{};
+    std::vector<raft_graph> shadow;      // n and nnz of each graph (plan sizes)
+    std::vector<uint64_t> seeds;
+    std::vector<int32_t> base;           // first row of graph g in the packed CSR
+    std::vector<int64_t> ebase;          // first stored entry of graph g
+    int32_t N = 0;
+    int64_t NNZ = 0;
+    int32_t *rp = nullptr, *ci = nullptr, *deg = nullptr, *order = nullptr;
+    float *s = nullptr, *sh = nullptr, *dcoef = nullptr;
+    // the captured embedding + seeding launches, valid for one workspace
+    bool use_graph = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void* exec_ws = nullptr;
+    // pinned host memory of the convergence polls: two slots of the dynamic
+    // control part and two of the active flags, allocated once
+    char* h_poll = nullptr;
+    size_t dyn_bytes = 0, flag_bytes = 0;
+    hipEvent_t poll_ev[2] = {};
+    double stage_ms[3] = {0, 0, 0};
+    hipEvent_t ev[4] = {};
+};
+
+namespace {
+
+// Work-group table of one batched launch kind (host side).
+struct HostTable {
+    std::vector<int32_t> start, count;
+    int grid = 0;
+    size_t off = 0;   // offset in the control block
+};
+
+HostTable make_table(const std::vector<int>& counts) {
+    HostTable t;
+    const int G = (int)counts.size();
+    t.start.assign(G + 1, 0);
+    t.count.assign(G, 0);
+    for (int g = 0; g < G; ++g) {
+        t.count[g] = counts[g];
+        t.start[g + 1] = t.start[g] + (counts[g] + 7) / 8 * 8;
+    }
+    t.grid = t.start[G];
+    return t;
+}
+
+enum BatchTab {
+    bt_one, bt_gtheta, bt_cpart, bt_cslices, bt_spmm_proj, bt_dense, bt_rownorm, bt_reset,
+    bt_zmax, bt_split, bt_race, bt_init, bt_ufinish, bt_transpose, bt_edge, bt_reduce,
+    bt_sfinal, bt_first, bt_apply, bt_copy, bt_gw0, bt_spmm_layer0 = bt_gw0 + RAFT_MAX_LAYERS,
+    bt_static_end = bt_spmm_layer0 + RAFT_MAX_LAYERS
+};
+
+// Per-run layout of a batch: the control block (per-graph plans, launch
+// items and tables, uploaded from the host), the packed feature buffers, and
+// one single-graph partition layout per graph.
+struct BatchLayout {
+    int Kc = 0, KP = 0, SK = 0, L = 0, d = 0, Lmax = 0, S = 0;
+    std::vector<Plan> P;
+    std::vector<GraphView> gv;
+    std::vector<KmeansPlan> km;
+    std::vector<ScorePlan> sc;
+    std::vector<HostTable> tab;          // static tables, index BatchTab
+    HostTable tab_assign, tab_update;
+    // control block offsets
+    size_t off_meta = 0, off_gv = 0, off_sc = 0, off_spmm = 0, off_cs = 0, off_ga = 0,
+           off_de = 0, off_dyn = 0, off_km = 0, off_lists = 0, off_ta = 0, off_tu = 0,
+           off_flags = 0, ctl_upload = 0, ctl_bytes = 0;
+    // feature buffers (device)
+    float *Y0 = nullptr, *Y1 = nullptr, *PB = nullptr, *YO = nullptr, *Zp = nullptr;
+    char* ctl = nullptr;
+    size_t bytes = 0;
+    std::vector<char> host;              // the uploaded part of the control block
+};
+
+template <typename T>
+T* at(char* base, size_t off) {
+    return base ? reinterpret_cast<T*>(base + off) : nullptr;
+}
+
+BatchTable dev_table(char* ctl, const HostTable& t, int G) {
+    BatchTable b;
+    b.start = at<int32_t>(ctl, t.off);
+    b.count = at<int32_t>(ctl, t.off + sizeof(int32_t) * (size_t)(G + 1));
+    b.G = G;
+    return b;
+}
+
+size_t table_bytes(int G) { return sizeof(int32_t) * (size_t)(2 * G + 1); }
+
+void put_table(std::vector<char>& host, const HostTable& t) {
+    memcpy(host.data() + t.off, t.start.data(), sizeof(int32_t) * t.start.size());
+    memcpy(host.data() + t.off + sizeof(int32_t) * t.start.size(), t.count.data(),
+           sizeof(int32_t) * t.count.size());
+}
+
+int width_in(const raft_config* c, int k) { return k == 0 ? c->proj_dim : c->layer_dims[k - 1]; }
+
+// Builds the layout for workspace `ws` (nullptr: sizes only) and the host
+// image of the control block.
+void batch_layout(raft_batch* b, char* ws, raft_outputs* outs, BatchLayout& B) {
+    raft_ctx* ctx = b->ctx;
+    const raft_config* c = &b->cfg;
+    const int G = b->G;
+    const Grid grid = make_grid(c->k_min, c->k_max, c->k_step);
+    B.Kc = grid.Kc;
+    B.KP = grid.KP;
+    B.SK = grid.SK;
+    B.L = c->proj_dim;
+    B.d = embed_dim(c);
+    B.Lmax = max_width(c);
+    B.S = (grid.Kc + 7) / 8 * 8;
+    const int nl = c->n_layers;
+    // control block
+    Arena a;
+    a.base = ws;
+    B.ctl = ws;
+    B.off_meta = a.off;
+    a.take<int32_t>((size_t)3 * B.Kc + B.KP);
+    B.off_gv = a.off;
+    a.take<GraphView>(G);
+    B.off_sc = a.off;
+    a.take<ScorePlan>(G);
+    B.off_spmm = a.off;
+    a.take<SpmmItem>((size_t)(nl + 1) * G);
+    B.off_cs = a.off;
+    a.take<ColsumItem>(G);
+    B.off_ga = a.off;
+    a.take<GaussItem>((size_t)(nl + 1) * G);
+    B.off_de = a.off;
+    a.take<DenseItem>((size_t)(nl + 1) * G);
+    B.tab.assign(bt_static_end, HostTable());
+    std::vector<size_t> tab_off(bt_static_end);
+    for (int t = 0; t < bt_static_end; ++t) {
+        tab_off[t] = a.off;
+        a.take<char>(table_bytes(G));
+    }
+    // the dynamic part, rewritten at every convergence poll
+    B.off_dyn = a.off;
+    B.off_km = a.off;
+    a.take<KmeansPlan>(G);
+    B.off_lists = a.off;
+    a.take<int32_t>((size_t)G * kDynLen(B.Kc));
+    B.off_ta = a.off;
+    a.take<char>(table_bytes(G));
+    B.off_tu = a.off;
+    a.take<char>(table_bytes(G));
+    B.ctl_upload = a.off;
+    // device-written active flags of every candidate of every graph
+    B.off_flags = a.off;
+    a.take<int32_t>((size_t)G * B.Kc);
+    B.ctl_bytes = a.off;
+    // packed features
+    const size_t NL = (size_t)b->N * B.Lmax;
+    B.Y0 = a.take<float>(NL);
+    B.Y1 = a.take<float>(NL);
+    B.PB = a.take<float>(NL);
+    B.YO = a.take<float>((size_t)b->N * B.L);
+    B.Zp = a.take<float>((size_t)b->N * B.d);
+    // per graph: the single-graph layout without feature buffers
+    B.P.assign(G, Plan());
+    B.gv.assign(G, GraphView());
+    B.km.assign(G, KmeansPlan());
+    B.sc.assign(G, ScorePlan());
+    for (int g = 0; g < G; ++g) {
+        raft_config cg = *c;
+        cg.seed = b->seeds[g];
+        char* sub = ws ? ws + a.off : nullptr;
+        plan_layout(ctx, &b->shadow[g], &cg, sub, B.P[g], false);
+        a.off += align256(B.P[g].bytes);
+    }
+    B.bytes = a.off;
+    if (!ws) return;
+    // ---- host image of the control block ----
+    B.host.assign(B.ctl_upload, 0);
+    char* H = B.host.data();
+    char* D = ws;
+    {
+        int32_t* m = reinterpret_cast<int32_t*>(H + B.off_meta);
+        std::copy(grid.ks.begin(), grid.ks.end(), m);
+        std::copy(grid.koff16.begin(), grid.koff16.end(), m + B.Kc);
+        std::copy(grid.koff.begin(), grid.koff.end(), m + 2 * B.Kc);
+        std::copy(grid.cand_of.begin(), grid.cand_of.end(), m + 3 * B.Kc);
+    }
+    const int32_t* d_meta = at<int32_t>(D, B.off_meta);
+    int32_t* d_lists = at<int32_t>(D, B.off_lists);
+    int32_t* d_flags = at<int32_t>(D, B.off_flags);
+    std::vector<std::vector<int>> cnt(bt_static_end, std::vector<int>(G, 0));
+    for (int g = 0; g < G; ++g) {
+        Plan& P = B.P[g];
+        const raft_graph& sg = b->shadow[g];
+        raft_outputs* o = outs ? &outs[g] : nullptr;
+        GraphView v;
+        v.n = sg.n;
+        v.nnz = sg.nnz;
+        v.rp = b->rp;
+        v.ci = b->ci;
+        v.deg = b->deg;
+        v.s = b->s;
+        v.sh = b->sh;
+        v.dcoef = b->dcoef;
+        v.order = b->order + b->base[g];
+        v.base = b->base[g];
+        B.gv[g] = v;
+        KmeansPlan km = P.km;
+        km.ks = d_meta;
+        km.koff16 = d_meta + B.Kc;
+        km.koff = d_meta + 2 * B.Kc;
+        km.cand_of = d_meta + 3 * B.Kc;
+        int32_t* dl = d_lists + (size_t)g * kDynLen(B.Kc);
+        km.alist = dl;
+        km.agrp = dl + B.Kc;
+        km.ugrp = dl + 2 * B.Kc + 1;
+        km.uwi0 = dl + 3 * B.Kc + 2;
+        km.ulen = dl + 4 * B.Kc + 3;
+        km.cranges = dl + 5 * B.Kc + 3;
+        km.active = d_flags + (size_t)g * B.Kc;
+        if (o && o->picks) km.picks = o->picks;
+        if (o && o->iters) km.iters = o->iters;
+        km.zoff = b->base[g];
+        km.seed = b->seeds[g];
+        B.km[g] = km;
+        pack_lists(P.lists, B.Kc,
+                   reinterpret_cast<int32_t*>(H + B.off_lists) + (size_t)g * kDynLen(B.Kc));
+        ScorePlan sc = P.sc;
+        sc.ks = d_meta;
+        sc.koff = d_meta + 2 * B.Kc;
+        if (o && o->mod) sc.mod = o->mod;
+        if (o && o->ncut) sc.ncut = o->ncut;
+        sc.lab = P.lab_pm;
+        sc.lab_cm = km.lab_cm;
+        sc.ksel_out = (o && o->k_selected) ? o->k_selected : P.ksel_int;
+        sc.labels_out = o ? o->labels : nullptr;
+        sc.labels_all_out = o ? o->labels_all : nullptr;
+        B.sc[g] = sc;
+        // launch items
+        const int n = sg.n;
+        for (int k = 0; k <= c->n_layers; ++k) {
+            // item k: the projection (k = 0) or the aggregation of layer k,
+            // whose SpMM runs at the layer's input width
+            const int w = width_in(c, k);
+            const int wsp = k == 0 ? B.L : width_in(c, k - 1);
+            SpmmItem it;
+            it.g = v;
+            it.cvec = P.cvec;
+            it.cpart = P.cpart;
+            it.R = 0;
+            it.nrb = 0;
+            const int gridk = spmm_launch_shape(n, wsp, ctx->num_cu, &it.R, &it.nrb);
+            cnt[k == 0 ? bt_spmm_proj : bt_spmm_layer0 + k - 1][g] = gridk;
+            reinterpret_cast<SpmmItem*>(H + B.off_spmm)[(size_t)k * G + g] = it;
+            GaussItem ga;
+            ga.seed = b->seeds[g];
+            if (k == 0) {
+                ga.stream = 0x10;
+                ga.rows = n;
+                ga.cols = B.L;
+                ga.sigma = 1.0 / std::sqrt((double)B.L);
+                ga.out = B.Y0 + (size_t)b->base[g] * B.L;
+                cnt[bt_gtheta][g] = gaussian_blocks(n, B.L);
+            } else {
+                const int lin = width_in(c, k - 1);
+                ga.stream = 0x10 + (uint64_t)k;
+                ga.rows = lin;
+                ga.cols = w;
+                ga.sigma = 1.0 / std::sqrt((double)lin);
+                ga.out = P.wbuf;
+                cnt[bt_gw0 + k - 1][g] = gaussian_blocks(lin, w);
+            }
+            reinterpret_cast<GaussItem*>(H + B.off_ga)[(size_t)k * G + g] = ga;
+        }
+        ColsumItem cs;
+        cs.g = v;
+        cs.part = P.cpart;
+        int rpw = 0;
+        cs.parts = spmm_grid(n, B.L, ctx->num_cu, &rpw);
+        cs.rpw = rpw;
+        cs.c64 = P.c64;
+        cs.cvec = P.cvec;
+        reinterpret_cast<ColsumItem*>(H + B.off_cs)[g] = cs;
+        cnt[bt_cpart][g] = cs.parts;
+        cnt[bt_cslices][g] = cs.parts > 0 ? kColsumSliceBlocks : 0;
+        cnt[bt_one][g] = 1;
+        cnt[bt_dense][g] = dense_blocks(n);
+        cnt[bt_rownorm][g] = rownorm_blocks(n);
+        cnt[bt_reset][g] = kmeans_blocks(km, kKmReset, ctx->num_cu);
+        cnt[bt_zmax][g] = kmeans_blocks(km, kKmZmax, ctx->num_cu);
+        cnt[bt_split][g] = km.split ? kmeans_blocks(km, kKmSplit, ctx->num_cu) : 0;
+        cnt[bt_race][g] = kmeans_blocks(km, kKmRace, ctx->num_cu);
+        cnt[bt_init][g] = kmeans_blocks(km, kKmInit, ctx->num_cu);
+        cnt[bt_ufinish][g] = kmeans_blocks(km, kKmUpdateFinish, ctx->num_cu);
+        cnt[bt_transpose][g] = score_blocks(sc, kScTranspose);
+        cnt[bt_edge][g] = score_blocks(sc, kScEdge);
+        cnt[bt_reduce][g] = score_blocks(sc, kScReduce);
+        cnt[bt_sfinal][g] = score_blocks(sc, kScFinalize);
+        cnt[bt_first][g] = score_blocks(sc, kScFirst);
+        cnt[bt_apply][g] = sc.labels_out ? score_blocks(sc, kScApply) : 0;
+        cnt[bt_copy][g] = sc.labels_all_out ? score_blocks(sc, kScCopy) : 0;
+    }
+    // dense items: layer k reads PB, writes the layer's destination buffer
+    {
+        DenseItem* de = reinterpret_cast<DenseItem*>(H + B.off_de);
+        const float* h = B.YO;
+        float* hbuf = c->normalize_input ? B.Y1 : nullptr;
+        if (hbuf) h = hbuf;
+        for (int g = 0; g < G; ++g) {
+            DenseItem it;
+            it.P = nullptr;
+            it.W = nullptr;
+            it.H = (c->n_layers == 0 ? B.Zp : B.Y1) + (size_t)b->base[g] * B.L;
+            it.n = b->shadow[g].n;
+            de[(size_t)c->n_layers * G + g] = it;      // row normalisation of the input
+        }
+        for (int k = 1; k <= c->n_layers; ++k) {
+            const int lin = width_in(c, k - 1), lout = width_in(c, k);
+            float* dst = (k == c->n_layers) ? B.Zp : (h == B.Y0 ? B.Y1 : B.Y0);
+            for (int g = 0; g < G; ++g) {
+                DenseItem it;
+                it.P = B.PB + (size_t)b->base[g] * lin;
+                it.W = B.P[g].wbuf;
+                it.H = dst + (size_t)b->base[g] * lout;
+                it.n = b->shadow[g].n;
+                de[(size_t)(k - 1) * G + g] = it;
+            }
+            h = dst;
+        }
+    }
+    for (int t = 0; t < bt_static_end; ++t) {
+        B.tab[t] = make_table(cnt[t]);
+        B.tab[t].off = tab_off[t];
+        put_table(B.host, B.tab[t]);
+    }
+    memcpy(H + B.off_gv, B.gv.data(), sizeof(GraphView) * G);
+    memcpy(H + B.off_sc, B.sc.data(), sizeof(ScorePlan) * G);
+}
+
+// Dynamic tables from the plans' current work lists (0 for a graph whose
+// candidates have all stopped), written with the plans into the host image.
+void batch_dynamic(raft_batch* b, BatchLayout& B, char* H, const std::vector<int>& live) {
+    const int G = b->G;
+    std::vector<int> ca(G), cu(G);
+    for (int g = 0; g < G; ++g) {
+        ca[g] = live[g] ? kmeans_blocks(B.km[g], kKmAssign, b->ctx->num_cu) : 0;
+        cu[g] = live[g] ? kmeans_blocks(B.km[g], kKmUpdate, b->ctx->num_cu) : 0;
+    }
+    B.tab_assign = make_table(ca);
+    B.tab_assign.off = B.off_ta - B.off_dyn;
+    B.tab_update = make_table(cu);
+    B.tab_update.off = B.off_tu - B.off_dyn;
+    memcpy(H + (B.off_km - B.off_dyn), B.km.data(), sizeof(KmeansPlan) * G);
+    const HostTable* ts[2] = {&B.tab_assign, &B.tab_update};
+    for (const HostTable* t : ts) {
+        memcpy(H + t->off, t->start.data(), sizeof(int32_t) * t->start.size());
+        memcpy(H + t->off + sizeof(int32_t) * t->start.size(), t->count.data(),
+               sizeof(int32_t) * t->count.size());
+    }
+    B.tab_assign.off = B.off_ta;
+    B.tab_update.off = B.off_tu;
+}
+
+// Host check of a batch layout before anything is launched: every array a
+// kernel of graph g indexes (at the extent its single-graph launch uses)
+// lies inside the graph's own part of the workspace, the control block or
+// the packed feature buffers, the parts do not overlap, and every table
+// gives each graph at least its count of work-groups.
+struct Span {
+    const char* lo;
+    size_t len;
+};
+
+bool span_in(const void* p, size_t bytes, const char* lo, size_t len) {
+    const char* q = reinterpret_cast<const char*>(p);
+    return q >= lo && bytes <= len && (size_t)(q - lo) <= len - bytes;
+}
+
+raft_status batch_check(raft_ctx* ctx, const raft_batch* b, const BatchLayout& B,
+                        size_t ws_bytes) {
+    const int G = b->G;
+    const char* ws = B.ctl;
+    if (B.bytes > ws_bytes) return fail(ctx, RAFT_E_WORKSPACE, "batch layout exceeds workspace");
+    const char* ctl = ws;
+    const size_t NL = (size_t)b->N * B.Lmax * sizeof(float);
+    auto bad = [&](int g, const char* what) {
+        return fail(ctx, RAFT_E_INVAL, "batch layout check: graph %d, %s", g, what);
+    };
+    std::vector<Span> subs;
+    size_t off = 0;
+    {
+        // the per-graph parts follow the features, in graph order
+        off = (size_t)(reinterpret_cast<const char*>(B.Zp) - ws) +
+              align256((size_t)b->N * B.d * sizeof(float));
+    }
+    for (int g = 0; g < G; ++g) {
+        const Plan& P = B.P[g];
+        const char* lo = ws + off;
+        const size_t len = P.bytes;
+        if (off + len > B.bytes) return bad(g, "part beyond the layout");
+        off += align256(len);
+        const KmeansPlan& k = B.km[g];
+        const ScorePlan& c = B.sc[g];
+        const size_t n = (size_t)b->shadow[g].n, d = (size_t)B.d, KP = (size_t)B.KP;
+        const size_t Kc = (size_t)B.Kc;
+        const size_t rmax = (size_t)update_ranges_max(b->shadow[g].n, ctx->num_cu);
+        struct Need {
+            const void* p;
+            size_t bytes;
+            const char* name;
+        } own[] = {
+            {k.C, KP * d * 4, "C"}, {k.cnorm, KP * 4, "cnorm"},
+            {k.S64, KP * d * 8, "S64"}, {k.N32, KP * 4, "N32"},
+            {k.pdelta, rmax * KP * d * 8, "pdelta"}, {k.pcnt, rmax * KP * 4, "pcnt"},
+            {k.pdirty, rmax * KP, "pdirty"}, {k.zmax_bits, 4, "zmax"}, {k.w, n * 4, "w"},
+            {k.race_val, (size_t)2 * k.race_grid * 8, "race_val"},
+            {k.race_idx, (size_t)2 * k.race_grid * 4, "race_idx"},
+            {k.lab_cm, Kc * n, "lab_cm"}, {k.lab_old, Kc * n, "lab_old"},
+            {k.moved_it, (size_t)k.nchunks * Kc * 4, "moved_it"},
+            {k.changes, Kc * 4, "changes"}, {k.active_count, 4, "active_count"},
+            {c.lpart, (size_t)c.grid * B.SK * 4, "lpart"},
+            {c.vpart, (size_t)c.grid * B.SK * 4, "vpart"}, {c.l64, (size_t)B.SK * 8, "l64"},
+            {c.v64, (size_t)B.SK * 8, "v64"}, {c.best, 4, "best"},
+            {c.first, (RAFT_MAX_K + 1) * 4, "first"}, {c.remap, (RAFT_MAX_K + 1) * 4, "remap"},
+            {c.lab, n * (size_t)B.S, "lab"},
+            {P.cpart, ((size_t)spmm_grid((int32_t)n, B.L, ctx->num_cu, nullptr) + kColsumStageRows) *
+                          B.L * 8, "cpart"},
+            {P.c64, (size_t)B.L * 8, "c64"}, {P.cvec, (size_t)B.L * 4, "cvec"},
+        };
+        for (const Need& q : own)
+            if (!span_in(q.p, q.bytes, lo, len)) return bad(g, q.name);
+        if (k.split && (!span_in(k.zh, n * d * 2, lo, len) || !span_in(k.zl, n * d * 2, lo, len) ||
+                        !span_in(k.ch, KP * d * 2, lo, len) || !span_in(k.cl, KP * d * 2, lo, len)))
+            return bad(g, "split halves");
+        // outputs may be caller memory; internal defaults must be in the part
+        if (k.n != (int)n || k.d != (int)d || k.Kc != B.Kc || k.KP != B.KP) return bad(g, "plan sizes");
+        if (!span_in(k.active, Kc * 4, ctl + B.off_flags, (size_t)G * Kc * 4)) return bad(g, "flags");
+        if (!span_in(k.alist, (size_t)kDynLen(B.Kc) * 4, ctl + B.off_lists,
+                     (size_t)G * kDynLen(B.Kc) * 4))
+            return bad(g, "lists");
+        if ((size_t)k.zoff + n > (size_t)b->N || b->base[g] != k.zoff) return bad(g, "zoff");
+        if (B.gv[g].base != b->base[g] || B.gv[g].n != (int)n) return bad(g, "view");
+        // widths of the layers: W buffer and row ranges of the packed features
+        size_t wmax = 1;
+        for (int l = 1; l <= b->cfg.n_layers; ++l)
+            wmax = std::max(wmax, (size_t)width_in(&b->cfg, l - 1) * width_in(&b->cfg, l));
+        if (!span_in(P.wbuf, wmax * 4, lo, len)) return bad(g, "W");
+        for (int l = 0; l <= b->cfg.n_layers; ++l)
+            if (((size_t)b->base[g] + n) * width_in(&b->cfg, l) * 4 > NL) return bad(g, "features");
+        for (int t = 0; t < bt_static_end; ++t) {
+            const HostTable& h = B.tab[t];
+            if (h.start[g + 1] - h.start[g] < h.count[g] || h.start[g] % 8) return bad(g, "table");
+        }
+    }
+    for (int t = 0; t < bt_static_end; ++t)
+        if (B.tab[t].grid != B.tab[t].start[G]) return fail(ctx, RAFT_E_INVAL, "table grid");
+    if (off > B.bytes) return fail(ctx, RAFT_E_INVAL, "parts beyond the layout");
+    return RAFT_OK;
+}
+
+// The fixed launch sequence before the Lloyd loop: projection, GCN, k-means
+// reset, scales and the k-means++ race.  Recorded into a HIP graph.
+raft_status batch_prefix(raft_batch* b, BatchLayout& B, hipStream_t st) {
+    raft_ctx* ctx = b->ctx;
+    const raft_config* c = &b->cfg;
+    const int G = b->G;
+    char* D = B.ctl;
+    auto T = [&](int k) { return dev_table(D, B.tab[k], G); };
+    auto grid = [&](int k) { return B.tab[k].grid; };
+    const SpmmItem* sp = at<SpmmItem>(D, B.off_spmm);
+    const GaussItem* ga = at<GaussItem>(D, B.off_ga);
+    const DenseItem* de = at<DenseItem>(D, B.off_de);
+    const ColsumItem* cs = at<ColsumItem>(D, B.off_cs);
+    const KmeansPlan* km = at<KmeansPlan>(D, B.off_km);
+    const int L = B.L;
+    // projection
+    launch_gaussian_batched(ga, T(bt_gtheta), grid(bt_gtheta), st);
+    const bool mod_full = c->op == RAFT_X_MOD_FULL;
+    float* src = B.Y0;
+    if (mod_full) {
+        launch_colsum_partials_batched(cs, L, src, T(bt_cpart), grid(bt_cpart), st);
+        launch_colsum_finish_batched(cs, L, T(bt_cslices), grid(bt_cslices), T(bt_one),
+                                     grid(bt_one), st);
+    }
+    for (int t = 1; t <= c->q; ++t) {
+        float* dst = (t == c->q) ? B.YO : (src == B.Y0 ? B.Y1 : B.Y0);
+        const bool need_cs = mod_full && t < c->q;
+        launch_spmm_batched(sp, c->op, L, src, dst, need_cs, T(bt_spmm_proj), grid(bt_spmm_proj),
+                            st);
+        if (need_cs)
+            launch_colsum_finish_batched(cs, L, T(bt_cslices), grid(bt_cslices), T(bt_one),
+                                         grid(bt_one), st);
+        src = dst;
+    }
+    // GCN
+    const float* h = B.YO;
+    if (c->n_layers == 0) {
+        HIP_TRY(ctx, hipMemcpyAsync(B.Zp, B.YO, (size_t)b->N * L * sizeof(float),
+                                    hipMemcpyDeviceToDevice, st));
+        if (c->normalize_input)
+            launch_rownorm_batched(de, L, T(bt_rownorm), grid(bt_rownorm), st);
+    } else {
+        if (c->normalize_input) {
+            HIP_TRY(ctx, hipMemcpyAsync(B.Y1, B.YO, (size_t)b->N * L * sizeof(float),
+                                        hipMemcpyDeviceToDevice, st));
+            launch_rownorm_batched(de + (size_t)c->n_layers * G, L, T(bt_rownorm),
+                                   grid(bt_rownorm), st);
+            h = B.Y1;
+        }
+        int lin = L;
+        for (int k = 1; k <= c->n_layers; ++k) {
+            const int lout = c->layer_dims[k - 1];
+            launch_gaussian_batched(ga + (size_t)k * G, T(bt_gw0 + k - 1), grid(bt_gw0 + k - 1),
+                                    st);
+            launch_spmm_batched(sp + (size_t)k * G, kOpGcn, lin, h, B.PB, false,
+                                T(bt_spmm_layer0 + k - 1), grid(bt_spmm_layer0 + k - 1), st);
+            launch_dense_layer_batched(de + (size_t)(k - 1) * G, lin, lout, false, ctx->d_status,
+                                       T(bt_dense), grid(bt_dense), st);
+            h = (k == c->n_layers) ? B.Zp : (h == B.Y0 ? B.Y1 : B.Y0);
+            lin = lout;
+        }
+    }
+    // k-means reset, scales, seeding
+    const int d = B.d;
+    const bool split = B.P[0].km.split != 0;
+    const int kmax = B.P[0].km.k_max;
+    launch_kmeans_batched(kKmReset, km, d, split, B.Zp, 0, 0, 0, 0, T(bt_reset), grid(bt_reset),
+                          st);
+    launch_kmeans_batched(kKmZmax, km, d, split, B.Zp, 0, 0, 0, 0, T(bt_zmax), grid(bt_zmax), st);
+    if (split)
+        launch_kmeans_batched(kKmSplit, km, d, split, B.Zp, 0, 0, 0, 0, T(bt_split),
+                              grid(bt_split), st);
+    for (int t = 0; t < kmax; ++t)
+        launch_kmeans_batched(kKmRace, km, d, split, B.Zp, t, 0, 0, 0, T(bt_race), grid(bt_race),
+                              st);
+    launch_kmeans_batched(kKmRaceFinal, km, d, split, B.Zp, 0, 0, 0, 0, T(bt_one), grid(bt_one),
+                          st);
+    launch_kmeans_batched(kKmInit, km, d, split, B.Zp, 0, 0, 0, 0, T(bt_init), grid(bt_init), st);
+    return launch_check(ctx);
+}
+
+}  // namespace
+
+extern "C" {
+
+raft_status raft_batch_create(raft_ctx* ctx, int32_t G, const raft_graph* const* graphs,
+                              const uint64_t* seeds, const raft_config* cfg, raft_batch** out) {
+    if (!ctx) return RAFT_E_INVAL;
+    if (!out) return fail(ctx, RAFT_E_INVAL, "out is null");
+    *out = nullptr;
+    if (G < 1 || !graphs) return fail(ctx, RAFT_E_INVAL, "batch of %d graphs", G);
+    RAFT_TRY(check_config(ctx, nullptr, cfg));
+    const int d = embed_dim(cfg);
+    if (!kmeans_supported(d)) return fail(ctx, RAFT_E_UNSUPPORTED, "embedding width %d", d);
+    int64_t N = 0, NNZ = 0;
+    for (int g = 0; g < G; ++g) {
+        RAFT_TRY(check_graph(ctx, graphs[g]));
+        if (graphs[g]->nnz == 0) return fail(ctx, RAFT_E_NOEDGES, "graph %d has no edges", g);
+        if (cfg->k_max > graphs[g]->n)
+            return fail(ctx, RAFT_E_INVAL, "k_max %d exceeds N of graph %d", cfg->k_max, g);
+        N += graphs[g]->n;
+        NNZ += graphs[g]->nnz;
+    }
+    if (N >= INT32_MAX || NNZ >= INT32_MAX)
+        return fail(ctx, RAFT_E_UNSUPPORTED, "batch of %lld rows, %lld entries exceeds int32",
+                    (long long)N, (long long)NNZ);
+    {
+        Plan P;
+        plan_layout(ctx, graphs[0], cfg, nullptr, P);
+        if (kmeans_update_lds(P.ucap, d) > ctx->lds_max)
+            return fail(ctx, RAFT_E_UNSUPPORTED, "k_max %d too large for width %d", P.grid.k_max, d);
+        if (!score_supported(P.grid.SK))
+            return fail(ctx, RAFT_E_UNSUPPORTED, "sum of candidate K %d > 16384", P.grid.SK);
+    }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    raft_batch* b = new raft_batch();
+    b->ctx = ctx;
+    b->G = G;
+    b->cfg = *cfg;
+    b->N = (int32_t)N;
+    b->NNZ = NNZ;
+    b->shadow.resize(G);
+    b->seeds.resize(G);
+    b->base.resize(G);
+    b->ebase.resize(G);
+    int64_t r = 0, e = 0;
+    for (int g = 0; g < G; ++g) {
+        b->shadow[g].ctx = ctx;
+        b->shadow[g].n = graphs[g]->n;
+        b->shadow[g].nnz = graphs[g]->nnz;
+        b->seeds[g] = seeds ? seeds[g] : cfg->seed;
+        b->base[g] = (int32_t)r;
+        b->ebase[g] = e;
+        r += graphs[g]->n;
+        e += graphs[g]->nnz;
+    }
+    auto cleanup = [&](raft_status st, const char* what) {
+        raft_batch_destroy(b);
+        return fail(ctx, st, "%s", what);
+    };
+    bool ok = hipMalloc(&b->rp, sizeof(int32_t) * ((size_t)N + 1)) == hipSuccess &&
+              hipMalloc(&b->ci, sizeof(int32_t) * (size_t)NNZ) == hipSuccess &&
+              hipMalloc(&b->deg, sizeof(int32_t) * (size_t)N) == hipSuccess &&
+              hipMalloc(&b->order, sizeof(int32_t) * (size_t)N) == hipSuccess &&
+              hipMalloc(&b->s, sizeof(float) * (size_t)N) == hipSuccess &&
+              hipMalloc(&b->sh, sizeof(float) * (size_t)N) == hipSuccess &&
+              hipMalloc(&b->dcoef, sizeof(float) * (size_t)N) == hipSuccess;
+    if (!ok) return cleanup(RAFT_E_NOMEM, "batch allocation failed");
+    // pack the graphs: block g of the block-diagonal CSR is graph g with its
+    // rows at base[g], its columns shifted by base[g], its entries at ebase[g]
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
+        return cleanup(RAFT_E_DEVICE, "stream creation failed");
+    b->cap_stream = st;
+    hipError_t err = hipSuccess;
+    for (int g = 0; g < G && err == hipSuccess; ++g) {
+        const raft_graph* gr = graphs[g];
+        const size_t off = (size_t)b->base[g];
+        launch_offset_copy(gr->rp, b->rp + off, (int64_t)gr->n + 1, (int32_t)b->ebase[g], st);
+        launch_offset_copy(gr->ci, b->ci + b->ebase[g], gr->nnz, b->base[g], st);
+        launch_offset_copy(gr->order, b->order + off, gr->n, b->base[g], st);
+        err = hipMemcpyAsync(b->deg + off, gr->deg, sizeof(int32_t) * gr->n,
+                             hipMemcpyDeviceToDevice, st);
+        if (err == hipSuccess)
+            err = hipMemcpyAsync(b->s + off, gr->s, sizeof(float) * gr->n, hipMemcpyDeviceToDevice,
+                                 st);
+        if (err == hipSuccess)
+            err = hipMemcpyAsync(b->sh + off, gr->sh, sizeof(float) * gr->n,
+                                 hipMemcpyDeviceToDevice, st);
+        if (err == hipSuccess)
+            err = hipMemcpyAsync(b->dcoef + off, gr->dcoef, sizeof(float) * gr->n,
+                                 hipMemcpyDeviceToDevice, st);
+        if (err == hipSuccess) err = hipGetLastError();
+    }
+    if (err == hipSuccess) err = hipStreamSynchronize(st);
+    if (err != hipSuccess) return cleanup(RAFT_E_DEVICE, "batch packing failed");
+    // pinned poll buffers
+    BatchLayout B;
+    batch_layout(b, nullptr, nullptr, B);
+    b->dyn_bytes = B.ctl_upload - B.off_dyn;
+    b->flag_bytes = sizeof(int32_t) * (size_t)G * B.Kc;
+    if (hipHostMalloc((void**)&b->h_poll, 2 * (b->dyn_bytes + b->flag_bytes),
+                      hipHostMallocDefault) != hipSuccess)
+        return cleanup(RAFT_E_NOMEM, "pinned poll buffer");
+    for (auto& ev : b->poll_ev)
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+            return cleanup(RAFT_E_DEVICE, "event creation failed");
+    for (auto& ev : b->ev)
+        if (hipEventCreate(&ev) != hipSuccess) return cleanup(RAFT_E_DEVICE, "event creation failed");
+    *out = b;
+    return RAFT_OK;
+}
+
+void raft_batch_destroy(raft_batch* b) {
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    for (auto& ev : b->poll_ev)
+        if (ev) (void)hipEventDestroy(ev);
+    for (auto& ev : b->ev)
+        if (ev) (void)hipEventDestroy(ev);
+    if (b->h_poll) (void)hipHostFree(b->h_poll);
+    int32_t* ip[] = {b->rp, b->ci, b->deg, b->order};
+    for (int32_t* q : ip)
+        if (q) (void)hipFree(q);
+    float* fp[] = {b->s, b->sh, b->dcoef};
+    for (float* q : fp)
+        if (q) (void)hipFree(q);
+    delete b;
+}
+
+raft_status raft_batch_workspace_size(raft_ctx* ctx, const raft_batch* b, size_t* bytes) {
+    if (!ctx) return RAFT_E_INVAL;
+    if (!b || !bytes) return fail(ctx, RAFT_E_INVAL, "null argument");
+    if (b->ctx != ctx) return fail(ctx, RAFT_E_INVAL, "batch belongs to another context");
+    BatchLayout B;
+    batch_layout(const_cast<raft_batch*>(b), nullptr, nullptr, B);
+    *bytes = B.bytes;
+    return RAFT_OK;
+}
+
+raft_status raft_batch_set_capture(raft_batch* b, int32_t enable) {
+    if (!b) return RAFT_E_INVAL;
+    b->use_graph = enable != 0;
+    return RAFT_OK;
+}
+
+raft_status raft_batch_run(raft_ctx* ctx, raft_batch* b, void* ws, size_t ws_bytes,
+                           raft_outputs* outs, void* stream) {
+    if (!ctx) return RAFT_E_INVAL;
+    if (!b) return fail(ctx, RAFT_E_INVAL, "batch is null");
+    if (b->ctx != ctx) return fail(ctx, RAFT_E_INVAL, "batch belongs to another context");
+    const int G = b->G;
+    const raft_config* c = &b->cfg;
+    BatchLayout B;
+    batch_layout(b, nullptr, nullptr, B);
+    RAFT_TRY(check_ws(ctx, ws, ws_bytes, B.bytes));
+    batch_layout(b, reinterpret_cast<char*>(ws), outs, B);
+    RAFT_TRY(batch_check(ctx, b, B, ws_bytes));
+    hipStream_t st = as_stream(stream);
+    // control block: static part and the initial dynamic part
+    {
+        std::vector<int> live(G, 1);
+        batch_dynamic(b, B, B.host.data() + B.off_dyn, live);
+        HIP_TRY(ctx, hipMemcpyAsync(B.ctl, B.host.data(), B.ctl_upload, hipMemcpyHostToDevice, st));
+        HIP_TRY(ctx, hipStreamSynchronize(st));   // pageable source
+        // both pinned slots start from this image (the last run ended with a
+        // synchronisation, so no copy from them is in flight)
+        for (int q = 0; q < 2; ++q)
+            memcpy(b->h_poll + q * b->dyn_bytes, B.host.data() + B.off_dyn, b->dyn_bytes);
+    }
+    HIP_TRY(ctx, hipEventRecord(b->ev[0], st));
+    if (b->use_graph) {
+        if (!b->exec || b->exec_ws != ws) {
+            if (b->exec) (void)hipGraphExecDestroy(b->exec);
+            if (b->graph) (void)hipGraphDestroy(b->graph);
+            b->exec = nullptr;
+            b->graph = nullptr;
+            HIP_TRY(ctx, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed));
+            const raft_status ps = batch_prefix(b, B, b->cap_stream);
+            hipGraph_t gr = nullptr;
+            const hipError_t ce = hipStreamEndCapture(b->cap_stream, &gr);
+            if (ps != RAFT_OK) {
+                if (gr) (void)hipGraphDestroy(gr);
+                return ps;
+            }
+            if (ce != hipSuccess)
+                return fail(ctx, RAFT_E_DEVICE, "graph capture: %s", hipGetErrorString(ce));
+            b->graph = gr;
+            HIP_TRY(ctx, hipGraphInstantiate(&b->exec, gr, nullptr, nullptr, 0));
+            b->exec_ws = ws;
+        }
+        HIP_TRY(ctx, hipGraphLaunch(b->exec, st));
+    } else {
+        RAFT_TRY(batch_prefix(b, B, st));
+    }
+    HIP_TRY(ctx, hipEventRecord(b->ev[1], st));
+    // Lloyd over every candidate of every graph: one launch per kernel and
+    // iteration; convergence polls as in the single-graph loop (the host acts
+    // on the flags of the previous poll), with all graphs' flags in one copy
+    char* D = B.ctl;
+    const KmeansPlan* kmd = at<KmeansPlan>(D, B.off_km);
+    const int d = B.d;
+    const bool split = B.P[0].km.split != 0;
+    const size_t ulds = kmeans_update_lds(B.P[0].ucap, d);
+    const int t_max = c->kmeans_max_iter;
+    const int check = c->check_every > 0 ? c->check_every : 4;
+    const Grid grid = make_grid(c->k_min, c->k_max, c->k_step);
+    char* h_dyn[2] = {b->h_poll, b->h_poll + b->dyn_bytes};
+    int32_t* h_flags[2] = {reinterpret_cast<int32_t*>(b->h_poll + 2 * b->dyn_bytes),
+                           reinterpret_cast<int32_t*>(b->h_poll + 2 * b->dyn_bytes + b->flag_bytes)};
+    std::vector<int> live(G, 1);
+    int poll = 0;
+    for (int it = 1; it <= t_max; ++it) {
+        launch_kmeans_batched(kKmAssign, kmd, d, split, B.Zp, it, t_max, ctx->lds_max, ulds,
+                              dev_table(D, B.tab_assign, G), B.tab_assign.grid, st);
+        if (it == t_max) {
+            launch_kmeans_batched(kKmFinalize, kmd, d, split, B.Zp, it, t_max, 0, 0,
+                                  dev_table(D, B.tab[bt_one], G), B.tab[bt_one].grid, st);
+            break;
+        }
+        launch_kmeans_batched(kKmUpdate, kmd, d, split, B.Zp, it, t_max, ctx->lds_max, ulds,
+                              dev_table(D, B.tab_update, G), B.tab_update.grid, st);
+        launch_kmeans_batched(kKmUpdateFinish, kmd, d, split, B.Zp, it, t_max, 0, 0,
+                              dev_table(D, B.tab[bt_ufinish], G), B.tab[bt_ufinish].grid, st);
+        if (it % check == 0) {
+            if (poll > 0) {
+                HIP_TRY(ctx, hipEventSynchronize(b->poll_ev[(poll - 1) & 1]));
+                const int32_t* ha = h_flags[(poll - 1) & 1];
+                int total = 0;
+                for (int g = 0; g < G; ++g) {
+                    const int32_t* hg = ha + (size_t)g * B.Kc;
+                    int lg = 0;
+                    for (int k = 0; k < B.Kc; ++k) lg += hg[k] != 0;
+                    live[g] = lg;
+                    total += lg;
+                }
+                if (total == 0) break;
+                char* hd = h_dyn[poll & 1];
+                int32_t* hl = reinterpret_cast<int32_t*>(hd + (B.off_lists - B.off_dyn));
+                for (int g = 0; g < G; ++g) {
+                    if (!live[g]) continue;
+                    const Lists l = make_lists(grid, ha + (size_t)g * B.Kc, B.P[g].ucap,
+                                               b->shadow[g].n, ctx->num_cu);
+                    pack_lists(l, B.Kc, hl + (size_t)g * kDynLen(B.Kc));
+                    B.km[g].agroups = (int)l.agrp.size() - 1;
+                    B.km[g].ugroups = (int)l.ugrp.size() - 1;
+                    B.km[g].uwork = l.uwork;
+                }
+                // a stopped graph keeps the lists the slot held (no kernel
+                // reads them: its assignment and update get no work-groups)
+                batch_dynamic(b, B, hd, live);
+                HIP_TRY(ctx, hipMemcpyAsync(D + B.off_dyn, hd, b->dyn_bytes, hipMemcpyHostToDevice,
+                                            st));
+            }
+            HIP_TRY(ctx, hipMemcpyAsync(h_flags[poll & 1], D + B.off_flags, b->flag_bytes,
+                                        hipMemcpyDeviceToHost, st));
+            HIP_TRY(ctx, hipEventRecord(b->poll_ev[poll & 1], st));
+            ++poll;
+        }
+    }
+    RAFT_TRY(launch_check(ctx));
+    HIP_TRY(ctx, hipEventRecord(b->ev[2], st));
+    // scores, selection and outputs of every graph
+    const GraphView* gvd = at<GraphView>(D, B.off_gv);
+    const ScorePlan* scd = at<ScorePlan>(D, B.off_sc);
+    const int sk[] = {bt_transpose, bt_edge, bt_reduce, bt_sfinal, bt_one, bt_first, bt_one,
+                      bt_apply, bt_copy};
+    const int kinds[] = {kScTranspose, kScEdge, kScReduce, kScFinalize, kScSelect, kScFirst,
+                         kScRank, kScApply, kScCopy};
+    for (int q = 0; q < 9; ++q)
+        launch_score_batched(kinds[q], gvd, scd, B.S, B.SK, dev_table(D, B.tab[sk[q]], G),
+                             B.tab[sk[q]].grid, st);
+    for (int g = 0; g < G && outs; ++g) {
+        const size_t r0 = (size_t)b->base[g];
+        const size_t n = (size_t)b->shadow[g].n;
+        if (outs[g].Y)
+            HIP_TRY(ctx, hipMemcpyAsync(outs[g].Y, B.YO + r0 * B.L, n * B.L * sizeof(float),
+                                        hipMemcpyDeviceToDevice, st));
+        if (outs[g].Z)
+            HIP_TRY(ctx, hipMemcpyAsync(outs[g].Z, B.Zp + r0 * d, n * d * sizeof(float),
+                                        hipMemcpyDeviceToDevice, st));
+        if (outs[g].centres) launch_copy_centres(B.km[g], outs[g].centres, st);
+    }
+    RAFT_TRY(launch_check(ctx));
+    HIP_TRY(ctx, hipEventRecord(b->ev[3], st));
+    HIP_TRY(ctx, hipEventSynchronize(b->ev[3]));
+    float ms = 0;
+    for (int s2 = 0; s2 < 3; ++s2)
+        if (hipEventElapsedTime(&ms, b->ev[s2], b->ev[s2 + 1]) == hipSuccess) b->stage_ms[s2] = ms;
+    return RAFT_OK;
+}
+
+raft_status raft_batch_plan_check(int32_t G, const int32_t* n, const int64_t* nnz,
+                                  const raft_config* cfg, int32_t num_cu, char* msg,
+                                  size_t msg_len) {
+    if (G < 1 || !n || !nnz || !cfg || num_cu < 1) return RAFT_E_INVAL;
+    raft_ctx ctx;
+    ctx.num_cu = num_cu;
+    raft_status st = check_config(&ctx, nullptr, cfg);
+    raft_batch b;
+    b.ctx = &ctx;
+    b.G = G;
+    b.cfg = *cfg;
+    b.shadow.resize(G);
+    b.seeds.assign(G, cfg->seed);
+    b.base.resize(G);
+    b.ebase.resize(G);
+    int64_t r = 0, e = 0;
+    for (int g = 0; g < G && st == RAFT_OK; ++g) {
+        if (n[g] < 1 || nnz[g] < 1 || cfg->k_max > n[g]) st = RAFT_E_INVAL;
+        b.shadow[g].n = n[g];
+        b.shadow[g].nnz = nnz[g];
+        b.base[g] = (int32_t)r;
+        b.ebase[g] = e;
+        r += n[g];
+        e += nnz[g];
+    }
+    if (st == RAFT_OK && (r >= INT32_MAX || e >= INT32_MAX)) st = RAFT_E_UNSUPPORTED;
+    if (st == RAFT_OK) {
+        b.N = (int32_t)r;
+        b.NNZ = e;
+        // stand-in addresses: the check only compares ranges
+        b.rp = b.ci = b.deg = b.order = reinterpret_cast<int32_t*>((uintptr_t)1 << 44);
+        b.s = b.sh = b.dcoef = reinterpret_cast<float*>((uintptr_t)1 << 44);
+        BatchLayout B;
+        batch_layout(&b, nullptr, nullptr, B);
+        const size_t bytes = B.bytes;
+        BatchLayout B2;
+        char* fake = reinterpret_cast<char*>((uintptr_t)1 << 40);
+        batch_layout(&b, fake, nullptr, B2);
+        std::vector<int> live(G, 1);
+        std::vector<char> dyn(B2.ctl_upload - B2.off_dyn);
+        batch_dynamic(&b, B2, dyn.data(), live);
+        st = batch_check(&ctx, &b, B2, bytes);
+    }
+    if (msg && msg_len) {
+        const size_t m = std::min(msg_len - 1, ctx.err.size());
+        memcpy(msg, ctx.err.data(), m);
+        msg[m] = 0;
+    }
+    b.rp = b.ci = b.deg = b.order = nullptr;
+    b.s = b.sh = b.dcoef = nullptr;
+    return st;
+}
+
+raft_status raft_batch_stage_times(const raft_batch* b, double* ms3) {
+    if (!b || !ms3) return RAFT_E_INVAL;
+    for (int s2 = 0; s2 < 3; ++s2) ms3[s2] = b->stage_ms[s2];
     return RAFT_OK;
 }
 

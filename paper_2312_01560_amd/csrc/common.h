@@ -20,6 +20,45 @@ constexpr int kStatusLabel = 1 << 9;
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Position of a work-group within the share of a launch that one partition
+// owns: index x of n.  A single-graph launch passes (blockIdx.x, gridDim.x);
+// a batched launch over several graphs maps each block to its graph first.
+struct Wg {
+    uint32_t x, n;
+};
+
+__device__ __forceinline__ Wg wg_self() { return Wg{blockIdx.x, gridDim.x}; }
+
+// Table of a batched launch: graph g owns blocks [start[g], start[g] +
+// count[g]) of the grid; start[g] is a multiple of 8, so a block's XCD
+// (blockIdx.x mod 8) is that of its local index, and the padding blocks
+// between count[g] and start[g + 1] exit at once.  start holds G + 1 entries
+// (the last is the grid size).
+struct BatchTable {
+    const int32_t* start;
+    const int32_t* count;
+    int32_t G;
+};
+
+// Graph g of this block (the last g with start[g] <= blockIdx.x) and its
+// local position; false for a padding block.
+__device__ __forceinline__ bool batch_find(const BatchTable& t, int& g, Wg& w) {
+    const int b = (int)blockIdx.x;
+    int lo = 0, hi = t.G - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (t.start[mid] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    g = lo;
+    const int x = b - t.start[lo];
+    w.x = (uint32_t)x;
+    w.n = (uint32_t)t.count[lo];
+    return x >= 0 && x < t.count[lo];
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll

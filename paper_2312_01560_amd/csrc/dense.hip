@@ -16,17 +16,16 @@ namespace raft {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 template <int LIN, int LOUT, bool LINEAR>
-__global__ __launch_bounds__(256) void k_dense(const float* __restrict__ P,
-                                               const float* __restrict__ W,
-                                               float* __restrict__ H, int n,
-                                               int32_t* __restrict__ status) {
+__device__ __forceinline__ void dense_body(const float* __restrict__ P,
+                                           const float* __restrict__ W, float* __restrict__ H,
+                                           int n, int32_t* __restrict__ status, int bx) {
     constexpr int KS = LIN / 4;
     constexpr int NB = LOUT / 16;
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
     const int g = lane >> 4;
     const int li = lane & 15;
-    const int row0 = (blockIdx.x * 4 + wid) * 16;
+    const int row0 = (bx * 4 + wid) * 16;
     if (row0 >= n) return;
     const int ra = min(row0 + li, n - 1);
     float a[KS];
@@ -82,9 +81,29 @@ __global__ __launch_bounds__(256) void k_dense(const float* __restrict__ P,
     }
 }
 
+template <int LIN, int LOUT, bool LINEAR>
+__global__ __launch_bounds__(256) void k_dense(const float* __restrict__ P,
+                                               const float* __restrict__ W,
+                                               float* __restrict__ H, int n,
+                                               int32_t* __restrict__ status) {
+    dense_body<LIN, LOUT, LINEAR>(P, W, H, n, status, (int)blockIdx.x);
+}
+
+// Batched: each graph's rows with its own W (one 64-row block never holds
+// two graphs' rows).
+template <int LIN, int LOUT, bool LINEAR>
+__global__ __launch_bounds__(256) void k_dense_b(const DenseItem* __restrict__ items,
+                                                 int32_t* __restrict__ status, BatchTable t) {
+    int gi;
+    Wg w;
+    if (!batch_find(t, gi, w)) return;
+    const DenseItem& it = items[gi];
+    dense_body<LIN, LOUT, LINEAR>(it.P, it.W, it.H, it.n, status, (int)w.x);
+}
+
 // Row L2 normalisation, one wave per row, lanes over columns.
-__global__ __launch_bounds__(256) void k_rownorm(float* __restrict__ x, int n, int L) {
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+__device__ __forceinline__ void rownorm_body(float* __restrict__ x, int n, int L, int bx) {
+    const int wave = (bx * blockDim.x + threadIdx.x) / kWave;
     const int lane = threadIdx.x & (kWave - 1);
     if (wave >= n) return;
     float* row = x + (size_t)wave * L;
@@ -93,6 +112,19 @@ __global__ __launch_bounds__(256) void k_rownorm(float* __restrict__ x, int n, i
     ss = wave_sum(ss);
     const float inv = 1.0f / fmaxf(sqrtf(ss), 1e-12f);
     for (int c = lane; c < L; c += kWave) row[c] *= inv;
+}
+
+__global__ __launch_bounds__(256) void k_rownorm(float* __restrict__ x, int n, int L) {
+    rownorm_body(x, n, L, (int)blockIdx.x);
+}
+
+// Batched row normalisation: item.H (rows n of width L) of each graph.
+__global__ __launch_bounds__(256) void k_rownorm_b(const DenseItem* __restrict__ items, int L,
+                                                   BatchTable t) {
+    int gi;
+    Wg w;
+    if (!batch_find(t, gi, w)) return;
+    rownorm_body(items[gi].H, items[gi].n, L, (int)w.x);
 }
 
 static bool pow2_width(int v) { return v == 16 || v == 32 || v == 64 || v == 128 || v == 256; }
@@ -111,6 +143,55 @@ static void dense_launch2(const float* P, const float* W, float* H, int32_t n, b
     else
         hipLaunchKernelGGL((k_dense<LIN, LOUT, false>), dim3(grid), dim3(256), 0, st, P, W, H, n,
                            status);
+}
+
+template <int LIN, int LOUT>
+static void dense_batched2(const DenseItem* items, bool linear, int32_t* status,
+                           const BatchTable& t, int grid, hipStream_t st) {
+    if (linear)
+        hipLaunchKernelGGL((k_dense_b<LIN, LOUT, true>), dim3(grid), dim3(256), 0, st, items,
+                           status, t);
+    else
+        hipLaunchKernelGGL((k_dense_b<LIN, LOUT, false>), dim3(grid), dim3(256), 0, st, items,
+                           status, t);
+}
+
+template <int LIN>
+static void dense_batched1(const DenseItem* items, int lout, bool linear, int32_t* status,
+                           const BatchTable& t, int grid, hipStream_t st) {
+    switch (lout) {
+        case 16: dense_batched2<LIN, 16>(items, linear, status, t, grid, st); break;
+        case 32: dense_batched2<LIN, 32>(items, linear, status, t, grid, st); break;
+        case 64: dense_batched2<LIN, 64>(items, linear, status, t, grid, st); break;
+        case 128: dense_batched2<LIN, 128>(items, linear, status, t, grid, st); break;
+        case 256:
+            if constexpr (LIN <= 128) dense_batched2<LIN, 256>(items, linear, status, t, grid, st);
+            break;
+        default: break;
+    }
+}
+
+int dense_blocks(int32_t n) { return (n + 63) / 64; }
+
+void launch_dense_layer_batched(const DenseItem* items, int lin, int lout, bool linear,
+                                int32_t* status, const BatchTable& t, int grid, hipStream_t st) {
+    if (grid == 0) return;
+    switch (lin) {
+        case 16: dense_batched1<16>(items, lout, linear, status, t, grid, st); break;
+        case 32: dense_batched1<32>(items, lout, linear, status, t, grid, st); break;
+        case 64: dense_batched1<64>(items, lout, linear, status, t, grid, st); break;
+        case 128: dense_batched1<128>(items, lout, linear, status, t, grid, st); break;
+        case 256: dense_batched1<256>(items, lout, linear, status, t, grid, st); break;
+        default: break;
+    }
+}
+
+int rownorm_blocks(int32_t n) { return (int)(((int64_t)n * kWave + 255) / 256); }
+
+void launch_rownorm_batched(const DenseItem* items, int L, const BatchTable& t, int grid,
+                            hipStream_t st) {
+    if (grid == 0) return;
+    hipLaunchKernelGGL(k_rownorm_b, dim3(grid), dim3(256), 0, st, items, L, t);
 }
 
 template <int LIN>

@@ -7,10 +7,9 @@
 
 namespace raft {
 
-__global__ __launch_bounds__(256) void k_gaussian(uint64_t seed, uint64_t stream, int64_t rows,
-                                                  int64_t cols, int64_t cblocks, double sigma,
-                                                  float* __restrict__ out) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void gaussian_body(uint64_t seed, uint64_t stream, int64_t rows,
+                                              int64_t cols, int64_t cblocks, double sigma,
+                                              float* __restrict__ out, int64_t idx) {
     if (idx >= rows * cblocks) return;
     const int64_t row = idx / cblocks;
     const int64_t cb = idx - row * cblocks;
@@ -35,6 +34,34 @@ __global__ __launch_bounds__(256) void k_gaussian(uint64_t seed, uint64_t stream
     } else {
         for (int t = 0; t < 4 && c0 + t < cols; ++t) o[t] = v[t];
     }
+}
+
+__global__ __launch_bounds__(256) void k_gaussian(uint64_t seed, uint64_t stream, int64_t rows,
+                                                  int64_t cols, int64_t cblocks, double sigma,
+                                                  float* __restrict__ out) {
+    gaussian_body(seed, stream, rows, cols, cblocks, sigma, out,
+                  (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_gaussian_b(const GaussItem* __restrict__ items,
+                                                    BatchTable t) {
+    int g;
+    Wg w;
+    if (!batch_find(t, g, w)) return;
+    const GaussItem it = items[g];
+    const int64_t cb = (it.cols + 3) / 4;
+    gaussian_body(it.seed, it.stream, it.rows, it.cols, cb, it.sigma, it.out,
+                  (int64_t)w.x * blockDim.x + threadIdx.x);
+}
+
+int gaussian_blocks(int64_t rows, int64_t cols) {
+    return (int)((rows * ((cols + 3) / 4) + 255) / 256);
+}
+
+void launch_gaussian_batched(const GaussItem* items, const BatchTable& t, int grid,
+                             hipStream_t st) {
+    if (grid == 0) return;
+    hipLaunchKernelGGL(k_gaussian_b, dim3(grid), dim3(256), 0, st, items, t);
 }
 
 void launch_gaussian(uint64_t seed, uint64_t stream_id, int64_t rows, int64_t cols, double sigma,

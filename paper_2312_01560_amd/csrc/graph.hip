@@ -75,4 +75,21 @@ void launch_degrees(const int32_t* rp, int32_t n, int64_t nnz, int32_t* deg, flo
                        dcoef);
 }
 
+// dst[i] = src[i] + add (packing graphs into one block-diagonal CSR: row
+// pointers shifted by the stored entries before the graph, column ids and
+// row orders by the rows before it).
+__global__ __launch_bounds__(256) void k_offset_copy(const int32_t* __restrict__ src,
+                                                     int32_t* __restrict__ dst, int64_t n,
+                                                     int32_t add) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i] + add;
+}
+
+void launch_offset_copy(const int32_t* src, int32_t* dst, int64_t n, int32_t add,
+                        hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_offset_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst,
+                       n, add);
+}
+
 }  // namespace raft

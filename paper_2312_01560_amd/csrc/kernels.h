@@ -14,10 +14,24 @@ void launch_validate_csr(const int32_t* rp, const int32_t* ci, int32_t n, int32_
                          int num_cu, hipStream_t st);
 void launch_degrees(const int32_t* rp, int32_t n, int64_t nnz, int32_t* deg, float* s, float* sh,
                     float* dcoef, hipStream_t st);
+void launch_offset_copy(const int32_t* src, int32_t* dst, int64_t n, int32_t add, hipStream_t st);
 
 // ---- gauss.hip -----------------------------------------------------------
 void launch_gaussian(uint64_t seed, uint64_t stream_id, int64_t rows, int64_t cols, double sigma,
                      float* out, hipStream_t st);
+
+// Batched launches (many graphs in one launch) take per-graph items in device
+// memory and a BatchTable (common.h) whose counts come from the *_blocks
+// functions below.
+struct GaussItem {
+    uint64_t seed, stream;
+    int64_t rows, cols;
+    double sigma;
+    float* out;
+};
+int gaussian_blocks(int64_t rows, int64_t cols);
+void launch_gaussian_batched(const GaussItem* items, const BatchTable& t, int grid,
+                             hipStream_t st);
 
 // ---- spmm.hip ------------------------------------------------------------
 enum SpmmOp { kOpNcut = 0, kOpModFull = 1, kOpModReduced = 2, kOpGcn = 3 };
@@ -32,6 +46,11 @@ struct GraphView {
     const float* sh;     // (D+1)^-1/2
     const float* dcoef;  // d_i / 2e
     const int32_t* order;  // [n] rows by degree class, heaviest first (row-split schedules)
+    // Global id of the graph's node 0: 0 for a graph on its own; in a batch,
+    // where the graphs form one block-diagonal CSR, the graph's first row.
+    // rp, ci, order and the per-node arrays hold global ids; kernels that walk
+    // the graph's rows by local index add base.
+    int32_t base = 0;
 };
 
 // Grid size (work-groups) of one SpMM launch; colsum partial buffers hold
@@ -51,6 +70,31 @@ constexpr int kColsumStageRows = 64;
 void launch_colsum_finish(const double* part, int parts, int L, double* c64, float* cvec,
                           hipStream_t st);
 
+// Grid of one graph's SpMM launch; R = rows per row block, nrb = row blocks.
+int spmm_launch_shape(int32_t n, int L, int num_cu, int* R, int* nrb);
+struct SpmmItem {
+    GraphView g;
+    const float* cvec;   // MOD_FULL: the graph's FP32 d^T x
+    double* cpart;       // the graph's colsum partials (with the epilogue)
+    int32_t R, nrb;
+};
+void launch_spmm_batched(const SpmmItem* items, int op, int L, const float* x, float* y, bool cs,
+                         const BatchTable& t, int grid, hipStream_t st);
+struct ColsumItem {
+    GraphView g;
+    double* part;        // [parts + kColsumStageRows] x L
+    int32_t parts, rpw;
+    double* c64;
+    float* cvec;
+};
+void launch_colsum_partials_batched(const ColsumItem* items, int L, const float* x,
+                                    const BatchTable& t, int grid, hipStream_t st);
+// kColsumSlices blocks per graph (t_slices), then one per graph (t_one).
+void launch_colsum_finish_batched(const ColsumItem* items, int L, const BatchTable& t_slices,
+                                  int grid_slices, const BatchTable& t_one, int grid_one,
+                                  hipStream_t st);
+constexpr int kColsumSliceBlocks = 64;
+
 // ---- dense.hip -----------------------------------------------------------
 bool dense_supported(int lin, int lout);
 // H = rownorm(tanh(P W)) (or U = P W when linear), P [n x lin], W [lin x lout].
@@ -58,6 +102,20 @@ void launch_dense_layer(const float* P, const float* W, float* H, int32_t n, int
                         bool linear, int32_t* status, hipStream_t st);
 // Row L2 normalisation in place (x / max(||x||, 1e-12)).
 void launch_rownorm(float* x, int32_t n, int L, hipStream_t st);
+
+struct DenseItem {
+    const float* P;      // [n x lin] (the graph's rows)
+    const float* W;      // [lin x lout] (the graph's own weights)
+    float* H;            // [n x lout]
+    int32_t n;
+};
+int dense_blocks(int32_t n);
+void launch_dense_layer_batched(const DenseItem* items, int lin, int lout, bool linear,
+                                int32_t* status, const BatchTable& t, int grid, hipStream_t st);
+int rownorm_blocks(int32_t n);
+// Normalises items[g].H (n rows of width L) in place.
+void launch_rownorm_batched(const DenseItem* items, int L, const BatchTable& t, int grid,
+                            hipStream_t st);
 
 // ---- kmeans.hip ----------------------------------------------------------
 struct KmeansPlan {
@@ -113,6 +171,8 @@ struct KmeansPlan {
     int32_t nchunks;         // ceil(n / 64)
     int32_t it;              // Lloyd iteration of the launch (1-based)
     int32_t* status;
+    uint64_t seed;           // Philox key word 0 of the race
+    int32_t zoff = 0;        // in a batch: first row of the graph's points in the packed Z
 };
 
 bool kmeans_supported(int d);
@@ -127,7 +187,7 @@ void launch_kmeans_reset(const KmeansPlan& p, hipStream_t st);
 void launch_zmax(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t st);
 // Pick t of the race (launch t resolves pick t-1; the launch of the last
 // pick also resolves it).
-void launch_race_pick(const KmeansPlan& p, const float* Z, int t, uint64_t seed, hipStream_t st);
+void launch_race_pick(const KmeansPlan& p, const float* Z, int t, hipStream_t st);
 void launch_init_centres(const KmeansPlan& p, const float* Z, hipStream_t st);
 void launch_assign(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t st);
 // Split-fp16 assignment is available for d multiple of 32.
@@ -141,6 +201,18 @@ void launch_update(const KmeansPlan& p, const float* Z, size_t lds_max, int it, 
                    hipStream_t st);
 // Real centre rows of every candidate, compacted: out [SK x d] (grid order).
 void launch_copy_centres(const KmeansPlan& p, float* out, hipStream_t st);
+
+// Launch kinds of the k-means stage, their grid per graph, and the batched
+// launch of one kind over all graphs (`it` is the pick index for kKmRace and
+// the Lloyd iteration otherwise).
+enum KmeansKind {
+    kKmReset, kKmZmax, kKmSplit, kKmRace, kKmRaceFinal, kKmInit, kKmAssign, kKmFinalize,
+    kKmUpdate, kKmUpdateFinish, kKmKinds
+};
+int kmeans_blocks(const KmeansPlan& p, int kind, int num_cu);
+void launch_kmeans_batched(int kind, const KmeansPlan* plans, int d, bool split, const float* Z,
+                           int it, int t_max, size_t lds_max, size_t update_lds,
+                           const BatchTable& t, int grid, hipStream_t st);
 
 // ---- score.hip -----------------------------------------------------------
 struct ScorePlan {
@@ -160,6 +232,12 @@ struct ScorePlan {
     int32_t* first;       // [RAFT_MAX_K + 1]
     int32_t* remap;       // [RAFT_MAX_K + 1]
     int32_t* status;
+    // batched launches only (a single graph passes these as arguments)
+    uint8_t* lab = nullptr;              // [n x S] point-major labels of the graph
+    const uint8_t* lab_cm = nullptr;     // [Kc x n] candidate-major labels (k-means)
+    int32_t* ksel_out = nullptr;         // [3] K*, K_eff, index of K*
+    int32_t* labels_out = nullptr;       // [n] canonical labels of K* (nullable)
+    uint8_t* labels_all_out = nullptr;   // [n x Kc] (nullable)
 };
 
 int score_grid(int32_t n, int num_cu);
@@ -174,6 +252,16 @@ void launch_select(const ScorePlan& p, const uint8_t* lab_pm, int32_t* labels_ou
                    int32_t* k_selected, hipStream_t st);
 // Copy point-major labels [n x S] into a dense [n x Kc] output.
 void launch_copy_labels(const uint8_t* pm, int32_t n, int Kc, int S, uint8_t* out, hipStream_t st);
+
+// Launch kinds of the score stage, their grid per graph, and the batched
+// launch of one kind over all graphs (S, SK: shared by every graph).
+enum ScoreKind {
+    kScTranspose, kScEdge, kScReduce, kScFinalize, kScSelect, kScFirst, kScRank, kScApply,
+    kScCopy, kScKinds
+};
+int score_blocks(const ScorePlan& p, int kind);
+void launch_score_batched(int kind, const GraphView* views, const ScorePlan* plans, int S, int SK,
+                          const BatchTable& t, int grid, hipStream_t st);
 
 // ---- confusion.hip -------------------------------------------------------
 // counts [ka x kb] int64 (zeroed here) = joint histogram of labels a, b [n];

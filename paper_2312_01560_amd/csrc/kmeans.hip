@@ -61,7 +61,7 @@ __device__ __forceinline__ bool lex_less(double v, int i, double bv, int bi) {
 // work-group): no launch needs a grid-wide "last work-group" step.
 // Work-group 0 records the pick.  If every weight was zero, the lowest index
 // not picked yet.
-__device__ int race_resolve(const KmeansPlan& p, int t) {
+__device__ int race_resolve(const KmeansPlan& p, int t, int bx) {
     __shared__ double sv[kRaceThreads / kWave];
     __shared__ int si[kRaceThreads / kWave];
     __shared__ int pick;
@@ -111,7 +111,7 @@ __device__ int race_resolve(const KmeansPlan& p, int t) {
             }
         }
         pick = bi;
-        if (blockIdx.x == 0) p.picks[t] = bi;
+        if (bx == 0) p.picks[t] = bi;
     }
     __syncthreads();
     return pick;
@@ -120,10 +120,11 @@ __device__ int race_resolve(const KmeansPlan& p, int t) {
 // Launch t: resolves pick t-1, updates the weights with the distances to it
 // and writes this work-group's minimum of E / w for pick t.
 template <int D>
-__global__ __launch_bounds__(kRaceThreads) void k_race(KmeansPlan p, const float* __restrict__ Z,
-                                                       int t, uint64_t seed) {
-    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-    const int stride = gridDim.x * blockDim.x;
+__device__ __forceinline__ void race_body(const KmeansPlan& p, const float* __restrict__ Z, int t,
+                                          Wg w) {
+    const uint64_t seed = p.seed;
+    const int tid = (int)w.x * blockDim.x + threadIdx.x;
+    const int stride = (int)w.n * blockDim.x;
     // Odd picks sweep from the last point: the end of Z, read last by the
     // previous pick, is still in the memory-side cache (the result does not
     // depend on the order: ties go to the lowest index).
@@ -146,7 +147,7 @@ __global__ __launch_bounds__(kRaceThreads) void k_race(KmeansPlan p, const float
             if (t > 1) wpre[k] = p.w[i];
         }
     }
-    const int prev = t > 0 ? race_resolve(p, t - 1) : -1;
+    const int prev = t > 0 ? race_resolve(p, t - 1, (int)w.x) : -1;
     double best = INFINITY;
     int bidx = INT_MAX;
     const float* zp = prev >= 0 ? Z + (size_t)prev * D : Z;
@@ -214,21 +215,48 @@ __global__ __launch_bounds__(kRaceThreads) void k_race(KmeansPlan p, const float
                 b = sv[w];
                 bi = si[w];
             }
-        p.race_val[(size_t)(t & 1) * p.race_grid + blockIdx.x] = b;
-        p.race_idx[(size_t)(t & 1) * p.race_grid + blockIdx.x] = bi;
+        p.race_val[(size_t)(t & 1) * p.race_grid + w.x] = b;
+        p.race_idx[(size_t)(t & 1) * p.race_grid + w.x] = bi;
     }
+}
+
+template <int D>
+__global__ __launch_bounds__(kRaceThreads) void k_race(KmeansPlan p, const float* __restrict__ Z,
+                                                       int t) {
+    race_body<D>(p, Z, t, wg_self());
+}
+
+// Batched: pick t of every graph (its points are rows zoff.. of the packed Z).
+template <int D>
+__global__ __launch_bounds__(kRaceThreads) void k_race_b(const KmeansPlan* __restrict__ plans,
+                                                         const float* __restrict__ Z, int t,
+                                                         BatchTable tb) {
+    int gi;
+    Wg w;
+    if (!batch_find(tb, gi, w)) return;
+    const KmeansPlan& p = plans[gi];
+    race_body<D>(p, Z + (size_t)p.zoff * D, t, w);
 }
 
 // The last pick (one work-group).
 __global__ __launch_bounds__(kRaceThreads) void k_race_final(KmeansPlan p) {
-    (void)race_resolve(p, p.k_max - 1);
+    (void)race_resolve(p, p.k_max - 1, 0);
+}
+
+__global__ __launch_bounds__(kRaceThreads) void k_race_final_b(
+    const KmeansPlan* __restrict__ plans, BatchTable tb) {
+    int gi;
+    Wg w;
+    if (!batch_find(tb, gi, w)) return;
+    (void)race_resolve(plans[gi], plans[gi].k_max - 1, 0);
 }
 
 // Copy the first K picks of every candidate into its centre rows; padding
 // rows are zero with norm +inf.  One wave per padded centre row.
 template <int D>
-__global__ __launch_bounds__(256) void k_init_centres(KmeansPlan p, const float* __restrict__ Z) {
-    const int c = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+__device__ __forceinline__ void init_centres_body(const KmeansPlan& p, const float* __restrict__ Z,
+                                                  int bx) {
+    const int c = (bx * blockDim.x + threadIdx.x) / kWave;
     const int lane = threadIdx.x & (kWave - 1);
     if (c >= p.KP) return;
     const int k = p.cand_of[c];
@@ -256,6 +284,22 @@ __global__ __launch_bounds__(256) void k_init_centres(KmeansPlan p, const float*
     }
     ss = wave_sum(ss);
     if (lane == 0) p.cnorm[c] = ss;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_init_centres(KmeansPlan p, const float* __restrict__ Z) {
+    init_centres_body<D>(p, Z, (int)blockIdx.x);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_init_centres_b(const KmeansPlan* __restrict__ plans,
+                                                        const float* __restrict__ Z,
+                                                        BatchTable tb) {
+    int gi;
+    Wg w;
+    if (!batch_find(tb, gi, w)) return;
+    const KmeansPlan& p = plans[gi];
+    init_centres_body<D>(p, Z + (size_t)p.zoff * D, (int)w.x);
 }
 
 // Assignment for all active candidates of one candidate group.
@@ -288,16 +332,15 @@ __device__ __forceinline__ void load_ctile(const KmeansPlan& p, int cb, int li, 
 // multiple of 8 and padding blocks exit.  Otherwise the point tile varies
 // fastest, which keeps a group's centre tiles hot (9 % faster at N = 50k,
 // where all points stay cached).
-__device__ __forceinline__ int assign_group(const KmeansPlan& p) {
-    if (p.group_major) return (int)((blockIdx.x >> 3) % (unsigned)p.agroups);
-    const int tiles = (int)(gridDim.x / (unsigned)p.agroups);
-    return (int)blockIdx.x / tiles;
+__device__ __forceinline__ int assign_group(const KmeansPlan& p, Wg w) {
+    if (p.group_major) return (int)((w.x >> 3) % (unsigned)p.agroups);
+    const int tiles = (int)(w.n / (unsigned)p.agroups);
+    return (int)w.x / tiles;
 }
-__device__ __forceinline__ int assign_tile(const KmeansPlan& p) {
-    if (p.group_major)
-        return (int)(((blockIdx.x >> 3) / (unsigned)p.agroups) * 8u + (blockIdx.x & 7u));
-    const int tiles = (int)(gridDim.x / (unsigned)p.agroups);
-    return (int)blockIdx.x % tiles;
+__device__ __forceinline__ int assign_tile(const KmeansPlan& p, Wg w) {
+    if (p.group_major) return (int)(((w.x >> 3) / (unsigned)p.agroups) * 8u + (w.x & 7u));
+    const int tiles = (int)(w.n / (unsigned)p.agroups);
+    return (int)w.x % tiles;
 }
 
 // End of a candidate in the assignment kernels.  Lane (li, g) holds, for
@@ -338,7 +381,8 @@ __device__ __forceinline__ int fold_lane_groups(float (&bv)[PS], int (&bi)[PS], 
 }
 
 template <int D, int PS>
-__global__ __launch_bounds__(256) void k_assign(KmeansPlan p, const float* __restrict__ Z) {
+__device__ __forceinline__ void assign_body(const KmeansPlan& p, const float* __restrict__ Z, Wg w,
+                                            int it) {
     constexpr int KS = D / 4;
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
@@ -346,7 +390,7 @@ __global__ __launch_bounds__(256) void k_assign(KmeansPlan p, const float* __res
     const int li = lane & 15;
     __shared__ float fold_all[4][2 * PS * kWave];
     float* fold = fold_all[wid];
-    const int pbase = (assign_tile(p) * 4 + wid) * 16 * PS;
+    const int pbase = (assign_tile(p, w) * 4 + wid) * 16 * PS;
     if (pbase >= p.n) return;
     float b[PS][KS];
 #pragma unroll
@@ -362,7 +406,7 @@ __global__ __launch_bounds__(256) void k_assign(KmeansPlan p, const float* __res
             b[ps][s + 3] = v.w;
         }
     }
-    const int grp = assign_group(p);
+    const int grp = assign_group(p, w);
     const int t0 = p.agrp[grp], t1 = p.agrp[grp + 1];
     // The group's candidates (at most kWave), one per lane: id, active flag,
     // tile count and centre offset are loaded once, in parallel; the walk
@@ -439,7 +483,7 @@ __global__ __launch_bounds__(256) void k_assign(KmeansPlan p, const float* __res
                 changed = old != nw;
                 *lp = nw;
                 p.lab_old[(size_t)k * p.n + pt] = old;
-                if (changed) p.moved_it[(size_t)(pt >> 6) * p.Kc + k] = p.it;
+                if (changed) p.moved_it[(size_t)(pt >> 6) * p.Kc + k] = it;
             }
             const uint64_t m = __ballot(changed);
             if (lane == 0 && m) p.changes[k] = 1;   // only zero / non-zero is read
@@ -451,6 +495,22 @@ __global__ __launch_bounds__(256) void k_assign(KmeansPlan p, const float* __res
         ntiles = nntiles;
         koff = nkoff;
     }
+}
+
+template <int D, int PS>
+__global__ __launch_bounds__(256) void k_assign(KmeansPlan p, const float* __restrict__ Z) {
+    assign_body<D, PS>(p, Z, wg_self(), p.it);
+}
+
+template <int D, int PS>
+__global__ __launch_bounds__(256) void k_assign_b(const KmeansPlan* __restrict__ plans,
+                                                  const float* __restrict__ Z, int it,
+                                                  BatchTable tb) {
+    int gi;
+    Wg w;
+    if (!batch_find(tb, gi, w)) return;
+    const KmeansPlan& p = plans[gi];
+    assign_body<D, PS>(p, Z + (size_t)p.zoff * D, w, it);
 }
 
 // Split-fp16 assignment (d a multiple of 32): the same walk and argmin as
@@ -476,7 +536,7 @@ __device__ __forceinline__ half8 neg_half8(half8 v) {
 // halves, norms) once, one tile ahead of the MFMAs, into a double buffer;
 // one barrier per tile.  Rows are padded by 8 halves against bank conflicts.
 template <int D, int PS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3))) void k_assign_h(KmeansPlan p) {
+__device__ __forceinline__ void assign_h_body(const KmeansPlan& p, Wg w, int it) {
     constexpr int NC = D / 32;
     constexpr int RS = D + 8;                 // LDS row stride (halves)
     constexpr int CPR = D / 8;                // 16-byte chunks per row and half
@@ -491,8 +551,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3))) voi
     const int li = lane & 15;
     // every wave takes part in the barriers; rows beyond n are clamped, and
     // a work-group wholly past n (tile padding) leaves before any barrier
-    if (p.group_major && assign_tile(p) * 4 * 16 * PS >= p.n) return;
-    const int pbase = (assign_tile(p) * 4 + wid) * 16 * PS;
+    if (p.group_major && assign_tile(p, w) * 4 * 16 * PS >= p.n) return;
+    const int pbase = (assign_tile(p, w) * 4 + wid) * 16 * PS;
     half8 bh[PS][NC], bl[PS][NC];
 #pragma unroll
     for (int ps = 0; ps < PS; ++ps) {
@@ -507,7 +567,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3))) voi
         }
     }
     // the group's candidates, one per lane (the same in every wave)
-    const int grp = assign_group(p);
+    const int grp = assign_group(p, w);
     const int t0 = p.agrp[grp], t1 = p.agrp[grp + 1];
     const int nc = min(t1 - t0, kWave);
     int my_k = 0, my_tiles = 0, my_off = 0;
@@ -639,7 +699,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3))) voi
                 changed = old_lab != nw;
                 p.lab_cm[(size_t)k * p.n + ptl] = nw;
                 p.lab_old[(size_t)k * p.n + ptl] = old_lab;
-                if (changed) p.moved_it[(size_t)(ptl >> 6) * p.Kc + k] = p.it;
+                if (changed) p.moved_it[(size_t)(ptl >> 6) * p.Kc + k] = it;
             }
             const uint64_t m = __ballot(changed);
             if (lane == 0 && m) p.changes[k] = 1;   // only zero / non-zero is read
@@ -659,6 +719,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3))) voi
 
 #undef ASSIGN_ISSUE
 #undef ASSIGN_COMMIT
+
+template <int D, int PS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3))) void k_assign_h(KmeansPlan p) {
+    assign_h_body<D, PS>(p, wg_self(), p.it);
+}
+
+template <int D, int PS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3))) void k_assign_h_b(
+    const KmeansPlan* __restrict__ plans, int it, BatchTable tb) {
+    int gi;
+    Wg w;
+    if (!batch_find(tb, gi, w)) return;
+    assign_h_body<D, PS>(plans[gi], w, it);
+}
 
 // After an assignment: a candidate whose labels did not change (from the
 // second assignment on) has converged; count the remaining active ones.
@@ -693,13 +767,21 @@ __global__ __launch_bounds__(256) void k_iter_finalize(KmeansPlan p, int it, int
     finalize_candidates(p, it, t_max);
 }
 
+__global__ __launch_bounds__(256) void k_iter_finalize_b(const KmeansPlan* __restrict__ plans,
+                                                         int it, int t_max, BatchTable tb) {
+    int gi;
+    Wg w;
+    if (!batch_find(tb, gi, w)) return;
+    finalize_candidates(plans[gi], it, t_max);
+}
+
 // Largest |z| (bit pattern of a non-negative float orders as an integer):
 // block maximum, then one atomic per block.
-__global__ __launch_bounds__(256) void k_zmax(KmeansPlan p, const float* __restrict__ Z) {
+__device__ __forceinline__ void zmax_body(const KmeansPlan& p, const float* __restrict__ Z, Wg w) {
     const int64_t total = (int64_t)p.n * p.d;
     float m = 0.f;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x)
+    for (int64_t i = (int64_t)w.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)w.n * blockDim.x)
         m = fmaxf(m, fabsf(Z[i]));
     if (!(m <= 3.0e38f)) m = 3.0e38f;   // non-finite input: keep the exponent sane
 #pragma unroll
@@ -713,6 +795,19 @@ __global__ __launch_bounds__(256) void k_zmax(KmeansPlan p, const float* __restr
     }
 }
 
+__global__ __launch_bounds__(256) void k_zmax(KmeansPlan p, const float* __restrict__ Z) {
+    zmax_body(p, Z, wg_self());
+}
+
+__global__ __launch_bounds__(256) void k_zmax_b(const KmeansPlan* __restrict__ plans,
+                                                const float* __restrict__ Z, BatchTable tb) {
+    int gi;
+    Wg w;
+    if (!batch_find(tb, gi, w)) return;
+    const KmeansPlan& p = plans[gi];
+    zmax_body(p, Z + (size_t)p.zoff * p.d, w);
+}
+
 // Fixed-point exponent e: |z| * 2^e < 2^30 for every |z| <= zmax.
 __device__ __forceinline__ int fixed_exp(const KmeansPlan& p) {
     const float zmax = __uint_as_float(*p.zmax_bits);
@@ -722,12 +817,27 @@ __device__ __forceinline__ int fixed_exp(const KmeansPlan& p) {
     return 30 - ez;
 }
 
-__global__ __launch_bounds__(256) void k_split_points(KmeansPlan p, const float* __restrict__ Z) {
+__device__ __forceinline__ void split_points_body(const KmeansPlan& p, const float* __restrict__ Z,
+                                                  Wg w) {
     const int64_t total = (int64_t)p.n * p.d;
     const float sc = ldexpf(1.0f, split_exp(p));
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x)
+    for (int64_t i = (int64_t)w.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)w.n * blockDim.x)
         split_half(Z[i], sc, p.zh + i, p.zl + i);
+}
+
+__global__ __launch_bounds__(256) void k_split_points(KmeansPlan p, const float* __restrict__ Z) {
+    split_points_body(p, Z, wg_self());
+}
+
+__global__ __launch_bounds__(256) void k_split_points_b(const KmeansPlan* __restrict__ plans,
+                                                        const float* __restrict__ Z,
+                                                        BatchTable tb) {
+    int gi;
+    Wg w;
+    if (!batch_find(tb, gi, w)) return;
+    const KmeansPlan& p = plans[gi];
+    split_points_body(p, Z + (size_t)p.zoff * p.d, w);
 }
 
 // Centre update, incremental and exact.  The sums of every centre are kept
@@ -781,10 +891,10 @@ __device__ __forceinline__ unsigned long long widen_at_use(int x) {
     return (unsigned long long)(long long)x;
 }
 
-__global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __restrict__ Z) {
+__device__ __forceinline__ void update_body(const KmeansPlan& p, const float* __restrict__ Z, int wi,
+                                            int it) {
     extern __shared__ unsigned long long acc64[];
-    // work item -> (group, range slot)
-    const int wi = blockIdx.x;
+    // work item wi -> (group, range slot)
     int g = 0;
     while (g + 1 < p.ugroups && p.uwi0[g + 1] <= wi) ++g;
     const int slot = wi - p.uwi0[g];
@@ -846,7 +956,7 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
             const int csj = cb + (lane >> 4) * kStride;
             bool f = false;
             if (mc < nc && my_act != 0 && csj < r1)
-                f = p.moved_it[(size_t)(csj >> 6) * p.Kc + my_k] == p.it;
+                f = p.moved_it[(size_t)(csj >> 6) * p.Kc + my_k] == it;
             F = __ballot(f);
         }
         for (int j = 0; j < 4; ++j) {
@@ -1004,6 +1114,20 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
     }
 }
 
+__global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __restrict__ Z) {
+    update_body(p, Z, (int)blockIdx.x, p.it);
+}
+
+__global__ __launch_bounds__(256) void k_update_b(const KmeansPlan* __restrict__ plans,
+                                                  const float* __restrict__ Z, int it,
+                                                  BatchTable tb) {
+    int gi;
+    Wg w;
+    if (!batch_find(tb, gi, w)) return;
+    const KmeansPlan& p = plans[gi];
+    update_body(p, Z + (size_t)p.zoff * p.d, (int)w.x, it);
+}
+
 // Folds the flagged partials of one centre row into its integer totals and
 // recomputes the centre as total * 2^-e / count (FP64, then FP32); a row no
 // point moved into or out of keeps its centre, and so does an empty cluster.
@@ -1014,12 +1138,11 @@ __global__ __launch_bounds__(256) void k_update(KmeansPlan p, const float* __res
 // (finalize_candidates) in the same launch: a candidate it retires has no
 // moved point, so no other work-group of this launch or of the update
 // depends on its flags.
-__global__ __launch_bounds__(256) void k_update_finish(KmeansPlan p, int it, int t_max) {
-    if ((int)blockIdx.x == p.KP) {
+__device__ __forceinline__ void update_finish_body(const KmeansPlan& p, int it, int t_max, int c) {
+    if (c == p.KP) {
         finalize_candidates(p, it, t_max);
         return;
     }
-    const int c = blockIdx.x;
     const int k = p.cand_of[c];
     if (!p.active[k]) return;
     if (c - p.koff16[k] >= p.ks[k]) return;
@@ -1092,9 +1215,21 @@ __global__ __launch_bounds__(256) void k_update_finish(KmeansPlan p, int it, int
     }
 }
 
-__global__ void k_kmeans_reset(KmeansPlan p) {
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+__global__ __launch_bounds__(256) void k_update_finish(KmeansPlan p, int it, int t_max) {
+    update_finish_body(p, it, t_max, (int)blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_update_finish_b(const KmeansPlan* __restrict__ plans,
+                                                         int it, int t_max, BatchTable tb) {
+    int gi;
+    Wg w;
+    if (!batch_find(tb, gi, w)) return;
+    update_finish_body(plans[gi], it, t_max, (int)w.x);
+}
+
+__device__ __forceinline__ void kmeans_reset_body(const KmeansPlan& p, Wg w) {
+    const int64_t tid = (int64_t)w.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)w.n * blockDim.x;
     for (int64_t i = tid; i < (int64_t)p.Kc * p.n; i += stride) p.lab_cm[i] = 0xFF;
     for (int64_t i = tid; i < (int64_t)p.KP * p.d; i += stride) p.S64[i] = 0;
     for (int64_t i = tid; i < p.KP; i += stride) p.N32[i] = 0;
@@ -1108,6 +1243,16 @@ __global__ void k_kmeans_reset(KmeansPlan p) {
         *p.active_count = p.Kc;
         *p.zmax_bits = 0u;
     }
+}
+
+__global__ void k_kmeans_reset(KmeansPlan p) { kmeans_reset_body(p, wg_self()); }
+
+__global__ __launch_bounds__(256) void k_kmeans_reset_b(const KmeansPlan* __restrict__ plans,
+                                                        BatchTable tb) {
+    int gi;
+    Wg w;
+    if (!batch_find(tb, gi, w)) return;
+    kmeans_reset_body(plans[gi], w);
 }
 
 bool kmeans_supported(int d) { return d == 16 || d == 32 || d == 64 || d == 128 || d == 256; }
@@ -1129,15 +1274,40 @@ int kmeans_update_rows(int K) { return K; }
 
 int kmeans_update_max_candidates() { return kUpdMaxCand; }
 
+int kmeans_blocks(const KmeansPlan& p, int kind, int num_cu) {
+    const int64_t nd = (int64_t)p.n * p.d;
+    switch (kind) {
+        case kKmZmax:
+            return (int)std::max<int64_t>(1, std::min<int64_t>((nd + 255) / 256, num_cu * 2));
+        case kKmReset: {
+            const int64_t total = std::max<int64_t>((int64_t)p.Kc * p.n, p.Kc);
+            return (int)std::min<int64_t>((total + 255) / 256, 4096);
+        }
+        case kKmSplit: return nd == 0 ? 0 : (int)std::min<int64_t>((nd + 255) / 256, 8192);
+        case kKmRace: return p.race_grid;
+        case kKmRaceFinal:
+        case kKmFinalize: return 1;
+        case kKmInit: return (p.KP * kWave + 255) / 256;
+        case kKmAssign: {
+            const int ps = p.d <= 64 ? 4 : (p.d == 128 ? 3 : 1);
+            const int pts_per_block = 4 * 16 * ps;
+            int tiles = (p.n + pts_per_block - 1) / pts_per_block;
+            if (p.group_major) tiles = (tiles + 7) / 8 * 8;
+            return tiles * p.agroups;
+        }
+        case kKmUpdate: return p.uwork;
+        case kKmUpdateFinish: return p.KP + 1;
+        default: return 0;
+    }
+}
+
 void launch_zmax(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t st) {
-    const int64_t total = (int64_t)p.n * p.d;
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, num_cu * 2));
+    const int grid = kmeans_blocks(p, kKmZmax, num_cu);
     hipLaunchKernelGGL(k_zmax, dim3(grid), dim3(256), 0, st, p, Z);
 }
 
 void launch_kmeans_reset(const KmeansPlan& p, hipStream_t st) {
-    const int64_t total = std::max<int64_t>((int64_t)p.Kc * p.n, p.Kc);
-    const int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
+    const int grid = kmeans_blocks(p, kKmReset, 0);
     hipLaunchKernelGGL(k_kmeans_reset, dim3(grid), dim3(256), 0, st, p);
 }
 
@@ -1151,9 +1321,9 @@ void launch_kmeans_reset(const KmeansPlan& p, hipStream_t st) {
         default: break;            \
     }
 
-void launch_race_pick(const KmeansPlan& p, const float* Z, int t, uint64_t seed, hipStream_t st) {
+void launch_race_pick(const KmeansPlan& p, const float* Z, int t, hipStream_t st) {
 #define RACE(DV) \
-    hipLaunchKernelGGL(k_race<DV>, dim3(p.race_grid), dim3(kRaceThreads), 0, st, p, Z, t, seed)
+    hipLaunchKernelGGL(k_race<DV>, dim3(p.race_grid), dim3(kRaceThreads), 0, st, p, Z, t)
     RAFT_D_SWITCH(p.d, RACE)
 #undef RACE
     if (t == p.k_max - 1) hipLaunchKernelGGL(k_race_final, dim3(1), dim3(kRaceThreads), 0, st, p);
@@ -1195,6 +1365,71 @@ void launch_assign(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t 
     }
     RAFT_D_SWITCH(p.d, ASSIGN)
 #undef ASSIGN
+}
+
+// ---- batched launches: the per-graph plans live in device memory, the
+// graphs' points are consecutive row ranges of one packed Z (plan.zoff) ----
+
+void launch_kmeans_batched(int kind, const KmeansPlan* plans, int d, bool split, const float* Z,
+                           int it, int t_max, size_t lds_max, size_t update_lds,
+                           const BatchTable& t, int grid, hipStream_t st) {
+    if (grid == 0) return;
+    const dim3 blk(256);
+    switch (kind) {
+        case kKmReset: hipLaunchKernelGGL(k_kmeans_reset_b, dim3(grid), blk, 0, st, plans, t); break;
+        case kKmZmax: hipLaunchKernelGGL(k_zmax_b, dim3(grid), blk, 0, st, plans, Z, t); break;
+        case kKmSplit: hipLaunchKernelGGL(k_split_points_b, dim3(grid), blk, 0, st, plans, Z, t); break;
+        case kKmRace: {
+#define RACE(DV) hipLaunchKernelGGL(k_race_b<DV>, dim3(grid), dim3(kRaceThreads), 0, st, plans, Z, it, t)
+            RAFT_D_SWITCH(d, RACE)
+#undef RACE
+            break;
+        }
+        case kKmRaceFinal:
+            hipLaunchKernelGGL(k_race_final_b, dim3(grid), dim3(kRaceThreads), 0, st, plans, t);
+            break;
+        case kKmInit: {
+#define INIT(DV) hipLaunchKernelGGL(k_init_centres_b<DV>, dim3(grid), blk, 0, st, plans, Z, t)
+            RAFT_D_SWITCH(d, INIT)
+#undef INIT
+            break;
+        }
+        case kKmAssign: {
+#define ASSIGN(DV)                                                                         \
+    {                                                                                      \
+        constexpr int PS = assign_ps<DV>();                                                \
+        if constexpr (DV % 32 == 0) {                                                      \
+            if (split) {                                                                   \
+                hipLaunchKernelGGL((k_assign_h_b<DV, PS>), dim3(grid), blk, 0, st, plans, it, t); \
+                break;                                                                     \
+            }                                                                              \
+        }                                                                                  \
+        hipLaunchKernelGGL((k_assign_b<DV, PS>), dim3(grid), blk, 0, st, plans, Z, it, t); \
+    }
+            RAFT_D_SWITCH(d, ASSIGN)
+#undef ASSIGN
+            break;
+        }
+        case kKmFinalize:
+            hipLaunchKernelGGL(k_iter_finalize_b, dim3(grid), blk, 0, st, plans, it, t_max, t);
+            break;
+        case kKmUpdate: {
+            static std::once_flag attr_once;
+            std::call_once(attr_once, [&] {
+                (void)hipFuncSetAttribute((const void*)k_update_b,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)lds_max);
+            });
+            const int nsl = (d + kUpdSlice - 1) / kUpdSlice;
+            hipLaunchKernelGGL(k_update_b, dim3(grid, nsl), dim3(kUpdWaves * kWave), update_lds, st,
+                               plans, Z, it, t);
+            break;
+        }
+        case kKmUpdateFinish:
+            hipLaunchKernelGGL(k_update_finish_b, dim3(grid), blk, 0, st, plans, it, t_max, t);
+            break;
+        default: break;
+    }
 }
 
 bool kmeans_split_supported(int d) { return d % 32 == 0 && d >= 32 && d <= 256; }

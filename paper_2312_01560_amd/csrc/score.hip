@@ -24,23 +24,33 @@
 
 namespace raft {
 
-__global__ __launch_bounds__(256) void k_transpose_labels(const uint8_t* __restrict__ cm, int n,
-                                                          int Kc, uint8_t* __restrict__ pm,
-                                                          int S) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void transpose_labels_body(const uint8_t* __restrict__ cm, int n, int Kc,
+                                                      uint8_t* __restrict__ pm, int S, int bx) {
+    const int64_t idx = (int64_t)bx * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)n * S) return;
     const int i = (int)(idx / S);
     const int k = (int)(idx - (int64_t)i * S);
     pm[idx] = k < Kc ? cm[(size_t)k * n + i] : (uint8_t)0;
 }
 
-__global__ __launch_bounds__(256) void k_copy_labels(const uint8_t* __restrict__ pm, int n, int Kc,
-                                                     int S, uint8_t* __restrict__ out) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_transpose_labels(const uint8_t* __restrict__ cm, int n,
+                                                          int Kc, uint8_t* __restrict__ pm,
+                                                          int S) {
+    transpose_labels_body(cm, n, Kc, pm, S, (int)blockIdx.x);
+}
+
+__device__ __forceinline__ void copy_labels_body(const uint8_t* __restrict__ pm, int n, int Kc, int S,
+                                                 uint8_t* __restrict__ out, int bx) {
+    const int64_t idx = (int64_t)bx * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)n * Kc) return;
     const int i = (int)(idx / Kc);
     const int k = (int)(idx - (int64_t)i * Kc);
     out[idx] = pm[(size_t)i * S + k];
+}
+
+__global__ __launch_bounds__(256) void k_copy_labels(const uint8_t* __restrict__ pm, int n, int Kc,
+                                                     int S, uint8_t* __restrict__ out) {
+    copy_labels_body(pm, n, Kc, S, out, (int)blockIdx.x);
 }
 
 __device__ __forceinline__ uint32_t zero_bytes_mask(uint32_t x) {
@@ -49,9 +59,11 @@ __device__ __forceinline__ uint32_t zero_bytes_mask(uint32_t x) {
     return ~(y | x | 0x7F7F7F7Fu);
 }
 
+// Node ids from the graph view are global (a batch's block-diagonal CSR); the
+// labels are the graph's own rows, so they are indexed by id - base.
 template <int LPR>
-__global__ __launch_bounds__(256) void k_edge_score(GraphView g, ScorePlan p,
-                                                    const uint8_t* __restrict__ lab, int rpw) {
+__device__ __forceinline__ void edge_score_body(const GraphView& g, const ScorePlan& p,
+                                                const uint8_t* __restrict__ lab, Wg w) {
     constexpr int G = kWave / LPR;                  // rows side by side per wave
     extern __shared__ int sm[];
     int* sl = sm;
@@ -66,10 +78,10 @@ __global__ __launch_bounds__(256) void k_edge_score(GraphView g, ScorePlan p,
     // passes of G positions of the graph's degree-class order (rows of
     // similar length side by side, the longest first), dealt to the waves
     // round robin so every wave gets its share of long and short rows
-    (void)rpw;
-    const int nwaves = gridDim.x * (blockDim.x / kWave);
+    const int nwaves = (int)w.n * (blockDim.x / kWave);
     const int npass = (g.n + G - 1) / G;
-    for (int pp = blockIdx.x * (blockDim.x / kWave) + wid; pp < npass; pp += nwaves) {
+    lab -= (size_t)g.base * p.S;
+    for (int pp = (int)w.x * (blockDim.x / kWave) + wid; pp < npass; pp += nwaves) {
         const int pos = pp * G + slot;
         const bool valid = pos < g.n;
         const int i = valid ? g.order[pos] : 0;
@@ -131,17 +143,33 @@ __global__ __launch_bounds__(256) void k_edge_score(GraphView g, ScorePlan p,
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < p.SK; idx += blockDim.x) {
-        p.lpart[(size_t)blockIdx.x * p.SK + idx] = sl[idx];
-        p.vpart[(size_t)blockIdx.x * p.SK + idx] = sv[idx];
+        p.lpart[(size_t)w.x * p.SK + idx] = sl[idx];
+        p.vpart[(size_t)w.x * p.SK + idx] = sv[idx];
     }
+}
+
+template <int LPR>
+__global__ __launch_bounds__(256) void k_edge_score(GraphView g, ScorePlan p,
+                                                    const uint8_t* __restrict__ lab) {
+    edge_score_body<LPR>(g, p, lab, wg_self());
+}
+
+template <int LPR>
+__global__ __launch_bounds__(256) void k_edge_score_b(const GraphView* __restrict__ views,
+                                                      const ScorePlan* __restrict__ plans,
+                                                      BatchTable t) {
+    int gi;
+    Wg w;
+    if (!batch_find(t, gi, w)) return;
+    edge_score_body<LPR>(views[gi], plans[gi], plans[gi].lab, w);
 }
 
 // Sum of the work-group partials: 16 entries x 16 slices per block, slices
 // combined through LDS.  Integer sums, exact.
-__global__ __launch_bounds__(256) void k_reduce_counts(ScorePlan p) {
+__device__ __forceinline__ void reduce_counts_body(const ScorePlan& p, int bx) {
     __shared__ long long sl[16][17], sv[16][17];
     const int e = threadIdx.x & 15, sl_id = threadIdx.x >> 4;
-    const int idx = blockIdx.x * 16 + e;
+    const int idx = bx * 16 + e;
     long long l = 0, v = 0;
     if (idx < p.SK) {
         const int per = (p.grid + 15) / 16;
@@ -165,11 +193,14 @@ __global__ __launch_bounds__(256) void k_reduce_counts(ScorePlan p) {
     }
 }
 
+__global__ __launch_bounds__(256) void k_reduce_counts(ScorePlan p) {
+    reduce_counts_body(p, (int)blockIdx.x);
+}
+
 // One wave per candidate: the counts are staged in LDS, the FP64 sums run
 // over r in ascending order on one lane.
-__global__ __launch_bounds__(64) void k_score_finalize(ScorePlan p) {
+__device__ __forceinline__ void score_finalize_body(const ScorePlan& p, int k) {
     __shared__ long long ls[RAFT_MAX_K_DEV + 1], vs[RAFT_MAX_K_DEV + 1];
-    const int k = blockIdx.x;
     if (k >= p.Kc) return;
     const int K = p.ks[k];
     for (int r = threadIdx.x; r < K; r += blockDim.x) {
@@ -197,8 +228,12 @@ __global__ __launch_bounds__(64) void k_score_finalize(ScorePlan p) {
     }
 }
 
+__global__ __launch_bounds__(64) void k_score_finalize(ScorePlan p) {
+    score_finalize_body(p, (int)blockIdx.x);
+}
+
 // K* = first maximum of Mod; init first-occurrence table.
-__global__ void k_select_best(ScorePlan p, int32_t* k_selected) {
+__device__ __forceinline__ void select_best_body(const ScorePlan& p, int32_t* k_selected) {
     if (threadIdx.x == 0) {
         int best = 0;
         for (int j = 1; j < p.Kc; ++j)
@@ -210,19 +245,26 @@ __global__ void k_select_best(ScorePlan p, int32_t* k_selected) {
     for (int r = threadIdx.x; r <= RAFT_MAX_K_DEV; r += blockDim.x) p.first[r] = INT_MAX;
 }
 
-__global__ __launch_bounds__(256) void k_first_occ(ScorePlan p, const uint8_t* __restrict__ lab) {
+__global__ void k_select_best(ScorePlan p, int32_t* k_selected) { select_best_body(p, k_selected); }
+
+__device__ __forceinline__ void first_occ_body(const ScorePlan& p, const uint8_t* __restrict__ lab,
+                                               Wg w) {
     __shared__ int first[RAFT_MAX_K_DEV + 1];
     for (int r = threadIdx.x; r <= RAFT_MAX_K_DEV; r += blockDim.x) first[r] = INT_MAX;
     __syncthreads();
     const int best = *p.best;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < p.n; i += gridDim.x * blockDim.x)
+    for (int i = (int)w.x * blockDim.x + threadIdx.x; i < p.n; i += (int)w.n * blockDim.x)
         atomicMin(&first[lab[(size_t)i * p.S + best]], i);
     __syncthreads();
     for (int r = threadIdx.x; r <= RAFT_MAX_K_DEV; r += blockDim.x)
         if (first[r] != INT_MAX) atomicMin(&p.first[r], first[r]);
 }
 
-__global__ void k_rank(ScorePlan p, int32_t* k_selected) {
+__global__ __launch_bounds__(256) void k_first_occ(ScorePlan p, const uint8_t* __restrict__ lab) {
+    first_occ_body(p, lab, wg_self());
+}
+
+__device__ __forceinline__ void rank_body(const ScorePlan& p, int32_t* k_selected) {
     __shared__ int keff;
     if (threadIdx.x == 0) keff = 0;
     __syncthreads();
@@ -242,11 +284,88 @@ __global__ void k_rank(ScorePlan p, int32_t* k_selected) {
     if (threadIdx.x == 0) k_selected[1] = keff;
 }
 
-__global__ __launch_bounds__(256) void k_apply(ScorePlan p, const uint8_t* __restrict__ lab,
-                                               int32_t* __restrict__ out) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_rank(ScorePlan p, int32_t* k_selected) { rank_body(p, k_selected); }
+
+__device__ __forceinline__ void apply_body(const ScorePlan& p, const uint8_t* __restrict__ lab,
+                                           int32_t* __restrict__ out, int bx) {
+    const int i = bx * blockDim.x + threadIdx.x;
     if (i >= p.n) return;
     out[i] = p.remap[lab[(size_t)i * p.S + *p.best]];
+}
+
+__global__ __launch_bounds__(256) void k_apply(ScorePlan p, const uint8_t* __restrict__ lab,
+                                               int32_t* __restrict__ out) {
+    apply_body(p, lab, out, (int)blockIdx.x);
+}
+
+// ---- batched forms: one launch per kernel over the graphs of a batch, each
+// graph with its own ScorePlan (labels, outputs) in device memory ----
+
+__global__ __launch_bounds__(256) void k_transpose_labels_b(const ScorePlan* __restrict__ plans,
+                                                            BatchTable t) {
+    int gi;
+    Wg w;
+    if (!batch_find(t, gi, w)) return;
+    const ScorePlan& p = plans[gi];
+    transpose_labels_body(p.lab_cm, p.n, p.Kc, p.lab, p.S, (int)w.x);
+}
+
+__global__ __launch_bounds__(256) void k_reduce_counts_b(const ScorePlan* __restrict__ plans,
+                                                         BatchTable t) {
+    int gi;
+    Wg w;
+    if (!batch_find(t, gi, w)) return;
+    reduce_counts_body(plans[gi], (int)w.x);
+}
+
+__global__ __launch_bounds__(64) void k_score_finalize_b(const ScorePlan* __restrict__ plans,
+                                                         BatchTable t) {
+    int gi;
+    Wg w;
+    if (!batch_find(t, gi, w)) return;
+    score_finalize_body(plans[gi], (int)w.x);
+}
+
+__global__ __launch_bounds__(256) void k_select_best_b(const ScorePlan* __restrict__ plans,
+                                                       BatchTable t) {
+    int gi;
+    Wg w;
+    if (!batch_find(t, gi, w)) return;
+    select_best_body(plans[gi], plans[gi].ksel_out);
+}
+
+__global__ __launch_bounds__(256) void k_first_occ_b(const ScorePlan* __restrict__ plans,
+                                                     BatchTable t) {
+    int gi;
+    Wg w;
+    if (!batch_find(t, gi, w)) return;
+    first_occ_body(plans[gi], plans[gi].lab, w);
+}
+
+__global__ __launch_bounds__(256) void k_rank_b(const ScorePlan* __restrict__ plans,
+                                                BatchTable t) {
+    int gi;
+    Wg w;
+    if (!batch_find(t, gi, w)) return;
+    rank_body(plans[gi], plans[gi].ksel_out);
+}
+
+__global__ __launch_bounds__(256) void k_apply_b(const ScorePlan* __restrict__ plans,
+                                                 BatchTable t) {
+    int gi;
+    Wg w;
+    if (!batch_find(t, gi, w)) return;
+    const ScorePlan& p = plans[gi];
+    if (p.labels_out) apply_body(p, p.lab, p.labels_out, (int)w.x);
+}
+
+__global__ __launch_bounds__(256) void k_copy_labels_b(const ScorePlan* __restrict__ plans,
+                                                       BatchTable t) {
+    int gi;
+    Wg w;
+    if (!batch_find(t, gi, w)) return;
+    const ScorePlan& p = plans[gi];
+    if (p.labels_all_out) copy_labels_body(p.lab, p.n, p.Kc, p.S, p.labels_all_out, (int)w.x);
 }
 
 static int score_lpr(int S) {
@@ -254,12 +373,6 @@ static int score_lpr(int S) {
     int lpr = 1;
     while (lpr < words) lpr <<= 1;
     return lpr;
-}
-
-static int score_rpw(int32_t n, int S, int grid) {
-    const int G = kWave / score_lpr(S);
-    const int64_t rows_per_block = ((int64_t)n + grid - 1) / grid;
-    return (int)std::max<int64_t>(1, (rows_per_block + 4 * G - 1) / (4 * G));
 }
 
 int score_grid(int32_t n, int num_cu) {
@@ -289,7 +402,6 @@ void launch_edge_score(const GraphView& g, const ScorePlan& p, const uint8_t* la
                        hipStream_t st) {
     const size_t lds = (size_t)2 * p.SK * sizeof(int);
     const int lpr = score_lpr(p.S);
-    const int rpw = score_rpw(g.n, p.S, p.grid);
 #define EDGE(LV)                                                                              \
     {                                                                                         \
         static std::once_flag attr_once;                                                      \
@@ -297,7 +409,7 @@ void launch_edge_score(const GraphView& g, const ScorePlan& p, const uint8_t* la
             (void)hipFuncSetAttribute((const void*)k_edge_score<LV>,                          \
                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024); \
         });                                                                                   \
-        hipLaunchKernelGGL(k_edge_score<LV>, dim3(p.grid), dim3(256), lds, st, g, p, lab, rpw); \
+        hipLaunchKernelGGL(k_edge_score<LV>, dim3(p.grid), dim3(256), lds, st, g, p, lab);    \
     }
     switch (lpr) {
         case 1: EDGE(1) break;
@@ -324,6 +436,65 @@ void launch_select(const ScorePlan& p, const uint8_t* lab, int32_t* labels_out,
     hipLaunchKernelGGL(k_rank, dim3(1), dim3(256), 0, st, p, k_selected);
     if (labels_out)
         hipLaunchKernelGGL(k_apply, dim3(grid), dim3(256), 0, st, p, lab, labels_out);
+}
+
+int score_blocks(const ScorePlan& p, int kind) {
+    const int ng = (p.n + 255) / 256;
+    switch (kind) {
+        case kScTranspose: return (int)(((int64_t)p.n * p.S + 255) / 256);
+        case kScEdge: return p.grid;
+        case kScReduce: return (p.SK + 15) / 16;
+        case kScFinalize: return p.Kc;
+        case kScSelect:
+        case kScRank: return 1;
+        case kScFirst: return p.n == 0 ? 0 : std::min(ng, 256);
+        case kScApply: return ng;
+        case kScCopy: return (int)(((int64_t)p.n * p.Kc + 255) / 256);
+        default: return 0;
+    }
+}
+
+void launch_score_batched(int kind, const GraphView* views, const ScorePlan* plans, int S, int SK,
+                          const BatchTable& t, int grid, hipStream_t st) {
+    if (grid == 0) return;
+    const dim3 blk(256);
+    switch (kind) {
+        case kScTranspose:
+            hipLaunchKernelGGL(k_transpose_labels_b, dim3(grid), blk, 0, st, plans, t);
+            break;
+        case kScEdge: {
+            const size_t lds = (size_t)2 * SK * sizeof(int);
+#define EDGE(LV)                                                                              \
+    {                                                                                         \
+        static std::once_flag attr_once;                                                      \
+        std::call_once(attr_once, [] {                                                        \
+            (void)hipFuncSetAttribute((const void*)k_edge_score_b<LV>,                        \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024); \
+        });                                                                                   \
+        hipLaunchKernelGGL(k_edge_score_b<LV>, dim3(grid), blk, lds, st, views, plans, t);    \
+    }
+            switch (score_lpr(S)) {
+                case 1: EDGE(1) break;
+                case 2: EDGE(2) break;
+                case 4: EDGE(4) break;
+                case 8: EDGE(8) break;
+                case 16: EDGE(16) break;
+                default: EDGE(32) break;
+            }
+#undef EDGE
+            break;
+        }
+        case kScReduce: hipLaunchKernelGGL(k_reduce_counts_b, dim3(grid), blk, 0, st, plans, t); break;
+        case kScFinalize:
+            hipLaunchKernelGGL(k_score_finalize_b, dim3(grid), dim3(64), 0, st, plans, t);
+            break;
+        case kScSelect: hipLaunchKernelGGL(k_select_best_b, dim3(grid), blk, 0, st, plans, t); break;
+        case kScFirst: hipLaunchKernelGGL(k_first_occ_b, dim3(grid), blk, 0, st, plans, t); break;
+        case kScRank: hipLaunchKernelGGL(k_rank_b, dim3(grid), blk, 0, st, plans, t); break;
+        case kScApply: hipLaunchKernelGGL(k_apply_b, dim3(grid), blk, 0, st, plans, t); break;
+        case kScCopy: hipLaunchKernelGGL(k_copy_labels_b, dim3(grid), blk, 0, st, plans, t); break;
+        default: break;
+    }
 }
 
 }  // namespace raft

@@ -47,13 +47,11 @@ struct SpmmGeom {
 };
 
 template <int L, int OP, bool CS>
-__global__ __launch_bounds__(256) void k_spmm(GraphView g, const float* __restrict__ x,
-                                              float* __restrict__ y,
-                                              const float* __restrict__ cvec,
-                                              double* __restrict__ cpart, int R, int nrb) {
+__device__ __forceinline__ void spmm_body(const GraphView& g, const float* __restrict__ x,
+                                          float* __restrict__ y, const float* __restrict__ cvec,
+                                          double* __restrict__ cpart, int R, int nrb, int b) {
     using GE = SpmmGeom<L>;
     constexpr int W = GE::W, LANES = GE::LANES, G = GE::G, XS = GE::XS;
-    const int b = blockIdx.x;
     const int xcd = b % 8;
     const int sl = xcd / XS;                        // column slice
     const int rb = (b / 8) * XS + xcd % XS;         // row block
@@ -187,23 +185,47 @@ __global__ __launch_bounds__(256) void k_spmm(GraphView g, const float* __restri
     }
 }
 
+template <int L, int OP, bool CS>
+__global__ __launch_bounds__(256) void k_spmm(GraphView g, const float* __restrict__ x,
+                                              float* __restrict__ y,
+                                              const float* __restrict__ cvec,
+                                              double* __restrict__ cpart, int R, int nrb) {
+    spmm_body<L, OP, CS>(g, x, y, cvec, cpart, R, nrb, (int)blockIdx.x);
+}
+
+// Batched: one launch over the graphs of a block-diagonal CSR, each graph's
+// blocks doing exactly what its own launch would (same row blocks, slices
+// and partial order), so every graph's result equals its single-graph run.
+template <int L, int OP, bool CS>
+__global__ __launch_bounds__(256) void k_spmm_b(const SpmmItem* __restrict__ items,
+                                                const float* __restrict__ x,
+                                                float* __restrict__ y, BatchTable t) {
+    int gi;
+    Wg w;
+    if (!batch_find(t, gi, w)) return;
+    const SpmmItem& it = items[gi];
+    spmm_body<L, OP, CS>(it.g, x, y, it.cvec, it.cpart, it.R, it.nrb, (int)w.x);
+}
+
 // FP64 partials of d^T x over the same row blocks as k_spmm<L>.
+// Rows are the graph's own (local index i, global row base + i).
 template <int L>
-__global__ __launch_bounds__(256) void k_colsum_part(GraphView g, const float* __restrict__ x,
-                                                     double* __restrict__ cpart, int rpw) {
+__device__ __forceinline__ void colsum_part_body(const GraphView& g, const float* __restrict__ x,
+                                                 double* __restrict__ cpart, int rpw, int b) {
     constexpr int LANES = L / 4;
     constexpr int G = kWave / LANES;
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
     const int slot = lane / LANES;
     const int sub = lane % LANES;
-    const int row0 = (blockIdx.x * kSpmmWaves + wid) * rpw * G;
+    const int row0 = (b * kSpmmWaves + wid) * rpw * G;
     double cs0 = 0, cs1 = 0, cs2 = 0, cs3 = 0;
     for (int r = 0; r < rpw; ++r) {
         const int i = row0 + r * G + slot;
         if (i < g.n) {
-            const float4 o = *reinterpret_cast<const float4*>(x + (size_t)i * L + sub * 4);
-            const double di = (double)g.deg[i];
+            const size_t gi = (size_t)g.base + i;
+            const float4 o = *reinterpret_cast<const float4*>(x + gi * L + sub * 4);
+            const double di = (double)g.deg[gi];
             cs0 += di * (double)o.x;
             cs1 += di * (double)o.y;
             cs2 += di * (double)o.z;
@@ -228,19 +250,37 @@ __global__ __launch_bounds__(256) void k_colsum_part(GraphView g, const float* _
     for (int c = threadIdx.x; c < L; c += blockDim.x) {
         double s = 0;
         for (int w = 0; w < kSpmmWaves; ++w) s += red[w][c];
-        cpart[(size_t)blockIdx.x * L + c] = s;
+        cpart[(size_t)b * L + c] = s;
     }
+}
+
+template <int L>
+__global__ __launch_bounds__(256) void k_colsum_part(GraphView g, const float* __restrict__ x,
+                                                     double* __restrict__ cpart, int rpw) {
+    colsum_part_body<L>(g, x, cpart, rpw, (int)blockIdx.x);
+}
+
+template <int L>
+__global__ __launch_bounds__(256) void k_colsum_part_b(const ColsumItem* __restrict__ items,
+                                                       const float* __restrict__ x, BatchTable t) {
+    int gi;
+    Wg w;
+    if (!batch_find(t, gi, w)) return;
+    const ColsumItem& it = items[gi];
+    colsum_part_body<L>(it.g, x, it.part, it.rpw, (int)w.x);
 }
 
 // c = sum over the partial rows in two fixed-order levels: block b sums the
 // contiguous slice b of the partials into stage[b]; one block then sums the
 // stage rows in order.  cvec = FP32(c).
 constexpr int kColsumSlices = 64;
+static_assert(kColsumSlices == kColsumSliceBlocks && kColsumSlices <= kColsumStageRows,
+              "colsum stage rows");
 
-__global__ __launch_bounds__(256) void k_colsum_slices(const double* __restrict__ part, int parts,
-                                                       int L, double* __restrict__ stage) {
+__device__ __forceinline__ void colsum_slices_body(const double* __restrict__ part, int parts,
+                                                   int L, double* __restrict__ stage, int bx) {
     const int per = (parts + kColsumSlices - 1) / kColsumSlices;
-    const int b0 = blockIdx.x * per, b1 = min(parts, b0 + per);
+    const int b0 = bx * per, b1 = min(parts, b0 + per);
     for (int col = threadIdx.x; col < L; col += blockDim.x) {
         double s = 0;
         int b = b0;
@@ -248,19 +288,49 @@ __global__ __launch_bounds__(256) void k_colsum_slices(const double* __restrict_
             s += part[(size_t)b * L + col] + part[(size_t)(b + 1) * L + col] +
                  part[(size_t)(b + 2) * L + col] + part[(size_t)(b + 3) * L + col];
         for (; b < b1; ++b) s += part[(size_t)b * L + col];
-        stage[(size_t)blockIdx.x * L + col] = s;
+        stage[(size_t)bx * L + col] = s;
     }
 }
 
-__global__ __launch_bounds__(256) void k_colsum_finish(const double* __restrict__ stage, int L,
-                                                       double* __restrict__ c64,
-                                                       float* __restrict__ cvec) {
+__global__ __launch_bounds__(256) void k_colsum_slices(const double* __restrict__ part, int parts,
+                                                       int L, double* __restrict__ stage) {
+    colsum_slices_body(part, parts, L, stage, (int)blockIdx.x);
+}
+
+__device__ __forceinline__ void colsum_finish_body(const double* __restrict__ stage, int L,
+                                                   double* __restrict__ c64,
+                                                   float* __restrict__ cvec) {
     for (int col = threadIdx.x; col < L; col += blockDim.x) {
         double t = 0;
         for (int k = 0; k < kColsumSlices; ++k) t += stage[(size_t)k * L + col];
         c64[col] = t;
         cvec[col] = (float)t;
     }
+}
+
+__global__ __launch_bounds__(256) void k_colsum_finish(const double* __restrict__ stage, int L,
+                                                       double* __restrict__ c64,
+                                                       float* __restrict__ cvec) {
+    colsum_finish_body(stage, L, c64, cvec);
+}
+
+// Batched forms: kColsumSlices blocks per graph, then one block per graph.
+__global__ __launch_bounds__(256) void k_colsum_slices_b(const ColsumItem* __restrict__ items,
+                                                         int L, BatchTable t) {
+    int gi;
+    Wg w;
+    if (!batch_find(t, gi, w)) return;
+    const ColsumItem& it = items[gi];
+    colsum_slices_body(it.part, it.parts, L, it.part + (size_t)it.parts * L, (int)w.x);
+}
+
+__global__ __launch_bounds__(256) void k_colsum_finish_b(const ColsumItem* __restrict__ items,
+                                                         int L, BatchTable t) {
+    int gi;
+    Wg w;
+    if (!batch_find(t, gi, w)) return;
+    const ColsumItem& it = items[gi];
+    colsum_finish_body(it.part + (size_t)it.parts * L, L, it.c64, it.cvec);
 }
 
 bool spmm_supported(int L) { return L == 16 || L == 32 || L == 64 || L == 128 || L == 256; }
@@ -276,14 +346,28 @@ int spmm_grid(int32_t n, int L, int num_cu, int* rows_per_wave) {
     return (int)((n + rows_per_block - 1) / rows_per_block);
 }
 
+static int spmm_xs(int L) {
+    const int W = L >= 64 ? 32 : L;
+    return 8 / (L / W);
+}
+
+int spmm_launch_shape(int32_t n, int L, int num_cu, int* R, int* nrb) {
+    int rpw;
+    const int rb = spmm_grid(n, L, num_cu, &rpw);
+    // rows per row block, as in spmm_grid (which k_colsum_part also uses)
+    if (R) *R = rpw * (kWave / (L / 4)) * kSpmmWaves;
+    if (nrb) *nrb = rb;
+    // every group of 8 consecutive work-groups covers XS row blocks x NS slices
+    const int xs = spmm_xs(L);
+    return rb == 0 ? 0 : (rb + xs - 1) / xs * 8;
+}
+
 template <int L>
 static void spmm_dispatch_op(const GraphView& g, int op, const float* x, float* y,
-                             const float* cvec, double* cpart, int nrb, int rpw, hipStream_t st) {
-    using GE = SpmmGeom<L>;
-    // rows per row block, as in spmm_grid (which k_colsum_part also uses)
-    const int R = rpw * (kWave / (L / 4)) * kSpmmWaves;
-    // every group of 8 consecutive work-groups covers XS row blocks x NS slices
-    const int grid = (nrb + GE::XS - 1) / GE::XS * 8;
+                             const float* cvec, double* cpart, int num_cu, hipStream_t st) {
+    int R, nrb;
+    const int grid = spmm_launch_shape(g.n, L, num_cu, &R, &nrb);
+    if (grid == 0) return;
 #define RAFT_SPMM_CASE(OPV)                                                                  \
     if (op == OPV) {                                                                         \
         if (cpart)                                                                           \
@@ -303,17 +387,68 @@ static void spmm_dispatch_op(const GraphView& g, int op, const float* x, float* 
 
 void launch_spmm(const GraphView& g, int op, int L, const float* x, float* y, const float* cvec,
                  double* cpart, int num_cu, hipStream_t st) {
-    int rpw;
-    const int grid = spmm_grid(g.n, L, num_cu, &rpw);
-    if (grid == 0) return;
     switch (L) {
-        case 16: spmm_dispatch_op<16>(g, op, x, y, cvec, cpart, grid, rpw, st); break;
-        case 32: spmm_dispatch_op<32>(g, op, x, y, cvec, cpart, grid, rpw, st); break;
-        case 64: spmm_dispatch_op<64>(g, op, x, y, cvec, cpart, grid, rpw, st); break;
-        case 128: spmm_dispatch_op<128>(g, op, x, y, cvec, cpart, grid, rpw, st); break;
-        case 256: spmm_dispatch_op<256>(g, op, x, y, cvec, cpart, grid, rpw, st); break;
+        case 16: spmm_dispatch_op<16>(g, op, x, y, cvec, cpart, num_cu, st); break;
+        case 32: spmm_dispatch_op<32>(g, op, x, y, cvec, cpart, num_cu, st); break;
+        case 64: spmm_dispatch_op<64>(g, op, x, y, cvec, cpart, num_cu, st); break;
+        case 128: spmm_dispatch_op<128>(g, op, x, y, cvec, cpart, num_cu, st); break;
+        case 256: spmm_dispatch_op<256>(g, op, x, y, cvec, cpart, num_cu, st); break;
         default: break;
     }
+}
+
+template <int L>
+static void spmm_batched_op(const SpmmItem* items, int op, const float* x, float* y, bool cs,
+                            const BatchTable& t, int grid, hipStream_t st) {
+#define RAFT_SPMM_CASE(OPV)                                                                    \
+    if (op == OPV) {                                                                           \
+        if (cs)                                                                                \
+            hipLaunchKernelGGL((k_spmm_b<L, OPV, true>), dim3(grid), dim3(256), 0, st, items, x, \
+                               y, t);                                                          \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_spmm_b<L, OPV, false>), dim3(grid), dim3(256), 0, st, items,  \
+                               x, y, t);                                                       \
+        return;                                                                                \
+    }
+    RAFT_SPMM_CASE(kOpNcut)
+    RAFT_SPMM_CASE(kOpModFull)
+    RAFT_SPMM_CASE(kOpModReduced)
+    RAFT_SPMM_CASE(kOpGcn)
+#undef RAFT_SPMM_CASE
+}
+
+void launch_spmm_batched(const SpmmItem* items, int op, int L, const float* x, float* y, bool cs,
+                         const BatchTable& t, int grid, hipStream_t st) {
+    if (grid == 0) return;
+    switch (L) {
+        case 16: spmm_batched_op<16>(items, op, x, y, cs, t, grid, st); break;
+        case 32: spmm_batched_op<32>(items, op, x, y, cs, t, grid, st); break;
+        case 64: spmm_batched_op<64>(items, op, x, y, cs, t, grid, st); break;
+        case 128: spmm_batched_op<128>(items, op, x, y, cs, t, grid, st); break;
+        case 256: spmm_batched_op<256>(items, op, x, y, cs, t, grid, st); break;
+        default: break;
+    }
+}
+
+void launch_colsum_partials_batched(const ColsumItem* items, int L, const float* x,
+                                    const BatchTable& t, int grid, hipStream_t st) {
+    if (grid == 0) return;
+    switch (L) {
+        case 16: hipLaunchKernelGGL(k_colsum_part_b<16>, dim3(grid), dim3(256), 0, st, items, x, t); break;
+        case 32: hipLaunchKernelGGL(k_colsum_part_b<32>, dim3(grid), dim3(256), 0, st, items, x, t); break;
+        case 64: hipLaunchKernelGGL(k_colsum_part_b<64>, dim3(grid), dim3(256), 0, st, items, x, t); break;
+        case 128: hipLaunchKernelGGL(k_colsum_part_b<128>, dim3(grid), dim3(256), 0, st, items, x, t); break;
+        case 256: hipLaunchKernelGGL(k_colsum_part_b<256>, dim3(grid), dim3(256), 0, st, items, x, t); break;
+        default: break;
+    }
+}
+
+void launch_colsum_finish_batched(const ColsumItem* items, int L, const BatchTable& t_slices,
+                                  int grid_slices, const BatchTable& t_one, int grid_one,
+                                  hipStream_t st) {
+    if (grid_slices == 0) return;
+    hipLaunchKernelGGL(k_colsum_slices_b, dim3(grid_slices), dim3(256), 0, st, items, L, t_slices);
+    hipLaunchKernelGGL(k_colsum_finish_b, dim3(grid_one), dim3(256), 0, st, items, L, t_one);
 }
 
 void launch_colsum_partials(const GraphView& g, int L, const float* x, double* part, int num_cu,
