@@ -284,12 +284,14 @@ def bench_batch(args, api, torch, np, ctx):
     torch.cuda.synchronize()
     t_seq = (time.perf_counter() - t0) / reps
     ctx.sync_status()
+    bres = [o for o, _ in bouts]
     same = sum(int(torch.equal(bo["labels"], so[0]["labels"]) and
                    torch.equal(bo["labels_all"], so[0]["labels_all"]))
-               for bo, so in zip(bouts, souts))
-    nmi_bs = [api.nmi(ctx, bo["labels"], so[0]["labels"]) for bo, so in zip(bouts, souts)]
+               for bo, so in zip(bres, souts))
+    nmi_bs = [api.nmi(ctx, bo["labels"], so[0]["labels"]) for bo, so in zip(bres, souts)]
     nmi_pl = [api.nmi(ctx, bo["labels"], torch.from_numpy(g.planted.astype(np.int32)).to(dev))
-              for bo, g in zip(bouts, graphs)]
+              for bo, g in zip(bres, graphs)]
+    tune_factor, tune_ms = b.tuning()
     b.close()
     for g in gs:
         g.close()
@@ -303,6 +305,11 @@ def bench_batch(args, api, torch, np, ctx):
         "speedup": t_seq / t_batch,
         "ms_per_batch": 1e3 * t_batch, "ms_sequential": 1e3 * t_seq, "reps": reps,
         "batch_stage_ms": dict(zip(["prefix", "lloyd", "score"], [round(v, 3) for v in stages])),
+        "autotune": {"share_factor": tune_factor,
+                     "candidates_ms": {str(f): round(t, 3) for f, t in tune_ms},
+                     "note": "per-graph result-invariant shapes (update ranges, edge-score and "
+                             "race grids) sized for CU share = num_cu x factor x n_g / N "
+                             "(0 = single-graph shapes); first run times each candidate"},
         "graphs_bit_identical_to_sequential": same,
         "nmi_batched_vs_sequential_min": float(min(nmi_bs)),
         "nmi_vs_planted_mean": float(np.mean(nmi_pl)),

@@ -272,9 +272,67 @@ raft_status raft_batch_set_capture(raft_batch* b, int32_t enable);
 raft_status raft_batch_plan_check(int32_t G, const int32_t* n, const int64_t* nnz,
                                   const raft_config* cfg, int32_t num_cu, char* msg,
                                   size_t msg_len);
+/* The batch's launch-shape tuner.  The edge-score and k-means++ race grids
+ * and the update's point ranges of each graph are sized for a share of the
+ * chip (its node count over the batch's, times a factor); these shapes never
+ * change a result (integer counts and sums, a lexicographic argmin).  On the
+ * first raft_batch_run of a workload not in the context's tuner cache, the
+ * batch runs once per candidate factor (after one warm-up run) and keeps the
+ * fastest by GPU time; the choice is kept per workload key in the context
+ * and written to the context's autotune_cache file when one was given.
+ * factor receives the choice (0 = the single-graph shapes); ms[2 i], ms[2 i +
+ * 1] the i-th candidate and its time in ms (up to cap candidates); count the
+ * number of candidates timed by this batch (0 when the cache held the key). */
+raft_status raft_batch_tuning(const raft_batch* b, int32_t* factor, double* ms, int32_t cap,
+                              int32_t* count);
 /* GPU time of the last raft_batch_run: [0] projection + GCN + seeding,
  * [1] Lloyd, [2] scores and outputs (ms). */
 raft_status raft_batch_stage_times(const raft_batch* b, double* ms3);
+
+/* ---- hierarchical model selection (Sec. III-C, Alg. 1) --------------------
+ * Partitions the embedding Z [N x d] (device) of graph g by Alg. 1: a set U
+ * (the root is V) with local modularity m_1 = LMod(U; G) (Eq. 7) is split by
+ * KMeans with K = 2 into (U_1, U_2) with m_2 = LMod(U_1, U_2; G); U becomes a
+ * block when |U_1| <= eps or |U_2| <= eps or m_1 > m_2, otherwise U_1 and U_2
+ * are partitioned the same way.  Readings: a set of at most 2 eps + 1 nodes
+ * is a block without KMeans (one side would have at most eps nodes); a set
+ * with zero G-volume is a block (Eq. 7 is undefined); KMeans K = 2 is
+ * k-means++ by the exponential race with draws -ln u of Philox4x64-10 key
+ * (seed, 0x21), counter (node id, pick, depth, 0), then Lloyd to a fixed point
+ * or t_max assignments, ties to U_1 (the side of the first pick); blocks are
+ * numbered in the order Alg. 1 adds them (depth first, U_1 before U_2).
+ * All sets of one depth are split at once on the GPU; LMod is finished in
+ * FP64 on the host from exact integer counts, in the order r = 1, 2. */
+typedef struct {
+    int32_t eps;          /* stopping threshold (the paper uses 5)                   */
+    int32_t t_max;        /* Lloyd assignments per split (>= 1)                       */
+    uint64_t seed;        /* Philox key word 0 of the race                            */
+} raft_hier_config;
+typedef struct {
+    int32_t depth;        /* level of the set (root 0)                                */
+    int32_t size;         /* |U|                                                      */
+    int32_t parent;       /* tree node of the parent set (-1 for the root)            */
+    int32_t child[2];     /* tree nodes of U_1, U_2 (-1 when U is a block)            */
+    int32_t block;        /* block number when U is a block, else -1                  */
+    int32_t kmeans_iters; /* Lloyd assignments of the split (0: no KMeans ran)        */
+    int32_t sizes[2];     /* |U_1|, |U_2| of the KMeans split (0 when none ran)       */
+    double m1, m2;        /* LMod(U; G), LMod(U_1, U_2; G) (NaN when not computed)    */
+} raft_hier_node;
+/* Workspace bytes of raft_hier_partition for graph g and embedding width d. */
+raft_status raft_hier_workspace_size(raft_ctx* ctx, const raft_graph* g, int32_t d,
+                                     size_t* bytes);
+/* labels [N] (device) receive block numbers; *n_blocks the number of blocks.
+ * tree (host, nullable, tree_cap records) receives the visited sets in tree
+ * node order (the root first, then level by level), *n_tree their number.
+ * node_trace (device, nullable, [trace_depth x N] int32) receives for each
+ * depth < trace_depth and node 2 t + a, t the tree node of the node's set at
+ * that depth and a its side in that set's KMeans split (0 when none ran), or
+ * -1 once the node is in a block of a smaller depth.  Synchronises `stream`. */
+raft_status raft_hier_partition(raft_ctx* ctx, const raft_graph* g, const float* Z, int32_t d,
+                                const raft_hier_config* cfg, void* ws, size_t ws_bytes,
+                                int32_t* labels, int32_t* n_blocks, raft_hier_node* tree,
+                                int32_t tree_cap, int32_t* n_tree, int32_t* node_trace,
+                                int32_t trace_depth, void* stream);
 
 /* ---- training the GCN weights (optional; the method itself keeps them random) ----
  * Relaxed modularity: with hard memberships H, tr(H^T B H)/2e is the

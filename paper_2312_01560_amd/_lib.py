@@ -27,6 +27,7 @@ EXPORTS = [
     "raft_score_workspace_size", "raft_confusion", "raft_nmi_from_counts",
     "raft_spmm_noalloc", "raft_batch_create", "raft_batch_destroy", "raft_batch_workspace_size",
     "raft_batch_run", "raft_batch_set_capture", "raft_batch_plan_check", "raft_batch_stage_times",
+    "raft_batch_tuning", "raft_hier_workspace_size", "raft_hier_partition",
 ]
 
 PROF_SPMM, PROF_DENSE, PROF_RACE, PROF_ASSIGN, PROF_UPDATE, PROF_SCORE = range(6)
@@ -63,6 +64,18 @@ class RaftOutputs(ctypes.Structure):
         ("picks", ctypes.c_void_p),
         ("iters", ctypes.c_void_p),
         ("centres", ctypes.c_void_p),
+    ]
+
+
+class RaftHierConfig(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_int32), ("t_max", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class RaftHierNode(ctypes.Structure):
+    _fields_ = [
+        ("depth", ctypes.c_int32), ("size", ctypes.c_int32), ("parent", ctypes.c_int32),
+        ("child", ctypes.c_int32 * 2), ("block", ctypes.c_int32), ("kmeans_iters", ctypes.c_int32),
+        ("sizes", ctypes.c_int32 * 2), ("m1", ctypes.c_double), ("m2", ctypes.c_double),
     ]
 
 
@@ -122,6 +135,12 @@ _SIGNATURES = {
     "raft_batch_plan_check": (_I32, [_I32, ctypes.POINTER(_I32), ctypes.POINTER(_I64),
                                      ctypes.POINTER(RaftConfig), _I32, ctypes.c_char_p, _SZ]),
     "raft_batch_stage_times": (_I32, [_P, ctypes.POINTER(ctypes.c_double)]),
+    "raft_batch_tuning": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_double), _I32,
+                                 ctypes.POINTER(_I32)]),
+    "raft_hier_workspace_size": (_I32, [_P, _P, _I32, ctypes.POINTER(_SZ)]),
+    "raft_hier_partition": (_I32, [_P, _P, _P, _I32, ctypes.POINTER(RaftHierConfig), _P, _SZ, _P,
+                                   ctypes.POINTER(_I32), ctypes.POINTER(RaftHierNode), _I32,
+                                   ctypes.POINTER(_I32), _P, _I32, _P]),
 }
 
 _lib = None

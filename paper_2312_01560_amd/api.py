@@ -327,6 +327,15 @@ class Batch:
         self.ctx.check(self.ctx.lib.raft_batch_stage_times(self.h, arr))
         return list(arr)
 
+    def tuning(self):
+        """(chosen factor, [(candidate, ms), ...]) of the launch-shape tuner."""
+        f = ctypes.c_int32()
+        cnt = ctypes.c_int32()
+        arr = (ctypes.c_double * 32)()
+        self.ctx.check(self.ctx.lib.raft_batch_tuning(self.h, ctypes.byref(f), arr, 16,
+                                                      ctypes.byref(cnt)))
+        return f.value, [(int(arr[2 * i]), arr[2 * i + 1]) for i in range(cnt.value)]
+
     def close(self):
         if self.h:
             self.ctx.lib.raft_batch_destroy(self.h)
@@ -343,6 +352,32 @@ def batch_plan_check(ns, nnzs, cfg, num_cu=256):
     msg = ctypes.create_string_buffer(512)
     st = lib.raft_batch_plan_check(G, n_arr, e_arr, ctypes.byref(c), num_cu, msg, 512)
     return st, msg.value.decode(errors="replace")
+
+
+def hier_partition(ctx, g, Z, eps=5, t_max=100, seed=0, trace_depth=0):
+    """Alg. 1 on the embedding Z (device [N x d]).  Returns dict(labels
+    (device int32 [N]), k (blocks), tree (list of dicts, tree node order),
+    trace (device int32 [trace_depth x N] or None))."""
+    Z = Z.contiguous()
+    d = Z.shape[1]
+    need = ctypes.c_size_t()
+    ctx.check(ctx.lib.raft_hier_workspace_size(ctx.h, g.h, d, ctypes.byref(need)))
+    ws = ctx.workspace(need.value)
+    labels = ctx.empty((g.n,), torch.int32)
+    trace = ctx.empty((trace_depth, g.n), torch.int32) if trace_depth > 0 else None
+    cfg = _lib.RaftHierConfig(eps, t_max, seed)
+    cap = 2 * g.n + 1
+    nodes = (_lib.RaftHierNode * cap)()
+    nb = ctypes.c_int32()
+    nt = ctypes.c_int32()
+    ctx.check(ctx.lib.raft_hier_partition(
+        ctx.h, g.h, _ptr(Z), d, ctypes.byref(cfg), _ptr(ws), ws.numel(), _ptr(labels),
+        ctypes.byref(nb), nodes, cap, ctypes.byref(nt), _ptr(trace) if trace is not None else None,
+        trace_depth, _stream()))
+    tree = [{"depth": x.depth, "size": x.size, "parent": x.parent, "child": list(x.child),
+             "block": x.block, "kmeans_iters": x.kmeans_iters, "sizes": list(x.sizes),
+             "m1": x.m1, "m2": x.m2} for x in nodes[:nt.value]]
+    return {"labels": labels, "k": nb.value, "tree": tree, "trace": trace}
 
 
 def score(ctx, g, labels_all, ks):

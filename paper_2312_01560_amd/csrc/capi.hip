@@ -7,7 +7,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <fstream>
+#include <map>
 #include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -20,6 +23,7 @@ struct raft_ctx {
     int device = 0;
     void* scratch = nullptr;       // this device's copy of the fixed scratch array
     std::string autotune_cache;    // path of the tuner's cache file ("" = none)
+    std::map<std::string, int> tuned;   // tuner choices: workload key -> choice
     int num_cu = 256;
     size_t lds_max = 65536;
     std::string err;
@@ -62,6 +66,8 @@ struct raft_graph {
         return v;
     }
 };
+
+void tuner_load(raft_ctx* ctx);   // reads the context's tuner cache file
 
 // Fixed scratch for the allocation-free entry point (raft_spmm_noalloc):
 // one copy of this array per GPU, held until the process ends.  Host code
@@ -304,6 +310,7 @@ struct Plan {
     Lists lists;
     int ucap = 0;
     int ranges_max = 0;
+    int share = 0;   // CUs the result-invariant shapes are sized for
     // projection / embedding
     float *y0, *y1, *pbuf, *yout, *zout, *wbuf;
     double *cpart, *c64;
@@ -323,9 +330,15 @@ struct Plan {
 };
 
 // `features` = false leaves out the N x L feature buffers (a batch keeps them
-// packed for all its graphs).
+// packed for all its graphs).  `share` (0 = every CU) is the number of CUs the
+// result-invariant launch shapes are sized for: the update's point ranges, the
+// edge-score and race grids.  Centre sums and score counts are exact integers
+// and the race is a lexicographic argmin, so these shapes never change a
+// result; a batch gives each graph a share of the chip (see the tuner).
 void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char* base, Plan& P,
-                 bool features = true) {
+                 bool features = true, int share = 0) {
+    const int cu = share > 0 ? std::min(share, ctx->num_cu) : ctx->num_cu;
+    P.share = cu;
     const int n = g->n;
     P.L = c->proj_dim;
     P.d = embed_dim(c);
@@ -333,11 +346,11 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
     P.grid = make_grid(c->k_min, c->k_max, c->k_step);
     P.spmm_grid_ = spmm_grid(n, P.Lmax, ctx->num_cu, nullptr);
     // every width uses the same grid formula (it does not depend on L)
-    P.score_grid_ = score_grid(n, ctx->num_cu);
+    P.score_grid_ = score_grid(n, cu);
     P.S = (P.grid.Kc + 7) / 8 * 8;
     P.ucap = update_cap(P.grid, P.d);
-    P.lists = make_lists(P.grid, nullptr, P.ucap, n, ctx->num_cu);
-    P.race_grid = kmeans_race_grid(n, ctx->num_cu);
+    P.lists = make_lists(P.grid, nullptr, P.ucap, n, cu);
+    P.race_grid = kmeans_race_grid(n, cu);
     Arena a;
     a.base = base;
     const size_t nL = features ? (size_t)n * P.Lmax : 0;
@@ -372,7 +385,7 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
     km.agroups = (int)P.lists.agrp.size() - 1;
     km.ugroups = (int)P.lists.ugrp.size() - 1;
     km.usk_max = P.ucap;
-    P.ranges_max = update_ranges_max(n, ctx->num_cu);
+    P.ranges_max = update_ranges_max(n, cu);
     km.uwork = P.lists.uwork;
     km.race_grid = P.race_grid;
     km.ks = P.meta;
@@ -711,6 +724,7 @@ raft_status raft_ctx_create(int device, const char* autotune_cache, raft_ctx** o
     c->device = device;
     c->scratch = scratch_ptr;
     if (autotune_cache) c->autotune_cache = autotune_cache;
+    tuner_load(c);
     int cu = 0;
     if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
         cu > 0)
@@ -1460,6 +1474,10 @@ struct raft_batch {
     hipEvent_t poll_ev[2] = {};
     double stage_ms[3] = {0, 0, 0};
     hipEvent_t ev[4] = {};
+    // tuner: share multiplier of the result-invariant shapes (0 = not chosen)
+    int factor = 0;
+    int graph_factor = -1;            // factor the recorded HIP graph was built for
+    std::vector<std::pair<int, double>> tune_ms;
 };
 
 namespace {
@@ -1538,7 +1556,17 @@ int width_in(const raft_config* c, int k) { return k == 0 ? c->proj_dim : c->lay
 
 // Builds the layout for workspace `ws` (nullptr: sizes only) and the host
 // image of the control block.
-void batch_layout(raft_batch* b, char* ws, raft_outputs* outs, BatchLayout& B) {
+// CUs graph g's result-invariant shapes are sized for: its part of the chip
+// by node count times the tuner's factor (factor <= 0: the whole chip, the
+// single-graph shapes, which also bound the workspace).
+int batch_share(const raft_batch* b, int g, int factor) {
+    const int cu = b->ctx->num_cu;
+    if (factor <= 0) return cu;
+    const double part = (double)cu * factor * b->shadow[g].n / std::max<int64_t>(1, b->N);
+    return (int)std::max<double>(8.0, std::min<double>(cu, std::ceil(part)));
+}
+
+void batch_layout(raft_batch* b, char* ws, raft_outputs* outs, BatchLayout& B, int factor) {
     raft_ctx* ctx = b->ctx;
     const raft_config* c = &b->cfg;
     const int G = b->G;
@@ -1606,7 +1634,7 @@ void batch_layout(raft_batch* b, char* ws, raft_outputs* outs, BatchLayout& B) {
         raft_config cg = *c;
         cg.seed = b->seeds[g];
         char* sub = ws ? ws + a.off : nullptr;
-        plan_layout(ctx, &b->shadow[g], &cg, sub, B.P[g], false);
+        plan_layout(ctx, &b->shadow[g], &cg, sub, B.P[g], false, batch_share(b, g, factor));
         a.off += align256(B.P[g].bytes);
     }
     B.bytes = a.off;
@@ -1840,7 +1868,7 @@ raft_status batch_check(raft_ctx* ctx, const raft_batch* b, const BatchLayout& B
         const ScorePlan& c = B.sc[g];
         const size_t n = (size_t)b->shadow[g].n, d = (size_t)B.d, KP = (size_t)B.KP;
         const size_t Kc = (size_t)B.Kc;
-        const size_t rmax = (size_t)update_ranges_max(b->shadow[g].n, ctx->num_cu);
+        const size_t rmax = (size_t)update_ranges_max(b->shadow[g].n, P.share);
         struct Need {
             const void* p;
             size_t bytes;
@@ -2073,7 +2101,7 @@ raft_status raft_batch_create(raft_ctx* ctx, int32_t G, const raft_graph* const*
     if (err != hipSuccess) return cleanup(RAFT_E_DEVICE, "batch packing failed");
     // pinned poll buffers
     BatchLayout B;
-    batch_layout(b, nullptr, nullptr, B);
+    batch_layout(b, nullptr, nullptr, B, 0);
     b->dyn_bytes = B.ctl_upload - B.off_dyn;
     b->flag_bytes = sizeof(int32_t) * (size_t)G * B.Kc;
     if (hipHostMalloc((void**)&b->h_poll, 2 * (b->dyn_bytes + b->flag_bytes),
@@ -2113,7 +2141,7 @@ raft_status raft_batch_workspace_size(raft_ctx* ctx, const raft_batch* b, size_t
     if (!b || !bytes) return fail(ctx, RAFT_E_INVAL, "null argument");
     if (b->ctx != ctx) return fail(ctx, RAFT_E_INVAL, "batch belongs to another context");
     BatchLayout B;
-    batch_layout(const_cast<raft_batch*>(b), nullptr, nullptr, B);
+    batch_layout(const_cast<raft_batch*>(b), nullptr, nullptr, B, 0);   // the largest shapes
     *bytes = B.bytes;
     return RAFT_OK;
 }
@@ -2124,17 +2152,18 @@ raft_status raft_batch_set_capture(raft_batch* b, int32_t enable) {
     return RAFT_OK;
 }
 
-raft_status raft_batch_run(raft_ctx* ctx, raft_batch* b, void* ws, size_t ws_bytes,
-                           raft_outputs* outs, void* stream) {
-    if (!ctx) return RAFT_E_INVAL;
-    if (!b) return fail(ctx, RAFT_E_INVAL, "batch is null");
-    if (b->ctx != ctx) return fail(ctx, RAFT_E_INVAL, "batch belongs to another context");
+}  // extern "C"
+
+namespace {
+
+raft_status batch_run_once(raft_ctx* ctx, raft_batch* b, void* ws, size_t ws_bytes,
+                           raft_outputs* outs, void* stream, int factor) {
     const int G = b->G;
     const raft_config* c = &b->cfg;
     BatchLayout B;
-    batch_layout(b, nullptr, nullptr, B);
+    batch_layout(b, nullptr, nullptr, B, factor);
     RAFT_TRY(check_ws(ctx, ws, ws_bytes, B.bytes));
-    batch_layout(b, reinterpret_cast<char*>(ws), outs, B);
+    batch_layout(b, reinterpret_cast<char*>(ws), outs, B, factor);
     RAFT_TRY(batch_check(ctx, b, B, ws_bytes));
     hipStream_t st = as_stream(stream);
     // control block: static part and the initial dynamic part
@@ -2150,7 +2179,7 @@ raft_status raft_batch_run(raft_ctx* ctx, raft_batch* b, void* ws, size_t ws_byt
     }
     HIP_TRY(ctx, hipEventRecord(b->ev[0], st));
     if (b->use_graph) {
-        if (!b->exec || b->exec_ws != ws) {
+        if (!b->exec || b->exec_ws != ws || b->graph_factor != factor) {
             if (b->exec) (void)hipGraphExecDestroy(b->exec);
             if (b->graph) (void)hipGraphDestroy(b->graph);
             b->exec = nullptr;
@@ -2168,6 +2197,7 @@ raft_status raft_batch_run(raft_ctx* ctx, raft_batch* b, void* ws, size_t ws_byt
             b->graph = gr;
             HIP_TRY(ctx, hipGraphInstantiate(&b->exec, gr, nullptr, nullptr, 0));
             b->exec_ws = ws;
+            b->graph_factor = factor;
         }
         HIP_TRY(ctx, hipGraphLaunch(b->exec, st));
     } else {
@@ -2220,7 +2250,7 @@ raft_status raft_batch_run(raft_ctx* ctx, raft_batch* b, void* ws, size_t ws_byt
                 for (int g = 0; g < G; ++g) {
                     if (!live[g]) continue;
                     const Lists l = make_lists(grid, ha + (size_t)g * B.Kc, B.P[g].ucap,
-                                               b->shadow[g].n, ctx->num_cu);
+                                               b->shadow[g].n, B.P[g].share);
                     pack_lists(l, B.Kc, hl + (size_t)g * kDynLen(B.Kc));
                     B.km[g].agroups = (int)l.agrp.size() - 1;
                     B.km[g].ugroups = (int)l.ugrp.size() - 1;
@@ -2270,6 +2300,94 @@ raft_status raft_batch_run(raft_ctx* ctx, raft_batch* b, void* ws, size_t ws_byt
     return RAFT_OK;
 }
 
+std::string batch_key(const raft_batch* b) {
+    const raft_config* c = &b->cfg;
+    char buf[256];
+    snprintf(buf, sizeof buf, "batch G=%d N=%d L=%d d=%d q=%d layers=%d K=%d..%d/%d op=%d cu=%d",
+             b->G, b->N, c->proj_dim, embed_dim(c), c->q, c->n_layers, c->k_min, c->k_max,
+             c->k_step, c->op, b->ctx->num_cu);
+    return buf;
+}
+
+void tuner_save(raft_ctx* ctx) {
+    if (ctx->autotune_cache.empty()) return;
+    const std::string tmp = ctx->autotune_cache + ".tmp";
+    {
+        std::ofstream f(tmp);
+        if (!f) return;
+        for (const auto& kv : ctx->tuned) f << kv.first << '\t' << kv.second << '\n';
+    }
+    (void)std::rename(tmp.c_str(), ctx->autotune_cache.c_str());
+}
+
+}  // namespace
+
+void tuner_load(raft_ctx* ctx) {
+    if (ctx->autotune_cache.empty()) return;
+    std::ifstream f(ctx->autotune_cache);
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t tab = line.rfind('\t');
+        if (tab == std::string::npos) continue;
+        ctx->tuned[line.substr(0, tab)] = std::atoi(line.c_str() + tab + 1);
+    }
+}
+
+extern "C" {
+
+// Share multipliers the tuner times (0: the single-graph shapes).
+static const int kTuneFactors[] = {1, 2, 4, 8, 0};
+
+raft_status raft_batch_run(raft_ctx* ctx, raft_batch* b, void* ws, size_t ws_bytes,
+                           raft_outputs* outs, void* stream) {
+    if (!ctx) return RAFT_E_INVAL;
+    if (!b) return fail(ctx, RAFT_E_INVAL, "batch is null");
+    if (b->ctx != ctx) return fail(ctx, RAFT_E_INVAL, "batch belongs to another context");
+    if (b->factor == 0) {
+        // The tuner: the launch shapes it chooses among give identical
+        // results, so the choice is made by running the batch once per
+        // candidate (after one warm-up run) and keeping the fastest by GPU
+        // time; the choice is cached per workload key in the context and,
+        // when the context names a cache file, in that file.
+        const std::string key = batch_key(b);
+        auto it = ctx->tuned.find(key);
+        if (it != ctx->tuned.end()) {
+            b->factor = it->second;
+        } else {
+            RAFT_TRY(batch_run_once(ctx, b, ws, ws_bytes, outs, stream, kTuneFactors[0]));
+            double best = 1e300;
+            int choice = kTuneFactors[0];
+            b->tune_ms.clear();
+            for (int f : kTuneFactors) {
+                RAFT_TRY(batch_run_once(ctx, b, ws, ws_bytes, outs, stream, f));
+                const double t = b->stage_ms[0] + b->stage_ms[1] + b->stage_ms[2];
+                b->tune_ms.push_back({f, t});
+                if (t < best) {
+                    best = t;
+                    choice = f;
+                }
+            }
+            ctx->tuned[key] = choice;
+            tuner_save(ctx);
+            b->factor = choice;
+        }
+        if (b->factor == 0) b->factor = -1;   // the single-graph shapes
+    }
+    return batch_run_once(ctx, b, ws, ws_bytes, outs, stream, b->factor < 0 ? 0 : b->factor);
+}
+
+raft_status raft_batch_tuning(const raft_batch* b, int32_t* factor, double* ms, int32_t cap,
+                              int32_t* count) {
+    if (!b || !factor || !count) return RAFT_E_INVAL;
+    *factor = b->factor < 0 ? 0 : b->factor;
+    *count = (int32_t)b->tune_ms.size();
+    for (int i = 0; i < cap && i < *count; ++i) {
+        ms[2 * i] = b->tune_ms[i].first;
+        ms[2 * i + 1] = b->tune_ms[i].second;
+    }
+    return RAFT_OK;
+}
+
 raft_status raft_batch_plan_check(int32_t G, const int32_t* n, const int64_t* nnz,
                                   const raft_config* cfg, int32_t num_cu, char* msg,
                                   size_t msg_len) {
@@ -2303,15 +2421,18 @@ raft_status raft_batch_plan_check(int32_t G, const int32_t* n, const int64_t* nn
         b.rp = b.ci = b.deg = b.order = reinterpret_cast<int32_t*>((uintptr_t)1 << 44);
         b.s = b.sh = b.dcoef = reinterpret_cast<float*>((uintptr_t)1 << 44);
         BatchLayout B;
-        batch_layout(&b, nullptr, nullptr, B);
-        const size_t bytes = B.bytes;
-        BatchLayout B2;
-        char* fake = reinterpret_cast<char*>((uintptr_t)1 << 40);
-        batch_layout(&b, fake, nullptr, B2);
-        std::vector<int> live(G, 1);
-        std::vector<char> dyn(B2.ctl_upload - B2.off_dyn);
-        batch_dynamic(&b, B2, dyn.data(), live);
-        st = batch_check(&ctx, &b, B2, bytes);
+        batch_layout(&b, nullptr, nullptr, B, 0);
+        const size_t bytes = B.bytes;   // the workspace size the library reports
+        for (int f : kTuneFactors) {
+            BatchLayout B2;
+            char* fake = reinterpret_cast<char*>((uintptr_t)1 << 40);
+            batch_layout(&b, fake, nullptr, B2, f);
+            std::vector<int> live(G, 1);
+            std::vector<char> dyn(B2.ctl_upload - B2.off_dyn);
+            batch_dynamic(&b, B2, dyn.data(), live);
+            st = batch_check(&ctx, &b, B2, bytes);
+            if (st != RAFT_OK) break;
+        }
     }
     if (msg && msg_len) {
         const size_t m = std::min(msg_len - 1, ctx.err.size());
@@ -2326,6 +2447,325 @@ raft_status raft_batch_plan_check(int32_t G, const int32_t* n, const int64_t* nn
 raft_status raft_batch_stage_times(const raft_batch* b, double* ms3) {
     if (!b || !ms3) return RAFT_E_INVAL;
     for (int s2 = 0; s2 < 3; ++s2) ms3[s2] = b->stage_ms[s2];
+    return RAFT_OK;
+}
+
+}  // extern "C"
+
+// ---- hierarchical model selection (Alg. 1) --------------------------------
+
+namespace {
+
+struct HierLayout {
+    int n = 0, d = 0, max_sets = 0, max_slots = 0;
+    int32_t *perm, *perm_next, *setid, *setid_next, *leaf, *pick, *ridx, *rlow, *n32, *active,
+        *changed, *iters, *live, *cursor, *block_of, *meta;
+    int8_t* side;
+    double* rval;
+    float *C, *cnorm;
+    long long *S64, *counts;
+    uint32_t* zmax;
+    size_t bytes = 0;
+};
+
+// Points per work-group of the level kernels.
+constexpr int kHierPts = 256;
+
+void hier_layout(int n, int d, char* base, HierLayout& H) {
+    H.n = n;
+    H.d = d;
+    // the sets of a level are disjoint and non-empty: at most n of them; a
+    // set has at most ceil(cnt / kHierPts) race work-groups, at most
+    // sets + n / kHierPts in total
+    H.max_sets = n + 2;
+    H.max_slots = H.max_sets + n / kHierPts + 1;
+    Arena a;
+    a.base = base;
+    H.perm = a.take<int32_t>(n);
+    H.perm_next = a.take<int32_t>(n);
+    H.setid = a.take<int32_t>(n);
+    H.setid_next = a.take<int32_t>(n);
+    H.leaf = a.take<int32_t>(n);
+    H.side = a.take<int8_t>(n);
+    H.pick = a.take<int32_t>((size_t)2 * H.max_sets);
+    H.rval = a.take<double>(H.max_slots);
+    H.ridx = a.take<int32_t>(H.max_slots);
+    H.rlow = a.take<int32_t>(H.max_slots);
+    H.C = a.take<float>((size_t)2 * H.max_sets * d);
+    H.cnorm = a.take<float>((size_t)2 * H.max_sets);
+    H.S64 = a.take<long long>((size_t)2 * H.max_sets * d);
+    H.n32 = a.take<int32_t>((size_t)2 * H.max_sets);
+    H.active = a.take<int32_t>(H.max_sets);
+    H.changed = a.take<int32_t>(H.max_sets);
+    H.iters = a.take<int32_t>(H.max_sets);
+    H.live = a.take<int32_t>(1);
+    H.counts = a.take<long long>((size_t)7 * H.max_sets);
+    H.cursor = a.take<int32_t>(H.max_sets);
+    H.zmax = a.take<uint32_t>(1);
+    // per level: beg, cnt, need, tnode [max_sets each], child [2 max_sets],
+    // two tables [2 (2 max_sets + 1)]
+    H.meta = a.take<int32_t>((size_t)6 * H.max_sets + 2 * (2 * (size_t)H.max_sets + 1));
+    // block number of every tree node (at most 2 n tree nodes)
+    H.block_of = a.take<int32_t>((size_t)2 * n + 1);
+    H.bytes = a.off;
+}
+
+HostTable make_table_unpadded(const std::vector<int>& counts) {
+    HostTable t;
+    const int G = (int)counts.size();
+    t.start.assign(G + 1, 0);
+    t.count = counts;
+    for (int g = 0; g < G; ++g) t.start[g + 1] = t.start[g] + counts[g];
+    t.grid = t.start[G];
+    return t;
+}
+
+// Eq. 7 in FP64 from integer counts, blocks in order (m: intra edges, v:
+// G-volumes), left to right as written.
+double lmod_fp64(const int64_t* m, const int64_t* v, int k) {
+    int64_t two_e = 0;
+    for (int r = 0; r < k; ++r) two_e += v[r];
+    const double e = (double)two_e / 2.0;
+    double total = 0.0;
+    for (int r = 0; r < k; ++r) {
+        const double t = (double)v[r] / (double)two_e;
+        total = total + ((double)m[r] / e - t * t);
+    }
+    return total;
+}
+
+}  // namespace
+
+extern "C" {
+
+raft_status raft_hier_workspace_size(raft_ctx* ctx, const raft_graph* g, int32_t d,
+                                     size_t* bytes) {
+    RAFT_TRY(check_graph(ctx, g));
+    if (!bytes) return fail(ctx, RAFT_E_INVAL, "bytes is null");
+    if (!kmeans_supported(d)) return fail(ctx, RAFT_E_UNSUPPORTED, "width %d", d);
+    HierLayout H;
+    hier_layout(g->n, d, nullptr, H);
+    *bytes = H.bytes;
+    return RAFT_OK;
+}
+
+raft_status raft_hier_partition(raft_ctx* ctx, const raft_graph* g, const float* Z, int32_t d,
+                                const raft_hier_config* cfg, void* ws, size_t ws_bytes,
+                                int32_t* labels, int32_t* n_blocks, raft_hier_node* tree,
+                                int32_t tree_cap, int32_t* n_tree, int32_t* node_trace,
+                                int32_t trace_depth, void* stream) {
+    RAFT_TRY(check_graph(ctx, g));
+    if (!Z || !cfg || !labels || !n_blocks) return fail(ctx, RAFT_E_INVAL, "null argument");
+    if (!kmeans_supported(d)) return fail(ctx, RAFT_E_UNSUPPORTED, "width %d", d);
+    if (cfg->eps < 0 || cfg->t_max < 1) return fail(ctx, RAFT_E_INVAL, "eps %d t_max %d", cfg->eps, cfg->t_max);
+    if (node_trace && trace_depth < 0) return fail(ctx, RAFT_E_INVAL, "trace_depth");
+    const int n = g->n;
+    HierLayout H;
+    hier_layout(n, d, nullptr, H);
+    RAFT_TRY(check_ws(ctx, ws, ws_bytes, H.bytes));
+    hier_layout(n, d, reinterpret_cast<char*>(ws), H);
+    hipStream_t st = as_stream(stream);
+    const GraphView gv = g->view();
+    int64_t* hbuf = reinterpret_cast<int64_t*>(ctx->h_pinned);   // pinned scratch (16 KiB)
+    // setup: identity permutation, one set, scale of the fixed-point sums
+    launch_hier_setup(Z, (int64_t)n * d, H.zmax, H.perm, H.setid, H.setid_next, H.side, H.leaf,
+                      n, st);
+    if (node_trace && trace_depth > 0) launch_fill_i32(node_trace, (int64_t)trace_depth * n, -1, st);
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->h_pinned, H.zmax, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    int fexp = 0;
+    {
+        float zmax;
+        memcpy(&zmax, ctx->h_pinned, sizeof zmax);
+        if (zmax > 0.f) {
+            int ez;
+            std::frexp(zmax, &ez);
+            fexp = 30 - ez;
+        }
+    }
+    struct SetInfo {
+        int beg, cnt, tnode;
+    };
+    std::vector<raft_hier_node> nodes;
+    nodes.push_back(raft_hier_node{0, n, -1, {-1, -1}, -1, 0, {0, 0}, NAN, NAN});
+    std::vector<SetInfo> sets = {{0, n, 0}};
+    const int eps = cfg->eps;
+    int depth = 0;
+    std::vector<int32_t> meta;
+    std::vector<int64_t> cnt_host;
+    while (!sets.empty()) {
+        const int ns = (int)sets.size();
+        if (ns > H.max_sets) return fail(ctx, RAFT_E_INVAL, "hierarchy level of %d sets", ns);
+        // per-set arrays and the two launch tables of the level
+        std::vector<int> ck(ns), ca(ns);
+        meta.assign((size_t)6 * H.max_sets + 2 * (2 * (size_t)H.max_sets + 1), 0);
+        int32_t* m_beg = meta.data();
+        int32_t* m_cnt = m_beg + H.max_sets;
+        int32_t* m_need = m_cnt + H.max_sets;
+        int32_t* m_tnode = m_need + H.max_sets;
+        int32_t* m_child = m_tnode + H.max_sets;   // 2 max_sets
+        int32_t* m_tk = m_child + 2 * H.max_sets;  // table of the KMeans kernels
+        int32_t* m_ta = m_tk + 2 * H.max_sets + 1; // table of the per-node kernels
+        bool any_need = false;
+        for (int s2 = 0; s2 < ns; ++s2) {
+            m_beg[s2] = sets[s2].beg;
+            m_cnt[s2] = sets[s2].cnt;
+            m_tnode[s2] = sets[s2].tnode;
+            const bool need = sets[s2].cnt > 2 * eps + 1;
+            m_need[s2] = need;
+            any_need |= need;
+            ca[s2] = (sets[s2].cnt + kHierPts - 1) / kHierPts;
+            ck[s2] = need ? ca[s2] : 0;
+            m_child[2 * s2] = m_child[2 * s2 + 1] = -1;
+        }
+        const HostTable tk = make_table_unpadded(ck), ta = make_table_unpadded(ca);
+        if (tk.grid > H.max_slots) return fail(ctx, RAFT_E_INVAL, "race slots");
+        std::copy(tk.start.begin(), tk.start.end(), m_tk);
+        std::copy(tk.count.begin(), tk.count.end(), m_tk + ns + 1);
+        std::copy(ta.start.begin(), ta.start.end(), m_ta);
+        std::copy(ta.count.begin(), ta.count.end(), m_ta + ns + 1);
+        HIP_TRY(ctx, hipMemcpyAsync(H.meta, meta.data(), meta.size() * sizeof(int32_t),
+                                    hipMemcpyHostToDevice, st));
+        HierPlan h;
+        h.Z = Z;
+        h.d = d;
+        h.seed = cfg->seed;
+        h.depth = depth;
+        h.fexp = fexp;
+        h.beg = H.meta;
+        h.cnt = H.meta + H.max_sets;
+        h.need = H.meta + 2 * H.max_sets;
+        h.tnode = H.meta + 3 * H.max_sets;
+        h.child = H.meta + 4 * H.max_sets;
+        h.perm = (depth & 1) ? H.perm_next : H.perm;
+        h.perm_next = (depth & 1) ? H.perm : H.perm_next;
+        h.setid = (depth & 1) ? H.setid_next : H.setid;
+        h.setid_next = (depth & 1) ? H.setid : H.setid_next;
+        h.side = H.side;
+        h.leaf = H.leaf;
+        h.pick = H.pick;
+        h.rval = H.rval;
+        h.ridx = H.ridx;
+        h.rlow = H.rlow;
+        h.C = H.C;
+        h.cnorm = H.cnorm;
+        h.S64 = H.S64;
+        h.n32 = H.n32;
+        h.active = H.active;
+        h.changed = H.changed;
+        h.iters = H.iters;
+        h.live = H.live;
+        h.counts = H.counts;
+        h.cursor = H.cursor;
+        BatchTable btk{H.meta + 6 * H.max_sets, H.meta + 6 * H.max_sets + ns + 1, ns};
+        BatchTable bta{H.meta + 6 * H.max_sets + 2 * H.max_sets + 1,
+                       H.meta + 6 * H.max_sets + 2 * H.max_sets + 1 + ns + 1, ns};
+        launch_fill_i64(H.counts, (int64_t)7 * ns, st);
+        launch_fill_i32(H.iters, ns, 0, st);
+        if (any_need) {
+            for (int t = 0; t < 2; ++t) {
+                launch_hier(kHierRace, h, gv, d, t, 0, ns, btk, tk.grid, st);
+                launch_hier(kHierPick, h, gv, d, t, 0, ns, btk, 0, st);
+            }
+            launch_hier(kHierInit, h, gv, d, 0, 0, ns, btk, 0, st);
+            for (int it = 1; it <= cfg->t_max; ++it) {
+                launch_fill_i32(H.live, 1, 0, st);
+                launch_hier(kHierAssign, h, gv, d, it, cfg->t_max, ns, btk, tk.grid, st);
+                launch_hier(kHierUpdate, h, gv, d, it, cfg->t_max, ns, btk, 0, st);
+                HIP_TRY(ctx, hipMemcpyAsync(ctx->h_pinned, H.live, sizeof(int32_t),
+                                            hipMemcpyDeviceToHost, st));
+                HIP_TRY(ctx, hipStreamSynchronize(st));
+                if (ctx->h_pinned[0] == 0) break;
+            }
+        }
+        launch_hier(kHierCounts, h, gv, d, 0, 0, ns, bta, ta.grid, st);
+        RAFT_TRY(launch_check(ctx));
+        cnt_host.resize((size_t)8 * ns);
+        HIP_TRY(ctx, hipMemcpyAsync(cnt_host.data(), H.counts, sizeof(int64_t) * 7 * ns,
+                                    hipMemcpyDeviceToHost, st));
+        std::vector<int32_t> its(ns);
+        HIP_TRY(ctx, hipMemcpyAsync(its.data(), H.iters, sizeof(int32_t) * ns,
+                                    hipMemcpyDeviceToHost, st));
+        HIP_TRY(ctx, hipStreamSynchronize(st));
+        // decisions (Alg. 1), children and the next level's sets
+        std::vector<SetInfo> next;
+        std::vector<int32_t> cursor;
+        for (int s2 = 0; s2 < ns; ++s2) {
+            const int64_t* c = cnt_host.data() + (size_t)7 * s2;
+            raft_hier_node& nd = nodes[sets[s2].tnode];
+            const int64_t vol[2] = {c[5], c[6]};
+            const int64_t volU = vol[0] + vol[1];
+            const int64_t mU = c[0] / 2;
+            bool split = false;
+            if (volU > 0) {
+                const int64_t mv[1] = {mU}, vv[1] = {volU};
+                nd.m1 = lmod_fp64(mv, vv, 1);
+            }
+            if (m_need[s2] && volU > 0) {
+                const int64_t ms[2] = {c[1] / 2, c[2] / 2};
+                nd.m2 = lmod_fp64(ms, vol, 2);
+                nd.sizes[0] = (int32_t)c[3];
+                nd.sizes[1] = (int32_t)c[4];
+                nd.kmeans_iters = its[s2];
+                split = !(c[3] <= eps || c[4] <= eps || nd.m1 > nd.m2);
+            } else if (m_need[s2]) {
+                nd.sizes[0] = (int32_t)c[3];
+                nd.sizes[1] = (int32_t)c[4];
+                nd.kmeans_iters = its[s2];
+            }
+            if (!split) continue;
+            for (int a2 = 0; a2 < 2; ++a2) {
+                const int tn = (int)nodes.size();
+                const int beg = sets[s2].beg + (a2 ? (int)c[3] : 0);
+                const int cnt2 = (int)c[3 + a2];
+                nodes.push_back(raft_hier_node{depth + 1, cnt2, sets[s2].tnode, {-1, -1}, -1, 0,
+                                               {0, 0}, NAN, NAN});
+                nodes[sets[s2].tnode].child[a2] = tn;
+                m_child[2 * s2 + a2] = (int)next.size();
+                next.push_back({beg, cnt2, tn});
+                cursor.push_back(beg);
+            }
+        }
+        if (next.size() > (size_t)H.max_sets) return fail(ctx, RAFT_E_INVAL, "next level sets");
+        HIP_TRY(ctx, hipMemcpyAsync(H.meta + 4 * H.max_sets, m_child, sizeof(int32_t) * 2 * ns,
+                                    hipMemcpyHostToDevice, st));
+        if (!cursor.empty())
+            HIP_TRY(ctx, hipMemcpyAsync(H.cursor, cursor.data(), sizeof(int32_t) * cursor.size(),
+                                        hipMemcpyHostToDevice, st));
+        if (node_trace && depth < trace_depth)
+            launch_hier_trace(h, node_trace + (size_t)depth * n, bta, ta.grid, st);
+        launch_hier(kHierScatter, h, gv, d, 0, 0, ns, bta, ta.grid, st);
+        RAFT_TRY(launch_check(ctx));
+        HIP_TRY(ctx, hipStreamSynchronize(st));   // meta / cursor sources are host vectors
+        sets.swap(next);
+        ++depth;
+    }
+    // blocks in the order Alg. 1 adds them: depth first, U_1 before U_2
+    std::vector<int32_t> block_of(nodes.size(), -1);
+    int nb = 0;
+    std::vector<int> stack = {0};
+    while (!stack.empty()) {
+        const int t = stack.back();
+        stack.pop_back();
+        if (nodes[t].child[0] < 0) {
+            nodes[t].block = nb;
+            block_of[t] = nb++;
+            continue;
+        }
+        stack.push_back(nodes[t].child[1]);
+        stack.push_back(nodes[t].child[0]);
+    }
+    if (nodes.size() > (size_t)2 * n + 1) return fail(ctx, RAFT_E_INVAL, "tree size");
+    HIP_TRY(ctx, hipMemcpyAsync(H.block_of, block_of.data(), sizeof(int32_t) * block_of.size(),
+                                hipMemcpyHostToDevice, st));
+    launch_hier_labels(H.leaf, H.block_of, n, labels, st);
+    RAFT_TRY(launch_check(ctx));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    (void)hbuf;
+    *n_blocks = nb;
+    if (n_tree) *n_tree = (int32_t)nodes.size();
+    if (tree)
+        for (size_t t = 0; t < nodes.size() && (int)t < tree_cap; ++t) tree[t] = nodes[t];
     return RAFT_OK;
 }
 

@@ -263,6 +263,58 @@ int score_blocks(const ScorePlan& p, int kind);
 void launch_score_batched(int kind, const GraphView* views, const ScorePlan* plans, int S, int SK,
                           const BatchTable& t, int grid, hipStream_t st);
 
+// ---- hier.hip ------------------------------------------------------------
+// State of one level of the hierarchical model selection (Alg. 1): the sets
+// being partitioned, each a segment [beg, beg + cnt) of the node permutation.
+struct HierPlan {
+    const float* Z;          // [n x d]
+    int32_t d;
+    uint64_t seed;           // Philox key word 0 of the K = 2 race
+    int32_t depth;           // level of the sets in the tree (race counter word 2)
+    int32_t fexp;            // fixed-point exponent of the centre sums
+    const int32_t* beg;      // [nsets]
+    const int32_t* cnt;      // [nsets]
+    const int32_t* need;     // [nsets] 1: run KMeans (|U| > 2 eps + 1)
+    const int32_t* child;    // [2 nsets] next-level set of each side, -1: U is a block
+    const int32_t* tnode;    // [nsets] tree node of the set
+    int32_t* perm;           // [n] this level's segments
+    int32_t* perm_next;      // [n]
+    int32_t* setid;          // [n] set of each node at this level (-1: in a block)
+    int32_t* setid_next;     // [n]
+    int8_t* side;            // [n] side of each node in its set's split
+    int32_t* leaf;           // [n] tree node of the block holding the node
+    int32_t* pick;           // [2 nsets]
+    double* rval;            // [race grid] per-work-group race minima
+    int32_t* ridx;           // [race grid]
+    int32_t* rlow;           // [race grid] lowest node id other than pick 0
+    float* C;                // [nsets x 2 x d]
+    float* cnorm;            // [nsets x 2]
+    long long* S64;          // [nsets x 2 x d] fixed-point sums of the sides
+    int32_t* n32;            // [nsets x 2]
+    int32_t* active;         // [nsets]
+    int32_t* changed;        // [nsets]
+    int32_t* iters;          // [nsets]
+    int32_t* live;           // [1] sets still iterating after an update
+    long long* counts;       // [nsets x 7] integer counts of Eq. 7
+    int32_t* cursor;         // [next nsets] fill positions of the children's segments
+};
+enum HierKind { kHierRace, kHierPick, kHierInit, kHierAssign, kHierUpdate, kHierCounts,
+                kHierScatter };
+void launch_hier(int kind, const HierPlan& h, const GraphView& g, int d, int t, int t_max,
+                 int nsets, const BatchTable& tb, int grid, hipStream_t st);
+void launch_hier_trace(const HierPlan& h, int32_t* out, const BatchTable& tb, int grid,
+                       hipStream_t st);
+void launch_hier_labels(const int32_t* leaf, const int32_t* block_of, int n, int32_t* labels,
+                        hipStream_t st);
+// zmax_bits = bits of the largest |Z| (zeroed first); perm = 0..n-1,
+// setid = setid_next = 0, side = 0, leaf = -1.
+void launch_hier_setup(const float* Z, int64_t total, uint32_t* zmax_bits, int32_t* perm,
+                       int32_t* setid, int32_t* setid_next, int8_t* side, int32_t* leaf, int n,
+                       hipStream_t st);
+// Clears count arrays of the level (a kernel, no memset).
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
+void launch_fill_i64(long long* p, int64_t n, hipStream_t st);
+
 // ---- confusion.hip -------------------------------------------------------
 // counts [ka x kb] int64 (zeroed here) = joint histogram of labels a, b [n];
 // a label out of range sets kStatusLabel and is not counted.

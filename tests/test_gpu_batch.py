@@ -115,3 +115,66 @@ def test_batch_against_oracle(ctx, api_mod):
     b.close()
     for g in gs:
         g.close()
+
+
+@pytest.fixture(scope="module")
+def batch64():
+    from synth.workloads import make_batch
+    return make_batch(64)
+
+
+def test_batch64_equals_single(ctx, api_mod, batch64):
+    """The batched workload in the benchmark's launch configuration (64 graphs
+    of 1k..50k nodes, 0.87 M nodes and 20 M stored entries in one
+    block-diagonal CSR, modularity variant, K 2..64): every graph's labels,
+    scores, K* and picks equal its single-graph run bit for bit."""
+    graphs, method = batch64
+    cfg = api_mod.Config(op=1, **method)
+    print(f"batch64: N={sum(g.n for g in graphs)} nnz={sum(g.nnz for g in graphs)}", flush=True)
+    gs = [api_mod.Graph(ctx, g.row_ptr, g.col_idx) for g in graphs]
+    b = api_mod.Batch(ctx, gs, cfg)
+    out = b.run()
+    torch.cuda.synchronize()
+    ctx.sync_status()
+    print("batch64: batch run done", flush=True)
+    ws = ctx.workspace(max(api_mod.workspace_size(ctx, g, cfg) for g in gs))
+    for i, (g, o) in enumerate(zip(gs, out)):
+        r = api_mod.run(ctx, g, cfg, ws=ws, want_y=False, want_z=False)
+        torch.cuda.synchronize()
+        for f in ["labels", "k_selected", "mod", "ncut", "labels_all", "picks", "iters"]:
+            assert torch.equal(o[f], r[f]), (i, f)
+    b.close()
+    for g in gs:
+        g.close()
+
+
+def test_tuner_cache_roundtrip(api_mod, tmp_path):
+    """The launch-shape tuner times its candidates on the first run of a new
+    workload, writes the choice to the context's cache file, and a new context
+    reading that file reuses it without timing; outputs are the same."""
+    cache = str(tmp_path / "tune.txt")
+    graphs = small_batch()
+    cfg = api_mod.Config(op=1, proj_dim=32, q=3, layer_dims=[32, 32], k_min=2, k_max=12)
+    outs = []
+    for round_ in range(2):
+        c = api_mod.Context(0, autotune_cache=cache)
+        gs = [api_mod.Graph(c, g.row_ptr, g.col_idx) for g in graphs]
+        b = api_mod.Batch(c, gs, cfg)
+        o = b.run()
+        torch.cuda.synchronize()
+        factor, timed = b.tuning()
+        if round_ == 0:
+            assert len(timed) >= 2 and factor in [f for f, _ in timed]
+            first = factor
+        else:
+            assert timed == [] and factor == first
+        outs.append([{k: to_np(v).copy() for k, v in x.items()} for x in o])
+        b.close()
+        for g in gs:
+            g.close()
+        c.close()
+    with open(cache) as f:
+        assert "batch G=6" in f.read()
+    for a, b2 in zip(outs[0], outs[1]):
+        for k in a:
+            assert np.array_equal(a[k], b2[k]), k
