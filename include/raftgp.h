@@ -173,6 +173,20 @@ raft_status raft_spmm(raft_ctx* ctx, const raft_graph* g, int32_t op, int32_t L,
 raft_status raft_spmm_noalloc(raft_ctx* ctx, const raft_graph* g, int32_t op, int32_t L,
                               const float* Y_in, float* Y_out, void* stream);
 
+/* raft_spmm with the work split by the merge path of the CSR (Merrill and
+ * Garland 2016) instead of by rows: the N row ends and nnz stored entries
+ * are cut into equal ranges of 256 path items, whatever the row lengths, so
+ * heavy-tailed degrees cost no imbalance; rows cut by a range boundary are
+ * finished by a fix-up pass that adds their pieces in range order
+ * (deterministic).  Same operators and layouts as raft_spmm; results equal
+ * raft_spmm's up to FP32 summation order.  Workspace: the range partials
+ * (raft_spmm_merge_workspace_size), plus the column sums for MOD_FULL. */
+raft_status raft_spmm_merge_workspace_size(raft_ctx* ctx, const raft_graph* g, int32_t op,
+                                           int32_t L, size_t* bytes);
+raft_status raft_spmm_merge(raft_ctx* ctx, const raft_graph* g, int32_t op, int32_t L,
+                            const float* Y_in, float* Y_out, void* ws, size_t ws_bytes,
+                            void* stream);
+
 /* Y = X^q Theta (Sec. III-A, Eq. 5 with q powers), Theta drawn as in
  * raft_gaussian with cfg->seed.  Y_out [N x L]. */
 raft_status raft_project(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg,

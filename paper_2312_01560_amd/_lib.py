@@ -28,6 +28,7 @@ EXPORTS = [
     "raft_spmm_noalloc", "raft_batch_create", "raft_batch_destroy", "raft_batch_workspace_size",
     "raft_batch_run", "raft_batch_set_capture", "raft_batch_plan_check", "raft_batch_stage_times",
     "raft_batch_tuning", "raft_hier_workspace_size", "raft_hier_partition",
+    "raft_spmm_merge_workspace_size", "raft_spmm_merge",
 ]
 
 PROF_SPMM, PROF_DENSE, PROF_RACE, PROF_ASSIGN, PROF_UPDATE, PROF_SCORE = range(6)
@@ -138,6 +139,8 @@ _SIGNATURES = {
     "raft_batch_tuning": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_double), _I32,
                                  ctypes.POINTER(_I32)]),
     "raft_hier_workspace_size": (_I32, [_P, _P, _I32, ctypes.POINTER(_SZ)]),
+    "raft_spmm_merge_workspace_size": (_I32, [_P, _P, _I32, _I32, ctypes.POINTER(_SZ)]),
+    "raft_spmm_merge": (_I32, [_P, _P, _I32, _I32, _P, _P, _P, _SZ, _P]),
     "raft_hier_partition": (_I32, [_P, _P, _P, _I32, ctypes.POINTER(RaftHierConfig), _P, _SZ, _P,
                                    ctypes.POINTER(_I32), ctypes.POINTER(RaftHierNode), _I32,
                                    ctypes.POINTER(_I32), _P, _I32, _P]),

@@ -192,6 +192,20 @@ def spmm(ctx, g, op, Y, out=None, ws=None):
     return out
 
 
+def spmm_merge(ctx, g, op, Y, out=None, ws=None):
+    """raft_spmm_merge: the merge-path split of the same product."""
+    Y = Y.contiguous()
+    L = Y.shape[1]
+    out = ctx.empty((g.n, L), torch.float32) if out is None else out
+    need = ctypes.c_size_t()
+    ctx.check(ctx.lib.raft_spmm_merge_workspace_size(ctx.h, g.h, op, L, ctypes.byref(need)))
+    if ws is None or ws.numel() < need.value:
+        ws = ctx.workspace(need.value)
+    ctx.check(ctx.lib.raft_spmm_merge(ctx.h, g.h, op, L, Y.data_ptr(), out.data_ptr(),
+                                      ws.data_ptr(), ws.numel(), _stream()))
+    return out
+
+
 def spmm_noalloc(ctx, g, op, Y, out):
     """raft_spmm_noalloc: the caller passes the output; the library allocates
     nothing (MOD_FULL's partials live in its fixed per-GPU scratch)."""

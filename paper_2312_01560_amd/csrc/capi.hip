@@ -1026,6 +1026,43 @@ raft_status raft_spmm_noalloc(raft_ctx* ctx, const raft_graph* g, int32_t op, in
     return spmm_body(ctx, g, op, L, Y_in, Y_out, ctx->scratch, as_stream(stream));
 }
 
+raft_status raft_spmm_merge_workspace_size(raft_ctx* ctx, const raft_graph* g, int32_t op,
+                                           int32_t L, size_t* bytes) {
+    RAFT_TRY(check_graph(ctx, g));
+    if (!bytes) return fail(ctx, RAFT_E_INVAL, "bytes is null");
+    if (op < RAFT_X_NCUT || op > RAFT_X_GCN) return fail(ctx, RAFT_E_INVAL, "op %d", op);
+    if (!spmm_supported(L)) return fail(ctx, RAFT_E_UNSUPPORTED, "width %d", L);
+    *bytes = align256(spmm_merge_ws_bytes(g->n, g->nnz, L, op)) +
+             (op == RAFT_X_MOD_FULL ? spmm_ws_bytes(ctx, g, L) : 0);
+    return RAFT_OK;
+}
+
+raft_status raft_spmm_merge(raft_ctx* ctx, const raft_graph* g, int32_t op, int32_t L,
+                            const float* Y_in, float* Y_out, void* ws, size_t ws_bytes,
+                            void* stream) {
+    RAFT_TRY(spmm_checks(ctx, g, op, L, Y_in, Y_out));
+    size_t need = 0;
+    RAFT_TRY(raft_spmm_merge_workspace_size(ctx, g, op, L, &need));
+    RAFT_TRY(check_ws(ctx, ws, ws_bytes, need));
+    hipStream_t st = as_stream(stream);
+    const GraphView gv = g->view();
+    char* w = reinterpret_cast<char*>(ws);
+    const float* cvec = nullptr;
+    if (op == RAFT_X_MOD_FULL) {
+        Arena a;
+        a.base = w + align256(spmm_merge_ws_bytes(g->n, g->nnz, L, op));
+        const int grid = spmm_grid(g->n, L, ctx->num_cu, nullptr);
+        double* cpart = a.take<double>(((size_t)grid + kColsumStageRows) * L);
+        double* c64 = a.take<double>(L);
+        float* cv = a.take<float>(L);
+        launch_colsum_partials(gv, L, Y_in, cpart, ctx->num_cu, st);
+        launch_colsum_finish(cpart, grid, L, c64, cv, st);
+        cvec = cv;
+    }
+    launch_spmm_merge(gv, op, L, Y_in, Y_out, cvec, w, st);
+    return launch_check(ctx);
+}
+
 raft_status raft_project(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg, void* ws,
                          size_t ws_bytes, float* Y_out, void* stream) {
     RAFT_TRY(check_graph(ctx, g));

@@ -70,6 +70,14 @@ constexpr int kColsumStageRows = 64;
 void launch_colsum_finish(const double* part, int parts, int L, double* c64, float* cvec,
                           hipStream_t st);
 
+// Merge-path SpMM (work split evenly over row ends + stored entries):
+// workspace bytes for (n, nnz, L, op) and the launch (a range pass and a
+// fix-up pass).  No column-sum epilogue.
+int spmm_merge_ranges(int32_t n, int64_t nnz);
+size_t spmm_merge_ws_bytes(int32_t n, int64_t nnz, int L, int op);
+void launch_spmm_merge(const GraphView& g, int op, int L, const float* x, float* y,
+                       const float* cvec, void* ws, hipStream_t st);
+
 // Grid of one graph's SpMM launch; R = rows per row block, nrb = row blocks.
 int spmm_launch_shape(int32_t n, int L, int num_cu, int* R, int* nrb);
 struct SpmmItem {

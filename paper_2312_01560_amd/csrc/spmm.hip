@@ -46,15 +46,19 @@ struct SpmmGeom {
     static constexpr int G = kWave / LANES;      // rows side by side per wave
 };
 
+// fixed_slice < 0: work-groups of all slices side by side, each XCD on its own
+// slices; fixed_slice = s: one launch per slice (all work-groups on slice s,
+// row block = block index), so only one slice of X is live at a time.
 template <int L, int OP, bool CS>
 __device__ __forceinline__ void spmm_body(const GraphView& g, const float* __restrict__ x,
                                           float* __restrict__ y, const float* __restrict__ cvec,
-                                          double* __restrict__ cpart, int R, int nrb, int b) {
+                                          double* __restrict__ cpart, int R, int nrb, int b,
+                                          int fixed_slice = -1) {
     using GE = SpmmGeom<L>;
     constexpr int W = GE::W, LANES = GE::LANES, G = GE::G, XS = GE::XS;
     const int xcd = b % 8;
-    const int sl = xcd / XS;                        // column slice
-    const int rb = (b / 8) * XS + xcd % XS;         // row block
+    const int sl = fixed_slice >= 0 ? fixed_slice : xcd / XS;            // column slice
+    const int rb = fixed_slice >= 0 ? b : (b / 8) * XS + xcd % XS;       // row block
     if (rb >= nrb) return;                          // uniform: padding of the grid
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
@@ -189,8 +193,9 @@ template <int L, int OP, bool CS>
 __global__ __launch_bounds__(256) void k_spmm(GraphView g, const float* __restrict__ x,
                                               float* __restrict__ y,
                                               const float* __restrict__ cvec,
-                                              double* __restrict__ cpart, int R, int nrb) {
-    spmm_body<L, OP, CS>(g, x, y, cvec, cpart, R, nrb, (int)blockIdx.x);
+                                              double* __restrict__ cpart, int R, int nrb,
+                                              int fixed_slice) {
+    spmm_body<L, OP, CS>(g, x, y, cvec, cpart, R, nrb, (int)blockIdx.x, fixed_slice);
 }
 
 // Batched: one launch over the graphs of a block-diagonal CSR, each graph's
@@ -333,6 +338,280 @@ __global__ __launch_bounds__(256) void k_colsum_finish_b(const ColsumItem* __res
     colsum_finish_body(it.part + (size_t)it.parts * L, L, it.c64, it.cvec);
 }
 
+// ---- merge-path SpMM -------------------------------------------------------
+// The same products with the work split evenly along the merge path of the
+// CSR (Merrill & Garland, SC'16): the path interleaves the N row ends with the
+// nnz stored entries (an entry e of row i comes before the end of row i), and
+// each lane group takes kMergeT consecutive path items for one column slice,
+// whatever the row lengths.  A group finds its start and end coordinates
+// (row, entry) by binary search on the row pointers, gathers the feature rows
+// of its entries in batches of 16 (indices first, then the rows back to back)
+// and sums them row by row in entry order.  A row that ends in the group's
+// range and began there is finished in place (epilogue and store); a row
+// still open at the end of the range leaves its partial sum as the range's
+// carry, and a row that began in an earlier range and ends in this one leaves
+// its last partial as the range's head; a fix-up pass adds, for every head,
+// the carries of the earlier ranges of that row in range order and applies
+// the epilogue, so the result does not depend on scheduling.
+constexpr int kMergeT = 256;
+
+// Merge-path coordinate of diagonal k: (row i, entry e) with i + e = k, i the
+// number of row ends before the k-th path item.
+__device__ __forceinline__ void merge_search(const int32_t* __restrict__ rp, int n, int64_t nnz,
+                                             int64_t k, int& i, int& e) {
+    int64_t lo = k - nnz > 0 ? k - nnz : 0;
+    int64_t hi = k < n ? k : n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)rp[mid + 1] <= k - mid - 1)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    i = (int)lo;
+    e = (int)(k - lo);
+}
+
+template <int OP>
+__device__ __forceinline__ float4 merge_epilogue(const GraphView& g, int i, float4 acc, float4 acc2,
+                                                 const float* __restrict__ x, int L, int cofs,
+                                                 const float* __restrict__ cvec) {
+    if (OP == kOpNcut) {
+        const float si = g.s[i];
+        return make_float4(si * acc.x, si * acc.y, si * acc.z, si * acc.w);
+    }
+    if (OP == kOpGcn) {
+        const float si = g.sh[i];
+        const float4 xi = *reinterpret_cast<const float4*>(x + (size_t)i * L + cofs);
+        return make_float4(si * (acc.x + si * xi.x), si * (acc.y + si * xi.y),
+                           si * (acc.z + si * xi.z), si * (acc.w + si * xi.w));
+    }
+    if (OP == kOpModFull) {
+        const float ci = g.dcoef[i];
+        const float4 c = *reinterpret_cast<const float4*>(cvec + cofs);
+        return make_float4(acc.x - ci * c.x, acc.y - ci * c.y, acc.z - ci * c.z, acc.w - ci * c.w);
+    }
+    const float ci = g.dcoef[i];
+    return make_float4(acc.x - ci * acc2.x, acc.y - ci * acc2.y, acc.z - ci * acc2.z,
+                       acc.w - ci * acc2.w);
+}
+
+// Partial buffers: part[(2 r + q) L + col], r = range, q = 0 carry, 1 head;
+// MOD_REDUCED keeps its second sum (sum d_j x_j) at part2 with the same
+// layout.  prow[2 r + q] = the row of that partial, -1 for none.
+template <int L, int OP>
+__global__ __launch_bounds__(256) void k_spmm_merge(GraphView g, const float* __restrict__ x,
+                                                    float* __restrict__ y,
+                                                    const float* __restrict__ cvec,
+                                                    float* __restrict__ part,
+                                                    float* __restrict__ part2,
+                                                    int32_t* __restrict__ prow, int nranges) {
+    using GE = SpmmGeom<L>;
+    constexpr int W = GE::W, LANES = GE::LANES, G = GE::G, XS = GE::XS;
+    const int b = blockIdx.x;
+    const int xcd = b % 8;
+    const int sl = xcd / XS;
+    const int rbk = (b / 8) * XS + xcd % XS;       // block of ranges
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int slot = lane / LANES;
+    const int sub = lane % LANES;
+    const int r = (rbk * kSpmmWaves + wid) * G + slot;
+    const int cofs = sl * W + sub * 4;
+    if (r >= nranges) return;                       // whole lane groups: no wave-wide sync below
+    const int64_t total = (int64_t)g.n + g.nnz;
+    const int64_t k0 = (int64_t)r * kMergeT;
+    const int64_t k1 = k0 + kMergeT < total ? k0 + kMergeT : total;
+    int i0, e0, i1, e1;
+    merge_search(g.rp, g.n, g.nnz, k0, i0, e0);
+    merge_search(g.rp, g.n, g.nnz, k1, i1, e1);
+    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 acc = zero, acc2 = zero;
+    int i = i0;
+    int rend = i < g.n ? g.rp[i + 1] : e1;
+    const bool began_before = i0 < g.n && e0 > g.rp[i0];
+    bool first = true;
+    bool any = false;                               // an entry of row i summed in this range
+    // closes row i (every row ending before entry e, or before the range end)
+#define MERGE_CLOSE_ROW()                                                                      \
+    {                                                                                          \
+        if (first && began_before) {                                                           \
+            *reinterpret_cast<float4*>(part + (size_t)(2 * r + 1) * L + cofs) = acc;          \
+            if (OP == kOpModReduced)                                                           \
+                *reinterpret_cast<float4*>(part2 + (size_t)(2 * r + 1) * L + cofs) = acc2;    \
+            if (sub == 0 && sl == 0) prow[2 * r + 1] = i;                                      \
+        } else {                                                                               \
+            *reinterpret_cast<float4*>(y + (size_t)i * L + cofs) =                            \
+                merge_epilogue<OP>(g, i, acc, acc2, x, L, cofs, cvec);                         \
+        }                                                                                      \
+        first = false;                                                                         \
+        any = false;                                                                           \
+        acc = zero;                                                                            \
+        acc2 = zero;                                                                           \
+        ++i;                                                                                   \
+        rend = i < g.n ? g.rp[i + 1] : e1;                                                     \
+    }
+    for (int base = e0; base < e1; base += 16) {
+        // the entries [base, base + 16) of the range, gathered back to back
+        int jv[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) jv[q] = base + q < e1 ? g.ci[base + q] : -1;
+        float4 xv[16];
+        float wv[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            xv[q] = zero;
+            wv[q] = 0.f;
+            if (jv[q] >= 0) {
+                xv[q] = *reinterpret_cast<const float4*>(x + (size_t)jv[q] * L + cofs);
+                wv[q] = edge_weight<L, OP>(g, jv[q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int e = base + q;
+            if (e < e1) {
+                // a row ending before entry e ends inside this range (i < i1)
+                while (rend <= e) MERGE_CLOSE_ROW()
+                if (OP == kOpModFull) {
+                    acc.x += xv[q].x;
+                    acc.y += xv[q].y;
+                    acc.z += xv[q].z;
+                    acc.w += xv[q].w;
+                } else if (OP == kOpModReduced) {
+                    acc.x += xv[q].x;
+                    acc.y += xv[q].y;
+                    acc.z += xv[q].z;
+                    acc.w += xv[q].w;
+                    acc2.x += wv[q] * xv[q].x;
+                    acc2.y += wv[q] * xv[q].y;
+                    acc2.z += wv[q] * xv[q].z;
+                    acc2.w += wv[q] * xv[q].w;
+                } else {
+                    acc.x += wv[q] * xv[q].x;
+                    acc.y += wv[q] * xv[q].y;
+                    acc.z += wv[q] * xv[q].z;
+                    acc.w += wv[q] * xv[q].w;
+                }
+                any = true;
+            }
+        }
+    }
+    // the row ends after the last entry of the range
+    while (i < i1) MERGE_CLOSE_ROW()
+#undef MERGE_CLOSE_ROW
+    // row i1 still open at the end of the range
+    const bool carry = any && i1 < g.n;
+    if (carry) {
+        *reinterpret_cast<float4*>(part + (size_t)(2 * r) * L + cofs) = acc;
+        if (OP == kOpModReduced)
+            *reinterpret_cast<float4*>(part2 + (size_t)(2 * r) * L + cofs) = acc2;
+    }
+    if (sub == 0 && sl == 0) {
+        prow[2 * r] = carry ? i1 : -1;
+        if (!(began_before && i1 > i0)) prow[2 * r + 1] = -1;
+    }
+}
+
+// For every range with a head: the carries of the earlier ranges of that row
+// (consecutive ranges ending inside it), in range order, then the head, and
+// the epilogue.
+template <int L, int OP>
+__global__ __launch_bounds__(256) void k_spmm_merge_fix(GraphView g, const float* __restrict__ x,
+                                                        float* __restrict__ y,
+                                                        const float* __restrict__ cvec,
+                                                        const float* __restrict__ part,
+                                                        const float* __restrict__ part2,
+                                                        const int32_t* __restrict__ prow,
+                                                        int nranges) {
+    using GE = SpmmGeom<L>;
+    constexpr int W = GE::W, LANES = GE::LANES, G = GE::G;
+    constexpr int NS = GE::NS;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int slot = lane / LANES;
+    const int sub = lane % LANES;
+    const int gi = (blockIdx.x * kSpmmWaves + wid) * G + slot;   // (range, slice)
+    const int r = gi / NS, sl = gi % NS;
+    if (r >= nranges) return;
+    const int row = prow[2 * r + 1];
+    if (row < 0) return;
+    const int cofs = sl * W + sub * 4;
+    int r0 = r;
+    while (r0 > 0 && prow[2 * (r0 - 1)] == row) --r0;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f), acc2 = acc;
+    for (int q = r0; q <= r; ++q) {
+        const size_t o = (size_t)(2 * q + (q == r ? 1 : 0)) * L + cofs;
+        const float4 v = *reinterpret_cast<const float4*>(part + o);
+        acc.x += v.x;
+        acc.y += v.y;
+        acc.z += v.z;
+        acc.w += v.w;
+        if (OP == kOpModReduced) {
+            const float4 v2 = *reinterpret_cast<const float4*>(part2 + o);
+            acc2.x += v2.x;
+            acc2.y += v2.y;
+            acc2.z += v2.z;
+            acc2.w += v2.w;
+        }
+    }
+    *reinterpret_cast<float4*>(y + (size_t)row * L + cofs) =
+        merge_epilogue<OP>(g, row, acc, acc2, x, L, cofs, cvec);
+}
+
+int spmm_merge_ranges(int32_t n, int64_t nnz) {
+    return (int)(((int64_t)n + nnz + kMergeT - 1) / kMergeT);
+}
+
+size_t spmm_merge_ws_bytes(int32_t n, int64_t nnz, int L, int op) {
+    const size_t nr = (size_t)spmm_merge_ranges(n, nnz);
+    const size_t part = ((nr * 2 * L * sizeof(float)) + 255) / 256 * 256;
+    const size_t rows = ((nr * 2 * sizeof(int32_t)) + 255) / 256 * 256;
+    return part * (op == kOpModReduced ? 2 : 1) + rows;
+}
+
+template <int L>
+static void spmm_merge_op(const GraphView& g, int op, const float* x, float* y, const float* cvec,
+                          char* ws, hipStream_t st) {
+    using GE = SpmmGeom<L>;
+    const int nr = spmm_merge_ranges(g.n, g.nnz);
+    if (nr == 0) return;
+    const size_t part_b = (((size_t)nr * 2 * L * sizeof(float)) + 255) / 256 * 256;
+    float* part = reinterpret_cast<float*>(ws);
+    float* part2 = op == kOpModReduced ? reinterpret_cast<float*>(ws + part_b) : part;
+    int32_t* prow = reinterpret_cast<int32_t*>(ws + part_b * (op == kOpModReduced ? 2 : 1));
+    const int per_block = kSpmmWaves * GE::G;                    // ranges per work-group
+    const int rblocks = (nr + per_block - 1) / per_block;
+    const int grid = (rblocks + GE::XS - 1) / GE::XS * 8;
+    const int fix_grid = (nr * GE::NS + per_block - 1) / per_block;
+#define RAFT_MERGE_CASE(OPV)                                                                   \
+    if (op == OPV) {                                                                           \
+        hipLaunchKernelGGL((k_spmm_merge<L, OPV>), dim3(grid), dim3(256), 0, st, g, x, y, cvec, \
+                           part, part2, prow, nr);                                             \
+        hipLaunchKernelGGL((k_spmm_merge_fix<L, OPV>), dim3(fix_grid), dim3(256), 0, st, g, x,  \
+                           y, cvec, part, part2, prow, nr);                                    \
+        return;                                                                                \
+    }
+    RAFT_MERGE_CASE(kOpNcut)
+    RAFT_MERGE_CASE(kOpModFull)
+    RAFT_MERGE_CASE(kOpModReduced)
+    RAFT_MERGE_CASE(kOpGcn)
+#undef RAFT_MERGE_CASE
+}
+
+void launch_spmm_merge(const GraphView& g, int op, int L, const float* x, float* y,
+                       const float* cvec, void* ws, hipStream_t st) {
+    char* w = reinterpret_cast<char*>(ws);
+    switch (L) {
+        case 16: spmm_merge_op<16>(g, op, x, y, cvec, w, st); break;
+        case 32: spmm_merge_op<32>(g, op, x, y, cvec, w, st); break;
+        case 64: spmm_merge_op<64>(g, op, x, y, cvec, w, st); break;
+        case 128: spmm_merge_op<128>(g, op, x, y, cvec, w, st); break;
+        case 256: spmm_merge_op<256>(g, op, x, y, cvec, w, st); break;
+        default: break;
+    }
+}
+
 bool spmm_supported(int L) { return L == 16 || L == 32 || L == 64 || L == 128 || L == 256; }
 
 int spmm_grid(int32_t n, int L, int num_cu, int* rows_per_wave) {
@@ -362,20 +641,32 @@ int spmm_launch_shape(int32_t n, int L, int num_cu, int* R, int* nrb) {
     return rb == 0 ? 0 : (rb + xs - 1) / xs * 8;
 }
 
+// Slices one launch at a time when X is larger than this (bytes): the
+// neighbour gathers of a launch then touch one slice of X (N x 128 bytes), which
+// the memory-side cache can hold, instead of all of it.
+constexpr size_t kSliceMajorBytes = (size_t)256 << 20;
+
 template <int L>
 static void spmm_dispatch_op(const GraphView& g, int op, const float* x, float* y,
                              const float* cvec, double* cpart, int num_cu, hipStream_t st) {
+    using GE = SpmmGeom<L>;
     int R, nrb;
     const int grid = spmm_launch_shape(g.n, L, num_cu, &R, &nrb);
     if (grid == 0) return;
+    const bool slice_major = GE::NS > 1 && (size_t)g.n * L * sizeof(float) > kSliceMajorBytes;
+    const int nl = slice_major ? GE::NS : 1;
+    const int lgrid = slice_major ? nrb : grid;
 #define RAFT_SPMM_CASE(OPV)                                                                  \
     if (op == OPV) {                                                                         \
-        if (cpart)                                                                           \
-            hipLaunchKernelGGL((k_spmm<L, OPV, true>), dim3(grid), dim3(256), 0, st, g, x, y, \
-                               cvec, cpart, R, nrb);                                         \
-        else                                                                                 \
-            hipLaunchKernelGGL((k_spmm<L, OPV, false>), dim3(grid), dim3(256), 0, st, g, x,   \
-                               y, cvec, cpart, R, nrb);                                      \
+        for (int s_ = 0; s_ < nl; ++s_) {                                                    \
+            const int fs = slice_major ? s_ : -1;                                            \
+            if (cpart)                                                                       \
+                hipLaunchKernelGGL((k_spmm<L, OPV, true>), dim3(lgrid), dim3(256), 0, st, g, \
+                                   x, y, cvec, cpart, R, nrb, fs);                           \
+            else                                                                             \
+                hipLaunchKernelGGL((k_spmm<L, OPV, false>), dim3(lgrid), dim3(256), 0, st,   \
+                                   g, x, y, cvec, cpart, R, nrb, fs);                        \
+        }                                                                                    \
         return;                                                                              \
     }
     RAFT_SPMM_CASE(kOpNcut)
