@@ -67,10 +67,12 @@ typedef struct raft_graph raft_graph;
 typedef struct {
     int32_t  abi_version;              /* must be RAFT_ABI_VERSION                    */
     int32_t  op;                       /* RAFT_X_NCUT / MOD_FULL / MOD_REDUCED        */
-    int32_t  proj_dim;                 /* L, one of 16, 32, 64, 128, 256              */
+    int32_t  proj_dim;                 /* L, a power of two 16..4096 (batches: <= 256) */
     int32_t  q;                        /* propagation steps, >= 1 (q = 1 is Eq. 5)    */
     int32_t  n_layers;                 /* GCN layers, 0..RAFT_MAX_LAYERS               */
-    int32_t  layer_dims[RAFT_MAX_LAYERS]; /* L_1..L_n, each in {16,32,64,128,256}; d = last */
+    int32_t  layer_dims[RAFT_MAX_LAYERS]; /* L_1..L_n, powers of two 16..4096 (a layer
+                                          * wider than 128 x 256 needs L_k >= 128); the
+                                          * embedding width d = last <= 256            */
     int32_t  normalize_input;          /* row-normalise Y before layer 1 (default 0)  */
     int32_t  k_min, k_max, k_step;     /* candidate grid, 1 <= k_min <= k_max <= min(N, 255) */
     int32_t  kmeans_max_iter;          /* T_max (assignments per candidate), >= 1     */
@@ -130,6 +132,38 @@ raft_status raft_graph_create(raft_ctx* ctx, const void* row_ptr, int row_ptr_is
 void        raft_graph_destroy(raft_graph* g);
 /* Device copies of the degree vector (int32 [N]) and of the CSR (for tests). */
 raft_status raft_graph_degrees(const raft_graph* g, int32_t* deg_out, void* stream);
+/* N and nnz (stored entries, 2|E|) of a graph; either pointer may be NULL. */
+raft_status raft_graph_size(const raft_graph* g, int64_t* n, int64_t* nnz);
+/* Device-to-device copy of the library's CSR: row_ptr int32 [N + 1],
+ * col_idx int32 [nnz] (sorted rows), asynchronous on `stream`. */
+raft_status raft_graph_csr(const raft_graph* g, int32_t* row_ptr, int32_t* col_idx, void* stream);
+
+/* ---- graph sampling (Sec. IV, Alg. 2: fast degree-corrected SBM) --------- */
+
+/* Samples an undirected graph from the degree-corrected SBM (Sec. II, SBM
+ * definition): i and j are joined with probability 1 - exp(-lambda_ij),
+ * lambda_ij = theta_i theta_j Omega_{c_i c_j}, independently over the pairs
+ * i < j.  Alg. 2's jump: the possible edges between blocks r <= s form a
+ * |C_r| x |C_s| table (C_r = the nodes of block r in increasing id); each row
+ * x of it (node C_r[x] against C_s; for r = s only columns y > x) is one
+ * device thread that jumps from one sampled entry to the next: from column m
+ * it draws E = -ln u, u the first word of Philox4x64-10 with key (seed, 0x30)
+ * and counter (r K + s, x, jump number, 0) as a 52-bit uniform in (0, 1),
+ * stops when E >= lambda_row (P_s[|C_s|] - P_s[m]), and otherwise takes the
+ * smallest t >= m with lambda_row (P_s[t + 1] - P_s[m]) > E (binary search;
+ * P_s = the FP64 theta prefix of block s accumulated left to right,
+ * lambda_row = Omega_rs theta_{C_r[x]}).  FP64 throughout; the result is a
+ * function of (theta, blocks, omega, seed) alone, bit for bit.
+ *   theta  [n] host FP64, finite, >= 0;  blocks [n] host int32 in 0..k-1;
+ *   omega  [k x k] host FP64 row-major, symmetric, finite, >= 0;
+ *   1 <= k <= 4096, 1 <= n < 2^31 - 1.
+ * *out receives a graph handle as from raft_graph_create (validated; the
+ * sampled nnz = 2|E| must stay below 2^31 - 1, else RAFT_E_UNSUPPORTED).
+ * Device memory: O(n + k^2 + number of table rows + |E|) temporaries, freed
+ * before return.  Synchronous. */
+raft_status raft_sbm_sample(raft_ctx* ctx, int64_t n, int32_t k, const double* theta,
+                            const int32_t* blocks, const double* omega, uint64_t seed,
+                            void* stream, raft_graph** out);
 
 /* ---- workspace ----------------------------------------------------------- */
 

@@ -28,7 +28,8 @@ EXPORTS = [
     "raft_spmm_noalloc", "raft_batch_create", "raft_batch_destroy", "raft_batch_workspace_size",
     "raft_batch_run", "raft_batch_set_capture", "raft_batch_plan_check", "raft_batch_stage_times",
     "raft_batch_tuning", "raft_hier_workspace_size", "raft_hier_partition",
-    "raft_spmm_merge_workspace_size", "raft_spmm_merge",
+    "raft_spmm_merge_workspace_size", "raft_spmm_merge", "raft_graph_size", "raft_graph_csr",
+    "raft_sbm_sample",
 ]
 
 PROF_SPMM, PROF_DENSE, PROF_RACE, PROF_ASSIGN, PROF_UPDATE, PROF_SCORE = range(6)
@@ -97,6 +98,10 @@ _SIGNATURES = {
                                  ctypes.POINTER(_P)]),
     "raft_graph_destroy": (None, [_P]),
     "raft_graph_degrees": (_I32, [_P, _P, _P]),
+    "raft_graph_size": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    "raft_graph_csr": (_I32, [_P, _P, _P, _P]),
+    "raft_sbm_sample": (_I32, [_P, _I64, _I32, _P, _P, _P, ctypes.c_uint64, _P,
+                               ctypes.POINTER(_P)]),
     "raft_workspace_size": (_I32, [_P, _P, ctypes.POINTER(RaftConfig), ctypes.POINTER(_SZ)]),
     "raft_gaussian": (_I32, [_P, _U64, _U64, _I64, _I64, ctypes.c_double, _P, _P]),
     "raft_spmm": (_I32, [_P, _P, _I32, _I32, _P, _P, _P, _SZ, _P]),

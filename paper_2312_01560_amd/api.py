@@ -142,10 +142,27 @@ class Graph:
         ctx.check(st)
         self.h = h
 
+    @classmethod
+    def _from_handle(cls, ctx, h):
+        g = cls.__new__(cls)
+        g.ctx, g.h = ctx, h
+        n, nnz = ctypes.c_int64(), ctypes.c_int64()
+        ctx.check(ctx.lib.raft_graph_size(h, ctypes.byref(n), ctypes.byref(nnz)))
+        g.n, g.nnz = int(n.value), int(nnz.value)
+        return g
+
     def degrees(self):
         out = self.ctx.empty((self.n,), torch.int32)
         self.ctx.check(self.ctx.lib.raft_graph_degrees(self.h, _ptr(out), _stream()))
         return out
+
+    def csr(self):
+        """The library's CSR as device tensors (row_ptr int32 [N + 1],
+        col_idx int32 [nnz])."""
+        rp = self.ctx.empty((self.n + 1,), torch.int32)
+        ci = self.ctx.empty((max(self.nnz, 1),), torch.int32)
+        self.ctx.check(self.ctx.lib.raft_graph_csr(self.h, _ptr(rp), _ptr(ci), _stream()))
+        return rp, ci[: self.nnz]
 
     def close(self):
         if getattr(self, "h", None):
@@ -449,3 +466,23 @@ def profile_read(ctx):
     ctx.check(ctx.lib.raft_profile_read(ctx.h, ms, n))
     names = ["spmm", "dense", "race", "assign", "update", "score"]
     return {names[k]: (ms[k], n[k]) for k in range(_lib.PROF_CLASSES)}
+
+
+def sbm_sample(ctx, theta, blocks, omega, seed):
+    """A graph sampled from the degree-corrected SBM by the fast jump sampler
+    (Sec. IV, Alg. 2) on the device: theta [n] FP64, blocks [n] int in
+    0..k-1, omega [k x k] FP64 symmetric (host arrays).  Returns a Graph."""
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    blocks = np.ascontiguousarray(blocks, dtype=np.int32)
+    omega = np.ascontiguousarray(omega, dtype=np.float64)
+    if omega.ndim != 2 or omega.shape[0] != omega.shape[1]:
+        raise ValueError("omega must be k x k")
+    if theta.shape != blocks.shape or theta.ndim != 1:
+        raise ValueError("theta and blocks must be vectors of one length")
+    h = ctypes.c_void_p()
+    ctx.check(ctx.lib.raft_sbm_sample(ctx.h, theta.size, omega.shape[0],
+                                      theta.ctypes.data_as(ctypes.c_void_p),
+                                      blocks.ctypes.data_as(ctypes.c_void_p),
+                                      omega.ctypes.data_as(ctypes.c_void_p),
+                                      ctypes.c_uint64(int(seed)), _stream(), ctypes.byref(h)))
+    return Graph._from_handle(ctx, h)

@@ -149,7 +149,8 @@ raft_status fail(raft_ctx* ctx, raft_status code, const char* fmt, ...) {
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
-bool width_ok(int v) { return v == 16 || v == 32 || v == 64 || v == 128 || v == 256; }
+// Feature widths: powers of two from 16 to 4096 (the paper's widths, Table I).
+bool width_ok(int v) { return v >= 16 && v <= 4096 && (v & (v - 1)) == 0; }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -928,6 +929,25 @@ raft_status raft_graph_degrees(const raft_graph* g, int32_t* deg_out, void* stre
     return RAFT_OK;
 }
 
+raft_status raft_graph_size(const raft_graph* g, int64_t* n, int64_t* nnz) {
+    if (!g) return RAFT_E_INVAL;
+    if (n) *n = g->n;
+    if (nnz) *nnz = g->nnz;
+    return RAFT_OK;
+}
+
+raft_status raft_graph_csr(const raft_graph* g, int32_t* row_ptr, int32_t* col_idx, void* stream) {
+    if (!g || !row_ptr || (g->nnz > 0 && !col_idx)) return RAFT_E_INVAL;
+    raft_ctx* ctx = g->ctx;
+    hipStream_t st = as_stream(stream);
+    HIP_TRY(ctx, hipMemcpyAsync(row_ptr, g->rp, sizeof(int32_t) * ((size_t)g->n + 1),
+                                hipMemcpyDeviceToDevice, st));
+    if (g->nnz > 0)
+        HIP_TRY(ctx, hipMemcpyAsync(col_idx, g->ci, sizeof(int32_t) * (size_t)g->nnz,
+                                    hipMemcpyDeviceToDevice, st));
+    return RAFT_OK;
+}
+
 raft_status raft_workspace_size(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg,
                                 size_t* bytes) {
     RAFT_TRY(check_graph(ctx, g));
@@ -1031,7 +1051,7 @@ raft_status raft_spmm_merge_workspace_size(raft_ctx* ctx, const raft_graph* g, i
     RAFT_TRY(check_graph(ctx, g));
     if (!bytes) return fail(ctx, RAFT_E_INVAL, "bytes is null");
     if (op < RAFT_X_NCUT || op > RAFT_X_GCN) return fail(ctx, RAFT_E_INVAL, "op %d", op);
-    if (!spmm_supported(L)) return fail(ctx, RAFT_E_UNSUPPORTED, "width %d", L);
+    if (!spmm_supported(L) || L > 256) return fail(ctx, RAFT_E_UNSUPPORTED, "width %d", L);
     *bytes = align256(spmm_merge_ws_bytes(g->n, g->nnz, L, op)) +
              (op == RAFT_X_MOD_FULL ? spmm_ws_bytes(ctx, g, L) : 0);
     return RAFT_OK;
@@ -1793,7 +1813,10 @@ void batch_layout(raft_batch* b, char* ws, raft_outputs* outs, BatchLayout& B, i
         cnt[bt_split][g] = km.split ? kmeans_blocks(km, kKmSplit, ctx->num_cu) : 0;
         cnt[bt_race][g] = kmeans_blocks(km, kKmRace, ctx->num_cu);
         cnt[bt_init][g] = kmeans_blocks(km, kKmInit, ctx->num_cu);
-        cnt[bt_ufinish][g] = kmeans_blocks(km, kKmUpdateFinish, ctx->num_cu);
+        // rows walked grid-stride (k_update_finish_b): two work-groups per
+        // CU of the graph's share of the chip
+        cnt[bt_ufinish][g] = std::min(kmeans_blocks(km, kKmUpdateFinish, ctx->num_cu),
+                                      2 * P.share);
         cnt[bt_transpose][g] = score_blocks(sc, kScTranspose);
         cnt[bt_edge][g] = score_blocks(sc, kScEdge);
         cnt[bt_reduce][g] = score_blocks(sc, kScReduce);
@@ -2054,6 +2077,9 @@ raft_status raft_batch_create(raft_ctx* ctx, int32_t G, const raft_graph* const*
     RAFT_TRY(check_config(ctx, nullptr, cfg));
     const int d = embed_dim(cfg);
     if (!kmeans_supported(d)) return fail(ctx, RAFT_E_UNSUPPORTED, "embedding width %d", d);
+    if (max_width(cfg) > 256)
+        return fail(ctx, RAFT_E_UNSUPPORTED, "batches take widths up to 256 (widest %d)",
+                    max_width(cfg));
     int64_t N = 0, NNZ = 0;
     for (int g = 0; g < G; ++g) {
         RAFT_TRY(check_graph(ctx, graphs[g]));
@@ -2804,6 +2830,154 @@ raft_status raft_hier_partition(raft_ctx* ctx, const raft_graph* g, const float*
     if (tree)
         for (size_t t = 0; t < nodes.size() && (int)t < tree_cap; ++t) tree[t] = nodes[t];
     return RAFT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 2: sampling from the degree-corrected SBM.  The host groups the nodes
+// by block (increasing id), accumulates each block's theta prefix left to
+// right in FP64 and lists the block pairs r <= s with both blocks non-empty;
+// every row of every pair is one device thread.  A counting pass, a scan and
+// a writing pass give the edge list, which becomes a symmetric sorted CSR and
+// then a graph handle (validated like any other).
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+struct DeviceAllocs {
+    std::vector<void*> p;
+    ~DeviceAllocs() {
+        for (void* q : p) (void)hipFree(q);
+    }
+    template <typename T>
+    bool get(T** out, size_t count) {
+        void* q = nullptr;
+        if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return false;
+        p.push_back(q);
+        *out = static_cast<T*>(q);
+        return true;
+    }
+};
+}  // namespace
+
+extern "C" {
+
+raft_status raft_sbm_sample(raft_ctx* ctx, int64_t n, int32_t k, const double* theta,
+                            const int32_t* blocks, const double* omega, uint64_t seed,
+                            void* stream, raft_graph** out) {
+    if (!ctx) return RAFT_E_INVAL;
+    if (!out) return fail(ctx, RAFT_E_INVAL, "out is null");
+    *out = nullptr;
+    if (!theta || !blocks || !omega) return fail(ctx, RAFT_E_INVAL, "null argument");
+    if (n < 1 || n >= INT32_MAX) return fail(ctx, RAFT_E_INVAL, "n = %lld", (long long)n);
+    if (k < 1 || k > kSbmMaxBlocks)
+        return fail(ctx, RAFT_E_INVAL, "k = %d outside 1..%d", k, kSbmMaxBlocks);
+    for (int64_t i = 0; i < n; ++i) {
+        if (blocks[i] < 0 || blocks[i] >= k)
+            return fail(ctx, RAFT_E_INVAL, "blocks[%lld] = %d outside 0..%d", (long long)i,
+                        blocks[i], k - 1);
+        if (!std::isfinite(theta[i]) || theta[i] < 0)
+            return fail(ctx, RAFT_E_INVAL, "theta[%lld] not finite and >= 0", (long long)i);
+    }
+    for (int64_t q = 0; q < (int64_t)k * k; ++q)
+        if (!std::isfinite(omega[q]) || omega[q] < 0)
+            return fail(ctx, RAFT_E_INVAL, "omega entry %lld not finite and >= 0", (long long)q);
+    for (int r = 0; r < k; ++r)
+        for (int s = r + 1; s < k; ++s)
+            if (omega[(size_t)r * k + s] != omega[(size_t)s * k + r])
+                return fail(ctx, RAFT_E_INVAL, "omega not symmetric at (%d, %d)", r, s);
+    // blocks, members in increasing id (a stable counting sort), prefixes
+    std::vector<int32_t> bcount(k, 0), boff(k, 0), members((size_t)n);
+    for (int64_t i = 0; i < n; ++i) ++bcount[blocks[i]];
+    for (int r = 1; r < k; ++r) boff[r] = boff[r - 1] + bcount[r - 1];
+    {
+        std::vector<int32_t> cur(boff);
+        for (int64_t i = 0; i < n; ++i) members[cur[blocks[i]]++] = (int32_t)i;
+    }
+    std::vector<double> pref((size_t)n + k);
+    for (int s = 0; s < k; ++s) {
+        double* ps = pref.data() + boff[s] + s;
+        double acc = 0.0;
+        ps[0] = 0.0;
+        for (int y = 0; y < bcount[s]; ++y) {
+            acc = acc + theta[members[(size_t)boff[s] + y]];
+            ps[y + 1] = acc;
+        }
+    }
+    std::vector<int32_t> pair_r, pair_s;
+    std::vector<int64_t> rowoff = {0};
+    for (int r = 0; r < k; ++r)
+        for (int s = r; s < k; ++s)
+            if (bcount[r] > 0 && bcount[s] > 0) {
+                pair_r.push_back(r);
+                pair_s.push_back(s);
+                rowoff.push_back(rowoff.back() + bcount[r]);
+            }
+    const int npairs = (int)pair_r.size();
+    const int64_t nrows = rowoff.back();
+    hipStream_t st = as_stream(stream);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    DeviceAllocs A;
+    SbmPlan P{};
+    double *d_theta, *d_omega, *d_pref;
+    int32_t *d_members, *d_boff, *d_bcount, *d_pr, *d_ps;
+    int64_t *d_rowoff, *cnt, *off, *bsum, *total;
+    const int64_t nb_rows = (nrows + 1023) / 1024 + 1, nb_n = ((int64_t)n + 1 + 1023) / 1024 + 1;
+    if (!A.get(&d_theta, n) || !A.get(&d_omega, (size_t)k * k) || !A.get(&d_pref, n + k) ||
+        !A.get(&d_members, n) || !A.get(&d_boff, k) || !A.get(&d_bcount, k) ||
+        !A.get(&d_pr, npairs) || !A.get(&d_ps, npairs) || !A.get(&d_rowoff, npairs + 1) ||
+        !A.get(&cnt, nrows) || !A.get(&off, nrows) ||
+        !A.get(&bsum, std::max(nb_rows, nb_n)) || !A.get(&total, 1))
+        return fail(ctx, RAFT_E_NOMEM, "sampler allocation failed (%lld rows)", (long long)nrows);
+    auto up = [&](void* dst, const void* src, size_t bytes) {
+        return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
+    };
+    hipError_t e = up(d_theta, theta, sizeof(double) * n);
+    if (e == hipSuccess) e = up(d_omega, omega, sizeof(double) * k * k);
+    if (e == hipSuccess) e = up(d_pref, pref.data(), sizeof(double) * pref.size());
+    if (e == hipSuccess) e = up(d_members, members.data(), sizeof(int32_t) * n);
+    if (e == hipSuccess) e = up(d_boff, boff.data(), sizeof(int32_t) * k);
+    if (e == hipSuccess) e = up(d_bcount, bcount.data(), sizeof(int32_t) * k);
+    if (e == hipSuccess) e = up(d_pr, pair_r.data(), sizeof(int32_t) * npairs);
+    if (e == hipSuccess) e = up(d_ps, pair_s.data(), sizeof(int32_t) * npairs);
+    if (e == hipSuccess) e = up(d_rowoff, rowoff.data(), sizeof(int64_t) * rowoff.size());
+    if (e != hipSuccess) return fail(ctx, RAFT_E_DEVICE, "sampler upload: %s", hipGetErrorString(e));
+    P.k = k;
+    P.npairs = npairs;
+    P.nrows = nrows;
+    P.seed = seed;
+    P.theta = d_theta;
+    P.omega = d_omega;
+    P.members = d_members;
+    P.boff = d_boff;
+    P.bcount = d_bcount;
+    P.pref = d_pref;
+    P.rowoff = d_rowoff;
+    P.pair_r = d_pr;
+    P.pair_s = d_ps;
+    // pass 1: edges per row; offsets by the scan; the total read back
+    launch_sbm_rows(P, false, cnt, nullptr, nullptr, nullptr, st);
+    launch_scan_i64(cnt, nrows, off, bsum, total, st);
+    RAFT_TRY(launch_check(ctx));
+    int64_t ne = 0;
+    int64_t* h_total = reinterpret_cast<int64_t*>(ctx->h_pinned);
+    HIP_TRY(ctx, hipMemcpyAsync(h_total, total, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    ne = h_total[0];
+    if (ne < 0) return fail(ctx, RAFT_E_DEVICE, "edge count %lld", (long long)ne);
+    if (2 * ne >= INT32_MAX)
+        return fail(ctx, RAFT_E_UNSUPPORTED, "%lld sampled edges exceed the int32 CSR",
+                    (long long)ne);
+    // pass 2: the same draws, edges stored; then the CSR
+    int32_t *src, *dst, *col;
+    int64_t *deg, *rp, *cursor;
+    if (!A.get(&src, ne) || !A.get(&dst, ne) || !A.get(&col, 2 * ne) || !A.get(&deg, n + 1) ||
+        !A.get(&rp, n + 1) || !A.get(&cursor, n))
+        return fail(ctx, RAFT_E_NOMEM, "sampler edge buffers (%lld edges)", (long long)ne);
+    launch_sbm_rows(P, true, nullptr, off, src, dst, st);
+    HIP_TRY(ctx, launch_sbm_csr(src, dst, ne, (int)n, deg, rp, cursor, bsum, total, col, st));
+    RAFT_TRY(launch_check(ctx));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    return raft_graph_create(ctx, rp, 1, col, n, 2 * ne, 1, stream, out);
 }
 
 }  // extern "C"

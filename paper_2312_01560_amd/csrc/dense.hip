@@ -127,10 +127,142 @@ __global__ __launch_bounds__(256) void k_rownorm_b(const DenseItem* __restrict__
     rownorm_body(items[gi].H, items[gi].n, L, (int)w.x);
 }
 
+// Wide layers (the paper's widths up to 4096, Table I): U = P W as a tiled
+// FP32 MFMA GEMM.  A work-group computes a 64 x 128 tile of U; per 16-deep
+// slab of the contraction the 256 threads stage the P tile (64 x 16) and the
+// W tile (16 x 128) in LDS (double-buffered, the next slab's loads issued
+// before this slab's MFMAs), and wave w computes the 64 x 32 columns
+// [32 w, 32 w + 32) of the tile as 4 x 2 blocks of v_mfma_f32_16x16x4f32.
+// Lane (li, g) supplies A[m + li][k0 + g] and B[k0 + g][n + li] per 4-deep
+// step.  Then tanh and the row normalisation run over whole rows in a
+// second kernel (a row spans several tiles).
+constexpr int kGemmBM = 64, kGemmBN = 128, kGemmBK = 16;
+
+__global__ __launch_bounds__(256) void k_gemm_wide(const float* __restrict__ P,
+                                                   const float* __restrict__ W,
+                                                   float* __restrict__ U, int n, int lin,
+                                                   int lout) {
+    __shared__ float As[2][kGemmBM][kGemmBK + 1];
+    __shared__ float Bs[2][kGemmBK][kGemmBN + 4];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wid = tid / kWave;
+    const int g = lane >> 4, li = lane & 15;
+    const int tiles_n = lout / kGemmBN;
+    const int m0 = (blockIdx.x / tiles_n) * kGemmBM;
+    const int n0 = (blockIdx.x % tiles_n) * kGemmBN;
+    // staging: P tile 64 x 16 = one float4 per thread; W tile 16 x 128 = two
+    const int ar = tid / 4, ac = (tid % 4) * 4;
+    const int arow = min(m0 + ar, n - 1);
+    const int br = tid / 32, bc = (tid % 32) * 4;
+    float4 pa, pb0, pb1;
+    auto issue = [&](int k0) {
+        pa = *reinterpret_cast<const float4*>(P + (size_t)arow * lin + k0 + ac);
+        pb0 = *reinterpret_cast<const float4*>(W + (size_t)(k0 + br) * lout + n0 + bc);
+        pb1 = *reinterpret_cast<const float4*>(W + (size_t)(k0 + br + 8) * lout + n0 + bc);
+    };
+    auto commit = [&](int buf) {
+        As[buf][ar][ac + 0] = pa.x;
+        As[buf][ar][ac + 1] = pa.y;
+        As[buf][ar][ac + 2] = pa.z;
+        As[buf][ar][ac + 3] = pa.w;
+        *reinterpret_cast<float4*>(&Bs[buf][br][bc]) = pb0;
+        *reinterpret_cast<float4*>(&Bs[buf][br + 8][bc]) = pb1;
+    };
+    floatx4 acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    issue(0);
+    commit(0);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = 0; k0 < lin; k0 += kGemmBK) {
+        const bool more = k0 + kGemmBK < lin;
+        if (more) issue(k0 + kGemmBK);
+#pragma unroll
+        for (int s = 0; s < kGemmBK / 4; ++s) {
+            float a[4], b[2];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[buf][16 * i + li][4 * s + g];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) b[j] = Bs[buf][4 * s + g][32 * wid + 16 * j + li];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        if (more) {
+            commit(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+        }
+    }
+    // block (i, j): rows m0 + 16 i + 4 g + v, column n0 + 32 wid + 16 j + li
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = m0 + 16 * i + 4 * g + v;
+            if (row < n) {
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    U[(size_t)row * lout + n0 + 32 * wid + 16 * j + li] = acc[i][j][v];
+            }
+        }
+}
+
+// tanh and the row normalisation of a wide layer, in place; one wave per row.
+__global__ __launch_bounds__(256) void k_tanh_rownorm(float* __restrict__ H, int n, int L,
+                                                      int32_t* __restrict__ status) {
+    const int row = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (row >= n) return;
+    float* h = H + (size_t)row * L;
+    float ss = 0.f;
+    for (int c = lane * 4; c < L; c += kWave * 4) {
+        float4 v = *reinterpret_cast<float4*>(h + c);
+        v.x = tanhf(v.x);
+        v.y = tanhf(v.y);
+        v.z = tanhf(v.z);
+        v.w = tanhf(v.w);
+        *reinterpret_cast<float4*>(h + c) = v;
+        ss += v.x * v.x;
+        ss += v.y * v.y;
+        ss += v.z * v.z;
+        ss += v.w * v.w;
+    }
+    ss = wave_sum(ss);
+    const float nrm = sqrtf(ss);
+    if (lane == 0 && !(nrm <= 3.0e38f)) atomicOr(status, kStatusNumeric);
+    const float inv = 1.0f / fmaxf(nrm, 1e-12f);
+    for (int c = lane * 4; c < L; c += kWave * 4) {
+        float4 v = *reinterpret_cast<float4*>(h + c);
+        v.x *= inv;
+        v.y *= inv;
+        v.z *= inv;
+        v.w *= inv;
+        *reinterpret_cast<float4*>(h + c) = v;
+    }
+}
+
 static bool pow2_width(int v) { return v == 16 || v == 32 || v == 64 || v == 128 || v == 256; }
 
-bool dense_supported(int lin, int lout) {
+static bool wide_width(int v) {
+    return v == 16 || v == 32 || v == 64 || v == 128 || v == 256 || v == 512 || v == 1024 ||
+           v == 2048 || v == 4096;
+}
+
+// The register-tile kernel (k_dense) for lin x lout <= 128 x 256; the tiled
+// GEMM otherwise (lout a multiple of 128, lin of 16).
+static bool dense_small(int lin, int lout) {
     return pow2_width(lin) && pow2_width(lout) && lin * lout <= 128 * 256;
+}
+
+bool dense_supported(int lin, int lout) {
+    return dense_small(lin, lout) || (wide_width(lin) && wide_width(lout) && lout >= kGemmBN);
 }
 
 template <int LIN, int LOUT>
@@ -212,6 +344,16 @@ static void dense_launch1(const float* P, const float* W, float* H, int32_t n, i
 void launch_dense_layer(const float* P, const float* W, float* H, int32_t n, int lin, int lout,
                         bool linear, int32_t* status, hipStream_t st) {
     if (n == 0) return;
+    if (!dense_small(lin, lout)) {
+        const int grid = ((n + kGemmBM - 1) / kGemmBM) * (lout / kGemmBN);
+        hipLaunchKernelGGL(k_gemm_wide, dim3(grid), dim3(256), 0, st, P, W, H, n, lin, lout);
+        if (!linear) {
+            const int64_t threads = (int64_t)n * kWave;
+            hipLaunchKernelGGL(k_tanh_rownorm, dim3((unsigned)((threads + 255) / 256)), dim3(256),
+                               0, st, H, n, lout, status);
+        }
+        return;
+    }
     switch (lin) {
         case 16: dense_launch1<16>(P, W, H, n, lout, linear, status, st); break;
         case 32: dense_launch1<32>(P, W, H, n, lout, linear, status, st); break;

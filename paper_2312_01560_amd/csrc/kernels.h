@@ -323,6 +323,36 @@ void launch_hier_setup(const float* Z, int64_t total, uint32_t* zmax_bits, int32
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 void launch_fill_i64(long long* p, int64_t n, hipStream_t st);
 
+// ---- sampler.hip -----------------------------------------------------------
+// One level of rows of the fast SBM sampler: row x of block pair (r, s),
+// r <= s, is node members[boff[r] + x] against block s.
+constexpr int kSbmMaxBlocks = 4096;
+struct SbmPlan {
+    int32_t k, npairs;
+    int64_t nrows;
+    uint64_t seed;
+    const double* theta;     // [n]
+    const double* omega;     // [k x k]
+    const int32_t* members;  // [n] nodes grouped by block, increasing id in a block
+    const int32_t* boff;     // [k] first member of each block
+    const int32_t* bcount;   // [k]
+    const double* pref;      // [n + k] per block: 0, theta sums left to right (n_s + 1 values)
+    const int64_t* rowoff;   // [npairs + 1] first row of each pair
+    const int32_t* pair_r;   // [npairs]
+    const int32_t* pair_s;   // [npairs]
+};
+void launch_sbm_rows(const SbmPlan& p, bool write, int64_t* cnt, const int64_t* off,
+                     int32_t* src, int32_t* dst, hipStream_t st);
+// Exclusive scan (out[i] = sum of v[0..i)); bsum holds ceil(n / 1024) values,
+// total the sum of all.
+void launch_scan_i64(const int64_t* v, int64_t n, int64_t* out, int64_t* bsum, int64_t* total,
+                     hipStream_t st);
+// Symmetric CSR of the edge list (both directions, rows sorted): deg [n + 1],
+// rp [n + 1], cursor [n], bsum [ceil((n + 1) / 1024)], total [1], col [2 ne].
+hipError_t launch_sbm_csr(const int32_t* src, const int32_t* dst, int64_t ne, int n,
+                          int64_t* deg, int64_t* rp, int64_t* cursor, int64_t* bsum,
+                          int64_t* total, int32_t* col, hipStream_t st);
+
 // ---- confusion.hip -------------------------------------------------------
 // counts [ka x kb] int64 (zeroed here) = joint histogram of labels a, b [n];
 // a label out of range sets kStatusLabel and is not counted.

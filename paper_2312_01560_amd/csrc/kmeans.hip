@@ -1219,12 +1219,19 @@ __global__ __launch_bounds__(256) void k_update_finish(KmeansPlan p, int it, int
     update_finish_body(p, it, t_max, (int)blockIdx.x);
 }
 
+// Batched: a graph's rows (and its bookkeeping, row KP) walked grid-stride by
+// its work-groups, so a launch over many graphs does not dispatch one
+// work-group per centre row of every graph (most of them exit at once).
 __global__ __launch_bounds__(256) void k_update_finish_b(const KmeansPlan* __restrict__ plans,
                                                          int it, int t_max, BatchTable tb) {
     int gi;
     Wg w;
     if (!batch_find(tb, gi, w)) return;
-    update_finish_body(plans[gi], it, t_max, (int)w.x);
+    const KmeansPlan& p = plans[gi];
+    for (int c = (int)w.x; c <= p.KP; c += (int)w.n) {
+        update_finish_body(p, it, t_max, c);
+        __syncthreads();   // the row's LDS staging is reused by the next row
+    }
 }
 
 __device__ __forceinline__ void kmeans_reset_body(const KmeansPlan& p, Wg w) {

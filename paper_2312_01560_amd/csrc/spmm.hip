@@ -37,28 +37,28 @@ __device__ __forceinline__ float edge_weight(const GraphView& g, int j) {
 // each XCD only ever touches its own slices: its L2 then holds N x 128 bytes
 // (or 2 slices' worth at L = 64) of X instead of all of it, and the random
 // neighbour gathers hit L2 more often.  For L <= 32 there is one slice.
+// Wider rows (L > 256, more than 8 slices) give each XCD NS / 8 slices
+// (SPX): block b runs slice (b mod 8) SPX + (b / 8) mod SPX of row block
+// (b / 8) / SPX.
 template <int L>
 struct SpmmGeom {
     static constexpr int W = L >= 64 ? 32 : L;   // columns per slice
     static constexpr int NS = L / W;             // slices
-    static constexpr int XS = 8 / NS;            // XCDs per slice
+    static constexpr int XS = NS <= 8 ? 8 / NS : 1;   // XCDs per slice
+    static constexpr int SPX = NS > 8 ? NS / 8 : 1;   // slices per XCD
     static constexpr int LANES = W / 4;          // lanes per feature row slice
     static constexpr int G = kWave / LANES;      // rows side by side per wave
 };
 
-// fixed_slice < 0: work-groups of all slices side by side, each XCD on its own
-// slices; fixed_slice = s: one launch per slice (all work-groups on slice s,
-// row block = block index), so only one slice of X is live at a time.
 template <int L, int OP, bool CS>
 __device__ __forceinline__ void spmm_body(const GraphView& g, const float* __restrict__ x,
                                           float* __restrict__ y, const float* __restrict__ cvec,
-                                          double* __restrict__ cpart, int R, int nrb, int b,
-                                          int fixed_slice = -1) {
+                                          double* __restrict__ cpart, int R, int nrb, int b) {
     using GE = SpmmGeom<L>;
-    constexpr int W = GE::W, LANES = GE::LANES, G = GE::G, XS = GE::XS;
+    constexpr int W = GE::W, LANES = GE::LANES, G = GE::G, XS = GE::XS, SPX = GE::SPX;
     const int xcd = b % 8;
-    const int sl = fixed_slice >= 0 ? fixed_slice : xcd / XS;            // column slice
-    const int rb = fixed_slice >= 0 ? b : (b / 8) * XS + xcd % XS;       // row block
+    const int sl = SPX > 1 ? xcd * SPX + (b / 8) % SPX : xcd / XS;        // column slice
+    const int rb = SPX > 1 ? (b / 8) / SPX : (b / 8) * XS + xcd % XS;     // row block
     if (rb >= nrb) return;                          // uniform: padding of the grid
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
@@ -193,9 +193,8 @@ template <int L, int OP, bool CS>
 __global__ __launch_bounds__(256) void k_spmm(GraphView g, const float* __restrict__ x,
                                               float* __restrict__ y,
                                               const float* __restrict__ cvec,
-                                              double* __restrict__ cpart, int R, int nrb,
-                                              int fixed_slice) {
-    spmm_body<L, OP, CS>(g, x, y, cvec, cpart, R, nrb, (int)blockIdx.x, fixed_slice);
+                                              double* __restrict__ cpart, int R, int nrb) {
+    spmm_body<L, OP, CS>(g, x, y, cvec, cpart, R, nrb, (int)blockIdx.x);
 }
 
 // Batched: one launch over the graphs of a block-diagonal CSR, each graph's
@@ -263,6 +262,43 @@ template <int L>
 __global__ __launch_bounds__(256) void k_colsum_part(GraphView g, const float* __restrict__ x,
                                                      double* __restrict__ cpart, int rpw) {
     colsum_part_body<L>(g, x, cpart, rpw, (int)blockIdx.x);
+}
+
+// L > 256: block (row block rb, 256-column chunk cc); a wave takes one row at
+// a time, its 64 lanes 4 columns each.
+template <int L>
+__global__ __launch_bounds__(256) void k_colsum_part_wide(GraphView g, const float* __restrict__ x,
+                                                          double* __restrict__ cpart, int rpw) {
+    constexpr int CH = L / 256;
+    const int rb = blockIdx.x / CH, cc = blockIdx.x % CH;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int col = cc * 256 + lane * 4;
+    const int row0 = (rb * kSpmmWaves + wid) * rpw;
+    double cs0 = 0, cs1 = 0, cs2 = 0, cs3 = 0;
+    for (int r = 0; r < rpw; ++r) {
+        const int i = row0 + r;
+        if (i < g.n) {
+            const size_t gi = (size_t)g.base + i;
+            const float4 o = *reinterpret_cast<const float4*>(x + gi * L + col);
+            const double di = (double)g.deg[gi];
+            cs0 += di * (double)o.x;
+            cs1 += di * (double)o.y;
+            cs2 += di * (double)o.z;
+            cs3 += di * (double)o.w;
+        }
+    }
+    __shared__ double red[kSpmmWaves][256];
+    red[wid][lane * 4 + 0] = cs0;
+    red[wid][lane * 4 + 1] = cs1;
+    red[wid][lane * 4 + 2] = cs2;
+    red[wid][lane * 4 + 3] = cs3;
+    __syncthreads();
+    for (int c = threadIdx.x; c < 256; c += blockDim.x) {
+        double s2 = 0;
+        for (int w = 0; w < kSpmmWaves; ++w) s2 += red[w][c];
+        cpart[(size_t)rb * L + cc * 256 + c] = s2;
+    }
 }
 
 template <int L>
@@ -612,10 +648,15 @@ void launch_spmm_merge(const GraphView& g, int op, int L, const float* x, float*
     }
 }
 
-bool spmm_supported(int L) { return L == 16 || L == 32 || L == 64 || L == 128 || L == 256; }
+bool spmm_supported(int L) {
+    return L == 16 || L == 32 || L == 64 || L == 128 || L == 256 || L == 512 || L == 1024 ||
+           L == 2048 || L == 4096;
+}
 
+// Row blocks of the SpMM and the column-sum partials: G full rows per wave
+// (one for L >= 256), rpw passes per wave, four waves.
 int spmm_grid(int32_t n, int L, int num_cu, int* rows_per_wave) {
-    const int G = kWave / (L / 4);
+    const int G = L >= 256 ? 1 : kWave / (L / 4);
     const int64_t target_waves = (int64_t)num_cu * 32;
     const int64_t per_wave = ((int64_t)n + target_waves - 1) / target_waves;
     int rpw = (int)((per_wave + G - 1) / G);
@@ -627,46 +668,35 @@ int spmm_grid(int32_t n, int L, int num_cu, int* rows_per_wave) {
 
 static int spmm_xs(int L) {
     const int W = L >= 64 ? 32 : L;
-    return 8 / (L / W);
+    return L / W <= 8 ? 8 / (L / W) : 1;
 }
 
 int spmm_launch_shape(int32_t n, int L, int num_cu, int* R, int* nrb) {
     int rpw;
     const int rb = spmm_grid(n, L, num_cu, &rpw);
     // rows per row block, as in spmm_grid (which k_colsum_part also uses)
-    if (R) *R = rpw * (kWave / (L / 4)) * kSpmmWaves;
+    if (R) *R = rpw * (L >= 256 ? 1 : kWave / (L / 4)) * kSpmmWaves;
     if (nrb) *nrb = rb;
+    if (L > 256) return rb * (L / 32);   // NS / 8 slices per XCD
     // every group of 8 consecutive work-groups covers XS row blocks x NS slices
     const int xs = spmm_xs(L);
     return rb == 0 ? 0 : (rb + xs - 1) / xs * 8;
 }
 
-// Slices one launch at a time when X is larger than this (bytes): the
-// neighbour gathers of a launch then touch one slice of X (N x 128 bytes), which
-// the memory-side cache can hold, instead of all of it.
-constexpr size_t kSliceMajorBytes = (size_t)256 << 20;
-
 template <int L>
 static void spmm_dispatch_op(const GraphView& g, int op, const float* x, float* y,
                              const float* cvec, double* cpart, int num_cu, hipStream_t st) {
-    using GE = SpmmGeom<L>;
     int R, nrb;
     const int grid = spmm_launch_shape(g.n, L, num_cu, &R, &nrb);
     if (grid == 0) return;
-    const bool slice_major = GE::NS > 1 && (size_t)g.n * L * sizeof(float) > kSliceMajorBytes;
-    const int nl = slice_major ? GE::NS : 1;
-    const int lgrid = slice_major ? nrb : grid;
 #define RAFT_SPMM_CASE(OPV)                                                                  \
     if (op == OPV) {                                                                         \
-        for (int s_ = 0; s_ < nl; ++s_) {                                                    \
-            const int fs = slice_major ? s_ : -1;                                            \
-            if (cpart)                                                                       \
-                hipLaunchKernelGGL((k_spmm<L, OPV, true>), dim3(lgrid), dim3(256), 0, st, g, \
-                                   x, y, cvec, cpart, R, nrb, fs);                           \
-            else                                                                             \
-                hipLaunchKernelGGL((k_spmm<L, OPV, false>), dim3(lgrid), dim3(256), 0, st,   \
-                                   g, x, y, cvec, cpart, R, nrb, fs);                        \
-        }                                                                                    \
+        if (cpart)                                                                           \
+            hipLaunchKernelGGL((k_spmm<L, OPV, true>), dim3(grid), dim3(256), 0, st, g, x, y, \
+                               cvec, cpart, R, nrb);                                         \
+        else                                                                                 \
+            hipLaunchKernelGGL((k_spmm<L, OPV, false>), dim3(grid), dim3(256), 0, st, g, x,   \
+                               y, cvec, cpart, R, nrb);                                      \
         return;                                                                              \
     }
     RAFT_SPMM_CASE(kOpNcut)
@@ -684,6 +714,10 @@ void launch_spmm(const GraphView& g, int op, int L, const float* x, float* y, co
         case 64: spmm_dispatch_op<64>(g, op, x, y, cvec, cpart, num_cu, st); break;
         case 128: spmm_dispatch_op<128>(g, op, x, y, cvec, cpart, num_cu, st); break;
         case 256: spmm_dispatch_op<256>(g, op, x, y, cvec, cpart, num_cu, st); break;
+        case 512: spmm_dispatch_op<512>(g, op, x, y, cvec, cpart, num_cu, st); break;
+        case 1024: spmm_dispatch_op<1024>(g, op, x, y, cvec, cpart, num_cu, st); break;
+        case 2048: spmm_dispatch_op<2048>(g, op, x, y, cvec, cpart, num_cu, st); break;
+        case 4096: spmm_dispatch_op<4096>(g, op, x, y, cvec, cpart, num_cu, st); break;
         default: break;
     }
 }
@@ -753,6 +787,10 @@ void launch_colsum_partials(const GraphView& g, int L, const float* x, double* p
         case 64: hipLaunchKernelGGL(k_colsum_part<64>, dim3(grid), dim3(256), 0, st, g, x, part, rpw); break;
         case 128: hipLaunchKernelGGL(k_colsum_part<128>, dim3(grid), dim3(256), 0, st, g, x, part, rpw); break;
         case 256: hipLaunchKernelGGL(k_colsum_part<256>, dim3(grid), dim3(256), 0, st, g, x, part, rpw); break;
+        case 512: hipLaunchKernelGGL(k_colsum_part_wide<512>, dim3(grid * 2), dim3(256), 0, st, g, x, part, rpw); break;
+        case 1024: hipLaunchKernelGGL(k_colsum_part_wide<1024>, dim3(grid * 4), dim3(256), 0, st, g, x, part, rpw); break;
+        case 2048: hipLaunchKernelGGL(k_colsum_part_wide<2048>, dim3(grid * 8), dim3(256), 0, st, g, x, part, rpw); break;
+        case 4096: hipLaunchKernelGGL(k_colsum_part_wide<4096>, dim3(grid * 16), dim3(256), 0, st, g, x, part, rpw); break;
         default: break;
     }
 }
