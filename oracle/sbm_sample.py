@@ -112,6 +112,36 @@ def sample_edges(theta, blocks, omega, seed):
     return np.concatenate(src), np.concatenate(dst)
 
 
+def row_edges(theta, members, pref, omega, r, s, x, seed):
+    """Columns (node ids) that row x of the (r, s) table joins to
+    C_r[x], one jump at a time (the scalar form of ``sample_edges`` for
+    single rows of large models)."""
+    k = omega.shape[0]
+    cs, ps = members[s], pref[s]
+    ns = cs.size
+    i = int(members[r][x])
+    lam = float(omega[r, s]) * float(theta[i])
+    key = np.array([seed, STREAM_SAMPLE], dtype=np.uint64)
+    m = x + 1 if r == s else 0
+    out, jump = [], 0
+    while m < ns:
+        ctr = np.array([[r * k + s, x, jump, 0]], dtype=np.uint64)
+        e = float(-fmath.ln(fmath.uniform52(philox.philox4x64(ctr, key)[:, 0]))[0])
+        jump += 1
+        if not e < lam * (ps[ns] - ps[m]):
+            break
+        lo, hi = m, ns - 1
+        while lo < hi:
+            mid = (lo + hi) // 2
+            if lam * (ps[mid + 1] - ps[m]) > e:
+                hi = mid
+            else:
+                lo = mid + 1
+        out.append(int(cs[lo]))
+        m = lo + 1
+    return out
+
+
 def sample_csr(theta, blocks, omega, seed):
     """The sampled graph as a symmetric CSR (int64 row_ptr, int64 col_idx,
     rows sorted)."""

@@ -118,6 +118,34 @@ def sample_edges(rng, theta, omega, sizes):
     return np.concatenate(src), np.concatenate(dst)
 
 
+def dcsbm_model(n, k, alpha=2.0, gamma=2.5, d_min=10.0, d_max=100.0, rho=2.5,
+                seed=0, min_block=10):
+    """The parameters of a DC-SBM graph with the recipe of ``dcsbm`` and no
+    sampling: (theta [n] FP64, blocks [n] int32, omega [k x k] FP64), node
+    ids randomly permuted, for samplers that take the model itself."""
+    rng = np.random.default_rng(np.random.SeedSequence([0x5C, int(seed)]))
+    sizes = _block_sizes(rng, n, k, alpha, min_block)
+    block_of = np.repeat(np.arange(k), sizes)
+    tdeg = _power_law(rng, n, gamma, d_min, d_max)
+    vol = np.bincount(block_of, weights=tdeg, minlength=k)
+    V = vol.sum()
+    S = V - np.sum(vol * vol) / V
+    beta = V / ((1.0 + rho) * S)
+    omega = beta * np.outer(vol, vol) / V
+    np.fill_diagonal(omega, 0.0)
+    diag = vol - omega.sum(axis=1)
+    if np.any(diag < 0):
+        raise ValueError("intra/inter ratio infeasible for these block volumes")
+    np.fill_diagonal(omega, diag)
+    theta = tdeg / vol[block_of]
+    perm = rng.permutation(n)
+    theta_p = np.empty(n)
+    blocks_p = np.empty(n, dtype=np.int32)
+    theta_p[perm] = theta
+    blocks_p[perm] = block_of
+    return theta_p, blocks_p, omega
+
+
 def dcsbm(n, k, alpha=2.0, gamma=2.5, d_min=10.0, d_max=100.0, rho=2.5,
           seed=0, min_block=10):
     rng = np.random.default_rng(np.random.SeedSequence([0x5B, int(seed)]))

@@ -1,0 +1,147 @@
+"""Fast SBM sampler on the GPU (raft_sbm_sample, Sec. IV Alg. 2) against the
+FP64 oracle on the same Philox streams: the CSR equal bit for bit on tiny
+models over many seeds, on DC-SBM models of 20k and 50k nodes, with empty and
+one-node blocks, at zero and overwhelming intensity; at 1M nodes, the rows of
+sampled nodes against the oracle's row form; argument errors."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import sbm_sample
+from synth.dcsbm import dcsbm_model
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api_mod():
+    from paper_2312_01560_amd import api
+    return api
+
+
+@pytest.fixture(scope="module")
+def ctx(api_mod):
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = api_mod.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_csr(api_mod, ctx, theta, blocks, omega, seed):
+    g = api_mod.sbm_sample(ctx, theta, blocks, omega, seed)
+    rp, ci = g.csr()
+    torch.cuda.synchronize()
+    out = rp.cpu().numpy().astype(np.int64), ci.cpu().numpy().astype(np.int64)
+    g.close()
+    return out
+
+
+def assert_same(api_mod, ctx, theta, blocks, omega, seed):
+    rp, ci = gpu_csr(api_mod, ctx, theta, blocks, omega, seed)
+    orp, oci = sbm_sample.sample_csr(theta, blocks, omega, seed)
+    assert np.array_equal(rp, orp), "row_ptr differs"
+    assert np.array_equal(ci, oci), "col_idx differs"
+    return rp, ci
+
+
+def test_tiny_models_many_seeds(api_mod, ctx):
+    theta = np.array([0.5, 1.0, 1.5, 0.8, 1.2, 0.7, 1.1])
+    blocks = np.array([0, 1, 0, 1, 0, 1, 1])
+    omega = np.array([[0.9, 0.15], [0.15, 0.6]])
+    total = 0
+    for seed in range(40):
+        rp, _ = assert_same(api_mod, ctx, theta, blocks, omega, seed)
+        total += int(rp[-1])
+    assert total > 0
+
+
+@pytest.mark.parametrize("n,k,seed", [(20000, 12, 3), (50000, 20, 8)])
+def test_dcsbm_models_equal_oracle(api_mod, ctx, n, k, seed):
+    theta, blocks, omega = dcsbm_model(n, k, seed=seed)
+    rp, _ = assert_same(api_mod, ctx, theta, blocks, omega, seed + 100)
+    print(f"sampler n={n} k={k}: {int(rp[-1]) // 2} edges", flush=True)
+    assert 15 * n / 2 < rp[-1] / 2 < 30 * n / 2
+
+
+def test_empty_and_single_blocks(api_mod, ctx):
+    rng = np.random.default_rng(5)
+    n, k = 3000, 7
+    blocks = rng.integers(0, k, n).astype(np.int32)
+    blocks[blocks == 3] = 1                       # empty block
+    blocks[blocks == 6] = 0                       # empty last block
+    blocks[blocks == 5] = 2
+    blocks[17] = 5                                # one-node block
+    theta = rng.uniform(0.0, 2.0, n)
+    theta[::50] = 0.0                             # nodes that never join
+    omega = np.full((k, k), 0.0005) + np.eye(k) * 0.004
+    omega[2, 4] = omega[4, 2] = 0.0               # a pair of blocks never joined
+    for seed in (0, 1, 2):
+        assert_same(api_mod, ctx, theta, blocks, omega, seed)
+
+
+def test_zero_and_complete(api_mod, ctx):
+    n = 300
+    blocks = (np.arange(n) % 3).astype(np.int32)
+    theta = np.ones(n)
+    rp, ci = assert_same(api_mod, ctx, theta, blocks, np.zeros((3, 3)), 4)
+    assert rp[-1] == 0
+    rp, ci = assert_same(api_mod, ctx, theta, blocks, np.full((3, 3), 1e6), 4)
+    assert rp[-1] == n * (n - 1)
+    assert np.all(np.diff(rp) == n - 1)
+
+
+def test_n1m_sampled_rows(api_mod, ctx):
+    """1M nodes, 50 blocks: the neighbours of a node i in block r that lie in
+    a later block, or in block r with a larger id, are exactly the output of
+    the oracle's rows (r, s, x_i), s >= r."""
+    n, k, seed = 1_000_000, 50, 21
+    theta, blocks, omega = dcsbm_model(n, k, seed=2)
+    g = api_mod.sbm_sample(ctx, theta, blocks, omega, seed)
+    rp, ci = g.csr()
+    torch.cuda.synchronize()
+    rp, ci = rp.cpu().numpy(), ci.cpu().numpy()
+    g.close()
+    print(f"sampler n1m: {int(rp[-1]) // 2} edges", flush=True)
+    members = sbm_sample.block_members(blocks, k)
+    pref = [sbm_sample.prefix(theta, m) for m in members]
+    pos = np.empty(n, dtype=np.int64)
+    for r in range(k):
+        pos[members[r]] = np.arange(members[r].size)
+    rng = np.random.default_rng(0)
+    nodes = list(rng.choice(n, 60, replace=False))
+    nodes.append(int(np.argmax(theta)))
+    for i in nodes:
+        r, x = int(blocks[i]), int(pos[i])
+        want = []
+        for s in range(r, k):
+            want += sbm_sample.row_edges(theta, members, pref, omega, r, s, x, seed)
+        nb = ci[rp[i]:rp[i + 1]].astype(np.int64)
+        later = nb[(blocks[nb] > r) | ((blocks[nb] == r) & (nb > i))]
+        assert np.array_equal(np.sort(later), np.sort(np.asarray(want, dtype=np.int64))), i
+    # edge count near the closed-form mean sum(1 - exp(-lambda)) ~ sum lambda
+    # (lambda <= 1e-2 here, so the two differ by under 1%)
+    vol = np.bincount(blocks, weights=theta, minlength=k)
+    mean_l = 0.5 * (vol @ omega @ vol - np.sum(omega[blocks, blocks] * theta * theta))
+    assert abs(rp[-1] / 2 - mean_l) < 0.02 * mean_l
+
+
+def test_argument_errors(api_mod, ctx):
+    theta = np.ones(10)
+    blocks = np.zeros(10, dtype=np.int32)
+    omega = np.full((2, 2), 0.1)
+    bad = blocks.copy()
+    bad[3] = 2
+    with pytest.raises(RuntimeError):
+        api_mod.sbm_sample(ctx, theta, bad, omega, 0)
+    asym = omega.copy()
+    asym[0, 1] = 0.2
+    with pytest.raises(RuntimeError):
+        api_mod.sbm_sample(ctx, theta, blocks, asym, 0)
+    neg = theta.copy()
+    neg[0] = -1.0
+    with pytest.raises(RuntimeError):
+        api_mod.sbm_sample(ctx, neg, blocks, omega, 0)
+    nan = omega.copy()
+    nan[1, 1] = np.nan
+    with pytest.raises(RuntimeError):
+        api_mod.sbm_sample(ctx, theta, blocks, nan, 0)

@@ -104,3 +104,33 @@ def test_csr_is_valid():
     # deterministic in the seed
     rp2, ci2 = sbm_sample.sample_csr(theta, blocks, omega, 11)
     assert np.array_equal(rp, rp2) and np.array_equal(ci, ci2)
+
+
+def test_row_form_equals_table_form():
+    """The scalar per-row form gives, row by row, the table form's edges
+    (models with an empty block, a one-node block and a strong diagonal)."""
+    rng = np.random.default_rng(5)
+    n, k = 120, 5
+    blocks = rng.integers(0, k, n)
+    blocks[blocks == 3] = 1                       # block 3 empty
+    blocks[7] = 4
+    blocks[blocks == 4] = 2
+    blocks[7] = 4                                 # block 4 = one node
+    theta = rng.uniform(0.2, 2.5, n)
+    omega = np.full((k, k), 0.02) + np.eye(k) * 0.3
+    members = sbm_sample.block_members(blocks, k)
+    pref = [sbm_sample.prefix(theta, m) for m in members]
+    for seed in (0, 9):
+        a, b = sbm_sample.sample_edges(theta, blocks, omega, seed)
+        got_a, got_b = [], []
+        for r in range(k):
+            for s in range(r, k):
+                if members[r].size == 0 or members[s].size == 0:
+                    continue
+                for x in range(members[r].size):
+                    cols = sbm_sample.row_edges(theta, members, pref, omega, r, s, x, seed)
+                    got_a += [int(members[r][x])] * len(cols)
+                    got_b += cols
+        # the table form emits jump by jump across rows; compare as edge sets
+        assert sorted(zip(a.tolist(), b.tolist())) == sorted(zip(got_a, got_b))
+        assert len(got_a) == a.size
