@@ -15,6 +15,8 @@ Modules (each function cites the passage of the paper it follows):
 * ``kmeans``     -- nested k-means++ seeding (exponential race) and Lloyd.
 * ``scores``     -- modularity (Eq. 3), NCut (Eq. 1), model selection, NMI.
 * ``hierarchical`` -- local modularity (Eq. 7) and hierarchical model selection (Alg. 1).
+* ``sbm_sample`` -- fast sampling from the degree-corrected SBM (Sec. IV, Alg. 2).
+* ``streaming``  -- incremental embedding update for new edges (Sec. III-D).
 * ``modloss``    -- relaxed modularity loss tr(S^T B S) and its adjoint.
 * ``pipeline``   -- the whole path end to end.
 
