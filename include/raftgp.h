@@ -138,6 +138,50 @@ raft_status raft_graph_size(const raft_graph* g, int64_t* n, int64_t* nnz);
  * col_idx int32 [nnz] (sorted rows), asynchronous on `stream`. */
 raft_status raft_graph_csr(const raft_graph* g, int32_t* row_ptr, int32_t* col_idx, void* stream);
 
+/* ---- streaming graphs (Sec. III-D) ------------------------------------------ */
+
+/* A stream holds a graph and every level of its embedding (Theta, Y_1..Y_q,
+ * the input of layer 1 and the GCN layer outputs, all in library-owned device
+ * memory, about (q + n_layers + 4) x N x max width floats) and updates them
+ * when edges arrive.  New edges change the degrees of their endpoints V'
+ * only; under the NCut operator M (Eq. 2) and the GCN operator (Eq. 6) an
+ * entry depends on its two endpoints' degrees, so level t of Y = X^q Theta
+ * can change only within t hops of V' and GCN layer k within q + k hops (the
+ * multi-hop neighbourhood V'' of the section).  raft_stream_add_edges
+ * recomputes each level on that ball only, with the row kernels of a full
+ * pass, so the result equals raft_project + raft_embed on the new graph bit
+ * for bit.  Under the modularity operators (Eq. 4, Q~) every entry carries
+ * 1/2e, which any new edge changes: there every level is recomputed in full.
+ * Model selection (raft_partition, raft_hier_partition) runs on the stream's
+ * current graph and embedding; it is not incremental.
+ *
+ * raft_stream_create: copies g, computes every level with cfg (op, proj_dim,
+ * q, layers, normalize_input, seed; the candidate grid is checked as for
+ * raft_run but not used); q + n_layers <= 64.  Synchronous. */
+typedef struct raft_stream raft_stream;
+raft_status raft_stream_create(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg,
+                               void* stream, raft_stream** out);
+void        raft_stream_destroy(raft_stream* s);
+/* Adds the m undirected edges (src[e], dst[e]) (host int32 arrays, either
+ * order).  RAFT_E_INVAL on an endpoint out of range, a self pair or an edge
+ * given twice, RAFT_E_CSR on an edge already in the graph: in both cases
+ * nothing changes.  rows_per_level (nullable, q + n_layers entries) receives
+ * the number of rows within each level's hop ball (N everywhere for the
+ * modularity operators); a level whose ball holds more than half of the rows
+ * is run over all rows (rows outside the ball recompute to their previous
+ * values).  The stream keeps two graph buffers and alternates between them,
+ * so a handle from raft_stream_graph must be fetched again after each update.
+ * Synchronous.  After RAFT_E_DEVICE the stream must be destroyed. */
+raft_status raft_stream_add_edges(raft_stream* s, const int32_t* src, const int32_t* dst,
+                                  int64_t m, void* stream, int64_t* rows_per_level);
+/* The current graph (owned by the stream, never passed to
+ * raft_graph_destroy; valid until the next raft_stream_add_edges or
+ * raft_stream_destroy). */
+raft_status raft_stream_graph(const raft_stream* s, const raft_graph** g);
+/* Device copies of the current Y = X^q Theta [N x L] and Z [N x d] (either
+ * pointer may be NULL), asynchronous on `stream`. */
+raft_status raft_stream_embedding(const raft_stream* s, float* Y, float* Z, void* stream);
+
 /* ---- graph sampling (Sec. IV, Alg. 2: fast degree-corrected SBM) --------- */
 
 /* Samples an undirected graph from the degree-corrected SBM (Sec. II, SBM

@@ -29,7 +29,8 @@ EXPORTS = [
     "raft_batch_run", "raft_batch_set_capture", "raft_batch_plan_check", "raft_batch_stage_times",
     "raft_batch_tuning", "raft_hier_workspace_size", "raft_hier_partition",
     "raft_spmm_merge_workspace_size", "raft_spmm_merge", "raft_graph_size", "raft_graph_csr",
-    "raft_sbm_sample",
+    "raft_sbm_sample", "raft_stream_create", "raft_stream_destroy", "raft_stream_add_edges",
+    "raft_stream_graph", "raft_stream_embedding",
 ]
 
 PROF_SPMM, PROF_DENSE, PROF_RACE, PROF_ASSIGN, PROF_UPDATE, PROF_SCORE = range(6)
@@ -100,6 +101,11 @@ _SIGNATURES = {
     "raft_graph_degrees": (_I32, [_P, _P, _P]),
     "raft_graph_size": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
     "raft_graph_csr": (_I32, [_P, _P, _P, _P]),
+    "raft_stream_create": (_I32, [_P, _P, ctypes.POINTER(RaftConfig), _P, ctypes.POINTER(_P)]),
+    "raft_stream_destroy": (None, [_P]),
+    "raft_stream_add_edges": (_I32, [_P, _P, _P, _I64, _P, _P]),
+    "raft_stream_graph": (_I32, [_P, ctypes.POINTER(_P)]),
+    "raft_stream_embedding": (_I32, [_P, _P, _P, _P]),
     "raft_sbm_sample": (_I32, [_P, _I64, _I32, _P, _P, _P, ctypes.c_uint64, _P,
                                ctypes.POINTER(_P)]),
     "raft_workspace_size": (_I32, [_P, _P, ctypes.POINTER(RaftConfig), ctypes.POINTER(_SZ)]),

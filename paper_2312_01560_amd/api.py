@@ -166,7 +166,8 @@ class Graph:
 
     def close(self):
         if getattr(self, "h", None):
-            self.ctx.lib.raft_graph_destroy(self.h)
+            if getattr(self, "_owned", True):
+                self.ctx.lib.raft_graph_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -486,3 +487,61 @@ def sbm_sample(ctx, theta, blocks, omega, seed):
                                       omega.ctypes.data_as(ctypes.c_void_p),
                                       ctypes.c_uint64(int(seed)), _stream(), ctypes.byref(h)))
     return Graph._from_handle(ctx, h)
+
+
+class Stream:
+    """A graph and every level of its embedding, updated as edges arrive
+    (Sec. III-D): under NCut each level is recomputed on the hop ball of the
+    new edges' endpoints only; under the modularity operators in full."""
+
+    def __init__(self, ctx, g, cfg):
+        self.ctx, self.cfg, self.n = ctx, cfg, g.n
+        c = cfg.to_c()
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.raft_stream_create(ctx.h, g.h, ctypes.byref(c), _stream(),
+                                             ctypes.byref(h)))
+        self.h = h
+
+    @property
+    def levels(self):
+        return self.cfg.q + len(self.cfg.layer_dims)
+
+    def add_edges(self, src, dst):
+        """Adds the undirected edges (src[e], dst[e]); returns the rows
+        recomputed at each level (numpy int64, q + layers entries)."""
+        src = np.ascontiguousarray(src, dtype=np.int32)
+        dst = np.ascontiguousarray(dst, dtype=np.int32)
+        if src.shape != dst.shape:
+            raise ValueError("src and dst differ in length")
+        rows = np.zeros(self.levels, dtype=np.int64)
+        self.ctx.check(self.ctx.lib.raft_stream_add_edges(
+            self.h, src.ctypes.data_as(ctypes.c_void_p), dst.ctypes.data_as(ctypes.c_void_p),
+            src.size, _stream(), rows.ctypes.data_as(ctypes.c_void_p)))
+        return rows
+
+    def graph(self):
+        """The current graph (owned by the stream; valid until the next
+        add_edges or close)."""
+        h = ctypes.c_void_p()
+        self.ctx.check(self.ctx.lib.raft_stream_graph(self.h, ctypes.byref(h)))
+        g = Graph._from_handle(self.ctx, h)
+        g._owned = False
+        return g
+
+    def embedding(self):
+        """(Y [N x L], Z [N x d]) device copies of the current levels."""
+        y = self.ctx.empty((self.n, self.cfg.proj_dim), torch.float32)
+        z = self.ctx.empty((self.n, self.cfg.embed_dim), torch.float32)
+        self.ctx.check(self.ctx.lib.raft_stream_embedding(self.h, _ptr(y), _ptr(z), _stream()))
+        return y, z
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.raft_stream_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libraftgp.so")
 SOURCES = ["capi.hip", "graph.hip", "gauss.hip", "spmm.hip", "dense.hip", "kmeans.hip", "train.hip",
-           "score.hip", "confusion.hip", "hier.hip", "sampler.hip"]
+           "score.hip", "confusion.hip", "hier.hip", "sampler.hip", "stream.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

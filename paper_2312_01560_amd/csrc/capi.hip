@@ -52,6 +52,7 @@ struct raft_graph {
     float* sh = nullptr;
     float* dcoef = nullptr;
     int32_t* order = nullptr;   // rows by degree class, heaviest first (stable)
+    bool owns = true;           // false: the arrays belong to a stream
     GraphView view() const {
         GraphView v;
         v.n = n;
@@ -909,7 +910,7 @@ raft_status raft_graph_create(raft_ctx* ctx, const void* row_ptr, int row_ptr_is
 }
 
 void raft_graph_destroy(raft_graph* g) {
-    if (!g) return;
+    if (!g || !g->owns) return;
     (void)hipDeviceSynchronize();
     if (g->rp) (void)hipFree(g->rp);
     if (g->ci) (void)hipFree(g->ci);
@@ -2978,6 +2979,377 @@ raft_status raft_sbm_sample(raft_ctx* ctx, int64_t n, int32_t k, const double* t
     RAFT_TRY(launch_check(ctx));
     HIP_TRY(ctx, hipStreamSynchronize(st));
     return raft_graph_create(ctx, rp, 1, col, n, 2 * ne, 1, stream, out);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Streaming update (Sec. III-D).  The stream keeps every level of the
+// embedding: Theta, Y_1..Y_q, the input of layer 1 (Y_q or its row-normalised
+// copy) and the layer outputs H_1..H_n.  New edges are merged into a new CSR
+// (the degree arrays recomputed by the same kernel as at graph creation, the
+// row schedule kept from the previous graph: it only orders work), and under
+// the NCut operator level t is recomputed on the rows within t hops of the
+// new edges' endpoints (layer k on q + k hops) by the same row kernels as a
+// full pass, so every row equals a full recomputation on the new graph bit
+// for bit.  The modularity operators carry 1/2e in every entry, so there
+// every level is recomputed in full.
+// ---------------------------------------------------------------------------
+struct raft_stream {
+    raft_ctx* ctx = nullptr;
+    raft_graph gr[2];                      // current and next graph (stream-owned arrays)
+    int cur = 0;
+    int64_t ci_cap[2] = {0, 0};
+    raft_config cfg{};
+    int n = 0, L = 0, R = 0, lmax = 0;
+    std::vector<int> lin, lout;            // per layer
+    std::vector<float*> y;                 // q + 1 levels, y[0] = Theta
+    float* h0 = nullptr;                   // normalised input (normalize_input only)
+    std::vector<float*> h, w;              // layer outputs and weights
+    float *pbuf = nullptr, *gin = nullptr, *gout = nullptr;
+    double *cpart = nullptr, *c64 = nullptr;
+    float* cvec = nullptr;
+    int32_t *dist = nullptr, *lists = nullptr, *mstatus = nullptr;
+    int64_t *flag = nullptr, *pos = nullptr, *bsum = nullptr, *totals = nullptr;
+    int64_t *add_cnt = nullptr, *add_off = nullptr;
+    int32_t* edges = nullptr;              // staging: rows, cols, V' (3 x edge_cap)
+    int64_t edge_cap = 0;
+    std::vector<void*> mem;
+    raft_graph* g() { return &gr[cur]; }
+    const float* input() const { return h0 ? h0 : y[cfg.q]; }
+    const float* z() const { return cfg.n_layers ? h[cfg.n_layers - 1] : input(); }
+};
+
+namespace {
+
+template <typename T>
+bool stream_alloc(raft_stream* s, T** p, size_t count) {
+    void* q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return false;
+    s->mem.push_back(q);
+    *p = static_cast<T*>(q);
+    return true;
+}
+
+// Replaces *p (a stream allocation, or null) by a larger one; the old
+// contents are not kept.
+template <typename T>
+bool stream_realloc(raft_stream* s, T** p, size_t count) {
+    if (*p) {
+        auto it = std::find(s->mem.begin(), s->mem.end(), (void*)*p);
+        if (it != s->mem.end()) s->mem.erase(it);
+        (void)hipFree(*p);
+        *p = nullptr;
+    }
+    return stream_alloc(s, p, count);
+}
+
+// Level t is run over all rows once its ball holds more than half of them:
+// rows outside the ball recompute to their previous values, and a full
+// launch needs no row gather and scatter.
+bool stream_level_full(const raft_stream* s, const int64_t* counts, int t) {
+    return 2 * counts[t - 1] > (int64_t)s->n;
+}
+
+// Every level from scratch, in the order and with the kernels of
+// raft_project and raft_embed.
+raft_status stream_full(raft_stream* s, hipStream_t st) {
+    raft_ctx* ctx = s->ctx;
+    const GraphView gv = s->g()->view();
+    const raft_config& c = s->cfg;
+    const int n = s->n, L = s->L;
+    const bool mod_full = c.op == RAFT_X_MOD_FULL;
+    const int grid = spmm_grid(n, L, ctx->num_cu, nullptr);
+    if (mod_full) {
+        launch_colsum_partials(gv, L, s->y[0], s->cpart, ctx->num_cu, st);
+        launch_colsum_finish(s->cpart, grid, L, s->c64, s->cvec, st);
+    }
+    for (int t = 1; t <= c.q; ++t) {
+        const bool need_cs = mod_full && t < c.q;
+        launch_spmm(gv, c.op, L, s->y[t - 1], s->y[t], s->cvec, need_cs ? s->cpart : nullptr,
+                    ctx->num_cu, st);
+        if (need_cs) launch_colsum_finish(s->cpart, grid, L, s->c64, s->cvec, st);
+    }
+    if (s->h0) {
+        HIP_TRY(ctx, hipMemcpyAsync(s->h0, s->y[c.q], (size_t)n * L * sizeof(float),
+                                    hipMemcpyDeviceToDevice, st));
+        launch_rownorm(s->h0, n, L, st);
+    }
+    const float* hin = s->input();
+    for (int k = 0; k < c.n_layers; ++k) {
+        launch_spmm(gv, kOpGcn, s->lin[k], hin, s->pbuf, nullptr, nullptr, ctx->num_cu, st);
+        launch_dense_layer(s->pbuf, s->w[k], s->h[k], n, s->lin[k], s->lout[k], false,
+                           ctx->d_status, st);
+        hin = s->h[k];
+    }
+    return launch_check(ctx);
+}
+
+// Level t on lists[t - 1] (counts[t - 1] rows), or on all rows once the
+// ball is most of the graph; NCut operator.
+raft_status stream_incremental(raft_stream* s, const int64_t* counts, hipStream_t st) {
+    raft_ctx* ctx = s->ctx;
+    const raft_config& c = s->cfg;
+    const int n = s->n, L = s->L;
+    const GraphView all = s->g()->view();
+    auto sub = [&](int t) {
+        if (stream_level_full(s, counts, t)) return all;
+        GraphView v = all;
+        v.order = s->lists + (size_t)(t - 1) * n;
+        v.n = (int32_t)counts[t - 1];
+        return v;
+    };
+    for (int t = 1; t <= c.q; ++t)
+        launch_spmm(sub(t), kOpNcut, L, s->y[t - 1], s->y[t], nullptr, nullptr, ctx->num_cu, st);
+    if (s->h0) {
+        if (stream_level_full(s, counts, c.q)) {
+            HIP_TRY(ctx, hipMemcpyAsync(s->h0, s->y[c.q], (size_t)n * L * sizeof(float),
+                                        hipMemcpyDeviceToDevice, st));
+            launch_rownorm(s->h0, n, L, st);
+        } else {
+            const int32_t* lq = s->lists + (size_t)(c.q - 1) * n;
+            const int32_t cq = (int32_t)counts[c.q - 1];
+            launch_stream_rows(true, lq, cq, L, s->y[c.q], s->gin, st);
+            launch_rownorm(s->gin, cq, L, st);
+            launch_stream_rows(false, lq, cq, L, s->gin, s->h0, st);
+        }
+    }
+    const float* hin = s->input();
+    for (int k = 0; k < c.n_layers; ++k) {
+        const int t = c.q + k + 1;
+        launch_spmm(sub(t), kOpGcn, s->lin[k], hin, s->pbuf, nullptr, nullptr, ctx->num_cu, st);
+        if (stream_level_full(s, counts, t)) {
+            launch_dense_layer(s->pbuf, s->w[k], s->h[k], n, s->lin[k], s->lout[k], false,
+                               ctx->d_status, st);
+        } else {
+            const int32_t* lt = s->lists + (size_t)(t - 1) * n;
+            const int32_t ct = (int32_t)counts[t - 1];
+            launch_stream_rows(true, lt, ct, s->lin[k], s->pbuf, s->gin, st);
+            launch_dense_layer(s->gin, s->w[k], s->gout, ct, s->lin[k], s->lout[k], false,
+                               ctx->d_status, st);
+            launch_stream_rows(false, lt, ct, s->lout[k], s->gout, s->h[k], st);
+        }
+        hin = s->h[k];
+    }
+    return launch_check(ctx);
+}
+
+}  // namespace
+
+extern "C" {
+
+void raft_stream_destroy(raft_stream* s) {
+    if (!s) return;
+    (void)hipDeviceSynchronize();
+    for (void* q : s->mem) (void)hipFree(q);
+    delete s;
+}
+
+raft_status raft_stream_create(raft_ctx* ctx, const raft_graph* g, const raft_config* cfg,
+                               void* stream, raft_stream** out) {
+    RAFT_TRY(check_graph(ctx, g));
+    if (!out) return fail(ctx, RAFT_E_INVAL, "out is null");
+    *out = nullptr;
+    RAFT_TRY(check_config(ctx, g, cfg));
+    if (cfg->q + cfg->n_layers > kStreamMaxLevels)
+        return fail(ctx, RAFT_E_UNSUPPORTED, "q + n_layers = %d exceeds %d",
+                    cfg->q + cfg->n_layers, kStreamMaxLevels);
+    hipStream_t st = as_stream(stream);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    raft_stream* s = new raft_stream();
+    s->ctx = ctx;
+    s->cfg = *cfg;
+    s->n = g->n;
+    s->L = cfg->proj_dim;
+    s->R = cfg->q + cfg->n_layers;
+    s->lmax = s->L;
+    int l = s->L;
+    for (int k = 0; k < cfg->n_layers; ++k) {
+        s->lin.push_back(l);
+        s->lout.push_back(cfg->layer_dims[k]);
+        l = cfg->layer_dims[k];
+        s->lmax = std::max(s->lmax, l);
+    }
+    auto cleanup = [&](raft_status code, const char* what) {
+        raft_stream_destroy(s);
+        return fail(ctx, code, "stream: %s", what);
+    };
+    const size_t n = (size_t)s->n;
+    bool ok = true;
+    // two graphs: the current one (a copy of g) and the next one
+    for (int b = 0; b < 2; ++b) {
+        raft_graph& G = s->gr[b];
+        G.ctx = ctx;
+        G.n = g->n;
+        G.nnz = g->nnz;
+        G.owns = false;
+        s->ci_cap[b] = std::max<int64_t>(g->nnz + g->nnz / 4, 1024);
+        ok = ok && stream_alloc(s, &G.rp, n + 1) && stream_alloc(s, &G.ci, s->ci_cap[b]) &&
+             stream_alloc(s, &G.deg, n) && stream_alloc(s, &G.s, n) && stream_alloc(s, &G.sh, n) &&
+             stream_alloc(s, &G.dcoef, n) && stream_alloc(s, &G.order, n);
+    }
+    s->y.assign(cfg->q + 1, nullptr);
+    s->h.assign(cfg->n_layers, nullptr);
+    s->w.assign(cfg->n_layers, nullptr);
+    for (auto& p : s->y) ok = ok && stream_alloc(s, &p, n * s->L);
+    if (cfg->normalize_input) ok = ok && stream_alloc(s, &s->h0, n * s->L);
+    for (int k = 0; k < cfg->n_layers; ++k)
+        ok = ok && stream_alloc(s, &s->h[k], n * s->lout[k]) &&
+             stream_alloc(s, &s->w[k], (size_t)s->lin[k] * s->lout[k]);
+    const int grid = spmm_grid(s->n, s->L, ctx->num_cu, nullptr);
+    ok = ok && stream_alloc(s, &s->pbuf, n * s->lmax) && stream_alloc(s, &s->gin, n * s->lmax) &&
+         stream_alloc(s, &s->gout, n * s->lmax) &&
+         stream_alloc(s, &s->cpart, ((size_t)grid + kColsumStageRows) * s->L) &&
+         stream_alloc(s, &s->c64, (size_t)s->L) && stream_alloc(s, &s->cvec, (size_t)s->L) &&
+         stream_alloc(s, &s->dist, n) && stream_alloc(s, &s->lists, n * s->R) &&
+         stream_alloc(s, &s->flag, n) && stream_alloc(s, &s->pos, n) &&
+         stream_alloc(s, &s->bsum, (n + 1 + 1023) / 1024 + 1) &&
+         stream_alloc(s, &s->totals, (size_t)kStreamMaxLevels + 1) &&
+         stream_alloc(s, &s->add_cnt, n + 1) && stream_alloc(s, &s->add_off, n + 1) &&
+         stream_alloc(s, &s->mstatus, 1);
+    if (!ok) return cleanup(RAFT_E_NOMEM, "device allocation failed");
+    raft_graph& G = s->gr[0];
+    const hipMemcpyKind dd = hipMemcpyDeviceToDevice;
+    hipError_t e = hipMemcpyAsync(G.rp, g->rp, sizeof(int32_t) * (n + 1), dd, st);
+    if (e == hipSuccess && g->nnz > 0)
+        e = hipMemcpyAsync(G.ci, g->ci, sizeof(int32_t) * g->nnz, dd, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(G.deg, g->deg, sizeof(int32_t) * n, dd, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(G.s, g->s, sizeof(float) * n, dd, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(G.sh, g->sh, sizeof(float) * n, dd, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(G.dcoef, g->dcoef, sizeof(float) * n, dd, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(G.order, g->order, sizeof(int32_t) * n, dd, st);
+    if (e != hipSuccess) return cleanup(RAFT_E_DEVICE, "graph copy");
+    launch_gaussian(cfg->seed, 0x10, s->n, s->L, 1.0 / std::sqrt((double)s->L), s->y[0], st);
+    for (int k = 0; k < cfg->n_layers; ++k)
+        launch_gaussian(cfg->seed, 0x10 + (uint64_t)(k + 1), s->lin[k], s->lout[k],
+                        1.0 / std::sqrt((double)s->lin[k]), s->w[k], st);
+    const raft_status r = stream_full(s, st);
+    if (r == RAFT_OK && hipStreamSynchronize(st) != hipSuccess)
+        return cleanup(RAFT_E_DEVICE, "initial levels");
+    if (r != RAFT_OK) {
+        raft_stream_destroy(s);
+        return r;
+    }
+    *out = s;
+    return RAFT_OK;
+}
+
+raft_status raft_stream_graph(const raft_stream* s, const raft_graph** g) {
+    if (!s || !g) return RAFT_E_INVAL;
+    *g = &s->gr[s->cur];
+    return RAFT_OK;
+}
+
+raft_status raft_stream_embedding(const raft_stream* s, float* Y, float* Z, void* stream) {
+    if (!s) return RAFT_E_INVAL;
+    raft_ctx* ctx = s->ctx;
+    hipStream_t st = as_stream(stream);
+    const size_t n = (size_t)s->n;
+    if (Y)
+        HIP_TRY(ctx, hipMemcpyAsync(Y, s->y[s->cfg.q], n * s->L * sizeof(float),
+                                    hipMemcpyDeviceToDevice, st));
+    if (Z) {
+        const int d = s->cfg.n_layers ? s->lout.back() : s->L;
+        HIP_TRY(ctx, hipMemcpyAsync(Z, s->z(), n * d * sizeof(float), hipMemcpyDeviceToDevice, st));
+    }
+    return RAFT_OK;
+}
+
+raft_status raft_stream_add_edges(raft_stream* s, const int32_t* src, const int32_t* dst,
+                                  int64_t m, void* stream, int64_t* rows_per_level) {
+    if (!s) return RAFT_E_INVAL;
+    raft_ctx* ctx = s->ctx;
+    if (m < 0 || (m > 0 && (!src || !dst))) return fail(ctx, RAFT_E_INVAL, "edge arrays");
+    const int n = s->n;
+    if (m == 0) {
+        if (rows_per_level) std::fill(rows_per_level, rows_per_level + s->R, (int64_t)0);
+        return RAFT_OK;
+    }
+    raft_graph* g = s->g();
+    if (g->nnz + 2 * m >= INT32_MAX)
+        return fail(ctx, RAFT_E_UNSUPPORTED, "%lld entries do not fit the int32 CSR",
+                    (long long)(g->nnz + 2 * m));
+    // both directions of every edge sorted by (row, col); V' = the rows
+    std::vector<std::pair<int32_t, int32_t>> dir;
+    dir.reserve((size_t)2 * m);
+    for (int64_t e = 0; e < m; ++e) {
+        const int32_t a = src[e], b = dst[e];
+        if (a < 0 || a >= n || b < 0 || b >= n)
+            return fail(ctx, RAFT_E_INVAL, "edge %lld (%d, %d) out of range", (long long)e, a, b);
+        if (a == b) return fail(ctx, RAFT_E_INVAL, "edge %lld is a self pair (%d)", (long long)e, a);
+        dir.emplace_back(a, b);
+        dir.emplace_back(b, a);
+    }
+    std::sort(dir.begin(), dir.end());
+    for (size_t q = 1; q < dir.size(); ++q)
+        if (dir[q] == dir[q - 1])
+            return fail(ctx, RAFT_E_INVAL, "edge (%d, %d) given twice", dir[q].first,
+                        dir[q].second);
+    const int64_t m2 = (int64_t)dir.size(), nnz2 = g->nnz + m2;
+    std::vector<int32_t> host((size_t)3 * m2);
+    int32_t* rows = host.data();
+    int32_t* cols = rows + m2;
+    int32_t* vp = cols + m2;
+    int nv = 0;
+    for (int64_t q = 0; q < m2; ++q) {
+        rows[q] = dir[q].first;
+        cols[q] = dir[q].second;
+        if (q == 0 || rows[q] != rows[q - 1]) vp[nv++] = rows[q];
+    }
+    hipStream_t st = as_stream(stream);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const int nxt = 1 - s->cur;
+    raft_graph* g2 = &s->gr[nxt];
+    if (s->edge_cap < m2) {
+        if (!stream_realloc(s, &s->edges, (size_t)3 * m2)) {
+            s->edge_cap = 0;
+            return fail(ctx, RAFT_E_NOMEM, "stream edge staging");
+        }
+        s->edge_cap = m2;
+    }
+    if (s->ci_cap[nxt] < nnz2) {
+        const int64_t cap = std::min<int64_t>(nnz2 + nnz2 / 4, INT32_MAX);
+        if (!stream_realloc(s, &g2->ci, cap)) {
+            s->ci_cap[nxt] = 0;
+            return fail(ctx, RAFT_E_NOMEM, "stream graph growth");
+        }
+        s->ci_cap[nxt] = cap;
+    }
+    int32_t* d_rows = s->edges;
+    int32_t* d_cols = d_rows + m2;
+    int32_t* d_vp = d_cols + m2;
+    HIP_TRY(ctx, hipMemcpyAsync(d_rows, host.data(), sizeof(int32_t) * (2 * m2 + nv),
+                                hipMemcpyHostToDevice, st));
+    HIP_TRY(ctx, hipMemsetAsync(s->mstatus, 0, sizeof(int32_t), st));
+    launch_stream_merge(g->rp, g->ci, n, d_rows, d_cols, m2, s->add_cnt, s->add_off, s->bsum,
+                        s->totals, g2->rp, g2->ci, s->mstatus, st);
+    HIP_TRY(ctx, hipMemcpyAsync(g2->order, g->order, sizeof(int32_t) * n, hipMemcpyDeviceToDevice,
+                                st));
+    launch_degrees(g2->rp, n, nnz2, g2->deg, g2->s, g2->sh, g2->dcoef, st);
+    const bool local = s->cfg.op == RAFT_X_NCUT;
+    if (local)
+        launch_stream_balls(g2->rp, g2->ci, n, d_vp, nv, s->R, s->dist, s->flag, s->pos, s->bsum,
+                            s->totals, s->lists, st);
+    RAFT_TRY(launch_check(ctx));
+    // status and the ball sizes in one read-back (the pageable staging
+    // vector above is also released by this wait)
+    int32_t* h_status = ctx->h_pinned;
+    int64_t* h_counts = reinterpret_cast<int64_t*>(ctx->h_pinned + 2);
+    HIP_TRY(ctx, hipMemcpyAsync(h_status, s->mstatus, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (local)
+        HIP_TRY(ctx, hipMemcpyAsync(h_counts, s->totals, sizeof(int64_t) * s->R,
+                                    hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    if (h_status[0])
+        return fail(ctx, RAFT_E_CSR, "stream update: an edge is already in the graph; nothing changed");
+    std::vector<int64_t> counts(s->R, n);
+    if (local) std::copy(h_counts, h_counts + s->R, counts.begin());
+    g2->nnz = nnz2;
+    s->cur = nxt;
+    const raft_status r = local ? stream_incremental(s, counts.data(), st) : stream_full(s, st);
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    if (rows_per_level) std::copy(counts.begin(), counts.end(), rows_per_level);
+    return r;
 }
 
 }  // extern "C"

@@ -353,6 +353,26 @@ hipError_t launch_sbm_csr(const int32_t* src, const int32_t* dst, int64_t ne, in
                           int64_t* deg, int64_t* rp, int64_t* cursor, int64_t* bsum,
                           int64_t* total, int32_t* col, hipStream_t st);
 
+// ---- stream.hip ------------------------------------------------------------
+constexpr int kStreamMaxLevels = 64;   // q + GCN layers of a stream
+// Merged CSR of a graph and m directed new entries (rows, cols) sorted by
+// (row, col): add_cnt / add_off [n + 1], bsum [ceil((n + 1) / 1024)],
+// total [1], rp_new [n + 1], ci_new [nnz + m].  A new entry already in the
+// graph sets kStatusCsrSym.
+void launch_stream_merge(const int32_t* rp, const int32_t* ci, int32_t n, const int32_t* rows,
+                         const int32_t* cols, int64_t m, int64_t* add_cnt, int64_t* add_off,
+                         int64_t* bsum, int64_t* total, int32_t* rp_new, int32_t* ci_new,
+                         int32_t* status, hipStream_t st);
+// Hop distances from vprime (radius + 1 beyond radius) and, for t = 1..radius,
+// lists[(t - 1) n ..] = the rows within t hops in increasing id, totals[t - 1]
+// their number.  flag / pos [n], bsum [ceil(n / 1024)].
+void launch_stream_balls(const int32_t* rp, const int32_t* ci, int32_t n, const int32_t* vprime,
+                         int32_t nv, int radius, int32_t* dist, int64_t* flag, int64_t* pos,
+                         int64_t* bsum, int64_t* totals, int32_t* lists, hipStream_t st);
+// Row gather (dst[r] = src[list[r]]) or scatter (dst[list[r]] = src[r]).
+void launch_stream_rows(bool gather, const int32_t* list, int32_t c, int L, const float* src,
+                        float* dst, hipStream_t st);
+
 // ---- confusion.hip -------------------------------------------------------
 // counts [ka x kb] int64 (zeroed here) = joint histogram of labels a, b [n];
 // a label out of range sets kStatusLabel and is not counted.
