@@ -212,13 +212,13 @@ Lists make_lists(const Grid& G, const int32_t* active, int ucap, int n, int num_
         if (!active || active[k]) l.alist.push_back(k);
     l.agrp.push_back(0);
     int acc = 0;
-    // groups of about 256 padded centres; the assignment kernel keeps a
-    // group's candidates one per lane, so a group never exceeds 64 of them
+    // groups of about 256 padded centres, at most kAssignMaxGroup
+    // candidates (the assignment keeps a label row per candidate in LDS)
     int in_group = 0;
     for (size_t t = 0; t < l.alist.size(); ++t) {
         acc += (G.ks[l.alist[t]] + 15) / 16 * 16;
         ++in_group;
-        if ((acc >= 256 || in_group == 64) && t + 1 < l.alist.size()) {
+        if ((acc >= 256 || in_group == kAssignMaxGroup) && t + 1 < l.alist.size()) {
             in_group = 0;
             l.agrp.push_back((int32_t)t + 1);
             acc = 0;

@@ -217,6 +217,12 @@ enum KmeansKind {
     kKmReset, kKmZmax, kKmSplit, kKmRace, kKmRaceFinal, kKmInit, kKmAssign, kKmFinalize,
     kKmUpdate, kKmUpdateFinish, kKmKinds
 };
+// Candidates of one assignment group at most (each has at least 16 padded
+// centre rows and a group closes at 256 rows, so groups stay below this).
+constexpr int kAssignMaxGroup = 16;
+// Waves per work-group of the split-fp16 assignment at d <= 64 (measured at
+// N = 50k, d = 64: 2 waves 70.4 us, 4 waves 48.8 us, 8 waves 53.4 us).
+constexpr int kAssignWavesSmallD = 4;
 int kmeans_blocks(const KmeansPlan& p, int kind, int num_cu);
 void launch_kmeans_batched(int kind, const KmeansPlan* plans, int d, bool split, const float* Z,
                            int it, int t_max, size_t lds_max, size_t update_lds,

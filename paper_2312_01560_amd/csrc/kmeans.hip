@@ -535,15 +535,25 @@ __device__ __forceinline__ half8 neg_half8(half8 v) {
 // candidate group, so the 256 threads load each 16-centre tile (hi and lo
 // halves, norms) once, one tile ahead of the MFMAs, into a double buffer;
 // one barrier per tile.  Rows are padded by 8 halves against bank conflicts.
-template <int D, int PS>
+// The new labels of every candidate wait in LDS and leave after the walk,
+// together with the previous labels, the move marks and the change flags, in
+// coalesced passes; the walk itself holds no label state in registers, which
+// leaves the kernel at d = 64 within 128 registers, four waves per SIMD
+// (48.8 us per launch at N = 50k against 53.4 us with three).  A work-group
+// has AW waves (AW x 16 PS points); more waves share each staged tile (fewer
+// centre loads) but wait at more crowded barriers.
+template <int D, int PS, int AW>
 __device__ __forceinline__ void assign_h_body(const KmeansPlan& p, Wg w, int it) {
     constexpr int NC = D / 32;
     constexpr int RS = D + 8;                 // LDS row stride (halves)
     constexpr int CPR = D / 8;                // 16-byte chunks per row and half
     constexpr int CHUNKS = 16 * CPR * 2;      // chunks per tile (hi and lo)
+    constexpr int NT = AW * kWave;            // threads
     __shared__ _Float16 hs[2][16][RS], ls[2][16][RS];
     __shared__ float cs[2][16];
-    __shared__ float fold_all[4][2 * PS * kWave];
+    __shared__ float fold_all[AW][2 * PS * kWave];
+    constexpr int WP = AW * 16 * PS;          // points of the work-group
+    __shared__ uint8_t labs[kAssignMaxGroup][WP];   // new labels per group position
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wid = tid / kWave;
@@ -551,8 +561,8 @@ __device__ __forceinline__ void assign_h_body(const KmeansPlan& p, Wg w, int it)
     const int li = lane & 15;
     // every wave takes part in the barriers; rows beyond n are clamped, and
     // a work-group wholly past n (tile padding) leaves before any barrier
-    if (p.group_major && assign_tile(p, w) * 4 * 16 * PS >= p.n) return;
-    const int pbase = (assign_tile(p, w) * 4 + wid) * 16 * PS;
+    if (p.group_major && assign_tile(p, w) * WP >= p.n) return;
+    const int pbase = (assign_tile(p, w) * AW + wid) * 16 * PS;
     half8 bh[PS][NC], bl[PS][NC];
 #pragma unroll
     for (int ps = 0; ps < PS; ++ps) {
@@ -569,7 +579,7 @@ __device__ __forceinline__ void assign_h_body(const KmeansPlan& p, Wg w, int it)
     // the group's candidates, one per lane (the same in every wave)
     const int grp = assign_group(p, w);
     const int t0 = p.agrp[grp], t1 = p.agrp[grp + 1];
-    const int nc = min(t1 - t0, kWave);
+    const int nc = min(t1 - t0, kAssignMaxGroup);
     int my_k = 0, my_tiles = 0, my_off = 0;
     bool my_act = false;
     if (lane < nc) {
@@ -591,14 +601,14 @@ __device__ __forceinline__ void assign_h_body(const KmeansPlan& p, Wg w, int it)
     // tile loader: global -> registers (issued early), registers -> LDS.
     // Written as macros so the staging registers are only ever indexed by
     // unrolled constants (a lambda capturing them put them on the stack).
-    constexpr int SQ = (CHUNKS + 255) / 256;
+    constexpr int SQ = (CHUNKS + NT - 1) / NT;
     uint4 stage[SQ];
     float cstage = 0.f;
 #define ASSIGN_ISSUE(KOFF, TILE)                                                            \
     {                                                                                      \
         const int base_ = (KOFF) + (TILE) * 16;                                            \
         _Pragma("unroll") for (int q = 0; q < SQ; ++q) {                                   \
-            const int c = tid + 256 * q;                                                   \
+            const int c = tid + NT * q;                                                    \
             if (c < CHUNKS) {                                                              \
                 const int which = c / (16 * CPR), rem = c - which * (16 * CPR);            \
                 const int r = rem / CPR, c8 = rem - r * CPR;                               \
@@ -611,7 +621,7 @@ __device__ __forceinline__ void assign_h_body(const KmeansPlan& p, Wg w, int it)
 #define ASSIGN_COMMIT(BUF)                                                                 \
     {                                                                                      \
         _Pragma("unroll") for (int q = 0; q < SQ; ++q) {                                   \
-            const int c = tid + 256 * q;                                                   \
+            const int c = tid + NT * q;                                                    \
             if (c < CHUNKS) {                                                              \
                 const int which = c / (16 * CPR), rem = c - which * (16 * CPR);            \
                 const int r = rem / CPR, c8 = rem - r * CPR;                               \
@@ -630,10 +640,7 @@ __device__ __forceinline__ void assign_h_body(const KmeansPlan& p, Wg w, int it)
     ASSIGN_ISSUE(koff, 0)
     ASSIGN_COMMIT(0)
     __syncthreads();
-    const int ptl = pbase + 16 * g + li;
-    const bool wl = g < PS && ptl < p.n;
-    uint8_t old_lab = wl ? p.lab_cm[(size_t)k * p.n + ptl] : 0;
-    uint8_t next_old = 0;
+    const int ptw = wid * 16 * PS + 16 * g + li;   // lane's point within the work-group
     float bv[PS];
     int bi[PS];
 #pragma unroll
@@ -653,7 +660,6 @@ __device__ __forceinline__ void assign_h_body(const KmeansPlan& p, Wg w, int it)
                 nk = __builtin_amdgcn_readlane(my_k, nt);
                 nntiles = __builtin_amdgcn_readlane(my_tiles, nt);
                 nkoff = __builtin_amdgcn_readlane(my_off, nt);
-                next_old = wl ? p.lab_cm[(size_t)nk * p.n + ptl] : 0;
             }
         }
         const bool more = nt < nc;
@@ -693,45 +699,68 @@ __device__ __forceinline__ void assign_h_body(const KmeansPlan& p, Wg w, int it)
         }
         if (tile == ntiles - 1) {
             const int mine = fold_lane_groups<PS>(bv, bi, fold_all[wid], lane);
-            bool changed = false;
-            if (wl) {
-                const uint8_t nw = (uint8_t)mine;
-                changed = old_lab != nw;
-                p.lab_cm[(size_t)k * p.n + ptl] = nw;
-                p.lab_old[(size_t)k * p.n + ptl] = old_lab;
-                if (changed) p.moved_it[(size_t)(ptl >> 6) * p.Kc + k] = it;
-            }
-            const uint64_t m = __ballot(changed);
-            if (lane == 0 && m) p.changes[k] = 1;   // only zero / non-zero is read
+            if (g < PS) labs[t][ptw] = (uint8_t)mine;
         }
         if (!more) break;                     // uniform across the work-group
         ASSIGN_COMMIT(buf ^ 1)
         __syncthreads();
         buf ^= 1;
-        if (nt != t) old_lab = next_old;
         k = nk;
         tile = ntile;
         t = nt;
         ntiles = nntiles;
         koff = nkoff;
     }
+    // the labels: thread = point (64 consecutive points per wave, one move
+    // mark chunk), candidate after candidate
+    __syncthreads();
+    const int wbase = assign_tile(p, w) * WP;
+    for (uint64_t rest = amask; rest != 0; rest &= rest - 1) {
+        const int tt = __builtin_ctzll(rest);
+        const int kk = __builtin_amdgcn_readlane(my_k, tt);
+#pragma unroll
+        for (int q = 0; q < (WP + NT - 1) / NT; ++q) {
+            const int lp = tid + NT * q;
+            const int pt = wbase + lp;
+            bool changed = false;
+            if (lp < WP && pt < p.n) {
+                const uint8_t nw = labs[tt][lp];
+                const uint8_t ol = p.lab_cm[(size_t)kk * p.n + pt];
+                changed = ol != nw;
+                p.lab_cm[(size_t)kk * p.n + pt] = nw;
+                p.lab_old[(size_t)kk * p.n + pt] = ol;
+            }
+            const uint64_t m = __ballot(changed);
+            if (lane == 0 && m) {
+                p.moved_it[(size_t)(pt >> 6) * p.Kc + kk] = it;
+                p.changes[kk] = 1;            // only zero / non-zero is read
+            }
+        }
+    }
 }
 
 #undef ASSIGN_ISSUE
 #undef ASSIGN_COMMIT
 
-template <int D, int PS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3))) void k_assign_h(KmeansPlan p) {
-    assign_h_body<D, PS>(p, wg_self(), p.it);
+// Waves per SIMD the split-fp16 assignment is compiled for: four at
+// d <= 64 (its registers fit 128 per lane), three above.
+template <int D>
+constexpr int assign_wpe() {
+    return D <= 64 ? 4 : 3;
 }
 
-template <int D, int PS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3))) void k_assign_h_b(
+template <int D, int PS, int AW>
+__global__ __launch_bounds__(AW * 64) __attribute__((amdgpu_waves_per_eu(1, assign_wpe<D>()))) void k_assign_h(KmeansPlan p) {
+    assign_h_body<D, PS, AW>(p, wg_self(), p.it);
+}
+
+template <int D, int PS, int AW>
+__global__ __launch_bounds__(AW * 64) __attribute__((amdgpu_waves_per_eu(1, assign_wpe<D>()))) void k_assign_h_b(
     const KmeansPlan* __restrict__ plans, int it, BatchTable tb) {
     int gi;
     Wg w;
     if (!batch_find(tb, gi, w)) return;
-    assign_h_body<D, PS>(plans[gi], w, it);
+    assign_h_body<D, PS, AW>(plans[gi], w, it);
 }
 
 // After an assignment: a candidate whose labels did not change (from the
@@ -1281,6 +1310,12 @@ int kmeans_update_rows(int K) { return K; }
 
 int kmeans_update_max_candidates() { return kUpdMaxCand; }
 
+// Waves per work-group of the assignment: the split-fp16 kernel at d <= 64
+// runs kAssignWavesSmallD, every other form four.
+static int assign_waves(const KmeansPlan& p) {
+    return (p.split && p.d % 32 == 0 && p.d <= 64) ? kAssignWavesSmallD : 4;
+}
+
 int kmeans_blocks(const KmeansPlan& p, int kind, int num_cu) {
     const int64_t nd = (int64_t)p.n * p.d;
     switch (kind) {
@@ -1297,7 +1332,7 @@ int kmeans_blocks(const KmeansPlan& p, int kind, int num_cu) {
         case kKmInit: return (p.KP * kWave + 255) / 256;
         case kKmAssign: {
             const int ps = p.d <= 64 ? 4 : (p.d == 128 ? 3 : 1);
-            const int pts_per_block = 4 * 16 * ps;
+            const int pts_per_block = assign_waves(p) * 16 * ps;
             int tiles = (p.n + pts_per_block - 1) / pts_per_block;
             if (p.group_major) tiles = (tiles + 7) / 8 * 8;
             return tiles * p.agroups;
@@ -1348,6 +1383,11 @@ static constexpr int assign_ps() {
     return D <= 64 ? 4 : (D == 128 ? 3 : 1);
 }
 
+template <int D>
+static constexpr int assign_aw() {
+    return D <= 64 ? kAssignWavesSmallD : 4;
+}
+
 // The point tile of a work-group is 64 PS points (256 at d <= 64, 192 at
 // d = 128).  Smaller tiles split a launch into more work-groups but re-read
 // the centre tiles more often; measured on gfx950 at N = 50k, 64-point tiles
@@ -1358,16 +1398,18 @@ void launch_assign(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t 
 #define ASSIGN(DV)                                                                        \
     {                                                                                     \
         constexpr int PS = assign_ps<DV>();                                               \
+        constexpr int AW = assign_aw<DV>();                                               \
+        if constexpr (DV % 32 == 0) {                                                     \
+            if (p.split) {                                                                \
+                const dim3 grid((unsigned)kmeans_blocks(p, kKmAssign, num_cu));           \
+                hipLaunchKernelGGL((k_assign_h<DV, PS, AW>), grid, dim3(AW * 64), 0, st, p); \
+                break;                                                                    \
+            }                                                                             \
+        }                                                                                 \
         const int pts_per_block = 4 * 16 * PS;                                            \
         int tiles_ = (p.n + pts_per_block - 1) / pts_per_block;                           \
         if (p.group_major) tiles_ = (tiles_ + 7) / 8 * 8;                                 \
         dim3 grid((unsigned)(tiles_ * p.agroups));                                        \
-        if constexpr (DV % 32 == 0) {                                                     \
-            if (p.split) {                                                                \
-                hipLaunchKernelGGL((k_assign_h<DV, PS>), grid, dim3(256), 0, st, p);      \
-                break;                                                                    \
-            }                                                                             \
-        }                                                                                 \
         hipLaunchKernelGGL((k_assign<DV, PS>), grid, dim3(256), 0, st, p, Z);             \
     }
     RAFT_D_SWITCH(p.d, ASSIGN)
@@ -1405,9 +1447,11 @@ void launch_kmeans_batched(int kind, const KmeansPlan* plans, int d, bool split,
 #define ASSIGN(DV)                                                                         \
     {                                                                                      \
         constexpr int PS = assign_ps<DV>();                                                \
+        constexpr int AW = assign_aw<DV>();                                                \
         if constexpr (DV % 32 == 0) {                                                      \
             if (split) {                                                                   \
-                hipLaunchKernelGGL((k_assign_h_b<DV, PS>), dim3(grid), blk, 0, st, plans, it, t); \
+                hipLaunchKernelGGL((k_assign_h_b<DV, PS, AW>), dim3(grid), dim3(AW * 64), 0, st, \
+                                   plans, it, t);                                          \
                 break;                                                                     \
             }                                                                              \
         }                                                                                  \
