@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--train-steps", type=int, default=200)
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-vs-sequential leg")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the sampler (Alg. 2) and streaming (Sec. III-D) records")
     ap.add_argument("--batch-graphs", type=int, default=64)
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -244,6 +246,126 @@ def bench_train(args, api, torch, np):
     ctx.close()
 
 
+def bench_sampler(api, torch, np, ctx):
+    """Alg. 2 on the device: DC-SBM models of 50k nodes / 44 blocks (the
+    n50k recipe) and 1M nodes / 100 blocks (the n1m recipe), sampled into a
+    validated graph; best of three calls, host preparation included."""
+    from synth.dcsbm import dcsbm_model
+    out = {}
+    for name, n, k, dmax, gamma in (("n50k", 50000, 44, 300.0, 2.5),
+                                    ("n1m", 1000000, 100, 1000.0, 2.3)):
+        theta, blocks, omega = dcsbm_model(n, k, gamma=gamma, d_max=dmax, rho=2.0, seed=7)
+        api.sbm_sample(ctx, theta, blocks, omega, 0).close()
+        best, edges = 1e9, 0
+        for rep in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g = api.sbm_sample(ctx, theta, blocks, omega, rep + 1)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+            edges = g.nnz // 2
+            g.close()
+        out[name] = {"n": n, "blocks": k, "edges": int(edges), "ms": round(best * 1e3, 3),
+                     "edges_per_s": edges / best}
+    return out
+
+
+def bench_stream(api, torch, np, ctx, graph, method):
+    """Streaming update (Sec. III-D) on the n50k graph, NCut: 64 random new
+    edges added to a stream against a full projection + GCN of the new
+    graph; and the same for a shallow configuration (q = 1, one layer),
+    whose hop balls stay small."""
+    out = {}
+    rng = np.random.default_rng(11)
+    n = graph.n
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(graph.row_ptr))
+    have = set((rows * n + graph.col_idx.astype(np.int64)).tolist())
+    for name, upd in (("q3_gcn2", {}), ("q1_gcn1", {"q": 1, "layer_dims": method["layer_dims"][:1]})):
+        m = dict(method)
+        m.update(upd)
+        cfg = api.Config(op=api.X_NCUT, seed=0, **m)
+        g = api.Graph(ctx, graph.row_ptr, graph.col_idx)
+        ws = ctx.workspace(api.workspace_size(ctx, g, cfg))
+        for _ in range(2):
+            api.embed(ctx, g, cfg, api.project(ctx, g, cfg, ws=ws), ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            api.embed(ctx, g, cfg, api.project(ctx, g, cfg, ws=ws), ws=ws)
+        torch.cuda.synchronize()
+        full = (time.perf_counter() - t0) / 5
+        st = api.Stream(ctx, g, cfg)
+        times, balls = [], None
+        for rep in range(4):
+            e = set()
+            while len(e) < 64:
+                a, b = (int(v) for v in rng.integers(0, n, 2))
+                a, b = min(a, b), max(a, b)
+                if a != b and a * n + b not in have and (a, b) not in e:
+                    e.add((a, b))
+            for a, b in e:
+                have.add(a * n + b)
+                have.add(b * n + a)
+            src = np.array([a for a, _ in e]), np.array([b for _, b in e])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            balls = st.add_edges(*src)
+            torch.cuda.synchronize()
+            if rep > 0:
+                times.append(time.perf_counter() - t0)
+        st.close()
+        g.close()
+        out[name] = {"new_edges": 64, "update_ms": round(1e3 * min(times), 3),
+                     "full_reembed_ms": round(1e3 * full, 3),
+                     "rows_per_level": [int(x) for x in balls]}
+    # a 1M-node graph sampled on the device (the n1m model), L = 128, q = 1,
+    # one 128-wide layer; 1 and 16 new edges
+    from synth.dcsbm import dcsbm_model
+    theta, blocks, omega = dcsbm_model(1000000, 100, gamma=2.3, d_max=1000.0, rho=2.0, seed=7)
+    g = api.sbm_sample(ctx, theta, blocks, omega, 1)
+    cfg = api.Config(op=api.X_NCUT, proj_dim=128, q=1, layer_dims=[128], k_min=50, k_max=150,
+                     k_step=5, seed=0)
+    ws = ctx.workspace(api.workspace_size(ctx, g, cfg))
+    api.embed(ctx, g, cfg, api.project(ctx, g, cfg, ws=ws), ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        api.embed(ctx, g, cfg, api.project(ctx, g, cfg, ws=ws), ws=ws)
+    torch.cuda.synchronize()
+    full = (time.perf_counter() - t0) / 3
+    del ws
+    st = api.Stream(ctx, g, cfg)
+    grp, gci = (t.cpu().numpy() for t in g.csr())
+    g.close()
+    n = 1000000
+    added = set()
+
+    def present(a, b):
+        row = gci[grp[a]:grp[a + 1]]
+        k = int(np.searchsorted(row, b))
+        return (k < row.size and row[k] == b) or (a, b) in added
+
+    res = {}
+    for m in (1, 1, 16, 16):
+        e = set()
+        while len(e) < m:
+            a, b = (int(v) for v in rng.integers(0, n, 2))
+            a, b = min(a, b), max(a, b)
+            if a != b and not present(a, b) and (a, b) not in e:
+                e.add((a, b))
+        added |= e
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        balls = st.add_edges(np.array([a for a, _ in e]), np.array([b for _, b in e]))
+        torch.cuda.synchronize()
+        res[m] = (time.perf_counter() - t0, [int(x) for x in balls])   # second of each size kept
+    st.close()
+    out["n1m_q1_gcn1"] = {"full_reembed_ms": round(1e3 * full, 3),
+                          "updates": {str(m): {"update_ms": round(1e3 * t, 3), "rows_per_level": b}
+                                      for m, (t, b) in res.items()}}
+    return out
+
+
 def bench_batch(args, api, torch, np, ctx):
     """The batched workload: 64 DC-SBM graphs (N log-uniform on [1e3, 5e4])
     through the whole path (modularity variant, K 2..64) as one batch -- one
@@ -422,6 +544,10 @@ def main():
                 "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": spmm_ach / PEAK_HBM,
                 "per_launch": {"bytes": spmm_bytes_per_launch, "avg_ms": ms_spmm / max(n_spmm, 1)}}
     roof["traffic"] = measured_traffic(dominant, args.workload)
+    roof["traffic_note"] = ("bytes per launch beyond L2 from two rocprofv3 counter passes "
+                            "(FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, scaled by a plain copy): "
+                            "Infinity Cache hits included, so an upper bound on HBM bytes; "
+                            "null once the kernel source differs from the profiled one")
 
     planted = torch.from_numpy(graph.planted.astype(np.int32)).to(dev)
     nmi_planted = {v: api.nmi(ctx, outs[v][0]["labels"], planted) for v in variants}
@@ -461,6 +587,10 @@ def main():
     if not args.no_batch and args.workload == "n50k":
         log("batched workload (batched vs one graph at a time)")
         rec["batch"] = bench_batch(args, api, torch, np, ctx)
+    if not args.no_extras and args.workload == "n50k":
+        log("sampler (Alg. 2) and streaming update (Sec. III-D) records")
+        rec["sampler"] = bench_sampler(api, torch, np, ctx)
+        rec["stream"] = bench_stream(api, torch, np, ctx, graph, method)
     if args.copy_calib_mib:
         a = torch.empty(args.copy_calib_mib << 18, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
