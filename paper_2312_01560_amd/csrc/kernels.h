@@ -197,7 +197,9 @@ void launch_zmax(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t st
 // pick also resolves it).
 void launch_race_pick(const KmeansPlan& p, const float* Z, int t, hipStream_t st);
 void launch_init_centres(const KmeansPlan& p, const float* Z, hipStream_t st);
-void launch_assign(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t st);
+// e0 / e1 (nullable): events the launch records itself at its start and end.
+void launch_assign(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t st,
+                   hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // Split-fp16 assignment is available for d multiple of 32.
 bool kmeans_split_supported(int d);
 // zh/zl from Z (after launch_zmax).

@@ -23,6 +23,8 @@
 #include <algorithm>
 #include <mutex>
 
+#include <hip/hip_ext.h>
+
 #include "kernels.h"
 
 namespace raft {
@@ -1393,7 +1395,8 @@ static constexpr int assign_aw() {
 // the centre tiles more often; measured on gfx950 at N = 50k, 64-point tiles
 // ran the assignment 1.7x slower than 256-point tiles, and at N = 1M
 // (d = 128) 48 points per wave ran 12 % faster than 32.
-void launch_assign(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t st) {
+void launch_assign(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t st, hipEvent_t e0,
+                   hipEvent_t e1) {
     (void)num_cu;
 #define ASSIGN(DV)                                                                        \
     {                                                                                     \
@@ -1402,7 +1405,11 @@ void launch_assign(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t 
         if constexpr (DV % 32 == 0) {                                                     \
             if (p.split) {                                                                \
                 const dim3 grid((unsigned)kmeans_blocks(p, kKmAssign, num_cu));           \
-                hipLaunchKernelGGL((k_assign_h<DV, PS, AW>), grid, dim3(AW * 64), 0, st, p); \
+                if (e0)                                                                   \
+                    hipExtLaunchKernelGGL((k_assign_h<DV, PS, AW>), grid, dim3(AW * 64), 0, st, \
+                                          e0, e1, 0, p);                                  \
+                else                                                                      \
+                    hipLaunchKernelGGL((k_assign_h<DV, PS, AW>), grid, dim3(AW * 64), 0, st, p); \
                 break;                                                                    \
             }                                                                             \
         }                                                                                 \
@@ -1410,7 +1417,10 @@ void launch_assign(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t 
         int tiles_ = (p.n + pts_per_block - 1) / pts_per_block;                           \
         if (p.group_major) tiles_ = (tiles_ + 7) / 8 * 8;                                 \
         dim3 grid((unsigned)(tiles_ * p.agroups));                                        \
-        hipLaunchKernelGGL((k_assign<DV, PS>), grid, dim3(256), 0, st, p, Z);             \
+        if (e0)                                                                           \
+            hipExtLaunchKernelGGL((k_assign<DV, PS>), grid, dim3(256), 0, st, e0, e1, 0, p, Z); \
+        else                                                                              \
+            hipLaunchKernelGGL((k_assign<DV, PS>), grid, dim3(256), 0, st, p, Z);         \
     }
     RAFT_D_SWITCH(p.d, ASSIGN)
 #undef ASSIGN
