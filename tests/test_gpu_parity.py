@@ -389,7 +389,9 @@ def test_kmeans_large_point_set(ctx, api_mod):
     assignment's other block order (all candidate groups of a point tile on
     one XCD, tile count padded to a multiple of 8): the first picks equal the
     oracle's, every point of every converged candidate sits at its nearest
-    centre, and the centres are the means of their points."""
+    centre, and the centres are the means of their points.  The grid
+    (K = 2..62 step 4, 640 padded centre rows) forms several candidate
+    groups, so the interleave of groups and point tiles is exercised."""
     n, d = 140001, 128
     rp = (2 * np.arange(n + 1)).astype(np.int32)                      # a ring
     nb = np.stack([(np.arange(n) - 1) % n, (np.arange(n) + 1) % n], axis=1)
@@ -403,8 +405,10 @@ def test_kmeans_large_point_set(ctx, api_mod):
     z = (z / np.linalg.norm(z, axis=1, keepdims=True)).astype(np.float32)
     z64 = z.astype(np.float64)
     g = api_mod.Graph(ctx, rp, ci)
-    cfg = api_mod.Config(op=0, proj_dim=d, layer_dims=[d], k_min=2, k_max=20, k_step=3,
+    cfg = api_mod.Config(op=0, proj_dim=d, layer_dims=[d], k_min=2, k_max=62, k_step=4,
                          kmeans_max_iter=300)
+    kp = sum((k + 15) // 16 * 16 for k in cfg.ks)
+    assert kp > 2 * 256                     # three or more assignment groups
     out = api_mod.partition(ctx, g, cfg, torch.from_numpy(z).cuda(), want_centres=True)
     torch.cuda.synchronize()
     ctx.sync_status()
