@@ -145,3 +145,15 @@ def test_argument_errors(api_mod, ctx):
     nan[1, 1] = np.nan
     with pytest.raises(RuntimeError):
         api_mod.sbm_sample(ctx, theta, blocks, nan, 0)
+
+
+def test_degenerate_sizes(api_mod, ctx):
+    """One node; one block; every node its own block."""
+    rp, ci = assert_same(api_mod, ctx, np.array([1.0]), np.array([0]), np.array([[5.0]]), 3)
+    assert rp.tolist() == [0, 0] and ci.size == 0
+    n = 40
+    theta = np.linspace(0.5, 1.5, n)
+    assert_same(api_mod, ctx, theta, np.zeros(n, dtype=np.int32), np.array([[0.3]]), 8)
+    k = n
+    omega = np.full((k, k), 0.2)
+    assert_same(api_mod, ctx, theta, np.arange(n, dtype=np.int32), omega, 9)

@@ -198,3 +198,25 @@ def test_n50k_stream(api_mod, ctx):
     yf, zf = fresh(api_mod, ctx, rp, ci, cfg)
     assert np.array_equal(y, yf) and np.array_equal(z, zf)
     st.close()
+
+
+@pytest.mark.parametrize("layers,width", [([], 32), ([512, 256], 512)])
+def test_stream_without_layers_and_wide(api_mod, ctx, layers, width):
+    """No GCN layer (the "w/o Emb" form: Z = Y) and Table I widths (512 ->
+    512 -> 256): the stream still equals a fresh projection and embedding."""
+    g0 = dcsbm(2500, 6, seed=13, d_min=3.0, d_max=30.0)
+    n = g0.n
+    cfg = api_mod.Config(op=0, proj_dim=width, q=2, layer_dims=layers, k_min=2, k_max=8, seed=6)
+    g = api_mod.Graph(ctx, g0.row_ptr, g0.col_idx)
+    st = api_mod.Stream(ctx, g, cfg)
+    g.close()
+    rp, ci = g0.row_ptr.astype(np.int64), g0.col_idx.astype(np.int64)
+    for batch, m in enumerate([3, 40]):
+        s, d = new_edges(rp, ci, n, m, 90 + batch)
+        rows = st.add_edges(s, d)
+        assert rows.size == cfg.q + len(layers)
+        rp, ci = streaming.add_edges(rp, ci, n, s, d)
+        y, z = stream_state(st)
+        yf, zf = fresh(api_mod, ctx, rp, ci, cfg)
+        assert np.array_equal(y, yf) and np.array_equal(z, zf)
+    st.close()
