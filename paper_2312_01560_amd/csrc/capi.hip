@@ -1838,9 +1838,11 @@ void batch_layout(raft_batch* b, char* ws, raft_outputs* outs, BatchLayout& B, i
         cnt[bt_race][g] = kmeans_blocks(km, kKmRace, ctx->num_cu);
         cnt[bt_init][g] = kmeans_blocks(km, kKmInit, ctx->num_cu);
         // rows walked grid-stride (k_update_finish_b): two work-groups per
-        // CU of the graph's share of the chip
+        // CU of the graph's share of the chip, and at most 16 rows per
+        // work-group (every graph has the grid's full row count, however
+        // small its share)
         cnt[bt_ufinish][g] = std::min(kmeans_blocks(km, kKmUpdateFinish, ctx->num_cu),
-                                      2 * P.share);
+                                      std::max(2 * P.share, (km.KP + 1 + 15) / 16));
         cnt[bt_transpose][g] = score_blocks(sc, kScTranspose);
         cnt[bt_edge][g] = score_blocks(sc, kScEdge);
         cnt[bt_reduce][g] = score_blocks(sc, kScReduce);
