@@ -297,7 +297,10 @@ raft_status raft_partition(raft_ctx* ctx, const raft_graph* g, const raft_config
 
 /* Stage A7 alone: Mod (Eq. 3) and NCut (Eq. 1) of Kc labelings given as
  * point-major bytes labels_all[N x Kc]; ks[Kc] (host) are the block counts.
- * mod/ncut are device arrays [Kc]. */
+ * mod/ncut are device arrays [Kc].  At most 256 labelings with a sum of
+ * block counts of at most 16384 (RAFT_E_UNSUPPORTED beyond); a label not
+ * below its labeling's K is not counted and latches a status that
+ * raft_sync_status returns as RAFT_E_INVAL. */
 raft_status raft_score(raft_ctx* ctx, const raft_graph* g, const uint8_t* labels_all,
                        int32_t Kc, const int32_t* ks, double* mod, double* ncut,
                        void* ws, size_t ws_bytes, void* stream);

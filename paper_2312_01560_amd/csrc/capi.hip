@@ -52,6 +52,9 @@ struct raft_graph {
     float* sh = nullptr;
     float* dcoef = nullptr;
     int32_t* order = nullptr;   // rows by degree class, heaviest first (stable)
+    // heavy[b]: the rows with at least b 16-edge batches (b <= 16; the last
+    // class holds every longer row), which lead the order
+    int32_t heavy[17] = {};
     bool owns = true;           // false: the arrays belong to a stream
     GraphView view() const {
         GraphView v;
@@ -463,6 +466,7 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
     sc.S = P.S;
     sc.SK = G.SK;
     sc.grid = P.score_grid_;
+    sc.heavy = g->heavy[score_split_batches(P.S)];
     sc.nnz = g->nnz;
     sc.ks = km.ks;
     sc.koff = km.koff;
@@ -698,8 +702,9 @@ raft_status plan_for(raft_ctx* ctx, const raft_graph* g, const raft_config* c, v
     if (!kmeans_supported(d)) return fail(ctx, RAFT_E_UNSUPPORTED, "embedding width %d", d);
     if (kmeans_update_lds(P.ucap, d) > ctx->lds_max)
         return fail(ctx, RAFT_E_UNSUPPORTED, "k_max %d too large for width %d", P.grid.k_max, d);
-    if (!score_supported(P.grid.SK))
-        return fail(ctx, RAFT_E_UNSUPPORTED, "sum of candidate K %d > 16384", P.grid.SK);
+    if (!score_supported(P.grid.Kc, P.grid.SK))
+        return fail(ctx, RAFT_E_UNSUPPORTED, "%d candidates with sum of K %d (at most 256 and 16384)",
+                    P.grid.Kc, P.grid.SK);
     RAFT_TRY(check_ws(ctx, ws, ws_bytes, P.bytes));
     plan_layout(ctx, g, c, reinterpret_cast<char*>(ws), P);
     return RAFT_OK;
@@ -898,6 +903,10 @@ raft_status raft_graph_create(raft_ctx* ctx, const void* row_ptr, int row_ptr_is
         for (int64_t i = 0; i < n; ++i) ++start[cls(i) + 1];
         for (int c = 0; c < kClasses; ++c) start[c + 1] += start[c];
         for (int64_t i = 0; i < n; ++i) order[start[cls(i)]++] = (int32_t)i;
+        // after the fill start[c] is the end of class c: the rows with at
+        // least b batches are those of classes 0 .. 16 - b
+        g->heavy[0] = (int32_t)n;
+        for (int b = 1; b < kClasses; ++b) g->heavy[b] = (int32_t)start[kClasses - 1 - b];
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(g->order, order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st);
@@ -1173,7 +1182,9 @@ raft_status raft_score(raft_ctx* ctx, const raft_graph* g, const uint8_t* labels
         koff[k] = SK;
         SK += ks[k];
     }
-    if (!score_supported(SK)) return fail(ctx, RAFT_E_UNSUPPORTED, "sum of K %d", SK);
+    if (!score_supported(Kc, SK))
+        return fail(ctx, RAFT_E_UNSUPPORTED, "%d labelings with sum of K %d (at most 256 and 16384)",
+                    Kc, SK);
     const int S = (Kc + 7) / 8 * 8;
     const int grid = score_grid(g->n, ctx->num_cu);
     RAFT_TRY(check_ws(ctx, ws, ws_bytes, score_ws_bytes(ctx, g, Kc, SK)));
@@ -1189,6 +1200,7 @@ raft_status raft_score(raft_ctx* ctx, const raft_graph* g, const uint8_t* labels
     sc.S = S;
     sc.SK = SK;
     sc.grid = grid;
+    sc.heavy = g->heavy[score_split_batches(S)];
     sc.nnz = g->nnz;
     sc.ks = meta;
     sc.koff = meta + Kc;
@@ -1237,7 +1249,9 @@ raft_status raft_score_workspace_size(raft_ctx* ctx, const raft_graph* g, int32_
         if (ks[k] < 1 || ks[k] > RAFT_MAX_K) return fail(ctx, RAFT_E_INVAL, "ks[%d] = %d", k, ks[k]);
         SK += ks[k];
     }
-    if (!score_supported(SK)) return fail(ctx, RAFT_E_UNSUPPORTED, "sum of K %d", SK);
+    if (!score_supported(Kc, SK))
+        return fail(ctx, RAFT_E_UNSUPPORTED, "%d labelings with sum of K %d (at most 256 and 16384)",
+                    Kc, SK);
     *bytes = score_ws_bytes(ctx, g, Kc, SK);
     return RAFT_OK;
 }
@@ -2123,8 +2137,10 @@ raft_status raft_batch_create(raft_ctx* ctx, int32_t G, const raft_graph* const*
         plan_layout(ctx, graphs[0], cfg, nullptr, P);
         if (kmeans_update_lds(P.ucap, d) > ctx->lds_max)
             return fail(ctx, RAFT_E_UNSUPPORTED, "k_max %d too large for width %d", P.grid.k_max, d);
-        if (!score_supported(P.grid.SK))
-            return fail(ctx, RAFT_E_UNSUPPORTED, "sum of candidate K %d > 16384", P.grid.SK);
+        if (!score_supported(P.grid.Kc, P.grid.SK))
+            return fail(ctx, RAFT_E_UNSUPPORTED,
+                        "%d candidates with sum of K %d (at most 256 and 16384)", P.grid.Kc,
+                        P.grid.SK);
     }
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     raft_batch* b = new raft_batch();
@@ -2142,6 +2158,7 @@ raft_status raft_batch_create(raft_ctx* ctx, int32_t G, const raft_graph* const*
         b->shadow[g].ctx = ctx;
         b->shadow[g].n = graphs[g]->n;
         b->shadow[g].nnz = graphs[g]->nnz;
+        std::copy(graphs[g]->heavy, graphs[g]->heavy + 17, b->shadow[g].heavy);
         b->seeds[g] = seeds ? seeds[g] : cfg->seed;
         b->base[g] = (int32_t)r;
         b->ebase[g] = e;
@@ -3207,6 +3224,7 @@ raft_status raft_stream_create(raft_ctx* ctx, const raft_graph* g, const raft_co
         G.ctx = ctx;
         G.n = g->n;
         G.nnz = g->nnz;
+        std::copy(g->heavy, g->heavy + 17, G.heavy);
         G.owns = false;
         s->ci_cap[b] = std::max<int64_t>(g->nnz + g->nnz / 4, 1024);
         ok = ok && stream_alloc(s, &G.rp, n + 1) && stream_alloc(s, &G.ci, s->ci_cap[b]) &&
@@ -3350,6 +3368,7 @@ raft_status raft_stream_add_edges(raft_stream* s, const int32_t* src, const int3
                         s->totals, g2->rp, g2->ci, s->mstatus, st);
     HIP_TRY(ctx, hipMemcpyAsync(g2->order, g->order, sizeof(int32_t) * n, hipMemcpyDeviceToDevice,
                                 st));
+    std::copy(g->heavy, g->heavy + 17, g2->heavy);
     launch_degrees(g2->rp, n, nnz2, g2->deg, g2->s, g2->sh, g2->dcoef, st);
     const bool local = s->cfg.op == RAFT_X_NCUT;
     if (local)

@@ -235,6 +235,7 @@ struct ScorePlan {
     int32_t n, Kc, S;     // S = row stride of point-major labels (multiple of 8)
     int32_t SK;           // sum of K
     int32_t grid;
+    int32_t heavy = 0;    // leading rows of the row order whose edges a wave splits
     int64_t nnz;
     const int32_t* ks;
     const int32_t* koff;
@@ -257,7 +258,10 @@ struct ScorePlan {
 };
 
 int score_grid(int32_t n, int num_cu);
-bool score_supported(int SK);
+bool score_supported(int Kc, int SK);   // Kc <= 256 labelings, sum of K <= 16384
+// Rows with at least this many 16-edge batches are split over the row groups
+// of a wave by the edge-score kernel (for label row stride S).
+int score_split_batches(int S);
 void launch_transpose_labels(const uint8_t* cm, int32_t n, int Kc, uint8_t* pm, int S,
                              hipStream_t st);
 void launch_edge_score(const GraphView& g, const ScorePlan& p, const uint8_t* lab_pm,

@@ -15,6 +15,11 @@
 // (broadcast loads) and gather the neighbours' label words back to back,
 // comparing bytes with an exact per-byte zero mask.  Counts are accumulated per work-group in LDS and
 // written as partials; all counts are integers, so their sums are exact.
+// The heaviest rows (the first `heavy` rows of the degree order) are taken
+// one per pass, their edges split over the wave's row groups, so that a
+// long row does not leave one row group walking its edges alone at the end
+// of the launch; each group adds its share of the count, and the first adds
+// the row's degree.
 #include <limits.h>
 
 #include <algorithm>
@@ -79,14 +84,25 @@ __device__ __forceinline__ void edge_score_body(const GraphView& g, const ScoreP
     // similar length side by side, the longest first), dealt to the waves
     // round robin so every wave gets its share of long and short rows
     const int nwaves = (int)w.n * (blockDim.x / kWave);
-    const int npass = (g.n + G - 1) / G;
+    const int H = p.heavy;
+    const int npass = H + (g.n - H + G - 1) / G;
     lab -= (size_t)g.base * p.S;
     for (int pp = (int)w.x * (blockDim.x / kWave) + wid; pp < npass; pp += nwaves) {
-        const int pos = pp * G + slot;
+        // pass pp < H: row order[pp], row group `slot` takes the slot-th of
+        // G equal runs of its edges; else G rows side by side
+        const bool split = pp < H;
+        const int pos = split ? pp : H + (pp - H) * G + slot;
         const bool valid = pos < g.n;
         const int i = valid ? g.order[pos] : 0;
-        const int beg = g.rp[i];
-        const int end = valid ? g.rp[i + 1] : beg;
+        const int rbeg = g.rp[i];
+        const int rend = valid ? g.rp[i + 1] : rbeg;
+        int beg = rbeg, end = rend;
+        if (split) {
+            const int run = (rend - rbeg + G - 1) / G;
+            beg = min(rend, rbeg + slot * run);
+            end = min(rend, beg + run);
+        }
+        const bool first = !split || slot == 0;   // adds the row's degree
         int maxdeg = end - beg;
 #pragma unroll
         for (int off = LPR; off < kWave; off <<= 1)
@@ -124,7 +140,7 @@ __device__ __forceinline__ void edge_score_body(const GraphView& g, const ScoreP
             }
         }
         if (valid && on) {
-            const int d = end - beg;
+            const int d = first ? rend - rbeg : 0;
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
                 const int k = 8 * m + b;
@@ -375,12 +391,18 @@ static int score_lpr(int S) {
     return lpr;
 }
 
+int score_split_batches(int S) { return std::min(16, kWave / score_lpr(S)); }
+
 int score_grid(int32_t n, int num_cu) {
     const int64_t want = ((int64_t)n + 63) / 64;
     return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)num_cu * 4));
 }
 
-bool score_supported(int SK) { return SK >= 1 && SK <= 16384; }
+// a label row of Kc bytes is covered by at most 32 lanes of 8 bytes; the
+// per-work-group counts (2 x SK ints) live in LDS
+bool score_supported(int Kc, int SK) {
+    return Kc >= 1 && Kc <= 8 * 32 && SK >= 1 && SK <= 16384;
+}
 
 void launch_transpose_labels(const uint8_t* cm, int32_t n, int Kc, uint8_t* pm, int S,
                              hipStream_t st) {

@@ -241,6 +241,40 @@ def test_scores_bit_exact(ctx, api_mod, ragged):
     assert np.array_equal(to_np(nc), rnc)
 
 
+@pytest.mark.parametrize("kc", [3, 9, 20, 40, 79, 200])
+def test_scores_split_rows(ctx, api_mod, kc):
+    """Hub rows (degrees from 17 to ~2,900) next to light ones, for every
+    label row width (rows side by side per wave from 64 down to 2): the rows
+    the edge-score kernel splits over a wave give the oracle's scores bit
+    for bit."""
+    rng = np.random.default_rng(kc)
+    n = 3001
+    src = rng.integers(0, n, 6 * n)
+    dst = rng.integers(0, n, 6 * n)
+    hubs = rng.choice(n, 12, replace=False)
+    for h, frac in zip(hubs, np.linspace(0.006, 0.97, hubs.size)):
+        nb = rng.choice(n, int(frac * n), replace=False)
+        src = np.concatenate([src, np.full(nb.size, h)])
+        dst = np.concatenate([dst, nb])
+    rp, ci = edges_to_csr(n, src, dst)
+    deg = np.diff(rp)
+    assert deg.max() > 2500 and np.sum(deg > 240) >= 8
+    g = api_mod.Graph(ctx, rp, ci)
+    ks = [int(2 + (7 * j) % 63) for j in range(kc)]
+    lab = np.stack([rng.integers(0, k, n) for k in ks], axis=1)
+    mod, nc = api_mod.score(ctx, g, torch.from_numpy(lab.astype(np.uint8)).cuda(), ks)
+    rmod, rnc = scores.score_candidates(rp, ci, lab, ks)
+    assert np.array_equal(to_np(mod), rmod)
+    assert np.array_equal(to_np(nc), rnc)
+
+
+def test_scores_too_many_labelings(ctx, api_mod, ragged):
+    g = api_mod.Graph(ctx, ragged.row_ptr, ragged.col_idx)
+    lab = torch.zeros((ragged.n, 257), dtype=torch.uint8, device="cuda")
+    with pytest.raises(RuntimeError):
+        api_mod.score(ctx, g, lab, [2] * 257)
+
+
 def test_scores_closed_form(ctx, api_mod):
     for m, num, den in ((4, 11, 26), (5, 19, 42), (6, 29, 62)):
         g0 = two_cliques(m)
