@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define RAFT_ABI_VERSION 3
+#define RAFT_ABI_VERSION 4
 
 typedef int32_t raft_status;
 #define RAFT_OK             0
@@ -77,6 +77,13 @@ typedef struct {
     int32_t  k_min, k_max, k_step;     /* candidate grid, 1 <= k_min <= k_max <= min(N, 255) */
     int32_t  kmeans_max_iter;          /* T_max (assignments per candidate), >= 1     */
     int32_t  check_every;              /* host convergence poll period (0 = 4)        */
+    int32_t  kmeans_prune;             /* Lloyd assignments from the third on may skip
+                                        * the points whose distance bounds prove their
+                                        * label cannot change (single graphs, split-fp16
+                                        * path): 0 (default) where it pays, when the
+                                        * grid's mean K is at least 64; 1 whenever
+                                        * supported; 2 never.  Labels, centres and
+                                        * iteration counts are the same in every mode. */
     uint64_t seed;                     /* Philox key word 0 for Theta, W and the race */
 } raft_config;
 

@@ -6,7 +6,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libraftgp.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 MAX_LAYERS = 8
 MAX_K = 255
 
@@ -51,6 +51,7 @@ class RaftConfig(ctypes.Structure):
         ("k_step", ctypes.c_int32),
         ("kmeans_max_iter", ctypes.c_int32),
         ("check_every", ctypes.c_int32),
+        ("kmeans_prune", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
     ]
 

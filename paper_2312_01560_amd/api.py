@@ -40,6 +40,7 @@ class Config:
     k_step: int = 1
     kmeans_max_iter: int = 100
     check_every: int = 4
+    kmeans_prune: int = 0   # 0 where it pays (mean K >= 64), 1 always, 2 never
     seed: int = 0
 
     @property
@@ -63,6 +64,7 @@ class Config:
         c.k_min, c.k_max, c.k_step = self.k_min, self.k_max, self.k_step
         c.kmeans_max_iter = self.kmeans_max_iter
         c.check_every = self.check_every
+        c.kmeans_prune = int(self.kmeans_prune)
         c.seed = self.seed
         return c
 

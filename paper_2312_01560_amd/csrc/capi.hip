@@ -328,6 +328,8 @@ raft_status check_config(raft_ctx* ctx, const raft_graph* g, const raft_config* 
                     c->k_step);
     if (g && c->k_max > g->n) return fail(ctx, RAFT_E_INVAL, "k_max %d exceeds N", c->k_max);
     if (c->kmeans_max_iter < 1) return fail(ctx, RAFT_E_INVAL, "kmeans_max_iter < 1");
+    if (c->kmeans_prune < 0 || c->kmeans_prune > 2)
+        return fail(ctx, RAFT_E_INVAL, "kmeans_prune %d (0, 1 or 2)", c->kmeans_prune);
     return RAFT_OK;
 }
 
@@ -456,6 +458,35 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
     km.lab_old = a.take<uint8_t>((size_t)G.Kc * n);
     km.nchunks = (int)(((int64_t)n + 63) / 64);
     km.moved_it = a.take<int32_t>((size_t)km.nchunks * G.Kc);
+    // bound-pruned assignment: graphs on their own (a batch assigns every
+    // point), split-fp16 operands, bounded running sums, tables that fit in
+    // LDS.  Scoring a listed point gathers its row (4 d bytes) for one
+    // candidate, where the full assignment reads each point once per group
+    // of candidates; the saving is in the MFMA work, which grows with K: by
+    // default only grids with a mean K of 64 or more are pruned (measured:
+    // N = 1M, K = 50..150 step 5, d = 128: 217 -> 145..165 ms per run;
+    // N = 50k, K = 2..80, d = 64: 8.4..11.5 -> 8.6..12.2 ms).
+    const int nranges = (int)((n + kPruneRange - 1) / kPruneRange);
+    const bool prune_pays = c->kmeans_prune == 1 || (c->kmeans_prune == 0 && G.SK >= 64 * G.Kc);
+    km.prune = features && km.split && prune_pays && c->kmeans_max_iter <= 65536 &&
+                       list_lds_bytes(P.d, (G.k_max + 15) / 16, G.Kc * nranges) + 4096 <=
+                           ((size_t)160 << 10)
+                   ? 1
+                   : 0;
+    if (km.prune) {
+        km.hu = a.take<float>((size_t)G.Kc * n);
+        km.hl = a.take<float>((size_t)G.Kc * n);
+        km.cum = a.take<double>(G.KP);
+        km.cmx = a.take<double>(G.Kc);
+        km.dmx = a.take<double>((size_t)2 * G.Kc);
+        km.zn2 = a.take<float>(n);
+        km.pe = a.take<float>(n);
+        km.plist = a.take<int32_t>((size_t)G.Kc * n);
+        km.scnt = a.take<int32_t>((size_t)G.Kc * nranges);
+        km.nranges = nranges;
+        km.znmax_bits = a.take<uint32_t>(1);
+        km.list_tiles = (G.k_max + 15) / 16;
+    }
     km.status = ctx->d_status;
     km.seed = c->seed;
     km.zoff = 0;
@@ -619,6 +650,7 @@ raft_status do_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* 
     launch_kmeans_reset(km, st);
     launch_zmax(km, Z, ctx->num_cu, st);
     if (km.split) launch_split_points(km, Z, st);
+    if (km.prune) launch_prune_init(km, Z, st);
     for (int t = 0; t < km.k_max; ++t) {
         ProfScope ps(ctx, RAFT_PROF_RACE, st);
         launch_race_pick(km, Z, t, st);
@@ -641,11 +673,15 @@ raft_status do_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* 
     static_assert(16 + 2 * (RAFT_MAX_K + 1) + 2 * kDynLen(RAFT_MAX_K) <= 4096,
                   "poll slots exceed the pinned scratch");
     int poll = 0;
+    int nact = (int)P.lists.alist.size();   // candidates of alist (the kernels skip retired ones)
     for (int it = 1; it <= t_max; ++it) {
         km.it = it;
         {
             const ProfLaunch pl(ctx, RAFT_PROF_ASSIGN);
-            launch_assign(km, Z, ctx->num_cu, st, pl.e0, pl.e1);
+            if (km.prune && it >= kPruneFrom)
+                launch_assign_pruned(km, nact, ctx->num_cu, st, pl.e0, pl.e1);
+            else
+                launch_assign(km, Z, ctx->num_cu, st, pl.e0, pl.e1);
         }
         if (it == t_max) {
             launch_iter_finalize(km, it, t_max, st);
@@ -671,6 +707,7 @@ raft_status do_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* 
                 km.agroups = (int)l.agrp.size() - 1;
                 km.ugroups = (int)l.ugrp.size() - 1;
                 km.uwork = l.uwork;
+                nact = (int)l.alist.size();
             }
             HIP_TRY(ctx, hipMemcpyAsync(h_active[poll & 1], km.active, Kc * sizeof(int32_t),
                                         hipMemcpyDeviceToHost, st));

@@ -181,7 +181,35 @@ struct KmeansPlan {
     int32_t* status;
     uint64_t seed;           // Philox key word 0 of the race
     int32_t zoff = 0;        // in a batch: first row of the graph's points in the packed Z
+    // Bound-pruned assignment (single graphs, split-fp16; prune != 0): from
+    // iteration kPruneFrom on, k_prune_test lists the points whose distance
+    // bounds do not prove their label and k_prune_score scores them.  Bounds per (candidate,
+    // point), with Cum the summed drift of a
+    // centre and CumMax the summed largest drift of the candidate's centres:
+    //   hu = u - Cum_a   (u >= distance to the own centre a, rounded up)
+    //   hl = l + CumMax  (l <= distance to every other centre, rounded down)
+    // as of the point's last scoring; null and 0 when not pruning.
+    int32_t prune = 0;
+    float* hu = nullptr;        // [Kc x n]
+    float* hl = nullptr;        // [Kc x n]
+    double* cum = nullptr;      // [KP] summed drift of each centre row
+    double* cmx = nullptr;      // [Kc] summed largest drift, updates before the previous one
+    double* dmx = nullptr;      // [Kc x 2] largest drift of an update, slot = iteration & 1
+    float* zn2 = nullptr;       // [n] |z|^2, rounded up
+    float* pe = nullptr;        // [n] bound on the error of a computed score, rounded up
+    int32_t* plist = nullptr;   // [Kc x n] listed points, each range in its own slots
+    int32_t* scnt = nullptr;    // [Kc x nranges] listed points per range
+    int32_t nranges = 0;        // ceil(n / kPruneRange)
+    int32_t lists_nact = 0;     // alist positions k_prune_score's LDS holds (set per launch)
+    int32_t list_tiles = 0;     // centre tiles of the largest candidate (LDS of k_prune_score)
+    uint32_t* znmax_bits = nullptr;   // [1] largest |z| (float bits)
 };
+
+// Points per work-group of the pruned assignment (bound tests, then scoring).
+constexpr int kPruneRange = 2048;
+// First Lloyd iteration whose assignment is pruned (the first two move the
+// centres too far for the bounds to hold many points).
+constexpr int kPruneFrom = 3;
 
 bool kmeans_supported(int d);
 int kmeans_race_grid(int32_t n, int num_cu);
@@ -202,6 +230,14 @@ void launch_assign(const KmeansPlan& p, const float* Z, int num_cu, hipStream_t 
                    hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // Split-fp16 assignment is available for d multiple of 32.
 bool kmeans_split_supported(int d);
+// Pruned assignment: bounds and the fills they start from (once per
+// partition, after the points are split); then per iteration from
+// kPruneFrom on, one launch over the `nact` candidates of alist.  e0 / e1 as
+// for launch_assign.
+void launch_prune_init(const KmeansPlan& p, const float* Z, hipStream_t st);
+size_t list_lds_bytes(int d, int tiles, int lists);
+void launch_assign_pruned(const KmeansPlan& p, int nact, int num_cu, hipStream_t st,
+                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // zh/zl from Z (after launch_zmax).
 void launch_split_points(const KmeansPlan& p, const float* Z, hipStream_t st);
 void launch_iter_finalize(const KmeansPlan& p, int it, int t_max, hipStream_t st);

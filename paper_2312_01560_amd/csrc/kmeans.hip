@@ -765,6 +765,421 @@ __global__ __launch_bounds__(AW * 64) __attribute__((amdgpu_waves_per_eu(1, assi
     assign_h_body<D, PS, AW>(plans[gi], w, it);
 }
 
+// ---- bound-pruned assignment ------------------------------------------------
+// Lloyd's assignment keeps a point's label for a candidate whenever the
+// label provably cannot change (Hamerly's bounds): u, an upper bound on the
+// distance to its own centre a, and l, a lower bound on the distance to
+// every other centre, are taken when the point is scored; each update moves
+// centre c by drift_c, which can raise the distance to a by at most drift_a
+// and lower the distance to any other centre by at most the candidate's
+// largest drift.  With Cum_c the summed drifts of centre c and CumMax the
+// summed largest drifts, the stored hu = u - Cum_a and hl = l + CumMax give
+// at a later iteration U = hu + Cum_a <= and Lb = hl - CumMax >= the true
+// distances.  The point is not re-scored when Lb^2 - U^2 > 2E, E a bound on
+// the error of a computed score: then the computed score of a is below every
+// other computed score, so scoring the point would return a again, and the
+// labels, centres and iteration counts are those of the full assignment.
+// Every bound is rounded outward (FP64 with relative slack, FP32 storage
+// rounded up or down).
+//
+// Score error.  A computed score is 2^nexp (|c|^2 - 2 z.c) from split
+// halves: each half pair carries z 2^s to 2^-22 relative (plus 2^-25
+// absolute below the fp16 normal range), the dropped lo.lo product is below
+// 2^-22 |z||c|, the 3d exact products and the norm are accumulated in FP32
+// (at most (3d + 1) 2^-24 of their absolute sum), and |c|^2 comes from an
+// FP32 sum (d 2^-24 |c|^2).  With cm >= every centre norm (centres are means
+// of points, or picked points, so cm = the largest |z| with a margin), all
+// of this is below (4d + 64) 2^-23 (cm + |z|)^2, twice the sum of the terms.
+__device__ __forceinline__ double prune_up(double x, double rel) {
+    return __builtin_isfinite(x) ? x + fabs(x) * rel : x;
+}
+__device__ __forceinline__ double prune_dn(double x, double rel) {
+    return __builtin_isfinite(x) ? x - fabs(x) * rel : x;
+}
+__device__ __forceinline__ float f32_up(double x) {
+    float f = (float)x;
+    if ((double)f < x) {
+        const uint32_t b = __float_as_uint(f);
+        f = f == 0.f ? __uint_as_float(1u) : (f > 0.f ? __uint_as_float(b + 1) : __uint_as_float(b - 1));
+    }
+    return f;
+}
+__device__ __forceinline__ float f32_dn(double x) {
+    float f = (float)x;
+    if ((double)f > x) {
+        const uint32_t b = __float_as_uint(f);
+        f = f == 0.f ? -__uint_as_float(1u) : (f > 0.f ? __uint_as_float(b - 1) : __uint_as_float(b + 1));
+    }
+    return f;
+}
+// slack of the running FP64 sums (at most 65536 terms each)
+constexpr double kSumSlack = 0x1p-36;
+constexpr double kRootSlack = 0x1p-40;
+
+__device__ __forceinline__ double prune_eps(const KmeansPlan& p, double zn2) {
+    const double cm = (double)__uint_as_float(*p.znmax_bits) * (1.0 + 0x1p-16);
+    const double s = cm + sqrt(zn2) * (1.0 + 0x1p-30);
+    return (double)(4 * p.d + 64) * 0x1p-23 * s * s;
+}
+// summed largest drift of candidate k before assignment `it` (it >= 2)
+__device__ __forceinline__ double prune_cummax(const KmeansPlan& p, int k, int it) {
+    return p.cmx[k] + p.dmx[2 * (size_t)k + ((it - 1) & 1)];
+}
+
+// |z|^2 per point (FP64 sum, rounded up to FP32) and the largest |z|.
+__global__ __launch_bounds__(256) void k_prune_prep(KmeansPlan p, const float* __restrict__ Z) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (i < p.n) {
+        const float* zr = Z + (size_t)i * p.d;
+        for (int j = 0; j < p.d; ++j) s += (double)zr[j] * (double)zr[j];
+        s = prune_up(s, kRootSlack);
+        p.zn2[i] = f32_up(s);
+    }
+    float m = f32_up(prune_up(sqrt(s), kRootSlack));
+    if (!(m <= 3.0e38f)) m = 3.0e38f;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(p.znmax_bits, __float_as_uint(m));
+}
+
+// Score error bound E of every point (needs the largest |z| of all points).
+__global__ __launch_bounds__(256) void k_prune_eps(KmeansPlan p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < p.n) p.pe[i] = f32_up(prune_eps(p, (double)p.zn2[i]));
+}
+
+// Bounds at rest: hu = +inf, hl = -inf (every point is listed until scored);
+// running sums and list lengths zero.
+__global__ __launch_bounds__(256) void k_prune_fill(KmeansPlan p) {
+    const size_t total = (size_t)p.Kc * p.n;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        p.hu[i] = INFINITY;
+        p.hl[i] = -INFINITY;
+    }
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid < p.KP) p.cum[tid] = 0.0;
+    if (tid < p.Kc) {
+        p.cmx[tid] = 0.0;
+        p.dmx[2 * tid] = 0.0;
+        p.dmx[2 * tid + 1] = 0.0;
+    }
+    if (tid == 0) *p.znmax_bits = 0u;
+}
+
+// Points held per lane group of the pruned assignment's waves.
+template <int D>
+constexpr int list_ps() {
+    return D <= 64 ? 4 : (D <= 128 ? 2 : 1);
+}
+
+// Pruned assignment, two launches per iteration.
+//
+// k_prune_test (grid: x = ranges of kPruneRange points, y = positions of
+// alist) tests the bounds of every point of its range for its candidate and
+// writes the points they do not hold, in point order, to the range's own
+// slots of the candidate's list (plist[k][range start ...]) and their count
+// to scnt[k][range]; the previous labels of the others are brought level
+// with the current ones (the update reads a difference of the two as a
+// move).  Every load of a wave's points is issued before its first test.
+//
+// k_prune_score (a persistent grid) scores the listed points.  Work items
+// are 256 listed points of one (candidate, range) list, numbered candidate
+// after candidate; each work-group takes a contiguous range of items, so it
+// changes candidate rarely: on a change it stages the candidate's whole
+// centre table in LDS (hi and lo halves, scaled norms, running drifts), and
+// its waves then walk the table with no barrier per tile.  The scores are
+// those of k_assign_h bit for bit (the same split operands, MFMA chain and
+// argmin with ties to the lowest row); each scored point also keeps its
+// second-lowest score for its new bounds.
+__global__ __launch_bounds__(256) void k_prune_test(KmeansPlan p) {
+    constexpr int QR = kPruneRange / 4;     // points per wave
+    constexpr int QI = QR / kWave;
+    __shared__ int lst[4][QR];
+    __shared__ int wcnt[4];
+    __shared__ double ccum[RAFT_MAX_K_DEV + 17];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wid = tid / kWave;
+    const int t = blockIdx.y;
+    if (t >= p.agrp[p.agroups]) return;     // uniform across the work-group
+    const int k = p.alist[t];
+    if (!p.active[k]) return;
+    const int koff = p.koff16[k];
+    const int K = p.ks[k];
+    const int r0 = (int)blockIdx.x * kPruneRange + wid * QR;
+    const size_t kb = (size_t)k * p.n;
+    uint32_t la[QI], lo[QI];
+    float fu[QI], fl[QI], fe[QI];
+#pragma unroll
+    for (int q = 0; q < QI; ++q) {
+        const int i = min(r0 + q * kWave + lane, p.n - 1);
+        la[q] = p.lab_cm[kb + i];
+        lo[q] = p.lab_old[kb + i];
+        fu[q] = p.hu[kb + i];
+        fl[q] = p.hl[kb + i];
+        fe[q] = p.pe[i];
+    }
+    for (int r = tid; r < K; r += blockDim.x) ccum[r] = p.cum[koff + r];
+    const double cx = prune_up(prune_cummax(p, k, p.it), kSumSlack);
+    __syncthreads();
+    int cnt = 0;
+#pragma unroll
+    for (int q = 0; q < QI; ++q) {
+        const int i = r0 + q * kWave + lane;
+        bool need = false;
+        if (i < p.n) {
+            if (lo[q] != la[q]) p.lab_old[kb + i] = (uint8_t)la[q];
+            const double cu = prune_up(ccum[min((int)la[q], K - 1)], kSumSlack);
+            const double U = prune_up((double)fu[q] + cu, kRootSlack);
+            const double Lb = prune_dn((double)fl[q] - cx, kRootSlack);
+            need = !(Lb > U && prune_dn((Lb - U) * (Lb + U), kRootSlack) > 2.0 * (double)fe[q]);
+        }
+        const uint64_t m = __ballot(need);
+        if (need) lst[wid][cnt + __popcll(m & ((1ull << lane) - 1ull))] = i;
+        cnt += __popcll(m);
+    }
+    if (lane == 0) wcnt[wid] = cnt;
+    __syncthreads();
+    int off = 0;
+    for (int q = 0; q < wid; ++q) off += wcnt[q];
+    int* dst = p.plist + kb + (size_t)blockIdx.x * kPruneRange + off;
+    for (int e = lane; e < cnt; e += kWave) dst[e] = lst[wid][e];
+    if (tid == 0)
+        p.scnt[(size_t)k * p.nranges + blockIdx.x] = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+}
+
+template <int D, int PS>
+__global__ __launch_bounds__(256) void k_prune_score(KmeansPlan p) {
+    constexpr int NC = D / 32;
+    constexpr int RS = D + 8;               // LDS row stride (halves)
+    constexpr int CPR = D / 8;              // 16-byte chunks per row and half
+    constexpr int WI = 16 * PS;             // points per wave and pass
+    extern __shared__ __align__(16) unsigned char list_lds[];
+    __shared__ double ccum[RAFT_MAX_K_DEV + 17];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wid = tid / kWave;
+    const int g = lane >> 4;
+    const int li = lane & 15;
+    // (alist position, range) lists; at most as many as the LDS was sized for
+    const int nact = min(p.agrp[p.agroups], p.lists_nact);
+    const int nr = p.nranges;
+    const int E = nact * nr;
+    const int ctiles = p.list_tiles;
+    _Float16* hs = reinterpret_cast<_Float16*>(list_lds);
+    _Float16* ls = hs + (size_t)ctiles * 16 * RS;
+    float* cs = reinterpret_cast<float*>(ls + (size_t)ctiles * 16 * RS);
+    int* pref = reinterpret_cast<int*>(cs + (size_t)ctiles * 16);   // [E + 1] items before list e
+    // items (256 listed points) of every list, prefix over the lists in order
+    {
+        constexpr int NT = 256;
+        const int per = (E + NT - 1) / NT;
+        const int e0 = tid * per, e1 = min(E, e0 + per);
+        int sum = 0;
+        for (int e = e0; e < e1; ++e) {
+            const int t = e / nr, r = e - t * nr;
+            const int k = p.alist[t];
+            const int c = p.active[k] ? p.scnt[(size_t)k * nr + r] : 0;
+            const int items = (c + 255) >> 8;
+            pref[e + 1] = items;
+            sum += items;
+        }
+        __shared__ int part[NT];
+        part[tid] = sum;
+        __syncthreads();
+        if (tid == 0) {
+            int run = 0;
+            for (int q = 0; q < NT; ++q) {
+                const int v = part[q];
+                part[q] = run;
+                run += v;
+            }
+            pref[0] = 0;
+        }
+        __syncthreads();
+        int run = part[tid];
+        for (int e = e0; e < e1; ++e) {
+            run += pref[e + 1];
+            pref[e + 1] = run;
+        }
+        __syncthreads();
+    }
+    const int total = pref[E];
+    const int per = (total + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int w0 = (int)blockIdx.x * per, w1 = min(total, w0 + per);
+    if (w0 >= w1) return;                    // uniform across the work-group
+    const int nexp = 2 * split_exp(p) - 1;
+    const _Float16* chp = reinterpret_cast<const _Float16*>(p.ch);
+    const _Float16* clp = reinterpret_cast<const _Float16*>(p.cl);
+    int e = 0;
+    {
+        int lo = 0, hi = E;                  // pref[lo] <= w0 < pref[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pref[mid] <= w0) lo = mid;
+            else hi = mid;
+        }
+        e = lo;
+    }
+    int staged = -1;                         // alist position of the staged table
+    for (int w = w0; w < w1; ++w) {
+        while (pref[e + 1] <= w) ++e;
+        const int t = e / nr, r = e - t * nr;
+        const int k = p.alist[t];
+        const int len = p.scnt[(size_t)k * nr + r];
+        const int koff = p.koff16[k];
+        const int ntiles = (p.ks[k] + 15) >> 4;
+        const int* lst = p.plist + (size_t)k * p.n + (size_t)r * kPruneRange;
+        const int ibase = (w - pref[e]) * 256;
+        if (t != staged) {
+            __syncthreads();                 // every wave is past the previous table
+            const int chunks = ntiles * 16 * CPR * 2;
+            for (int c = tid; c < chunks; c += blockDim.x) {
+                const int which = c / (ntiles * 16 * CPR);
+                const int rem = c - which * (ntiles * 16 * CPR);
+                const int rr = rem / CPR, c8 = rem - rr * CPR;
+                const uint4 v = *reinterpret_cast<const uint4*>((which ? clp : chp) +
+                                                                (size_t)(koff + rr) * D + 8 * c8);
+                *reinterpret_cast<uint4*>((which ? ls : hs) + (size_t)rr * RS + 8 * c8) = v;
+            }
+            for (int rr = tid; rr < ntiles * 16; rr += blockDim.x) {
+                cs[rr] = ldexpf(p.cnorm[koff + rr], nexp);
+                ccum[rr] = p.cum[koff + rr];
+            }
+            __syncthreads();
+            staged = t;
+        }
+        // the wave's passes over its quarter of the item's 256 points
+        for (int base = ibase + wid * WI; base < min(len, ibase + 256); base += 4 * WI) {
+            int idx[PS];
+#pragma unroll
+            for (int ps = 0; ps < PS; ++ps) idx[ps] = lst[min(base + 16 * ps + li, len - 1)];
+            half8 bh[PS][NC], bl[PS][NC];
+#pragma unroll
+            for (int ps = 0; ps < PS; ++ps) {
+                const size_t row = (size_t)idx[ps] * D + 8 * g;
+                const _Float16* hr = reinterpret_cast<const _Float16*>(p.zh) + row;
+                const _Float16* lr = reinterpret_cast<const _Float16*>(p.zl) + row;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    bh[ps][c] = neg_half8(*reinterpret_cast<const half8*>(hr + 32 * c));
+                    bl[ps][c] = neg_half8(*reinterpret_cast<const half8*>(lr + 32 * c));
+                }
+            }
+            // the writing lane's point: previous label and norms, loaded ahead
+            int mi = 0;
+#pragma unroll
+            for (int ps = 0; ps < PS; ++ps)
+                if (g == ps) mi = idx[ps];
+            const bool wr = g < PS && base + 16 * g + li < len;
+            uint32_t old = 0;
+            float zq = 0.f, eq = 0.f;
+            if (wr) {
+                old = p.lab_cm[(size_t)k * p.n + mi];
+                zq = p.zn2[mi];
+                eq = p.pe[mi];
+            }
+            float bv[PS], b2[PS];
+            int bi[PS];
+#pragma unroll
+            for (int ps = 0; ps < PS; ++ps) {
+                bv[ps] = INFINITY;
+                b2[ps] = INFINITY;
+                bi[ps] = 0;
+            }
+            for (int tile = 0; tile < ntiles; ++tile) {
+                const float4 cnn = *reinterpret_cast<const float4*>(&cs[tile * 16 + 4 * g]);
+                floatx4 acc[PS];
+#pragma unroll
+                for (int ps = 0; ps < PS; ++ps) acc[ps] = floatx4{cnn.x, cnn.y, cnn.z, cnn.w};
+                const _Float16* hrow = hs + (size_t)(tile * 16 + li) * RS + 8 * g;
+                const _Float16* lrow = ls + (size_t)(tile * 16 + li) * RS + 8 * g;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const half8 ah = *reinterpret_cast<const half8*>(hrow + 32 * c);
+                    const half8 al = *reinterpret_cast<const half8*>(lrow + 32 * c);
+#pragma unroll
+                    for (int ps = 0; ps < PS; ++ps)
+                        acc[ps] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[ps][c], acc[ps], 0, 0, 0);
+#pragma unroll
+                    for (int ps = 0; ps < PS; ++ps)
+                        acc[ps] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl[ps][c], acc[ps], 0, 0, 0);
+#pragma unroll
+                    for (int ps = 0; ps < PS; ++ps)
+                        acc[ps] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[ps][c], acc[ps], 0, 0, 0);
+                }
+#pragma unroll
+                for (int ps = 0; ps < PS; ++ps) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const float sc = acc[ps][v];
+                        const bool lt = sc < bv[ps];
+                        b2[ps] = lt ? bv[ps] : fminf(b2[ps], sc);
+                        bi[ps] = lt ? tile * 16 + 4 * g + v : bi[ps];
+                        bv[ps] = lt ? sc : bv[ps];
+                    }
+                }
+            }
+            // the four lane groups of each point: lowest score, lowest row
+            // among equal ones; the second-lowest over both sides and the
+            // other's best
+#pragma unroll
+            for (int ps = 0; ps < PS; ++ps) {
+#pragma unroll
+                for (int off = 16; off < kWave; off <<= 1) {
+                    const float ov = __shfl_xor(bv[ps], off, kWave);
+                    const int oi = __shfl_xor(bi[ps], off, kWave);
+                    const float o2 = __shfl_xor(b2[ps], off, kWave);
+                    const bool take = (ov < bv[ps]) | ((ov == bv[ps]) & (oi < bi[ps]));
+                    b2[ps] = fminf(fminf(b2[ps], o2), take ? bv[ps] : ov);
+                    bv[ps] = take ? ov : bv[ps];
+                    bi[ps] = take ? oi : bi[ps];
+                }
+            }
+            float mv = 0.f, m2 = 0.f;
+            int mb = 0;
+#pragma unroll
+            for (int ps = 0; ps < PS; ++ps)
+                if (g == ps) {
+                    mv = bv[ps];
+                    m2 = b2[ps];
+                    mb = bi[ps];
+                }
+            bool changed = false;
+            if (wr) {
+                const size_t o = (size_t)k * p.n + mi;
+                const uint8_t nw = (uint8_t)mb;
+                changed = old != nw;
+                p.lab_cm[o] = nw;
+                p.lab_old[o] = (uint8_t)old;
+                if (changed) p.moved_it[(size_t)(mi >> 6) * p.Kc + k] = p.it;
+                const double zn2 = (double)zq;
+                const double Eq = (double)eq;
+                const double sa = ldexp((double)mv, -nexp);
+                const double s2 = ldexp((double)m2, -nexp);
+                const double u =
+                    prune_up(sqrt(fmax(0.0, prune_up(zn2 + sa + Eq, kRootSlack))), kRootSlack);
+                const double l = prune_dn(
+                    sqrt(fmax(0.0, prune_dn(zn2 * (1.0 - 0x1p-20) + s2 - Eq, kRootSlack))), kRootSlack);
+                const double cd = prune_dn(ccum[nw], kSumSlack);
+                const double cxd = prune_dn(prune_cummax(p, k, p.it), kSumSlack);
+                p.hu[o] = f32_up(prune_up(u - cd, kRootSlack));
+                p.hl[o] = f32_dn(prune_dn(l + cxd, kRootSlack));
+            }
+            const uint64_t cm = __ballot(changed);
+            if (lane == 0 && cm) p.changes[k] = 1;
+        }
+    }
+}
+
+// Dynamic LDS bytes of k_prune_score: centre tables of up to `tiles` tiles
+// and the item prefix over `lists` (candidate, range) lists.
+size_t list_lds_bytes(int d, int tiles, int lists) {
+    return (size_t)tiles * 16 * ((size_t)2 * (d + 8) * 2 + 4) + (size_t)(lists + 1) * 4;
+}
+
 // After an assignment: a candidate whose labels did not change (from the
 // second assignment on) has converged; count the remaining active ones.
 // changes[k] is a flag (plain stores of 1): a counter updated by every wave
@@ -776,6 +1191,16 @@ __device__ __forceinline__ void finalize_candidates(const KmeansPlan& p, int it,
     __syncthreads();
     int mine = 0;
     for (int k = threadIdx.x; k < p.Kc; k += blockDim.x) {
+        if (p.prune) {
+            // pruned assignment: the previous update's largest drift
+            // (complete since that launch ended) joins the running sum and
+            // its slot is cleared for the update after the next assignment
+            if (it >= 2) {
+                double* slot = p.dmx + 2 * (size_t)k + ((it - 1) & 1);
+                p.cmx[k] += *slot;
+                *slot = 0.0;
+            }
+        }
         if (!p.active[k]) continue;
         const int ch = p.changes[k];
         p.changes[k] = 0;
@@ -1201,6 +1626,7 @@ __device__ __forceinline__ void update_finish_body(const KmeansPlan& p, int it, 
     const size_t stride = (size_t)p.KP * p.d;
     float* crow = p.C + (size_t)c * p.d;
     float ss = 0.f;
+    double drift2 = 0.0;   // squared move of the centre (exact differences of FP32 values)
     for (int d0 = 0; d0 < p.d; d0 += kWave) {
         const int dd = d0 + lane;
         long long s = 0;
@@ -1231,6 +1657,8 @@ __device__ __forceinline__ void update_finish_body(const KmeansPlan& p, int it, 
             p.S64[(size_t)c * p.d + dd] = t;
             if (total > 0) {
                 const float v = (float)((double)t * inv / (double)total);
+                const double mv = (double)v - (double)crow[dd];
+                drift2 += mv * mv;
                 crow[dd] = v;
                 if (p.split)
                     split_half(v, ldexpf(1.0f, split_exp(p)), p.ch + (size_t)c * p.d + dd,
@@ -1243,6 +1671,17 @@ __device__ __forceinline__ void update_finish_body(const KmeansPlan& p, int it, 
         if (lane == 0) p.N32[c] = total;
         ss = wave_sum(ss);
         if (lane == 0 && total > 0) p.cnorm[c] = ss;
+        if (p.prune) {
+            // drift of the centre, rounded up, into its running sum (one
+            // writer per row) and the candidate's largest drift of this update
+            drift2 = wave_sum(drift2);
+            if (lane == 0 && drift2 > 0.0) {
+                const double dl = sqrt(drift2) * (1.0 + 0x1p-40);
+                p.cum[c] += dl;
+                atomicMax(reinterpret_cast<unsigned long long*>(p.dmx + 2 * (size_t)k + (it & 1)),
+                          (unsigned long long)__double_as_longlong(dl));
+            }
+        }
     }
 }
 
@@ -1518,6 +1957,46 @@ void launch_copy_centres(const KmeansPlan& p, float* out, hipStream_t st) {
     if (total == 0) return;
     const int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
     hipLaunchKernelGGL(k_copy_centres, dim3(grid), dim3(256), 0, st, p, out);
+}
+
+void launch_prune_init(const KmeansPlan& p, const float* Z, hipStream_t st) {
+    const size_t total = (size_t)p.Kc * p.n;
+    const int fill = (int)std::max<size_t>(
+        (size_t)(std::max(p.KP, p.Kc) + 255) / 256, std::min<size_t>((total + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_prune_fill, dim3(fill), dim3(256), 0, st, p);
+    if (p.n > 0) {
+        hipLaunchKernelGGL(k_prune_prep, dim3((p.n + 255) / 256), dim3(256), 0, st, p, Z);
+        hipLaunchKernelGGL(k_prune_eps, dim3((p.n + 255) / 256), dim3(256), 0, st, p);
+    }
+}
+
+void launch_assign_pruned(const KmeansPlan& p, int nact, int num_cu, hipStream_t st, hipEvent_t e0,
+                          hipEvent_t e1) {
+    if (p.n == 0 || nact <= 0) return;
+    hipExtLaunchKernelGGL(k_prune_test, dim3((unsigned)p.nranges, (unsigned)nact), dim3(256), 0, st,
+                          e0, nullptr, 0, p);
+    const dim3 grid((unsigned)(num_cu * (p.d <= 64 ? 3 : 2)));
+    KmeansPlan q = p;
+    q.lists_nact = nact;
+    const size_t lds = list_lds_bytes(p.d, p.list_tiles, nact * p.nranges);
+#define PRUNED(DV)                                                                                 \
+    {                                                                                              \
+        static std::once_flag attr_once;                                                           \
+        std::call_once(attr_once, [] {                                                             \
+            (void)hipFuncSetAttribute((const void*)k_prune_score<DV, list_ps<DV>()>,               \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, 156 * 1024);     \
+        });                                                                                        \
+        hipExtLaunchKernelGGL((k_prune_score<DV, list_ps<DV>()>), grid, dim3(256), lds, st,        \
+                              nullptr, e1, 0, q);                                                  \
+    }
+    switch (p.d) {
+        case 32: PRUNED(32); break;
+        case 64: PRUNED(64); break;
+        case 128: PRUNED(128); break;
+        case 256: PRUNED(256); break;
+        default: break;
+    }
+#undef PRUNED
 }
 
 void launch_iter_finalize(const KmeansPlan& p, int it, int t_max, hipStream_t st) {
