@@ -469,8 +469,8 @@ void plan_layout(raft_ctx* ctx, const raft_graph* g, const raft_config* c, char*
     const int nranges = (int)((n + kPruneRange - 1) / kPruneRange);
     const bool prune_pays = c->kmeans_prune == 1 || (c->kmeans_prune == 0 && G.SK >= 64 * G.Kc);
     km.prune = features && km.split && prune_pays && c->kmeans_max_iter <= 65536 &&
-                       list_lds_bytes(P.d, (G.k_max + 15) / 16, G.Kc * nranges) + 4096 <=
-                           ((size_t)160 << 10)
+                       list_lds_bytes(P.d, (G.k_max + 15) / 16, G.Kc * nranges) <=
+                           (size_t)kPruneDynLdsMax
                    ? 1
                    : 0;
     if (km.prune) {

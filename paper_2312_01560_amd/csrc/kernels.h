@@ -236,6 +236,8 @@ bool kmeans_split_supported(int d);
 // for launch_assign.
 void launch_prune_init(const KmeansPlan& p, const float* Z, hipStream_t st);
 size_t list_lds_bytes(int d, int tiles, int lists);
+// Dynamic LDS the scoring kernel may use (its static LDS stays below 8 KB).
+constexpr int kPruneDynLdsMax = 152 * 1024;
 void launch_assign_pruned(const KmeansPlan& p, int nact, int num_cu, hipStream_t st,
                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // zh/zl from Z (after launch_zmax).

@@ -868,10 +868,15 @@ __global__ __launch_bounds__(256) void k_prune_fill(KmeansPlan p) {
     if (tid == 0) *p.znmax_bits = 0u;
 }
 
-// Points held per lane group of the pruned assignment's waves.
+// Points held per lane group of the pruned assignment's waves, and waves
+// per scoring work-group.
 template <int D>
 constexpr int list_ps() {
     return D <= 64 ? 4 : (D <= 128 ? 2 : 1);
+}
+template <int D>
+constexpr int prune_nw() {
+    return D <= 64 ? 4 : 16;
 }
 
 // Pruned assignment, two launches per iteration.
@@ -950,12 +955,13 @@ __global__ __launch_bounds__(256) void k_prune_test(KmeansPlan p) {
         p.scnt[(size_t)k * p.nranges + blockIdx.x] = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
 }
 
-template <int D, int PS>
-__global__ __launch_bounds__(256) void k_prune_score(KmeansPlan p) {
+template <int D, int PS, int NW>
+__global__ __launch_bounds__(NW * 64) void k_prune_score(KmeansPlan p) {
     constexpr int NC = D / 32;
     constexpr int RS = D + 8;               // LDS row stride (halves)
     constexpr int CPR = D / 8;              // 16-byte chunks per row and half
     constexpr int WI = 16 * PS;             // points per wave and pass
+    constexpr int IP = NW * WI > 256 ? NW * WI : 256;   // points per work item
     extern __shared__ __align__(16) unsigned char list_lds[];
     __shared__ double ccum[RAFT_MAX_K_DEV + 17];
     const int tid = threadIdx.x;
@@ -974,7 +980,7 @@ __global__ __launch_bounds__(256) void k_prune_score(KmeansPlan p) {
     int* pref = reinterpret_cast<int*>(cs + (size_t)ctiles * 16);   // [E + 1] items before list e
     // items (256 listed points) of every list, prefix over the lists in order
     {
-        constexpr int NT = 256;
+        constexpr int NT = NW * 64;
         const int per = (E + NT - 1) / NT;
         const int e0 = tid * per, e1 = min(E, e0 + per);
         int sum = 0;
@@ -982,7 +988,7 @@ __global__ __launch_bounds__(256) void k_prune_score(KmeansPlan p) {
             const int t = e / nr, r = e - t * nr;
             const int k = p.alist[t];
             const int c = p.active[k] ? p.scnt[(size_t)k * nr + r] : 0;
-            const int items = (c + 255) >> 8;
+            const int items = (c + IP - 1) / IP;
             pref[e + 1] = items;
             sum += items;
         }
@@ -1032,7 +1038,7 @@ __global__ __launch_bounds__(256) void k_prune_score(KmeansPlan p) {
         const int koff = p.koff16[k];
         const int ntiles = (p.ks[k] + 15) >> 4;
         const int* lst = p.plist + (size_t)k * p.n + (size_t)r * kPruneRange;
-        const int ibase = (w - pref[e]) * 256;
+        const int ibase = (w - pref[e]) * IP;
         if (t != staged) {
             __syncthreads();                 // every wave is past the previous table
             const int chunks = ntiles * 16 * CPR * 2;
@@ -1052,7 +1058,7 @@ __global__ __launch_bounds__(256) void k_prune_score(KmeansPlan p) {
             staged = t;
         }
         // the wave's passes over its quarter of the item's 256 points
-        for (int base = ibase + wid * WI; base < min(len, ibase + 256); base += 4 * WI) {
+        for (int base = ibase + wid * WI; base < min(len, ibase + IP); base += NW * WI) {
             int idx[PS];
 #pragma unroll
             for (int ps = 0; ps < PS; ++ps) idx[ps] = lst[min(base + 16 * ps + li, len - 1)];
@@ -1975,7 +1981,9 @@ void launch_assign_pruned(const KmeansPlan& p, int nact, int num_cu, hipStream_t
     if (p.n == 0 || nact <= 0) return;
     hipExtLaunchKernelGGL(k_prune_test, dim3((unsigned)p.nranges, (unsigned)nact), dim3(256), 0, st,
                           e0, nullptr, 0, p);
-    const dim3 grid((unsigned)(num_cu * (p.d <= 64 ? 3 : 2)));
+    // d <= 64: 256-thread work-groups, three per CU; wider: one 1024-thread
+    // work-group per CU, its sixteen waves sharing one staged table
+    const dim3 grid((unsigned)(num_cu * (p.d <= 64 ? 3 : 1)));
     KmeansPlan q = p;
     q.lists_nact = nact;
     const size_t lds = list_lds_bytes(p.d, p.list_tiles, nact * p.nranges);
@@ -1983,11 +1991,12 @@ void launch_assign_pruned(const KmeansPlan& p, int nact, int num_cu, hipStream_t
     {                                                                                              \
         static std::once_flag attr_once;                                                           \
         std::call_once(attr_once, [] {                                                             \
-            (void)hipFuncSetAttribute((const void*)k_prune_score<DV, list_ps<DV>()>,               \
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, 156 * 1024);     \
+            (void)hipFuncSetAttribute((const void*)k_prune_score<DV, list_ps<DV>(), prune_nw<DV>()>, \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,                  \
+                                      kPruneDynLdsMax);                                            \
         });                                                                                        \
-        hipExtLaunchKernelGGL((k_prune_score<DV, list_ps<DV>()>), grid, dim3(256), lds, st,        \
-                              nullptr, e1, 0, q);                                                  \
+        hipExtLaunchKernelGGL((k_prune_score<DV, list_ps<DV>(), prune_nw<DV>()>), grid,            \
+                              dim3(prune_nw<DV>() * 64), lds, st, nullptr, e1, 0, q);              \
     }
     switch (p.d) {
         case 32: PRUNED(32); break;
