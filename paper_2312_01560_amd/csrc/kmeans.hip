@@ -1356,22 +1356,37 @@ __device__ __forceinline__ unsigned long long widen_at_use(int x) {
 __device__ __forceinline__ void update_body(const KmeansPlan& p, const float* __restrict__ Z, int wi,
                                             int it) {
     extern __shared__ unsigned long long acc64[];
-    // work item wi -> (group, range slot)
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    // work item wi -> (group, range slot): g = the number of groups after the
+    // first whose first item is at most wi (the first items increase), read
+    // 64 at a time rather than walked one dependent load after another
     int g = 0;
-    while (g + 1 < p.ugroups && p.uwi0[g + 1] <= wi) ++g;
+    for (int b0 = 1; b0 < p.ugroups; b0 += kWave) {
+        const int q = b0 + lane;
+        g += __popcll(__ballot(q < p.ugroups && p.uwi0[q] <= wi));
+    }
     const int slot = wi - p.uwi0[g];
     const int sl = blockIdx.y;
     const int t0 = p.ugrp[g], t1 = p.ugrp[g + 1];
-    int rows = 0;
-    bool any = false;
-    for (int t = t0; t < t1; ++t) {
-        const int k = p.alist[t];
-        rows += p.ks[k];
-        any |= p.active[k] != 0;
+    const int nc = t1 - t0;
+    // the group's candidates: lane l holds candidate l % 16 (read back with
+    // readlane from lanes 0..15, and by lane in the moved-flag loads), its
+    // centre count, padded centre offset and first accumulator row
+    const int mc = lane & (kUpdMaxCand - 1);
+    int my_k = 0, my_K = 0, my_act = 0, my_off = 0;
+    if (mc < nc) {
+        my_k = p.alist[t0 + mc];
+        my_K = p.ks[my_k];
+        my_act = p.active[my_k] != 0;
+        my_off = p.koff16[my_k];
     }
-    if (!any) return;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    int my_base = 0, rows = 0;
+    for (int m = 0; m < nc; ++m) {
+        if (mc == m) my_base = rows;
+        rows += __builtin_amdgcn_readlane(my_K, m);
+    }
+    if (__ballot(my_act != 0) == 0) return;   // uniform across the work-group
     const int total_rows = rows + 1;                          // + one dummy row
     int* cnt = reinterpret_cast<int*>(acc64 + (size_t)total_rows * kUpdSlice);
     int* touch = cnt + total_rows;
@@ -1392,22 +1407,6 @@ __device__ __forceinline__ void update_body(const KmeansPlan& p, const float* __
     const int r0 = slot * len;
     const int r1 = min(p.n, r0 + len);
     unsigned long long* acol = acc64 + lane;
-    const int nc = t1 - t0;
-    // the group's candidates: lane l holds candidate l % 16 (read back with
-    // readlane from lanes 0..15, and by lane in the moved-flag loads), its
-    // centre count and its first accumulator row
-    const int mc = lane & (kUpdMaxCand - 1);
-    int my_k = 0, my_K = 0, my_act = 0;
-    if (mc < nc) {
-        my_k = p.alist[t0 + mc];
-        my_K = p.ks[my_k];
-        my_act = p.active[my_k] != 0;
-    }
-    int my_base = 0;
-    for (int m = 0, b = 0; m < nc; ++m) {
-        if (mc == m) my_base = b;
-        b += __builtin_amdgcn_readlane(my_K, m);
-    }
     // Chunks of this wave in batches of four: lane (j, m) reads whether
     // candidate m moved a point of chunk j in this iteration; the update skips
     // every (chunk, candidate) without a move, and whole chunks without one.
@@ -1554,11 +1553,10 @@ __device__ __forceinline__ void update_body(const KmeansPlan& p, const float* __
     __syncthreads();
     const int sw = min(kUpdSlice, p.d - sl * kUpdSlice);
     int base = 0;
-    for (int t = t0; t < t1; ++t) {
-        const int k = p.alist[t];
-        const int K = p.ks[k];
-        if (p.active[k]) {
-            const size_t row0 = (size_t)slot * p.KP + p.koff16[k];
+    for (int m = 0; m < nc; ++m) {
+        const int K = __builtin_amdgcn_readlane(my_K, m);
+        if (__builtin_amdgcn_readlane(my_act, m)) {
+            const size_t row0 = (size_t)slot * p.KP + __builtin_amdgcn_readlane(my_off, m);
             long long* dst = p.pdelta + row0 * p.d + sl * kUpdSlice;
             for (int r = wid; r < K; r += kUpdWaves) {
                 if (touch[base + r] == 0) continue;          // uniform per wave
