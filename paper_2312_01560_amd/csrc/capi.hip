@@ -637,6 +637,12 @@ raft_status do_embed(raft_ctx* ctx, const raft_graph* g, const raft_config* c, P
     return launch_check(ctx);
 }
 
+static int live_polled(const int32_t* active, int Kc) {
+    int live = 0;
+    for (int k = 0; k < Kc; ++k) live += active[k] != 0;
+    return live;
+}
+
 raft_status do_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* c, Plan& P,
                          const float* Z, raft_outputs* out, hipStream_t st, bool timed) {
     KmeansPlan km = P.km;
@@ -676,6 +682,7 @@ raft_status do_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* 
                   "poll slots exceed the pinned scratch");
     int poll = 0;
     int nact = (int)P.lists.alist.size();   // candidates of alist (the kernels skip retired ones)
+    int live_listed = Kc;                   // live candidates when the lists were built
     for (int it = 1; it <= t_max; ++it) {
         km.it = it;
         {
@@ -694,13 +701,17 @@ raft_status do_partition(raft_ctx* ctx, const raft_graph* g, const raft_config* 
             launch_update(km, Z, ctx->lds_max, it, t_max, st);
         }
         if (it % check == 0) {
+            const int32_t* ha = h_active[(poll - 1) & 1];
+            int live = live_listed;
             if (poll > 0) {
                 HIP_TRY(ctx, hipEventSynchronize(ctx->poll_ev[(poll - 1) & 1]));
-                const int32_t* ha = h_active[(poll - 1) & 1];
-                int live = 0;
-                for (int k = 0; k < Kc; ++k) live += ha[k] != 0;
+                live = live_polled(ha, Kc);
                 if (live == 0) break;
-                // compact the work lists to the candidates still iterating
+            }
+            // compact the work lists to the candidates still iterating (a
+            // candidate never resumes, so the same count is the same set)
+            if (live != live_listed) {
+                live_listed = live;
                 const Lists l = make_lists(P.grid, ha, P.ucap, g->n, ctx->num_cu);
                 int32_t* hl = h_lists[poll & 1];
                 pack_lists(l, Kc, hl);
