@@ -521,6 +521,7 @@ def main():
     assign_ach = assign_flops * args.steps / (ms_assign * 1e-3) if ms_assign > 0 else 0.0
     spmm_ach = spmm_bytes_per_launch * n_spmm / (ms_spmm * 1e-3) if ms_spmm > 0 else 0.0
     dominant = "assign" if ms_assign >= ms_spmm else "spmm"
+    pruned = False
     if dominant == "assign":
         split = d % 32 == 0
         peak = PEAK_MFMA_F16 if split else PEAK_MFMA_F32
@@ -533,17 +534,27 @@ def main():
                                  "candidates still iterating",
                 "per_launch": {"flops": assign_flops * args.steps / max(n_assign, 1),
                                "avg_ms": ms_assign / max(n_assign, 1)}}
-        if split:
+        pruned = split and cfgs[variants[0]].kmeans_prune != 2 and (
+            cfgs[variants[0]].kmeans_prune == 1 or float(np.mean(ks)) >= 64)
+        if split and not pruned:
             # what the matrix unit actually executes: three fp16 products per
             # FP32 product, centre rows padded to multiples of 16
             issued = issued_flops * args.steps / (ms_assign * 1e-3) if ms_assign > 0 else 0.0
             roof["issued_mfma"] = {"achieved": issued / 1e12, "frac": issued / PEAK_MFMA_F16,
                                    "note": "3 fp16 products per FP32 product, padded centres"}
+        if pruned:
+            roof["kernel"] = ("bound-pruned assignment (k_prune_test + k_prune_score, the "
+                              "first two iterations k_assign_h)")
+            roof["note"] = ("a launch is one iteration's assignment; from the third on only the "
+                            "points whose bounds do not hold their label are scored, so the "
+                            "rate on the method's full Lloyd FLOPs is an effective one")
     else:
         roof = {"kernel": "k_spmm", "bound": "hbm", "achieved": spmm_ach / 1e9,
                 "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": spmm_ach / PEAK_HBM,
                 "per_launch": {"bytes": spmm_bytes_per_launch, "avg_ms": ms_spmm / max(n_spmm, 1)}}
     roof["traffic"] = measured_traffic(dominant, args.workload)
+    if dominant == "assign" and pruned:
+        roof["traffic"] = None   # the counters cover the full assignment kernel only
     roof["traffic_note"] = ("bytes per launch beyond L2 from two rocprofv3 counter passes "
                             "(FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, scaled by a plain copy): "
                             "Infinity Cache hits included, so an upper bound on HBM bytes; "
