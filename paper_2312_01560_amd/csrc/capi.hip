@@ -29,6 +29,11 @@ struct raft_ctx {
     std::string err;
     int32_t* d_status = nullptr;   // device status word
     int32_t* h_pinned = nullptr;   // pinned host scratch (4096 ints)
+    // pinned staging of raft_graph_create (row pointers, row order): grown on
+    // demand; every use ends with a synchronisation of its stream, so no copy
+    // from it is in flight when the next call regrows it
+    char* stage = nullptr;
+    size_t stage_bytes = 0;
     double stage_ms[5] = {0, 0, 0, 0, 0};
     hipEvent_t ev[6] = {};
     hipEvent_t poll_ev[2] = {};    // convergence polls of the Lloyd loop (no timing)
@@ -843,6 +848,7 @@ void raft_ctx_destroy(raft_ctx* ctx) {
     for (auto& e : ctx->prof_pool) (void)hipEventDestroy(e);
     if (ctx->d_status) (void)hipFree(ctx->d_status);
     if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
+    if (ctx->stage) (void)hipHostFree(ctx->stage);
     delete ctx;
 }
 
@@ -888,19 +894,36 @@ raft_status raft_graph_create(raft_ctx* ctx, const void* row_ptr, int row_ptr_is
     hipStream_t st = as_stream(stream);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     // row_ptr is checked on the host before any kernel indexes col_idx with
-    // it; an int64 row_ptr is narrowed to int32 after the checks
-    std::vector<int32_t> h_rp((size_t)n + 1);
+    // it; an int64 row_ptr is narrowed to int32 after the checks.  Host
+    // copies go through the context's pinned staging (one DMA each, where
+    // pageable memory is copied in many small pieces):
+    // [raw row_ptr (n+1) x elem][int32 row_ptr (n+1)][row order n]
+    const size_t elem = row_ptr_is_int64 ? sizeof(int64_t) : sizeof(int32_t);
+    const size_t raw_bytes = ((size_t)n + 1) * elem;
+    const size_t raw_pad = (raw_bytes + 255) / 256 * 256;
+    const size_t rp_pad = (((size_t)n + 1) * sizeof(int32_t) + 255) / 256 * 256;
+    const size_t need = raw_pad + rp_pad + (size_t)n * sizeof(int32_t);
+    if (ctx->stage_bytes < need) {
+        if (ctx->stage) (void)hipHostFree(ctx->stage);
+        ctx->stage = nullptr;
+        ctx->stage_bytes = 0;
+        if (hipHostMalloc((void**)&ctx->stage, need) != hipSuccess) {
+            ctx->stage = nullptr;
+            return fail(ctx, RAFT_E_NOMEM, "pinned staging of %zu bytes", need);
+        }
+        ctx->stage_bytes = need;
+    }
+    int32_t* h_rp = reinterpret_cast<int32_t*>(ctx->stage + raw_pad);
+    int32_t* order = reinterpret_cast<int32_t*>(ctx->stage + raw_pad + rp_pad);
     {
-        const size_t elem = row_ptr_is_int64 ? sizeof(int64_t) : sizeof(int32_t);
-        std::vector<char> raw(((size_t)n + 1) * elem);
+        const char* raw = reinterpret_cast<const char*>(row_ptr);
         if (inputs_on_device) {
-            HIP_TRY(ctx, hipMemcpyAsync(raw.data(), row_ptr, raw.size(), hipMemcpyDeviceToHost, st));
+            HIP_TRY(ctx, hipMemcpyAsync(ctx->stage, row_ptr, raw_bytes, hipMemcpyDeviceToHost, st));
             HIP_TRY(ctx, hipStreamSynchronize(st));
-        } else {
-            memcpy(raw.data(), row_ptr, raw.size());
+            raw = ctx->stage;
         }
         if (row_ptr_is_int64) {
-            const int64_t* r64 = reinterpret_cast<const int64_t*>(raw.data());
+            const int64_t* r64 = reinterpret_cast<const int64_t*>(raw);
             if (r64[0] != 0 || r64[n] != nnz)
                 return fail(ctx, RAFT_E_CSR, "row_ptr must start at 0 and end at nnz");
             for (int64_t i = 0; i < n; ++i)
@@ -909,7 +932,7 @@ raft_status raft_graph_create(raft_ctx* ctx, const void* row_ptr, int row_ptr_is
             // non-decreasing from 0 to nnz < INT32_MAX: every entry fits int32
             for (int64_t i = 0; i <= n; ++i) h_rp[i] = (int32_t)r64[i];
         } else {
-            memcpy(h_rp.data(), raw.data(), raw.size());
+            memcpy(h_rp, raw, raw_bytes);
         }
     }
     if (h_rp[0] != 0 || h_rp[n] != nnz)
@@ -933,7 +956,7 @@ raft_status raft_graph_create(raft_ctx* ctx, const void* row_ptr, int row_ptr_is
         return fail(ctx, RAFT_E_NOMEM, "graph allocation failed");
     }
     const hipMemcpyKind kind = inputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    hipError_t e = hipMemcpyAsync(g->rp, h_rp.data(), sizeof(int32_t) * (n + 1),
+    hipError_t e = hipMemcpyAsync(g->rp, h_rp, sizeof(int32_t) * (n + 1),
                                   hipMemcpyHostToDevice, st);
     if (e == hipSuccess && nnz > 0)
         e = hipMemcpyAsync(g->ci, col_idx, sizeof(int32_t) * nnz, kind, st);
@@ -942,7 +965,6 @@ raft_status raft_graph_create(raft_ctx* ctx, const void* row_ptr, int row_ptr_is
     // classes), heaviest first, so the rows a wave takes side by side have
     // similar lengths and the longest start first.  Only the schedule
     // changes: every row is summed in its own edge order.
-    std::vector<int32_t> order((size_t)n);
     {
         constexpr int kClasses = 17;
         auto cls = [&](int64_t i) {
@@ -959,7 +981,7 @@ raft_status raft_graph_create(raft_ctx* ctx, const void* row_ptr, int row_ptr_is
         for (int b = 1; b < kClasses; ++b) g->heavy[b] = (int32_t)start[kClasses - 1 - b];
     }
     if (e == hipSuccess)
-        e = hipMemcpyAsync(g->order, order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st);
+        e = hipMemcpyAsync(g->order, order, sizeof(int32_t) * n, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->d_status, 0, sizeof(int32_t), st);
     if (e != hipSuccess) {
         raft_graph_destroy(g);
