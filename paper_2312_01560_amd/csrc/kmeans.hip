@@ -827,20 +827,23 @@ __device__ __forceinline__ double prune_cummax(const KmeansPlan& p, int k, int i
 }
 
 // |z|^2 per point (FP64 sum, rounded up to FP32) and the largest |z|.
+// One wave per row (lanes read consecutive columns), rows strided over the
+// grid's waves; each wave's largest norm joins the maximum once.
 __global__ __launch_bounds__(256) void k_prune_prep(KmeansPlan p, const float* __restrict__ Z) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double s = 0.0;
-    if (i < p.n) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int waves = (int)gridDim.x * (blockDim.x / kWave);
+    float m = 0.f;
+    for (int i = (int)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; i < p.n; i += waves) {
         const float* zr = Z + (size_t)i * p.d;
-        for (int j = 0; j < p.d; ++j) s += (double)zr[j] * (double)zr[j];
+        double s = 0.0;
+        for (int j = lane; j < p.d; j += kWave) s += (double)zr[j] * (double)zr[j];
+        s = wave_sum(s);
         s = prune_up(s, kRootSlack);
-        p.zn2[i] = f32_up(s);
+        if (lane == 0) p.zn2[i] = f32_up(s);
+        m = fmaxf(m, f32_up(prune_up(sqrt(s), kRootSlack)));
     }
-    float m = f32_up(prune_up(sqrt(s), kRootSlack));
     if (!(m <= 3.0e38f)) m = 3.0e38f;
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, kWave));
-    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(p.znmax_bits, __float_as_uint(m));
+    if (lane == 0) atomicMax(p.znmax_bits, __float_as_uint(m));
 }
 
 // Score error bound E of every point (needs the largest |z| of all points).
@@ -1969,7 +1972,8 @@ void launch_prune_init(const KmeansPlan& p, const float* Z, hipStream_t st) {
         (size_t)(std::max(p.KP, p.Kc) + 255) / 256, std::min<size_t>((total + 255) / 256, 4096));
     hipLaunchKernelGGL(k_prune_fill, dim3(fill), dim3(256), 0, st, p);
     if (p.n > 0) {
-        hipLaunchKernelGGL(k_prune_prep, dim3((p.n + 255) / 256), dim3(256), 0, st, p, Z);
+        hipLaunchKernelGGL(k_prune_prep, dim3((unsigned)std::min((p.n + 3) / 4, 4096)), dim3(256), 0,
+                           st, p, Z);
         hipLaunchKernelGGL(k_prune_eps, dim3((p.n + 255) / 256), dim3(256), 0, st, p);
     }
 }
