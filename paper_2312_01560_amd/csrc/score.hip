@@ -190,6 +190,7 @@ __device__ __forceinline__ void reduce_counts_body(const ScorePlan& p, int bx) {
     if (idx < p.SK) {
         const int per = (p.grid + 15) / 16;
         const int b0 = sl_id * per, b1 = min(p.grid, b0 + per);
+#pragma unroll 8
         for (int b = b0; b < b1; ++b) {
             l += p.lpart[(size_t)b * p.SK + idx];
             v += p.vpart[(size_t)b * p.SK + idx];
@@ -213,32 +214,30 @@ __global__ __launch_bounds__(256) void k_reduce_counts(ScorePlan p) {
     reduce_counts_body(p, (int)blockIdx.x);
 }
 
-// One wave per candidate: the counts are staged in LDS, the FP64 sums run
-// over r in ascending order on one lane.
+// One wave per candidate: the lanes compute the per-block terms (each with
+// its divisions) into LDS, then one lane sums them over r in ascending order
+// (the same terms and the same order as a single lane doing both).
 __device__ __forceinline__ void score_finalize_body(const ScorePlan& p, int k) {
-    __shared__ long long ls[RAFT_MAX_K_DEV + 1], vs[RAFT_MAX_K_DEV + 1];
+    __shared__ double tm[RAFT_MAX_K_DEV + 1], tn[RAFT_MAX_K_DEV + 1];
     if (k >= p.Kc) return;
     const int K = p.ks[k];
-    for (int r = threadIdx.x; r < K; r += blockDim.x) {
-        ls[r] = p.l64[p.koff[k] + r];
-        vs[r] = p.v64[p.koff[k] + r];
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
     {
 #pragma clang fp contract(off)
         const double e = (double)(p.nnz / 2);
         const double m2 = (double)p.nnz;
+        for (int r = threadIdx.x; r < K; r += blockDim.x) {
+            const long long l = p.l64[p.koff[k] + r];
+            const long long v = p.v64[p.koff[k] + r];
+            const double t = (double)v / m2;
+            tm[r] = (double)l / e - t * t;
+            tn[r] = v > 0 ? (double)(v - 2 * l) / (double)v : 0.0;
+        }
+        __syncthreads();
+        if (threadIdx.x != 0) return;
         double mod = 0.0;
-        for (int r = 0; r < K; ++r) {
-            const double t = (double)vs[r] / m2;
-            const double term = (double)ls[r] / e - t * t;
-            mod = mod + term;
-        }
-        double nc = 0.0;
-        for (int r = 0; r < K; ++r) {
-            if (vs[r] > 0) nc = nc + (double)(vs[r] - 2 * ls[r]) / (double)vs[r];
-        }
+        for (int r = 0; r < K; ++r) mod = mod + tm[r];
+        double nc = 0.0;   // an empty block adds +0.0, which leaves the sum as it is
+        for (int r = 0; r < K; ++r) nc = nc + tn[r];
         p.mod[k] = mod;
         p.ncut[k] = 0.5 * nc;
     }
