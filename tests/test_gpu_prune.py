@@ -152,3 +152,27 @@ def test_automatic_mode_prunes_large_k(api_mod, ctx, ragged):
     with pytest.raises(RuntimeError):
         api_mod.run(ctx, g, api_mod.Config(kmeans_prune=3, k_min=2, k_max=10))
     g.close()
+
+
+def test_pruned_tiny_and_isolated(api_mod, ctx):
+    """Graphs smaller than one range and one wave (two K5 cliques and a
+    bridge; a ring with isolated nodes, whose embedding rows are zero):
+    pruned == dense, bit for bit."""
+    from synth import two_cliques
+    g0 = two_cliques(5)
+    g = api_mod.Graph(ctx, g0.row_ptr, g0.col_idx)
+    out = run_both(api_mod, ctx, g, op=1, proj_dim=32, q=2, layer_dims=[32], k_min=1, k_max=6,
+                   seed=4)
+    assert_same(out)
+    g.close()
+    n = 300
+    ring = np.arange(200)
+    src = np.concatenate([ring, ring])
+    dst = np.concatenate([(ring + 1) % 200, (ring + 7) % 200])
+    from synth.dcsbm import edges_to_csr
+    rp, ci = edges_to_csr(n, src, dst)          # nodes 200..299 isolated
+    g = api_mod.Graph(ctx, rp, ci)
+    out = run_both(api_mod, ctx, g, op=0, proj_dim=64, q=2, layer_dims=[64], k_min=2, k_max=40,
+                   k_step=2, seed=6)
+    assert_same(out)
+    g.close()
