@@ -50,6 +50,110 @@ struct SpmmGeom {
     static constexpr int G = kWave / LANES;      // rows side by side per wave
 };
 
+// Sum over the edges beg..end-1 of one row (this lane's 4 columns), in
+// batches of 16: the lanes of a row group load the same column indices
+// (broadcast loads), then all feature rows are gathered; the next batch's
+// indices are requested before this batch's gathers, so each batch waits on
+// memory once.  maxdeg: the longest range among the wave's row groups.
+template <int L, int OP>
+__device__ __forceinline__ void spmm_edges(const GraphView& g, const float* __restrict__ x, int cofs,
+                                           int beg, int end, int maxdeg, float4& acc,
+                                           float4& acc2) {
+    int jv[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int e = beg + q;
+        jv[q] = e < end ? g.ci[e] : -1;
+    }
+    for (int base = 0; base < maxdeg; base += 16) {
+        int jn[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int e = beg + base + 16 + q;
+            jn[q] = e < end ? g.ci[e] : -1;
+        }
+        float4 xv[16];
+        float wv[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            xv[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+            wv[q] = 0.f;
+            if (jv[q] >= 0) {
+                xv[q] = *reinterpret_cast<const float4*>(x + (size_t)jv[q] * L + cofs);
+                wv[q] = edge_weight<L, OP>(g, jv[q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            if (OP == kOpModFull) {
+                acc.x += xv[q].x;
+                acc.y += xv[q].y;
+                acc.z += xv[q].z;
+                acc.w += xv[q].w;
+            } else if (OP == kOpModReduced) {
+                acc.x += xv[q].x;
+                acc.y += xv[q].y;
+                acc.z += xv[q].z;
+                acc.w += xv[q].w;
+                acc2.x += wv[q] * xv[q].x;
+                acc2.y += wv[q] * xv[q].y;
+                acc2.z += wv[q] * xv[q].z;
+                acc2.w += wv[q] * xv[q].w;
+            } else {
+                acc.x += wv[q] * xv[q].x;
+                acc.y += wv[q] * xv[q].y;
+                acc.z += wv[q] * xv[q].z;
+                acc.w += wv[q] * xv[q].w;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) jv[q] = jn[q];
+    }
+}
+
+// Row i's output from its neighbour sum (this lane's 4 columns), written to
+// y, and its term d_i y_i added to the column sums.
+template <int L, int OP, bool CS>
+__device__ __forceinline__ void spmm_row_out(const GraphView& g, const float* __restrict__ x,
+                                             float* __restrict__ y, const float* __restrict__ cvec,
+                                             int cofs, int i, float4 acc, float4 acc2, double& cs0,
+                                             double& cs1, double& cs2, double& cs3) {
+    float4 o;
+    if (OP == kOpNcut) {
+        const float si = g.s[i];
+        o = make_float4(si * acc.x, si * acc.y, si * acc.z, si * acc.w);
+    } else if (OP == kOpGcn) {
+        const float si = g.sh[i];
+        const float4 xi = *reinterpret_cast<const float4*>(x + (size_t)i * L + cofs);
+        o = make_float4(si * (acc.x + si * xi.x), si * (acc.y + si * xi.y),
+                        si * (acc.z + si * xi.z), si * (acc.w + si * xi.w));
+    } else if (OP == kOpModFull) {
+        const float ci = g.dcoef[i];
+        const float4 c = *reinterpret_cast<const float4*>(cvec + cofs);
+        o = make_float4(acc.x - ci * c.x, acc.y - ci * c.y, acc.z - ci * c.z, acc.w - ci * c.w);
+    } else {
+        const float ci = g.dcoef[i];
+        o = make_float4(acc.x - ci * acc2.x, acc.y - ci * acc2.y, acc.z - ci * acc2.z,
+                        acc.w - ci * acc2.w);
+    }
+    *reinterpret_cast<float4*>(y + (size_t)i * L + cofs) = o;
+    if (CS) {
+        const double di = (double)g.deg[i];
+        cs0 += di * (double)o.x;
+        cs1 += di * (double)o.y;
+        cs2 += di * (double)o.z;
+        cs3 += di * (double)o.w;
+    }
+}
+
+// Rows with more stored entries than this are summed by the whole wave: each
+// of its G row groups takes one of G equal runs of the row's edges and the
+// runs' sums are combined by a fixed butterfly, so a long row does not keep
+// one row group walking alone.  The treatment depends only on the row (its
+// length), not on where the row order places it, so a row list (the
+// streaming levels) sums every row exactly as the full pass does.
+constexpr int kSpmmSplit = 512;
+
 template <int L, int OP, bool CS>
 __device__ __forceinline__ void spmm_body(const GraphView& g, const float* __restrict__ x,
                                           float* __restrict__ y, const float* __restrict__ cvec,
@@ -73,94 +177,40 @@ __device__ __forceinline__ void spmm_body(const GraphView& g, const float* __res
         const int i = valid ? g.order[r0 + slot] : 0;
         const int beg = g.rp[i];
         const int end = valid ? g.rp[i + 1] : beg;
-        int maxdeg = end - beg;
+        const bool heavy = end - beg > kSpmmSplit;
+        int maxdeg = heavy ? 0 : end - beg;
 #pragma unroll
         for (int off = LANES; off < kWave; off <<= 1)
             maxdeg = max(maxdeg, __shfl_xor(maxdeg, off, kWave));
         float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
         float4 acc2 = make_float4(0.f, 0.f, 0.f, 0.f);
-        // batches of 16 edges per row: the lanes of a row group load the same
-        // column index (a broadcast load), then all feature rows are gathered.
-        // The next batch's indices are requested before this batch's gathers,
-        // so each batch waits on memory once.
-        int jv[16];
+        spmm_edges<L, OP>(g, x, cofs, beg, heavy ? beg : end, maxdeg, acc, acc2);
+        if (valid && !heavy)
+            spmm_row_out<L, OP, CS>(g, x, y, cvec, cofs, i, acc, acc2, cs0, cs1, cs2, cs3);
+        // the pass's long rows, one after another, over all row groups
+        for (uint64_t hm = __ballot(heavy && sub == 0); hm != 0; hm &= hm - 1) {
+            const int hl = __builtin_ctzll(hm);
+            const int hi = __shfl(i, hl, kWave);
+            const int hb = __shfl(beg, hl, kWave), he = __shfl(end, hl, kWave);
+            const int run = (he - hb + G - 1) / G;
+            const int b0 = min(he, hb + slot * run), b1 = min(he, b0 + run);
+            float4 h = make_float4(0.f, 0.f, 0.f, 0.f);
+            float4 h2 = make_float4(0.f, 0.f, 0.f, 0.f);
+            spmm_edges<L, OP>(g, x, cofs, b0, b1, run, h, h2);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int e = beg + q;
-            jv[q] = e < end ? g.ci[e] : -1;
-        }
-        for (int base = 0; base < maxdeg; base += 16) {
-            int jn[16];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int e = beg + base + 16 + q;
-                jn[q] = e < end ? g.ci[e] : -1;
-            }
-            float4 xv[16];
-            float wv[16];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                xv[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-                wv[q] = 0.f;
-                if (jv[q] >= 0) {
-                    xv[q] = *reinterpret_cast<const float4*>(x + (size_t)jv[q] * L + cofs);
-                    wv[q] = edge_weight<L, OP>(g, jv[q]);
+            for (int off = LANES; off < kWave; off <<= 1) {
+                h.x += __shfl_xor(h.x, off, kWave);
+                h.y += __shfl_xor(h.y, off, kWave);
+                h.z += __shfl_xor(h.z, off, kWave);
+                h.w += __shfl_xor(h.w, off, kWave);
+                if (OP == kOpModReduced) {
+                    h2.x += __shfl_xor(h2.x, off, kWave);
+                    h2.y += __shfl_xor(h2.y, off, kWave);
+                    h2.z += __shfl_xor(h2.z, off, kWave);
+                    h2.w += __shfl_xor(h2.w, off, kWave);
                 }
             }
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                if (OP == kOpModFull) {
-                    acc.x += xv[q].x;
-                    acc.y += xv[q].y;
-                    acc.z += xv[q].z;
-                    acc.w += xv[q].w;
-                } else if (OP == kOpModReduced) {
-                    acc.x += xv[q].x;
-                    acc.y += xv[q].y;
-                    acc.z += xv[q].z;
-                    acc.w += xv[q].w;
-                    acc2.x += wv[q] * xv[q].x;
-                    acc2.y += wv[q] * xv[q].y;
-                    acc2.z += wv[q] * xv[q].z;
-                    acc2.w += wv[q] * xv[q].w;
-                } else {
-                    acc.x += wv[q] * xv[q].x;
-                    acc.y += wv[q] * xv[q].y;
-                    acc.z += wv[q] * xv[q].z;
-                    acc.w += wv[q] * xv[q].w;
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < 16; ++q) jv[q] = jn[q];
-        }
-        if (valid) {
-            float4 o;
-            if (OP == kOpNcut) {
-                const float si = g.s[i];
-                o = make_float4(si * acc.x, si * acc.y, si * acc.z, si * acc.w);
-            } else if (OP == kOpGcn) {
-                const float si = g.sh[i];
-                const float4 xi = *reinterpret_cast<const float4*>(x + (size_t)i * L + cofs);
-                o = make_float4(si * (acc.x + si * xi.x), si * (acc.y + si * xi.y),
-                                si * (acc.z + si * xi.z), si * (acc.w + si * xi.w));
-            } else if (OP == kOpModFull) {
-                const float ci = g.dcoef[i];
-                const float4 c = *reinterpret_cast<const float4*>(cvec + cofs);
-                o = make_float4(acc.x - ci * c.x, acc.y - ci * c.y, acc.z - ci * c.z,
-                                acc.w - ci * c.w);
-            } else {
-                const float ci = g.dcoef[i];
-                o = make_float4(acc.x - ci * acc2.x, acc.y - ci * acc2.y, acc.z - ci * acc2.z,
-                                acc.w - ci * acc2.w);
-            }
-            *reinterpret_cast<float4*>(y + (size_t)i * L + cofs) = o;
-            if (CS) {
-                const double di = (double)g.deg[i];
-                cs0 += di * (double)o.x;
-                cs1 += di * (double)o.y;
-                cs2 += di * (double)o.z;
-                cs3 += di * (double)o.w;
-            }
+            if (slot == 0) spmm_row_out<L, OP, CS>(g, x, y, cvec, cofs, hi, h, h2, cs0, cs1, cs2, cs3);
         }
     }
     if (CS) {

@@ -55,6 +55,21 @@ def edges_to_csr(n, src, dst):
     return row_ptr.astype(np.int32), cols.astype(np.int32)
 
 
+def hub_graph(seed, n=3001, hubs=12):
+    """Sparse uniform edges (six per node) plus `hubs` hub nodes joined to
+    0.6 % .. 97 % of the nodes: rows of up to ~0.97 n entries next to rows of
+    a few.  Returns (row_ptr, col_idx)."""
+    rng = np.random.default_rng(seed)
+    src = rng.integers(0, n, 6 * n)
+    dst = rng.integers(0, n, 6 * n)
+    centres = rng.choice(n, hubs, replace=False)
+    for h, frac in zip(centres, np.linspace(0.006, 0.97, hubs)):
+        nb = rng.choice(n, int(frac * n), replace=False)
+        src = np.concatenate([src, np.full(nb.size, h)])
+        dst = np.concatenate([dst, nb])
+    return edges_to_csr(n, src, dst)
+
+
 def _block_sizes(rng, n, k, alpha, min_block):
     p = rng.dirichlet(np.full(k, alpha))
     raw = n * p

@@ -11,7 +11,7 @@ from oracle import gcn as ogcn
 from oracle import graph as ograph
 from oracle import kmeans as okm
 from oracle import pipeline, projection, scores
-from synth import dcsbm, make_workload, two_cliques
+from synth import dcsbm, hub_graph, make_workload, two_cliques
 from synth.dcsbm import edges_to_csr
 
 pytestmark = pytest.mark.gpu
@@ -187,6 +187,36 @@ def test_spmm_one_step(ctx, api_mod, ragged, op, L):
     assert col_err(got, ref).max() < COL_TOL
 
 
+@pytest.mark.parametrize("L", [16, 32, 64, 256])
+@pytest.mark.parametrize("op", [0, 1, 2, 3])
+def test_spmm_hub_rows(ctx, api_mod, op, L):
+    """Rows long enough that the whole wave sums them (edges split over the
+    row groups, their sums folded) next to light rows: every operator and
+    rows-per-wave geometry against the FP64 oracle, the hub rows alone too."""
+    rp, ci = hub_graph(L + op)
+    n = rp.size - 1
+    deg = np.diff(rp)
+    assert np.sum(deg > 512) >= 6 and deg.max() > 2500
+    g = api_mod.Graph(ctx, rp, ci)
+    y = torch.randn(n, L, device="cuda", generator=torch.Generator("cuda").manual_seed(op))
+    got = to_np(api_mod.spmm(ctx, g, op, y))
+    x = to_np(y).astype(np.float64)
+    if op == 0:
+        ref = projection.ncut_operator(rp, ci, n) @ x
+    elif op == 1:
+        a = ograph.adjacency(rp, ci, n)
+        d = ograph.degrees(rp).astype(float)
+        ref = projection.apply_modularity(a, d, float(ograph.two_e(rp)), x)
+    elif op == 2:
+        ref = projection.reduced_modularity_operator(rp, ci, n) @ x
+    else:
+        ref = ogcn.gcn_operator(rp, ci, n) @ x
+    assert col_err(got, ref).max() < COL_TOL
+    hub = deg > 512
+    assert col_err(got[hub], ref[hub]).max() < COL_TOL
+    g.close()
+
+
 @pytest.mark.parametrize("op", [0, 1, 2])
 def test_project_q3(ctx, api_mod, small_graph, op):
     g0, m = small_graph
@@ -248,15 +278,8 @@ def test_scores_split_rows(ctx, api_mod, kc):
     the edge-score kernel splits over a wave give the oracle's scores bit
     for bit."""
     rng = np.random.default_rng(kc)
-    n = 3001
-    src = rng.integers(0, n, 6 * n)
-    dst = rng.integers(0, n, 6 * n)
-    hubs = rng.choice(n, 12, replace=False)
-    for h, frac in zip(hubs, np.linspace(0.006, 0.97, hubs.size)):
-        nb = rng.choice(n, int(frac * n), replace=False)
-        src = np.concatenate([src, np.full(nb.size, h)])
-        dst = np.concatenate([dst, nb])
-    rp, ci = edges_to_csr(n, src, dst)
+    rp, ci = hub_graph(kc)
+    n = rp.size - 1
     deg = np.diff(rp)
     assert deg.max() > 2500 and np.sum(deg > 240) >= 8
     g = api_mod.Graph(ctx, rp, ci)
