@@ -634,7 +634,8 @@ raft_status do_embed(raft_ctx* ctx, const raft_graph* g, const raft_config* c, P
         float* dst = (k == c->n_layers) ? Z : (h == P.y0 ? P.y1 : P.y0);
         {
             ProfScope ps(ctx, RAFT_PROF_DENSE, st);
-            launch_dense_layer(P.pbuf, P.wbuf, dst, g->n, lin, lout, false, ctx->d_status, st);
+            launch_dense_layer(P.pbuf, P.wbuf, dst, g->n, lin, lout, false, ctx->d_status,
+                               ctx->num_cu, st);
         }
         h = dst;
         lin = lout;
@@ -1214,7 +1215,8 @@ raft_status raft_gcn_layer(raft_ctx* ctx, const raft_graph* g, int32_t L_in, int
         P = reinterpret_cast<float*>(ws);
     }
     launch_spmm(g->view(), kOpGcn, L_in, H_in, P, nullptr, nullptr, ctx->num_cu, st);
-    launch_dense_layer(P, W, H_out, g->n, L_in, L_out, linear != 0, ctx->d_status, st);
+    launch_dense_layer(P, W, H_out, g->n, L_in, L_out, linear != 0, ctx->d_status, ctx->num_cu,
+                       st);
     return launch_check(ctx);
 }
 
@@ -1496,7 +1498,8 @@ raft_status raft_gcn_forward(raft_ctx* ctx, const raft_graph* g, int32_t n_layer
         const bool last = k == n_layers - 1;
         float* out = last ? U_out : H_saved[k];
         if (!out || !W[k]) return fail(ctx, RAFT_E_INVAL, "null layer buffer");
-        launch_dense_layer(t.P, W[k], out, g->n, dims[k], dims[k + 1], last, ctx->d_status, st);
+        launch_dense_layer(t.P, W[k], out, g->n, dims[k], dims[k + 1], last, ctx->d_status,
+                           ctx->num_cu, st);
         h = out;
     }
     return launch_check(ctx);
@@ -1524,13 +1527,15 @@ raft_status raft_gcn_backward(raft_ctx* ctx, const raft_graph* g, int32_t n_laye
         const float* gu = gcur;
         if (k != n_layers - 1) {
             // recompute the pre-activation, then back through normalisation and tanh
-            launch_dense_layer(t.P, W[k], t.U, g->n, li, lo, true, ctx->d_status, st);
+            launch_dense_layer(t.P, W[k], t.U, g->n, li, lo, true, ctx->d_status, ctx->num_cu,
+                               st);
             launch_tanh_norm_backward(t.U, const_cast<float*>(gcur), g->n, lo, st);
         }
         launch_wgrad(t.P, gu, g->n, li, lo, t.wpart, G_W[k], st);
         if (k > 0 || G_H0) {
             launch_transpose(W[k], li, lo, t.WT, st);
-            launch_dense_layer(gu, t.WT, t.Gb, g->n, lo, li, true, ctx->d_status, st);   // G_P
+            launch_dense_layer(gu, t.WT, t.Gb, g->n, lo, li, true, ctx->d_status, ctx->num_cu,
+                               st);   // G_P
             float* dst = (k == 0) ? G_H0 : gnext;
             launch_spmm(gv, kOpGcn, li, t.Gb, dst, nullptr, nullptr, ctx->num_cu, st);   // A_hat_n G_P
             gcur = dst;
@@ -3193,7 +3198,7 @@ raft_status stream_full(raft_stream* s, hipStream_t st) {
     for (int k = 0; k < c.n_layers; ++k) {
         launch_spmm(gv, kOpGcn, s->lin[k], hin, s->pbuf, nullptr, nullptr, ctx->num_cu, st);
         launch_dense_layer(s->pbuf, s->w[k], s->h[k], n, s->lin[k], s->lout[k], false,
-                           ctx->d_status, st);
+                           ctx->d_status, ctx->num_cu, st);
         hin = s->h[k];
     }
     return launch_check(ctx);
@@ -3234,13 +3239,13 @@ raft_status stream_incremental(raft_stream* s, const int64_t* counts, hipStream_
         launch_spmm(sub(t), kOpGcn, s->lin[k], hin, s->pbuf, nullptr, nullptr, ctx->num_cu, st);
         if (stream_level_full(s, counts, t)) {
             launch_dense_layer(s->pbuf, s->w[k], s->h[k], n, s->lin[k], s->lout[k], false,
-                               ctx->d_status, st);
+                               ctx->d_status, ctx->num_cu, st);
         } else {
             const int32_t* lt = s->lists + (size_t)(t - 1) * n;
             const int32_t ct = (int32_t)counts[t - 1];
             launch_stream_rows(true, lt, ct, s->lin[k], s->pbuf, s->gin, st);
             launch_dense_layer(s->gin, s->w[k], s->gout, ct, s->lin[k], s->lout[k], false,
-                               ctx->d_status, st);
+                               ctx->d_status, ctx->num_cu, st);
             launch_stream_rows(false, lt, ct, s->lout[k], s->gout, s->h[k], st);
         }
         hin = s->h[k];

@@ -15,18 +15,19 @@ namespace raft {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-template <int LIN, int LOUT, bool LINEAR>
-__device__ __forceinline__ void dense_body(const float* __restrict__ P,
-                                           const float* __restrict__ W, float* __restrict__ H,
-                                           int n, int32_t* __restrict__ status, int bx) {
+// One wave's 16-row tile from row0 (row0 < n): U = P W on the matrix
+// cores, then tanh and the row norm unless LINEAR.  getb(nb, s) returns the
+// B operand of this lane for column block nb and contraction step s, i.e.
+// W[g*KS + s][nb*16 + li]; where it comes from does not change the result.
+template <int LIN, int LOUT, bool LINEAR, class GetB>
+__device__ __forceinline__ void dense_tile(const float* __restrict__ P, float* __restrict__ H,
+                                           int n, int32_t* __restrict__ status, int row0,
+                                           GetB getb) {
     constexpr int KS = LIN / 4;
     constexpr int NB = LOUT / 16;
     const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x / kWave;
     const int g = lane >> 4;
     const int li = lane & 15;
-    const int row0 = (bx * 4 + wid) * 16;
-    if (row0 >= n) return;
     const int ra = min(row0 + li, n - 1);
     float a[KS];
     const float* prow = P + (size_t)ra * LIN + g * KS;
@@ -42,12 +43,9 @@ __device__ __forceinline__ void dense_body(const float* __restrict__ P,
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
         acc[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-        const float* wcol = W + (size_t)(g * KS) * LOUT + nb * 16 + li;
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            const float b = wcol[(size_t)s * LOUT];
-            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b, acc[nb], 0, 0, 0);
-        }
+        for (int s = 0; s < KS; ++s)
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], getb(nb, s), acc[nb], 0, 0, 0);
     }
     float inv[4] = {1.f, 1.f, 1.f, 1.f};
     if (!LINEAR) {
@@ -82,11 +80,72 @@ __device__ __forceinline__ void dense_body(const float* __restrict__ P,
 }
 
 template <int LIN, int LOUT, bool LINEAR>
+__device__ __forceinline__ void dense_body(const float* __restrict__ P,
+                                           const float* __restrict__ W, float* __restrict__ H,
+                                           int n, int32_t* __restrict__ status, int bx) {
+    constexpr int KS = LIN / 4;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int g = lane >> 4;
+    const int li = lane & 15;
+    const int row0 = (bx * 4 + (int)threadIdx.x / kWave) * 16;
+    if (row0 >= n) return;
+    const float* wcol = W + (size_t)(g * KS) * LOUT + li;
+    dense_tile<LIN, LOUT, LINEAR>(P, H, n, status, row0, [&](int nb, int s) {
+        return wcol[(size_t)s * LOUT + nb * 16];
+    });
+}
+
+template <int LIN, int LOUT, bool LINEAR>
 __global__ __launch_bounds__(256) void k_dense(const float* __restrict__ P,
                                                const float* __restrict__ W,
                                                float* __restrict__ H, int n,
                                                int32_t* __restrict__ status) {
     dense_body<LIN, LOUT, LINEAR>(P, W, H, n, status, (int)blockIdx.x);
+}
+
+// W staged in LDS once per work-group of kDenseLdsWaves waves, which then
+// walk 16-row tiles (one per wave at a time, grid-stride).  Layout: for
+// column block nb and contraction steps s..s+3 (s a multiple of 4) the 64
+// lanes' operands are 64 consecutive float4s, lane-major, so a wave reads
+// them with one conflict-free 16-byte load per lane; the staging writes are
+// scattered once per work-group.  Used while W fits 64 KB, so that two
+// work-groups (four waves per SIMD) share a CU.
+constexpr int kDenseLdsWaves = 8;
+
+template <int LIN, int LOUT>
+struct DenseLds {
+    static constexpr int kFloats = LIN * LOUT;
+    static constexpr bool kFits = kFloats * 4 <= 64 * 1024;
+};
+
+template <int LIN, int LOUT, bool LINEAR>
+__global__ __launch_bounds__(kDenseLdsWaves * kWave, 2) void k_dense_lds(
+    const float* __restrict__ P, const float* __restrict__ W, float* __restrict__ H, int n,
+    int32_t* __restrict__ status) {
+    constexpr int KS = LIN / 4;
+    __shared__ float4 wl4[DenseLds<LIN, LOUT>::kFloats / 4];
+    float* wl = reinterpret_cast<float*>(wl4);
+    for (int e = threadIdx.x; e < LIN * LOUT; e += blockDim.x) {
+        const int k = e / LOUT, col = e % LOUT;
+        const int g = k / KS, s = k - g * KS;
+        const int ln = g * 16 + (col & 15);
+        wl[((((col >> 4) * (KS / 4) + (s >> 2)) * kWave + ln) << 2) + (s & 3)] = W[e];
+    }
+    __syncthreads();
+    const int tiles = (n + 15) / 16;
+    for (int t = (int)blockIdx.x * kDenseLdsWaves + (int)threadIdx.x / kWave; t < tiles;
+         t += (int)gridDim.x * kDenseLdsWaves) {
+        // the lane's offset made opaque per tile: W's operands are the same
+        // for every tile, and held in registers across tiles they would take
+        // 256 of them (one wave per SIMD); read per tile they take four
+        int lane = (int)(threadIdx.x & (kWave - 1));
+        asm volatile("" : "+v"(lane));
+        const float4* wp = wl4 + lane;
+        dense_tile<LIN, LOUT, LINEAR>(P, H, n, status, t * 16, [&](int nb, int s) {
+            const float4 v = wp[(nb * (KS / 4) + (s >> 2)) * kWave];
+            return (s & 3) == 0 ? v.x : (s & 3) == 1 ? v.y : (s & 3) == 2 ? v.z : v.w;
+        });
+    }
 }
 
 // Batched: each graph's rows with its own W (one 64-row block never holds
@@ -267,8 +326,22 @@ bool dense_supported(int lin, int lout) {
 
 template <int LIN, int LOUT>
 static void dense_launch2(const float* P, const float* W, float* H, int32_t n, bool linear,
-                          int32_t* status, hipStream_t st) {
+                          int32_t* status, int num_cu, hipStream_t st) {
     const int grid = (n + 63) / 64;
+    if constexpr (DenseLds<LIN, LOUT>::kFits) {
+        // as many work-groups as fit the CUs' LDS at once (at most 4 per CU)
+        constexpr int per_cu = std::min(4, (160 * 1024) / (DenseLds<LIN, LOUT>::kFloats * 4));
+        const int tiles = (n + 16 * kDenseLdsWaves - 1) / (16 * kDenseLdsWaves);
+        const int g2 = std::min(tiles, std::max(1, num_cu) * per_cu);
+        const dim3 blk(kDenseLdsWaves * kWave);
+        if (linear)
+            hipLaunchKernelGGL((k_dense_lds<LIN, LOUT, true>), dim3(g2), blk, 0, st, P, W, H, n,
+                               status);
+        else
+            hipLaunchKernelGGL((k_dense_lds<LIN, LOUT, false>), dim3(g2), blk, 0, st, P, W, H, n,
+                               status);
+        return;
+    }
     if (linear)
         hipLaunchKernelGGL((k_dense<LIN, LOUT, true>), dim3(grid), dim3(256), 0, st, P, W, H, n,
                            status);
@@ -328,21 +401,21 @@ void launch_rownorm_batched(const DenseItem* items, int L, const BatchTable& t, 
 
 template <int LIN>
 static void dense_launch1(const float* P, const float* W, float* H, int32_t n, int lout,
-                          bool linear, int32_t* status, hipStream_t st) {
+                          bool linear, int32_t* status, int num_cu, hipStream_t st) {
     switch (lout) {
-        case 16: dense_launch2<LIN, 16>(P, W, H, n, linear, status, st); break;
-        case 32: dense_launch2<LIN, 32>(P, W, H, n, linear, status, st); break;
-        case 64: dense_launch2<LIN, 64>(P, W, H, n, linear, status, st); break;
-        case 128: dense_launch2<LIN, 128>(P, W, H, n, linear, status, st); break;
+        case 16: dense_launch2<LIN, 16>(P, W, H, n, linear, status, num_cu, st); break;
+        case 32: dense_launch2<LIN, 32>(P, W, H, n, linear, status, num_cu, st); break;
+        case 64: dense_launch2<LIN, 64>(P, W, H, n, linear, status, num_cu, st); break;
+        case 128: dense_launch2<LIN, 128>(P, W, H, n, linear, status, num_cu, st); break;
         case 256:
-            if constexpr (LIN <= 128) dense_launch2<LIN, 256>(P, W, H, n, linear, status, st);
+            if constexpr (LIN <= 128) dense_launch2<LIN, 256>(P, W, H, n, linear, status, num_cu, st);
             break;
         default: break;
     }
 }
 
 void launch_dense_layer(const float* P, const float* W, float* H, int32_t n, int lin, int lout,
-                        bool linear, int32_t* status, hipStream_t st) {
+                        bool linear, int32_t* status, int num_cu, hipStream_t st) {
     if (n == 0) return;
     if (!dense_small(lin, lout)) {
         const int grid = ((n + kGemmBM - 1) / kGemmBM) * (lout / kGemmBN);
@@ -355,11 +428,11 @@ void launch_dense_layer(const float* P, const float* W, float* H, int32_t n, int
         return;
     }
     switch (lin) {
-        case 16: dense_launch1<16>(P, W, H, n, lout, linear, status, st); break;
-        case 32: dense_launch1<32>(P, W, H, n, lout, linear, status, st); break;
-        case 64: dense_launch1<64>(P, W, H, n, lout, linear, status, st); break;
-        case 128: dense_launch1<128>(P, W, H, n, lout, linear, status, st); break;
-        case 256: dense_launch1<256>(P, W, H, n, lout, linear, status, st); break;
+        case 16: dense_launch1<16>(P, W, H, n, lout, linear, status, num_cu, st); break;
+        case 32: dense_launch1<32>(P, W, H, n, lout, linear, status, num_cu, st); break;
+        case 64: dense_launch1<64>(P, W, H, n, lout, linear, status, num_cu, st); break;
+        case 128: dense_launch1<128>(P, W, H, n, lout, linear, status, num_cu, st); break;
+        case 256: dense_launch1<256>(P, W, H, n, lout, linear, status, num_cu, st); break;
         default: break;
     }
 }

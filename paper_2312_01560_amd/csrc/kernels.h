@@ -107,7 +107,7 @@ constexpr int kColsumSliceBlocks = 64;
 bool dense_supported(int lin, int lout);
 // H = rownorm(tanh(P W)) (or U = P W when linear), P [n x lin], W [lin x lout].
 void launch_dense_layer(const float* P, const float* W, float* H, int32_t n, int lin, int lout,
-                        bool linear, int32_t* status, hipStream_t st);
+                        bool linear, int32_t* status, int num_cu, hipStream_t st);
 // Row L2 normalisation in place (x / max(||x||, 1e-12)).
 void launch_rownorm(float* x, int32_t n, int L, hipStream_t st);
 
