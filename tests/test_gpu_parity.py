@@ -229,7 +229,8 @@ def test_project_q3(ctx, api_mod, small_graph, op):
 
 # ---------------------------------------------------------------- A4 -----
 
-@pytest.mark.parametrize("lin,lout", [(64, 64), (128, 128), (64, 32), (256, 64), (16, 256)])
+@pytest.mark.parametrize("lin,lout", [(64, 64), (128, 128), (64, 32), (256, 64), (16, 256),
+                                      (128, 256), (256, 128)])
 def test_gcn_layer(ctx, api_mod, ragged, lin, lout):
     g = api_mod.Graph(ctx, ragged.row_ptr, ragged.col_idx)
     h = torch.randn(ragged.n, lin, device="cuda")
@@ -243,6 +244,24 @@ def test_gcn_layer(ctx, api_mod, ragged, lin, lout):
     lin_out, _ = api_mod.gcn_layer(ctx, g, h, w, linear=True, want_p=True)
     u = to_np(p).astype(np.float64) @ to_np(w).astype(np.float64)
     assert col_err(to_np(lin_out), u).max() < COL_TOL
+
+
+@pytest.mark.parametrize("n,width", [(70000, 128), (140000, 64)])
+def test_gcn_layer_many_tiles(ctx, api_mod, n, width):
+    """More rows than the dense layer's work-groups cover in one pass (its
+    grid is capped at what the CUs' LDS holds at once), so every work-group
+    walks several rounds of row tiles: the layer against the FP64 oracle."""
+    rng = np.random.default_rng(n)
+    rp, ci = edges_to_csr(n, rng.integers(0, n, 4 * n), rng.integers(0, n, 4 * n))
+    g = api_mod.Graph(ctx, rp, ci)
+    h = torch.randn(n, width, device="cuda", generator=torch.Generator("cuda").manual_seed(width))
+    w = api_mod.gaussian(ctx, 5, 0x11, width, width, width ** -0.5)
+    got, p = api_mod.gcn_layer(ctx, g, h, w, want_p=True)
+    pref = ogcn.gcn_operator(rp, ci, n) @ to_np(h).astype(np.float64)
+    assert col_err(to_np(p), pref).max() < COL_TOL
+    z = ogcn.row_normalize(np.tanh(to_np(p).astype(np.float64) @ to_np(w).astype(np.float64)))
+    assert col_err(to_np(got), z).max() < COL_TOL
+    g.close()
 
 
 def test_embed(ctx, api_mod, small_graph):
