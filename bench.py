@@ -20,6 +20,7 @@ import hashlib
 import json
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -40,6 +41,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="n50k")
     ap.add_argument("--variants", default="ncut,mod_full")
+    ap.add_argument("--concurrent-variants", action="store_true",
+                    help="time the steps with each variant on its own context and stream, "
+                         "driven from its own host thread, so their kernels overlap (default: "
+                         "one after the other on one stream; the overlapped schedule is then "
+                         "timed as an extra record unless --no-extras)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-stride", type=int, default=26)
     ap.add_argument("--train", action="store_true",
@@ -465,39 +471,107 @@ def main():
     rp = torch.from_numpy(graph.row_ptr).to(dev)
     ci = torch.from_numpy(graph.col_idx).to(dev)
     cfgs = {v: api.Config(op=VARIANTS[v], **method) for v in variants}
-    g0 = api.Graph(ctx, rp, ci)
-    ws = ctx.workspace(max(api.workspace_size(ctx, g0, c) for c in cfgs.values()))
-    g0.close()
-    outs = {v: api._outputs(ctx, g0, cfgs[v], want_y=True, want_z=True) for v in variants}
+    # The variants of a step are independent runs over the same graph.  By
+    # default each has its own context (workspace, events, pinned staging)
+    # and stream and is driven from its own host thread, so the kernels of
+    # one fill the latency of the other's; every result is the same as in a
+    # serial run.  Streams keep the default priority.
+    concurrent = len(variants) > 1 and args.concurrent_variants
+    conc_leg = len(variants) > 1 and not concurrent and not args.no_extras
+    two = concurrent or conc_leg
+    vctx = {v: (api.Context(0) if two and i > 0 else ctx) for i, v in enumerate(variants)}
+    vstream = {v: torch.cuda.Stream() for v in variants} if two else {}
+    ctxs = list({id(c): c for c in vctx.values()}.values())
+    wsv, outs = {}, {}
+    for v in variants:
+        c = vctx[v]
+        g0 = api.Graph(c, rp, ci)
+        if two:
+            wsv[v] = c.workspace(api.workspace_size(c, g0, cfgs[v]))
+        elif variants[0] in wsv:
+            wsv[v] = wsv[variants[0]]
+        else:
+            wsv[v] = ctx.workspace(max(api.workspace_size(ctx, g0, cf) for cf in cfgs.values()))
+        outs[v] = api._outputs(c, g0, cfgs[v], want_y=True, want_z=True)
+        g0.close()
 
-    def step():
-        g = api.Graph(ctx, rp, ci)
-        for v in variants:
-            api.run(ctx, g, cfgs[v], ws=ws, outputs=outs[v])
-        g.close()
+    def steps(k, acc=None, conc=concurrent):
+        """k steps: every variant over a graph created for the step."""
+        if not conc:
+            for _ in range(k):
+                g = api.Graph(ctx, rp, ci)
+                for v in variants:
+                    api.run(ctx, g, cfgs[v], ws=wsv[v], outputs=outs[v])
+                    if acc is not None:
+                        acc[v] += np.array(api.stage_times(ctx))
+                g.close()
+            return
+        errors = []
 
-    log(f"workload {args.workload}: n={graph.n} nnz={graph.nnz} variants={variants}; warm-up")
-    for _ in range(args.warmup):
-        step()
+        def worker(v):
+            try:
+                c = vctx[v]
+                with torch.cuda.stream(vstream[v]):
+                    for _ in range(k):
+                        g = api.Graph(c, rp, ci)
+                        api.run(c, g, cfgs[v], ws=wsv[v], outputs=outs[v])
+                        if acc is not None:
+                            acc[v] += np.array(api.stage_times(c))
+                        g.close()
+                    vstream[v].synchronize()
+            except BaseException as e:   # re-raised in the main thread
+                errors.append(e)
+
+        threads = [threading.Thread(target=worker, args=(v,)) for v in variants]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        if errors:
+            raise errors[0]
+
+    log(f"workload {args.workload}: n={graph.n} nnz={graph.nnz} variants={variants} "
+        f"({'concurrent' if concurrent else 'serial'}); warm-up")
+    steps(args.warmup)
     torch.cuda.synchronize()
-    ctx.sync_status()
+    for c in ctxs:
+        c.sync_status()
     log("warm-up done; timed steps")
-    api.profile_read(ctx)
-    api.profile_enable(ctx, (1 << 0) | (1 << 3) | (1 << 5))   # SpMM, assignment, edge scores
+    for c in ctxs:
+        api.profile_read(c)
+        api.profile_enable(c, (1 << 0) | (1 << 3) | (1 << 5))   # SpMM, assignment, edge scores
     stage = {v: np.zeros(5) for v in variants}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        g = api.Graph(ctx, rp, ci)
-        for v in variants:
-            api.run(ctx, g, cfgs[v], ws=ws, outputs=outs[v])
-            stage[v] += np.array(api.stage_times(ctx))
-        g.close()
+    steps(args.steps, stage)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = api.profile_read(ctx)
-    api.profile_enable(ctx, 0)
-    ctx.sync_status()
+    prof = {}
+    for c in ctxs:
+        for key, (ms, cnt) in api.profile_read(c).items():
+            m0, c0 = prof.get(key, (0.0, 0))
+            prof[key] = (m0 + ms, c0 + cnt)
+        api.profile_enable(c, 0)
+        c.sync_status()
+    conc_rec = None
+    if conc_leg:
+        # the same steps with the variants overlapped (after one untimed step)
+        lab_serial = {v: outs[v][0]["labels_all"].clone() for v in variants}
+        steps(1, conc=True)
+        torch.cuda.synchronize()
+        tc0 = time.perf_counter()
+        steps(args.steps, conc=True)
+        torch.cuda.synchronize()
+        tc = time.perf_counter() - tc0
+        for c in ctxs:
+            c.sync_status()
+        conc_rec = {"value": args.steps / tc, "unit": "graphs/s",
+                    "ms_per_step": 1e3 * tc / args.steps,
+                    "schedule": "a context, stream and host thread per variant",
+                    "labels_identical_to_serial": all(
+                        bool(torch.equal(lab_serial[v], outs[v][0]["labels_all"]))
+                        for v in variants)}
+        log(f"variants overlapped: {conc_rec['ms_per_step']:.2f} ms/step")
     elapsed = t1 - t0
     log(f"timed steps done: {1e3 * elapsed / args.steps:.2f} ms/step")
     value = args.steps / elapsed
@@ -552,6 +626,10 @@ def main():
         roof = {"kernel": "k_spmm", "bound": "hbm", "achieved": spmm_ach / 1e9,
                 "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": spmm_ach / PEAK_HBM,
                 "per_launch": {"bytes": spmm_bytes_per_launch, "avg_ms": ms_spmm / max(n_spmm, 1)}}
+    if concurrent:
+        roof["duration_note"] = ("launch durations timed while the other variant's kernels "
+                                 "share the GPU (the variants run concurrently), so the "
+                                 "per-launch rate is below that of a kernel running alone")
     roof["traffic"] = measured_traffic(dominant, args.workload)
     if dominant == "assign" and pruned:
         roof["traffic"] = None   # the counters cover the full assignment kernel only
@@ -575,8 +653,11 @@ def main():
                    "proj_dim": method["proj_dim"], "q": method["q"],
                    "layer_dims": method["layer_dims"],
                    "k_grid": [method["k_min"], method["k_max"], method["k_step"]],
-                   "variants": variants},
+                   "variants": variants,
+                   "variant_schedule": ("concurrent: a context, stream and host thread per "
+                                        "variant" if concurrent else "serial: one stream")},
         "roofline": roof,
+        "variants_concurrent": conc_rec,
         "spmm": {"achieved_gbs": spmm_ach / 1e9, "frac_hbm": spmm_ach / PEAK_HBM,
                  "avg_us": 1e3 * ms_spmm / max(n_spmm, 1), "launches": n_spmm,
                  "bytes_per_launch": spmm_bytes_per_launch,
